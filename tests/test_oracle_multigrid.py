@@ -1,0 +1,211 @@
+"""Pins of the oracle's multigrid (Sec. 3 and Sec. 4.1 of the paper).
+
+P5  Proposition 1 (energy preservation): a_k(I_k lam, I_k lam) = a_{k-1}(lam, lam).
+P6  Galerkin product Q_{k-1} A_k I_k equals the Schur form (eqs. coarse, Akm1).
+P7  Proposition 2: A_{k-1} = J^T (dense Schur complement of A_k onto E_{k,B}) J.
+P8  Q_{k-1} = I_k^T for the symmetric HDG operator.
+P9  after the local correction the residual vanishes on E_{k,I} and
+    Q_{k-1} r = J^T r_B.
+P10 nested-dissection limit: exact coarse spaces, no smoothing -> one
+    V-cycle solves the system (Sec. 3.5).
+P11 mesh-independent iteration counts for tau = 1, k >= 4 (Sec. 4.1).
+P12 the paper's iteration counts for Example I (Tables HDG_tau2_bj,
+    HDG_tau1_bj, HDG_tau1_bj_without_local): exact for tau = 1, p = 1, 2;
+    within 2 elsewhere.
+P13 without local correction the method diverges for p = 1 (and p = 3 on
+    finer meshes) while GMRES still converges on coarse meshes.
+P15 the symmetric cycle (local correction in steps 3 and 5) is a symmetric
+    positive definite preconditioner.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mg
+from oracle.hdg import HDG
+from paper_1811_09909_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _problem(d, n, k, tau=1.0, seed=0, lo=1e-2, hi=1e2):
+    rng = np.random.default_rng(seed)
+    kap = 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), n ** d)
+    P = HDG(d, n, k, tau, kap)
+    f = rng.standard_normal((n ** d, P.nv))
+    A, g, _ = P.assemble(f)
+    return P, A, g
+
+
+CASES = [(2, 8, 1), (2, 8, 3), (3, 4, 1), (3, 4, 2)]
+
+
+@pytest.mark.parametrize("d,n,k", CASES)
+def test_P5_P6_P8_energy_galerkin_adjoint(d, n, k):
+    P, A, g = _problem(d, n, k)
+    H = mg.Hierarchy(A, d, n, k)
+    rng = np.random.default_rng(1)
+    for i in range(len(H.levels) - 1):
+        L, Lc = H.levels[i], H.levels[i + 1]
+        lc = rng.standard_normal(Lc.A.shape[0])
+        Il = L.I @ lc
+        e_f = Il @ (L.A @ Il)
+        e_c = lc @ (Lc.A @ lc)
+        assert abs(e_f - e_c) <= 1e-12 * abs(e_c)
+        G = (L.Q @ L.A @ L.I).toarray()
+        Ac = Lc.A.toarray()
+        assert np.abs(G - Ac).max() <= 1e-12 * np.abs(Ac).max()
+        assert abs(L.Q - L.I.T).max() <= 1e-12 * max(abs(L.Q).max(), 1)
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 2), (3, 4, 1)])
+def test_P7_coarse_operator_is_dense_schur(d, n, k):
+    P, A, g = _problem(d, n, k)
+    H = mg.Hierarchy(A, d, n, k)
+    for i, L in enumerate(H.levels[:-1]):
+        if L.kind != "h":
+            continue
+        Ad = L.A.toarray()
+        I, B = L.I_dofs, L.B_dofs
+        S = Ad[np.ix_(B, B)] - Ad[np.ix_(B, I)] @ np.linalg.solve(Ad[np.ix_(I, I)], Ad[np.ix_(I, B)])
+        J = L.JB.toarray()
+        Ac = H.levels[i + 1].A.toarray()
+        assert np.abs(J.T @ S @ J - Ac).max() <= 1e-11 * np.abs(Ac).max()
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 1), (3, 4, 1)])
+def test_P9_local_correction_zeroes_interior_residual(d, n, k):
+    P, A, g = _problem(d, n, k)
+    H = mg.Hierarchy(A, d, n, k)
+    L = H.levels[0]
+    assert L.kind == "h"
+    rng = np.random.default_rng(2)
+    e = rng.standard_normal(A.shape[0])
+    r = g
+    rho = r - A @ e
+    e2 = e + H.local_correction(0, rho)
+    rho2 = r - A @ e2
+    assert np.abs(rho2[L.I_dofs]).max() <= 1e-11 * np.abs(rho).max()
+    assert np.allclose(L.Q @ rho2, L.JB.T @ rho2[L.B_dofs], rtol=0, atol=1e-11 * np.abs(rho).max())
+    # and the full restriction formula applied before the correction gives the same
+    assert np.allclose(L.Q @ rho, L.Q @ rho2, rtol=0, atol=1e-11 * np.abs(rho).max())
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 16, 1), (3, 4, 2)])
+def test_P10_nested_dissection_limit_is_direct(d, n, k):
+    P, A, g = _problem(d, n, k, lo=1e-1, hi=1e1)
+    H = mg.Hierarchy(A, d, n, k, coarse="exact", sweeps=0)
+    e = H.vcycle(g)
+    lam = spla.spsolve(A.tocsc(), g)
+    assert np.linalg.norm(g - A @ e) <= 1e-11 * np.linalg.norm(g)
+    assert np.abs(e - lam).max() <= 1e-9 * np.abs(lam).max()
+
+
+def _ex1_source(X):
+    """f = -lap u for u = x y exp(x^2 y^3), differentiated by hand."""
+    x, y = X[:, 0], X[:, 1]
+    e = np.exp(x ** 2 * y ** 3)
+    uxx = y * e * (6 * x * y ** 3 + 4 * x ** 3 * y ** 6)
+    uyy = x * e * (12 * x ** 2 * y ** 2 + 9 * x ** 4 * y ** 5)
+    return -(uxx + uyy)
+
+
+def _ex1(k, L, tau_mode, lc=mg.LC_PRE):
+    n = 2 ** L
+    tau = 1.0 if tau_mode == "tau2" else n / np.sqrt(2.0)  # tau = 1/h_min, h_min = diameter
+
+    def u(X):
+        return X[:, 0] * X[:, 1] * np.exp(X[:, 0] ** 2 * X[:, 1] ** 3)
+
+    P = HDG(2, n, k, tau, np.ones(n * n))
+    fn = _ex1_source(P.volume_nodes().reshape(-1, 2)).reshape(P.mesh.nel, -1)
+    A, g, _ = P.assemble(fn, u)
+    H = mg.Hierarchy(A, 2, n, k, sweeps=3, growth=2, local_corr=lc)
+    r1 = mg.mg_solve(H, A, g, tol=1e-9)
+    r2 = mg.gmres_solve(H, A, g, tol=1e-9, side="left")
+    return (r1.iters if r1.converged else "*"), (r2.iters if r2.converged else "*")
+
+
+def _golden():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "ex1_hdg_bj_iterations.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            conv = [x if x == "*" else int(x) for x in t[2:]]
+            rows[(t[0], int(t[1]))] = (conv[:4], conv[4:])
+    return rows
+
+
+def test_exact_solution_source_is_minus_laplacian():
+    """The hand-differentiated source of Example I against finite differences."""
+    X = np.array([[0.3, 0.7], [0.9, 0.2], [0.55, 0.95]])
+    eps = 1e-4
+
+    def u(X):
+        return X[:, 0] * X[:, 1] * np.exp(X[:, 0] ** 2 * X[:, 1] ** 3)
+    lap = np.zeros(len(X))
+    for c in range(2):
+        dX = np.zeros_like(X)
+        dX[:, c] = eps
+        lap += (u(X + dX) - 2 * u(X) + u(X - dX)) / eps ** 2
+    assert np.allclose(_ex1_source(X), -lap, rtol=1e-5)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_P12_paper_counts_tau1_exact(k):
+    gold = _golden()[("tau2", k)]
+    for j, L in enumerate([2, 3, 4, 5]):
+        assert _ex1(k, L, "tau2") == (gold[0][j], gold[1][j])
+
+
+@pytest.mark.parametrize("table,k", [("tau2", 3), ("tau2", 4), ("tau2", 5), ("tau1", 1), ("tau1", 2), ("tau1", 3)])
+def test_P12_paper_counts_within_two(table, k):
+    gold = _golden()[(table, k)]
+    for j, L in enumerate([2, 3, 4]):
+        mgc, gmc = _ex1(k, L, table)
+        assert abs(mgc - gold[0][j]) <= 2 and abs(gmc - gold[1][j]) <= 2, (L, mgc, gmc, gold)
+
+
+def test_P11_mesh_independence_k4():
+    counts = [_ex1(4, L, "tau2")[0] for L in [3, 4, 5]]
+    assert max(counts) - min(counts) <= 1, counts
+
+
+def test_P13_no_local_correction_diverges_for_p1_and_p3():
+    gold = _golden()
+    for L in [2, 3, 4]:
+        mgc, gmc = _ex1(1, L, "tau1", lc=mg.LC_NONE)
+        assert mgc == "*"
+        assert abs(gmc - gold[("nolc", 1)][1][L - 2]) <= 2
+    assert _ex1(3, 4, "tau1", lc=mg.LC_NONE)[0] == "*"
+    # with the local correction the same case converges
+    assert _ex1(3, 4, "tau1")[0] != "*"
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 1), (2, 8, 2), (3, 4, 1)])
+def test_P15_symmetric_cycle_is_spd(d, n, k):
+    P, A, g = _problem(d, n, k, lo=1e-3, hi=1e3)
+    H = mg.Hierarchy(A, d, n, k, local_corr=mg.LC_BOTH)
+    N = A.shape[0]
+    B = np.column_stack([H.vcycle(np.eye(N)[:, j]) for j in range(N)])
+    assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+
+
+@pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
+def test_outer_solvers_reach_direct_solution(method):
+    P, A, g = _problem(2, 16, 3, lo=1e-1, hi=1e1)
+    lam = spla.spsolve(A.tocsc(), g)
+    if method == "mg":
+        r = mg.mg_solve(mg.Hierarchy(A, 2, 16, 3), A, g, tol=1e-12)
+    elif method == "pcg":
+        r = mg.pcg_solve(mg.Hierarchy(A, 2, 16, 3, local_corr=mg.LC_BOTH), A, g, tol=1e-12)
+    else:
+        r = mg.gmres_solve(mg.Hierarchy(A, 2, 16, 3), A, g, tol=1e-12)
+    assert r.converged
+    assert np.linalg.norm(g - A @ r.lam) <= 1e-12 * np.linalg.norm(g)
+    assert np.abs(r.lam - lam).max() <= 1e-8 * np.abs(lam).max()

@@ -1,0 +1,181 @@
+/*
+ * hdg.h -- C ABI of the MI355X (gfx950) unified geometric multigrid solver
+ * for the statically condensed HDG trace system.
+ *
+ * The method: hybridized DG discretization of -div(kappa grad u) = f with
+ * Dirichlet data (Sec. 2, eqs. primal_elliptic, mixed_elliptic, HDG,
+ * HDG_flux), static condensation to the trace system A lambda = g
+ * (eq. trace_linear_system), and the multigrid of Sec. 3: p-coarsening to
+ * P1 (Sec. 3.1.1), h-coarsening by agglomeration (eq. trace_partition),
+ * DtN-based prolongation/restriction (eqs. n_1_Ik, n_g1_Ik, n_1_Qk,
+ * n_g1_Qk), Galerkin coarse operators (eqs. Akm1, ANm1), face-block Jacobi
+ * smoothing (Sec. 3.3, Sec. 4.1), local correction (eq. localCorrection),
+ * the V-cycle (Algorithm 1) used as a solver (Sec. 3.6) or as a CG/GMRES
+ * preconditioner (Sec. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh: the unit box [0,1]^d, d in {2,3}, n^d equal quads/hexes, h = 1/n.
+ *   Elements are numbered lexicographically, x fastest.
+ * Spaces: Q^k on elements, nodal at tensor Gauss-Lobatto-Legendre points
+ *   (x fastest); Q^k on faces (P^k in 2D) nodal at GLL points ordered by
+ *   increasing global coordinate, first tangential direction fastest.
+ * Trace vectors (lambda, g, residuals): interior faces only, face-major.
+ *   x-normal faces first, then y (then z); within a direction the faces
+ *   are lexicographic on the grid of extent n-1 along the normal and n
+ *   elsewhere (x fastest); (k+1)^(d-1) values per face.
+ * Boundary trace data: block (c, side) for c = 0..d-1, side = 0 (x_c=0),
+ *   1 (x_c=1); inside a block the n^(d-1) faces are lexicographic over the
+ *   tangential coordinates; (k+1)^(d-1) values per face.
+ * Volume arrays: u[N_T][(k+1)^d], q[N_T][d][(k+1)^d], nodal.
+ * Source: nodal values f[N_T][(k+1)^d] (its interpolant is integrated
+ *   exactly: load b_T = M_T f_T), or a load vector in the same layout.
+ * kappa: per element [N_T] (HDG_KAPPA_PER_ELEMENT) or at the tensor Gauss
+ *   points with k+2 points per direction [N_T][(k+2)^d] (HDG_KAPPA_AT_QP).
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller,
+ * except the option/info structs, which live on the host.  The library
+ * copies what it keeps and never frees caller memory.  The handle owns all
+ * internal device memory (allocated in setup/build, freed in destroy).
+ * Work is ordered on the stream given at setup; calls that fill an info
+ * struct synchronize that stream.  A handle is not thread-safe; distinct
+ * handles are independent.  Every call returns an hdg_status; nothing
+ * throws across the ABI.  On HDG_ERR_NOT_CONVERGED the output holds the
+ * last iterate and info is filled.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_problem* hdg_handle;
+
+typedef enum {
+  HDG_OK = 0,
+  HDG_ERR_INVALID_ARG = -1,   /* null pointer, bad size, kappa <= 0 or not finite, ... */
+  HDG_ERR_UNSUPPORTED = -2,   /* e.g. n not a power of two at mg_build, k or d out of range */
+  HDG_ERR_STATE = -3,         /* e.g. solve before mg_build */
+  HDG_ERR_NOT_CONVERGED = -4, /* max_it reached; outputs hold the last iterate */
+  HDG_ERR_BREAKDOWN = -5,     /* non-finite residual or zero Krylov denominator */
+  HDG_ERR_DEVICE = -6         /* a HIP call failed */
+} hdg_status;
+
+enum { HDG_KAPPA_PER_ELEMENT = 0, HDG_KAPPA_AT_QP = 1 };
+enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_MIXED = 1 };
+enum { HDG_LC_NONE = 0, HDG_LC_PRE = 1, HDG_LC_POST = 2, HDG_LC_BOTH = 3 };
+enum { HDG_METHOD_MG = 0, HDG_METHOD_PCG = 1, HDG_METHOD_GMRES = 2 };
+enum { HDG_RHS_F_NODAL = 0, HDG_RHS_F_LOAD = 1, HDG_RHS_TRACE = 2 };
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int n;            /* elements per direction; a power of two for mg_build */
+} hdg_mesh;
+
+typedef struct {
+  int sweeps;       /* block-Jacobi sweeps before and after the coarse correction on the finest level (default 2) */
+  int growth;       /* 1: same sweeps on every level; 2: doubled per coarser level (Sec. 3.3, beta0 = beta1 = 2) */
+  double omega;     /* block-Jacobi damping (default 1, Sec. 4.1) */
+  int local_corr;   /* HDG_LC_*: Algorithm 1 step 3 (PRE), step 5 (POST) or both */
+  int precision;    /* HDG_FP64 or HDG_MIXED (FP32 V-cycle inside FP64 outer iteration) */
+  int method;       /* HDG_METHOD_MG | PCG | GMRES (GMRES: right preconditioned, MGS) */
+  int max_it;       /* outer iteration limit (default 200, Sec. 4) */
+  int restart;      /* GMRES restart length (0: no restart up to max_it) */
+} hdg_mg_opts;
+
+typedef struct {
+  int iters;        /* outer iterations (V-cycles applied) */
+  double relres;    /* final ||g - A lambda||_2 / ||g||_2 computed in FP64 */
+  double t_solve_ms;/* stream time of the solve */
+  int n_levels;
+} hdg_solve_info;
+
+/* Fill opts with the defaults above (constant 2 sweeps, omega 1, step-3
+ * local correction, FP64, MG, 200 iterations). */
+void hdg_default_opts(hdg_mg_opts* opts);
+
+/* Form the element-local HDG problems and their DtN matrices
+ * A^e = tau H - S^T L^-1 R (static condensation, Sec. 2) on the device.
+ * k in 1..6 for d = 2, 1..3 for d = 3; tau > 0.  kappa: device array laid
+ * out per kappa_kind.  hip_stream: a hipStream_t (NULL = default stream).
+ * store_recovery != 0 keeps the per-element factors needed by
+ * hdg_reconstruct and hdg_adjoint.  On success *out owns the problem. */
+hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                     int store_recovery, void* hip_stream, hdg_handle* out);
+
+/* Re-form A^e for a new kappa (same layout rules); invalidates the
+ * hierarchy (call hdg_mg_build again). */
+hdg_status hdg_update_kappa(hdg_handle h, const double* kappa, int kappa_kind);
+
+/* Build the multigrid hierarchy of Sec. 3: J_N^T A J_N (eq. ANm1) for
+ * k > 1, then per h-level the macro-element Schur complements
+ * A_{k-1} = J^T (A_BB - A_BI A_II^-1 A_IB) J (eq. Akm1) with the local
+ * factors A_II^-1 and P = -A_II^-1 A_IB J, face-block inverses, and the
+ * coarsest dense inverse (B_1 = A_1^-1).  Needs n = 2^m, n >= 2. */
+hdg_status hdg_mg_build(hdg_handle h, const hdg_mg_opts* opts);
+
+/* One V-cycle e = B_L r on the finest level (Algorithm 1), r and e trace
+ * vectors of length N_lambda (double for HDG_FP64, float for HDG_FP32);
+ * nrhs vectors stored one after another. */
+hdg_status hdg_vcycle(hdg_handle h, const void* r, void* e, int precision, int nrhs);
+
+/* Right-hand side g of eq. trace_linear_system from a volume source
+ * (rhs_kind F_NODAL or F_LOAD, [N_T][(k+1)^d]) and optional Dirichlet
+ * boundary traces g_dirichlet (boundary layout, NULL = 0); g: [N_lambda]. */
+hdg_status hdg_rhs(hdg_handle h, const double* rhs, int rhs_kind, const double* g_dirichlet, double* g);
+
+/* Solve A lambda = g to ||g - A lambda||_2 <= tol ||g||_2 with the method of
+ * the build options.  rhs: volume source (F_NODAL/F_LOAD) or g itself
+ * (TRACE).  lambda: in = initial guess, out = solution, [nrhs][N_lambda]. */
+hdg_status hdg_solve(hdg_handle h, const double* rhs, int rhs_kind, const double* g_dirichlet, int nrhs,
+                     double tol, double* lambda, hdg_solve_info* info);
+
+/* Local recovery (q, u) = L_T^-1 (R_T Lambda_T + [0; b_T]) element by
+ * element (Sec. 2); needs store_recovery at setup. */
+hdg_status hdg_reconstruct(hdg_handle h, const double* lambda, const double* rhs, int rhs_kind,
+                           const double* g_dirichlet, double* u, double* q);
+
+/* Adjoint gradient: given the forward flux q_fwd [N_T][d][(k+1)^d] and the
+ * misfit derivative dJdu in load form ([N_T][(k+1)^d], j_T = dJ/du_T),
+ * solve the adjoint trace system (the forward operator with load j), recover
+ * q*, and return grad[T] = dJ/d(log kappa_T) = -(q*_T)^T A_T q_T, A_T the
+ * kappa^-1 weighted mass.  Derived from eqs. HDG and HDG_flux. */
+hdg_status hdg_adjoint(hdg_handle h, const double* dJdu, const double* q_fwd, double tol,
+                       double* grad_log_kappa, hdg_solve_info* info);
+
+/* M_T u_T per element (the volume mass matrix), to turn nodal misfits into
+ * loads: out[N_T][(k+1)^d]. */
+hdg_status hdg_mass_apply(hdg_handle h, const double* u, double* out);
+
+/* Inspection: y = A_l x on level l (0 = finest), precision per HDG_FP64/FP32. */
+hdg_status hdg_level_apply(hdg_handle h, int level, const void* x, void* y, int precision);
+
+/* Inspection: m face-block Jacobi sweeps on A_l e = r from e = 0. */
+hdg_status hdg_level_smooth(hdg_handle h, int level, const void* r, void* e, int sweeps, int precision);
+
+/* Inspection: copy the element-form local matrices of level l
+ * ([N_macro][n_loc][n_loc] row-major, local DOFs ordered by face slot
+ * x-,x+,y-,y+,(z-,z+) then node) into out (device, double). */
+hdg_status hdg_level_export(hdg_handle h, int level, double* out);
+
+enum {
+  HDG_Q_NT = 0, HDG_Q_NLAMBDA = 1, HDG_Q_NLEVELS = 2, HDG_Q_NV = 3, HDG_Q_NQ = 4,
+  HDG_Q_LEVEL_NLAMBDA = 100, /* + level */
+  HDG_Q_LEVEL_N = 200,       /* + level: macro-elements per direction */
+  HDG_Q_LEVEL_NE = 300,      /* + level: DOFs per face */
+  HDG_Q_DEVICE_BYTES = 400
+};
+hdg_status hdg_query(hdg_handle h, int what, long long* out);
+
+/* GLL nodes (k+1 values on [0,1]) and Gauss points (k+2 values) used by the
+ * library, written to host arrays. */
+hdg_status hdg_reference_nodes(int k, double* gll, double* gauss);
+
+hdg_status hdg_destroy(hdg_handle h);
+const char* hdg_status_string(hdg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

@@ -1,0 +1,92 @@
+"""ctypes declarations of the C ABI in include/hdg.h (marshalling only)."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libhdg.so")
+
+HDG_OK, HDG_ERR_INVALID_ARG, HDG_ERR_UNSUPPORTED, HDG_ERR_STATE = 0, -1, -2, -3
+HDG_ERR_NOT_CONVERGED, HDG_ERR_BREAKDOWN, HDG_ERR_DEVICE = -4, -5, -6
+KAPPA_PER_ELEMENT, KAPPA_AT_QP = 0, 1
+FP64, FP32, MIXED = 0, 1, 1
+LC_NONE, LC_PRE, LC_POST, LC_BOTH = 0, 1, 2, 3
+METHOD_MG, METHOD_PCG, METHOD_GMRES = 0, 1, 2
+RHS_F_NODAL, RHS_F_LOAD, RHS_TRACE = 0, 1, 2
+Q_NT, Q_NLAMBDA, Q_NLEVELS, Q_NV, Q_NQ = 0, 1, 2, 3, 4
+Q_LEVEL_NLAMBDA, Q_LEVEL_N, Q_LEVEL_NE, Q_DEVICE_BYTES = 100, 200, 300, 400
+
+EXPORTS = [
+    "hdg_default_opts", "hdg_setup", "hdg_update_kappa", "hdg_mg_build", "hdg_vcycle", "hdg_rhs", "hdg_solve",
+    "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
+    "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
+]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("growth", ctypes.c_int), ("omega", ctypes.c_double),
+                ("local_corr", ctypes.c_int), ("precision", ctypes.c_int), ("method", ctypes.c_int),
+                ("max_it", ctypes.c_int), ("restart", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("n_levels", ctypes.c_int)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I = ctypes.c_int
+D = ctypes.c_double
+
+
+def load():
+    """Open libhdg.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_1811_09909_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "hdg_default_opts": (None, [ctypes.POINTER(Opts)]),
+        "hdg_setup": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, P, ctypes.POINTER(P)]),
+        "hdg_update_kappa": (I, [P, P, I]),
+        "hdg_mg_build": (I, [P, ctypes.POINTER(Opts)]),
+        "hdg_vcycle": (I, [P, P, P, I, I]),
+        "hdg_rhs": (I, [P, P, I, P, P]),
+        "hdg_solve": (I, [P, P, I, P, I, D, P, ctypes.POINTER(Info)]),
+        "hdg_reconstruct": (I, [P, P, P, I, P, P, P]),
+        "hdg_adjoint": (I, [P, P, P, D, P, ctypes.POINTER(Info)]),
+        "hdg_mass_apply": (I, [P, P, P]),
+        "hdg_level_apply": (I, [P, I, P, P, I]),
+        "hdg_level_smooth": (I, [P, I, P, P, I, I]),
+        "hdg_level_export": (I, [P, I, P]),
+        "hdg_query": (I, [P, I, ctypes.POINTER(ctypes.c_longlong)]),
+        "hdg_reference_nodes": (I, [I, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "hdg_destroy": (I, [P]),
+        "hdg_status_string": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HDGError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = load().hdg_status_string(status).decode()
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+def check(status, where, allow=()):
+    if status != HDG_OK and status not in allow:
+        raise HDGError(status, where)
+    return status

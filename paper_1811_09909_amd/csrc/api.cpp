@@ -1,0 +1,799 @@
+// C ABI of the HDG trace multigrid library: problem setup, hierarchy build,
+// V-cycle (Algorithm 1) and the outer iterations (Sec. 3.6 and Sec. 4), all
+// driving the HIP kernels of element.hip, build.hip, trace.hip, blas.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "blas.hpp"
+#include "hdg_internal.hpp"
+
+using namespace hdg;
+
+struct hdg_problem {
+  int d = 0, n = 0, k = 0;
+  double tau = 1.0;
+  hipStream_t st = nullptr;
+  RefElement ref;
+  RefDevice rd;
+  long nelem = 0;
+  int nv = 0, ne = 0, nl = 0, nq = 0;
+  double *kqp = nullptr, *Ae = nullptr, *W = nullptr, *Kinv = nullptr, *Minv = nullptr, *ework = nullptr;
+  int* bad = nullptr;
+  int* hbad = nullptr;
+  bool store_recovery = false;
+  bool built = false;
+  hdg_mg_opts opts{};
+  std::vector<Level> L;
+  long N = 0;  // trace DOFs of the finest level
+  double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *zold = nullptr, *lam = nullptr;
+  double *ustar = nullptr, *qstar = nullptr;
+  Scratch s;
+  double* hpin = nullptr;
+  // GMRES
+  double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gsv = nullptr, *y = nullptr;
+  int gm_m = 0;
+  std::vector<void*> allocs;        // freed in destroy
+  std::vector<void*> build_allocs;  // freed on rebuild
+  long long bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+T* dalloc(hdg_problem* P, long count, bool build) {
+  if (count <= 0) count = 1;
+  void* ptr = nullptr;
+  HDG_CHECK(hipMalloc(&ptr, sizeof(T) * (size_t)count));
+  (build ? P->build_allocs : P->allocs).push_back(ptr);
+  P->bytes += (long long)sizeof(T) * count;
+  return (T*)ptr;
+}
+
+template <typename T>
+T* upload(hdg_problem* P, const std::vector<T>& v) {
+  T* d = dalloc<T>(P, (long)v.size(), false);
+  HDG_CHECK(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return d;
+}
+
+long ipow(long b, int e) {
+  long r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+void init_level(Level& L, int d, int n, int ne) {
+  L.d = d;
+  L.n = n;
+  L.ne = ne;
+  L.nl = 2 * d * ne;
+  L.nelem = ipow(n, d);
+  L.nfd = n >= 1 ? (long)(n - 1) * ipow(n, d - 1) : 0;
+  L.nface = d * L.nfd;
+  L.nlam = L.nface * ne;
+}
+
+hdg_status map_error(const HipError& e) {
+  (void)e;
+  return HDG_ERR_DEVICE;
+}
+
+#define HDG_GUARD_BEGIN try {
+#define HDG_GUARD_END                        \
+  }                                          \
+  catch (const HipError& e) {                \
+    return map_error(e);                     \
+  }                                          \
+  catch (const std::bad_alloc&) {            \
+    return HDG_ERR_DEVICE;                   \
+  }
+
+bool check_kappa(hdg_problem* P, const double* kappa, int kind) {
+  HDG_CHECK(hipMemsetAsync(P->bad, 0, sizeof(int), P->st));
+  launch_kappa_expand(P->nelem, P->nq, kappa, kind, P->kqp, P->bad, P->st);
+  HDG_CHECK(hipMemcpyAsync(P->hbad, P->bad, sizeof(int), hipMemcpyDeviceToHost, P->st));
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  return *P->hbad == 0;
+}
+
+void form_elements(hdg_problem* P) {
+  launch_element_dtn(P->d, P->k, P->nelem, P->tau, P->rd, P->kqp, P->Ae, P->W, P->Kinv, P->Minv, P->st);
+}
+
+void free_build(hdg_problem* P) {
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  for (void* ptr : P->build_allocs) HDG_CHECK(hipFree(ptr));
+  P->build_allocs.clear();
+  P->L.clear();
+  P->built = false;
+  P->V = P->Z = P->H = P->cs = P->sn = P->gsv = P->y = nullptr;
+  P->gm_m = 0;
+}
+
+// -------------------------------------------------------------------------
+// Algorithm 1 on level i; returns the device pointer holding e = B_i r.
+// If `out` is given the result is written there.
+template <typename T>
+T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
+  Level& L = P->L[i];
+  const int pr = sizeof(T) == 8 ? 0 : 1;
+  hipStream_t st = P->st;
+  T* e = (T*)L.e[pr];
+  T* w = (T*)L.w[pr];
+  if (L.kind == 2) {
+    T* dst = out ? out : e;
+    launch_coarse_solve<T>(L, r, dst, st);
+    return dst;
+  }
+  const int m = L.sweeps;
+  const int lc = P->opts.local_corr;
+  // pre-smoothing from e = 0
+  if (m >= 1)
+    launch_jacobi0<T>(L, r, e, st);
+  else
+    blas_fill<T>(e, T(0), L.nlam, st);
+  for (int s = 1; s < m; ++s) {
+    launch_apply<T>(L, APPLY_SWEEP, e, r, w, nullptr, nullptr, st);
+    std::swap(e, w);
+  }
+  Level& C = P->L[i + 1];
+  T* rc = (T*)C.r[pr];
+  if (L.kind == 0) {
+    launch_apply<T>(L, APPLY_RES_PRESTRICT, e, r, nullptr, P->rd.Jp, rc, st);
+  } else {
+    launch_apply<T>(L, APPLY_RES, e, r, w, nullptr, nullptr, st);
+    launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st);
+    launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st);
+  }
+  const T* ec = vcycle<T>(P, i + 1, rc, nullptr);
+  if (L.kind == 0)
+    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st);
+  else
+    launch_hprolong<T>(L, C, ec, e, st);
+  if (L.kind == 1 && (lc & HDG_LC_POST)) {
+    launch_apply<T>(L, APPLY_RES, e, r, w, nullptr, nullptr, st);
+    launch_hcorr<T>(L, w, e, 1, 0, nullptr, st);
+  }
+  for (int s = 0; s < m; ++s) {
+    T* dst = (out && s == m - 1) ? out : w;
+    launch_apply<T>(L, APPLY_SWEEP, e, r, dst, nullptr, nullptr, st);
+    if (dst == w) std::swap(e, w);
+    else e = dst;
+  }
+  if (out && e != out) {
+    HDG_CHECK(hipMemcpyAsync(out, e, sizeof(T) * L.nlam, hipMemcpyDeviceToDevice, st));
+    e = out;
+  }
+  return e;
+}
+
+// z = B r in FP64 or with an FP32 V-cycle (mixed precision)
+void precond(hdg_problem* P, const double* r, double* z, bool mixed) {
+  if (!mixed) {
+    vcycle<double>(P, 0, r, z);
+    return;
+  }
+  Level& L0 = P->L[0];
+  float* r32 = (float*)L0.r[1];
+  blas_d2f(r, r32, P->N, P->st);
+  float* e32 = vcycle<float>(P, 0, r32, nullptr);
+  blas_f2d(e32, z, P->N, P->st);
+}
+
+double read_scalar(hdg_problem* P, const double* dptr) {
+  HDG_CHECK(hipMemcpyAsync(P->hpin, dptr, sizeof(double), hipMemcpyDeviceToHost, P->st));
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  return P->hpin[0];
+}
+
+void residual(hdg_problem* P, const double* lam, const double* g, double* r) {
+  launch_apply<double>(P->L[0], APPLY_RES, lam, g, r, nullptr, nullptr, P->st);
+}
+
+struct SolveOut {
+  int iters = 0;
+  double relres = 0.0;
+  hdg_status status = HDG_OK;
+};
+
+SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
+  SolveOut o;
+  const long N = P->N;
+  residual(P, lam, g, P->r);
+  blas_dot(P->r, P->r, N, P->s, FIN_STORE, P->s.sc + SC_RNORM2, P->st);
+  double rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
+  while (rel > tol && o.iters < P->opts.max_it && std::isfinite(rel)) {
+    precond(P, P->r, P->z, mixed);
+    blas_axpy(lam, P->z, N, nullptr, 1.0, P->st);
+    residual(P, lam, g, P->r);
+    blas_dot(P->r, P->r, N, P->s, FIN_STORE, P->s.sc + SC_RNORM2, P->st);
+    rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
+    ++o.iters;
+  }
+  o.relres = rel;
+  o.status = !std::isfinite(rel) ? HDG_ERR_BREAKDOWN : (rel <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED);
+  return o;
+}
+
+SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
+  SolveOut o;
+  const long N = P->N;
+  hipStream_t st = P->st;
+  double* sc = P->s.sc;
+  for (;;) {
+    residual(P, lam, g, P->r);
+    blas_dot(P->r, P->r, N, P->s, FIN_STORE, sc + SC_RNORM2, st);
+    double rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
+    o.relres = rel;
+    if (!std::isfinite(rel)) {
+      o.status = HDG_ERR_BREAKDOWN;
+      return o;
+    }
+    if (rel <= tol || o.iters >= P->opts.max_it) break;
+    precond(P, P->r, P->z, mixed);
+    blas_dot(P->r, P->z, N, P->s, FIN_RZ0, nullptr, st);
+    blas_copy(P->p, P->z, N, st);
+    while (o.iters < P->opts.max_it) {
+      launch_apply<double>(P->L[0], APPLY_Y, P->p, nullptr, P->Ap, nullptr, nullptr, st);
+      blas_dot(P->p, P->Ap, N, P->s, FIN_ALPHA, nullptr, st);
+      blas_cg_update(lam, P->r, P->p, P->Ap, N, P->s, st);
+      ++o.iters;
+      rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
+      if (rel <= tol || !std::isfinite(rel)) break;
+      if (mixed) blas_copy(P->zold, P->z, N, st);
+      precond(P, P->r, P->z, mixed);
+      if (mixed)
+        blas_dot2_flex(P->r, P->z, P->zold, N, P->s, st);
+      else
+        blas_dot(P->r, P->z, N, P->s, FIN_BETA, nullptr, st);
+      blas_cg_direction(P->p, P->z, N, P->s, st);
+    }
+    if (!std::isfinite(rel)) {
+      o.relres = rel;
+      o.status = HDG_ERR_BREAKDOWN;
+      return o;
+    }
+    // confirm with the true residual (loop again from the current iterate)
+  }
+  o.status = o.relres <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED;
+  return o;
+}
+
+SolveOut solve_gmres(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
+  SolveOut o;
+  const long N = P->N;
+  hipStream_t st = P->st;
+  double* sc = P->s.sc;
+  const int m = P->gm_m;
+  const long ld = N;
+  for (;;) {
+    residual(P, lam, g, P->r);
+    blas_dot(P->r, P->r, N, P->s, FIN_NORM_INV, sc + SC_HNORM, st);
+    double beta = read_scalar(P, sc + SC_HNORM);
+    o.relres = beta / gn;
+    if (!std::isfinite(beta)) {
+      o.status = HDG_ERR_BREAKDOWN;
+      return o;
+    }
+    if (o.relres <= tol || o.iters >= P->opts.max_it) break;
+    blas_scale(P->V, P->r, N, sc + SC_TMP, st);
+    blas_fill<double>(P->gsv, 0.0, m + 1, st);
+    HDG_CHECK(hipMemcpyAsync(P->gsv, sc + SC_HNORM, sizeof(double), hipMemcpyDeviceToDevice, st));
+    int j = 0;
+    while (j < m && o.iters < P->opts.max_it) {
+      double* vj = P->V + j * ld;
+      double* zj = P->Z + j * ld;
+      double* w = P->V + (j + 1) * ld;
+      precond(P, vj, zj, mixed);
+      launch_apply<double>(P->L[0], APPLY_Y, zj, nullptr, w, nullptr, nullptr, st);
+      double* hcol = P->H + (long)j * (m + 1);
+      for (int i = 0; i <= j; ++i) {
+        blas_dot(w, P->V + i * ld, N, P->s, FIN_STORE, hcol + i, st);
+        blas_axpy(w, P->V + i * ld, N, hcol + i, -1.0, st);
+      }
+      blas_dot(w, w, N, P->s, FIN_NORM_INV, hcol + j + 1, st);
+      blas_scale(w, w, N, sc + SC_TMP, st);
+      blas_gmres_rot(P->H, P->cs, P->sn, P->gsv, j, m + 1, sc, st);
+      ++j;
+      ++o.iters;
+      double res = read_scalar(P, sc + SC_GRES);
+      if (!std::isfinite(res)) {
+        o.status = HDG_ERR_BREAKDOWN;
+        return o;
+      }
+      if (res / gn <= tol) break;
+    }
+    blas_gmres_backsolve(P->H, P->gsv, j, m + 1, P->y, st);
+    blas_gmres_combine(lam, P->Z, ld, j, P->y, N, st);
+  }
+  o.status = o.relres <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED;
+  return o;
+}
+
+void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g) {
+  launch_element_load(P->d, P->k, P->nelem, P->rd, rhs, kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->ework, P->st);
+  launch_load_pull(P->d, P->k, P->n, P->ework, P->Ae, gdir, g, P->st);
+}
+
+hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, hdg_solve_info* info) {
+  const long N = P->N;
+  if (N == 0) {
+    if (info) info->relres = 0.0;
+    return HDG_OK;
+  }
+  blas_dot(g, g, N, P->s, FIN_STORE, P->s.sc + SC_GNORM2, P->st);
+  const double gn = std::sqrt(read_scalar(P, P->s.sc + SC_GNORM2));
+  if (!std::isfinite(gn)) return HDG_ERR_BREAKDOWN;
+  if (gn == 0.0) {
+    blas_fill<double>(lam, 0.0, N, P->st);
+    if (info) {
+      info->iters = 0;
+      info->relres = 0.0;
+    }
+    return HDG_OK;
+  }
+  const bool mixed = P->opts.precision == HDG_MIXED;
+  SolveOut o;
+  switch (P->opts.method) {
+    case HDG_METHOD_PCG: o = solve_pcg(P, g, lam, tol, gn, mixed); break;
+    case HDG_METHOD_GMRES: o = solve_gmres(P, g, lam, tol, gn, mixed); break;
+    default: o = solve_mg(P, g, lam, tol, gn, mixed); break;
+  }
+  if (info) {
+    info->iters += o.iters;
+    info->relres = std::max(info->relres, o.relres);
+  }
+  return o.status;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+void hdg_default_opts(hdg_mg_opts* o) {
+  if (!o) return;
+  o->sweeps = 2;
+  o->growth = 1;
+  o->omega = 1.0;
+  o->local_corr = HDG_LC_PRE;
+  o->precision = HDG_FP64;
+  o->method = HDG_METHOD_MG;
+  o->max_it = 200;
+  o->restart = 0;
+}
+
+const char* hdg_status_string(hdg_status s) {
+  switch (s) {
+    case HDG_OK: return "ok";
+    case HDG_ERR_INVALID_ARG: return "invalid argument";
+    case HDG_ERR_UNSUPPORTED: return "unsupported";
+    case HDG_ERR_STATE: return "wrong state";
+    case HDG_ERR_NOT_CONVERGED: return "not converged";
+    case HDG_ERR_BREAKDOWN: return "breakdown";
+    case HDG_ERR_DEVICE: return "device error";
+  }
+  return "unknown";
+}
+
+hdg_status hdg_reference_nodes(int k, double* gll, double* gauss) {
+  if (k < 1 || k > 12 || !gll || !gauss) return HDG_ERR_INVALID_ARG;
+  std::vector<double> x, gx, gw;
+  gll_points(k, x);
+  gauss_points(k + 2, gx, gw);
+  std::memcpy(gll, x.data(), sizeof(double) * (k + 1));
+  std::memcpy(gauss, gx.data(), sizeof(double) * (k + 2));
+  return HDG_OK;
+}
+
+hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                     int store_recovery, void* hip_stream, hdg_handle* out) {
+  if (!mesh || !out || !kappa) return HDG_ERR_INVALID_ARG;
+  if (mesh->dim != 2 && mesh->dim != 3) return HDG_ERR_UNSUPPORTED;
+  if (mesh->n < 1 || mesh->n > (mesh->dim == 2 ? 8192 : 512)) return HDG_ERR_INVALID_ARG;
+  if (k < 1 || (mesh->dim == 2 && k > 6) || (mesh->dim == 3 && k > 3)) return HDG_ERR_UNSUPPORTED;
+  if (!(tau > 0.0) || !std::isfinite(tau)) return HDG_ERR_INVALID_ARG;
+  if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  hdg_problem* P = new (std::nothrow) hdg_problem();
+  if (!P) return HDG_ERR_DEVICE;
+  HDG_GUARD_BEGIN
+  P->d = mesh->dim;
+  P->n = mesh->n;
+  P->k = k;
+  P->tau = tau;
+  P->st = (hipStream_t)hip_stream;
+  P->store_recovery = store_recovery != 0;
+  P->ref.build(P->d, k, 1.0 / P->n);
+  P->nv = P->ref.nv;
+  P->ne = P->ref.ne;
+  P->nl = P->ref.nl;
+  P->nq = P->ref.nq;
+  P->nelem = ipow(P->n, P->d);
+  P->rd.Phi = upload(P, P->ref.Phi);
+  P->rd.Wq = upload(P, P->ref.Wq);
+  P->rd.B = upload(P, P->ref.B);
+  P->rd.F = upload(P, P->ref.F);
+  P->rd.G = upload(P, P->ref.G);
+  P->rd.E = upload(P, P->ref.E);
+  P->rd.H = upload(P, P->ref.H);
+  P->rd.M = upload(P, P->ref.M);
+  P->rd.Jp = upload(P, P->ref.Jp);
+  P->kqp = dalloc<double>(P, P->nelem * P->nq, false);
+  P->Ae = dalloc<double>(P, P->nelem * P->nl * P->nl, false);
+  P->W = dalloc<double>(P, P->nelem * P->nv * P->nl, false);
+  if (P->store_recovery) {
+    P->Kinv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
+    P->Minv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
+  }
+  P->ework = dalloc<double>(P, P->nelem * (P->nv + P->nl), false);
+  P->bad = dalloc<int>(P, 1, false);
+  HDG_CHECK(hipHostMalloc((void**)&P->hbad, sizeof(int) * 4, hipHostMallocDefault));
+  HDG_CHECK(hipHostMalloc((void**)&P->hpin, sizeof(double) * 16, hipHostMallocDefault));
+  P->s.sc = dalloc<double>(P, SC_COUNT, false);
+  P->s.partials = dalloc<double>(P, 2 * 512, false);
+  P->s.counter = dalloc<unsigned>(P, 1, false);
+  HDG_CHECK(hipMemsetAsync(P->s.counter, 0, sizeof(unsigned), P->st));
+  HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT, P->st));
+  if (!check_kappa(P, kappa, kappa_kind)) {
+    hdg_destroy(P);
+    return HDG_ERR_INVALID_ARG;
+  }
+  form_elements(P);
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  hdg_default_opts(&P->opts);
+  *out = P;
+  return HDG_OK;
+  }
+  catch (const HipError& e) {
+    hdg_destroy(P);
+    return map_error(e);
+  }
+  catch (const std::bad_alloc&) {
+    hdg_destroy(P);
+    return HDG_ERR_DEVICE;
+  }
+}
+
+hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
+  if (!P || !kappa) return HDG_ERR_INVALID_ARG;
+  if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  if (!check_kappa(P, kappa, kappa_kind)) return HDG_ERR_INVALID_ARG;
+  free_build(P);
+  form_elements(P);
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
+  if (!P) return HDG_ERR_INVALID_ARG;
+  hdg_mg_opts o;
+  if (opts)
+    o = *opts;
+  else
+    hdg_default_opts(&o);
+  if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
+      o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
+      o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0)
+    return HDG_ERR_INVALID_ARG;
+  if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
+  HDG_GUARD_BEGIN
+  free_build(P);
+  P->opts = o;
+  const int d = P->d;
+  const int nc = 1 << (d - 1);
+  std::vector<Level>& L = P->L;
+  L.emplace_back();
+  init_level(L[0], d, P->n, P->ne);
+  L[0].Aelem = P->Ae;
+  L[0].own_Aelem = false;
+  if (P->k > 1 && P->n >= 2) {
+    L[0].kind = 0;
+    L.emplace_back();
+    init_level(L[1], d, P->n, nc);
+    L[1].Aelem = dalloc<double>(P, L[1].nelem * L[1].nl * L[1].nl, true);
+    launch_pgalerkin(d, P->ne, P->nelem, P->rd.Jp, P->Ae, L[1].Aelem, P->st);
+  }
+  while (L.back().n > 2) {
+    const size_t fi = L.size() - 1;
+    L.emplace_back();
+    Level& F = L[fi];
+    Level& C = L.back();
+    F.kind = 1;
+    init_level(C, d, F.n / 2, nc);
+    F.nmacro = C.nelem;
+    F.nI = d * nc * nc;
+    F.ncl = 2 * d * nc;
+    const long pm = pad64(F.nmacro);
+    F.AIIinv64 = dalloc<double>(P, pm * F.nI * F.nI, true);
+    F.AIIinv32 = dalloc<float>(P, pm * F.nI * F.nI, true);
+    F.P64 = dalloc<double>(P, pm * F.nI * F.ncl, true);
+    F.P32 = dalloc<float>(P, pm * F.nI * F.ncl, true);
+    F.cb[0] = dalloc<double>(P, F.nmacro * F.ncl, true);
+    F.cb[1] = dalloc<float>(P, F.nmacro * F.ncl, true);
+    C.Aelem = dalloc<double>(P, C.nelem * C.nl * C.nl, true);
+    launch_macro_schur(F, C, P->st);
+  }
+  Level& Lc = L.back();
+  Lc.kind = 2;
+  if (Lc.nlam > 64) return HDG_ERR_UNSUPPORTED;
+  if (Lc.nlam > 0) {
+    Lc.Ainv64 = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
+    Lc.Ainv32 = dalloc<float>(P, Lc.nlam * Lc.nlam, true);
+    launch_coarse_inverse(Lc, P->st);
+  }
+  for (size_t i = 0; i < L.size(); ++i) {
+    Level& Li = L[i];
+    Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min<size_t>(i, 20)) : 1);
+    const long pf = pad64(Li.nface);
+    Li.Af64 = dalloc<double>(P, pf * 2 * Li.nl * Li.ne, true);
+    Li.Af32 = dalloc<float>(P, pf * 2 * Li.nl * Li.ne, true);
+    Li.Dinv64 = dalloc<double>(P, pf * Li.ne * Li.ne, true);
+    Li.Dinv32 = dalloc<float>(P, pf * Li.ne * Li.ne, true);
+    for (int pr = 0; pr < 2; ++pr) {
+      const size_t es = pr == 0 ? sizeof(double) : sizeof(float);
+      for (void** slot : {&Li.r[pr], &Li.e[pr], &Li.w[pr]}) {
+        if (pr == 0)
+          *slot = dalloc<double>(P, Li.nlam, true);
+        else
+          *slot = dalloc<float>(P, Li.nlam, true);
+        (void)es;
+      }
+    }
+    if (Li.nface > 0) {
+      launch_face_major(Li, P->st);
+      launch_dinv(Li, o.omega, P->st);
+    }
+  }
+  P->N = L[0].nlam;
+  const long N = P->N;
+  P->g = dalloc<double>(P, N, true);
+  P->r = dalloc<double>(P, N, true);
+  P->z = dalloc<double>(P, N, true);
+  P->p = dalloc<double>(P, N, true);
+  P->Ap = dalloc<double>(P, N, true);
+  P->zold = dalloc<double>(P, N, true);
+  P->lam = dalloc<double>(P, N, true);
+  if (o.method == HDG_METHOD_GMRES) {
+    const int m = o.restart > 0 ? std::min(o.restart, std::max(o.max_it, 1)) : std::max(o.max_it, 1);
+    P->gm_m = m;
+    P->V = dalloc<double>(P, (long)(m + 1) * N, true);
+    P->Z = dalloc<double>(P, (long)m * N, true);
+    P->H = dalloc<double>(P, (long)(m + 1) * (m + 1), true);
+    P->cs = dalloc<double>(P, m + 1, true);
+    P->sn = dalloc<double>(P, m + 1, true);
+    P->gsv = dalloc<double>(P, m + 2, true);
+    P->y = dalloc<double>(P, m + 1, true);
+  }
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  P->built = true;
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_vcycle(hdg_handle P, const void* r, void* e, int precision, int nrhs) {
+  if (!P || !r || !e || nrhs < 1) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  if (precision != HDG_FP64 && precision != HDG_FP32) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  for (int i = 0; i < nrhs; ++i) {
+    if (P->N == 0) break;
+    if (precision == HDG_FP64)
+      vcycle<double>(P, 0, (const double*)r + i * P->N, (double*)e + i * P->N);
+    else
+      vcycle<float>(P, 0, (const float*)r + i * P->N, (float*)e + i * P->N);
+  }
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_rhs(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, double* g) {
+  if (!P || !rhs || !g) return HDG_ERR_INVALID_ARG;
+  if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  form_rhs(P, rhs, rhs_kind, gdir, g);
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, int nrhs, double tol,
+                     double* lambda, hdg_solve_info* info) {
+  if (!P || !rhs || !lambda || nrhs < 1 || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  HDG_GUARD_BEGIN
+  if (info) {
+    info->iters = 0;
+    info->relres = 0.0;
+    info->t_solve_ms = 0.0;
+    info->n_levels = (int)P->L.size();
+  }
+  hipEvent_t e0, e1;
+  HDG_CHECK(hipEventCreate(&e0));
+  HDG_CHECK(hipEventCreate(&e1));
+  HDG_CHECK(hipEventRecord(e0, P->st));
+  hdg_status worst = HDG_OK;
+  const long vstride = P->nelem * P->nv;
+  for (int i = 0; i < nrhs; ++i) {
+    const double* g = nullptr;
+    if (rhs_kind == HDG_RHS_TRACE) {
+      g = rhs + i * P->N;
+    } else {
+      form_rhs(P, rhs + i * vstride, rhs_kind, gdir, P->g);
+      g = P->g;
+    }
+    hdg_status s = solve_one(P, g, lambda + i * P->N, tol, info);
+    if (s != HDG_OK && worst == HDG_OK) worst = s;
+  }
+  HDG_CHECK(hipEventRecord(e1, P->st));
+  HDG_CHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HDG_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  if (info) info->t_solve_ms = ms;
+  HDG_CHECK(hipEventDestroy(e0));
+  HDG_CHECK(hipEventDestroy(e1));
+  return worst;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs, int rhs_kind,
+                           const double* gdir, double* u, double* q) {
+  if (!P || !lambda || !rhs || !u || !q) return HDG_ERR_INVALID_ARG;
+  if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
+  if (!P->store_recovery) return HDG_ERR_STATE;
+  HDG_GUARD_BEGIN
+  launch_reconstruct(P->d, P->k, P->n, P->rd, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
+                     P->Minv, P->ework, u, q, P->st);
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, double tol, double* grad,
+                       hdg_solve_info* info) {
+  if (!P || !dJdu || !q_fwd || !grad || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  if (!P->built || !P->store_recovery) return HDG_ERR_STATE;
+  HDG_GUARD_BEGIN
+  if (!P->ustar) {
+    P->ustar = dalloc<double>(P, P->nelem * P->nv, false);
+    P->qstar = dalloc<double>(P, P->nelem * P->d * P->nv, false);
+  }
+  if (info) {
+    info->iters = 0;
+    info->relres = 0.0;
+    info->t_solve_ms = 0.0;
+    info->n_levels = (int)P->L.size();
+  }
+  form_rhs(P, dJdu, HDG_RHS_F_LOAD, nullptr, P->g);
+  blas_fill<double>(P->lam, 0.0, P->N, P->st);
+  hdg_status s = solve_one(P, P->g, P->lam, tol, info);
+  launch_reconstruct(P->d, P->k, P->n, P->rd, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
+                     P->ustar, P->qstar, P->st);
+  launch_grad(P->d, P->k, P->nelem, P->rd, P->kqp, q_fwd, P->qstar, grad, P->st);
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  return s;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_mass_apply(hdg_handle P, const double* u, double* out) {
+  if (!P || !u || !out) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  launch_mass(P->d, P->k, P->nelem, P->rd, u, out, P->st);
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_level_apply(hdg_handle P, int level, const void* x, void* y, int precision) {
+  if (!P || !x || !y) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  if (level < 0 || level >= (int)P->L.size()) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  const Level& L = P->L[level];
+  if (precision == HDG_FP64)
+    launch_apply<double>(L, APPLY_Y, (const double*)x, nullptr, (double*)y, nullptr, nullptr, P->st);
+  else if (precision == HDG_FP32)
+    launch_apply<float>(L, APPLY_Y, (const float*)x, nullptr, (float*)y, nullptr, nullptr, P->st);
+  else
+    return HDG_ERR_INVALID_ARG;
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_level_smooth(hdg_handle P, int level, const void* r, void* e, int sweeps, int precision) {
+  if (!P || !r || !e || sweeps < 0) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  if (level < 0 || level >= (int)P->L.size()) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  Level& L = P->L[level];
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const int pr = sizeof(T) == 8 ? 0 : 1;
+    T* a = (T*)L.e[pr];
+    T* b = (T*)L.w[pr];
+    if (sweeps == 0) {
+      blas_fill<T>((T*)e, T(0), L.nlam, P->st);
+      return;
+    }
+    launch_jacobi0<T>(L, (const T*)r, a, P->st);
+    for (int s = 1; s < sweeps; ++s) {
+      launch_apply<T>(L, APPLY_SWEEP, a, (const T*)r, b, nullptr, nullptr, P->st);
+      std::swap(a, b);
+    }
+    HDG_CHECK(hipMemcpyAsync(e, a, sizeof(T) * L.nlam, hipMemcpyDeviceToDevice, P->st));
+  };
+  if (precision == HDG_FP64)
+    run(double(0));
+  else if (precision == HDG_FP32)
+    run(float(0));
+  else
+    return HDG_ERR_INVALID_ARG;
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_level_export(hdg_handle P, int level, double* out) {
+  if (!P || !out) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  if (level == 0) {
+    HDG_CHECK(hipMemcpyAsync(out, P->Ae, sizeof(double) * P->nelem * P->nl * P->nl, hipMemcpyDeviceToDevice,
+                             P->st));
+    return HDG_OK;
+  }
+  if (!P->built) return HDG_ERR_STATE;
+  if (level < 0 || level >= (int)P->L.size()) return HDG_ERR_INVALID_ARG;
+  const Level& L = P->L[level];
+  HDG_CHECK(hipMemcpyAsync(out, L.Aelem, sizeof(double) * L.nelem * L.nl * L.nl, hipMemcpyDeviceToDevice, P->st));
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_query(hdg_handle P, int what, long long* out) {
+  if (!P || !out) return HDG_ERR_INVALID_ARG;
+  const int nL = (int)P->L.size();
+  if (what == HDG_Q_NT) {
+    *out = P->nelem;
+  } else if (what == HDG_Q_NLAMBDA) {
+    Level tmp;
+    init_level(tmp, P->d, P->n, P->ne);
+    *out = tmp.nlam;
+  } else if (what == HDG_Q_NLEVELS) {
+    *out = nL;
+  } else if (what == HDG_Q_NV) {
+    *out = P->nv;
+  } else if (what == HDG_Q_NQ) {
+    *out = P->nq;
+  } else if (what == HDG_Q_DEVICE_BYTES) {
+    *out = P->bytes;
+  } else if (what >= HDG_Q_LEVEL_NLAMBDA && what < HDG_Q_LEVEL_NLAMBDA + 100) {
+    int l = what - HDG_Q_LEVEL_NLAMBDA;
+    if (l >= nL) return HDG_ERR_INVALID_ARG;
+    *out = P->L[l].nlam;
+  } else if (what >= HDG_Q_LEVEL_N && what < HDG_Q_LEVEL_N + 100) {
+    int l = what - HDG_Q_LEVEL_N;
+    if (l >= nL) return HDG_ERR_INVALID_ARG;
+    *out = P->L[l].n;
+  } else if (what >= HDG_Q_LEVEL_NE && what < HDG_Q_LEVEL_NE + 100) {
+    int l = what - HDG_Q_LEVEL_NE;
+    if (l >= nL) return HDG_ERR_INVALID_ARG;
+    *out = P->L[l].ne;
+  } else {
+    return HDG_ERR_INVALID_ARG;
+  }
+  return HDG_OK;
+}
+
+hdg_status hdg_destroy(hdg_handle P) {
+  if (!P) return HDG_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(P->st);
+  for (void* ptr : P->build_allocs) (void)hipFree(ptr);
+  for (void* ptr : P->allocs) (void)hipFree(ptr);
+  if (P->hbad) (void)hipHostFree(P->hbad);
+  if (P->hpin) (void)hipHostFree(P->hpin);
+  delete P;
+  return HDG_OK;
+}
+
+}  // extern "C"

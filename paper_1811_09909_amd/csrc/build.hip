@@ -1,0 +1,414 @@
+// Hierarchy construction kernels (gfx950), all in FP64:
+//  * face-major copies of the element matrices for the trace apply,
+//  * assembled face-block inverses for block-Jacobi (Sec. 4.1),
+//  * p-level Galerkin operator J_N^T A^e J_N per element (eq. ANm1),
+//  * per coarse macro-element: assembly of the 2^d children on the interior
+//    faces I and boundary faces B of the macro-element, A_II^-1,
+//    S = A_BB - A_BI A_II^-1 A_IB, coarse matrix J^T S J (eq. Akm1) and the
+//    prolongation block P = -A_II^-1 A_IB J (eq. n_1_Ik).  The trace operator
+//    of HDG is symmetric, so A_BI is taken as A_IB^T (Q = I^T, eq. n_1_Qk),
+//  * dense inverse of the coarsest operator (Algorithm 1, B_1 = A_1^-1).
+#include "hdg_internal.hpp"
+
+namespace hdg {
+
+namespace {
+
+inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+
+__device__ inline long nfd_of(int d, int n) {
+  long v = n - 1;
+  for (int a = 1; a < d; ++a) v *= n;
+  return v;
+}
+
+__device__ inline int decode_face_rt(int d, long F, int n, int* g) {
+  long nfd = nfd_of(d, n);
+  int c = (int)(F / nfd);
+  long r = F % nfd;
+  for (int a = 0; a < d; ++a) {
+    int ext = a == c ? n - 1 : n;
+    g[a] = (int)(r % ext) + (a == c ? 1 : 0);
+    r /= ext;
+  }
+  return c;
+}
+
+__device__ inline long elem_rt(int d, const int* e, int n) {
+  long T = 0;
+  for (int a = d - 1; a >= 0; --a) T = T * n + e[a];
+  return T;
+}
+
+// Af[F, side, j, a] = A_{T_side}[slot_side*ne + a][j] (FP64 and FP32 copies)
+__global__ void face_major_kernel(int d, int n, int ne, long nface, const double* __restrict__ Aelem,
+                                  double* __restrict__ Af64, float* __restrict__ Af32) {
+  const int nl = 2 * d * ne;
+  const long per = 2L * nl * ne;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= nface * per) return;
+  const long F = t / per;
+  long r = t % per;
+  const int side = (int)(r / (nl * ne));
+  r %= nl * ne;
+  const int j = (int)(r / ne), a = (int)(r % ne);
+  int g[3] = {0, 0, 0};
+  const int c = decode_face_rt(d, F, n, g);
+  int e[3] = {g[0], g[1], g[2]};
+  e[c] = g[c] - 1 + side;
+  const long T = elem_rt(d, e, n);
+  const int slot = side == 0 ? 2 * c + 1 : 2 * c;
+  const double v = Aelem[(T * nl + slot * ne + a) * nl + j];
+  const long idx = ((((F >> 6) * 2 + side) * nl + j) * ne + a) * LANES + (F & 63);
+  Af64[idx] = v;
+  Af32[idx] = (float)v;
+}
+
+// omega * (A_{T-}[F,F] + A_{T+}[F,F])^-1 per face
+template <int NE>
+__global__ void dinv_kernel(int d, int n, long nface, double omega, const double* __restrict__ Aelem,
+                            double* __restrict__ D64, float* __restrict__ D32) {
+  const long F = blockIdx.x * 256L + threadIdx.x;
+  if (F >= nface) return;
+  const int nl = 2 * d * NE;
+  int g[3] = {0, 0, 0};
+  const int c = decode_face_rt(d, F, n, g);
+  double A[NE * NE];
+  for (int i = 0; i < NE * NE; ++i) A[i] = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    int e[3] = {g[0], g[1], g[2]};
+    e[c] = g[c] - 1 + side;
+    const long T = elem_rt(d, e, n);
+    const int slot = side == 0 ? 2 * c + 1 : 2 * c;
+    for (int a = 0; a < NE; ++a)
+      for (int b = 0; b < NE; ++b) A[a * NE + b] += Aelem[(T * nl + slot * NE + a) * nl + slot * NE + b];
+  }
+  // Gauss-Jordan, SPD block: no pivoting
+  for (int k = 0; k < NE; ++k) {
+    const double p = 1.0 / A[k * NE + k];
+    for (int j = 0; j < NE; ++j)
+      if (j != k) A[k * NE + j] *= p;
+    for (int i = 0; i < NE; ++i) {
+      if (i == k) continue;
+      const double f = A[i * NE + k];
+      for (int j = 0; j < NE; ++j)
+        if (j != k) A[i * NE + j] -= f * A[k * NE + j];
+      A[i * NE + k] = -f * p;
+    }
+    A[k * NE + k] = p;
+  }
+  const long base = (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
+  for (int i = 0; i < NE * NE; ++i) {
+    const double v = omega * A[i];
+    D64[base + i * LANES] = v;
+    D32[base + i * LANES] = (float)v;
+  }
+}
+
+// Ac[(s1,v1),(s2,v2)] = sum_ab Jp[a][v1] A[(s1,a),(s2,b)] Jp[b][v2]
+__global__ void pgalerkin_kernel(int d, int ne, long nelem, const double* __restrict__ Jp,
+                                 const double* __restrict__ Af, double* __restrict__ Ac) {
+  const int nc = 1 << (d - 1);
+  const int nl = 2 * d * ne, ncl = 2 * d * nc;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= nelem * ncl * ncl) return;
+  const long T = t / (ncl * ncl);
+  const int r = (int)(t % (ncl * ncl));
+  const int I = r / ncl, J = r % ncl;
+  const int s1 = I / nc, v1 = I % nc, s2 = J / nc, v2 = J % nc;
+  double s = 0.0;
+  for (int a = 0; a < ne; ++a) {
+    double inner = 0.0;
+    for (int b = 0; b < ne; ++b) inner += Af[(T * nl + s1 * ne + a) * nl + s2 * ne + b] * Jp[b * nc + v2];
+    s += Jp[a * nc + v1] * inner;
+  }
+  Ac[t] = s;
+}
+
+template <int N>
+__device__ void gj_lds(double* A, int tid, int nt) {
+  __shared__ double pv;
+  for (int k = 0; k < N; ++k) {
+    __syncthreads();
+    if (tid == 0) pv = 1.0 / A[k * N + k];
+    __syncthreads();
+    const double p = pv;
+    for (int j = tid; j < N; j += nt)
+      if (j != k) A[k * N + j] *= p;
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+      const int i = idx / N, j = idx % N;
+      if (i != k && j != k) A[idx] -= A[i * N + k] * A[k * N + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += nt)
+      if (i != k) A[i * N + k] = -A[i * N + k] * p;
+    if (tid == 0) A[k * N + k] = p;
+  }
+  __syncthreads();
+}
+
+// one workgroup per coarse macro-element
+template <int D, int NT>
+__global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __restrict__ Achild,
+                                                         double* __restrict__ Acoarse, double* __restrict__ Ai64,
+                                                         float* __restrict__ Ai32, double* __restrict__ P64,
+                                                         float* __restrict__ P32) {
+  constexpr int NC = 1 << (D - 1);    // DOFs per (sub)face
+  constexpr int NS = NC;              // sub-faces per macro-face
+  constexpr int NLC = 2 * D * NC;     // child local size == coarse local size
+  constexpr int NI = D * NS * NC;     // interior DOFs of the macro-element
+  constexpr int NB = 2 * D * NS * NC; // boundary DOFs of the macro-element
+  __shared__ double sII[NI * NI];
+  __shared__ double sIB[NI * NB];
+  __shared__ double sBB[NB * NB];
+  __shared__ double sY[NI * NLC];
+  __shared__ int map[(1 << D) * NLC];
+  const int tid = threadIdx.x;
+  const int nm = n / 2;
+  const long M = blockIdx.x;
+  int m[3] = {0, 0, 0};
+  {
+    long r = M;
+    for (int a = 0; a < D; ++a) {
+      m[a] = (int)(r % nm);
+      r /= nm;
+    }
+  }
+  // child-local DOF -> macro DOF (>= 0: I index, < 0: -(B index) - 1)
+  for (int idx = tid; idx < (1 << D) * NLC; idx += NT) {
+    const int ch = idx / NLC, l = idx % NLC;
+    const int sl = l / NC, v = l % NC;
+    const int c = sl / 2, sd = sl % 2;
+    const int q = ((ch >> c) & 1) + sd;  // position inside the macro-element along c
+    int t = 0, j = 0;
+    for (int a = 0; a < D; ++a)
+      if (a != c) {
+        t |= ((ch >> a) & 1) << j;
+        ++j;
+      }
+    if (q == 1)
+      map[idx] = (c * NS + t) * NC + v;
+    else
+      map[idx] = -(((2 * c + (q == 2 ? 1 : 0)) * NS + t) * NC + v) - 1;
+  }
+  for (int idx = tid; idx < NI * NI; idx += NT) sII[idx] = 0.0;
+  for (int idx = tid; idx < NI * NB; idx += NT) sIB[idx] = 0.0;
+  for (int idx = tid; idx < NB * NB; idx += NT) sBB[idx] = 0.0;
+  __syncthreads();
+  for (int ch = 0; ch < (1 << D); ++ch) {
+    int e[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) e[a] = 2 * m[a] + ((ch >> a) & 1);
+    long T = 0;
+    for (int a = D - 1; a >= 0; --a) T = T * n + e[a];
+    const double* Ac = Achild + T * NLC * NLC;
+    for (int idx = tid; idx < NLC * NLC; idx += NT) {
+      const int r = idx / NLC, s = idx % NLC;
+      const int mr = map[ch * NLC + r], ms = map[ch * NLC + s];
+      const double v = Ac[idx];
+      if (mr >= 0 && ms >= 0)
+        sII[mr * NI + ms] += v;
+      else if (mr >= 0 && ms < 0)
+        sIB[mr * NB + (-ms - 1)] += v;
+      else if (mr < 0 && ms < 0)
+        sBB[(-mr - 1) * NB + (-ms - 1)] += v;
+    }
+    __syncthreads();
+  }
+  gj_lds<NI>(sII, tid, NT);
+  // S = A_BB - A_IB^T A_II^-1 A_IB, column j owned by one thread
+  for (int j = tid; j < NB; j += NT) {
+    double x[NI];
+    for (int i = 0; i < NI; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sIB[l * NB + j];
+      x[i] = s;
+    }
+    for (int i = 0; i < NB; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < NI; ++l) s += sIB[l * NB + i] * x[l];
+      sBB[i * NB + j] -= s;
+    }
+  }
+  __syncthreads();
+  // J: coarse DOF (S, V) -> B DOF (S*NS + t, v) with weight jw(t, v, V)
+  auto jw = [](int t, int v, int V) {
+    double w = 1.0;
+    for (int j = 0; j < D - 1; ++j) {
+      double s = 0.5 * (((t >> j) & 1) + ((v >> j) & 1));
+      w *= ((V >> j) & 1) ? s : 1.0 - s;
+    }
+    return w;
+  };
+  // Y = A_IB J  (NI x NLC)
+  for (int idx = tid; idx < NI * NLC; idx += NT) {
+    const int i = idx / NLC, J = idx % NLC;
+    const int S = J / NC, V = J % NC;
+    double s = 0.0;
+    for (int t = 0; t < NS; ++t)
+      for (int v = 0; v < NC; ++v) s += sIB[i * NB + (S * NS + t) * NC + v] * jw(t, v, V);
+    sY[idx] = s;
+  }
+  __syncthreads();
+  // P = -A_II^-1 Y, written AoSoA over macro-elements
+  const long pbase = (M >> 6) * (long)(NI * NLC * LANES) + (M & 63);
+  for (int idx = tid; idx < NI * NLC; idx += NT) {
+    const int i = idx / NLC, J = idx % NLC;
+    double s = 0.0;
+    for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sY[l * NLC + J];
+    P64[pbase + (long)idx * LANES] = -s;
+    P32[pbase + (long)idx * LANES] = (float)(-s);
+  }
+  const long abase = (M >> 6) * (long)(NI * NI * LANES) + (M & 63);
+  for (int idx = tid; idx < NI * NI; idx += NT) {
+    Ai64[abase + (long)idx * LANES] = sII[idx];
+    Ai32[abase + (long)idx * LANES] = (float)sII[idx];
+  }
+  __syncthreads();
+  // T1 = S J (NB x NLC) into sIB, then A_coarse = J^T T1
+  for (int idx = tid; idx < NB * NLC; idx += NT) {
+    const int i = idx / NLC, J = idx % NLC;
+    const int S = J / NC, V = J % NC;
+    double s = 0.0;
+    for (int t = 0; t < NS; ++t)
+      for (int v = 0; v < NC; ++v) s += sBB[i * NB + (S * NS + t) * NC + v] * jw(t, v, V);
+    sIB[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NLC * NLC; idx += NT) {
+    const int I = idx / NLC, J = idx % NLC;
+    const int S = I / NC, V = I % NC;
+    double s = 0.0;
+    for (int t = 0; t < NS; ++t)
+      for (int v = 0; v < NC; ++v) s += jw(t, v, V) * sIB[((S * NS + t) * NC + v) * NLC + J];
+    Acoarse[M * NLC * NLC + idx] = s;
+  }
+}
+
+// dense assembly and inverse of the coarsest operator (n = 2), one workgroup
+__global__ void coarse_inverse_kernel(int d, int n, int ne, int N, const double* __restrict__ Aelem,
+                                      double* __restrict__ Ai64, float* __restrict__ Ai32) {
+  __shared__ double A[64 * 64];
+  __shared__ double pv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nl = 2 * d * ne;
+  long nelem = 1;
+  for (int a = 0; a < d; ++a) nelem *= n;
+  for (int idx = tid; idx < N * N; idx += nt) A[idx] = 0.0;
+  __syncthreads();
+  for (long T = 0; T < nelem; ++T) {
+    int e[3] = {0, 0, 0};
+    long r = T;
+    for (int a = 0; a < d; ++a) {
+      e[a] = (int)(r % n);
+      r /= n;
+    }
+    for (int idx = tid; idx < nl * nl; idx += nt) {
+      const int i = idx / nl, j = idx % nl;
+      long gi = -1, gj = -1;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int l = pass == 0 ? i : j;
+        const int sl = l / ne, a = l % ne;
+        const int c = sl / 2, sd = sl % 2;
+        const int p = e[c] + sd;
+        long gid = -1;
+        if (p > 0 && p < n) {
+          int g[3] = {e[0], e[1], e[2]};
+          g[c] = p;
+          long idx2 = 0, stride = 1;
+          for (int aa = 0; aa < d; ++aa) {
+            if (aa == c) {
+              idx2 += (long)(g[aa] - 1) * stride;
+              stride *= n - 1;
+            } else {
+              idx2 += (long)g[aa] * stride;
+              stride *= n;
+            }
+          }
+          gid = (c * nfd_of(d, n) + idx2) * ne + a;
+        }
+        if (pass == 0)
+          gi = gid;
+        else
+          gj = gid;
+      }
+      if (gi >= 0 && gj >= 0) A[gi * N + gj] += Aelem[(T * nl + i) * nl + j];
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < N; ++k) {
+    __syncthreads();
+    if (tid == 0) pv = 1.0 / A[k * N + k];
+    __syncthreads();
+    const double p = pv;
+    for (int j = tid; j < N; j += nt)
+      if (j != k) A[k * N + j] *= p;
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+      const int i = idx / N, j = idx % N;
+      if (i != k && j != k) A[idx] -= A[i * N + k] * A[k * N + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += nt)
+      if (i != k) A[i * N + k] = -A[i * N + k] * p;
+    if (tid == 0) A[k * N + k] = p;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < N * N; idx += nt) {
+    Ai64[idx] = A[idx];
+    Ai32[idx] = (float)A[idx];
+  }
+}
+
+}  // namespace
+
+void launch_face_major(const Level& L, hipStream_t st) {
+  if (L.nface == 0) return;
+  long tot = L.nface * 2L * L.nl * L.ne;
+  hipLaunchKernelGGL(face_major_kernel, dim3(nblk(tot)), dim3(256), 0, st, L.d, L.n, L.ne, L.nface, L.Aelem,
+                     L.Af64, L.Af32);
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_dinv(const Level& L, double omega, hipStream_t st) {
+  if (L.nface == 0) return;
+#define HDG_DCASE(NN)                                                                                     \
+  case NN:                                                                                                \
+    hipLaunchKernelGGL((dinv_kernel<NN>), dim3(nblk(L.nface)), dim3(256), 0, st, L.d, L.n, L.nface, omega, \
+                       L.Aelem, L.Dinv64, L.Dinv32);                                                      \
+    break;
+  switch (L.ne) {
+    HDG_DCASE(2) HDG_DCASE(3) HDG_DCASE(4) HDG_DCASE(5) HDG_DCASE(6) HDG_DCASE(7) HDG_DCASE(9) HDG_DCASE(16)
+    default:
+      throw HipError{hipErrorInvalidValue, "unsupported face size"};
+  }
+#undef HDG_DCASE
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double* Afine, double* Acoarse,
+                      hipStream_t st) {
+  const int ncl = 2 * d * (1 << (d - 1));
+  long tot = nelem * ncl * ncl;
+  hipLaunchKernelGGL(pgalerkin_kernel, dim3(nblk(tot)), dim3(256), 0, st, d, ne, nelem, Jp, Afine, Acoarse);
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st) {
+  if (fine.d == 2)
+    hipLaunchKernelGGL((macro_schur_kernel<2, 64>), dim3((unsigned)fine.nmacro), dim3(64), 0, st, fine.n,
+                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32);
+  else
+    hipLaunchKernelGGL((macro_schur_kernel<3, 256>), dim3((unsigned)fine.nmacro), dim3(256), 0, st, fine.n,
+                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32);
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_coarse_inverse(const Level& L, hipStream_t st) {
+  if (L.nlam == 0) return;
+  hipLaunchKernelGGL(coarse_inverse_kernel, dim3(1), dim3(256), 0, st, L.d, L.n, L.ne, (int)L.nlam, L.Aelem,
+                     L.Ainv64, L.Ainv32);
+  HDG_CHECK(hipGetLastError());
+}
+
+}  // namespace hdg

@@ -1,0 +1,499 @@
+// Element-local kernels of the HDG discretization (gfx950).
+//
+// For each element T the local problem of eqs. HDG / HDG_flux reads
+//   A_T Q - B^T U + F Lambda = 0,      B Q + tau E U = tau G Lambda + b_T,
+// with A_T = blockdiag_c(Mk), Mk = (kappa^-1 phi_j, phi_i)_T, B = [B_c],
+// B_c[i][j] = (d_c phi_j, phi_i), F = [F_c], G, E, H the face integrals.
+// Eliminating Q with the SPD blocks Mk gives the SPD volume Schur complement
+//   K = sum_c B_c Mk^-1 B_c^T + tau E,   Z = tau G + sum_c B_c Mk^-1 F_c,
+// and the element DtN map of the condensed trace system (Sec. 2, static
+// condensation; eq. trace_linear_system):
+//   A^e = tau H + sum_c F_c^T Mk^-1 F_c - Z^T K^-1 Z,   b^e = (K^-1 Z)^T b_T.
+// Local recovery: U = K^-1 (Z Lambda + b), Q_c = Mk^-1 (B_c^T U - F_c Lambda).
+// F_c only touches the two face slots of normal c, which keeps the LDS
+// footprint of a 3D k=3 element at 144 KB.
+#include "hdg_internal.hpp"
+
+namespace hdg {
+
+namespace {
+
+template <int D, int K>
+struct Dims {
+  static constexpr int P1 = K + 1;
+  static constexpr int NV = D == 2 ? P1 * P1 : P1 * P1 * P1;
+  static constexpr int NE = D == 2 ? P1 : P1 * P1;
+  static constexpr int NF = 2 * D;
+  static constexpr int NL = NF * NE;
+  static constexpr int NQ = D == 2 ? (K + 2) * (K + 2) : (K + 2) * (K + 2) * (K + 2);
+  static constexpr int SA = (2 * NV * NV > NV * NL) ? 2 * NV * NV : NV * NL;
+};
+
+// In-place Gauss-Jordan inverse of an SPD n x n matrix in LDS (no pivoting),
+// cooperative over the workgroup.
+template <int N>
+__device__ void gj_inverse_lds(double* A) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double piv_s;
+  for (int k = 0; k < N; ++k) {
+    __syncthreads();
+    if (tid == 0) piv_s = 1.0 / A[k * N + k];
+    __syncthreads();
+    const double p = piv_s;
+    for (int j = tid; j < N; j += nt)
+      if (j != k) A[k * N + j] *= p;
+    __syncthreads();
+    for (int idx = tid; idx < N * N; idx += nt) {
+      int i = idx / N, j = idx % N;
+      if (i != k && j != k) A[idx] -= A[i * N + k] * A[k * N + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += nt)
+      if (i != k) A[i * N + k] = -A[i * N + k] * p;
+    if (tid == 0) A[k * N + k] = p;
+  }
+  __syncthreads();
+}
+
+template <int D, int K, int NT>
+__global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau, const double* __restrict__ Phi,
+                                                         const double* __restrict__ Wq,
+                                                         const double* __restrict__ Bm,
+                                                         const double* __restrict__ Fm,
+                                                         const double* __restrict__ Gm,
+                                                         const double* __restrict__ Em,
+                                                         const double* __restrict__ Hm,
+                                                         const double* __restrict__ kqp, double* __restrict__ Aelem,
+                                                         double* __restrict__ Wout, double* __restrict__ Kinv_out,
+                                                         double* __restrict__ Minv_out) {
+  using Dm = Dims<D, K>;
+  constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL, NQ = Dm::NQ;
+  __shared__ double sA[Dm::SA];      // Mk^-1 | Y   (later: W)
+  __shared__ double sK[NV * NV];     // K -> K^-1
+  __shared__ double sZ[NV * NL];     // Z
+  __shared__ double sW[NQ];          // w_q / kappa_q
+  const long T = blockIdx.x;
+  if (T >= nelem) return;
+  const int tid = threadIdx.x;
+  double* sM = sA;
+  double* sY = sA + NV * NV;
+  double* Ae = Aelem + T * (long)NL * NL;
+
+  for (int q = tid; q < NQ; q += NT) sW[q] = Wq[q] / kqp[T * NQ + q];
+  __syncthreads();
+  // Mk = Phi^T diag(w/kappa) Phi
+  for (int idx = tid; idx < NV * NV; idx += NT) {
+    int i = idx / NV, j = idx % NV;
+    double s = 0.0;
+    for (int q = 0; q < NQ; ++q) s += Phi[q * NV + i] * Phi[q * NV + j] * sW[q];
+    sM[idx] = s;
+  }
+  // K = tau E, Z = tau G, A^e = tau H
+  for (int idx = tid; idx < NV * NV; idx += NT) sK[idx] = tau * Em[idx];
+  for (int idx = tid; idx < NV * NL; idx += NT) sZ[idx] = tau * Gm[idx];
+  for (int idx = tid; idx < NL * NL; idx += NT) Ae[idx] = tau * Hm[idx];
+  gj_inverse_lds<NV>(sM);
+  if (Minv_out)
+    for (int idx = tid; idx < NV * NV; idx += NT) Minv_out[T * NV * NV + idx] = sM[idx];
+
+  for (int c = 0; c < D; ++c) {
+    const double* Bc = Bm + (long)c * NV * NV;
+    const double* Fc = Fm + (long)c * NV * NL;
+    // Y = Mk^-1 B_c^T ; K += B_c Y
+    __syncthreads();
+    for (int idx = tid; idx < NV * NV; idx += NT) {
+      int i = idx / NV, j = idx % NV;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * Bc[j * NV + l];
+      sY[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * NV; idx += NT) {
+      int i = idx / NV, j = idx % NV;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += Bc[i * NV + l] * sY[l * NV + j];
+      sK[idx] += s;
+    }
+    __syncthreads();
+    // Y(:, 0:2NE) = Mk^-1 F_c(:, slots of normal c)
+    const int col0 = 2 * c * NE;
+    for (int idx = tid; idx < NV * 2 * NE; idx += NT) {
+      int i = idx / (2 * NE), j = idx % (2 * NE);
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * Fc[l * NL + col0 + j];
+      sY[i * 2 * NE + j] = s;
+    }
+    __syncthreads();
+    // Z(:, slots c) += B_c Y ; A^e(slots c, slots c) += F_c^T Y
+    for (int idx = tid; idx < NV * 2 * NE; idx += NT) {
+      int i = idx / (2 * NE), j = idx % (2 * NE);
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += Bc[i * NV + l] * sY[l * 2 * NE + j];
+      sZ[i * NL + col0 + j] += s;
+    }
+    // same entry-to-thread map as every other pass over A^e: no thread reads
+    // an entry another thread wrote
+    for (int idx = tid; idx < NL * NL; idx += NT) {
+      const int i = idx / NL - col0, j = idx % NL - col0;
+      if (i < 0 || i >= 2 * NE || j < 0 || j >= 2 * NE) continue;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += Fc[l * NL + col0 + i] * sY[l * 2 * NE + j];
+      Ae[idx] += s;
+    }
+  }
+  __syncthreads();
+  gj_inverse_lds<NV>(sK);
+  if (Kinv_out)
+    for (int idx = tid; idx < NV * NV; idx += NT) Kinv_out[T * NV * NV + idx] = sK[idx];
+  // W = K^-1 Z (into sA) ; A^e -= Z^T W
+  double* sWm = sA;
+  for (int idx = tid; idx < NV * NL; idx += NT) {
+    int i = idx / NL, j = idx % NL;
+    double s = 0.0;
+    for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
+    sWm[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NL * NL; idx += NT) {
+    int i = idx / NL, j = idx % NL;
+    double s = 0.0;
+    for (int l = 0; l < NV; ++l) s += sZ[l * NL + i] * sWm[l * NL + j];
+    Ae[idx] -= s;
+  }
+  for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sWm[idx];
+}
+
+// b = M f (or f itself when it is already a load), per (element, node)
+template <int NV>
+__global__ void load_vec_kernel(long nelem, const double* __restrict__ M, const double* __restrict__ f,
+                                int is_load, double* __restrict__ b) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nelem * NV) return;
+  long T = t / NV;
+  int i = (int)(t % NV);
+  if (is_load) {
+    b[t] = f[t];
+    return;
+  }
+  double s = 0.0;
+  for (int j = 0; j < NV; ++j) s += M[i * NV + j] * f[T * NV + j];
+  b[t] = s;
+}
+
+// b^e = W^T b per (element, local trace DOF)
+template <int NV, int NL>
+__global__ void load_elem_kernel(long nelem, const double* __restrict__ W, const double* __restrict__ b,
+                                 double* __restrict__ ebuf) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nelem * NL) return;
+  long T = t / NL;
+  int r = (int)(t % NL);
+  double s = 0.0;
+  for (int i = 0; i < NV; ++i) s += W[(T * NV + i) * NL + r] * b[T * NV + i];
+  ebuf[t] = s;
+}
+
+// element coordinates <-> index, face ids (interior / boundary)
+template <int D>
+__device__ inline void elem_coords(long T, int n, int* e) {
+  for (int a = 0; a < D; ++a) {
+    e[a] = (int)(T % n);
+    T /= n;
+  }
+}
+
+template <int D>
+__device__ inline long elem_index(const int* e, int n) {
+  long T = 0;
+  for (int a = D - 1; a >= 0; --a) T = T * n + e[a];
+  return T;
+}
+
+// interior face id of direction c at grid coordinates g (g[c] = position 1..n-1)
+template <int D>
+__device__ inline long iface_id(int c, const int* g, int n) {
+  long idx = 0, stride = 1;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      idx += (long)(g[a] - 1) * stride;
+      stride *= (n - 1);
+    } else {
+      idx += (long)g[a] * stride;
+      stride *= n;
+    }
+  }
+  long nfd = (long)(n - 1);
+  for (int a = 1; a < D; ++a) nfd *= n;
+  return c * nfd + idx;
+}
+
+template <int D>
+__device__ inline long bface_id(int c, int side, const int* g, int n) {
+  long idx = 0, stride = 1;
+  for (int a = 0; a < D; ++a)
+    if (a != c) {
+      idx += (long)g[a] * stride;
+      stride *= n;
+    }
+  long blk = 1;
+  for (int a = 1; a < D; ++a) blk *= n;
+  return (2 * c + side) * blk + idx;
+}
+
+// g_F = b^e_{T-}[slot 2c+1] + b^e_{T+}[slot 2c] - (Dirichlet lift)
+template <int D, int NE>
+__global__ void load_pull_kernel(int n, const double* __restrict__ ebuf, const double* __restrict__ Aelem,
+                                 const double* __restrict__ gdir, double* __restrict__ g) {
+  constexpr int NL = 2 * D * NE;
+  long nfd = (long)(n - 1);
+  for (int a = 1; a < D; ++a) nfd *= n;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= D * nfd * NE) return;
+  long F = t / NE;
+  int a = (int)(t % NE);
+  int c = (int)(F / nfd);
+  long r = F % nfd;
+  int gco[3] = {0, 0, 0};
+  for (int dd = 0; dd < D; ++dd) {
+    int ext = dd == c ? n - 1 : n;
+    gco[dd] = (int)(r % ext) + (dd == c ? 1 : 0);
+    r /= ext;
+  }
+  double s = 0.0;
+  for (int side = 0; side < 2; ++side) {
+    int e[3] = {gco[0], gco[1], gco[2]};
+    e[c] = gco[c] - 1 + side;
+    long T = elem_index<D>(e, n);
+    int row = (side == 0 ? 2 * c + 1 : 2 * c) * NE + a;
+    s += ebuf[T * NL + row];
+    if (gdir) {
+      for (int sl = 0; sl < 2 * D; ++sl) {
+        int cc = sl / 2, sd = sl % 2;
+        int p = e[cc] + sd;
+        if (p == 0 || p == n) {
+          int fg[3] = {e[0], e[1], e[2]};
+          long bid = bface_id<D>(cc, p == n ? 1 : 0, fg, n);
+          for (int b = 0; b < NE; ++b) s -= Aelem[(T * NL + row) * NL + sl * NE + b] * gdir[bid * NE + b];
+        }
+      }
+    }
+  }
+  g[t] = s;
+}
+
+// Local recovery, one workgroup per element.
+template <int D, int K, int NT>
+__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, const double* __restrict__ Bm,
+                                                         const double* __restrict__ Fm,
+                                                         const double* __restrict__ lam,
+                                                         const double* __restrict__ gdir,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ Kinv,
+                                                         const double* __restrict__ Minv, double* __restrict__ u,
+                                                         double* __restrict__ q) {
+  using Dm = Dims<D, K>;
+  constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL;
+  __shared__ double sL[NL], sU[NV], sT[NV];
+  const long T = blockIdx.x;
+  const int tid = threadIdx.x;
+  int e[3] = {0, 0, 0};
+  elem_coords<D>(T, n, e);
+  for (int idx = tid; idx < NL; idx += NT) {
+    int sl = idx / NE, a = idx % NE;
+    int c = sl / 2, sd = sl % 2;
+    int gco[3] = {e[0], e[1], e[2]};
+    int p = e[c] + sd;
+    gco[c] = p;
+    double v = 0.0;
+    if (p == 0 || p == n) {
+      if (gdir) v = gdir[bface_id<D>(c, p == n ? 1 : 0, gco, n) * NE + a];
+    } else {
+      v = lam[iface_id<D>(c, gco, n) * NE + a];
+    }
+    sL[idx] = v;
+  }
+  __syncthreads();
+  // U = W Lambda + K^-1 b
+  for (int i = tid; i < NV; i += NT) {
+    double s = 0.0;
+    for (int j = 0; j < NL; ++j) s += W[(T * NV + i) * NL + j] * sL[j];
+    for (int j = 0; j < NV; ++j) s += Kinv[(T * NV + i) * NV + j] * b[T * NV + j];
+    sU[i] = s;
+    u[T * NV + i] = s;
+  }
+  __syncthreads();
+  for (int c = 0; c < D; ++c) {
+    // t = B_c^T U - F_c Lambda ; Q_c = Mk^-1 t
+    for (int i = tid; i < NV; i += NT) {
+      double s = 0.0;
+      for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
+      for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
+      sT[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < NV; i += NT) {
+      double s = 0.0;
+      for (int j = 0; j < NV; ++j) s += Minv[(T * NV + i) * NV + j] * sT[j];
+      q[(T * D + c) * NV + i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// dJ/dlog kappa_T = -sum_c (q*_c)^T Mk q_c, evaluated at the Gauss points.
+template <int D, int K, int NT>
+__global__ void __launch_bounds__(NT) grad_kernel(long nelem, const double* __restrict__ Phi,
+                                                  const double* __restrict__ Wq, const double* __restrict__ kqp,
+                                                  const double* __restrict__ q, const double* __restrict__ qs,
+                                                  double* __restrict__ grad) {
+  using Dm = Dims<D, K>;
+  constexpr int NV = Dm::NV, NQ = Dm::NQ;
+  __shared__ double red[NT];
+  const long T = blockIdx.x;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int Q = tid; Q < NQ; Q += NT) {
+    double s = 0.0;
+    for (int c = 0; c < D; ++c) {
+      double a = 0.0, b = 0.0;
+      for (int i = 0; i < NV; ++i) {
+        a += Phi[Q * NV + i] * q[(T * D + c) * NV + i];
+        b += Phi[Q * NV + i] * qs[(T * D + c) * NV + i];
+      }
+      s += a * b;
+    }
+    acc += Wq[Q] / kqp[T * NQ + Q] * s;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) grad[T] = -red[0];
+}
+
+__global__ void kappa_expand_kernel(long nelem, int nq, const double* __restrict__ kappa, int kind,
+                                    double* __restrict__ kqp, int* bad) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= nelem * nq) return;
+  double v = kind == HDG_KAPPA_PER_ELEMENT ? kappa[t / nq] : kappa[t];
+  if (!(v > 0.0) || !(v < INFINITY)) atomicOr(bad, 1);
+  kqp[t] = v;
+}
+
+template <typename F>
+void dispatch_dk(int d, int k, F&& f) {
+  if (d == 2) {
+    switch (k) {
+      case 1: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{}); return;
+      case 2: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{}); return;
+      case 3: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{}); return;
+      case 4: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 4>{}); return;
+      case 5: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 5>{}); return;
+      case 6: f(std::integral_constant<int, 2>{}, std::integral_constant<int, 6>{}); return;
+    }
+  } else {
+    switch (k) {
+      case 1: f(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{}); return;
+      case 2: f(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{}); return;
+      case 3: f(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{}); return;
+    }
+  }
+  throw HipError{hipErrorInvalidValue, "unsupported (d, k)"};
+}
+
+}  // namespace
+
+void launch_element_dtn(int d, int k, long nelem, double tau, const RefDevice& rd, const double* kqp,
+                        double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    constexpr int NT = D == 2 ? 64 : 256;
+    hipLaunchKernelGGL((element_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau,
+                       rd.Phi, rd.Wq, rd.B, rd.F, rd.G, rd.E, rd.H, kqp, Aelem, W, Kinv, Minv);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_element_load(int d, int k, long nelem, const RefDevice& rd, const double* f, int is_load,
+                         const double* W, double* ebuf, hipStream_t st) {
+  // ebuf must hold nelem*(NV + NL) doubles: b then b^e
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    using Dm = Dims<D, K>;
+    double* b = ebuf + nelem * Dm::NL;
+    long n1 = nelem * Dm::NV, n2 = nelem * Dm::NL;
+    hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
+                       rd.M, f, is_load, b);
+    hipLaunchKernelGGL((load_elem_kernel<Dm::NV, Dm::NL>), dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st,
+                       nelem, W, b, ebuf);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Aelem, const double* gdir,
+                      double* g, hipStream_t st) {
+  if (n < 2) return;
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    using Dm = Dims<D, K>;
+    long nfd = n - 1;
+    for (int a = 1; a < D; ++a) nfd *= n;
+    long tot = D * nfd * Dm::NE;
+    hipLaunchKernelGGL((load_pull_kernel<D, Dm::NE>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n,
+                       ebuf, Aelem, gdir, g);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_reconstruct(int d, int k, int n, const RefDevice& rd, const double* lam, const double* gdir,
+                        const double* f, int is_load, const double* W, const double* Kinv, const double* Minv,
+                        double* b, double* u, double* q, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    using Dm = Dims<D, K>;
+    long nelem = 1;
+    for (int a = 0; a < D; ++a) nelem *= n;
+    long n1 = nelem * Dm::NV;
+    hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
+                       rd.M, f, is_load, b);
+    constexpr int NT = 64;
+    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, rd.B, rd.F,
+                       lam, gdir, b, W, Kinv, Minv, u, q);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_grad(int d, int k, long nelem, const RefDevice& rd, const double* kqp, const double* q,
+                 const double* qs, double* grad, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    constexpr int NT = 64;
+    hipLaunchKernelGGL((grad_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, rd.Phi, rd.Wq, kqp,
+                       q, qs, grad);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_mass(int d, int k, long nelem, const RefDevice& rd, const double* u, double* out, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    using Dm = Dims<D, K>;
+    long n1 = nelem * Dm::NV;
+    hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
+                       rd.M, u, 0, out);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_kappa_expand(long nelem, int nq, const double* kappa, int kind, double* kqp, int* bad,
+                         hipStream_t st) {
+  long tot = nelem * nq;
+  hipLaunchKernelGGL(kappa_expand_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, nelem, nq, kappa,
+                     kind, kqp, bad);
+  HDG_CHECK(hipGetLastError());
+}
+
+}  // namespace hdg

@@ -1,0 +1,131 @@
+// Internal declarations of the HDG trace multigrid library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hdg.h"
+
+namespace hdg {
+
+constexpr int LANES = 64;  // AoSoA block width = one wavefront
+
+inline long pad64(long n) { return (n + LANES - 1) / LANES * LANES; }
+
+struct HipError {
+  hipError_t err;
+  std::string where;
+};
+
+#define HDG_CHECK(x)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (x);                                                    \
+    if (e_ != hipSuccess) throw ::hdg::HipError{e_, std::string(#x)};       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Reference element (host).  Q^k on [0,h]^d, GLL-nodal, Gauss rules with k+2
+// points per direction.  All matrices are row-major and already scaled by the
+// powers of h of a cell of size h.
+struct RefElement {
+  int d = 0, k = 0, nv = 0, ne = 0, nf = 0, nl = 0, nq = 0, nc = 0;
+  double h = 0;
+  std::vector<double> gll, gauss, gw;  // 1D
+  std::vector<double> Phi;             // [nq][nv]
+  std::vector<double> Wq;              // [nq]
+  std::vector<double> B;               // [d][nv][nv]: B[c][i][j] = (d_c phi_j, phi_i)
+  std::vector<double> F;               // [d][nv][nl]: <mu_m, phi_i n_c> on faces of normal c
+  std::vector<double> G;               // [nv][nl]:   <mu_m, phi_i>
+  std::vector<double> E;               // [nv][nv]:   <phi_j, phi_i> on the element boundary
+  std::vector<double> H;               // [nl][nl]:   face mass
+  std::vector<double> M;               // [nv][nv]:   volume mass
+  std::vector<double> Jp;              // [ne][nc]:   P1/Q1 face vertex values -> GLL values
+  void build(int d, int k, double h);
+};
+
+void gll_points(int k, std::vector<double>& x);                       // k+1 points on [0,1]
+void gauss_points(int n, std::vector<double>& x, std::vector<double>& w);  // on [0,1]
+
+// Device copies of the reference data
+struct RefDevice {
+  double *Phi = nullptr, *Wq = nullptr, *B = nullptr, *F = nullptr, *G = nullptr, *E = nullptr,
+         *H = nullptr, *M = nullptr, *Jp = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// One multigrid level.  The local operators are stored twice: element form
+// (row-major [nelem][nl][nl], FP64; input of the next coarsening) and face
+// form (AoSoA-64 over interior faces, FP64 and FP32; read by the apply):
+//   Af[((F/64)*2 + side)*nl*ne + j*ne + a][F%64] = A_{T_side}[slot_side*ne + a][j]
+// where side 0 is the element below the face along its normal (the face is
+// its slot 2c+1), side 1 the element above (slot 2c).
+struct Level {
+  int d = 0, n = 0, ne = 0, nl = 0;
+  long nelem = 0, nfd = 0, nface = 0, nlam = 0;
+  int kind = 2;  // 0: p-transition below, 1: h-transition below, 2: coarsest
+  int sweeps = 2;
+  double* Aelem = nullptr;  bool own_Aelem = true;
+  double* Af64 = nullptr;   float* Af32 = nullptr;
+  double* Dinv64 = nullptr; float* Dinv32 = nullptr;
+  // h-transition to the next level
+  long nmacro = 0;
+  int nI = 0, ncl = 0;
+  double* AIIinv64 = nullptr; float* AIIinv32 = nullptr;  // AoSoA [M/64][nI][nI][64]
+  double* P64 = nullptr;      float* P32 = nullptr;       // AoSoA [M/64][nI][ncl][64]
+  // coarsest direct inverse (dense row-major nlam x nlam)
+  double* Ainv64 = nullptr; float* Ainv32 = nullptr;
+  // work vectors, [0] = FP64, [1] = FP32
+  void* r[2] = {nullptr, nullptr};
+  void* e[2] = {nullptr, nullptr};
+  void* w[2] = {nullptr, nullptr};
+  void* cb[2] = {nullptr, nullptr};
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).  All run on `st`.
+// element.hip
+void launch_element_dtn(int d, int k, long nelem, double tau, const RefDevice& rd, const double* kqp,
+                        double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st);
+void launch_element_load(int d, int k, long nelem, const RefDevice& rd, const double* f, int is_load,
+                         const double* W, double* ebuf, hipStream_t st);
+void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Aelem, const double* gdir,
+                      double* g, hipStream_t st);
+void launch_reconstruct(int d, int k, int n, const RefDevice& rd, const double* lam, const double* gdir,
+                        const double* f, int is_load, const double* W, const double* Kinv, const double* Minv,
+                        double* b, double* u, double* q, hipStream_t st);
+void launch_grad(int d, int k, long nelem, const RefDevice& rd, const double* kqp, const double* q,
+                 const double* qs, double* grad, hipStream_t st);
+void launch_mass(int d, int k, long nelem, const RefDevice& rd, const double* u, double* out, hipStream_t st);
+void launch_kappa_expand(long nelem, int nq, const double* kappa, int kind, double* kqp, int* bad,
+                         hipStream_t st);
+
+// build.hip
+void launch_face_major(const Level& L, hipStream_t st);
+void launch_dinv(const Level& L, double omega, hipStream_t st);
+void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double* Afine, double* Acoarse,
+                      hipStream_t st);
+void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st);
+void launch_coarse_inverse(const Level& L, hipStream_t st);
+
+// trace.hip
+template <typename T>
+void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
+                  hipStream_t st);
+template <typename T>
+void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st);
+template <typename T>
+void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st);
+template <typename T>
+void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st);
+template <typename T>
+void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st);
+template <typename T>
+void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st);
+template <typename T>
+void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st);
+
+enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3 };
+
+}  // namespace hdg

@@ -1,0 +1,234 @@
+// Reference element of the HDG discretization (host side, built once per
+// problem): GLL-nodal Q^k bases on a cell of size h, Gauss rules with k+2
+// points per direction, and the element integrals that enter the local
+// problem of eqs. HDG and HDG_flux.
+#include <cmath>
+#include <stdexcept>
+
+#include "hdg_internal.hpp"
+
+namespace hdg {
+
+namespace {
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence (long double).
+void legendre(int n, long double x, long double& p, long double& dp) {
+  long double p0 = 1.0L, p1 = x;
+  if (n == 0) {
+    p = 1.0L;
+    dp = 0.0L;
+    return;
+  }
+  for (int m = 2; m <= n; ++m) {
+    long double p2 = ((2 * m - 1) * x * p1 - (m - 1) * p0) / m;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  // n P_{n-1} = n x P_n + (1 - x^2) P_n'  ->  P_n' = n (P_{n-1} - x P_n) / (1 - x^2)
+  dp = n * (p0 - x * p1) / (1.0L - x * x);
+}
+
+long double lagrange_value(const std::vector<double>& xi, int i, long double t) {
+  long double v = 1.0L;
+  for (size_t j = 0; j < xi.size(); ++j)
+    if ((int)j != i) v *= (t - xi[j]) / ((long double)xi[i] - xi[j]);
+  return v;
+}
+
+long double lagrange_deriv(const std::vector<double>& xi, int i, long double t) {
+  long double s = 0.0L;
+  for (size_t m = 0; m < xi.size(); ++m) {
+    if ((int)m == i) continue;
+    long double term = 1.0L / ((long double)xi[i] - xi[m]);
+    for (size_t j = 0; j < xi.size(); ++j)
+      if ((int)j != i && j != m) term *= (t - xi[j]) / ((long double)xi[i] - xi[j]);
+    s += term;
+  }
+  return s;
+}
+
+}  // namespace
+
+void gll_points(int k, std::vector<double>& out) {
+  // end points plus the k-1 roots of P_k' on [-1,1], found by Newton's method
+  // on P_k' with P_k'' from the Legendre equation; mapped to [0,1].
+  std::vector<long double> x(k + 1);
+  x[0] = -1.0L;
+  x[k] = 1.0L;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 1; j < k; ++j) {
+    long double t = -std::cos(pi * j / k);
+    for (int it = 0; it < 100; ++it) {
+      long double p, dp;
+      legendre(k, t, p, dp);
+      long double d2p = (2.0L * t * dp - k * (k + 1.0L) * p) / (1.0L - t * t);
+      long double dt = dp / d2p;
+      t -= dt;
+      if (std::fabs(dt) < 1e-19L) break;
+    }
+    x[j] = t;
+  }
+  out.resize(k + 1);
+  for (int j = 0; j <= k; ++j) out[j] = (double)(0.5L * (x[j] + 1.0L));
+  out[0] = 0.0;
+  out[k] = 1.0;
+}
+
+void gauss_points(int n, std::vector<double>& xo, std::vector<double>& wo) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  xo.resize(n);
+  wo.resize(n);
+  for (int i = 0; i < n; ++i) {
+    long double t = -std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double p, dp;
+    for (int it = 0; it < 100; ++it) {
+      legendre(n, t, p, dp);
+      long double dt = p / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-19L) break;
+    }
+    legendre(n, t, p, dp);
+    long double w = 2.0L / ((1.0L - t * t) * dp * dp);
+    xo[i] = (double)(0.5L * (t + 1.0L));
+    wo[i] = (double)(0.5L * w);
+  }
+}
+
+void RefElement::build(int d_, int k_, double h_) {
+  d = d_;
+  k = k_;
+  h = h_;
+  const int p1 = k + 1, q1 = k + 2;
+  nv = 1;
+  ne = 1;
+  nq = 1;
+  for (int i = 0; i < d; ++i) {
+    nv *= p1;
+    nq *= q1;
+  }
+  for (int i = 0; i < d - 1; ++i) ne *= p1;
+  nc = 1 << (d - 1);
+  nf = 2 * d;
+  nl = nf * ne;
+  gll_points(k, gll);
+  gauss_points(q1, gauss, gw);
+
+  // 1D tables: l[i][q] = l_i(g_q), dl[i][q] = l_i'(g_q), end[i][side] = l_i(side)
+  std::vector<double> l(p1 * q1), dl(p1 * q1), end(p1 * 2);
+  for (int i = 0; i < p1; ++i) {
+    for (int q = 0; q < q1; ++q) {
+      l[i * q1 + q] = (double)lagrange_value(gll, i, gauss[q]);
+      dl[i * q1 + q] = (double)(lagrange_deriv(gll, i, gauss[q]) / h);
+    }
+    end[i * 2 + 0] = (i == 0) ? 1.0 : 0.0;
+    end[i * 2 + 1] = (i == k) ? 1.0 : 0.0;
+  }
+  auto digit = [](int idx, int base, int pos) {
+    for (int t = 0; t < pos; ++t) idx /= base;
+    return idx % base;
+  };
+
+  // volume quadrature
+  Phi.assign((size_t)nq * nv, 1.0);
+  Wq.assign(nq, 1.0);
+  std::vector<double> dPhi((size_t)d * nq * nv, 1.0);
+  double hd = std::pow(h, d);
+  for (int Q = 0; Q < nq; ++Q) {
+    double w = hd;
+    for (int a = 0; a < d; ++a) w *= gw[digit(Q, q1, a)];
+    Wq[Q] = w;
+    for (int I = 0; I < nv; ++I) {
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) v *= l[digit(I, p1, a) * q1 + digit(Q, q1, a)];
+      Phi[(size_t)Q * nv + I] = v;
+      for (int c = 0; c < d; ++c) {
+        double g = 1.0;
+        for (int a = 0; a < d; ++a) {
+          int i = digit(I, p1, a), q = digit(Q, q1, a);
+          g *= (a == c) ? dl[i * q1 + q] : l[i * q1 + q];
+        }
+        dPhi[((size_t)c * nq + Q) * nv + I] = g;
+      }
+    }
+  }
+  M.assign((size_t)nv * nv, 0.0);
+  B.assign((size_t)d * nv * nv, 0.0);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) {
+      double s = 0.0;
+      for (int Q = 0; Q < nq; ++Q) s += Wq[Q] * Phi[(size_t)Q * nv + i] * Phi[(size_t)Q * nv + j];
+      M[(size_t)i * nv + j] = s;
+      for (int c = 0; c < d; ++c) {
+        double b = 0.0;
+        for (int Q = 0; Q < nq; ++Q)
+          b += Wq[Q] * dPhi[((size_t)c * nq + Q) * nv + j] * Phi[(size_t)Q * nv + i];
+        B[((size_t)c * nv + i) * nv + j] = b;
+      }
+    }
+
+  // face quadrature: tangential Gauss points of each face slot
+  int nfq = 1;
+  for (int i = 0; i < d - 1; ++i) nfq *= q1;
+  double hf = std::pow(h, d - 1);
+  F.assign((size_t)d * nv * nl, 0.0);
+  G.assign((size_t)nv * nl, 0.0);
+  E.assign((size_t)nv * nv, 0.0);
+  H.assign((size_t)nl * nl, 0.0);
+  std::vector<double> pf((size_t)nfq * nv), mu((size_t)nfq * ne), wf(nfq);
+  for (int s = 0; s < nf; ++s) {
+    int c = s / 2, side = s % 2;
+    double nrm = side ? 1.0 : -1.0;
+    int tang[2] = {0, 0}, nt = 0;
+    for (int a = 0; a < d; ++a)
+      if (a != c) tang[nt++] = a;
+    for (int P = 0; P < nfq; ++P) {
+      double w = hf;
+      for (int j = 0; j < d - 1; ++j) w *= gw[digit(P, q1, j)];
+      wf[P] = w;
+      for (int m = 0; m < ne; ++m) {
+        double v = 1.0;
+        for (int j = 0; j < d - 1; ++j) v *= l[digit(m, p1, j) * q1 + digit(P, q1, j)];
+        mu[(size_t)P * ne + m] = v;
+      }
+      for (int I = 0; I < nv; ++I) {
+        double v = end[digit(I, p1, c) * 2 + side];
+        for (int j = 0; j < d - 1; ++j) v *= l[digit(I, p1, tang[j]) * q1 + digit(P, q1, j)];
+        pf[(size_t)P * nv + I] = v;
+      }
+    }
+    for (int i = 0; i < nv; ++i) {
+      for (int m = 0; m < ne; ++m) {
+        double g = 0.0;
+        for (int P = 0; P < nfq; ++P) g += wf[P] * mu[(size_t)P * ne + m] * pf[(size_t)P * nv + i];
+        G[(size_t)i * nl + s * ne + m] = g;
+        F[((size_t)c * nv + i) * nl + s * ne + m] = nrm * g;
+      }
+      for (int j = 0; j < nv; ++j) {
+        double e = 0.0;
+        for (int P = 0; P < nfq; ++P) e += wf[P] * pf[(size_t)P * nv + i] * pf[(size_t)P * nv + j];
+        E[(size_t)i * nv + j] += e;
+      }
+    }
+    for (int m = 0; m < ne; ++m)
+      for (int mm = 0; mm < ne; ++mm) {
+        double v = 0.0;
+        for (int P = 0; P < nfq; ++P) v += wf[P] * mu[(size_t)P * ne + m] * mu[(size_t)P * ne + mm];
+        H[(size_t)(s * ne + m) * nl + s * ne + mm] = v;
+      }
+  }
+
+  // P1 (Q1) vertex basis of a face evaluated at its GLL nodes
+  Jp.assign((size_t)ne * nc, 1.0);
+  for (int a = 0; a < ne; ++a)
+    for (int v = 0; v < nc; ++v) {
+      double w = 1.0;
+      for (int j = 0; j < d - 1; ++j) {
+        double t = gll[digit(a, p1, j)];
+        w *= ((v >> j) & 1) ? t : 1.0 - t;
+      }
+      Jp[(size_t)a * nc + v] = w;
+    }
+}
+
+}  // namespace hdg

@@ -1,0 +1,522 @@
+// Trace-space kernels of the V-cycle (gfx950): matrix-free trace apply
+// (eq. trace_linear_system, unassembled element DtN maps pulled per face),
+// face-block Jacobi (Sec. 4.1), p-transfers (eqs. n_g1_Ik, n_g1_Qk),
+// local correction (eq. localCorrection), h-transfers (eqs. n_1_Ik, n_1_Qk)
+// and the coarsest direct solve (Algorithm 1, B_1 = A_1^-1).
+//
+// One lane per interior face.  The two element matrices that touch a face
+// are read as one contiguous face-major AoSoA-64 block, so every matrix load
+// of a wavefront is a 512 B (FP64) or 256 B (FP32) contiguous segment; the
+// trace vector is gathered through the caches.  No atomics: every output is
+// written by exactly one lane, so results are bitwise reproducible.
+#include "hdg_internal.hpp"
+
+namespace hdg {
+
+namespace {
+
+template <int D>
+__device__ inline long nface_dir(int n) {
+  long v = n - 1;
+  for (int a = 1; a < D; ++a) v *= n;
+  return v;
+}
+
+// interior face id of normal c at grid coordinates g (g[c] in 1..n-1)
+template <int D>
+__device__ inline long face_id(int c, const int* g, int n) {
+  long idx = 0, stride = 1;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      idx += (long)(g[a] - 1) * stride;
+      stride *= (n - 1);
+    } else {
+      idx += (long)g[a] * stride;
+      stride *= n;
+    }
+  }
+  return c * nface_dir<D>(n) + idx;
+}
+
+template <int D>
+__device__ inline int decode_face(long F, int n, int* g) {
+  long nfd = nface_dir<D>(n);
+  int c = (int)(F / nfd);
+  long r = F % nfd;
+  for (int a = 0; a < D; ++a) {
+    int ext = a == c ? n - 1 : n;
+    g[a] = (int)(r % ext) + (a == c ? 1 : 0);
+    r /= ext;
+  }
+  return c;
+}
+
+template <int D>
+__device__ inline void decode_elem(long T, int n, int* e) {
+  for (int a = 0; a < D; ++a) {
+    e[a] = (int)(T % n);
+    T /= n;
+  }
+}
+
+template <int D>
+__device__ inline long elem_id(const int* e, int n) {
+  long T = 0;
+  for (int a = D - 1; a >= 0; --a) T = T * n + e[a];
+  return T;
+}
+
+// -------------------------------------------------------------------------
+// y = A x | y = b - A x | y = x + Dinv (b - A x) | rc = Jp^T (b - A x)
+template <int D, int NE, typename T, int MODE>
+__global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
+                                                    const T* __restrict__ x, const T* __restrict__ bvec,
+                                                    T* __restrict__ y, const double* __restrict__ Jp,
+                                                    T* __restrict__ rc) {
+  constexpr int NL = 2 * D * NE;
+  const long nface = D * nface_dir<D>(n);
+  const long F = blockIdx.x * 256L + threadIdx.x;
+  if (F >= nface) return;
+  int g[3] = {0, 0, 0};
+  const int c = decode_face<D>(F, n, g);
+  T acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = T(0);
+  const T* Mbase = Af + (F >> 6) * (2L * NL * NE * LANES) + (F & 63);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    int e[3] = {g[0], g[1], g[2]};
+    e[c] = g[c] - 1 + side;
+    const T* M = Mbase + side * (long)NL * NE * LANES;
+#pragma unroll
+    for (int sl = 0; sl < 2 * D; ++sl) {
+      const int cc = sl / 2, sd = sl % 2;
+      const int p = e[cc] + sd;
+      if (p == 0 || p == n) continue;
+      int fg[3] = {e[0], e[1], e[2]};
+      fg[cc] = p;
+      const T* xf = x + face_id<D>(cc, fg, n) * NE;
+#pragma unroll
+      for (int bb = 0; bb < NE; ++bb) {
+        const T xv = xf[bb];
+#pragma unroll
+        for (int a = 0; a < NE; ++a) acc[a] += M[((sl * NE + bb) * NE + a) * LANES] * xv;
+      }
+    }
+  }
+  if (MODE == APPLY_Y) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = acc[a];
+  } else if (MODE == APPLY_RES) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = bvec[F * NE + a] - acc[a];
+  } else if (MODE == APPLY_SWEEP) {
+    T res[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
+    const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      T s = x[F * NE + a];
+#pragma unroll
+      for (int bb = 0; bb < NE; ++bb) s += Dp[(a * NE + bb) * LANES] * res[bb];
+      y[F * NE + a] = s;
+    }
+  } else {  // residual restricted by J_N^T (p-coarsening)
+    constexpr int NC = 1 << (D - 1);
+    T res[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+      T s = T(0);
+#pragma unroll
+      for (int a = 0; a < NE; ++a) s += T(Jp[a * NC + v]) * res[a];
+      rc[F * NC + v] = s;
+    }
+  }
+}
+
+// e = Dinv r (first sweep from e = 0)
+template <int NE, typename T>
+__global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* __restrict__ r, T* __restrict__ e) {
+  const long F = blockIdx.x * 256L + threadIdx.x;
+  if (F >= nface) return;
+  const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
+  T rv[NE];
+#pragma unroll
+  for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    T s = T(0);
+#pragma unroll
+    for (int b = 0; b < NE; ++b) s += Dp[(a * NE + b) * LANES] * rv[b];
+    e[F * NE + a] = s;
+  }
+}
+
+// e += J_N ec on every face (p-prolongation)
+template <int NE, int NC, typename T>
+__global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, const T* __restrict__ ec,
+                                 T* __restrict__ e) {
+  const long F = blockIdx.x * 256L + threadIdx.x;
+  if (F >= nface) return;
+  T cv[NC];
+#pragma unroll
+  for (int v = 0; v < NC; ++v) cv[v] = ec[F * NC + v];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    T s = e[F * NE + a];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) s += T(Jp[a * NC + v]) * cv[v];
+    e[F * NE + a] = s;
+  }
+}
+
+// interior faces of a coarse macro-element m (grid n/2) on the fine grid n:
+// iota = c * 2^(D-1) + lex(t) over the tangential child bits t.
+template <int D>
+__device__ inline long macro_iface(const int* m, int iota, int n) {
+  constexpr int NS = 1 << (D - 1);
+  const int c = iota / NS, t = iota % NS;
+  int g[3] = {0, 0, 0};
+  int j = 0;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      g[a] = 2 * m[a] + 1;
+    } else {
+      g[a] = 2 * m[a] + ((t >> j) & 1);
+      ++j;
+    }
+  }
+  return face_id<D>(c, g, n);
+}
+
+// Local correction and the macro-element part of the restriction:
+//   e_I += A_II^-1 rho_I            (eq. localCorrection, when do_corr)
+//   cb_M = P_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__ AIIinv, const T* __restrict__ P,
+                                                    const T* __restrict__ rho, T* __restrict__ e, int do_corr,
+                                                    int do_restrict, T* __restrict__ cb) {
+  constexpr int NC = 1 << (D - 1);
+  constexpr int NIF = D * NC;  // interior faces per macro-element
+  constexpr int NI = NIF * NC;
+  constexpr int NCL = 2 * D * NC;
+  const int nm = n / 2;
+  long nmacro = 1;
+  for (int a = 0; a < D; ++a) nmacro *= nm;
+  const long M = blockIdx.x * 256L + threadIdx.x;
+  if (M >= nmacro) return;
+  int m[3] = {0, 0, 0};
+  decode_elem<D>(M, nm, m);
+  T rI[NI];
+  long fid[NIF];
+#pragma unroll
+  for (int i = 0; i < NIF; ++i) {
+    fid[i] = macro_iface<D>(m, i, n);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rI[i * NC + a] = rho[fid[i] * NC + a];
+  }
+  const long base = (M >> 6) * LANES;
+  const long lane = M & 63;
+  if (do_corr) {
+    const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + lane;
+#pragma unroll
+    for (int i = 0; i < NIF; ++i) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rI[j];
+        e[fid[i] * NC + a] += s;
+      }
+    }
+  }
+  if (do_restrict) {
+    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + lane;
+#pragma unroll
+    for (int j = 0; j < NCL; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int i = 0; i < NI; ++i) s += Pm[(i * NCL + j) * LANES] * rI[i];
+      cb[(base + lane) * NCL + j] = s;
+    }
+  }
+}
+
+// weight of coarse vertex V at fine vertex v of sub-face t of a macro-face
+template <int D>
+__device__ inline double jh_weight(int t, int v, int V) {
+  double w = 1.0;
+#pragma unroll
+  for (int j = 0; j < D - 1; ++j) {
+    double s = 0.5 * (((t >> j) & 1) + ((v >> j) & 1));
+    w *= ((V >> j) & 1) ? s : 1.0 - s;
+  }
+  return w;
+}
+
+// sub-face t of coarse face with grid coords G (coarse grid) on the fine grid
+template <int D>
+__device__ inline long subface(int c, const int* G, int t, int n) {
+  int g[3] = {0, 0, 0};
+  int j = 0;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      g[a] = 2 * G[a];
+    } else {
+      g[a] = 2 * G[a] + ((t >> j) & 1);
+      ++j;
+    }
+  }
+  return face_id<D>(c, g, n);
+}
+
+// rc_F = J^T rho_B(F) + cb_{M-}(slot 2c+1) + cb_{M+}(slot 2c)   (eq. n_1_Qk)
+template <int D, typename T>
+__global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __restrict__ cb, T* __restrict__ rc) {
+  constexpr int NC = 1 << (D - 1);
+  constexpr int NS = NC;
+  constexpr int NCL = 2 * D * NC;
+  const int nm = n / 2;
+  const long ncf = D * nface_dir<D>(nm);
+  const long Fc = blockIdx.x * 256L + threadIdx.x;
+  if (Fc >= ncf) return;
+  int G[3] = {0, 0, 0};
+  const int c = decode_face<D>(Fc, nm, G);
+  T out[NC];
+#pragma unroll
+  for (int V = 0; V < NC; ++V) out[V] = T(0);
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const long f = subface<D>(c, G, t, n);
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+      const T rv = rho[f * NC + v];
+#pragma unroll
+      for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+    }
+  }
+  int mm[3] = {G[0], G[1], G[2]};
+  mm[c] = G[c] - 1;
+  const long Mm = elem_id<D>(mm, nm);
+  mm[c] = G[c];
+  const long Mp = elem_id<D>(mm, nm);
+#pragma unroll
+  for (int V = 0; V < NC; ++V) {
+    out[V] += cb[Mm * NCL + (2 * c + 1) * NC + V];
+    out[V] += cb[Mp * NCL + (2 * c) * NC + V];
+    rc[Fc * NC + V] = out[V];
+  }
+}
+
+// e_I += P_M ec_M per macro-element (blocks [0, nbm)), e_B += J ec per coarse
+// face (blocks [nbm, ...))   (eq. n_1_Ik)
+template <int D, typename T>
+__global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T* __restrict__ P,
+                                                       const T* __restrict__ ec, T* __restrict__ e) {
+  constexpr int NC = 1 << (D - 1);
+  constexpr int NIF = D * NC;
+  constexpr int NI = NIF * NC;
+  constexpr int NCL = 2 * D * NC;
+  const int nm = n / 2;
+  if (blockIdx.x < nbm) {
+    long nmacro = 1;
+    for (int a = 0; a < D; ++a) nmacro *= nm;
+    const long M = blockIdx.x * 256L + threadIdx.x;
+    if (M >= nmacro) return;
+    int m[3] = {0, 0, 0};
+    decode_elem<D>(M, nm, m);
+    T cv[NCL];
+#pragma unroll
+    for (int sl = 0; sl < 2 * D; ++sl) {
+      const int cc = sl / 2, sd = sl % 2;
+      const int p = m[cc] + sd;
+      if (p == 0 || p == nm) {
+#pragma unroll
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = T(0);
+      } else {
+        int G[3] = {m[0], m[1], m[2]};
+        G[cc] = p;
+        const long Fc = face_id<D>(cc, G, nm);
+#pragma unroll
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
+      }
+    }
+    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + (M & 63);
+#pragma unroll
+    for (int i = 0; i < NIF; ++i) {
+      const long f = macro_iface<D>(m, i, n);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T s = e[f * NC + a];
+#pragma unroll
+        for (int j = 0; j < NCL; ++j) s += Pm[((i * NC + a) * NCL + j) * LANES] * cv[j];
+        e[f * NC + a] = s;
+      }
+    }
+  } else {
+    const long ncf = D * nface_dir<D>(nm);
+    const long Fc = (blockIdx.x - nbm) * 256L + threadIdx.x;
+    if (Fc >= ncf) return;
+    int G[3] = {0, 0, 0};
+    const int c = decode_face<D>(Fc, nm, G);
+    T cv[NC];
+#pragma unroll
+    for (int V = 0; V < NC; ++V) cv[V] = ec[Fc * NC + V];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const long f = subface<D>(c, G, t, n);
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        T s = e[f * NC + v];
+#pragma unroll
+        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[V];
+        e[f * NC + v] = s;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    T s = T(0);
+    for (int j = 0; j < N; ++j) s += Ainv[i * N + j] * r[j];
+    e[i] = s;
+  }
+}
+
+inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename F>
+void dispatch_d_ne(int d, int ne, F&& f) {
+#define HDG_CASE(DD, NN)                                                            \
+  if (d == DD && ne == NN) {                                                        \
+    f(std::integral_constant<int, DD>{}, std::integral_constant<int, NN>{});        \
+    return;                                                                         \
+  }
+  HDG_CASE(2, 2) HDG_CASE(2, 3) HDG_CASE(2, 4) HDG_CASE(2, 5) HDG_CASE(2, 6) HDG_CASE(2, 7)
+  HDG_CASE(3, 4) HDG_CASE(3, 9) HDG_CASE(3, 16)
+#undef HDG_CASE
+  throw HipError{hipErrorInvalidValue, "unsupported (d, ne)"};
+}
+
+}  // namespace
+
+template <typename T>
+void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
+                  hipStream_t st) {
+  if (L.nface == 0) return;
+  const T* Af = nullptr;
+  const T* Dv = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    Af = (const T*)L.Af64;
+    Dv = (const T*)L.Dinv64;
+  } else {
+    Af = (const T*)L.Af32;
+    Dv = (const T*)L.Dinv32;
+  }
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+    switch (mode) {
+      case APPLY_Y:
+        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_Y>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv, x,
+                           b, y, Jp, rc);
+        break;
+      case APPLY_RES:
+        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv,
+                           x, b, y, Jp, rc);
+        break;
+      case APPLY_SWEEP:
+        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_SWEEP>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af,
+                           Dv, x, b, y, Jp, rc);
+        break;
+      default:
+        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(nblk(L.nface)), dim3(256), 0, st,
+                           L.n, Af, Dv, x, b, y, Jp, rc);
+        break;
+    }
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st) {
+  if (L.nface == 0) return;
+  const T* Dv = sizeof(T) == 8 ? (const T*)L.Dinv64 : (const T*)L.Dinv32;
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int NE = decltype(NE_)::value;
+    hipLaunchKernelGGL((jacobi0_kernel<NE, T>), dim3(nblk(L.nface)), dim3(256), 0, st, L.nface, Dv, r, e);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st) {
+  if (L.nface == 0) return;
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+    constexpr int NC = 1 << (D - 1);
+    hipLaunchKernelGGL((prolong_p_kernel<NE, NC, T>), dim3(nblk(L.nface)), dim3(256), 0, st, L.nface, Jp, ec, e);
+  });
+  (void)nc;
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st) {
+  const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
+  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  if (L.d == 2)
+    hipLaunchKernelGGL((hcorr_kernel<2, T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Ai, P, rho, e, do_corr,
+                       do_restrict, cb);
+  else
+    hipLaunchKernelGGL((hcorr_kernel<3, T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Ai, P, rho, e, do_corr,
+                       do_restrict, cb);
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st) {
+  if (C.nface == 0) return;
+  if (L.d == 2)
+    hipLaunchKernelGGL((hrestrict_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, rho, cb, rc);
+  else
+    hipLaunchKernelGGL((hrestrict_kernel<3, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, rho, cb, rc);
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st) {
+  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
+  if (L.d == 2)
+    hipLaunchKernelGGL((hprolong_kernel<2, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, P, ec, e);
+  else
+    hipLaunchKernelGGL((hprolong_kernel<3, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, P, ec, e);
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st) {
+  if (L.nlam == 0) return;
+  const T* Ai = sizeof(T) == 8 ? (const T*)L.Ainv64 : (const T*)L.Ainv32;
+  hipLaunchKernelGGL((coarse_solve_kernel<T>), dim3(1), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
+  HDG_CHECK(hipGetLastError());
+}
+
+#define HDG_INST(T)                                                                                         \
+  template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t);  \
+  template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t);                                  \
+  template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t);            \
+  template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t);                      \
+  template void launch_hrestrict<T>(const Level&, const Level&, const T*, const T*, T*, hipStream_t);        \
+  template void launch_hprolong<T>(const Level&, const Level&, const T*, T*, hipStream_t);                   \
+  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t);
+HDG_INST(double)
+HDG_INST(float)
+#undef HDG_INST
+
+}  // namespace hdg

@@ -1,0 +1,207 @@
+"""Thin torch binding of the HIP library (include/hdg.h).
+
+Only argument marshalling happens here: torch provides device memory and
+the stream, every step of the solver runs in the library's kernels.  The
+library must be built (``python -m paper_1811_09909_amd.build``); without
+it, or without a GPU, every call raises.
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, device):
+    return torch.as_tensor(t, dtype=dtype, device=device).contiguous()
+
+
+class Problem:
+    """One HDG trace problem on the unit box (d = 2 or 3, n^d elements, Q^k).
+
+    ``kappa``: per element [n^d] or at the (k+2)^d Gauss points of every
+    element [n^d, (k+2)^d] (then ``kappa_kind='qp'``)."""
+
+    def __init__(self, d, n, k, kappa, tau=1.0, kappa_kind="element", store_recovery=True, device="cuda"):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HDG library needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.d, self.n, self.k, self.tau = d, n, k, float(tau)
+        self.kind = L.KAPPA_AT_QP if kappa_kind == "qp" else L.KAPPA_PER_ELEMENT
+        kap = _dev(kappa, torch.float64, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        mesh = L.Mesh(d, n)
+        h = ctypes.c_void_p()
+        L.check(self.lib.hdg_setup(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, 1 if store_recovery else 0,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hdg_setup")
+        self.h = h
+        self.nT = self.query(L.Q_NT)
+        self.nlam = self.query(L.Q_NLAMBDA)
+        self.nv = self.query(L.Q_NV)
+        self.nq = self.query(L.Q_NQ)
+        self.built = False
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, what):
+        out = ctypes.c_longlong()
+        L.check(self.lib.hdg_query(self.h, what, ctypes.byref(out)), "hdg_query")
+        return out.value
+
+    def update_kappa(self, kappa):
+        kap = _dev(kappa, torch.float64, self.device)
+        L.check(self.lib.hdg_update_kappa(self.h, _vp(kap), self.kind), "hdg_update_kappa")
+        self.built = False
+
+    def build(self, sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
+              max_it=200, restart=0):
+        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart)
+        L.check(self.lib.hdg_mg_build(self.h, ctypes.byref(o)), "hdg_mg_build")
+        self.built = True
+        self.opts = o
+        self.n_levels = self.query(L.Q_NLEVELS)
+        return self
+
+    def level_sizes(self):
+        return [self.query(L.Q_LEVEL_NLAMBDA + i) for i in range(self.n_levels)]
+
+    # -- operators -----------------------------------------------------------
+    def rhs(self, f, kind=L.RHS_F_NODAL, gdir=None):
+        f = _dev(f, torch.float64, self.device)
+        gd = None if gdir is None else _dev(gdir, torch.float64, self.device)
+        g = torch.empty(self.nlam, dtype=torch.float64, device=self.device)
+        L.check(self.lib.hdg_rhs(self.h, _vp(f), kind, _vp(gd), _vp(g)), "hdg_rhs")
+        return g
+
+    def solve(self, rhs, kind=L.RHS_F_NODAL, tol=1e-10, lam0=None, gdir=None, nrhs=1, allow_not_converged=False):
+        rhs = _dev(rhs, torch.float64, self.device)
+        gd = None if gdir is None else _dev(gdir, torch.float64, self.device)
+        lam = (torch.zeros(nrhs * self.nlam, dtype=torch.float64, device=self.device) if lam0 is None
+               else _dev(lam0, torch.float64, self.device).clone().reshape(-1))
+        info = L.Info()
+        allow = (L.HDG_ERR_NOT_CONVERGED,) if allow_not_converged else ()
+        st = L.check(self.lib.hdg_solve(self.h, _vp(rhs), kind, _vp(gd), nrhs, float(tol), _vp(lam),
+                                        ctypes.byref(info)), "hdg_solve", allow)
+        return lam, {"iters": info.iters, "relres": info.relres, "t_solve_ms": info.t_solve_ms,
+                     "n_levels": info.n_levels, "status": st}
+
+    def vcycle(self, r, precision=L.FP64):
+        dt = torch.float64 if precision == L.FP64 else torch.float32
+        r = _dev(r, dt, self.device)
+        e = torch.empty_like(r)
+        L.check(self.lib.hdg_vcycle(self.h, _vp(r), _vp(e), precision, r.numel() // max(self.nlam, 1)),
+                "hdg_vcycle")
+        return e
+
+    def reconstruct(self, lam, f, kind=L.RHS_F_NODAL, gdir=None):
+        lam = _dev(lam, torch.float64, self.device)
+        f = _dev(f, torch.float64, self.device)
+        gd = None if gdir is None else _dev(gdir, torch.float64, self.device)
+        u = torch.empty(self.nT, self.nv, dtype=torch.float64, device=self.device)
+        q = torch.empty(self.nT, self.d, self.nv, dtype=torch.float64, device=self.device)
+        L.check(self.lib.hdg_reconstruct(self.h, _vp(lam), _vp(f), kind, _vp(gd), _vp(u), _vp(q)),
+                "hdg_reconstruct")
+        return u, q
+
+    def adjoint(self, dJdu_load, q_fwd, tol=1e-10):
+        j = _dev(dJdu_load, torch.float64, self.device)
+        q = _dev(q_fwd, torch.float64, self.device)
+        grad = torch.empty(self.nT, dtype=torch.float64, device=self.device)
+        info = L.Info()
+        L.check(self.lib.hdg_adjoint(self.h, _vp(j), _vp(q), float(tol), _vp(grad), ctypes.byref(info)),
+                "hdg_adjoint")
+        return grad, {"iters": info.iters, "relres": info.relres}
+
+    def mass_apply(self, u):
+        u = _dev(u, torch.float64, self.device)
+        out = torch.empty_like(u)
+        L.check(self.lib.hdg_mass_apply(self.h, _vp(u), _vp(out)), "hdg_mass_apply")
+        return out
+
+    def level_apply(self, level, x, precision=L.FP64):
+        dt = torch.float64 if precision == L.FP64 else torch.float32
+        x = _dev(x, dt, self.device)
+        y = torch.empty_like(x)
+        L.check(self.lib.hdg_level_apply(self.h, level, _vp(x), _vp(y), precision), "hdg_level_apply")
+        return y
+
+    def level_smooth(self, level, r, sweeps, precision=L.FP64):
+        dt = torch.float64 if precision == L.FP64 else torch.float32
+        r = _dev(r, dt, self.device)
+        e = torch.empty_like(r)
+        L.check(self.lib.hdg_level_smooth(self.h, level, _vp(r), _vp(e), sweeps, precision), "hdg_level_smooth")
+        return e
+
+    def level_export(self, level):
+        if level == 0:
+            nel, nl = self.nT, 2 * self.d * (self.k + 1) ** (self.d - 1)
+        else:
+            n = self.query(L.Q_LEVEL_N + level)
+            ne = self.query(L.Q_LEVEL_NE + level)
+            nel, nl = n ** self.d, 2 * self.d * ne
+        out = torch.empty(nel, nl, nl, dtype=torch.float64, device=self.device)
+        L.check(self.lib.hdg_level_export(self.h, level, _vp(out)), "hdg_level_export")
+        return out
+
+    # -- geometry for evaluating sources and coefficients --------------------
+    def reference_nodes(self):
+        gll = (ctypes.c_double * (self.k + 1))()
+        gau = (ctypes.c_double * (self.k + 2))()
+        L.check(self.lib.hdg_reference_nodes(self.k, gll, gau), "hdg_reference_nodes")
+        return torch.tensor(list(gll), dtype=torch.float64), torch.tensor(list(gau), dtype=torch.float64)
+
+    def _tensor_points(self, pts1d):
+        d, n = self.d, self.n
+        m = len(pts1d)
+        idx = torch.arange(m ** d)
+        digits = torch.stack([(idx // m ** a) % m for a in range(d)], 1)
+        ref = pts1d[digits]
+        el = torch.arange(n ** d)
+        ec = torch.stack([(el // n ** a) % n for a in range(d)], 1).to(torch.float64)
+        return (ec[:, None, :] + ref[None]) / n
+
+    def volume_nodes(self):
+        """[N_T, (k+1)^d, d] coordinates of the GLL nodes (host tensor)."""
+        return self._tensor_points(self.reference_nodes()[0])
+
+    def volume_qpoints(self):
+        """[N_T, (k+2)^d, d] coordinates of the Gauss points (host tensor)."""
+        return self._tensor_points(self.reference_nodes()[1])
+
+
+class HDGSolve(torch.autograd.Function):
+    """U(theta): nodal u of the HDG solution for kappa_T = exp(theta_T).
+
+    backward uses the library's adjoint solve (same operator and V-cycle)
+    and returns dL/dtheta = -(q*)^T A_T q per element."""
+
+    @staticmethod
+    def forward(ctx, theta, problem, f, tol, build_kw):
+        problem.update_kappa(torch.exp(theta.detach()))
+        problem.build(**build_kw)
+        lam, info = problem.solve(f, tol=tol)
+        u, q = problem.reconstruct(lam, f)
+        ctx.problem, ctx.tol = problem, tol
+        ctx.save_for_backward(q)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        (q,) = ctx.saved_tensors
+        grad, _ = ctx.problem.adjoint(gu.contiguous(), q, ctx.tol)
+        return grad, None, None, None, None

@@ -1,0 +1,286 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Operators on identical inputs: element DtN matrices, load vectors, trace
+apply (FP64 and FP32), every coarse operator of the hierarchy, block-Jacobi
+sweeps, one V-cycle; then iterates at fixed iteration counts, converged
+solutions, local recovery and the adjoint gradient.  Meshes span several
+64-face tiles with ragged tails.  Tolerances: 1e-12 (FP64 operators),
+1e-10 (iterates, converged solutions), 1e-5 (FP32 operators).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import adjoint as oadj
+from oracle import mg as omg
+from oracle.hdg import HDG
+from paper_1811_09909_amd import inputs
+
+from ._helpers import assemble, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _kappa(d, n, lo=1e-3, hi=1e3, seed=0):
+    rng = np.random.default_rng(seed)
+    return inputs.kappa_loguniform(rng, n ** d, lo, hi), rng
+
+
+def _gpu(torch, d, n, k, kap, kind="element", **bk):
+    from paper_1811_09909_amd.hdg import Problem
+    P = Problem(d, n, k, torch.as_tensor(kap), tau=1.0, kappa_kind=kind)
+    if bk is not None:
+        P.build(**bk)
+    return P
+
+
+LC = {"pre": omg.LC_PRE, "both": omg.LC_BOTH, "none": omg.LC_NONE, "post": omg.LC_POST}
+
+
+@pytest.mark.parametrize("d,n,k,kind", [(2, 4, 1, "element"), (2, 5, 2, "element"), (2, 4, 3, "qp"),
+                                        (2, 3, 4, "element"), (2, 2, 5, "element"), (2, 2, 6, "element"),
+                                        (3, 2, 1, "element"), (3, 2, 2, "qp"), (3, 2, 3, "element")])
+def test_element_dtn_matrices(torch_cuda, d, n, k, kind):
+    say(f"[element_dtn] d={d} n={n} k={k} kappa={kind}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    if kind == "qp":
+        kap = kap[:, None] * (1.0 + 0.5 * rng.uniform(-1, 1, (n ** d, O.nq)))
+        O.set_kappa(kap)
+    P = _gpu(torch_cuda, d, n, k, kap, kind=kind)
+    Ae = P.level_export(0).cpu().numpy()
+    Ao = O.all_element_dtn()
+    worst = max(relerr(Ae[T], Ao[T]) for T in range(n ** d))
+    say(f"  worst element relerr {worst:.2e}")
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 9, 3), (3, 3, 2)])
+def test_rhs_with_dirichlet_data(torch_cuda, d, n, k):
+    say(f"[rhs] d={d} n={n} k={k}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    f = rng.standard_normal((n ** d, O.nv))
+
+    def gD(X):
+        return np.cos(3 * X.sum(1)) + X[:, 0] ** 2
+    A, g, lb = O.assemble(f, gD)
+    P = _gpu(torch_cuda, d, n, k, kap)
+    gg = P.rhs(torch_cuda.as_tensor(f), gdir=torch_cuda.as_tensor(lb)).cpu().numpy()
+    say(f"  relerr {relerr(gg, g):.2e}")
+    assert relerr(gg, g) <= 1e-12
+    # load form: b_T given directly
+    _, g2, _ = O.assemble(f)
+    b = f @ O.M.T
+    gl = P.rhs(torch_cuda.as_tensor(b), kind=1).cpu().numpy()
+    assert relerr(gl, g2) <= 1e-12
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 1), (2, 16, 2), (2, 12, 4), (3, 4, 1), (3, 3, 3)])
+def test_trace_apply_fp64_fp32(torch_cuda, d, n, k):
+    say(f"[apply] d={d} n={n} k={k}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    P = _gpu(torch_cuda, d, n, k, kap)
+    P.build()
+    x = rng.standard_normal(A.shape[0])
+    y = P.level_apply(0, torch_cuda.as_tensor(x)).cpu().numpy()
+    say(f"  fp64 relerr {relerr(y, A @ x):.2e}")
+    assert relerr(y, A @ x) <= 1e-13
+    y32 = P.level_apply(0, torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  fp32 relerr {relerr(y32, A @ x):.2e}")
+    assert relerr(y32, A @ x) <= 2e-6
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 16, 1), (2, 16, 3), (3, 4, 2), (3, 8, 1)])
+def test_hierarchy_operators_and_smoother(torch_cuda, d, n, k):
+    say(f"[hierarchy] d={d} n={n} k={k}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    H = omg.Hierarchy(A, d, n, k)
+    P = _gpu(torch_cuda, d, n, k, kap)
+    P.build()
+    assert P.n_levels == len(H.levels)
+    assert P.level_sizes() == [L.A.shape[0] for L in H.levels]
+    for lvl in range(1, P.n_levels):
+        Lo = H.levels[lvl]
+        Ag = assemble(P.level_export(lvl).cpu().numpy(), d, Lo.mesh.n, Lo.m)
+        err = abs(Ag - Lo.A).max() / abs(Lo.A).max()
+        say(f"  level {lvl}: N={Lo.A.shape[0]} coarse-operator err {err:.2e}")
+        assert err <= 1e-11
+    for lvl in range(P.n_levels):
+        Lo = H.levels[lvl]
+        x = rng.standard_normal(Lo.A.shape[0])
+        y = P.level_apply(lvl, torch_cuda.as_tensor(x)).cpu().numpy()
+        assert relerr(y, Lo.A @ x) <= 1e-12
+        for m in (1, 3):
+            e = P.level_smooth(lvl, torch_cuda.as_tensor(x), m).cpu().numpy()
+            eo = H.block_jacobi(lvl, x, m)
+            say(f"  level {lvl} smoother m={m} err {relerr(e, eo):.2e}")
+            assert relerr(e, eo) <= 1e-11
+
+
+@pytest.mark.parametrize("d,n,k,lc,sweeps,growth", [(2, 8, 2, "pre", 2, 1), (2, 16, 3, "both", 2, 1),
+                                                    (2, 16, 1, "none", 1, 2), (2, 8, 4, "post", 3, 2),
+                                                    (3, 4, 2, "pre", 2, 1), (3, 4, 1, "both", 1, 1)])
+def test_vcycle(torch_cuda, d, n, k, lc, sweeps, growth):
+    say(f"[vcycle] d={d} n={n} k={k} lc={lc} sweeps={sweeps} growth={growth}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    H = omg.Hierarchy(A, d, n, k, sweeps=sweeps, growth=growth, local_corr=LC[lc])
+    P = _gpu(torch_cuda, d, n, k, kap)
+    P.build(sweeps=sweeps, growth=growth, local_corr=LC[lc])
+    r = rng.standard_normal(A.shape[0])
+    eo = H.vcycle(r)
+    e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+    say(f"  fp64 relerr {relerr(e, eo):.2e}")
+    assert relerr(e, eo) <= 1e-11
+    e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  fp32 relerr {relerr(e32, eo):.2e}")
+    assert relerr(e32, eo) <= 1e-3
+
+
+@pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
+def test_iterates_at_fixed_count(torch_cuda, method):
+    d, n, k = 2, 16, 2
+    say(f"[iterates] {method}")
+    kap, rng = _kappa(d, n, 1e-1, 1e1)
+    O = HDG(d, n, k, 1.0, kap)
+    f = rng.standard_normal((n * n, O.nv))
+    A, g, _ = O.assemble(f)
+    lc = omg.LC_BOTH if method == "pcg" else omg.LC_PRE
+    H = omg.Hierarchy(A, d, n, k, local_corr=lc)
+    mid = {"mg": 0, "pcg": 1, "gmres": 2}[method]
+    P = _gpu(torch_cuda, d, n, k, kap)
+    for its in (1, 3):
+        P.build(local_corr=lc, method=mid, max_it=its)
+        lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-14, allow_not_converged=True)
+        if method == "mg":
+            ro = omg.mg_solve(H, A, g, tol=1e-14, maxit=its)
+        elif method == "pcg":
+            ro = omg.pcg_solve(H, A, g, tol=1e-14, maxit=its)
+        else:
+            ro = omg.gmres_solve(H, A, g, tol=1e-14, maxit=its)
+        err = relerr(lam.cpu().numpy(), ro.lam)
+        say(f"  its={its} gpu iters={info['iters']} relerr {err:.2e}")
+        assert info["iters"] == its == ro.iters
+        assert err <= 1e-10
+
+
+@pytest.mark.parametrize("method,prec", [("mg", 0), ("pcg", 0), ("gmres", 0), ("mg", 1), ("pcg", 1), ("gmres", 1)])
+def test_converged_solution(torch_cuda, method, prec):
+    d, n, k = 2, 32, 3
+    say(f"[converged] {method} precision={prec}")
+    kap, rng = _kappa(d, n, 1e-2, 1e2)
+    O = HDG(d, n, k, 1.0, kap)
+    f = rng.standard_normal((n * n, O.nv))
+    A, g, _ = O.assemble(f)
+    lam_ref = spla.spsolve(A.tocsc(), g)
+    mid = {"mg": 0, "pcg": 1, "gmres": 2}[method]
+    lc = omg.LC_BOTH if method == "pcg" else omg.LC_PRE
+    P = _gpu(torch_cuda, d, n, k, kap)
+    P.build(local_corr=lc, method=mid, precision=prec, max_it=400)
+    lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+    lam = lam.cpu().numpy()
+    rel = np.linalg.norm(g - A @ lam) / np.linalg.norm(g)
+    say(f"  iters={info['iters']} gpu relres={info['relres']:.2e} oracle relres={rel:.2e} "
+        f"err={relerr(lam, lam_ref):.2e}")
+    assert rel <= 1.05e-10
+    assert info["relres"] <= 1e-10
+    # two solves both stopped at 1e-10 differ by at most cond * 1e-10
+    assert relerr(lam, lam_ref) <= 1e-6
+
+
+def test_iteration_counts_match_oracle(torch_cuda):
+    wl = inputs.poisson2d(8, 2)
+    say("[counts] poisson2d n=8 k=2")
+    O = HDG(2, 8, 2, 1.0, wl.kappa)
+    f = wl.f(O.volume_nodes())
+    A, g, _ = O.assemble(f)
+    P = _gpu(torch_cuda, 2, 8, 2, wl.kappa)
+    for method, fn, lc in [(0, omg.mg_solve, omg.LC_PRE), (1, omg.pcg_solve, omg.LC_BOTH),
+                           (2, omg.gmres_solve, omg.LC_PRE)]:
+        for sweeps, growth in [(2, 1), (3, 2)]:
+            H = omg.Hierarchy(A, 2, 8, 2, sweeps=sweeps, growth=growth, local_corr=lc)
+            ro = fn(H, A, g, tol=1e-10)
+            P.build(sweeps=sweeps, growth=growth, local_corr=lc, method=method)
+            lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+            say(f"  method={method} sweeps={sweeps} growth={growth}: gpu {info['iters']} oracle {ro.iters}")
+            assert abs(info["iters"] - ro.iters) <= (1 if method == 1 else 0)
+            assert relerr(lam.cpu().numpy(), ro.lam) <= 1e-9
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 4, 5), (3, 2, 2)])
+def test_reconstruction(torch_cuda, d, n, k):
+    say(f"[reconstruct] d={d} n={n} k={k}")
+    kap, rng = _kappa(d, n)
+    O = HDG(d, n, k, 1.0, kap)
+    f = rng.standard_normal((n ** d, O.nv))
+    A, g, lb = O.assemble(f)
+    lam = spla.spsolve(A.tocsc(), g)
+    uo, qo = O.reconstruct(lam, f, lb)
+    P = _gpu(torch_cuda, d, n, k, kap)
+    u, q = P.reconstruct(torch_cuda.as_tensor(lam), torch_cuda.as_tensor(f))
+    say(f"  u {relerr(u.cpu().numpy(), uo):.2e} q {relerr(q.cpu().numpy(), qo):.2e}")
+    assert relerr(u.cpu().numpy(), uo) <= 1e-12
+    assert relerr(q.cpu().numpy(), qo) <= 1e-12
+
+
+def test_manufactured_solution_end_to_end(torch_cuda):
+    """Poisson on 8x8, k=2: GPU solve + recovery vs the oracle and the exact solution."""
+    wl = inputs.poisson2d(8, 2)
+    say("[poisson2d end-to-end]")
+    P = _gpu(torch_cuda, 2, 8, 2, wl.kappa)
+    P.build(method=1, local_corr=omg.LC_BOTH)
+    f = wl.f(P.volume_nodes().numpy())
+    lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+    u, q = P.reconstruct(lam, torch_cuda.as_tensor(f))
+    O = HDG(2, 8, 2, 1.0, wl.kappa)
+    fo = wl.f(O.volume_nodes())
+    assert np.abs(f - fo).max() < 1e-14
+    A, g, lb = O.assemble(fo)
+    lam_ref = spla.spsolve(A.tocsc(), g)
+    uo, qo = O.reconstruct(lam_ref, fo, lb)
+    assert relerr(u.cpu().numpy(), uo) <= 1e-9
+    eu, eq = O.errors(u.cpu().numpy(), q.cpu().numpy(), wl.u_exact, wl.grad_exact)
+    euo, eqo = O.errors(uo, qo, wl.u_exact, wl.grad_exact)
+    say(f"  L2 errors gpu {eu:.3e} {eq:.3e} oracle {euo:.3e} {eqo:.3e}")
+    assert abs(eu - euo) <= 1e-9 * euo and abs(eq - eqo) <= 1e-9 * eqo
+
+
+def test_adjoint_gradient(torch_cuda):
+    d, n, k = 2, 8, 2
+    say("[adjoint] 8x8 k=2")
+    rng = np.random.default_rng(5)
+    O = HDG(d, n, k, 1.0, np.ones(n * n))
+    theta = rng.standard_normal(n * n)
+    f = np.ones((n * n, O.nv))
+    u0, _, _, _ = oadj.forward(O, np.zeros(n * n), f)
+    u_obs = u0 + 0.01 * np.sqrt(np.mean(u0 ** 2)) * rng.standard_normal(u0.shape)
+    J, go = oadj.gradient(O, theta, f, u_obs)
+    P = _gpu(torch_cuda, d, n, k, np.exp(theta))
+    P.build(method=1, local_corr=omg.LC_BOTH)
+    lam, _ = P.solve(torch_cuda.as_tensor(f), tol=1e-13)
+    u, q = P.reconstruct(lam, torch_cuda.as_tensor(f))
+    j = P.mass_apply(u - torch_cuda.as_tensor(u_obs))
+    grad, info = P.adjoint(j, q, tol=1e-13)
+    say(f"  grad relerr {relerr(grad.cpu().numpy(), go):.2e}")
+    assert relerr(grad.cpu().numpy(), go) <= 1e-9

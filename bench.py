@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the HDG trace multigrid solve on one MI355X.
+
+Workload (default): 2D diffusion -div(kappa grad u) = f on the unit square,
+512 x 512 quads, HDG degree k = 4, tau = 1, kappa per element log-uniform in
+[1e-3, 1e3], nodal f ~ N(0, 1), zero Dirichlet data, seed 0 (synthetic).
+
+A step is one complete solve: the load vector g from the nodal source, then
+the outer iteration (V-cycle-preconditioned CG) until the FP64 residual
+||g - A lambda|| <= 1e-10 ||g||.  `value` is the mixed-precision leg (FP32
+V-cycle inside FP64 CG); the FP64 leg is reported beside it.  Operator setup
+(element DtN maps, hierarchy) is outside the step and reported separately.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+METRIC = "trace DOFs/s to rel. resid 1e-10: FP64 vs FP32 V-cycle+FP64 refine"
+HERE = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--method", default="pcg", choices=["mg", "pcg", "gmres"])
+    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--growth", type=int, default=1)
+    ap.add_argument("--max-it", type=int, default=20000)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, k):
+    """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of the workload:
+    same kappa/f distribution on an n x n mesh; times the solve only."""
+    sys.path.insert(0, HERE)
+    from oracle import mg as omg
+    from oracle.hdg import HDG
+    from paper_1811_09909_amd import inputs
+    wl = inputs.diffusion2d(n, k, 1e-3, 1e3, seed=0)
+    t0 = time.perf_counter()
+    O = HDG(2, n, k, 1.0, wl.kappa)
+    A, g, _ = O.assemble(wl.f)
+    t1 = time.perf_counter()
+    H = omg.Hierarchy(A, 2, n, k, sweeps=2, growth=1, local_corr=omg.LC_BOTH)
+    t2 = time.perf_counter()
+    r = omg.pcg_solve(H, A, g, tol=1e-10, maxit=20000)
+    t3 = time.perf_counter()
+    return {"n": n, "k": k, "trace_dofs": int(A.shape[0]), "setup_s": t1 - t0, "build_s": t2 - t1,
+            "solve_s": t3 - t2, "iters": r.iters, "relres": r.relres}
+
+
+def run_cpu_baseline(n, k):
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
+        env[v] = "1"
+    env["HIP_VISIBLE_DEVICES"] = ""
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-n", str(n),
+                          "--k", str(k)], capture_output=True, text=True, env=env, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": res["trace_dofs"] / res["solve_s"], "unit": "trace DOFs/s", "cores": 1, "kind": "oracle",
+            "sample": f"diffusion2d n={n} k={k} (same kappa/f distribution, seed 0), oracle CG + V-cycle "
+                      f"solve to 1e-10: {res['iters']} iterations in {res['solve_s']:.1f} s "
+                      f"(assembly {res['setup_s']:.1f} s, hierarchy {res['build_s']:.1f} s excluded); "
+                      "single-threaded SciPy/NumPy",
+            "iters": res["iters"], "trace_dofs": res["trace_dofs"]}
+
+
+def main():
+    args = parse()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_n, args.k)))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
+              "design note, not a build target", file=sys.stderr)
+        return 2
+    import torch
+    sys.path.insert(0, HERE)
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, k = args.n, args.k
+    wl = inputs.diffusion2d(n, k, 1e-3, 1e3, seed=0)
+    kap = torch.as_tensor(wl.kappa, device=dev)
+    f = torch.as_tensor(wl.f, device=dev)
+    method = {"mg": L.METHOD_MG, "pcg": L.METHOD_PCG, "gmres": L.METHOD_GMRES}[args.method]
+    lc = L.LC_BOTH if args.method == "pcg" else L.LC_PRE
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Problem(2, n, k, kap, tau=1.0, store_recovery=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    N = P.nlam
+
+    def leg(precision, profile):
+        t0 = time.perf_counter()
+        P.build(sweeps=args.sweeps, growth=args.growth, local_corr=lc, precision=precision, method=method,
+                max_it=args.max_it)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            P.solve(f, tol=args.tol)
+        torch.cuda.synchronize()
+        if profile:
+            P.profile_begin()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lam, info = P.solve(f, tol=args.tol)
+            infos.append(info)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = {}
+            for mode, name in [(0, "apply"), (1, "residual"), (2, "sweep"), (3, "residual_prestrict")]:
+                for pr, pn in [(0, "fp64"), (1, "fp32")]:
+                    r = P.profile_read(mode, pr)
+                    if r["launches"]:
+                        prof[f"{name}_{pn}"] = r
+        return {"elapsed_s": el, "ms_per_step": 1e3 * el / args.steps, "value": N * args.steps / el,
+                "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos), "build_s": t_build,
+                "n_levels": infos[-1]["n_levels"], "prof": prof, "lam": lam}
+
+    res64 = None if args.skip_fp64 else leg(L.FP64, False)
+    resmx = leg(L.MIXED, True)
+    # recovery of (u, q) from the mixed solution, timed once (outside the step)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, q = P.reconstruct(resmx["lam"], f)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+
+    # dominant kernel of the mixed leg: largest summed event time
+    prof = resmx["prof"]
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"trace {dom_name} (finest level)",
+                "avg_launch_ms": round(avg_ms, 5), "launches": dom["launches"],
+                "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
+    kernels = {name: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 5),
+                      "GBps": round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e9, 1)}
+               for name, v in prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = run_cpu_baseline(args.cpu_n, k)
+        except Exception as e:  # reported, never fatal for the GPU figure
+            cpu = {"error": str(e)[:300]}
+
+    out = {
+        "metric": METRIC, "value": round(resmx["value"], 1), "unit": "trace DOFs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(resmx["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 V-cycle + f64 CG",
+        "data": "synthetic",
+        "config": {"workload": wl.name + " tau=1", "trace_dofs": N, "levels": resmx["n_levels"],
+                   "method": f"{args.method} + V-cycle (sweeps {args.sweeps}, growth {args.growth})",
+                   "tol": args.tol, "iters_mixed": resmx["iters"], "relres_mixed": resmx["relres"],
+                   "fp64": None if res64 is None else {"value": round(res64["value"], 1),
+                                                       "ms_per_step": round(res64["ms_per_step"], 3),
+                                                       "iters": res64["iters"], "relres": res64["relres"]},
+                   "setup_ms": round(1e3 * t_setup, 2), "build_ms_mixed": round(1e3 * resmx["build_s"], 2),
+                   "reconstruct_ms": round(1e3 * t_rec, 3),
+                   "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1)},
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

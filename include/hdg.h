@@ -159,6 +159,18 @@ hdg_status hdg_level_smooth(hdg_handle h, int level, const void* r, void* e, int
  * x-,x+,y-,y+,(z-,z+) then node) into out (device, double). */
 hdg_status hdg_level_export(hdg_handle h, int level, double* out);
 
+/* Inspection: time every launch of the finest-level trace kernels with HIP
+ * events recorded on the handle's stream, from hdg_profile_begin until
+ * hdg_profile_read.  kernel = 2 * mode + precision, mode 0 apply y = A x,
+ * 1 residual b - A x, 2 block-Jacobi sweep x + D^-1 (b - A x), 3 residual
+ * restricted to P1 (J_N^T); precision HDG_FP64 / HDG_FP32.  Returns the
+ * number of launches, their summed duration, and the algorithmic HBM bytes
+ * of one launch (stored face-major matrix blocks, face-block inverses and
+ * each vector entry read or written once). */
+hdg_status hdg_profile_begin(hdg_handle h);
+hdg_status hdg_profile_read(hdg_handle h, int kernel, long long* launches, double* total_ms,
+                            double* bytes_per_launch);
+
 enum {
   HDG_Q_NT = 0, HDG_Q_NLAMBDA = 1, HDG_Q_NLEVELS = 2, HDG_Q_NV = 3, HDG_Q_NQ = 4,
   HDG_Q_LEVEL_NLAMBDA = 100, /* + level */

@@ -152,6 +152,25 @@ class Level:
         self.kind = None
         self.Dinv = None
 
+    def face_block_inverses(self):
+        """Inverses of the assembled diagonal blocks D_e, one per face (Sec. 4.1)."""
+        if self.faces.size:
+            r = np.repeat(self.faces[:, :, None], self.m, axis=2)
+            c = np.repeat(self.faces[:, None, :], self.m, axis=1)
+            D = np.asarray(self.A[r.ravel(), c.ravel()]).reshape(r.shape)
+            self.Dinv = np.linalg.inv(D)
+        return self
+
+
+def block_jacobi(L, res, m, omega=1.0):
+    """m face-block Jacobi sweeps on L.A delta = res from delta = 0."""
+    delta = np.zeros_like(res)
+    for _ in range(m):
+        t = res - L.A @ delta
+        delta = delta.copy()
+        delta[L.faces] += omega * np.einsum("fab,fb->fa", L.Dinv, t[L.faces])
+    return delta
+
 
 class Hierarchy:
     """Levels ordered from finest (index 0) to coarsest."""
@@ -199,23 +218,12 @@ class Hierarchy:
         self.coarse_lu = sla.lu_factor(self.levels[-1].A.toarray()) if self.levels[-1].A.shape[0] else None
         for i, L in enumerate(self.levels):
             L.sweeps = sweeps * (2 ** i if growth == 2 else 1)
-            if L.faces.size:
-                A = L.A
-                r = np.repeat(L.faces[:, :, None], L.m, axis=2)
-                c = np.repeat(L.faces[:, None, :], L.m, axis=1)
-                D = np.asarray(A[r.ravel(), c.ravel()]).reshape(r.shape)
-                L.Dinv = np.linalg.inv(D)
+            L.face_block_inverses()
 
     # ---- smoothing, local correction, cycle --------------------------------
     def block_jacobi(self, i, res, m):
         """m face-block Jacobi sweeps on A_i delta = res from delta = 0."""
-        L = self.levels[i]
-        delta = np.zeros_like(res)
-        for _ in range(m):
-            t = res - L.A @ delta
-            delta = delta.copy()
-            delta[L.faces] += self.omega * np.einsum("fab,fb->fa", L.Dinv, t[L.faces])
-        return delta
+        return block_jacobi(self.levels[i], res, m, self.omega)
 
     def local_correction(self, i, rho):
         """T_i rho = [A_II^-1 rho_I ; 0] (eq. localCorrection)."""

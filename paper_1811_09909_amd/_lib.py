@@ -19,6 +19,7 @@ EXPORTS = [
     "hdg_default_opts", "hdg_setup", "hdg_update_kappa", "hdg_mg_build", "hdg_vcycle", "hdg_rhs", "hdg_solve",
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
+    "hdg_profile_begin", "hdg_profile_read",
 ]
 
 
@@ -69,6 +70,8 @@ def load():
         "hdg_query": (I, [P, I, ctypes.POINTER(ctypes.c_longlong)]),
         "hdg_reference_nodes": (I, [I, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "hdg_destroy": (I, [P]),
+        "hdg_profile_begin": (I, [P]),
+        "hdg_profile_read": (I, [P, I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D), ctypes.POINTER(D)]),
         "hdg_status_string": (ctypes.c_char_p, [I]),
     }
     for name, (res, args) in sig.items():

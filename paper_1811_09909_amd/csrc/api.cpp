@@ -34,6 +34,16 @@ struct hdg_problem {
   // GMRES
   double *V = nullptr, *Z = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gsv = nullptr, *y = nullptr;
   int gm_m = 0;
+  // inspection timing of finest-level trace kernels
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<void*> allocs;        // freed in destroy
   std::vector<void*> build_allocs;  // freed on rebuild
   long long bytes = 0;
@@ -112,6 +122,48 @@ void free_build(hdg_problem* P) {
   P->gm_m = 0;
 }
 
+hipEvent_t take_event(hdg_problem* P) {
+  if (!P->ev_pool.empty()) {
+    hipEvent_t e = P->ev_pool.back();
+    P->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HDG_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+// Sum the durations of completed event pairs (called right after a stream
+// synchronisation, so every recorded pair is complete).
+void harvest(hdg_problem* P) {
+  for (auto& pd : P->pending) {
+    float ms = 0.f;
+    HDG_CHECK(hipEventElapsedTime(&ms, pd.a, pd.b));
+    P->prof_ms[pd.cls] += ms;
+    P->prof_n[pd.cls] += 1;
+    P->ev_pool.push_back(pd.a);
+    P->ev_pool.push_back(pd.b);
+  }
+  P->pending.clear();
+}
+
+// trace apply on level i; finest-level launches are timed when profiling
+template <typename T>
+void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc) {
+  const bool timed = P->prof_on && i == 0;
+  hdg_problem::Pending pd{2 * mode + (sizeof(T) == 8 ? 0 : 1), nullptr, nullptr};
+  if (timed) {
+    pd.a = take_event(P);
+    pd.b = take_event(P);
+    HDG_CHECK(hipEventRecord(pd.a, P->st));
+  }
+  launch_apply<T>(P->L[i], mode, x, b, y, P->rd.Jp, rc, P->st);
+  if (timed) {
+    HDG_CHECK(hipEventRecord(pd.b, P->st));
+    P->pending.push_back(pd);
+  }
+}
+
 // -------------------------------------------------------------------------
 // Algorithm 1 on level i; returns the device pointer holding e = B_i r.
 // If `out` is given the result is written there.
@@ -135,15 +187,15 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
   else
     blas_fill<T>(e, T(0), L.nlam, st);
   for (int s = 1; s < m; ++s) {
-    launch_apply<T>(L, APPLY_SWEEP, e, r, w, nullptr, nullptr, st);
+    apply<T>(P, i, APPLY_SWEEP, e, r, w, nullptr);
     std::swap(e, w);
   }
   Level& C = P->L[i + 1];
   T* rc = (T*)C.r[pr];
   if (L.kind == 0) {
-    launch_apply<T>(L, APPLY_RES_PRESTRICT, e, r, nullptr, P->rd.Jp, rc, st);
+    apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc);
   } else {
-    launch_apply<T>(L, APPLY_RES, e, r, w, nullptr, nullptr, st);
+    apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
     launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st);
     launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st);
   }
@@ -153,17 +205,17 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
   else
     launch_hprolong<T>(L, C, ec, e, st);
   if (L.kind == 1 && (lc & HDG_LC_POST)) {
-    launch_apply<T>(L, APPLY_RES, e, r, w, nullptr, nullptr, st);
+    apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
     launch_hcorr<T>(L, w, e, 1, 0, nullptr, st);
   }
   for (int s = 0; s < m; ++s) {
     T* dst = (out && s == m - 1) ? out : w;
-    launch_apply<T>(L, APPLY_SWEEP, e, r, dst, nullptr, nullptr, st);
+    apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr);
     if (dst == w) std::swap(e, w);
     else e = dst;
   }
   if (out && e != out) {
-    HDG_CHECK(hipMemcpyAsync(out, e, sizeof(T) * L.nlam, hipMemcpyDeviceToDevice, st));
+    blas_copy_t<T>(out, e, L.nlam, st);
     e = out;
   }
   return e;
@@ -185,11 +237,12 @@ void precond(hdg_problem* P, const double* r, double* z, bool mixed) {
 double read_scalar(hdg_problem* P, const double* dptr) {
   HDG_CHECK(hipMemcpyAsync(P->hpin, dptr, sizeof(double), hipMemcpyDeviceToHost, P->st));
   HDG_CHECK(hipStreamSynchronize(P->st));
+  if (!P->pending.empty()) harvest(P);
   return P->hpin[0];
 }
 
 void residual(hdg_problem* P, const double* lam, const double* g, double* r) {
-  launch_apply<double>(P->L[0], APPLY_RES, lam, g, r, nullptr, nullptr, P->st);
+  apply<double>(P, 0, APPLY_RES, lam, g, r, nullptr);
 }
 
 struct SolveOut {
@@ -236,7 +289,7 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, dou
     blas_dot(P->r, P->z, N, P->s, FIN_RZ0, nullptr, st);
     blas_copy(P->p, P->z, N, st);
     while (o.iters < P->opts.max_it) {
-      launch_apply<double>(P->L[0], APPLY_Y, P->p, nullptr, P->Ap, nullptr, nullptr, st);
+      apply<double>(P, 0, APPLY_Y, P->p, nullptr, P->Ap, nullptr);
       blas_dot(P->p, P->Ap, N, P->s, FIN_ALPHA, nullptr, st);
       blas_cg_update(lam, P->r, P->p, P->Ap, N, P->s, st);
       ++o.iters;
@@ -287,7 +340,7 @@ SolveOut solve_gmres(hdg_problem* P, const double* g, double* lam, double tol, d
       double* zj = P->Z + j * ld;
       double* w = P->V + (j + 1) * ld;
       precond(P, vj, zj, mixed);
-      launch_apply<double>(P->L[0], APPLY_Y, zj, nullptr, w, nullptr, nullptr, st);
+      apply<double>(P, 0, APPLY_Y, zj, nullptr, w, nullptr);
       double* hcol = P->H + (long)j * (m + 1);
       for (int i = 0; i <= j; ++i) {
         blas_dot(w, P->V + i * ld, N, P->s, FIN_STORE, hcol + i, st);
@@ -646,7 +699,7 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
   if (!P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
-  launch_reconstruct(P->d, P->k, P->n, P->rd, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
+  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
                      P->Minv, P->ework, u, q, P->st);
   return HDG_OK;
   HDG_GUARD_END
@@ -670,7 +723,7 @@ hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, do
   form_rhs(P, dJdu, HDG_RHS_F_LOAD, nullptr, P->g);
   blas_fill<double>(P->lam, 0.0, P->N, P->st);
   hdg_status s = solve_one(P, P->g, P->lam, tol, info);
-  launch_reconstruct(P->d, P->k, P->n, P->rd, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
+  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
                      P->ustar, P->qstar, P->st);
   launch_grad(P->d, P->k, P->nelem, P->rd, P->kqp, q_fwd, P->qstar, grad, P->st);
   HDG_CHECK(hipStreamSynchronize(P->st));
@@ -750,6 +803,43 @@ hdg_status hdg_level_export(hdg_handle P, int level, double* out) {
   HDG_GUARD_END
 }
 
+hdg_status hdg_profile_begin(hdg_handle P) {
+  if (!P) return HDG_ERR_INVALID_ARG;
+  HDG_GUARD_BEGIN
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  harvest(P);
+  for (int i = 0; i < 8; ++i) {
+    P->prof_ms[i] = 0.0;
+    P->prof_n[i] = 0;
+  }
+  P->prof_on = true;
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, double* total_ms,
+                            double* bytes_per_launch) {
+  if (!P || kernel < 0 || kernel > 7) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  HDG_GUARD_BEGIN
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  harvest(P);
+  const Level& L = P->L[0];
+  const int mode = kernel / 2;
+  const double s = (kernel % 2) ? 4.0 : 8.0;
+  const double N = (double)L.nlam;
+  double bytes = (double)L.nface * 2.0 * L.ne * L.nl * s;
+  if (mode == APPLY_Y) bytes += 2.0 * N * s;
+  if (mode == APPLY_RES) bytes += 3.0 * N * s;
+  if (mode == APPLY_SWEEP) bytes += (double)L.nface * L.ne * L.ne * s + 3.0 * N * s;
+  if (mode == APPLY_RES_PRESTRICT) bytes += 2.0 * N * s + (double)L.nface * (1 << (L.d - 1)) * s;
+  if (launches) *launches = P->prof_n[kernel];
+  if (total_ms) *total_ms = P->prof_ms[kernel];
+  if (bytes_per_launch) *bytes_per_launch = bytes;
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
 hdg_status hdg_query(hdg_handle P, int what, long long* out) {
   if (!P || !out) return HDG_ERR_INVALID_ARG;
   const int nL = (int)P->L.size();
@@ -790,6 +880,11 @@ hdg_status hdg_destroy(hdg_handle P) {
   (void)hipStreamSynchronize(P->st);
   for (void* ptr : P->build_allocs) (void)hipFree(ptr);
   for (void* ptr : P->allocs) (void)hipFree(ptr);
+  for (auto& pd : P->pending) {
+    (void)hipEventDestroy(pd.a);
+    (void)hipEventDestroy(pd.b);
+  }
+  for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   if (P->hbad) (void)hipHostFree(P->hbad);
   if (P->hpin) (void)hipHostFree(P->hpin);
   delete P;

@@ -290,6 +290,20 @@ void blas_f2d(const float* x, double* y, long n, hipStream_t st) {
   HDG_CHECK(hipGetLastError());
 }
 
+template <typename T>
+__global__ void copy_t_kernel(T* __restrict__ y, const T* __restrict__ x, long n) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = x[i];
+}
+
+template <typename T>
+void blas_copy_t(T* y, const T* x, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((copy_t_kernel<T>), dim3(gs(n)), dim3(256), 0, st, y, x, n);
+  HDG_CHECK(hipGetLastError());
+}
+template void blas_copy_t<double>(double*, const double*, long, hipStream_t);
+template void blas_copy_t<float>(float*, const float*, long, hipStream_t);
+
 void blas_copy(double* y, const double* x, long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(copy_kernel, dim3(gs(n)), dim3(256), 0, st, y, x, n);

@@ -27,6 +27,8 @@ void blas_d2f(const double* x, float* y, long n, hipStream_t st);
 void blas_f2d(const float* x, double* y, long n, hipStream_t st);
 void blas_copy(double* y, const double* x, long n, hipStream_t st);
 template <typename T>
+void blas_copy_t(T* y, const T* x, long n, hipStream_t st);
+template <typename T>
 void blas_fill(T* y, T v, long n, hipStream_t st);
 void blas_gmres_rot(double* H, double* cs, double* sn, double* s, int j, int ld, double* sc, hipStream_t st);
 void blas_gmres_backsolve(const double* H, const double* s, int j, int ld, double* y, hipStream_t st);

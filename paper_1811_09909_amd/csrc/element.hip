@@ -281,10 +281,18 @@ __global__ void load_pull_kernel(int n, const double* __restrict__ ebuf, const d
   g[t] = s;
 }
 
-// Local recovery, one workgroup per element.
+// Local recovery, one workgroup per element.  U = W Lambda + K^-1 b from the
+// stored explicit inverses, Q_c = Mk^-1 (B_c^T U - F_c Lambda), then one step
+// of refinement on the second local equation: the residual
+// rho = tau G Lambda + b - sum_c B_c Q_c - tau E U (reference matrices only)
+// gives U += K^-1 rho.  Without it the error that the explicit K^-1 leaves in
+// U is amplified by the cancellation in B^T U - F Lambda on elements with
+// large kappa (where u is nearly constant).
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, const double* __restrict__ Bm,
+__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, const double* __restrict__ Bm,
                                                          const double* __restrict__ Fm,
+                                                         const double* __restrict__ Gm,
+                                                         const double* __restrict__ Em,
                                                          const double* __restrict__ lam,
                                                          const double* __restrict__ gdir,
                                                          const double* __restrict__ b,
@@ -294,7 +302,7 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, const double* __
                                                          double* __restrict__ q) {
   using Dm = Dims<D, K>;
   constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL;
-  __shared__ double sL[NL], sU[NV], sT[NV];
+  __shared__ double sL[NL], sU[NV], sT[NV], sQ[D * NV], sR[NV];
   const long T = blockIdx.x;
   const int tid = threadIdx.x;
   int e[3] = {0, 0, 0};
@@ -320,25 +328,46 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, const double* __
     for (int j = 0; j < NL; ++j) s += W[(T * NV + i) * NL + j] * sL[j];
     for (int j = 0; j < NV; ++j) s += Kinv[(T * NV + i) * NV + j] * b[T * NV + j];
     sU[i] = s;
-    u[T * NV + i] = s;
   }
-  __syncthreads();
-  for (int c = 0; c < D; ++c) {
-    // t = B_c^T U - F_c Lambda ; Q_c = Mk^-1 t
+  for (int pass = 0; pass < 2; ++pass) {
+    __syncthreads();
+    for (int c = 0; c < D; ++c) {
+      // t = B_c^T U - F_c Lambda ; Q_c = Mk^-1 t
+      for (int i = tid; i < NV; i += NT) {
+        double s = 0.0;
+        for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
+        for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
+        sT[i] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < NV; i += NT) {
+        double s = 0.0;
+        for (int j = 0; j < NV; ++j) s += Minv[(T * NV + i) * NV + j] * sT[j];
+        sQ[c * NV + i] = s;
+      }
+      __syncthreads();
+    }
+    if (pass == 1) break;
+    // rho = tau G Lambda + b - sum_c B_c Q_c - tau E U ; U += K^-1 rho
+    for (int i = tid; i < NV; i += NT) {
+      double s = b[T * NV + i];
+      for (int j = 0; j < NL; ++j) s += tau * Gm[i * NL + j] * sL[j];
+      for (int j = 0; j < NV; ++j) s -= tau * Em[i * NV + j] * sU[j];
+      for (int c = 0; c < D; ++c)
+        for (int j = 0; j < NV; ++j) s -= Bm[(c * NV + i) * NV + j] * sQ[c * NV + j];
+      sR[i] = s;
+    }
+    __syncthreads();
     for (int i = tid; i < NV; i += NT) {
       double s = 0.0;
-      for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
-      for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
+      for (int j = 0; j < NV; ++j) s += Kinv[(T * NV + i) * NV + j] * sR[j];
       sT[i] = s;
     }
     __syncthreads();
-    for (int i = tid; i < NV; i += NT) {
-      double s = 0.0;
-      for (int j = 0; j < NV; ++j) s += Minv[(T * NV + i) * NV + j] * sT[j];
-      q[(T * D + c) * NV + i] = s;
-    }
-    __syncthreads();
+    for (int i = tid; i < NV; i += NT) sU[i] += sT[i];
   }
+  for (int i = tid; i < NV; i += NT) u[T * NV + i] = sU[i];
+  for (int i = tid; i < D * NV; i += NT) q[T * D * NV + i] = sQ[i];
 }
 
 // dJ/dlog kappa_T = -sum_c (q*_c)^T Mk q_c, evaluated at the Gauss points.
@@ -448,9 +477,9 @@ void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Ael
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_reconstruct(int d, int k, int n, const RefDevice& rd, const double* lam, const double* gdir,
-                        const double* f, int is_load, const double* W, const double* Kinv, const double* Minv,
-                        double* b, double* u, double* q, hipStream_t st) {
+void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* lam,
+                        const double* gdir, const double* f, int is_load, const double* W, const double* Kinv,
+                        const double* Minv, double* b, double* u, double* q, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
     using Dm = Dims<D, K>;
@@ -460,8 +489,8 @@ void launch_reconstruct(int d, int k, int n, const RefDevice& rd, const double* 
     hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
                        rd.M, f, is_load, b);
     constexpr int NT = 64;
-    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, rd.B, rd.F,
-                       lam, gdir, b, W, Kinv, Minv, u, q);
+    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, tau, rd.B, rd.F,
+                       rd.G, rd.E, lam, gdir, b, W, Kinv, Minv, u, q);
   });
   HDG_CHECK(hipGetLastError());
 }

@@ -158,6 +158,18 @@ class Problem:
         L.check(self.lib.hdg_level_export(self.h, level, _vp(out)), "hdg_level_export")
         return out
 
+    # -- inspection timing ---------------------------------------------------
+    def profile_begin(self):
+        L.check(self.lib.hdg_profile_begin(self.h), "hdg_profile_begin")
+
+    def profile_read(self, mode, precision):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        L.check(self.lib.hdg_profile_read(self.h, 2 * mode + precision, ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(by)), "hdg_profile_read")
+        return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}
+
     # -- geometry for evaluating sources and coefficients --------------------
     def reference_nodes(self):
         gll = (ctypes.c_double * (self.k + 1))()

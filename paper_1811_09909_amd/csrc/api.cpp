@@ -3,6 +3,7 @@
 // driving the HIP kernels of element.hip, build.hip, trace.hip, blas.hip.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -14,7 +15,10 @@ using namespace hdg;
 struct hdg_problem {
   int d = 0, n = 0, k = 0;
   double tau = 1.0;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;      // caller's stream: all work is ordered on it
+  hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
+  bool use_graphs = true;
+  hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   RefElement ref;
   RefDevice rd;
   long nelem = 0;
@@ -28,6 +32,7 @@ struct hdg_problem {
   std::vector<Level> L;
   long N = 0;  // trace DOFs of the finest level
   double *g = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *Ap = nullptr, *zold = nullptr, *lam = nullptr;
+  float *r32 = nullptr, *z32 = nullptr;
   double *ustar = nullptr, *qstar = nullptr;
   Scratch s;
   double* hpin = nullptr;
@@ -112,8 +117,17 @@ void form_elements(hdg_problem* P) {
   launch_element_dtn(P->d, P->k, P->nelem, P->tau, P->rd, P->kqp, P->Ae, P->W, P->Kinv, P->Minv, P->st);
 }
 
+void drop_graphs(hdg_problem* P) {
+  for (auto& g : P->gx)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 void free_build(hdg_problem* P) {
   HDG_CHECK(hipStreamSynchronize(P->st));
+  drop_graphs(P);
   for (void* ptr : P->build_allocs) HDG_CHECK(hipFree(ptr));
   P->build_allocs.clear();
   P->L.clear();
@@ -163,6 +177,47 @@ void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc)
     P->pending.push_back(pd);
   }
 }
+
+// Run `body` (device work only, fixed pointers) as a captured hipGraph on the
+// caller's stream; captured once per slot on the private stream.  Eager when
+// graphs are disabled or finest-level kernels are being timed.
+template <class F>
+void run_graph(hdg_problem* P, int slot, F&& body) {
+  if (!P->use_graphs || P->prof_on) {
+    body();
+    return;
+  }
+  if (!P->gx[slot]) {
+    hipStream_t user = P->st;
+    P->st = P->cap_st;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(P->cap_st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      P->st = user;
+      throw HipError{e, "hipStreamBeginCapture"};
+    }
+    try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(P->cap_st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      P->st = user;
+      throw;
+    }
+    e = hipStreamEndCapture(P->cap_st, &g);
+    P->st = user;
+    if (e != hipSuccess) throw HipError{e, "hipStreamEndCapture"};
+    e = hipGraphInstantiate(&P->gx[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      P->gx[slot] = nullptr;
+      throw HipError{e, "hipGraphInstantiate"};
+    }
+  }
+  HDG_CHECK(hipGraphLaunch(P->gx[slot], P->st));
+}
+
+enum { G_PCG64 = 0, G_PCGMX = 1, G_MG64 = 2, G_MGMX = 3, G_PRE64 = 4, G_PREMX = 5 };
 
 // -------------------------------------------------------------------------
 // Algorithm 1 on level i; returns the device pointer holding e = B_i r.
@@ -251,17 +306,45 @@ struct SolveOut {
   hdg_status status = HDG_OK;
 };
 
+// r = g - A lam and ||r||^2 in one pass (plus the FP32 copy of r when mixed)
+void residual_norm(hdg_problem* P, const double* lam, const double* g, bool mixed) {
+  float* r32 = mixed ? P->r32 : nullptr;
+  const bool timed = P->prof_on;
+  hdg_problem::Pending pd{2 * APPLY_RES + 0, nullptr, nullptr};
+  if (timed) {
+    pd.a = take_event(P);
+    pd.b = take_event(P);
+    HDG_CHECK(hipEventRecord(pd.a, P->st));
+  }
+  launch_apply_red<double>(P->L[0], APPLY_RES_NORM, lam, g, P->r, nullptr, nullptr, r32, &P->s, P->st);
+  if (timed) {
+    HDG_CHECK(hipEventRecord(pd.b, P->st));
+    P->pending.push_back(pd);
+  }
+}
+
+// z = B r: FP64 V-cycle on r, or FP32 V-cycle on the FP32 copy r32 into z32
+void precond_fused(hdg_problem* P, bool mixed) {
+  if (mixed)
+    vcycle<float>(P, 0, P->r32, P->z32);
+  else
+    vcycle<double>(P, 0, P->r, P->z);
+}
+
 SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
   SolveOut o;
   const long N = P->N;
-  residual(P, lam, g, P->r);
-  blas_dot(P->r, P->r, N, P->s, FIN_STORE, P->s.sc + SC_RNORM2, P->st);
+  residual_norm(P, lam, g, mixed);
   double rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
   while (rel > tol && o.iters < P->opts.max_it && std::isfinite(rel)) {
-    precond(P, P->r, P->z, mixed);
-    blas_axpy(lam, P->z, N, nullptr, 1.0, P->st);
-    residual(P, lam, g, P->r);
-    blas_dot(P->r, P->r, N, P->s, FIN_STORE, P->s.sc + SC_RNORM2, P->st);
+    run_graph(P, mixed ? G_MGMX : G_MG64, [&] {
+      precond_fused(P, mixed);
+      if (mixed)
+        blas_add<float>(lam, P->z32, N, P->st);
+      else
+        blas_add<double>(lam, P->z, N, P->st);
+      residual_norm(P, lam, g, mixed);
+    });
     rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
     ++o.iters;
   }
@@ -270,14 +353,15 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, doub
   return o;
 }
 
+// Preconditioned CG.  FP64: Fletcher-Reeves beta.  Mixed (FP32 V-cycle, not
+// exactly symmetric): flexible Polak-Ribiere beta = (r.z - r.z_old) / rz_old.
+// r.z_old is accumulated in the update pass, while z still holds z_old.
 SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
   SolveOut o;
   const long N = P->N;
-  hipStream_t st = P->st;
   double* sc = P->s.sc;
   for (;;) {
-    residual(P, lam, g, P->r);
-    blas_dot(P->r, P->r, N, P->s, FIN_STORE, sc + SC_RNORM2, st);
+    residual_norm(P, lam, g, mixed);
     double rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
     o.relres = rel;
     if (!std::isfinite(rel)) {
@@ -285,23 +369,48 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, dou
       return o;
     }
     if (rel <= tol || o.iters >= P->opts.max_it) break;
-    precond(P, P->r, P->z, mixed);
-    blas_dot(P->r, P->z, N, P->s, FIN_RZ0, nullptr, st);
-    blas_copy(P->p, P->z, N, st);
+    precond_fused(P, mixed);
+    if (mixed) {
+      blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st);
+      blas_f2d(P->z32, P->p, N, P->st);
+    } else {
+      blas_rz<double>(P->r, P->z, N, FIN_RZ0, P->s, P->st);
+      blas_copy(P->p, P->z, N, P->st);
+    }
+    // one CG iteration per graph launch: lambda and r are updated first, so
+    // after convergence the trailing preconditioner application and
+    // direction update change nothing that is returned
     while (o.iters < P->opts.max_it) {
-      apply<double>(P, 0, APPLY_Y, P->p, nullptr, P->Ap, nullptr);
-      blas_dot(P->p, P->Ap, N, P->s, FIN_ALPHA, nullptr, st);
-      blas_cg_update(lam, P->r, P->p, P->Ap, N, P->s, st);
+      run_graph(P, mixed ? G_PCGMX : G_PCG64, [&] {
+        hipStream_t s2 = P->st;
+        const bool timed = P->prof_on;
+        hdg_problem::Pending pd{2 * APPLY_Y + 0, nullptr, nullptr};
+        if (timed) {
+          pd.a = take_event(P);
+          pd.b = take_event(P);
+          HDG_CHECK(hipEventRecord(pd.a, s2));
+        }
+        launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s, s2);
+        if (timed) {
+          HDG_CHECK(hipEventRecord(pd.b, s2));
+          P->pending.push_back(pd);
+        }
+        if (mixed)
+          blas_cg_update2<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, P->s, s2);
+        else
+          blas_cg_update2<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, P->s, s2);
+        precond_fused(P, mixed);
+        if (mixed) {
+          blas_rz<float>(P->r, P->z32, N, FIN_BETA_FLEX, P->s, s2);
+          blas_cg_dir<float>(P->p, P->z32, N, P->s, s2);
+        } else {
+          blas_rz<double>(P->r, P->z, N, FIN_BETA, P->s, s2);
+          blas_cg_dir<double>(P->p, P->z, N, P->s, s2);
+        }
+      });
       ++o.iters;
       rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
       if (rel <= tol || !std::isfinite(rel)) break;
-      if (mixed) blas_copy(P->zold, P->z, N, st);
-      precond(P, P->r, P->z, mixed);
-      if (mixed)
-        blas_dot2_flex(P->r, P->z, P->zold, N, P->s, st);
-      else
-        blas_dot(P->r, P->z, N, P->s, FIN_BETA, nullptr, st);
-      blas_cg_direction(P->p, P->z, N, P->s, st);
     }
     if (!std::isfinite(rel)) {
       o.relres = rel;
@@ -339,7 +448,9 @@ SolveOut solve_gmres(hdg_problem* P, const double* g, double* lam, double tol, d
       double* vj = P->V + j * ld;
       double* zj = P->Z + j * ld;
       double* w = P->V + (j + 1) * ld;
-      precond(P, vj, zj, mixed);
+      blas_copy(P->r, vj, N, st);
+      run_graph(P, mixed ? G_PREMX : G_PRE64, [&] { precond(P, P->r, P->z, mixed); });
+      blas_copy(zj, P->z, N, st);
       apply<double>(P, 0, APPLY_Y, zj, nullptr, w, nullptr);
       double* hcol = P->H + (long)j * (m + 1);
       for (int i = 0; i <= j; ++i) {
@@ -388,12 +499,16 @@ hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, h
     return HDG_OK;
   }
   const bool mixed = P->opts.precision == HDG_MIXED;
+  // iterate in the handle's own buffers so captured graphs see fixed pointers
+  if (g != P->g) blas_copy(P->g, g, N, P->st);
+  if (lam != P->lam) blas_copy(P->lam, lam, N, P->st);
   SolveOut o;
   switch (P->opts.method) {
-    case HDG_METHOD_PCG: o = solve_pcg(P, g, lam, tol, gn, mixed); break;
-    case HDG_METHOD_GMRES: o = solve_gmres(P, g, lam, tol, gn, mixed); break;
-    default: o = solve_mg(P, g, lam, tol, gn, mixed); break;
+    case HDG_METHOD_PCG: o = solve_pcg(P, P->g, P->lam, tol, gn, mixed); break;
+    case HDG_METHOD_GMRES: o = solve_gmres(P, P->g, P->lam, tol, gn, mixed); break;
+    default: o = solve_mg(P, P->g, P->lam, tol, gn, mixed); break;
   }
+  if (lam != P->lam) blas_copy(lam, P->lam, N, P->st);
   if (info) {
     info->iters += o.iters;
     info->relres = std::max(info->relres, o.relres);
@@ -459,6 +574,8 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->tau = tau;
   P->st = (hipStream_t)hip_stream;
   P->store_recovery = store_recovery != 0;
+  P->use_graphs = std::getenv("HDG_NO_GRAPH") == nullptr;
+  HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
   P->nv = P->ref.nv;
   P->ne = P->ref.ne;
@@ -486,9 +603,12 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   HDG_CHECK(hipHostMalloc((void**)&P->hbad, sizeof(int) * 4, hipHostMallocDefault));
   HDG_CHECK(hipHostMalloc((void**)&P->hpin, sizeof(double) * 16, hipHostMallocDefault));
   P->s.sc = dalloc<double>(P, SC_COUNT, false);
-  P->s.partials = dalloc<double>(P, 2 * 512, false);
-  P->s.counter = dalloc<unsigned>(P, 1, false);
-  HDG_CHECK(hipMemsetAsync(P->s.counter, 0, sizeof(unsigned), P->st));
+  {
+    // partial sums of the reductions: one per block of the widest launch
+    const long nface0 = (long)P->d * (P->n - 1) * ipow(P->n, P->d - 1);
+    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 1);
+    P->s.partials = dalloc<double>(P, 2 * nb, false);
+  }
   HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT, P->st));
   if (!check_kappa(P, kappa, kappa_kind)) {
     hdg_destroy(P);
@@ -611,6 +731,8 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   P->Ap = dalloc<double>(P, N, true);
   P->zold = dalloc<double>(P, N, true);
   P->lam = dalloc<double>(P, N, true);
+  P->r32 = dalloc<float>(P, N, true);
+  P->z32 = dalloc<float>(P, N, true);
   if (o.method == HDG_METHOD_GMRES) {
     const int m = o.restart > 0 ? std::min(o.restart, std::max(o.max_it, 1)) : std::max(o.max_it, 1);
     P->gm_m = m;
@@ -878,6 +1000,8 @@ hdg_status hdg_query(hdg_handle P, int what, long long* out) {
 hdg_status hdg_destroy(hdg_handle P) {
   if (!P) return HDG_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(P->st);
+  drop_graphs(P);
+  if (P->cap_st) (void)hipStreamDestroy(P->cap_st);
   for (void* ptr : P->build_allocs) (void)hipFree(ptr);
   for (void* ptr : P->allocs) (void)hipFree(ptr);
   for (auto& pd : P->pending) {

@@ -1,150 +1,145 @@
 // Vector kernels of the outer iterations (fixed point, CG, GMRES; Sec. 3.6
-// and Sec. 4): dot products with a deterministic two-level reduction
-// (wavefront shuffles, one partial per block, the last block to finish sums
-// the partials in block order), fused CG updates whose scalars never leave
-// the device, precision conversions, and the small GMRES Hessenberg work.
-#include "hdg_internal.hpp"
+// and Sec. 4).
+//
+// Reductions: every block writes one partial sum (wavefront shuffles, then
+// LDS) with plain stores, and a one-block finaliser launched next sums the
+// partials in block order and updates the device scalars.  The grid depends
+// only on the vector length, so sums are reproducible.  No device-scope
+// fences or atomics: on MI355X the eight XCDs' L2 caches are not coherent
+// with each other, so a per-block release fence costs an L2 write-back and a
+// per-block atomic on one counter serialises; the kernel boundary is the
+// cheap synchronisation point.
 #include "blas.hpp"
+#include "hdg_internal.hpp"
+#include "reduce.hpp"
 
 namespace hdg {
 
 namespace {
 
-constexpr int RB = 256;     // reduction block size
-constexpr int RG = 512;     // reduction grid (fixed -> reproducible sums)
+constexpr int RB = 256;  // reduction block size
+constexpr int RPT = 4;   // elements per thread per pass (independent loads in flight)
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
+__device__ inline double block_sum(double v, double* sh) { return block_sum_t<RB>(v, sh); }
 
-__device__ inline double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < RB / 64; ++w) s += sh[w];
-  return s;
-}
-
-// Sum partials in block order in the last block; apply the finaliser.
-__device__ inline bool last_block(unsigned* counter) {
-  __shared__ bool last;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  return last;
-}
-
-__device__ inline double sum_partials(const double* partials, int np, double* sh) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += RB)
-    v += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // fixed order: each thread sums a fixed strided subset, then the block tree
-  return block_sum(v, sh);
-}
-
-// out_slots: dot(x, y) finalised according to mode
 __global__ void __launch_bounds__(RB) dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                                 long n, double* __restrict__ partials, unsigned* counter,
-                                                 double* sc, int mode, double* out) {
+                                                 long n, double* __restrict__ partials) {
   __shared__ double sh[RB / 64];
   double v = 0.0;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) v += x[i] * y[i];
-  double s = block_sum(v, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (!last_block(counter)) return;
-  __syncthreads();
-  double tot = sum_partials(partials, gridDim.x, sh);
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    switch (mode) {
-      case FIN_STORE: *out = tot; break;
-      case FIN_ALPHA:  // alpha = rz / pAp
-        sc[SC_PAP] = tot;
-        sc[SC_ALPHA] = sc[SC_RZ] / tot;
-        break;
-      case FIN_BETA:   // beta = rz_new / rz ; rz = rz_new
-        sc[SC_BETA] = tot / sc[SC_RZ];
-        sc[SC_RZ] = tot;
-        break;
-      case FIN_RZ0: sc[SC_RZ] = tot; break;
-      case FIN_NORM_INV:  // out <- ||x||, SC_TMP <- 1/||x||
-        *out = sqrt(tot);
-        sc[SC_TMP] = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
-        break;
+  for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const long i = base + u * RB + threadIdx.x;
+      if (i < n) v += x[i] * y[i];
     }
   }
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// flexible CG direction scalar: beta = (rz_new - r.z_old) / rz ; rz = rz_new
-__global__ void __launch_bounds__(RB) dot2_kernel(const double* __restrict__ r, const double* __restrict__ z,
-                                                  const double* __restrict__ zold, long n,
-                                                  double* __restrict__ partials, unsigned* counter, double* sc) {
+// sum partials[nv * i + v] over i < nb (fixed order) and apply the finaliser
+__global__ void __launch_bounds__(RB) finalize_kernel(const double* __restrict__ partials, int nb, int nv, int mode,
+                                                      double* sc, double* out) {
   __shared__ double sh[RB / 64];
-  double a = 0.0, b = 0.0;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    a += r[i] * z[i];
-    b += r[i] * zold[i];
+  double tot[2] = {0.0, 0.0};
+  for (int v = 0; v < nv; ++v) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += RB) a += partials[(long)nv * i + v];
+    tot[v] = block_sum(a, sh);
+    __syncthreads();
   }
-  double sa = block_sum(a, sh);
+  if (threadIdx.x != 0) return;
+  const double t0 = tot[0], t1 = tot[1];
+  switch (mode) {
+    case FIN_STORE: *out = t0; break;
+    case FIN_ALPHA:
+      sc[SC_PAP] = t0;
+      sc[SC_ALPHA] = sc[SC_RZ] / t0;
+      break;
+    case FIN_BETA:
+      sc[SC_BETA] = t0 / sc[SC_RZ];
+      sc[SC_RZ] = t0;
+      break;
+    case FIN_BETA_FLEX:
+      sc[SC_BETA] = (t0 - sc[SC_RZOLD]) / sc[SC_RZ];
+      sc[SC_RZ] = t0;
+      break;
+    case FIN_RZ0: sc[SC_RZ] = t0; break;
+    case FIN_NORM_INV:
+      *out = sqrt(t0);
+      sc[SC_TMP] = t0 > 0.0 ? 1.0 / sqrt(t0) : 0.0;
+      break;
+    case FIN_RNORM: sc[SC_RNORM2] = t0; break;
+    case FIN_RNORM_RZOLD:
+      sc[SC_RNORM2] = t0;
+      sc[SC_RZOLD] = t1;
+      break;
+  }
+}
+
+// Fused CG update (one pass over the vectors):
+//   lam += alpha p ; r -= alpha Ap ; r32 = (float) r (mixed only)
+//   partial sums of r.r and r.z_old, where z still holds the previous
+//   preconditioned residual.
+template <typename ZT>
+__global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam, double* __restrict__ r,
+                                                        float* __restrict__ r32, const double* __restrict__ p,
+                                                        const double* __restrict__ Ap, const ZT* __restrict__ z,
+                                                        long n, double* __restrict__ partials, const double* sc) {
+  __shared__ double sh[RB / 64];
+  const double alpha = sc[SC_ALPHA];
+  double rr = 0.0, rz = 0.0;
+  for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const long i = base + u * RB + threadIdx.x;
+      if (i < n) {
+        lam[i] += alpha * p[i];
+        const double ri = r[i] - alpha * Ap[i];
+        r[i] = ri;
+        if (r32) r32[i] = (float)ri;
+        rr += ri * ri;
+        rz += ri * (double)z[i];
+      }
+    }
+  }
+  const double sa = block_sum(rr, sh);
   __syncthreads();
-  double sb = block_sum(b, sh);
+  const double sb = block_sum(rz, sh);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = sa;
     partials[2 * blockIdx.x + 1] = sb;
   }
-  if (!last_block(counter)) return;
-  __syncthreads();
-  double ta = 0.0, tb = 0.0;
-  if (threadIdx.x == 0)
-    for (unsigned i = 0; i < gridDim.x; ++i) {
-      ta += __hip_atomic_load(partials + 2 * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      tb += __hip_atomic_load(partials + 2 * i + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    sc[SC_BETA] = (ta - tb) / sc[SC_RZ];
-    sc[SC_RZ] = ta;
-  }
 }
 
-// lam += alpha p ; r -= alpha Ap ; rnorm2 = r.r
-__global__ void __launch_bounds__(RB) cg_update_kernel(double* __restrict__ lam, double* __restrict__ r,
-                                                       const double* __restrict__ p,
-                                                       const double* __restrict__ Ap, long n,
-                                                       double* __restrict__ partials, unsigned* counter,
-                                                       double* sc) {
+// partial sums of r.z (z FP64 or FP32)
+template <typename ZT>
+__global__ void __launch_bounds__(RB) rz_kernel(const double* __restrict__ r, const ZT* __restrict__ z, long n,
+                                                double* __restrict__ partials) {
   __shared__ double sh[RB / 64];
-  const double alpha = sc[SC_ALPHA];
   double v = 0.0;
-  for (long i = blockIdx.x * (long)RB + threadIdx.x; i < n; i += (long)gridDim.x * RB) {
-    lam[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Ap[i];
-    r[i] = ri;
-    v += ri * ri;
+  for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const long i = base + u * RB + threadIdx.x;
+      if (i < n) v += r[i] * (double)z[i];
+    }
   }
-  double s = block_sum(v, sh);
+  const double s = block_sum(v, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (!last_block(counter)) return;
-  __syncthreads();
-  double tot = sum_partials(partials, gridDim.x, sh);
-  if (threadIdx.x == 0) {
-    *counter = 0u;
-    sc[SC_RNORM2] = tot;
-  }
 }
 
 // p = z + beta p
-__global__ void cg_direction_kernel(double* __restrict__ p, const double* __restrict__ z, long n,
-                                    const double* sc) {
+template <typename ZT>
+__global__ void cg_dir_kernel(double* __restrict__ p, const ZT* __restrict__ z, long n, const double* sc) {
   const double beta = sc[SC_BETA];
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) p[i] = z[i] + beta * p[i];
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) p[i] = (double)z[i] + beta * p[i];
+}
+
+// lam += z (z FP64 or FP32)
+template <typename ZT>
+__global__ void add_kernel(double* __restrict__ lam, const ZT* __restrict__ z, long n) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) lam[i] += (double)z[i];
 }
 
 // y += sign * x, or y += sign * (*coef) * x when coef is given
@@ -170,7 +165,8 @@ __global__ void fill_kernel(T* __restrict__ y, T v, long n) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = v;
 }
 
-__global__ void copy_kernel(double* __restrict__ y, const double* __restrict__ x, long n) {
+template <typename T>
+__global__ void copy_t_kernel(T* __restrict__ y, const T* __restrict__ x, long n) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = x[i];
 }
 
@@ -219,18 +215,6 @@ __global__ void gmres_combine_kernel(double* __restrict__ x, const double* __res
   }
 }
 
-__global__ void set_scalar_kernel(double* sc, int slot, const double* src, int mode) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (mode == 0) sc[slot] = *src;
-    else sc[slot] = -(*src);
-  }
-}
-
-__global__ void finite_kernel(const double* __restrict__ x, long n, int* bad) {
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L)
-    if (!isfinite(x[i])) atomicOr(bad, 1);
-}
-
 inline unsigned gs(long n) {
   long b = (n + 255) / 256;
   if (b > 4096) b = 4096;
@@ -238,35 +222,66 @@ inline unsigned gs(long n) {
   return (unsigned)b;
 }
 
+// the grid depends only on n, so sums are reproducible run to run
 inline unsigned rg(long n) {
-  long b = (n + RB - 1) / RB;
-  if (b > RG) b = RG;
+  long b = (n + RB * RPT - 1) / (RB * RPT);
+  if (b > MAX_RED_BLOCKS) b = MAX_RED_BLOCKS;
   if (b < 1) b = 1;
   return (unsigned)b;
 }
 
 }  // namespace
 
+void blas_finalize(int nb, int nv, int mode, double* out, Scratch& s, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RB), 0, st, s.partials, nb, nv, mode, s.sc, out);
+  HDG_CHECK(hipGetLastError());
+}
+
 void blas_dot(const double* x, const double* y, long n, Scratch& s, int mode, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(dot_kernel, dim3(rg(n)), dim3(RB), 0, st, x, y, n, s.partials, s.counter, s.sc, mode, out);
+  const unsigned nb = rg(n);
+  hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(RB), 0, st, x, y, n, s.partials);
   HDG_CHECK(hipGetLastError());
+  blas_finalize((int)nb, 1, mode, out, s, st);
 }
 
-void blas_dot2_flex(const double* r, const double* z, const double* zold, long n, Scratch& s, hipStream_t st) {
-  hipLaunchKernelGGL(dot2_kernel, dim3(rg(n)), dim3(RB), 0, st, r, z, zold, n, s.partials, s.counter, s.sc);
+template <typename ZT>
+void blas_cg_update2(double* lam, double* r, float* r32, const double* p, const double* Ap, const ZT* z, long n,
+                     Scratch& s, hipStream_t st) {
+  const unsigned nb = rg(n);
+  hipLaunchKernelGGL((cg_update2_kernel<ZT>), dim3(nb), dim3(RB), 0, st, lam, r, r32, p, Ap, z, n, s.partials, s.sc);
   HDG_CHECK(hipGetLastError());
+  blas_finalize((int)nb, 2, FIN_RNORM_RZOLD, nullptr, s, st);
 }
+template void blas_cg_update2<double>(double*, double*, float*, const double*, const double*, const double*, long,
+                                      Scratch&, hipStream_t);
+template void blas_cg_update2<float>(double*, double*, float*, const double*, const double*, const float*, long,
+                                     Scratch&, hipStream_t);
 
-void blas_cg_update(double* lam, double* r, const double* p, const double* Ap, long n, Scratch& s,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(rg(n)), dim3(RB), 0, st, lam, r, p, Ap, n, s.partials, s.counter, s.sc);
+template <typename ZT>
+void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st) {
+  const unsigned nb = rg(n);
+  hipLaunchKernelGGL((rz_kernel<ZT>), dim3(nb), dim3(RB), 0, st, r, z, n, s.partials);
   HDG_CHECK(hipGetLastError());
+  blas_finalize((int)nb, 1, mode, nullptr, s, st);
 }
+template void blas_rz<double>(const double*, const double*, long, int, Scratch&, hipStream_t);
+template void blas_rz<float>(const double*, const float*, long, int, Scratch&, hipStream_t);
 
-void blas_cg_direction(double* p, const double* z, long n, Scratch& s, hipStream_t st) {
-  hipLaunchKernelGGL(cg_direction_kernel, dim3(gs(n)), dim3(256), 0, st, p, z, n, s.sc);
+template <typename ZT>
+void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st) {
+  hipLaunchKernelGGL((cg_dir_kernel<ZT>), dim3(gs(n)), dim3(256), 0, st, p, z, n, s.sc);
   HDG_CHECK(hipGetLastError());
 }
+template void blas_cg_dir<double>(double*, const double*, long, Scratch&, hipStream_t);
+template void blas_cg_dir<float>(double*, const float*, long, Scratch&, hipStream_t);
+
+template <typename ZT>
+void blas_add(double* lam, const ZT* z, long n, hipStream_t st) {
+  hipLaunchKernelGGL((add_kernel<ZT>), dim3(gs(n)), dim3(256), 0, st, lam, z, n);
+  HDG_CHECK(hipGetLastError());
+}
+template void blas_add<double>(double*, const double*, long, hipStream_t);
+template void blas_add<float>(double*, const float*, long, hipStream_t);
 
 void blas_axpy(double* y, const double* x, long n, const double* coef, double sign, hipStream_t st) {
   hipLaunchKernelGGL(axpy_kernel, dim3(gs(n)), dim3(256), 0, st, y, x, n, coef, sign);
@@ -291,11 +306,6 @@ void blas_f2d(const float* x, double* y, long n, hipStream_t st) {
 }
 
 template <typename T>
-__global__ void copy_t_kernel(T* __restrict__ y, const T* __restrict__ x, long n) {
-  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = x[i];
-}
-
-template <typename T>
 void blas_copy_t(T* y, const T* x, long n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL((copy_t_kernel<T>), dim3(gs(n)), dim3(256), 0, st, y, x, n);
@@ -304,11 +314,7 @@ void blas_copy_t(T* y, const T* x, long n, hipStream_t st) {
 template void blas_copy_t<double>(double*, const double*, long, hipStream_t);
 template void blas_copy_t<float>(float*, const float*, long, hipStream_t);
 
-void blas_copy(double* y, const double* x, long n, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(copy_kernel, dim3(gs(n)), dim3(256), 0, st, y, x, n);
-  HDG_CHECK(hipGetLastError());
-}
+void blas_copy(double* y, const double* x, long n, hipStream_t st) { blas_copy_t<double>(y, x, n, st); }
 
 template <typename T>
 void blas_fill(T* y, T v, long n, hipStream_t st) {
@@ -333,17 +339,6 @@ void blas_gmres_backsolve(const double* H, const double* s, int j, int ld, doubl
 
 void blas_gmres_combine(double* x, const double* Z, long ldz, int j, const double* y, long n, hipStream_t st) {
   hipLaunchKernelGGL(gmres_combine_kernel, dim3(gs(n)), dim3(256), 0, st, x, Z, ldz, j, y, n);
-  HDG_CHECK(hipGetLastError());
-}
-
-void blas_set_scalar(double* sc, int slot, const double* src, int negate, hipStream_t st) {
-  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(64), 0, st, sc, slot, src, negate);
-  HDG_CHECK(hipGetLastError());
-}
-
-void blas_finite(const double* x, long n, int* bad, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(finite_kernel, dim3(gs(n)), dim3(256), 0, st, x, n, bad);
   HDG_CHECK(hipGetLastError());
 }
 

@@ -126,6 +126,10 @@ void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStrea
 template <typename T>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st);
 
-enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3 };
+enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5 };
+struct Scratch;
+template <typename T>
+void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
+                      Scratch* red, hipStream_t st);
 
 }  // namespace hdg

@@ -10,6 +10,8 @@
 // trace vector is gathered through the caches.  No atomics: every output is
 // written by exactly one lane, so results are bitwise reproducible.
 #include "hdg_internal.hpp"
+#include "blas.hpp"
+#include "reduce.hpp"
 
 namespace hdg {
 
@@ -68,15 +70,22 @@ __device__ inline long elem_id(const int* e, int n) {
 
 // -------------------------------------------------------------------------
 // y = A x | y = b - A x | y = x + Dinv (b - A x) | rc = Jp^T (b - A x)
+// Modes with a reduction (APPLY_Y_DOT: partial sums of x.y; APPLY_RES_NORM:
+// of ||y||^2, and y32 = (float) y when given) write one partial per block;
+// the caller launches the one-block finaliser.
 template <int D, int NE, typename T, int MODE>
 __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
-                                                    T* __restrict__ rc) {
+                                                    T* __restrict__ rc, float* __restrict__ y32,
+                                                    double* __restrict__ partials) {
   constexpr int NL = 2 * D * NE;
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
   const long nface = D * nface_dir<D>(n);
   const long F = blockIdx.x * 256L + threadIdx.x;
-  if (F >= nface) return;
+  if (!RED && F >= nface) return;
+  double part = 0.0;
+  if (F < nface) {
   int g[3] = {0, 0, 0};
   const int c = decode_face<D>(F, n, g);
   T acc[NE];
@@ -122,7 +131,7 @@ __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__
       for (int bb = 0; bb < NE; ++bb) s += Dp[(a * NE + bb) * LANES] * res[bb];
       y[F * NE + a] = s;
     }
-  } else {  // residual restricted by J_N^T (p-coarsening)
+  } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
     constexpr int NC = 1 << (D - 1);
     T res[NE];
 #pragma unroll
@@ -134,6 +143,26 @@ __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__
       for (int a = 0; a < NE; ++a) s += T(Jp[a * NC + v]) * res[a];
       rc[F * NC + v] = s;
     }
+  } else if (MODE == APPLY_Y_DOT) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      y[F * NE + a] = acc[a];
+      part += (double)x[F * NE + a] * (double)acc[a];
+    }
+  } else {  // APPLY_RES_NORM
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      const T v = bvec[F * NE + a] - acc[a];
+      y[F * NE + a] = v;
+      if (y32) y32[F * NE + a] = (float)v;
+      part += (double)v * (double)v;
+    }
+  }
+  }  // F < nface
+  if constexpr (RED) {
+    __shared__ double sh[4];
+    const double s = block_sum_t<256>(part, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
   }
 }
 
@@ -408,7 +437,14 @@ void dispatch_d_ne(int d, int ne, F&& f) {
 template <typename T>
 void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
                   hipStream_t st) {
+  launch_apply_red<T>(L, mode, x, b, y, Jp, rc, nullptr, nullptr, st);
+}
+
+template <typename T>
+void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
+                      Scratch* red, hipStream_t st) {
   if (L.nface == 0) return;
+  double* partials = red ? red->partials : nullptr;
   const T* Af = nullptr;
   const T* Dv = nullptr;
   if constexpr (sizeof(T) == 8) {
@@ -420,26 +456,23 @@ void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const 
   }
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+#define HDG_AK(MM)                                                                                   \
+  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv, x, b, y, \
+                     Jp, rc, y32, partials)
     switch (mode) {
-      case APPLY_Y:
-        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_Y>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv, x,
-                           b, y, Jp, rc);
-        break;
-      case APPLY_RES:
-        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv,
-                           x, b, y, Jp, rc);
-        break;
-      case APPLY_SWEEP:
-        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_SWEEP>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af,
-                           Dv, x, b, y, Jp, rc);
-        break;
-      default:
-        hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(nblk(L.nface)), dim3(256), 0, st,
-                           L.n, Af, Dv, x, b, y, Jp, rc);
-        break;
+      case APPLY_Y: HDG_AK(APPLY_Y); break;
+      case APPLY_RES: HDG_AK(APPLY_RES); break;
+      case APPLY_SWEEP: HDG_AK(APPLY_SWEEP); break;
+      case APPLY_RES_PRESTRICT: HDG_AK(APPLY_RES_PRESTRICT); break;
+      case APPLY_Y_DOT: HDG_AK(APPLY_Y_DOT); break;
+      case APPLY_RES_NORM: HDG_AK(APPLY_RES_NORM); break;
+      default: throw HipError{hipErrorInvalidValue, "apply mode"};
     }
+#undef HDG_AK
   });
   HDG_CHECK(hipGetLastError());
+  if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
+    blas_finalize((int)nblk(L.nface), 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st);
 }
 
 template <typename T>
@@ -509,6 +542,8 @@ void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st) {
 
 #define HDG_INST(T)                                                                                         \
   template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t);  \
+  template void launch_apply_red<T>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,     \
+                                    Scratch*, hipStream_t);                                                  \
   template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t);                                  \
   template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t);            \
   template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t);                      \

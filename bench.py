@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--method", default="pcg", choices=["mg", "pcg", "gmres"])
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--growth", type=int, default=1)
+    ap.add_argument("--coarse-n", type=int, default=2,
+                    help="coarsest macro grid (n x n) of the h-hierarchy, solved directly")
     ap.add_argument("--max-it", type=int, default=20000)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--skip-fp64", action="store_true")
@@ -44,7 +46,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(n, k):
+def cpu_baseline(n, k, coarse_n):
     """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of the workload:
     same kappa/f distribution on an n x n mesh; times the solve only."""
     sys.path.insert(0, HERE)
@@ -56,7 +58,7 @@ def cpu_baseline(n, k):
     O = HDG(2, n, k, 1.0, wl.kappa)
     A, g, _ = O.assemble(wl.f)
     t1 = time.perf_counter()
-    H = omg.Hierarchy(A, 2, n, k, sweeps=2, growth=1, local_corr=omg.LC_BOTH)
+    H = omg.Hierarchy(A, 2, n, k, sweeps=2, growth=1, local_corr=omg.LC_BOTH, coarsest_n=coarse_n)
     t2 = time.perf_counter()
     r = omg.pcg_solve(H, A, g, tol=1e-10, maxit=20000)
     t3 = time.perf_counter()
@@ -64,13 +66,13 @@ def cpu_baseline(n, k):
             "solve_s": t3 - t2, "iters": r.iters, "relres": r.relres}
 
 
-def run_cpu_baseline(n, k):
+def run_cpu_baseline(n, k, coarse_n):
     env = dict(os.environ)
     for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS"):
         env[v] = "1"
     env["HIP_VISIBLE_DEVICES"] = ""
     out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-n", str(n),
-                          "--k", str(k)], capture_output=True, text=True, env=env, timeout=600)
+                          "--k", str(k), "--coarse-n", str(coarse_n)], capture_output=True, text=True, env=env, timeout=600)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     res = json.loads(out.stdout.strip().splitlines()[-1])
@@ -85,7 +87,7 @@ def run_cpu_baseline(n, k):
 def main():
     args = parse()
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline(args.cpu_n, args.k)))
+        print(json.dumps(cpu_baseline(args.cpu_n, args.k, args.coarse_n)))
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
@@ -116,7 +118,7 @@ def main():
     def leg(precision, profile):
         t0 = time.perf_counter()
         P.build(sweeps=args.sweeps, growth=args.growth, local_corr=lc, precision=precision, method=method,
-                max_it=args.max_it)
+                max_it=args.max_it, coarse_n=args.coarse_n)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
         for _ in range(args.warmup):
@@ -168,7 +170,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = run_cpu_baseline(args.cpu_n, k)
+            cpu = run_cpu_baseline(args.cpu_n, k, args.coarse_n)
         except Exception as e:  # reported, never fatal for the GPU figure
             cpu = {"error": str(e)[:300]}
 
@@ -178,7 +180,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 V-cycle + f64 CG",
         "data": "synthetic",
         "config": {"workload": wl.name + " tau=1", "trace_dofs": N, "levels": resmx["n_levels"],
-                   "method": f"{args.method} + V-cycle (sweeps {args.sweeps}, growth {args.growth})",
+                   "method": f"{args.method} + V-cycle (sweeps {args.sweeps}, growth {args.growth}, "
+                             f"coarsest {args.coarse_n}x{args.coarse_n} macro grid)",
                    "tol": args.tol, "iters_mixed": resmx["iters"], "relres_mixed": resmx["relres"],
                    "fp64": None if res64 is None else {"value": round(res64["value"], 1),
                                                        "ms_per_step": round(res64["ms_per_step"], 3),

@@ -82,6 +82,9 @@ typedef struct {
   int method;       /* HDG_METHOD_MG | PCG | GMRES (GMRES: right preconditioned, MGS) */
   int max_it;       /* outer iteration limit (default 200, Sec. 4) */
   int restart;      /* GMRES restart length (0: no restart up to max_it) */
+  int coarse_n;     /* stop h-coarsening at the first macro grid with <= coarse_n macro-elements per
+                       direction and solve it directly (B_1 = A_1^-1); 2 (default) coarsens to 2 x 2.
+                       The paper leaves the number of levels free (Sec. 3.1.2, Sec. 4.5). */
 } hdg_mg_opts;
 
 typedef struct {
@@ -92,7 +95,7 @@ typedef struct {
 } hdg_solve_info;
 
 /* Fill opts with the defaults above (constant 2 sweeps, omega 1, step-3
- * local correction, FP64, MG, 200 iterations). */
+ * local correction, FP64, MG, 200 iterations, coarsening down to 2 x 2). */
 void hdg_default_opts(hdg_mg_opts* opts);
 
 /* Form the element-local HDG problems and their DtN matrices

@@ -24,8 +24,12 @@ paper writes them:
 * outer iterations: fixed point lambda += B_N (g - A lambda) (Sec. 3.6),
   preconditioned CG, and GMRES (right or left preconditioned).
 
-The hierarchy stops at 2^d macro-elements: one macro-element has no
-interior faces under Dirichlet conditions, so its level would be empty.
+The hierarchy stops at 2^d macro-elements by default: one macro-element
+has no interior faces under Dirichlet conditions, so its level would be
+empty.  ``coarsest_n`` stops the h-coarsening earlier, at the first macro
+grid with at most that many macro-elements per direction; the paper treats
+the number of levels N as a free parameter (Sec. 3.1.2, Sec. 4.5) and always
+solves the coarsest level directly (Algorithm 1, B_1 = A_1^-1).
 
 ``coarse='exact'`` keeps every trace unknown of E_{k,B} on the coarse level
 (J_k = identity, no p-coarsening): the coarse operators become exact Schur
@@ -176,7 +180,7 @@ class Hierarchy:
     """Levels ordered from finest (index 0) to coarsest."""
 
     def __init__(self, A, d, n, k, coarse="p1", sweeps=2, growth=1, omega=1.0,
-                 local_corr=LC_PRE):
+                 local_corr=LC_PRE, coarsest_n=2):
         self.coarse, self.omega, self.local_corr = coarse, omega, local_corr
         mesh = Mesh(d, n)
         lev = Level(A, mesh, (k + 1) ** (d - 1))
@@ -191,7 +195,7 @@ class Hierarchy:
             Ac = (J.T @ lev.A @ J).tocsr()
             lev = Level(Ac, mesh, 2 ** (d - 1))
             self.levels.append(lev)
-        while lev.mesh.n > 2:
+        while lev.mesh.n > max(2, coarsest_n):
             I_d, B_d, JB, mc, cm = h_partition(lev.mesh, lev.m, coarse)
             A = lev.A
             AII = A[I_d][:, I_d]

@@ -30,7 +30,7 @@ class Mesh(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("growth", ctypes.c_int), ("omega", ctypes.c_double),
                 ("local_corr", ctypes.c_int), ("precision", ctypes.c_int), ("method", ctypes.c_int),
-                ("max_it", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("max_it", ctypes.c_int), ("restart", ctypes.c_int), ("coarse_n", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libhdg.so")
 OBJ_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["refelem.cpp", "api.cpp", "element.hip", "build.hip", "trace.hip", "blas.hip"]
+SOURCES = ["refelem.cpp", "api.cpp", "element.hip", "build.hip", "trace.hip", "tail.hip", "blas.hip"]
 ARCH = os.environ.get("HDG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

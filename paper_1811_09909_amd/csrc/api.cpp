@@ -18,6 +18,10 @@ struct hdg_problem {
   hipStream_t st = nullptr;      // caller's stream: all work is ordered on it
   hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
   bool use_graphs = true;
+  bool fuse = true;              // fused 2D transition kernels (HDG_NO_FUSE=1 selects the unfused ones)
+  int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (HDG_TAIL_N, 0 = off)
+  int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
+  TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   RefElement ref;
   RefDevice rd;
@@ -221,14 +225,33 @@ enum { G_PCG64 = 0, G_PCGMX = 1, G_MG64 = 2, G_MGMX = 3, G_PRE64 = 4, G_PREMX = 
 
 // -------------------------------------------------------------------------
 // Algorithm 1 on level i; returns the device pointer holding e = B_i r.
-// If `out` is given the result is written there.
+// If `out` is given the result is written there.  `pre_done`: the caller
+// already applied the first block-Jacobi step (e = D^-1 r into L.e).
+//
+// In 2D with at least one sweep the transitions use fused kernels: the
+// finest residual's P1 restriction also takes the P1 level's first Jacobi
+// step; an h-transition is one macro-element pass (interior residual, local
+// correction of step 3, its share of the restricted residual), one
+// coarse-face pass (restricted residual + coarse first Jacobi step, or the
+// coarsest direct solve), and one out-of-place pass (prolongation + local
+// correction of step 5).  Same arithmetic as the unfused kernels up to the
+// order of the last rounding.
 template <typename T>
-T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
+T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false) {
   Level& L = P->L[i];
   const int pr = sizeof(T) == 8 ? 0 : 1;
   hipStream_t st = P->st;
   T* e = (T*)L.e[pr];
   T* w = (T*)L.w[pr];
+  if (i == P->tail_start[pr]) {
+    TailArgs a = P->tail_args[pr];
+    a.rin = r;
+    a.ein = e;
+    a.pre_done = pre_done ? 1 : 0;
+    a.eout = out ? out : e;
+    launch_tail<T>(a, st);
+    return (T*)a.eout;
+  }
   if (L.kind == 2) {
     T* dst = out ? out : e;
     launch_coarse_solve<T>(L, r, dst, st);
@@ -236,11 +259,14 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
   }
   const int m = L.sweeps;
   const int lc = P->opts.local_corr;
+  const bool fused = P->fuse && L.d == 2 && m >= 1;
   // pre-smoothing from e = 0
-  if (m >= 1)
-    launch_jacobi0<T>(L, r, e, st);
-  else
-    blas_fill<T>(e, T(0), L.nlam, st);
+  if (!pre_done) {
+    if (m >= 1)
+      launch_jacobi0<T>(L, r, e, st);
+    else
+      blas_fill<T>(e, T(0), L.nlam, st);
+  }
   for (int s = 1; s < m; ++s) {
     apply<T>(P, i, APPLY_SWEEP, e, r, w, nullptr);
     std::swap(e, w);
@@ -248,26 +274,57 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out) {
   Level& C = P->L[i + 1];
   T* rc = (T*)C.r[pr];
   if (L.kind == 0) {
-    apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc);
+    const T* ec;
+    if (fused && C.kind != 2) {
+      const bool timed = P->prof_on && i == 0;
+      hdg_problem::Pending pd{2 * APPLY_RES_PRESTRICT + pr, nullptr, nullptr};
+      if (timed) {
+        pd.a = take_event(P);
+        pd.b = take_event(P);
+        HDG_CHECK(hipEventRecord(pd.a, st));
+      }
+      launch_res_prestrict<T>(L, C, e, r, rc, (T*)C.e[pr], P->rd.Jp, st);
+      if (timed) {
+        HDG_CHECK(hipEventRecord(pd.b, st));
+        P->pending.push_back(pd);
+      }
+      ec = vcycle<T>(P, i + 1, rc, nullptr, true);
+    } else {
+      apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc);
+      ec = vcycle<T>(P, i + 1, rc, nullptr);
+    }
+    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st);
+  } else if (fused) {
+    T* cb = (T*)L.cb[pr];
+    launch_hpre<T>(L, r, e, (lc & HDG_LC_PRE) ? 1 : 0, cb, st);
+    const T* ec;
+    if (C.kind == 2) {
+      launch_hsum<T>(L, C, r, cb, nullptr, (T*)C.e[pr], st);
+      ec = (const T*)C.e[pr];
+    } else {
+      launch_hsum<T>(L, C, r, cb, rc, (T*)C.e[pr], st);
+      ec = vcycle<T>(P, i + 1, rc, nullptr, true);
+    }
+    launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st);
+    std::swap(e, w);
   } else {
     apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
     launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st);
     launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st);
-  }
-  const T* ec = vcycle<T>(P, i + 1, rc, nullptr);
-  if (L.kind == 0)
-    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st);
-  else
+    const T* ec = vcycle<T>(P, i + 1, rc, nullptr);
     launch_hprolong<T>(L, C, ec, e, st);
-  if (L.kind == 1 && (lc & HDG_LC_POST)) {
-    apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
-    launch_hcorr<T>(L, w, e, 1, 0, nullptr, st);
+    if (lc & HDG_LC_POST) {
+      apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
+      launch_hcorr<T>(L, w, e, 1, 0, nullptr, st);
+    }
   }
   for (int s = 0; s < m; ++s) {
     T* dst = (out && s == m - 1) ? out : w;
     apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr);
-    if (dst == w) std::swap(e, w);
-    else e = dst;
+    if (dst == w)
+      std::swap(e, w);
+    else
+      e = dst;
   }
   if (out && e != out) {
     blas_copy_t<T>(out, e, L.nlam, st);
@@ -531,6 +588,7 @@ void hdg_default_opts(hdg_mg_opts* o) {
   o->method = HDG_METHOD_MG;
   o->max_it = 200;
   o->restart = 0;
+  o->coarse_n = 2;
 }
 
 const char* hdg_status_string(hdg_status s) {
@@ -575,6 +633,8 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->st = (hipStream_t)hip_stream;
   P->store_recovery = store_recovery != 0;
   P->use_graphs = std::getenv("HDG_NO_GRAPH") == nullptr;
+  P->fuse = std::getenv("HDG_NO_FUSE") == nullptr;
+  if (const char* tn = std::getenv("HDG_TAIL_N")) P->tail_nmax = std::atoi(tn);
   HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
   P->nv = P->ref.nv;
@@ -651,8 +711,9 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     hdg_default_opts(&o);
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
-      o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0)
+      o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0)
     return HDG_ERR_INVALID_ARG;
+  if (o.coarse_n < 2) o.coarse_n = 2;
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   free_build(P);
@@ -671,7 +732,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     L[1].Aelem = dalloc<double>(P, L[1].nelem * L[1].nl * L[1].nl, true);
     launch_pgalerkin(d, P->ne, P->nelem, P->rd.Jp, P->Ae, L[1].Aelem, P->st);
   }
-  while (L.back().n > 2) {
+  while (L.back().n > o.coarse_n) {
     const size_t fi = L.size() - 1;
     L.emplace_back();
     Level& F = L[fi];
@@ -693,7 +754,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   }
   Level& Lc = L.back();
   Lc.kind = 2;
-  if (Lc.nlam > 64) return HDG_ERR_UNSUPPORTED;
+  if (Lc.nlam > 8192) return HDG_ERR_UNSUPPORTED;  // dense coarsest inverse: N^2 doubles
   if (Lc.nlam > 0) {
     Lc.Ainv64 = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
     Lc.Ainv32 = dalloc<float>(P, Lc.nlam * Lc.nlam, true);
@@ -722,6 +783,50 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
       launch_dinv(Li, o.omega, P->st);
     }
   }
+  // one-workgroup coarse tail (2D, fused path): the first level from which
+  // every remaining level's vectors fit the LDS arena
+  for (int pr = 0; pr < 2; ++pr) {
+    P->tail_start[pr] = -1;
+    if (d != 2 || !P->fuse || o.sweeps < 1 || P->tail_nmax <= 0) continue;
+    const long es = pr == 0 ? 8 : 4;
+    for (int t = 0; t < (int)L.size(); ++t) {
+      if (L[t].kind != 1 || L[t].n > P->tail_nmax || L.back().nlam > 64) continue;
+      if ((int)L.size() - t > TAIL_MAX_LEVELS) continue;
+      TailArgs ta;
+      ta.nlev = (int)L.size() - t;
+      ta.lc = o.local_corr;
+      long off = 0;
+      auto take = [&](long cnt) {
+        long o2 = off;
+        off += (cnt + 3) / 4 * 4;
+        return o2;
+      };
+      for (int l = t; l < (int)L.size(); ++l) {
+        const Level& Ll = L[l];
+        TailLevel& tl = ta.lev[l - t];
+        tl.n = Ll.n;
+        tl.kind = Ll.kind;
+        tl.sweeps = Ll.sweeps;
+        tl.nlam = Ll.nlam;
+        tl.nface = Ll.nface;
+        tl.nmacro = Ll.kind == 1 ? Ll.nmacro : 0;
+        tl.Af = pr == 0 ? (const void*)Ll.Af64 : (const void*)Ll.Af32;
+        tl.Dinv = pr == 0 ? (const void*)Ll.Dinv64 : (const void*)Ll.Dinv32;
+        tl.AIIinv = pr == 0 ? (const void*)Ll.AIIinv64 : (const void*)Ll.AIIinv32;
+        tl.P = pr == 0 ? (const void*)Ll.P64 : (const void*)Ll.P32;
+        tl.Ainv = pr == 0 ? (const void*)Ll.Ainv64 : (const void*)Ll.Ainv32;
+        tl.off_r = take(Ll.nlam);
+        tl.off_e = take(Ll.nlam);
+        tl.off_w = take(Ll.nlam);
+        tl.off_cb = take(Ll.kind == 1 ? Ll.nmacro * Ll.ncl : 0);
+      }
+      if (off * es > TAIL_ARENA_BYTES) continue;
+      P->tail_start[pr] = t;
+      P->tail_args[pr] = ta;
+      break;
+    }
+  }
+
   P->N = L[0].nlam;
   const long N = P->N;
   P->g = dalloc<double>(P, N, true);

@@ -360,6 +360,75 @@ __global__ void coarse_inverse_kernel(int d, int n, int ne, int N, const double*
   }
 }
 
+// Dense assembly of a level operator: elements of one colour (parity of
+// their coordinates) share no face, so a pass adds without conflicts.
+__global__ void dense_assemble_kernel(int d, int n, int ne, int color, long N, const double* __restrict__ Aelem,
+                                      double* __restrict__ A) {
+  const int nl = 2 * d * ne;
+  long nelem = 1;
+  for (int a = 0; a < d; ++a) nelem *= n;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= nelem * nl * nl) return;
+  const long T = t / (nl * nl);
+  const int ij = (int)(t % (nl * nl));
+  int e[3] = {0, 0, 0};
+  long r = T;
+  int col = 0;
+  for (int a = 0; a < d; ++a) {
+    e[a] = (int)(r % n);
+    r /= n;
+    col |= (e[a] & 1) << a;
+  }
+  if (col != color) return;
+  long gid[2];
+  const int loc[2] = {ij / nl, ij % nl};
+  for (int pass = 0; pass < 2; ++pass) {
+    const int l = loc[pass];
+    const int sl = l / ne, a = l % ne;
+    const int c = sl / 2, sd = sl % 2;
+    const int p = e[c] + sd;
+    gid[pass] = -1;
+    if (p > 0 && p < n) {
+      long idx2 = 0, stride = 1;
+      for (int aa = 0; aa < d; ++aa) {
+        const int g = aa == c ? p : e[aa];
+        if (aa == c) {
+          idx2 += (long)(g - 1) * stride;
+          stride *= n - 1;
+        } else {
+          idx2 += (long)g * stride;
+          stride *= n;
+        }
+      }
+      gid[pass] = (c * nfd_of(d, n) + idx2) * ne + a;
+    }
+  }
+  if (gid[0] >= 0 && gid[1] >= 0) A[gid[0] * N + gid[1]] += Aelem[T * nl * nl + ij];
+}
+
+// One Gauss-Jordan elimination step on pivot k, out of place (A -> B), for
+// an SPD matrix (no pivoting); after N steps B holds A^-1.
+__global__ void gj_step_kernel(long N, int k, const double* __restrict__ A, double* __restrict__ B) {
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= N * N) return;
+  const long i = t / N, j = t % N;
+  const double p = 1.0 / A[(long)k * N + k];
+  double v;
+  if (i == k && j == k)
+    v = p;
+  else if (i == k)
+    v = A[t] * p;
+  else if (j == k)
+    v = -A[t] * p;
+  else
+    v = A[t] - A[i * N + k] * A[(long)k * N + j] * p;
+  B[t] = v;
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, long n) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) b[i] = (float)a[i];
+}
+
 }  // namespace
 
 void launch_face_major(const Level& L, hipStream_t st) {
@@ -406,6 +475,29 @@ void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st) {
 
 void launch_coarse_inverse(const Level& L, hipStream_t st) {
   if (L.nlam == 0) return;
+  if (L.nlam > 64) {
+    // dense assembly, then N out-of-place Gauss-Jordan steps (FP64)
+    const long N = L.nlam;
+    double *A = nullptr, *B = nullptr;
+    HDG_CHECK(hipMalloc((void**)&A, sizeof(double) * N * N));
+    HDG_CHECK(hipMalloc((void**)&B, sizeof(double) * N * N));
+    HDG_CHECK(hipMemsetAsync(A, 0, sizeof(double) * N * N, st));
+    const long tot = L.nelem * L.nl * L.nl;
+    for (int color = 0; color < (1 << L.d); ++color)
+      hipLaunchKernelGGL(dense_assemble_kernel, dim3(nblk(tot)), dim3(256), 0, st, L.d, L.n, L.ne, color, N, L.Aelem,
+                         A);
+    for (long k = 0; k < N; ++k) {
+      hipLaunchKernelGGL(gj_step_kernel, dim3(nblk(N * N)), dim3(256), 0, st, N, (int)k, A, B);
+      std::swap(A, B);
+    }
+    HDG_CHECK(hipMemcpyAsync(L.Ainv64, A, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, st, A, L.Ainv32, N * N);
+    HDG_CHECK(hipGetLastError());
+    HDG_CHECK(hipStreamSynchronize(st));
+    HDG_CHECK(hipFree(A));
+    HDG_CHECK(hipFree(B));
+    return;
+  }
   hipLaunchKernelGGL(coarse_inverse_kernel, dim3(1), dim3(256), 0, st, L.d, L.n, L.ne, (int)L.nlam, L.Aelem,
                      L.Ainv64, L.Ainv32);
   HDG_CHECK(hipGetLastError());

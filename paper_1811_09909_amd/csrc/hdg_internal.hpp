@@ -125,6 +125,36 @@ template <typename T>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st);
 template <typename T>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st);
+template <typename T>
+void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
+                          hipStream_t st);
+// fused 2D h-transition kernels
+template <typename T>
+void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st);
+template <typename T>
+void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st);
+template <typename T>
+void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const T* eold, T* enew, int do_corr,
+                  hipStream_t st);
+
+// single-workgroup coarse tail of the V-cycle (tail.hip)
+constexpr int TAIL_MAX_LEVELS = 12;
+constexpr int TAIL_ARENA_BYTES = 144 * 1024;
+struct TailLevel {
+  int n = 0, kind = 2, sweeps = 0;
+  long nlam = 0, nface = 0, nmacro = 0;
+  const void *Af = nullptr, *Dinv = nullptr, *AIIinv = nullptr, *P = nullptr, *Ainv = nullptr;
+  long off_r = 0, off_e = 0, off_w = 0, off_cb = 0;  // element offsets into the LDS arena
+};
+struct TailArgs {
+  int nlev = 0, lc = 0, pre_done = 0;
+  TailLevel lev[TAIL_MAX_LEVELS];
+  const void* rin = nullptr;
+  const void* ein = nullptr;
+  void* eout = nullptr;
+};
+template <typename T>
+void launch_tail(const TailArgs& a, hipStream_t st);
 
 enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5 };
 struct Scratch;

@@ -12,61 +12,13 @@
 #include "hdg_internal.hpp"
 #include "blas.hpp"
 #include "reduce.hpp"
+#include "trace_dev.hpp"
 
 namespace hdg {
 
 namespace {
 
-template <int D>
-__device__ inline long nface_dir(int n) {
-  long v = n - 1;
-  for (int a = 1; a < D; ++a) v *= n;
-  return v;
-}
-
-// interior face id of normal c at grid coordinates g (g[c] in 1..n-1)
-template <int D>
-__device__ inline long face_id(int c, const int* g, int n) {
-  long idx = 0, stride = 1;
-  for (int a = 0; a < D; ++a) {
-    if (a == c) {
-      idx += (long)(g[a] - 1) * stride;
-      stride *= (n - 1);
-    } else {
-      idx += (long)g[a] * stride;
-      stride *= n;
-    }
-  }
-  return c * nface_dir<D>(n) + idx;
-}
-
-template <int D>
-__device__ inline int decode_face(long F, int n, int* g) {
-  long nfd = nface_dir<D>(n);
-  int c = (int)(F / nfd);
-  long r = F % nfd;
-  for (int a = 0; a < D; ++a) {
-    int ext = a == c ? n - 1 : n;
-    g[a] = (int)(r % ext) + (a == c ? 1 : 0);
-    r /= ext;
-  }
-  return c;
-}
-
-template <int D>
-__device__ inline void decode_elem(long T, int n, int* e) {
-  for (int a = 0; a < D; ++a) {
-    e[a] = (int)(T % n);
-    T /= n;
-  }
-}
-
-template <int D>
-__device__ inline long elem_id(const int* e, int n) {
-  long T = 0;
-  for (int a = D - 1; a >= 0; --a) T = T * n + e[a];
-  return T;
-}
+using namespace dev;
 
 // -------------------------------------------------------------------------
 // y = A x | y = b - A x | y = x + Dinv (b - A x) | rc = Jp^T (b - A x)
@@ -136,12 +88,24 @@ __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__
     T res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
+    T rcv[NC];
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
       T s = T(0);
 #pragma unroll
       for (int a = 0; a < NE; ++a) s += T(Jp[a * NC + v]) * res[a];
       rc[F * NC + v] = s;
+      rcv[v] = s;
+    }
+    if (y) {  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
+      const T* Dp = Dinv + (F >> 6) * (long)(NC * NC * LANES) + (F & 63);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int b = 0; b < NC; ++b) s += Dp[(a * NC + b) * LANES] * rcv[b];
+        y[F * NC + a] = s;
+      }
     }
   } else if (MODE == APPLY_Y_DOT) {
 #pragma unroll
@@ -202,25 +166,6 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
   }
 }
 
-// interior faces of a coarse macro-element m (grid n/2) on the fine grid n:
-// iota = c * 2^(D-1) + lex(t) over the tangential child bits t.
-template <int D>
-__device__ inline long macro_iface(const int* m, int iota, int n) {
-  constexpr int NS = 1 << (D - 1);
-  const int c = iota / NS, t = iota % NS;
-  int g[3] = {0, 0, 0};
-  int j = 0;
-  for (int a = 0; a < D; ++a) {
-    if (a == c) {
-      g[a] = 2 * m[a] + 1;
-    } else {
-      g[a] = 2 * m[a] + ((t >> j) & 1);
-      ++j;
-    }
-  }
-  return face_id<D>(c, g, n);
-}
-
 // Local correction and the macro-element part of the restriction:
 //   e_I += A_II^-1 rho_I            (eq. localCorrection, when do_corr)
 //   cb_M = P_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict)
@@ -272,34 +217,6 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
       cb[(base + lane) * NCL + j] = s;
     }
   }
-}
-
-// weight of coarse vertex V at fine vertex v of sub-face t of a macro-face
-template <int D>
-__device__ inline double jh_weight(int t, int v, int V) {
-  double w = 1.0;
-#pragma unroll
-  for (int j = 0; j < D - 1; ++j) {
-    double s = 0.5 * (((t >> j) & 1) + ((v >> j) & 1));
-    w *= ((V >> j) & 1) ? s : 1.0 - s;
-  }
-  return w;
-}
-
-// sub-face t of coarse face with grid coords G (coarse grid) on the fine grid
-template <int D>
-__device__ inline long subface(int c, const int* G, int t, int n) {
-  int g[3] = {0, 0, 0};
-  int j = 0;
-  for (int a = 0; a < D; ++a) {
-    if (a == c) {
-      g[a] = 2 * G[a];
-    } else {
-      g[a] = 2 * G[a] + ((t >> j) & 1);
-      ++j;
-    }
-  }
-  return face_id<D>(c, g, n);
 }
 
 // rc_F = J^T rho_B(F) + cb_{M-}(slot 2c+1) + cb_{M+}(slot 2c)   (eq. n_1_Qk)
@@ -417,6 +334,94 @@ __global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* 
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) hpre_kernel(int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                                   const T* __restrict__ P, const T* __restrict__ r,
+                                                   T* __restrict__ e, int do_corr, T* __restrict__ cb) {
+  const long nmacro = (long)(n / 2) * (n / 2);
+  const long M = blockIdx.x * 256L + threadIdx.x;
+  if (M < nmacro) hpre_item<2, T>(M, n, Af, AIIinv, P, r, e, do_corr, cb);
+}
+
+template <int D, typename T>
+__global__ void hsum_kernel(int n, const T* __restrict__ r, const T* __restrict__ cb, const T* __restrict__ Dc,
+                            T* __restrict__ rc, T* __restrict__ ec) {
+  const long ncf = D * nface_dir<D>(n / 2);
+  const long Fc = blockIdx.x * 256L + threadIdx.x;
+  if (Fc < ncf) hsum_item<D, T>(Fc, n, r, cb, Dc, rc, ec);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __restrict__ Af,
+                                                    const T* __restrict__ AIIinv, const T* __restrict__ P,
+                                                    const T* __restrict__ r, const T* __restrict__ ec,
+                                                    const T* __restrict__ eold, T* __restrict__ enew, int do_corr) {
+  if (blockIdx.x < nbm) {
+    const long nmacro = (long)(n / 2) * (n / 2);
+    const long M = blockIdx.x * 256L + threadIdx.x;
+    if (M < nmacro) hpost_m_item<D, T>(M, n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
+  } else {
+    const long ncf = D * nface_dir<D>(n / 2);
+    const long Fc = (blockIdx.x - nbm) * 256L + threadIdx.x;
+    if (Fc < ncf) hpost_f_item<D, T>(Fc, n, ec, eold, enew);
+  }
+}
+
+// Coarsest level reached from an h-transition: r_c by the restriction sum
+// and e_c = A_1^-1 r_c, in one workgroup (N <= 64)
+template <int D, typename T>
+__global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T* __restrict__ cb,
+                                  const T* __restrict__ Ainv, T* __restrict__ ec) {
+  constexpr int NC = 1 << (D - 1);
+  constexpr int NCL = 2 * D * NC;
+  __shared__ T rcs[64];
+  const int nm = n / 2;
+  const long ncf = D * nface_dir<D>(nm);
+  for (long Fc = threadIdx.x; Fc < ncf; Fc += blockDim.x) {
+    int G[3] = {0, 0, 0};
+    const int c = decode_face<D>(Fc, nm, G);
+    T out[NC];
+#pragma unroll
+    for (int V = 0; V < NC; ++V) out[V] = T(0);
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const long f = subface<D>(c, G, t, n);
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        const T rv = r[f * NC + v];
+#pragma unroll
+        for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+      }
+    }
+    int mm[3] = {G[0], G[1], G[2]};
+    mm[c] = G[c] - 1;
+    const long Mm = elem_id<D>(mm, nm);
+    mm[c] = G[c];
+    const long Mp = elem_id<D>(mm, nm);
+#pragma unroll
+    for (int V = 0; V < NC; ++V)
+      rcs[Fc * NC + V] = out[V] + cb[Mm * NCL + (2 * c + 1) * NC + V] + cb[Mp * NCL + (2 * c) * NC + V];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    T s = T(0);
+    for (int j = 0; j < N; ++j) s += Ainv[i * N + j] * rcs[j];
+    ec[i] = s;
+  }
+}
+
+// e = A_1^-1 r for a larger coarsest level: one wavefront per row
+template <typename T>
+__global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  double s = 0.0;
+  for (int j = lane; j < N; j += 64) s += (double)Ainv[(long)row * N + j] * (double)r[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) e[row] = (T)s;
+}
+
 inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
 template <typename F>
@@ -473,6 +478,22 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
   HDG_CHECK(hipGetLastError());
   if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
     blas_finalize((int)nblk(L.nface), 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st);
+}
+
+// residual of level L restricted to P1 on the same faces (level C), and when
+// ec is given the first block-Jacobi step of C on it
+template <typename T>
+void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
+                          hipStream_t st) {
+  if (L.nface == 0) return;
+  const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
+  const T* Dc = sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32;
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af,
+                       Dc, x, b, ec, Jp, rc, nullptr, nullptr);
+  });
+  HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
@@ -536,7 +557,53 @@ template <typename T>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st) {
   if (L.nlam == 0) return;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.Ainv64 : (const T*)L.Ainv32;
+  if (L.nlam > 64) {
+    hipLaunchKernelGGL((coarse_gemv_kernel<T>), dim3((unsigned)((L.nlam + 3) / 4)), dim3(256), 0, st, (int)L.nlam, Ai,
+                       r, e);
+    HDG_CHECK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL((coarse_solve_kernel<T>), dim3(1), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
+  HDG_CHECK(hipGetLastError());
+}
+
+
+template <typename T>
+void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st) {
+  const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
+  const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
+  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr, cb);
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st) {
+  if (C.kind == 2 && C.nlam <= 64) {
+    const T* Ai = sizeof(T) == 8 ? (const T*)C.Ainv64 : (const T*)C.Ainv32;
+    hipLaunchKernelGGL((hsum_solve_kernel<2, T>), dim3(1), dim3(64), 0, st, L.n, (int)C.nlam, r, cb, Ai, ec);
+  } else if (C.kind == 2) {
+    // restricted residual into C.r, then the dense coarsest solve
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, r, cb, (const T*)nullptr,
+                       (T*)C.r[sizeof(T) == 8 ? 0 : 1], (T*)nullptr);
+    HDG_CHECK(hipGetLastError());
+    launch_coarse_solve<T>(C, (const T*)C.r[sizeof(T) == 8 ? 0 : 1], ec, st);
+  } else {
+    const T* Dc = ec ? (sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32) : nullptr;
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, r, cb, Dc, rc, ec);
+  }
+  HDG_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const T* eold, T* enew, int do_corr,
+                  hipStream_t st) {
+  const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
+  const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
+  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  const long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
+  hipLaunchKernelGGL((hpost_kernel<2, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, Af, Ai, P, r, ec,
+                     eold, enew, do_corr);
   HDG_CHECK(hipGetLastError());
 }
 
@@ -549,7 +616,12 @@ void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st) {
   template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t);                      \
   template void launch_hrestrict<T>(const Level&, const Level&, const T*, const T*, T*, hipStream_t);        \
   template void launch_hprolong<T>(const Level&, const Level&, const T*, T*, hipStream_t);                   \
-  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t);
+  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t);                             \
+  template void launch_hpre<T>(const Level&, const T*, T*, int, T*, hipStream_t);                            \
+  template void launch_res_prestrict<T>(const Level&, const Level&, const T*, const T*, T*, T*, const double*, \
+                                        hipStream_t);                                                        \
+  template void launch_hsum<T>(const Level&, const Level&, const T*, const T*, T*, T*, hipStream_t);         \
+  template void launch_hpost<T>(const Level&, const Level&, const T*, const T*, const T*, T*, int, hipStream_t);
 HDG_INST(double)
 HDG_INST(float)
 #undef HDG_INST

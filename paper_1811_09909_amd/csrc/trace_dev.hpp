@@ -1,0 +1,547 @@
+// Device-side geometry of the structured trace spaces and the per-face /
+// per-macro-element work items shared by the grid kernels (trace.hip) and
+// the single-workgroup coarse tail (tail.hip).
+#pragma once
+#include "hdg_internal.hpp"
+
+namespace hdg {
+namespace dev {
+
+template <int D>
+__device__ inline long nface_dir(int n) {
+  long v = n - 1;
+  for (int a = 1; a < D; ++a) v *= n;
+  return v;
+}
+
+// interior face id of normal c at grid coordinates g (g[c] in 1..n-1)
+template <int D>
+__device__ inline long face_id(int c, const int* g, int n) {
+  long idx = 0, stride = 1;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      idx += (long)(g[a] - 1) * stride;
+      stride *= (n - 1);
+    } else {
+      idx += (long)g[a] * stride;
+      stride *= n;
+    }
+  }
+  return c * nface_dir<D>(n) + idx;
+}
+
+// 32-bit index arithmetic: face and element counts stay below 2^31 for every
+// supported mesh (n <= 8192 in 2D, 512 in 3D)
+template <int D>
+__device__ inline int decode_face(long F, int n, int* g) {
+  const unsigned nfd = (unsigned)nface_dir<D>(n);
+  const unsigned f = (unsigned)F;
+  const int c = (int)(f / nfd);
+  unsigned r = f - (unsigned)c * nfd;
+  for (int a = 0; a < D; ++a) {
+    const unsigned ext = a == c ? (unsigned)(n - 1) : (unsigned)n;
+    const unsigned q = r / ext;
+    g[a] = (int)(r - q * ext) + (a == c ? 1 : 0);
+    r = q;
+  }
+  return c;
+}
+
+template <int D>
+__device__ inline void decode_elem(long T, int n, int* e) {
+  unsigned t = (unsigned)T;
+  for (int a = 0; a < D; ++a) {
+    const unsigned q = t / (unsigned)n;
+    e[a] = (int)(t - q * (unsigned)n);
+    t = q;
+  }
+}
+
+template <int D>
+__device__ inline long elem_id(const int* e, int n) {
+  long T = 0;
+  for (int a = D - 1; a >= 0; --a) T = T * n + e[a];
+  return T;
+}
+
+// interior faces of a coarse macro-element m (grid n/2) on the fine grid n:
+// iota = c * 2^(D-1) + lex(t) over the tangential child bits t.
+template <int D>
+__device__ inline long macro_iface(const int* m, int iota, int n) {
+  constexpr int NS = 1 << (D - 1);
+  const int c = iota / NS, t = iota % NS;
+  int g[3] = {0, 0, 0};
+  int j = 0;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      g[a] = 2 * m[a] + 1;
+    } else {
+      g[a] = 2 * m[a] + ((t >> j) & 1);
+      ++j;
+    }
+  }
+  return face_id<D>(c, g, n);
+}
+
+// weight of coarse vertex V at fine vertex v of sub-face t of a macro-face
+template <int D>
+__device__ inline double jh_weight(int t, int v, int V) {
+  double w = 1.0;
+#pragma unroll
+  for (int j = 0; j < D - 1; ++j) {
+    double s = 0.5 * (((t >> j) & 1) + ((v >> j) & 1));
+    w *= ((V >> j) & 1) ? s : 1.0 - s;
+  }
+  return w;
+}
+
+// sub-face t of coarse face with grid coords G (coarse grid) on the fine grid
+template <int D>
+__device__ inline long subface(int c, const int* G, int t, int n) {
+  int g[3] = {0, 0, 0};
+  int j = 0;
+  for (int a = 0; a < D; ++a) {
+    if (a == c) {
+      g[a] = 2 * G[a];
+    } else {
+      g[a] = 2 * G[a] + ((t >> j) & 1);
+      ++j;
+    }
+  }
+  return face_id<D>(c, g, n);
+}
+
+// ---------------------------------------------------------------------------
+// Fused h-transition kernels (2D).  A macro-element M of the coarse grid owns
+// its NIF interior faces (I) exclusively and sees its NBF boundary sub-faces
+// (B) from its own children only; every output is written by one lane.
+//   I face iota = c*NS + t (t: tangential child bit), sides = children with
+//   bit c = 0 / 1;  B face beta = (2c+sd)*NS + t, the child inside M is on
+//   face-major side 1-sd.
+// Child ch, local slot (cc, sd2) lies on M-face: q = bit_cc(ch) + sd2;
+//   q == 1 -> I face cc*NS + t(ch, cc); else B face (2cc + (q==2))*NS + t.
+template <int D>
+struct Macro {
+  static constexpr int NC = 1 << (D - 1);
+  static constexpr int NS = NC;
+  static constexpr int NIF = D * NS;
+  static constexpr int NBF = 2 * D * NS;
+  static constexpr int NL = 2 * D * NC;
+  static constexpr int NI = NIF * NC;
+  static constexpr int NCL = 2 * D * NC;
+};
+
+template <int D>
+__device__ inline int tbits(int ch, int cc) {
+  int t = 0, j = 0;
+  for (int a = 0; a < D; ++a)
+    if (a != cc) {
+      t |= ((ch >> a) & 1) << j;
+      ++j;
+    }
+  return t;
+}
+
+// M-face index (0..NIF-1 interior, NIF.. boundary) of child ch's slot sl
+template <int D>
+__device__ inline int mface_of(int ch, int sl) {
+  constexpr int NS = 1 << (D - 1);
+  const int cc = sl / 2, sd2 = sl % 2;
+  const int q = ((ch >> cc) & 1) + sd2;
+  const int t = tbits<D>(ch, cc);
+  if (q == 1) return cc * NS + t;
+  return D * NS + (2 * cc + (q == 2 ? 1 : 0)) * NS + t;
+}
+
+// fine face id of M-face mf (-1 on the domain boundary), and for B faces the
+// face-major side holding M's child
+template <int D>
+__device__ inline long mface_id(const int* m, int mf, int n, int* side_in) {
+  constexpr int NS = 1 << (D - 1);
+  constexpr int NIF = D * NS;
+  int g[3] = {0, 0, 0};
+  int c, t;
+  if (mf < NIF) {
+    c = mf / NS;
+    t = mf % NS;
+    g[c] = 2 * m[c] + 1;
+    *side_in = -1;
+  } else {
+    const int b = mf - NIF;
+    const int S = b / NS;
+    t = b % NS;
+    c = S / 2;
+    const int sd = S % 2;
+    g[c] = 2 * m[c] + 2 * sd;
+    *side_in = 1 - sd;
+    if (g[c] == 0 || g[c] == n) return -1;
+  }
+  int j = 0;
+  for (int a = 0; a < D; ++a)
+    if (a != c) {
+      g[a] = 2 * m[a] + ((t >> j) & 1);
+      ++j;
+    }
+  return face_id<D>(c, g, n);
+}
+
+// (A e) on face fid, side `side` only (child ch), e given per M-face
+template <int D, typename T>
+__device__ inline void side_apply(const T* __restrict__ Af, long fid, int side, int ch, const T (*eM)[1 << (D - 1)],
+                                  T* acc) {
+  using Mc = Macro<D>;
+  constexpr int NE = Mc::NC, NL = Mc::NL;
+  const T* Mb = Af + (fid >> 6) * (2L * NL * NE * LANES) + (fid & 63) + side * (long)NL * NE * LANES;
+#pragma unroll
+  for (int sl = 0; sl < 2 * D; ++sl) {
+    const int mf = mface_of<D>(ch, sl);
+#pragma unroll
+    for (int bb = 0; bb < NE; ++bb) {
+      const T xv = eM[mf][bb];
+#pragma unroll
+      for (int a = 0; a < NE; ++a) acc[a] += Mb[((sl * NE + bb) * NE + a) * LANES] * xv;
+    }
+  }
+}
+
+// child of M on side `side` of I face iota
+template <int D>
+__device__ inline int ichild(int iota, int side) {
+  constexpr int NS = 1 << (D - 1);
+  const int c = iota / NS, t = iota % NS;
+  int ch = side << c, j = 0;
+  for (int a = 0; a < D; ++a)
+    if (a != c) {
+      ch |= ((t >> j) & 1) << a;
+      ++j;
+    }
+  return ch;
+}
+
+template <int D>
+__device__ inline int bchild(int b) {  // b = beta - NIF
+  constexpr int NS = 1 << (D - 1);
+  const int S = b / NS, t = b % NS;
+  const int c = S / 2, sd = S % 2;
+  int ch = sd << c, j = 0;
+  for (int a = 0; a < D; ++a)
+    if (a != c) {
+      ch |= ((t >> j) & 1) << a;
+      ++j;
+    }
+  return ch;
+}
+
+// Pre-coarse-correction work of level l for one macro-element:
+//   rho_I = r_I - (A e)_I, e_I += A_II^-1 rho_I (if do_corr),
+//   cb_M = -J^T (A_M e)_B + P_M^T rho_I      (its share of Q (r - A e))
+template <int D, typename T>
+__device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                 const T* __restrict__ P, const T* r, T* e, int do_corr, T* cb) {
+  using Mc = Macro<D>;
+  constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
+  const int nm = n / 2;
+  int m[3] = {0, 0, 0};
+  decode_elem<D>(M, nm, m);
+  T eM[NIF + NBF][NC];
+  long fid[NIF + NBF];
+  int sidein[NIF + NBF];
+#pragma unroll
+  for (int f = 0; f < NIF + NBF; ++f) {
+    fid[f] = mface_id<D>(m, f, n, &sidein[f]);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? e[fid[f] * NC + a] : T(0);
+  }
+  T rho[NI];
+#pragma unroll
+  for (int i = 0; i < NIF; ++i) {
+    T acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    side_apply<D, T>(Af, fid[i], 0, ichild<D>(i, 0), eM, acc);
+    side_apply<D, T>(Af, fid[i], 1, ichild<D>(i, 1), eM, acc);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
+  }
+  const long lane = M & 63;
+  if (do_corr) {
+    const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + lane;
+#pragma unroll
+    for (int i = 0; i < NIF; ++i) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rho[j];
+        e[fid[i] * NC + a] = eM[i][a] + s;
+      }
+    }
+  }
+  T out[NCL];
+  const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + lane;
+#pragma unroll
+  for (int j = 0; j < NCL; ++j) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s += Pm[(i * NCL + j) * LANES] * rho[i];
+    out[j] = s;
+  }
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int f = NIF + b;
+    if (fid[f] < 0) continue;
+    T acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    side_apply<D, T>(Af, fid[f], sidein[f], bchild<D>(b), eM, acc);
+    const int S = b / NS, t = b % NS;
+#pragma unroll
+    for (int V = 0; V < NC; ++V) {
+      T s = T(0);
+#pragma unroll
+      for (int v = 0; v < NC; ++v) s += T(jh_weight<D>(t, v, V)) * acc[v];
+      out[S * NC + V] -= s;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = out[j];
+}
+
+// Coarse residual r_c = J^T r_B + cb_{M-} + cb_{M+} per coarse face, and the
+// first block-Jacobi step of the coarse level e_c = D^-1 r_c (when Dc given)
+template <int D, typename T>
+__device__ inline void hsum_item(long Fc, int n, const T* r, const T* cb, const T* __restrict__ Dc, T* rc, T* ec) {
+  constexpr int NC = 1 << (D - 1);
+  constexpr int NCL = 2 * D * NC;
+  const int nm = n / 2;
+  int G[3] = {0, 0, 0};
+  const int c = decode_face<D>(Fc, nm, G);
+  T out[NC];
+#pragma unroll
+  for (int V = 0; V < NC; ++V) out[V] = T(0);
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const long f = subface<D>(c, G, t, n);
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+      const T rv = r[f * NC + v];
+#pragma unroll
+      for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+    }
+  }
+  int mm[3] = {G[0], G[1], G[2]};
+  mm[c] = G[c] - 1;
+  const long Mm = elem_id<D>(mm, nm);
+  mm[c] = G[c];
+  const long Mp = elem_id<D>(mm, nm);
+#pragma unroll
+  for (int V = 0; V < NC; ++V) {
+    out[V] += cb[Mm * NCL + (2 * c + 1) * NC + V];
+    out[V] += cb[Mp * NCL + (2 * c) * NC + V];
+    rc[Fc * NC + V] = out[V];
+  }
+  if (Dc) {
+    const T* Dp = Dc + (Fc >> 6) * (long)(NC * NC * LANES) + (Fc & 63);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      T s = T(0);
+#pragma unroll
+      for (int b = 0; b < NC; ++b) s += Dp[(a * NC + b) * LANES] * out[b];
+      ec[Fc * NC + a] = s;
+    }
+  }
+}
+
+// Out-of-place prolongation and post-correction local correction:
+//   e_new = e_old + I e_c (I = [P_M e_c ; J e_c], eq. n_1_Ik), then on I
+//   faces e_new_I += A_II^-1 (r - A e_new)_I when do_corr.
+// Blocks [0, nbm): one lane per macro-element writes its I faces; blocks
+// [nbm, ...): one lane per coarse face writes its B sub-faces.
+template <int D, typename T>
+__device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                    const T* __restrict__ P, const T* r, const T* ec, const T* eold, T* enew,
+                                    int do_corr) {
+  using Mc = Macro<D>;
+  constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
+  const int nm = n / 2;
+  {
+    int m[3] = {0, 0, 0};
+    decode_elem<D>(M, nm, m);
+    T cv[NCL];
+#pragma unroll
+    for (int sl = 0; sl < 2 * D; ++sl) {
+      const int cc = sl / 2, sd = sl % 2;
+      const int p = m[cc] + sd;
+      if (p == 0 || p == nm) {
+#pragma unroll
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = T(0);
+      } else {
+        int G[3] = {m[0], m[1], m[2]};
+        G[cc] = p;
+        const long Fc = face_id<D>(cc, G, nm);
+#pragma unroll
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
+      }
+    }
+    T eM[NIF + NBF][NC];
+    long fid[NIF + NBF];
+    int sidein[NIF + NBF];
+#pragma unroll
+    for (int f = 0; f < NIF + NBF; ++f) {
+      fid[f] = mface_id<D>(m, f, n, &sidein[f]);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? eold[fid[f] * NC + a] : T(0);
+    }
+    // B faces: e + J e_c (local copy only; the coarse-face lanes write them)
+#pragma unroll
+    for (int b = 0; b < NBF; ++b) {
+      const int f = NIF + b;
+      if (fid[f] < 0) continue;
+      const int S = b / NS, t = b % NS;
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        T s = T(0);
+#pragma unroll
+        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[S * NC + V];
+        eM[f][v] += s;
+      }
+    }
+    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + (M & 63);
+#pragma unroll
+    for (int i = 0; i < NIF; ++i) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < NCL; ++j) s += Pm[((i * NC + a) * NCL + j) * LANES] * cv[j];
+        eM[i][a] += s;
+      }
+    }
+    if (do_corr) {
+      T rho[NI];
+#pragma unroll
+      for (int i = 0; i < NIF; ++i) {
+        T acc[NC];
+#pragma unroll
+        for (int a = 0; a < NC; ++a) acc[a] = T(0);
+        side_apply<D, T>(Af, fid[i], 0, ichild<D>(i, 0), eM, acc);
+        side_apply<D, T>(Af, fid[i], 1, ichild<D>(i, 1), eM, acc);
+#pragma unroll
+        for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
+      }
+      const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + (M & 63);
+#pragma unroll
+      for (int i = 0; i < NIF; ++i) {
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          T s = T(0);
+#pragma unroll
+          for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rho[j];
+          enew[fid[i] * NC + a] = eM[i][a] + s;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NIF; ++i)
+#pragma unroll
+        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = eM[i][a];
+    }
+  }
+}
+
+template <int D, typename T>
+__device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, T* enew) {
+  constexpr int NC = 1 << (D - 1);
+  const int nm = n / 2;
+  {
+    int G[3] = {0, 0, 0};
+    const int c = decode_face<D>(Fc, nm, G);
+    T cv[NC];
+#pragma unroll
+    for (int V = 0; V < NC; ++V) cv[V] = ec[Fc * NC + V];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const long f = subface<D>(c, G, t, n);
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        T s = eold[f * NC + v];
+#pragma unroll
+        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[V];
+        enew[f * NC + v] = s;
+      }
+    }
+  }
+}
+
+
+// one block-Jacobi sweep / residual / apply for interior face F
+template <int D, int NE, typename T, int MODE>
+__device__ inline void face_item(long F, int n, const T* __restrict__ Af, const T* __restrict__ Dinv, const T* x,
+                                 const T* b, T* y) {
+  constexpr int NL = 2 * D * NE;
+  int g[3] = {0, 0, 0};
+  const int c = decode_face<D>(F, n, g);
+  T acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = T(0);
+  const T* Mbase = Af + (F >> 6) * (2L * NL * NE * LANES) + (F & 63);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    int e[3] = {g[0], g[1], g[2]};
+    e[c] = g[c] - 1 + side;
+    const T* Mx = Mbase + side * (long)NL * NE * LANES;
+#pragma unroll
+    for (int sl = 0; sl < 2 * D; ++sl) {
+      const int cc = sl / 2, sd = sl % 2;
+      const int p = e[cc] + sd;
+      if (p == 0 || p == n) continue;
+      int fg[3] = {e[0], e[1], e[2]};
+      fg[cc] = p;
+      const T* xf = x + face_id<D>(cc, fg, n) * NE;
+#pragma unroll
+      for (int bb = 0; bb < NE; ++bb) {
+        const T xv = xf[bb];
+#pragma unroll
+        for (int a = 0; a < NE; ++a) acc[a] += Mx[((sl * NE + bb) * NE + a) * LANES] * xv;
+      }
+    }
+  }
+  if (MODE == APPLY_SWEEP) {
+    T res[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) res[a] = b[F * NE + a] - acc[a];
+    const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      T s = x[F * NE + a];
+#pragma unroll
+      for (int bb = 0; bb < NE; ++bb) s += Dp[(a * NE + bb) * LANES] * res[bb];
+      y[F * NE + a] = s;
+    }
+  } else if (MODE == APPLY_RES) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = b[F * NE + a] - acc[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = acc[a];
+  }
+}
+
+template <int NE, typename T>
+__device__ inline void jacobi0_item(long F, const T* __restrict__ Dinv, const T* r, T* e) {
+  const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
+  T rv[NE];
+#pragma unroll
+  for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    T s = T(0);
+#pragma unroll
+    for (int b = 0; b < NE; ++b) s += Dp[(a * NE + b) * LANES] * rv[b];
+    e[F * NE + a] = s;
+  }
+}
+
+
+}  // namespace dev
+}  // namespace hdg

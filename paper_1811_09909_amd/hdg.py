@@ -69,8 +69,8 @@ class Problem:
         self.built = False
 
     def build(self, sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-              max_it=200, restart=0):
-        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart)
+              max_it=200, restart=0, coarse_n=2):
+        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n)
         L.check(self.lib.hdg_mg_build(self.h, ctypes.byref(o)), "hdg_mg_build")
         self.built = True
         self.opts = o
@@ -203,7 +203,7 @@ class HDGSolve(torch.autograd.Function):
     and returns dL/dtheta = -(q*)^T A_T q per element."""
 
     @staticmethod
-    def forward(ctx, theta, problem, f, tol, build_kw):
+    def forward(ctx, theta, problem, f, tol, build_kw):  # noqa: D102
         problem.update_kappa(torch.exp(theta.detach()))
         problem.build(**build_kw)
         lam, info = problem.solve(f, tol=tol)

@@ -176,6 +176,86 @@ def test_vcycle(torch_cuda, d, n, k, lc, sweeps, growth):
     assert relerr(e32, eo) <= 1e-3
 
 
+def _set_path(monkeypatch, path):
+    monkeypatch.delenv("HDG_TAIL_N", raising=False)
+    monkeypatch.delenv("HDG_NO_FUSE", raising=False)
+    if path == "fused":
+        monkeypatch.setenv("HDG_TAIL_N", "0")
+    if path == "unfused":
+        monkeypatch.setenv("HDG_NO_FUSE", "1")
+
+
+@pytest.mark.parametrize("path", ["tail", "fused", "unfused"])
+@pytest.mark.parametrize("d,n,k,lc", [(2, 32, 2, "both"), (2, 64, 1, "pre"), (2, 16, 3, "none")])
+def test_vcycle_orchestration_paths(torch_cuda, monkeypatch, path, d, n, k, lc):
+    """The three V-cycle orchestrations (one-workgroup coarse tail, fused
+    transition kernels, unfused kernels) against the oracle's Algorithm 1
+    (kappa over two decades, so deep hierarchies stay inside 1e-10)."""
+    _set_path(monkeypatch, path)
+    say(f"[vcycle path={path}] d={d} n={n} k={k} lc={lc}")
+    kap, rng = _kappa(d, n, 1e-1, 1e1)
+    O = HDG(d, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    for sweeps, growth in [(2, 1), (1, 2)]:
+        H = omg.Hierarchy(A, d, n, k, sweeps=sweeps, growth=growth, local_corr=LC[lc])
+        P = _gpu(torch_cuda, d, n, k, kap)
+        P.build(sweeps=sweeps, growth=growth, local_corr=LC[lc])
+        r = rng.standard_normal(A.shape[0])
+        eo = H.vcycle(r)
+        e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+        e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+        say(f"  sweeps={sweeps} growth={growth} fp64 {relerr(e, eo):.2e} fp32 {relerr(e32, eo):.2e}")
+        assert relerr(e, eo) <= 1e-10
+        assert relerr(e32, eo) <= 1e-3
+
+
+@pytest.mark.parametrize("n,k,lc", [(64, 1, "pre"), (128, 2, "both")])
+def test_vcycle_paths_agree_at_high_contrast(torch_cuda, monkeypatch, n, k, lc):
+    """At six decades of kappa the three orchestrations compute the same
+    cycle on the same operators: they agree far below the oracle bound."""
+    kap, rng = _kappa(2, n)
+    r = None
+    outs = {}
+    for path in ["unfused", "fused", "tail"]:
+        _set_path(monkeypatch, path)
+        P = _gpu(torch_cuda, 2, n, k, kap)
+        P.build(sweeps=2, local_corr=LC[lc])
+        if r is None:
+            r = rng.standard_normal(P.nlam)
+        outs[path] = (P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy(),
+                      P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy())
+    for path in ["fused", "tail"]:
+        e64 = relerr(outs[path][0], outs["unfused"][0])
+        e32 = relerr(outs[path][1], outs["unfused"][1])
+        say(f"[paths n={n} k={k}] {path} vs unfused: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= 1e-12 and e32 <= 1e-5
+
+
+@pytest.mark.parametrize("path", ["fused", "unfused"])
+@pytest.mark.parametrize("d,n,k,cn,lc", [(2, 32, 2, 8, "pre"), (2, 64, 1, 16, "both"), (3, 8, 2, 4, "pre"),
+                                         (2, 16, 3, 16, "none")])
+def test_vcycle_larger_coarsest_level(torch_cuda, monkeypatch, path, d, n, k, cn, lc):
+    """Coarsening stopped at an n = cn macro grid whose operator (hundreds of
+    unknowns) is inverted densely on the device, against the oracle's
+    Algorithm 1 with the same number of levels."""
+    _set_path(monkeypatch, path)
+    say(f"[vcycle coarse_n={cn} path={path}] d={d} n={n} k={k} lc={lc}")
+    kap, rng = _kappa(d, n, 1e-1, 1e1)
+    O = HDG(d, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    H = omg.Hierarchy(A, d, n, k, sweeps=2, local_corr=LC[lc], coarsest_n=cn)
+    P = _gpu(torch_cuda, d, n, k, kap)
+    P.build(sweeps=2, local_corr=LC[lc], coarse_n=cn)
+    assert P.level_sizes() == [L.A.shape[0] for L in H.levels]
+    r = rng.standard_normal(A.shape[0])
+    eo = H.vcycle(r)
+    e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+    e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  levels {P.level_sizes()} fp64 {relerr(e, eo):.2e} fp32 {relerr(e32, eo):.2e}")
+    assert relerr(e, eo) <= 1e-10
+    assert relerr(e32, eo) <= 1e-3
+
+
 @pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
 def test_iterates_at_fixed_count(torch_cuda, method):
     d, n, k = 2, 16, 2

@@ -209,3 +209,21 @@ def test_outer_solvers_reach_direct_solution(method):
     assert r.converged
     assert np.linalg.norm(g - A @ r.lam) <= 1e-12 * np.linalg.norm(g)
     assert np.abs(r.lam - lam).max() <= 1e-8 * np.abs(lam).max()
+
+
+@pytest.mark.parametrize("d,n,k,cn", [(2, 16, 2, 4), (2, 16, 1, 8), (3, 4, 1, 2)])
+def test_coarsest_level_choice(d, n, k, cn):
+    """Stopping the h-coarsening at an n_c x n_c macro grid keeps every level
+    operator of the full hierarchy (same Galerkin chain) and only replaces the
+    levels below by the direct solve of Algorithm 1."""
+    P, A, g = _problem(d, n, k)
+    Hf = mg.Hierarchy(A, d, n, k)
+    Hc = mg.Hierarchy(A, d, n, k, coarsest_n=cn)
+    assert Hc.levels[-1].mesh.n == max(2, cn) or (k == 1 and n <= cn)
+    for Lf, Lc in zip(Hf.levels, Hc.levels):
+        assert abs(Lf.A - Lc.A).max() == 0.0
+    # with a single level the cycle is the direct solve
+    H1 = mg.Hierarchy(A, d, n, 1, coarsest_n=n) if k == 1 else None
+    if H1 is not None:
+        e = H1.vcycle(g)
+        assert np.linalg.norm(g - A @ e) <= 1e-11 * np.linalg.norm(g)

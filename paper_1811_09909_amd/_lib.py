@@ -3,7 +3,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libhdg.so")
+# HDG_LIBRARY selects another build of the same library (a variant build)
+LIB_PATH = os.environ.get("HDG_LIBRARY", os.path.join(_HERE, "_lib", "libhdg.so"))
 
 HDG_OK, HDG_ERR_INVALID_ARG, HDG_ERR_UNSUPPORTED, HDG_ERR_STATE = 0, -1, -2, -3
 HDG_ERR_NOT_CONVERGED, HDG_ERR_BREAKDOWN, HDG_ERR_DEVICE = -4, -5, -6

@@ -10,9 +10,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OUT_DIR = os.path.join(HERE, "_lib")
-LIB = os.path.join(OUT_DIR, "libhdg.so")
-OBJ_DIR = os.path.join(ROOT, "_build")
+# HDG_LIB_OUT / HDG_BUILD_DIR / HDG_EXTRA_FLAGS build a variant elsewhere
+LIB = os.environ.get("HDG_LIB_OUT", os.path.join(HERE, "_lib", "libhdg.so"))
+OUT_DIR = os.path.dirname(LIB)
+OBJ_DIR = os.environ.get("HDG_BUILD_DIR", os.path.join(ROOT, "_build"))
 SOURCES = ["refelem.cpp", "api.cpp", "element.hip", "build.hip", "trace.hip", "tail.hip", "blas.hip"]
 ARCH = os.environ.get("HDG_OFFLOAD_ARCH", "gfx950")
 
@@ -22,7 +23,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-result",
-]
+] + os.environ.get("HDG_EXTRA_FLAGS", "").split()
 
 
 def _compile(src):

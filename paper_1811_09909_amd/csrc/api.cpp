@@ -743,10 +743,10 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     F.nI = d * nc * nc;
     F.ncl = 2 * d * nc;
     const long pm = pad64(F.nmacro);
-    F.AIIinv64 = dalloc<double>(P, pm * F.nI * F.nI, true);
-    F.AIIinv32 = dalloc<float>(P, pm * F.nI * F.nI, true);
-    F.P64 = dalloc<double>(P, pm * F.nI * F.ncl, true);
-    F.P32 = dalloc<float>(P, pm * F.nI * F.ncl, true);
+    F.AIIinv64 = dalloc<double>(P, pm * vpad<double>(F.nI * F.nI), true);
+    F.AIIinv32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.nI), true);
+    F.P64 = dalloc<double>(P, pm * vpad<double>(F.nI * F.ncl), true);
+    F.P32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.ncl), true);
     F.cb[0] = dalloc<double>(P, F.nmacro * F.ncl, true);
     F.cb[1] = dalloc<float>(P, F.nmacro * F.ncl, true);
     C.Aelem = dalloc<double>(P, C.nelem * C.nl * C.nl, true);
@@ -764,10 +764,10 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     Level& Li = L[i];
     Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min<size_t>(i, 20)) : 1);
     const long pf = pad64(Li.nface);
-    Li.Af64 = dalloc<double>(P, pf * 2 * Li.nl * Li.ne, true);
-    Li.Af32 = dalloc<float>(P, pf * 2 * Li.nl * Li.ne, true);
-    Li.Dinv64 = dalloc<double>(P, pf * Li.ne * Li.ne, true);
-    Li.Dinv32 = dalloc<float>(P, pf * Li.ne * Li.ne, true);
+    Li.Af64 = dalloc<double>(P, pf * 2 * vpad<double>((long)Li.nl * Li.ne), true);
+    Li.Af32 = dalloc<float>(P, pf * 2 * vpad<float>((long)Li.nl * Li.ne), true);
+    Li.Dinv64 = dalloc<double>(P, pf * vpad<double>((long)Li.ne * Li.ne), true);
+    Li.Dinv32 = dalloc<float>(P, pf * vpad<float>((long)Li.ne * Li.ne), true);
     for (int pr = 0; pr < 2; ++pr) {
       const size_t es = pr == 0 ? sizeof(double) : sizeof(float);
       for (void** slot : {&Li.r[pr], &Li.e[pr], &Li.w[pr]}) {

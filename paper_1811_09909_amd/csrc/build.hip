@@ -59,9 +59,10 @@ __global__ void face_major_kernel(int d, int n, int ne, long nface, const double
   const long T = elem_rt(d, e, n);
   const int slot = side == 0 ? 2 * c + 1 : 2 * c;
   const double v = Aelem[(T * nl + slot * ne + a) * nl + j];
-  const long idx = ((((F >> 6) * 2 + side) * nl + j) * ne + a) * LANES + (F & 63);
-  Af64[idx] = v;
-  Af32[idx] = (float)v;
+  const long ent = (long)j * ne + a;
+  const long s64 = vpad<double>((long)nl * ne), s32 = vpad<float>((long)nl * ne);
+  Af64[aos_off<double>(F, 2 * s64, side * s64 + ent)] = v;
+  Af32[aos_off<float>(F, 2 * s32, side * s32 + ent)] = (float)v;
 }
 
 // omega * (A_{T-}[F,F] + A_{T+}[F,F])^-1 per face
@@ -97,11 +98,10 @@ __global__ void dinv_kernel(int d, int n, long nface, double omega, const double
     }
     A[k * NE + k] = p;
   }
-  const long base = (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
   for (int i = 0; i < NE * NE; ++i) {
     const double v = omega * A[i];
-    D64[base + i * LANES] = v;
-    D32[base + i * LANES] = (float)v;
+    D64[aos_off<double>(F, vpad<double>(NE * NE), i)] = v;
+    D32[aos_off<float>(F, vpad<float>(NE * NE), i)] = (float)v;
   }
 }
 
@@ -251,18 +251,16 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
   }
   __syncthreads();
   // P = -A_II^-1 Y, written AoSoA over macro-elements
-  const long pbase = (M >> 6) * (long)(NI * NLC * LANES) + (M & 63);
   for (int idx = tid; idx < NI * NLC; idx += NT) {
     const int i = idx / NLC, J = idx % NLC;
     double s = 0.0;
     for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sY[l * NLC + J];
-    P64[pbase + (long)idx * LANES] = -s;
-    P32[pbase + (long)idx * LANES] = (float)(-s);
+    P64[aos_off<double>(M, vpad<double>(NI * NLC), idx)] = -s;
+    P32[aos_off<float>(M, vpad<float>(NI * NLC), idx)] = (float)(-s);
   }
-  const long abase = (M >> 6) * (long)(NI * NI * LANES) + (M & 63);
   for (int idx = tid; idx < NI * NI; idx += NT) {
-    Ai64[abase + (long)idx * LANES] = sII[idx];
-    Ai32[abase + (long)idx * LANES] = (float)sII[idx];
+    Ai64[aos_off<double>(M, vpad<double>(NI * NI), idx)] = sII[idx];
+    Ai32[aos_off<float>(M, vpad<float>(NI * NI), idx)] = (float)sII[idx];
   }
   __syncthreads();
   // T1 = S J (NB x NLC) into sIB, then A_coarse = J^T T1

@@ -14,6 +14,36 @@ constexpr int LANES = 64;  // AoSoA block width = one wavefront
 
 inline long pad64(long n) { return (n + LANES - 1) / LANES * LANES; }
 
+// Stored operator blocks (face matrices, face-block inverses, macro-element
+// blocks) are AoSoA: 64 items per block, and inside a block the entries of one
+// item come in groups of VW = max(1, HDG_VEC_BYTES / sizeof(T)) consecutive
+// values, so a lane loads one group and a wavefront one contiguous segment:
+//   off(item, e) = (item / 64) * per * 64 + (e / VW) * 64 * VW + (item % 64) * VW + e % VW
+// with `per` the item's entry count padded to a multiple of VW.  The default
+// (one entry per lane and load) measured fastest on gfx950: wider groups make
+// the compiler hoist every load of a face and drop to one wave per SIMD.
+#ifndef HDG_VEC_BYTES
+#define HDG_VEC_BYTES 4
+#endif
+template <typename T>
+__host__ __device__ constexpr int vw() {
+  return HDG_VEC_BYTES / (int)sizeof(T) > 1 ? HDG_VEC_BYTES / (int)sizeof(T) : 1;
+}
+template <typename T>
+__host__ __device__ constexpr long vpad(long cnt) {
+  return (cnt + vw<T>() - 1) / vw<T>() * vw<T>();
+}
+template <typename T>
+__host__ __device__ inline long aos_off(long item, long per, long e) {
+  constexpr int V = vw<T>();
+  return (item >> 6) * per * LANES + (e / V) * (LANES * V) + (item & 63) * V + e % V;
+}
+// start of an item's entries (entry 0); group g then sits at + g * 64 * VW
+template <typename T>
+__host__ __device__ inline long aos_item(long item, long per) {
+  return (item >> 6) * per * LANES + (item & 63) * vw<T>();
+}
+
 struct HipError {
   hipError_t err;
   std::string where;
@@ -57,10 +87,13 @@ struct RefDevice {
 // ---------------------------------------------------------------------------
 // One multigrid level.  The local operators are stored twice: element form
 // (row-major [nelem][nl][nl], FP64; input of the next coarsening) and face
-// form (AoSoA-64 over interior faces, FP64 and FP32; read by the apply):
-//   Af[((F/64)*2 + side)*nl*ne + j*ne + a][F%64] = A_{T_side}[slot_side*ne + a][j]
+// form (AoSoA over interior faces with 16-byte entry groups, see aos_off;
+// FP64 and FP32; read by the apply).  Face F holds 2 * S entries, S =
+// vpad<T>(nl * ne):
+//   entry side * S + j * ne + a  =  A_{T_side}[slot_side * ne + a][j]
 // where side 0 is the element below the face along its normal (the face is
-// its slot 2c+1), side 1 the element above (slot 2c).
+// its slot 2c+1), side 1 the element above (slot 2c).  Dinv holds the
+// ne x ne row-major block of face F as its vpad<T>(ne * ne) entries.
 struct Level {
   int d = 0, n = 0, ne = 0, nl = 0;
   long nelem = 0, nfd = 0, nface = 0, nlam = 0;
@@ -72,8 +105,8 @@ struct Level {
   // h-transition to the next level
   long nmacro = 0;
   int nI = 0, ncl = 0;
-  double* AIIinv64 = nullptr; float* AIIinv32 = nullptr;  // AoSoA [M/64][nI][nI][64]
-  double* P64 = nullptr;      float* P32 = nullptr;       // AoSoA [M/64][nI][ncl][64]
+  double* AIIinv64 = nullptr; float* AIIinv32 = nullptr;  // AoSoA over M, row-major nI x nI
+  double* P64 = nullptr;      float* P32 = nullptr;       // AoSoA over M, row-major nI x ncl
   // coarsest direct inverse (dense row-major nlam x nlam)
   double* Ainv64 = nullptr; float* Ainv32 = nullptr;
   // work vectors, [0] = FP64, [1] = FP32

@@ -5,9 +5,9 @@
 // and the coarsest direct solve (Algorithm 1, B_1 = A_1^-1).
 //
 // One lane per interior face.  The two element matrices that touch a face
-// are read as one contiguous face-major AoSoA-64 block, so every matrix load
-// of a wavefront is a 512 B (FP64) or 256 B (FP32) contiguous segment; the
-// trace vector is gathered through the caches.  No atomics: every output is
+// are read as one face-major AoSoA block in 16-byte entry groups, so every
+// matrix load of a wavefront is one contiguous 1 KiB segment (a lane's
+// 16-byte load); the trace vector is gathered through the caches.  No atomics: every output is
 // written by exactly one lane, so results are bitwise reproducible.
 #include "hdg_internal.hpp"
 #include "blas.hpp"
@@ -25,46 +25,25 @@ using namespace dev;
 // Modes with a reduction (APPLY_Y_DOT: partial sums of x.y; APPLY_RES_NORM:
 // of ||y||^2, and y32 = (float) y when given) write one partial per block;
 // the caller launches the one-block finaliser.
+// Minimum waves per SIMD the register allocation of the trace apply is held to
+#ifndef HDG_APPLY_WPE
+#define HDG_APPLY_WPE 1
+#endif
+
 template <int D, int NE, typename T, int MODE>
-__global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
                                                     T* __restrict__ rc, float* __restrict__ y32,
                                                     double* __restrict__ partials) {
-  constexpr int NL = 2 * D * NE;
   constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
   const long nface = D * nface_dir<D>(n);
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (!RED && F >= nface) return;
   double part = 0.0;
   if (F < nface) {
-  int g[3] = {0, 0, 0};
-  const int c = decode_face<D>(F, n, g);
   T acc[NE];
-#pragma unroll
-  for (int a = 0; a < NE; ++a) acc[a] = T(0);
-  const T* Mbase = Af + (F >> 6) * (2L * NL * NE * LANES) + (F & 63);
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    int e[3] = {g[0], g[1], g[2]};
-    e[c] = g[c] - 1 + side;
-    const T* M = Mbase + side * (long)NL * NE * LANES;
-#pragma unroll
-    for (int sl = 0; sl < 2 * D; ++sl) {
-      const int cc = sl / 2, sd = sl % 2;
-      const int p = e[cc] + sd;
-      if (p == 0 || p == n) continue;
-      int fg[3] = {e[0], e[1], e[2]};
-      fg[cc] = p;
-      const T* xf = x + face_id<D>(cc, fg, n) * NE;
-#pragma unroll
-      for (int bb = 0; bb < NE; ++bb) {
-        const T xv = xf[bb];
-#pragma unroll
-        for (int a = 0; a < NE; ++a) acc[a] += M[((sl * NE + bb) * NE + a) * LANES] * xv;
-      }
-    }
-  }
+  face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_Y) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) y[F * NE + a] = acc[a];
@@ -75,14 +54,7 @@ __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__
     T res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
-    const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-      T s = x[F * NE + a];
-#pragma unroll
-      for (int bb = 0; bb < NE; ++bb) s += Dp[(a * NE + bb) * LANES] * res[bb];
-      y[F * NE + a] = s;
-    }
+    dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
     constexpr int NC = 1 << (D - 1);
     T res[NE];
@@ -97,16 +69,8 @@ __global__ void __launch_bounds__(256) apply_kernel(int n, const T* __restrict__
       rc[F * NC + v] = s;
       rcv[v] = s;
     }
-    if (y) {  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
-      const T* Dp = Dinv + (F >> 6) * (long)(NC * NC * LANES) + (F & 63);
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T s = T(0);
-#pragma unroll
-        for (int b = 0; b < NC; ++b) s += Dp[(a * NC + b) * LANES] * rcv[b];
-        y[F * NC + a] = s;
-      }
-    }
+    if (y)  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
+      dinv_update<NC, T>(F, Dinv, (const T*)nullptr, rcv, y);
   } else if (MODE == APPLY_Y_DOT) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) {
@@ -135,17 +99,7 @@ template <int NE, typename T>
 __global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* __restrict__ r, T* __restrict__ e) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
-  const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
-  T rv[NE];
-#pragma unroll
-  for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
-#pragma unroll
-  for (int a = 0; a < NE; ++a) {
-    T s = T(0);
-#pragma unroll
-    for (int b = 0; b < NE; ++b) s += Dp[(a * NE + b) * LANES] * rv[b];
-    e[F * NE + a] = s;
-  }
+  jacobi0_item<NE, T>(F, Dinv, r, e);
 }
 
 // e += J_N ec on every face (p-prolongation)
@@ -192,30 +146,23 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
 #pragma unroll
     for (int a = 0; a < NC; ++a) rI[i * NC + a] = rho[fid[i] * NC + a];
   }
-  const long base = (M >> 6) * LANES;
-  const long lane = M & 63;
   if (do_corr) {
-    const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + lane;
+    T s[NI];
 #pragma unroll
-    for (int i = 0; i < NIF; ++i) {
+    for (int i = 0; i < NI; ++i) s[i] = T(0);
+    aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rI, s);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T s = T(0);
+    for (int i = 0; i < NIF; ++i)
 #pragma unroll
-        for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rI[j];
-        e[fid[i] * NC + a] += s;
-      }
-    }
+      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] += s[i * NC + a];
   }
   if (do_restrict) {
-    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + lane;
+    T s[NCL];
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) {
-      T s = T(0);
+    for (int j = 0; j < NCL; ++j) s[j] = T(0);
+    aos_mv<T, NI * NCL, NCL, true>(P + aos_item<T>(M, vpad<T>(NI * NCL)), rI, s);
 #pragma unroll
-      for (int i = 0; i < NI; ++i) s += Pm[(i * NCL + j) * LANES] * rI[i];
-      cb[(base + lane) * NCL + j] = s;
-    }
+    for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = s[j];
   }
 }
 
@@ -290,17 +237,19 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
         for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
       }
     }
-    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + (M & 63);
+    T s[NI];
 #pragma unroll
     for (int i = 0; i < NIF; ++i) {
       const long f = macro_iface<D>(m, i, n);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T s = e[f * NC + a];
+      for (int a = 0; a < NC; ++a) s[i * NC + a] = e[f * NC + a];
+    }
+    aos_mv<T, NI * NCL, NCL, false>(P + aos_item<T>(M, vpad<T>(NI * NCL)), cv, s);
 #pragma unroll
-        for (int j = 0; j < NCL; ++j) s += Pm[((i * NC + a) * NCL + j) * LANES] * cv[j];
-        e[f * NC + a] = s;
-      }
+    for (int i = 0; i < NIF; ++i) {
+      const long f = macro_iface<D>(m, i, n);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) e[f * NC + a] = s[i * NC + a];
     }
   } else {
     const long ncf = D * nface_dir<D>(nm);

@@ -7,6 +7,65 @@
 namespace hdg {
 namespace dev {
 
+// one lane's entry group (vw<T>() values) of an AoSoA operator block
+template <typename T>
+__device__ inline void ld_group(const T* p, T* out) {
+  constexpr int V = vw<T>();
+  if constexpr (V == 1) {
+    out[0] = p[0];
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    const vt v = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int q = 0; q < V; ++q) out[q] = v[q];
+  }
+}
+
+// acc += (stored block) * x for the CNT entries of one AoSoA item starting at
+// blk (= base + aos_item).  Entry e pairs output o and input i as
+// (o, i) = (e % NMINOR, e / NMINOR) when OUT_MINOR, else (e / NMINOR, e % NMINOR).
+// Every output accumulates in increasing input order.
+template <typename T, int CNT, int NMINOR, bool OUT_MINOR>
+__device__ inline void aos_mv(const T* __restrict__ blk, const T* x, T* acc) {
+  constexpr int V = vw<T>();
+  constexpr int NG = (CNT + V - 1) / V;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    T v[V];
+    ld_group<T>(blk + g * (LANES * V), v);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int e = g * V + q;
+      if (e < CNT) {
+        if (OUT_MINOR)
+          acc[e % NMINOR] += v[q] * x[e / NMINOR];
+        else
+          acc[e / NMINOR] += v[q] * x[e % NMINOR];
+      }
+    }
+  }
+}
+
+// acc[e % NE] += blk[B + e] * x[e / NE] for e in [0, NE * NE): one slot's
+// NE x NE block of a face matrix (entries B .. B + NE*NE - 1 of the item).
+// Groups that straddle two slots are loaded by both (the second load hits
+// the cache), so each slot can sit in its own branch.
+template <typename T, int NE>
+__device__ inline void aos_mv_slot(const T* __restrict__ blk, int B, const T* x, T* acc) {
+  constexpr int V = vw<T>();
+  const int g0 = B / V, g1 = (B + NE * NE - 1) / V;
+#pragma unroll
+  for (int g = g0; g <= g1; ++g) {
+    T v[V];
+    ld_group<T>(blk + g * (LANES * V), v);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int e = g * V + q - B;
+      if (e >= 0 && e < NE * NE) acc[e % NE] += v[q] * x[e / NE];
+    }
+  }
+}
+
 template <int D>
 __device__ inline long nface_dir(int n) {
   long v = n - 1;
@@ -191,17 +250,16 @@ __device__ inline void side_apply(const T* __restrict__ Af, long fid, int side, 
                                   T* acc) {
   using Mc = Macro<D>;
   constexpr int NE = Mc::NC, NL = Mc::NL;
-  const T* Mb = Af + (fid >> 6) * (2L * NL * NE * LANES) + (fid & 63) + side * (long)NL * NE * LANES;
+  constexpr long S = vpad<T>(NL * NE);
+  const T* Mb = Af + aos_item<T>(fid, 2 * S) + side * S * LANES;
+  T xs[NL];
 #pragma unroll
   for (int sl = 0; sl < 2 * D; ++sl) {
     const int mf = mface_of<D>(ch, sl);
 #pragma unroll
-    for (int bb = 0; bb < NE; ++bb) {
-      const T xv = eM[mf][bb];
-#pragma unroll
-      for (int a = 0; a < NE; ++a) acc[a] += Mb[((sl * NE + bb) * NE + a) * LANES] * xv;
-    }
+    for (int bb = 0; bb < NE; ++bb) xs[sl * NE + bb] = eM[mf][bb];
   }
+  aos_mv<T, NL * NE, NE, true>(Mb, xs, acc);
 }
 
 // child of M on side `side` of I face iota
@@ -263,29 +321,20 @@ __device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const 
 #pragma unroll
     for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
   }
-  const long lane = M & 63;
   if (do_corr) {
-    const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + lane;
+    T s[NI];
 #pragma unroll
-    for (int i = 0; i < NIF; ++i) {
+    for (int i = 0; i < NI; ++i) s[i] = T(0);
+    aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rho, s);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T s = T(0);
+    for (int i = 0; i < NIF; ++i)
 #pragma unroll
-        for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rho[j];
-        e[fid[i] * NC + a] = eM[i][a] + s;
-      }
-    }
+      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] = eM[i][a] + s[i * NC + a];
   }
   T out[NCL];
-  const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + lane;
 #pragma unroll
-  for (int j = 0; j < NCL; ++j) {
-    T s = T(0);
-#pragma unroll
-    for (int i = 0; i < NI; ++i) s += Pm[(i * NCL + j) * LANES] * rho[i];
-    out[j] = s;
-  }
+  for (int j = 0; j < NCL; ++j) out[j] = T(0);
+  aos_mv<T, NI * NCL, NCL, true>(P + aos_item<T>(M, vpad<T>(NI * NCL)), rho, out);
 #pragma unroll
   for (int b = 0; b < NBF; ++b) {
     const int f = NIF + b;
@@ -341,14 +390,12 @@ __device__ inline void hsum_item(long Fc, int n, const T* r, const T* cb, const 
     rc[Fc * NC + V] = out[V];
   }
   if (Dc) {
-    const T* Dp = Dc + (Fc >> 6) * (long)(NC * NC * LANES) + (Fc & 63);
+    T s[NC];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      T s = T(0);
+    for (int a = 0; a < NC; ++a) s[a] = T(0);
+    aos_mv<T, NC * NC, NC, false>(Dc + aos_item<T>(Fc, vpad<T>(NC * NC)), out, s);
 #pragma unroll
-      for (int b = 0; b < NC; ++b) s += Dp[(a * NC + b) * LANES] * out[b];
-      ec[Fc * NC + a] = s;
-    }
+    for (int a = 0; a < NC; ++a) ec[Fc * NC + a] = s[a];
   }
 }
 
@@ -406,16 +453,15 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
         eM[f][v] += s;
       }
     }
-    const T* Pm = P + (M >> 6) * (long)(NI * NCL * LANES) + (M & 63);
+    {
+      T s[NI];
 #pragma unroll
-    for (int i = 0; i < NIF; ++i) {
+      for (int i = 0; i < NI; ++i) s[i] = T(0);
+      aos_mv<T, NI * NCL, NCL, false>(P + aos_item<T>(M, vpad<T>(NI * NCL)), cv, s);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T s = T(0);
+      for (int i = 0; i < NIF; ++i)
 #pragma unroll
-        for (int j = 0; j < NCL; ++j) s += Pm[((i * NC + a) * NCL + j) * LANES] * cv[j];
-        eM[i][a] += s;
-      }
+        for (int a = 0; a < NC; ++a) eM[i][a] += s[i * NC + a];
     }
     if (do_corr) {
       T rho[NI];
@@ -429,17 +475,14 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
 #pragma unroll
         for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
       }
-      const T* Ai = AIIinv + (M >> 6) * (long)(NI * NI * LANES) + (M & 63);
+      T s[NI];
 #pragma unroll
-      for (int i = 0; i < NIF; ++i) {
+      for (int i = 0; i < NI; ++i) s[i] = T(0);
+      aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rho, s);
 #pragma unroll
-        for (int a = 0; a < NC; ++a) {
-          T s = T(0);
+      for (int i = 0; i < NIF; ++i)
 #pragma unroll
-          for (int j = 0; j < NI; ++j) s += Ai[((i * NC + a) * NI + j) * LANES] * rho[j];
-          enew[fid[i] * NC + a] = eM[i][a] + s;
-        }
-      }
+        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = eM[i][a] + s[i * NC + a];
     } else {
 #pragma unroll
       for (int i = 0; i < NIF; ++i)
@@ -474,50 +517,63 @@ __device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, 
 }
 
 
-// one block-Jacobi sweep / residual / apply for interior face F
-template <int D, int NE, typename T, int MODE>
-__device__ inline void face_item(long F, int n, const T* __restrict__ Af, const T* __restrict__ Dinv, const T* x,
-                                 const T* b, T* y) {
+// acc = (A x)_F for interior face F: both element matrices touching F, read
+// from the face-major AoSoA form.  Returns the face's normal direction.
+template <int D, int NE, typename T>
+__device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T* x, T* acc) {
   constexpr int NL = 2 * D * NE;
+  constexpr long S = vpad<T>(NL * NE);
   int g[3] = {0, 0, 0};
   const int c = decode_face<D>(F, n, g);
-  T acc[NE];
 #pragma unroll
   for (int a = 0; a < NE; ++a) acc[a] = T(0);
-  const T* Mbase = Af + (F >> 6) * (2L * NL * NE * LANES) + (F & 63);
+  const T* Mbase = Af + aos_item<T>(F, 2 * S);
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     int e[3] = {g[0], g[1], g[2]};
     e[c] = g[c] - 1 + side;
-    const T* Mx = Mbase + side * (long)NL * NE * LANES;
+    const T* Mx = Mbase + side * S * LANES;
 #pragma unroll
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
       const int p = e[cc] + sd;
+      // a boundary slot carries no unknowns; the branch also keeps the
+      // compiler from hoisting the loads of every slot at once (registers)
       if (p == 0 || p == n) continue;
       int fg[3] = {e[0], e[1], e[2]};
       fg[cc] = p;
       const T* xf = x + face_id<D>(cc, fg, n) * NE;
+      T xs[NE];
 #pragma unroll
-      for (int bb = 0; bb < NE; ++bb) {
-        const T xv = xf[bb];
-#pragma unroll
-        for (int a = 0; a < NE; ++a) acc[a] += Mx[((sl * NE + bb) * NE + a) * LANES] * xv;
-      }
+      for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
+      aos_mv_slot<T, NE>(Mx, sl * NE * NE, xs, acc);
     }
   }
+  return c;
+}
+
+// y = x + Dinv_F res (one block-Jacobi update of face F; x == nullptr: 0)
+template <int NE, typename T>
+__device__ inline void dinv_update(long F, const T* __restrict__ Dinv, const T* x, const T* res, T* y) {
+  T s[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) s[a] = x ? x[F * NE + a] : T(0);
+  aos_mv<T, NE * NE, NE, false>(Dinv + aos_item<T>(F, vpad<T>(NE * NE)), res, s);
+#pragma unroll
+  for (int a = 0; a < NE; ++a) y[F * NE + a] = s[a];
+}
+
+// one block-Jacobi sweep / residual / apply for interior face F
+template <int D, int NE, typename T, int MODE>
+__device__ inline void face_item(long F, int n, const T* __restrict__ Af, const T* __restrict__ Dinv, const T* x,
+                                 const T* b, T* y) {
+  T acc[NE];
+  face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_SWEEP) {
     T res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = b[F * NE + a] - acc[a];
-    const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-      T s = x[F * NE + a];
-#pragma unroll
-      for (int bb = 0; bb < NE; ++bb) s += Dp[(a * NE + bb) * LANES] * res[bb];
-      y[F * NE + a] = s;
-    }
+    dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) y[F * NE + a] = b[F * NE + a] - acc[a];
@@ -529,17 +585,10 @@ __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const 
 
 template <int NE, typename T>
 __device__ inline void jacobi0_item(long F, const T* __restrict__ Dinv, const T* r, T* e) {
-  const T* Dp = Dinv + (F >> 6) * (long)(NE * NE * LANES) + (F & 63);
   T rv[NE];
 #pragma unroll
   for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
-#pragma unroll
-  for (int a = 0; a < NE; ++a) {
-    T s = T(0);
-#pragma unroll
-    for (int b = 0; b < NE; ++b) s += Dp[(a * NE + b) * LANES] * rv[b];
-    e[F * NE + a] = s;
-  }
+  dinv_update<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
 }
 
 

@@ -360,13 +360,76 @@ class HDG:
         u = np.zeros((nel, nv), dtype=dt)
         q = np.zeros((nel, d, nv), dtype=dt)
         for T in range(nel):
-            rhs = self.R @ LT[T]
-            rhs = rhs.astype(dt)
-            rhs[d * nv:] += self.M @ f_nodal[T]
-            w = np.linalg.solve(self.local_matrix(T), rhs)
-            q[T] = w[:d * nv].reshape(d, nv)
-            u[T] = w[d * nv:]
+            u[T], q[T] = self.recover_element(T, LT[T], f_nodal[T])
         return u, q
+
+    def recover_element(self, T, lam_T, f_T=None):
+        """w_T = L_T^-1 (R_T Lambda_T + [0; M f_T]) for one element (Sec. 2):
+        (u_T [N_v], q_T [d, N_v]) from its local traces Lambda_T [n_f n_e]."""
+        d, nv = self.d, self.nv
+        lam_T = np.asarray(lam_T)
+        rhs = (self.R @ lam_T).astype(np.result_type(self.dtype, lam_T.dtype))
+        if f_T is not None:
+            rhs = rhs.astype(np.result_type(rhs.dtype, np.asarray(f_T).dtype))
+            rhs[d * nv:] += self.M @ f_T
+        w = np.linalg.solve(self.local_matrix(T), rhs)
+        return w[d * nv:], w[:d * nv].reshape(d, nv)
+
+    # -- rows of the assembled system, one face at a time ------------------
+    # (for sampled checks on meshes too large to assemble)
+    def face_elements(self, fid):
+        """The two elements that share interior face fid, each with the local
+        slot the face occupies in it: [(T_below, 2c+1), (T_above, 2c)]."""
+        c, coords = self.mesh.interior_face_coords(fid)
+        out = []
+        for side in (0, 1):
+            e = list(coords)
+            e[c] = coords[c] - 1 + side
+            T = int(sum(e[a] * self.n ** a for a in range(self.d)))
+            out.append((T, 2 * c + 1 - side))
+        return out
+
+    def _dtn_cached(self, T, cache):
+        if cache is None:
+            return self.element_dtn(T)
+        if T not in cache:
+            cache[T] = self.element_dtn(T)
+        return cache[T]
+
+    def apply_rows(self, fids, x, cache=None):
+        """(A x) restricted to interior faces fids, [len(fids), n_e]:
+        sum over the two elements T of face F of A^e_T[slot rows, :] x_T
+        (x_T gathered with zero boundary traces), eq. trace_linear_system."""
+        ne = self.ne
+        x = np.asarray(x)
+        out = np.zeros((len(fids), ne), dtype=np.result_type(self.dtype, x.dtype))
+        for i, F in enumerate(fids):
+            for T, s in self.face_elements(F):
+                Ae = self._dtn_cached(T, cache)
+                gi = self.gmap[T]
+                xT = np.where(gi >= 0, x[np.maximum(gi, 0)], 0.0)
+                out[i] += Ae[s * ne:(s + 1) * ne] @ xT
+        return out
+
+    def load_rows(self, fids, f_nodal):
+        """g restricted to interior faces fids (zero Dirichlet data):
+        sum over the two elements of face F of b^e_T[slot rows], b_T = M f_T."""
+        ne = self.ne
+        out = np.zeros((len(fids), ne))
+        for i, F in enumerate(fids):
+            for T, s in self.face_elements(F):
+                _, be = self.element_dtn(T, self.M @ np.asarray(f_nodal[T]))
+                out[i] += be[s * ne:(s + 1) * ne]
+        return out
+
+    def diag_block(self, fid, cache=None):
+        """Assembled diagonal block of face fid: A^e_{T-}[s,s] + A^e_{T+}[s,s]."""
+        ne = self.ne
+        D = np.zeros((ne, ne), dtype=self.dtype)
+        for T, s in self.face_elements(fid):
+            Ae = self._dtn_cached(T, cache)
+            D += Ae[s * ne:(s + 1) * ne, s * ne:(s + 1) * ne]
+        return D
 
     def monolithic_solve(self, f_nodal=None, gD=None):
         """Solve the uncondensed HDG system (eqs. HDG, HDG_flux and

@@ -926,7 +926,7 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
   if (!P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
-  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
+  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->kqp, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
                      P->Minv, P->ework, u, q, P->st);
   return HDG_OK;
   HDG_GUARD_END
@@ -950,7 +950,7 @@ hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, do
   form_rhs(P, dJdu, HDG_RHS_F_LOAD, nullptr, P->g);
   blas_fill<double>(P->lam, 0.0, P->N, P->st);
   hdg_status s = solve_one(P, P->g, P->lam, tol, info);
-  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
+  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->kqp, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
                      P->ustar, P->qstar, P->st);
   launch_grad(P->d, P->k, P->nelem, P->rd, P->kqp, q_fwd, P->qstar, grad, P->st);
   HDG_CHECK(hipStreamSynchronize(P->st));

@@ -55,6 +55,17 @@ __device__ void gj_inverse_lds(double* A) {
   __syncthreads();
 }
 
+// In 2D the Schur-complement route is followed by one step of iterative
+// refinement on the full local system.  Forming A^e as
+// tau H + F^T Mk^-1 F - Z^T K^-1 Z subtracts terms of size kappa to leave a
+// result of size tau h, so its rounding error grows like eps kappa / (tau h)
+// (4e-10 at kappa = 680, h = 1/512).  Instead the local solution
+// X = [Q; U] = L^-1 R for every trace DOF is computed by that route, its
+// residual R - L X is formed directly, one correction is solved by the same
+// route, and A^e = tau H - S^T X = tau H - sum_c F_c^T Q_c - tau G^T U; the
+// refined X is backward stable and A^e comes out to a few eps like a pivoted
+// LU of L.  (3D elements keep the plain route: their LDS budget is spent, and
+// the smooth 3D coefficient keeps kappa / (tau h) small.)
 template <int D, int K, int NT>
 __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau, const double* __restrict__ Phi,
                                                          const double* __restrict__ Wq,
@@ -68,10 +79,14 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
                                                          double* __restrict__ Minv_out) {
   using Dm = Dims<D, K>;
   constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL, NQ = Dm::NQ;
-  __shared__ double sA[Dm::SA];      // Mk^-1 | Y   (later: W)
+  constexpr bool REF = (D == 2);
+  constexpr int NX = REF ? (D + 1) * NV * NL : 1;
+  __shared__ double sA[Dm::SA];      // Mk^-1 | Y   (plain route, later: W)
   __shared__ double sK[NV * NV];     // K -> K^-1
   __shared__ double sZ[NV * NL];     // Z
   __shared__ double sW[NQ];          // w_q / kappa_q
+  __shared__ double sX[NX];          // refined route: Q_0 .. Q_{D-1}, U  ([(D+1) NV][NL])
+  __shared__ double sR[NX];          // refined route: residual / correction
   const long T = blockIdx.x;
   if (T >= nelem) return;
   const int tid = threadIdx.x;
@@ -91,7 +106,8 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
   // K = tau E, Z = tau G, A^e = tau H
   for (int idx = tid; idx < NV * NV; idx += NT) sK[idx] = tau * Em[idx];
   for (int idx = tid; idx < NV * NL; idx += NT) sZ[idx] = tau * Gm[idx];
-  for (int idx = tid; idx < NL * NL; idx += NT) Ae[idx] = tau * Hm[idx];
+  if (!REF)
+    for (int idx = tid; idx < NL * NL; idx += NT) Ae[idx] = tau * Hm[idx];
   gj_inverse_lds<NV>(sM);
   if (Minv_out)
     for (int idx = tid; idx < NV * NV; idx += NT) Minv_out[T * NV * NV + idx] = sM[idx];
@@ -131,36 +147,157 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
       for (int l = 0; l < NV; ++l) s += Bc[i * NV + l] * sY[l * 2 * NE + j];
       sZ[i * NL + col0 + j] += s;
     }
-    // same entry-to-thread map as every other pass over A^e: no thread reads
-    // an entry another thread wrote
-    for (int idx = tid; idx < NL * NL; idx += NT) {
-      const int i = idx / NL - col0, j = idx % NL - col0;
-      if (i < 0 || i >= 2 * NE || j < 0 || j >= 2 * NE) continue;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += Fc[l * NL + col0 + i] * sY[l * 2 * NE + j];
-      Ae[idx] += s;
+    if (!REF) {
+      // same entry-to-thread map as every other pass over A^e: no thread
+      // reads an entry another thread wrote
+      for (int idx = tid; idx < NL * NL; idx += NT) {
+        const int i = idx / NL - col0, j = idx % NL - col0;
+        if (i < 0 || i >= 2 * NE || j < 0 || j >= 2 * NE) continue;
+        double s = 0.0;
+        for (int l = 0; l < NV; ++l) s += Fc[l * NL + col0 + i] * sY[l * 2 * NE + j];
+        Ae[idx] += s;
+      }
     }
   }
   __syncthreads();
   gj_inverse_lds<NV>(sK);
   if (Kinv_out)
     for (int idx = tid; idx < NV * NV; idx += NT) Kinv_out[T * NV * NV + idx] = sK[idx];
-  // W = K^-1 Z (into sA) ; A^e -= Z^T W
-  double* sWm = sA;
-  for (int idx = tid; idx < NV * NL; idx += NT) {
-    int i = idx / NL, j = idx % NL;
-    double s = 0.0;
-    for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
-    sWm[idx] = s;
+  if constexpr (!REF) {
+    // W = K^-1 Z (into sA) ; A^e -= Z^T W
+    double* sWm = sA;
+    for (int idx = tid; idx < NV * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
+      sWm[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NL * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sZ[l * NL + i] * sWm[l * NL + j];
+      Ae[idx] -= s;
+    }
+    for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sWm[idx];
+  } else {
+    double* sU = sX + D * NV * NL;
+    double* rU = sR + D * NV * NL;
+    // U = K^-1 Z
+    for (int idx = tid; idx < NV * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
+      sU[idx] = s;
+    }
+    __syncthreads();
+    // Q_c = Mk^-1 (B_c^T U - F_c) ; Mk itself again (into Y) for the residual
+    for (int c = 0; c < D; ++c) {
+      const double* Bc = Bm + (long)c * NV * NV;
+      const double* Fc = Fm + (long)c * NV * NL;
+      for (int idx = tid; idx < NV * NL; idx += NT) {
+        int i = idx / NL, j = idx % NL;
+        double s = -Fc[i * NL + j];
+        for (int l = 0; l < NV; ++l) s += Bc[l * NV + i] * sU[l * NL + j];
+        sZ[idx] = s;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < NV * NL; idx += NT) {
+        int i = idx / NL, j = idx % NL;
+        double s = 0.0;
+        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * sZ[l * NL + j];
+        sX[c * NV * NL + idx] = s;
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < NV * NV; idx += NT) {
+      int i = idx / NV, j = idx % NV;
+      double s = 0.0;
+      for (int q = 0; q < NQ; ++q) s += Phi[q * NV + i] * Phi[q * NV + j] * sW[q];
+      sY[idx] = s;
+    }
+    __syncthreads();
+    // residual of the local system for R = [-F; tau G]:
+    //   r_c = -F_c - Mk Q_c + B_c^T U,   r_u = tau G - sum_c B_c Q_c - tau E U
+    for (int idx = tid; idx < NV * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double su = tau * Gm[i * NL + j];
+      for (int l = 0; l < NV; ++l) su -= tau * Em[i * NV + l] * sU[l * NL + j];
+      for (int c = 0; c < D; ++c) {
+        const double* Bc = Bm + (long)c * NV * NV;
+        const double* Fc = Fm + (long)c * NV * NL;
+        const double* Qc = sX + c * NV * NL;
+        double sq = -Fc[i * NL + j];
+        for (int l = 0; l < NV; ++l) sq += Bc[l * NV + i] * sU[l * NL + j] - sY[i * NV + l] * Qc[l * NL + j];
+        sR[c * NV * NL + idx] = sq;
+        for (int l = 0; l < NV; ++l) su -= Bc[i * NV + l] * Qc[l * NL + j];
+      }
+      rU[idx] = su;
+    }
+    __syncthreads();
+    // correction by the same route: y_c = Mk^-1 r_c (in place via Z),
+    // dU = K^-1 (r_u - sum_c B_c y_c), dQ_c = y_c + Mk^-1 B_c^T dU
+    for (int c = 0; c < D; ++c) {
+      double* rc = sR + c * NV * NL;
+      for (int idx = tid; idx < NV * NL; idx += NT) {
+        int i = idx / NL, j = idx % NL;
+        double s = 0.0;
+        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * rc[l * NL + j];
+        sZ[idx] = s;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < NV * NL; idx += NT) rc[idx] = sZ[idx];
+      __syncthreads();
+    }
+    for (int idx = tid; idx < NV * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = rU[idx];
+      for (int c = 0; c < D; ++c) {
+        const double* Bc = Bm + (long)c * NV * NV;
+        for (int l = 0; l < NV; ++l) s -= Bc[i * NV + l] * sR[c * NV * NL + l * NL + j];
+      }
+      sZ[idx] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NV * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = 0.0;
+      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
+      rU[idx] = s;  // dU
+    }
+    __syncthreads();
+    for (int c = 0; c < D; ++c) {
+      const double* Bc = Bm + (long)c * NV * NV;
+      // t = B_c^T dU (into Z), then Q_c += y_c + Mk^-1 t
+      for (int idx = tid; idx < NV * NL; idx += NT) {
+        int i = idx / NL, j = idx % NL;
+        double s = 0.0;
+        for (int l = 0; l < NV; ++l) s += Bc[l * NV + i] * rU[l * NL + j];
+        sZ[idx] = s;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < NV * NL; idx += NT) {
+        int i = idx / NL, j = idx % NL;
+        double s = sR[c * NV * NL + idx];
+        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * sZ[l * NL + j];
+        sX[c * NV * NL + idx] += s;
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < NV * NL; idx += NT) sU[idx] += rU[idx];
+    __syncthreads();
+    // A^e = tau H - sum_c F_c^T Q_c - tau G^T U
+    for (int idx = tid; idx < NL * NL; idx += NT) {
+      int i = idx / NL, j = idx % NL;
+      double s = tau * Hm[idx];
+      for (int l = 0; l < NV; ++l) {
+        s -= tau * Gm[l * NL + i] * sU[l * NL + j];
+        for (int c = 0; c < D; ++c) s -= Fm[((long)c * NV + l) * NL + i] * sX[c * NV * NL + l * NL + j];
+      }
+      Ae[idx] = s;
+    }
+    for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sU[idx];
   }
-  __syncthreads();
-  for (int idx = tid; idx < NL * NL; idx += NT) {
-    int i = idx / NL, j = idx % NL;
-    double s = 0.0;
-    for (int l = 0; l < NV; ++l) s += sZ[l * NL + i] * sWm[l * NL + j];
-    Ae[idx] -= s;
-  }
-  for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sWm[idx];
 }
 
 // b = M f (or f itself when it is already a load), per (element, node)
@@ -281,15 +418,22 @@ __global__ void load_pull_kernel(int n, const double* __restrict__ ebuf, const d
   g[t] = s;
 }
 
-// Local recovery, one workgroup per element.  U = W Lambda + K^-1 b from the
-// stored explicit inverses, Q_c = Mk^-1 (B_c^T U - F_c Lambda), then one step
-// of refinement on the second local equation: the residual
-// rho = tau G Lambda + b - sum_c B_c Q_c - tau E U (reference matrices only)
-// gives U += K^-1 rho.  Without it the error that the explicit K^-1 leaves in
-// U is amplified by the cancellation in B^T U - F Lambda on elements with
-// large kappa (where u is nearly constant).
+// Local recovery, one workgroup per element.  X = [Q; U] solves the local
+// system L X = R Lambda + [0; b]: first by the Schur-complement route with
+// the stored inverses (U = W Lambda + K^-1 b, Q_c = Mk^-1 (B_c^T U - F_c
+// Lambda)), then one step of refinement on the full system: the residuals
+//   r_c = -F_c Lambda - Mk Q_c + B_c^T U,
+//   r_u = tau G Lambda + b - sum_c B_c Q_c - tau E U
+// (Mk applied as Phi^T diag(w / kappa) Phi) are corrected by the same route,
+// dU = K^-1 (r_u - sum_c B_c Mk^-1 r_c), dQ_c = Mk^-1 (r_c + B_c^T dU).  On
+// elements with large kappa / (tau h) the first solution carries an error of
+// eps kappa / (tau h) (the route cancels terms of size kappa); after the step
+// it is backward stable.
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, const double* __restrict__ Bm,
+__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, const double* __restrict__ Phi,
+                                                         const double* __restrict__ Wq,
+                                                         const double* __restrict__ kqp,
+                                                         const double* __restrict__ Bm,
                                                          const double* __restrict__ Fm,
                                                          const double* __restrict__ Gm,
                                                          const double* __restrict__ Em,
@@ -301,10 +445,12 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, cons
                                                          const double* __restrict__ Minv, double* __restrict__ u,
                                                          double* __restrict__ q) {
   using Dm = Dims<D, K>;
-  constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL;
-  __shared__ double sL[NL], sU[NV], sT[NV], sQ[D * NV], sR[NV];
+  constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL, NQ = Dm::NQ;
+  __shared__ double sL[NL], sU[NV], sT[D * NV], sQ[D * NV], sY[D * NV], sR[NV], sP[NQ];
   const long T = blockIdx.x;
   const int tid = threadIdx.x;
+  const double* Mi = Minv + T * (long)NV * NV;
+  const double* Ki = Kinv + T * (long)NV * NV;
   int e[3] = {0, 0, 0};
   elem_coords<D>(T, n, e);
   for (int idx = tid; idx < NL; idx += NT) {
@@ -326,46 +472,93 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, cons
   for (int i = tid; i < NV; i += NT) {
     double s = 0.0;
     for (int j = 0; j < NL; ++j) s += W[(T * NV + i) * NL + j] * sL[j];
-    for (int j = 0; j < NV; ++j) s += Kinv[(T * NV + i) * NV + j] * b[T * NV + j];
+    for (int j = 0; j < NV; ++j) s += Ki[i * NV + j] * b[T * NV + j];
     sU[i] = s;
   }
-  for (int pass = 0; pass < 2; ++pass) {
+  __syncthreads();
+  // Q_c = Mk^-1 (B_c^T U - F_c Lambda)
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, i = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
+    for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
+    sT[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, i = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Mi[i * NV + j] * sT[c * NV + j];
+    sQ[idx] = s;
+  }
+  __syncthreads();
+  // residual of the second equation
+  for (int i = tid; i < NV; i += NT) {
+    double s = b[T * NV + i];
+    for (int j = 0; j < NL; ++j) s += tau * Gm[i * NL + j] * sL[j];
+    for (int j = 0; j < NV; ++j) s -= tau * Em[i * NV + j] * sU[j];
+    for (int c = 0; c < D; ++c)
+      for (int j = 0; j < NV; ++j) s -= Bm[(c * NV + i) * NV + j] * sQ[c * NV + j];
+    sR[i] = s;
+  }
+  // residual of the first equations: r_c = -F_c Lambda + B_c^T U - Mk Q_c,
+  // with Mk Q_c = Phi^T (w / kappa * (Phi Q_c)), one direction at a time
+  for (int c = 0; c < D; ++c) {
     __syncthreads();
-    for (int c = 0; c < D; ++c) {
-      // t = B_c^T U - F_c Lambda ; Q_c = Mk^-1 t
-      for (int i = tid; i < NV; i += NT) {
-        double s = 0.0;
-        for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
-        for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
-        sT[i] = s;
-      }
-      __syncthreads();
-      for (int i = tid; i < NV; i += NT) {
-        double s = 0.0;
-        for (int j = 0; j < NV; ++j) s += Minv[(T * NV + i) * NV + j] * sT[j];
-        sQ[c * NV + i] = s;
-      }
-      __syncthreads();
-    }
-    if (pass == 1) break;
-    // rho = tau G Lambda + b - sum_c B_c Q_c - tau E U ; U += K^-1 rho
-    for (int i = tid; i < NV; i += NT) {
-      double s = b[T * NV + i];
-      for (int j = 0; j < NL; ++j) s += tau * Gm[i * NL + j] * sL[j];
-      for (int j = 0; j < NV; ++j) s -= tau * Em[i * NV + j] * sU[j];
-      for (int c = 0; c < D; ++c)
-        for (int j = 0; j < NV; ++j) s -= Bm[(c * NV + i) * NV + j] * sQ[c * NV + j];
-      sR[i] = s;
+    for (int qp = tid; qp < NQ; qp += NT) {
+      double s = 0.0;
+      for (int j = 0; j < NV; ++j) s += Phi[qp * NV + j] * sQ[c * NV + j];
+      sP[qp] = s * Wq[qp] / kqp[T * NQ + qp];
     }
     __syncthreads();
     for (int i = tid; i < NV; i += NT) {
       double s = 0.0;
-      for (int j = 0; j < NV; ++j) s += Kinv[(T * NV + i) * NV + j] * sR[j];
-      sT[i] = s;
+      for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sU[j];
+      for (int j = 0; j < NL; ++j) s -= Fm[(c * NV + i) * NL + j] * sL[j];
+      for (int qp = 0; qp < NQ; ++qp) s -= Phi[qp * NV + i] * sP[qp];
+      sT[c * NV + i] = s;
     }
-    __syncthreads();
-    for (int i = tid; i < NV; i += NT) sU[i] += sT[i];
   }
+  __syncthreads();
+  // y_c = Mk^-1 r_c ; Q_c += y_c
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, i = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Mi[i * NV + j] * sT[c * NV + j];
+    sY[idx] = s;
+    sQ[idx] += s;
+  }
+  __syncthreads();
+  // dU = K^-1 (r_u - sum_c B_c y_c)
+  for (int i = tid; i < NV; i += NT) {
+    double s = sR[i];
+    for (int c = 0; c < D; ++c)
+      for (int j = 0; j < NV; ++j) s -= Bm[(c * NV + i) * NV + j] * sY[c * NV + j];
+    sP[i] = s;  // NQ >= NV
+  }
+  __syncthreads();
+  for (int i = tid; i < NV; i += NT) {
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Ki[i * NV + j] * sP[j];
+    sR[i] = s;  // dU
+  }
+  __syncthreads();
+  // Q_c += Mk^-1 B_c^T dU ; U += dU
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, i = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Bm[(c * NV + j) * NV + i] * sR[j];
+    sT[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, i = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Mi[i * NV + j] * sT[c * NV + j];
+    sQ[idx] += s;
+  }
+  for (int i = tid; i < NV; i += NT) sU[i] += sR[i];
+  __syncthreads();
   for (int i = tid; i < NV; i += NT) u[T * NV + i] = sU[i];
   for (int i = tid; i < D * NV; i += NT) q[T * D * NV + i] = sQ[i];
 }
@@ -477,7 +670,7 @@ void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Ael
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* lam,
+void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* kqp, const double* lam,
                         const double* gdir, const double* f, int is_load, const double* W, const double* Kinv,
                         const double* Minv, double* b, double* u, double* q, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
@@ -489,8 +682,8 @@ void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, co
     hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
                        rd.M, f, is_load, b);
     constexpr int NT = 64;
-    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, tau, rd.B, rd.F,
-                       rd.G, rd.E, lam, gdir, b, W, Kinv, Minv, u, q);
+    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, tau, rd.Phi,
+                       rd.Wq, kqp, rd.B, rd.F, rd.G, rd.E, lam, gdir, b, W, Kinv, Minv, u, q);
   });
   HDG_CHECK(hipGetLastError());
 }

@@ -125,7 +125,7 @@ void launch_element_load(int d, int k, long nelem, const RefDevice& rd, const do
                          const double* W, double* ebuf, hipStream_t st);
 void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Aelem, const double* gdir,
                       double* g, hipStream_t st);
-void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* lam,
+void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* kqp, const double* lam,
                         const double* gdir, const double* f, int is_load, const double* W, const double* Kinv,
                         const double* Minv, double* b, double* u, double* q, hipStream_t st);
 void launch_grad(int d, int k, long nelem, const RefDevice& rd, const double* kqp, const double* q,

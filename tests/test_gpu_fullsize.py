@@ -1,0 +1,288 @@
+"""Parity at the full workload sizes, in the configuration the benchmark times.
+
+The oracle cannot assemble or cycle systems of millions of unknowns in
+seconds, so at these sizes the GPU is checked on sampled outputs that the
+oracle computes one at a time from the element matrices of the elements
+involved (element DtN maps, load rows, apply rows, smoother rows, recovered
+element fields), and through properties that hold at any size (the p-level
+Galerkin identity, symmetry and positivity of the symmetric V-cycle, the
+true residual of the converged solve, manufactured convergence rates).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mg as omg
+from oracle.hdg import HDG
+from paper_1811_09909_amd import inputs
+
+from ._helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _bench_solver():
+    sys.path.insert(0, ROOT)
+    from bench import SOLVER
+    return SOLVER
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def big2d(torch_cuda):
+    """2D diffusion, 512 x 512 quads, k = 4, kappa log-uniform over six
+    decades (seed 0): the benchmark workload, built as the benchmark builds it."""
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import Problem
+    S = _bench_solver()
+    say("[fullsize 2d] oracle setup n=512 k=4")
+    wl = inputs.diffusion2d(512, 4, 1e-3, 1e3, seed=0)
+    O = HDG(2, 512, 4, 1.0, wl.kappa)
+    P = Problem(2, 512, 4, torch_cuda.as_tensor(wl.kappa), tau=1.0, store_recovery=True)
+    P.build(sweeps=S["sweeps"], growth=S["growth"], local_corr=L.LC_BOTH, precision=L.MIXED, method=L.METHOD_PCG,
+            max_it=S["max_it"], coarse_n=S["coarse_n"])
+    rng = np.random.default_rng(11)
+    nf = O.mesh.nface
+    fids = sorted(set(rng.choice(nf, 40, replace=False).tolist()) | {0, 1, 510, nf // 2 - 1, nf // 2, nf - 1})
+    return wl, O, P, fids, rng
+
+
+def test_fullsize_element_dtn(big2d, torch_cuda):
+    wl, O, P, fids, rng = big2d
+    Ts = sorted(set(rng.choice(O.mesh.nel, 48, replace=False).tolist()) | {0, 511, O.mesh.nel - 1})
+    Ae = P.level_export(0)[torch_cuda.as_tensor(Ts, device=P.device)].cpu().numpy()
+    errs = [relerr(Ae[i], O.element_dtn(T)) for i, T in enumerate(Ts)]
+    worst = int(np.argmax(errs))
+    say(f"  element DtN, {len(Ts)} sampled elements: worst relerr {errs[worst]:.2e} "
+        f"(kappa {wl.kappa[Ts[worst]]:.3e}); largest kappa sampled {max(wl.kappa[Ts]):.3e}")
+    assert errs[worst] <= 1e-12
+
+
+def test_fullsize_rhs_apply_smoother(big2d, torch_cuda):
+    wl, O, P, fids, rng = big2d
+    ne = O.ne
+    idx = np.concatenate([np.arange(F * ne, (F + 1) * ne) for F in fids])
+    g = P.rhs(torch_cuda.as_tensor(wl.f)).cpu().numpy()
+    go = O.load_rows(fids, wl.f).ravel()
+    say(f"  load rows: relerr {relerr(g[idx], go):.2e}")
+    assert relerr(g[idx], go) <= 1e-10
+    cache = {}
+    x = rng.standard_normal(O.nlam)
+    yo = O.apply_rows(fids, x, cache).ravel()
+    y = P.level_apply(0, torch_cuda.as_tensor(x)).cpu().numpy()
+    y32 = P.level_apply(0, torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  apply rows: fp64 {relerr(y[idx], yo):.2e} fp32 {relerr(y32[idx], yo):.2e}")
+    assert relerr(y[idx], yo) <= 1e-10
+    assert relerr(y32[idx], yo) <= 1e-5
+    # block Jacobi (Sec. 4.1): one sweep from zero is D^-1 r; the second
+    # needs the first on the neighbouring faces, also computed here
+    r = x
+    e1 = P.level_smooth(0, torch_cuda.as_tensor(r), 1).cpu().numpy()
+    e2 = P.level_smooth(0, torch_cuda.as_tensor(r), 2).cpu().numpy()
+    e1o = np.concatenate([np.linalg.solve(O.diag_block(F, cache), r[F * ne:(F + 1) * ne]) for F in fids])
+    say(f"  one sweep: relerr {relerr(e1[idx], e1o):.2e}")
+    assert relerr(e1[idx], e1o) <= 1e-10
+    need = set()
+    for F in fids:
+        for T, _ in O.face_elements(F):
+            need |= {int(gd) // ne for gd in O.gmap[T] if gd >= 0}
+    e1n = np.zeros(O.nlam)
+    for F in need:
+        e1n[F * ne:(F + 1) * ne] = np.linalg.solve(O.diag_block(F, cache), r[F * ne:(F + 1) * ne])
+    Ae1 = O.apply_rows(fids, e1n, cache)
+    e2o = np.concatenate([e1n[F * ne:(F + 1) * ne] + np.linalg.solve(O.diag_block(F, cache),
+                                                                     r[F * ne:(F + 1) * ne] - Ae1[i])
+                          for i, F in enumerate(fids)])
+    say(f"  two sweeps: relerr {relerr(e2[idx], e2o):.2e}")
+    assert relerr(e2[idx], e2o) <= 1e-10
+
+
+def test_fullsize_p_level_galerkin(big2d, torch_cuda):
+    """A_{N-1} = J_N^T A_N J_N (eq. ANm1) at full size, with the oracle's J_N."""
+    wl, O, P, fids, rng = big2d
+    J = omg.p_injection(O.mesh, 4)
+    xc = rng.standard_normal(J.shape[1])
+    y1 = P.level_apply(1, torch_cuda.as_tensor(xc)).cpu().numpy()
+    y0 = P.level_apply(0, torch_cuda.as_tensor(J @ xc)).cpu().numpy()
+    err = relerr(y1, J.T @ y0)
+    say(f"  p-level Galerkin identity: relerr {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_fullsize_symmetric_vcycle(big2d, torch_cuda):
+    """The cycle with local corrections before and after the coarse step is
+    symmetric and positive (it preconditions CG), at full size in FP64; the
+    FP32 cycle the mixed solve uses agrees with it to single precision."""
+    from paper_1811_09909_amd import _lib as L
+    wl, O, P, fids, rng = big2d
+    x = rng.standard_normal(O.nlam)
+    y = rng.standard_normal(O.nlam)
+    Bx = P.vcycle(torch_cuda.as_tensor(x)).cpu().numpy()
+    By = P.vcycle(torch_cuda.as_tensor(y)).cpu().numpy()
+    asym = abs(x @ By - y @ Bx) / (np.linalg.norm(x) * np.linalg.norm(By))
+    say(f"  |x.By - y.Bx| / (|x||By|) = {asym:.2e}, x.Bx = {x @ Bx:.3e}")
+    assert asym <= 1e-10
+    assert x @ Bx > 0 and y @ By > 0
+    Bx32 = P.vcycle(torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=L.FP32).cpu().numpy()
+    say(f"  FP32 cycle vs FP64 cycle: relerr {relerr(Bx32, Bx):.2e}")
+    assert relerr(Bx32, Bx) <= 1e-3
+
+
+def test_fullsize_benchmark_solve(big2d, torch_cuda):
+    """The timed solve (mixed precision PCG) converges: its FP64 residual,
+    recomputed with the apply checked above and, on sampled rows, by the
+    oracle, is below the tolerance; recovered fields on sampled elements
+    match the oracle's local solves with the same traces."""
+    wl, O, P, fids, rng = big2d
+    S = _bench_solver()
+    ne = O.ne
+    f = torch_cuda.as_tensor(wl.f)
+    lam, info = P.solve(f, tol=S["tol"])
+    g = P.rhs(f)
+    res = g - P.level_apply(0, lam)
+    rel = float(res.norm() / g.norm())
+    say(f"  mixed PCG: {info['iters']} iterations, reported relres {info['relres']:.2e}, recomputed {rel:.2e}")
+    assert info["relres"] <= S["tol"]
+    assert rel <= 1.05 * S["tol"]
+    lam_np = lam.cpu().numpy()
+    cache = {}
+    go = O.load_rows(fids, wl.f)
+    ro = go - O.apply_rows(fids, lam_np, cache)
+    # the residual is a small difference of rows of size (|A| |lambda|)_F
+    scale = np.abs(go) + O.apply_rows(fids, np.abs(lam_np), {T: np.abs(A) for T, A in cache.items()})
+    idx = np.concatenate([np.arange(F * ne, (F + 1) * ne) for F in fids])
+    diff = np.abs(ro.ravel() - res.cpu().numpy()[idx]) / scale.ravel()
+    say(f"  sampled residual rows: oracle vs GPU max diff {diff.max():.2e} of (|A||lambda| + |g|)_F")
+    assert diff.max() <= 1e-12
+    u, q = P.reconstruct(lam, f)
+    u, q = u.cpu().numpy(), q.cpu().numpy()
+    LT = O.local_traces(lam_np, np.zeros(O.nbdof))
+    Ts = rng.choice(O.mesh.nel, 24, replace=False)
+    # The local solve's forward error grows like eps kappa / (tau h) (the
+    # oracle's own LU loses 1.4e-12 at kappa = 1e3, h = 1/512; see
+    # test_element_dtn_conditioning_bound): per element the bound is
+    # 1e-14 max(1, kappa_T / (tau h)).
+    worst = 0.0
+    for T in Ts:
+        uo, qo = O.recover_element(T, LT[T], wl.f[T])
+        eu, eq = relerr(u[T], uo), relerr(q[T], qo)
+        bound = 1e-14 * max(1.0, wl.kappa[T] * 512)
+        say(f"    T={T} kappa={wl.kappa[T]:.2e}: u {eu:.1e} q {eq:.1e} (bound {bound:.1e})")
+        worst = max(worst, max(eu, eq) / bound)
+    say(f"  recovered (u, q) on {len(Ts)} sampled elements: worst error / bound {worst:.2e}")
+    assert worst <= 1.0
+
+
+def test_fullsize_fp64_and_mixed_agree(big2d, torch_cuda):
+    """Plain FP64 and mixed precision reach solutions of the same system: both
+    residuals below the tolerance and the difference of the traces within
+    what two 1e-10 residuals allow (measured against the residual gap)."""
+    from paper_1811_09909_amd import _lib as L
+    wl, O, P, fids, rng = big2d
+    S = _bench_solver()
+    f = torch_cuda.as_tensor(wl.f)
+    lam_mx, info_mx = P.solve(f, tol=S["tol"])
+    P.build(sweeps=S["sweeps"], growth=S["growth"], local_corr=L.LC_BOTH, precision=L.FP64, method=L.METHOD_PCG,
+            max_it=S["max_it"], coarse_n=S["coarse_n"])
+    try:
+        lam64, info64 = P.solve(f, tol=S["tol"])
+    finally:
+        P.build(sweeps=S["sweeps"], growth=S["growth"], local_corr=L.LC_BOTH, precision=L.MIXED,
+                method=L.METHOD_PCG, max_it=S["max_it"], coarse_n=S["coarse_n"])
+    g = P.rhs(f)
+    r64 = float((g - P.level_apply(0, lam64)).norm() / g.norm())
+    rmx = float((g - P.level_apply(0, lam_mx)).norm() / g.norm())
+    d = float((lam64 - lam_mx).norm() / lam64.norm())
+    say(f"  FP64 {info64['iters']} it relres {r64:.2e}; mixed {info_mx['iters']} it relres {rmx:.2e}; "
+        f"|lam64 - lam_mixed| / |lam64| = {d:.2e}")
+    assert r64 <= 1.05 * S["tol"] and rmx <= 1.05 * S["tol"]
+    assert abs(info64["iters"] - info_mx["iters"]) <= 0.05 * info64["iters"] + 5
+    assert d <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def cube3d(torch_cuda):
+    """3D diffusion on the unit cube, 32^3 hexahedra, k = 3, kappa(x) at the
+    Gauss points, manufactured u = sin(pi x) sin(pi y) sin(pi z)."""
+    from paper_1811_09909_amd.hdg import Problem
+    wl = inputs.diffusion3d(32, 3)
+    O = HDG(3, 32, 3, 1.0, np.ones(32 ** 3))
+    kq = wl.kappa_fn(O.volume_qpoints())
+    O.set_kappa(kq)
+    P = Problem(3, 32, 3, torch_cuda.as_tensor(kq), tau=1.0, kappa_kind="qp", store_recovery=True)
+    f = wl.f(O.volume_nodes())
+    return wl, O, P, f
+
+
+def test_fullsize_3d_operators(cube3d, torch_cuda):
+    wl, O, P, f = cube3d
+    rng = np.random.default_rng(5)
+    Ts = sorted(set(rng.choice(O.mesh.nel, 16, replace=False).tolist()) | {0, O.mesh.nel - 1})
+    Ae = P.level_export(0)[torch_cuda.as_tensor(Ts, device=P.device)].cpu().numpy()
+    worst = max(relerr(Ae[i], O.element_dtn(T)) for i, T in enumerate(Ts))
+    say(f"[fullsize 3d] element DtN worst relerr {worst:.2e}")
+    assert worst <= 1e-10
+    P.build()
+    nf = O.mesh.nface
+    fids = sorted(set(rng.choice(nf, 24, replace=False).tolist()) | {0, nf - 1})
+    ne = O.ne
+    idx = np.concatenate([np.arange(F * ne, (F + 1) * ne) for F in fids])
+    x = rng.standard_normal(O.nlam)
+    yo = O.apply_rows(fids, x).ravel()
+    y = P.level_apply(0, torch_cuda.as_tensor(x)).cpu().numpy()
+    y32 = P.level_apply(0, torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  apply rows: fp64 {relerr(y[idx], yo):.2e} fp32 {relerr(y32[idx], yo):.2e}")
+    assert relerr(y[idx], yo) <= 1e-10
+    assert relerr(y32[idx], yo) <= 1e-5
+    g = P.rhs(torch_cuda.as_tensor(f)).cpu().numpy()
+    go = O.load_rows(fids, f).ravel()
+    say(f"  load rows: relerr {relerr(g[idx], go):.2e}")
+    assert relerr(g[idx], go) <= 1e-10
+
+
+def test_fullsize_3d_manufactured_rates(cube3d, torch_cuda):
+    """FP64 CG + V-cycle solves at n = 16 and 32 (k = 3): residual below 1e-10
+    and L2 errors of u and q = -kappa grad u falling at rate >= k + 1 - 0.3."""
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import Problem
+    wl, O32, P32, f32 = cube3d
+    errs = []
+    for n in (16, 32):
+        if n == 32:
+            O, P, f = O32, P32, f32
+        else:
+            O = HDG(3, n, 3, 1.0, np.ones(n ** 3))
+            kq = wl.kappa_fn(O.volume_qpoints())
+            O.set_kappa(kq)
+            P = Problem(3, n, 3, torch_cuda.as_tensor(kq), tau=1.0, kappa_kind="qp", store_recovery=True)
+            f = wl.f(O.volume_nodes())
+        P.build(local_corr=L.LC_BOTH, precision=L.FP64, method=L.METHOD_PCG, max_it=3000)
+        ft = torch_cuda.as_tensor(f)
+        lam, info = P.solve(ft, tol=1e-10)
+        g = P.rhs(ft)
+        rel = float((g - P.level_apply(0, lam)).norm() / g.norm())
+        u, q = P.reconstruct(lam, ft)
+        eu, eq = O.errors(u.cpu().numpy(), q.cpu().numpy(), wl.u_exact, wl.grad_exact, wl.kappa_fn)
+        say(f"  n={n}: {info['iters']} iterations, relres {rel:.2e}, |u-u_h| {eu:.3e}, |q-q_h| {eq:.3e}")
+        assert rel <= 1.05e-10
+        errs.append((eu, eq))
+    ru = np.log2(errs[0][0] / errs[1][0])
+    rq = np.log2(errs[0][1] / errs[1][1])
+    say(f"  rates u {ru:.2f} q {rq:.2f}")
+    assert ru >= 3.7 and rq >= 3.7

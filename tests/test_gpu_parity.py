@@ -157,7 +157,8 @@ def test_hierarchy_operators_and_smoother(torch_cuda, d, n, k):
 
 @pytest.mark.parametrize("d,n,k,lc,sweeps,growth", [(2, 8, 2, "pre", 2, 1), (2, 16, 3, "both", 2, 1),
                                                     (2, 16, 1, "none", 1, 2), (2, 8, 4, "post", 3, 2),
-                                                    (3, 4, 2, "pre", 2, 1), (3, 4, 1, "both", 1, 1)])
+                                                    (3, 4, 2, "pre", 2, 1), (3, 4, 1, "both", 1, 1),
+                                                    (3, 8, 3, "both", 2, 1), (3, 8, 1, "pre", 2, 1)])
 def test_vcycle(torch_cuda, d, n, k, lc, sweeps, growth):
     say(f"[vcycle] d={d} n={n} k={k} lc={lc} sweeps={sweeps} growth={growth}")
     kap, rng = _kappa(d, n)
@@ -326,6 +327,34 @@ def test_iteration_counts_match_oracle(torch_cuda):
             say(f"  method={method} sweeps={sweeps} growth={growth}: gpu {info['iters']} oracle {ro.iters}")
             assert abs(info["iters"] - ro.iters) <= (1 if method == 1 else 0)
             assert relerr(lam.cpu().numpy(), ro.lam) <= 1e-9
+
+
+def test_iteration_counts_match_oracle_3d(torch_cuda):
+    """3D, 8^3 hexahedra, k = 3, kappa(x) at the Gauss points: MG and PCG
+    in FP64 against the oracle's counts and solution; the mixed-precision
+    solve reaches the same solution (its count is not the oracle's: the FP32
+    cycle is a different preconditioner)."""
+    from paper_1811_09909_amd import _lib as L
+    wl = inputs.diffusion3d(8, 3)
+    say("[counts 3d] diffusion3d n=8 k=3")
+    O = HDG(3, 8, 3, 1.0, np.ones(8 ** 3))
+    kq = wl.kappa_fn(O.volume_qpoints())
+    O.set_kappa(kq)
+    f = wl.f(O.volume_nodes())
+    A, g, _ = O.assemble(f)
+    P = _gpu(torch_cuda, 3, 8, 3, kq, kind="qp")
+    for method, fn, lc, prec in [(0, omg.mg_solve, omg.LC_PRE, L.FP64), (1, omg.pcg_solve, omg.LC_BOTH, L.FP64),
+                                 (1, omg.pcg_solve, omg.LC_BOTH, L.MIXED)]:
+        H = omg.Hierarchy(A, 3, 8, 3, local_corr=lc)
+        ro = fn(H, A, g, tol=1e-10)
+        P.build(local_corr=lc, method=method, precision=prec)
+        lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10, allow_not_converged=True)
+        say(f"  method={method} precision={prec}: gpu {info['iters']} (relres {info['relres']:.2e}) "
+            f"oracle {ro.iters}; solution relerr {relerr(lam.cpu().numpy(), ro.lam):.2e}")
+        assert info["relres"] <= 1e-10
+        if prec == L.FP64:
+            assert abs(info["iters"] - ro.iters) <= (1 if method == 1 else 0)
+        assert relerr(lam.cpu().numpy(), ro.lam) <= 1e-9
 
 
 @pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 4, 5), (3, 2, 2)])

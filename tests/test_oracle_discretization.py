@@ -152,3 +152,69 @@ def test_P4_planted_sign_error_is_caught():
     A, g, lb = P.assemble(f, ue)
     lam = spla.spsolve(A.tocsc(), g)
     assert np.abs(lam - ue(P.interior_trace_nodes())).max() > 1e-6
+
+
+def test_face_rows_match_assembly():
+    """The per-face row functions used for sampled checks on large meshes
+    reproduce the assembled system (apply, load, diagonal blocks) and the
+    per-element recovery reproduces the global one."""
+    rng = np.random.default_rng(3)
+    for d, n, k in [(2, 6, 2), (3, 3, 1)]:
+        O = HDG(d, n, k, 1.0, 10 ** rng.uniform(-2, 2, n ** d))
+        f = rng.standard_normal((n ** d, O.nv))
+        A, g, _ = O.assemble(f)
+        x = rng.standard_normal(A.shape[0])
+        fids = list(range(O.mesh.nface))
+        assert np.abs(O.apply_rows(fids, x).ravel() - A @ x).max() <= 1e-13 * np.abs(A @ x).max()
+        assert np.abs(O.load_rows(fids, f).ravel() - g).max() <= 1e-13 * np.abs(g).max()
+        ne = O.ne
+        for F in (0, O.mesh.nface // 2, O.mesh.nface - 1):
+            Dd = A[F * ne:(F + 1) * ne, F * ne:(F + 1) * ne].toarray()
+            assert np.abs(O.diag_block(F) - Dd).max() <= 1e-13 * np.abs(Dd).max()
+        lam = np.linalg.solve(A.toarray(), g)
+        u, q = O.reconstruct(lam, f)
+        LT = O.local_traces(lam, np.zeros(O.nbdof))
+        for T in (0, n ** d - 1):
+            uT, qT = O.recover_element(T, LT[T], f[T])
+            assert np.allclose(uT, u[T], rtol=0, atol=1e-14 * np.abs(u).max())
+            assert np.allclose(qT, q[T], rtol=0, atol=1e-14 * np.abs(q).max())
+
+
+def _ge_solve_longdouble(A, B):
+    """Gaussian elimination with partial pivoting in extended precision."""
+    A = np.array(A, dtype=np.longdouble)
+    B = np.array(B, dtype=np.longdouble)
+    n = A.shape[0]
+    for k in range(n):
+        p = k + int(np.argmax(np.abs(A[k:, k])))
+        if p != k:
+            A[[k, p]] = A[[p, k]]
+            B[[k, p]] = B[[p, k]]
+        f = A[k + 1:, k] / A[k, k]
+        A[k + 1:, k:] -= f[:, None] * A[k, k:][None, :]
+        B[k + 1:] -= f[:, None] * B[k][None, :]
+    X = np.zeros_like(B)
+    for k in range(n - 1, -1, -1):
+        X[k] = (B[k] - A[k, k + 1:] @ X[k + 1:]) / A[k, k]
+    return X
+
+
+def test_element_dtn_conditioning_bound():
+    """Forming A^e in FP64 loses accuracy in proportion to kappa / (tau h):
+    for a highly conductive element the DtN map is a small difference of
+    terms of size kappa.  Against an extended-precision evaluation of the
+    same definition the FP64 oracle stays within 1e-14 max(1, kappa/(tau h)),
+    the bound the full-size GPU comparisons use, on the benchmark mesh
+    (h = 1/512, k = 4) across the kappa range [1e-3, 1e3]."""
+    n, k, tau = 512, 4, 1.0
+    kap = np.ones(n * n)
+    kap[:4] = [1e-3, 1.0, 30.0, 1e3]
+    O = HDG(2, n, k, tau, kap)
+    for T in range(4):
+        A64 = O.element_dtn(T)
+        X = _ge_solve_longdouble(O.local_matrix(T), O.R)
+        Aref = tau * np.asarray(O.H, dtype=np.longdouble) - np.asarray(O.S, dtype=np.longdouble).T @ X
+        err = float(np.linalg.norm((A64 - Aref).astype(float)) / np.linalg.norm(Aref.astype(float)))
+        amp = max(1.0, kap[T] * n / tau)
+        print(f"kappa={kap[T]:g}: FP64 relerr {err:.2e}, bound {1e-14 * amp:.2e}")
+        assert err <= 1e-14 * amp

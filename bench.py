@@ -23,6 +23,30 @@ import time
 METRIC = "trace DOFs/s to rel. resid 1e-10: FP64 vs FP32 V-cycle+FP64 refine"
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+CAL_BYTES = 1 << 30
+# HBM traffic of one finest-level FP32 sweep launch of the 512^2, k = 4
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
+# `bench.py --traffic-probe` (per-dispatch counter values, KiB units), each
+# scaled by what the same counter reads for a kernel that reads and writes
+# exactly CAL_BYTES.  Valid only for the kernel sources it was taken on.
+TRAFFIC = {"fetch": 263930.0, "write": 10220.2, "cal_fetch": 524300.0, "cal_write": 1048576.0,
+           "sources_sha256_16": "0137d2572628230e"}
+TRAFFIC_SOURCES = ["paper_1811_09909_amd/csrc/trace.hip", "paper_1811_09909_amd/csrc/trace_dev.hpp",
+                   "paper_1811_09909_amd/csrc/hdg_internal.hpp"]
+
+
+def sweep_traffic_bytes():
+    """Measured bytes per sweep launch, or None when the kernel sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["sources_sha256_16"]:
+        return None
+    kib = CAL_BYTES / 1024.0
+    return (TRAFFIC["fetch"] * kib / TRAFFIC["cal_fetch"] + TRAFFIC["write"] * kib / TRAFFIC["cal_write"]) * 1024.0
 # Solver configuration of the timed step; the full-size parity tests import it
 SOLVER = {"method": "pcg", "sweeps": 2, "growth": 1, "coarse_n": 16, "max_it": 20000, "tol": 1e-10}
 
@@ -46,6 +70,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-min-s", type=float, default=10.0, help="repeat the oracle solve until this much time")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only finest-level FP32 sweeps of the workload and a plain copy-like kernel of known "
+                         "size (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), then exit")
     return ap.parse_args()
 
 
@@ -93,8 +120,35 @@ def run_cpu_baseline(n, k, coarse_n, min_s):
             "iters": res["iters"], "trace_dofs": res["trace_dofs"]}
 
 
+def traffic_probe(args):
+    """Finest-level FP32 block-Jacobi sweeps of the benchmark workload (the
+    dominant kernel, same template and launch shape as in the solve) and a
+    calibration kernel that reads and writes exactly CAL_BYTES each."""
+    import torch
+    sys.path.insert(0, HERE)
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+    wl = inputs.diffusion2d(args.n, args.k, 1e-3, 1e3, seed=0)
+    P = Problem(2, args.n, args.k, torch.as_tensor(wl.kappa), tau=1.0, store_recovery=False)
+    P.build(sweeps=args.sweeps, growth=args.growth, local_corr=L.LC_BOTH, precision=L.MIXED,
+            method=L.METHOD_PCG, coarse_n=args.coarse_n)
+    r = torch.randn(P.nlam, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        P.level_smooth(0, r, 4, precision=L.FP32)  # one first step + 3 sweep launches
+    x = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "nlam": P.nlam, "cal_bytes": CAL_BYTES}))
+    return 0
+
+
 def main():
     args = parse()
+    if args.traffic_probe:
+        return traffic_probe(args)
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_n, args.k, args.coarse_n, args.cpu_min_s)))
         return 0
@@ -168,8 +222,12 @@ def main():
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
     achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    traffic = sweep_traffic_bytes() if (dom_name == "sweep_fp32" and n == 512 and k == 4) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"trace {dom_name} (finest level)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                "kernel": f"trace {dom_name} (finest level)",
                 "avg_launch_ms": round(avg_ms, 5), "launches": dom["launches"],
                 "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {name: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 5),

@@ -666,7 +666,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   {
     // partial sums of the reductions: one per block of the widest launch
     const long nface0 = (long)P->d * (P->n - 1) * ipow(P->n, P->d - 1);
-    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 1);
+    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
     P->s.partials = dalloc<double>(P, 2 * nb, false);
   }
   HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT, P->st));

@@ -37,11 +37,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
                                                     T* __restrict__ rc, float* __restrict__ y32,
                                                     double* __restrict__ partials) {
   constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
-  const long nface = D * nface_dir<D>(n);
-  const long F = blockIdx.x * 256L + threadIdx.x;
-  if (!RED && F >= nface) return;
+  const long F = xcd_face<D>(n, blockIdx.x, threadIdx.x);
+  if (!RED && F < 0) return;
   double part = 0.0;
-  if (F < nface) {
+  if (F >= 0) {
   T acc[NE];
   face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_Y) {
@@ -86,7 +85,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
       part += (double)v * (double)v;
     }
   }
-  }  // F < nface
+  }  // F >= 0
   if constexpr (RED) {
     __shared__ double sh[4];
     const double s = block_sum_t<256>(part, sh);
@@ -373,6 +372,15 @@ __global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* _
 
 inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
+// grid of the XCD-aware face launches (see xcd_face): 8 chunks of C blocks
+// per normal direction
+inline unsigned xcd_grid(int d, int n) {
+  long nfd = n - 1;
+  for (int a = 1; a < d; ++a) nfd *= n;
+  const long nbh = (nfd + 255) / 256;
+  return (unsigned)(8L * d * ((nbh + 7) / 8));
+}
+
 template <typename F>
 void dispatch_d_ne(int d, int ne, F&& f) {
 #define HDG_CASE(DD, NN)                                                            \
@@ -411,8 +419,8 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
 #define HDG_AK(MM)                                                                                   \
-  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af, Dv, x, b, y, \
-                     Jp, rc, y32, partials)
+  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(xcd_grid(L.d, L.n)), dim3(256), 0, st, L.n, Af, Dv, x, b, \
+                     y, Jp, rc, y32, partials)
     switch (mode) {
       case APPLY_Y: HDG_AK(APPLY_Y); break;
       case APPLY_RES: HDG_AK(APPLY_RES); break;
@@ -426,7 +434,7 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
   });
   HDG_CHECK(hipGetLastError());
   if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
-    blas_finalize((int)nblk(L.nface), 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st);
+    blas_finalize((int)xcd_grid(L.d, L.n), 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st);
 }
 
 // residual of level L restricted to P1 on the same faces (level C), and when
@@ -439,8 +447,8 @@ void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b
   const T* Dc = sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
-    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(nblk(L.nface)), dim3(256), 0, st, L.n, Af,
-                       Dc, x, b, ec, Jp, rc, nullptr, nullptr);
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(xcd_grid(L.d, L.n)), dim3(256), 0, st,
+                       L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr);
   });
   HDG_CHECK(hipGetLastError());
 }

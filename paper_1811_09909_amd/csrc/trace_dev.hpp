@@ -123,6 +123,25 @@ __device__ inline long elem_id(const int* e, int n) {
   return T;
 }
 
+// XCD-aware face blocks.  Workgroups are dealt to the 8 XCDs round-robin
+// (workgroup p runs on XCD p % 8), and each XCD has its own L2.  The faces of
+// each normal direction are cut into 8 contiguous chunks of C blocks of 256;
+// XCD j takes chunk j of every direction, i.e. the same band of grid rows in
+// every direction, so the neighbouring traces a face gathers were mostly
+// fetched into the same L2 (with the plain mapping every XCD touches almost
+// every line of the vector).  Returns the face of lane tid of workgroup p, or
+// -1 for the padding lanes.  The matching grid has 8 * D * C workgroups.
+template <int D>
+__device__ inline long xcd_face(int n, unsigned p, unsigned tid) {
+  const unsigned nfd = (unsigned)nface_dir<D>(n);
+  const unsigned C = ((nfd + 255u) / 256u + 7u) / 8u;
+  const unsigned j = p & 7u, m = p >> 3;
+  const unsigned c = m / C, w = m - c * C;
+  const unsigned local = (j * C + w) * 256u + tid;
+  if (c >= (unsigned)D || local >= nfd) return -1;
+  return (long)c * nfd + local;
+}
+
 // interior faces of a coarse macro-element m (grid n/2) on the fine grid n:
 // iota = c * 2^(D-1) + lex(t) over the tangential child bits t.
 template <int D>

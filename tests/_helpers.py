@@ -36,3 +36,22 @@ def relerr(a, b):
     a, b = np.asarray(a), np.asarray(b)
     den = np.linalg.norm(b.ravel())
     return np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0)
+
+
+def ge_solve_longdouble(A, B):
+    """Gaussian elimination with partial pivoting in extended precision."""
+    A = np.array(A, dtype=np.longdouble)
+    B = np.array(B, dtype=np.longdouble)
+    n = A.shape[0]
+    for k in range(n):
+        p = k + int(np.argmax(np.abs(A[k:, k])))
+        if p != k:
+            A[[k, p]] = A[[p, k]]
+            B[[k, p]] = B[[p, k]]
+        f = A[k + 1:, k] / A[k, k]
+        A[k + 1:, k:] -= f[:, None] * A[k, k:][None, :]
+        B[k + 1:] -= f[:, None] * B[k][None, :]
+    X = np.zeros_like(B)
+    for k in range(n - 1, -1, -1):
+        X[k] = (B[k] - A[k, k + 1:] @ X[k + 1:]) / A[k, k]
+    return X

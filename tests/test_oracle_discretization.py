@@ -14,6 +14,7 @@ import scipy.sparse.linalg as spla
 
 from oracle.hdg import HDG
 from paper_1811_09909_amd import inputs
+from ._helpers import ge_solve_longdouble
 
 
 def _rel(a, b):
@@ -180,25 +181,6 @@ def test_face_rows_match_assembly():
             assert np.allclose(qT, q[T], rtol=0, atol=1e-14 * np.abs(q).max())
 
 
-def _ge_solve_longdouble(A, B):
-    """Gaussian elimination with partial pivoting in extended precision."""
-    A = np.array(A, dtype=np.longdouble)
-    B = np.array(B, dtype=np.longdouble)
-    n = A.shape[0]
-    for k in range(n):
-        p = k + int(np.argmax(np.abs(A[k:, k])))
-        if p != k:
-            A[[k, p]] = A[[p, k]]
-            B[[k, p]] = B[[p, k]]
-        f = A[k + 1:, k] / A[k, k]
-        A[k + 1:, k:] -= f[:, None] * A[k, k:][None, :]
-        B[k + 1:] -= f[:, None] * B[k][None, :]
-    X = np.zeros_like(B)
-    for k in range(n - 1, -1, -1):
-        X[k] = (B[k] - A[k, k + 1:] @ X[k + 1:]) / A[k, k]
-    return X
-
-
 def test_element_dtn_conditioning_bound():
     """Forming A^e in FP64 loses accuracy in proportion to kappa / (tau h):
     for a highly conductive element the DtN map is a small difference of
@@ -212,7 +194,7 @@ def test_element_dtn_conditioning_bound():
     O = HDG(2, n, k, tau, kap)
     for T in range(4):
         A64 = O.element_dtn(T)
-        X = _ge_solve_longdouble(O.local_matrix(T), O.R)
+        X = ge_solve_longdouble(O.local_matrix(T), O.R)
         Aref = tau * np.asarray(O.H, dtype=np.longdouble) - np.asarray(O.S, dtype=np.longdouble).T @ X
         err = float(np.linalg.norm((A64 - Aref).astype(float)) / np.linalg.norm(Aref.astype(float)))
         amp = max(1.0, kap[T] * n / tau)

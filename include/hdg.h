@@ -67,6 +67,7 @@ enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_MIXED = 1 };
 enum { HDG_LC_NONE = 0, HDG_LC_PRE = 1, HDG_LC_POST = 2, HDG_LC_BOTH = 3 };
 enum { HDG_METHOD_MG = 0, HDG_METHOD_PCG = 1, HDG_METHOD_GMRES = 2 };
 enum { HDG_RHS_F_NODAL = 0, HDG_RHS_F_LOAD = 1, HDG_RHS_TRACE = 2 };
+#define HDG_MAX_NRHS 64 /* right-hand sides one group of a solve or V-cycle can hold */
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -85,6 +86,10 @@ typedef struct {
   int coarse_n;     /* stop h-coarsening at the first macro grid with <= coarse_n macro-elements per
                        direction and solve it directly (B_1 = A_1^-1); 2 (default) coarsens to 2 x 2.
                        The paper leaves the number of levels free (Sec. 3.1.2, Sec. 4.5). */
+  int nrhs;         /* right-hand sides one solve or V-cycle call iterates together (1 .. HDG_MAX_NRHS);
+                       larger counts go through in groups of this size.  Every kernel of the cycle and
+                       of CG then runs all of them in one launch, and the trace apply reads each
+                       operator block once for the group (through the L2 of its XCD). */
 } hdg_mg_opts;
 
 typedef struct {
@@ -95,7 +100,8 @@ typedef struct {
 } hdg_solve_info;
 
 /* Fill opts with the defaults above (constant 2 sweeps, omega 1, step-3
- * local correction, FP64, MG, 200 iterations, coarsening down to 2 x 2). */
+ * local correction, FP64, MG, 200 iterations, coarsening down to 2 x 2,
+ * one right-hand side per group). */
 void hdg_default_opts(hdg_mg_opts* opts);
 
 /* Form the element-local HDG problems and their DtN matrices
@@ -133,6 +139,27 @@ hdg_status hdg_rhs(hdg_handle h, const double* rhs, int rhs_kind, const double* 
  * (TRACE).  lambda: in = initial guess, out = solution, [nrhs][N_lambda]. */
 hdg_status hdg_solve(hdg_handle h, const double* rhs, int rhs_kind, const double* g_dirichlet, int nrhs,
                      double tol, double* lambda, hdg_solve_info* info);
+
+/* Batched solves (many meshes, many right-hand sides): problem i solves its
+ * nrhs[i] right-hand sides rhs[i] (layout as in hdg_solve) into lambda[i]
+ * (in: initial guesses) with its own built handle hs[i], tolerance tol, and
+ * fills info[i] (may be NULL).  Problems are spread over `nstreams` private
+ * HIP streams (<= 0: 4), one host thread each, so that the latency-bound
+ * coarse levels of different problems overlap on the GPU; within a problem
+ * the right-hand sides go through in groups of its build's nrhs.  Each
+ * handle's stream is ordered before and after its solve; the call returns
+ * when all are done.  Handles must be distinct (a handle is not
+ * thread-safe).  Returns the worst status.  Zero Dirichlet data. */
+hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const* rhs, int rhs_kind,
+                           const int* nrhs, double tol, double* const* lambda, hdg_solve_info* info,
+                           int nstreams);
+
+/* Autotuner: times a few outer iterations of every candidate layout of the
+ * work - coarsest macro grid (2, 8, 16) x right-hand-side group size (1, 2,
+ * 4, ... <= nrhs) - on top of `base` (NULL: defaults), builds the handle with
+ * the fastest per right-hand side and iteration, and returns it in *best
+ * (and that time in microseconds in *us_per_rhs_it when not NULL). */
+hdg_status hdg_autotune(hdg_handle h, const hdg_mg_opts* base, int nrhs, hdg_mg_opts* best, double* us_per_rhs_it);
 
 /* Local recovery (q, u) = L_T^-1 (R_T Lambda_T + [0; b_T]) element by
  * element (Sec. 2); needs store_recovery at setup. */

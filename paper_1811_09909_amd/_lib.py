@@ -20,8 +20,11 @@ EXPORTS = [
     "hdg_default_opts", "hdg_setup", "hdg_update_kappa", "hdg_mg_build", "hdg_vcycle", "hdg_rhs", "hdg_solve",
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
-    "hdg_profile_begin", "hdg_profile_read",
+    "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune",
 ]
+
+
+MAX_NRHS = 64  # HDG_MAX_NRHS
 
 
 class Mesh(ctypes.Structure):
@@ -31,7 +34,8 @@ class Mesh(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("growth", ctypes.c_int), ("omega", ctypes.c_double),
                 ("local_corr", ctypes.c_int), ("precision", ctypes.c_int), ("method", ctypes.c_int),
-                ("max_it", ctypes.c_int), ("restart", ctypes.c_int), ("coarse_n", ctypes.c_int)]
+                ("max_it", ctypes.c_int), ("restart", ctypes.c_int), ("coarse_n", ctypes.c_int),
+                ("nrhs", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -62,6 +66,8 @@ def load():
         "hdg_vcycle": (I, [P, P, P, I, I]),
         "hdg_rhs": (I, [P, P, I, P, P]),
         "hdg_solve": (I, [P, P, I, P, I, D, P, ctypes.POINTER(Info)]),
+        "hdg_solve_batch": (I, [I, P, P, I, P, D, P, ctypes.POINTER(Info), I]),
+        "hdg_autotune": (I, [P, ctypes.POINTER(Opts), I, ctypes.POINTER(Opts), ctypes.POINTER(D)]),
         "hdg_reconstruct": (I, [P, P, P, I, P, P, P]),
         "hdg_adjoint": (I, [P, P, P, D, P, ctypes.POINTER(Info)]),
         "hdg_mass_apply": (I, [P, P, P]),

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
+#include <limits>
 #include <new>
+#include <thread>
 
 #include "blas.hpp"
 #include "hdg_internal.hpp"
@@ -23,6 +26,8 @@ struct hdg_problem {
   int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
   TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int gnrhs = 1;                 // right-hand sides the captured graphs iterate
+  int cap = 1;                   // right-hand sides the build's buffers hold
   RefElement ref;
   RefDevice rd;
   long nelem = 0;
@@ -137,7 +142,9 @@ void free_build(hdg_problem* P) {
   P->L.clear();
   P->built = false;
   P->V = P->Z = P->H = P->cs = P->sn = P->gsv = P->y = nullptr;
+  P->s.sc = P->s.partials = nullptr;
   P->gm_m = 0;
+  P->cap = 1;
 }
 
 hipEvent_t take_event(hdg_problem* P) {
@@ -167,15 +174,15 @@ void harvest(hdg_problem* P) {
 
 // trace apply on level i; finest-level launches are timed when profiling
 template <typename T>
-void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc) {
-  const bool timed = P->prof_on && i == 0;
+void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc, int nr = 1) {
+  const bool timed = P->prof_on && i == 0 && nr == 1;
   hdg_problem::Pending pd{2 * mode + (sizeof(T) == 8 ? 0 : 1), nullptr, nullptr};
   if (timed) {
     pd.a = take_event(P);
     pd.b = take_event(P);
     HDG_CHECK(hipEventRecord(pd.a, P->st));
   }
-  launch_apply<T>(P->L[i], mode, x, b, y, P->rd.Jp, rc, P->st);
+  launch_apply<T>(P->L[i], mode, x, b, y, P->rd.Jp, rc, P->st, nr);
   if (timed) {
     HDG_CHECK(hipEventRecord(pd.b, P->st));
     P->pending.push_back(pd);
@@ -186,10 +193,14 @@ void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc)
 // caller's stream; captured once per slot on the private stream.  Eager when
 // graphs are disabled or finest-level kernels are being timed.
 template <class F>
-void run_graph(hdg_problem* P, int slot, F&& body) {
+void run_graph(hdg_problem* P, int slot, F&& body, int nr = 1) {
   if (!P->use_graphs || P->prof_on) {
     body();
     return;
+  }
+  if (nr != P->gnrhs) {  // graphs are captured for one right-hand-side count
+    drop_graphs(P);
+    P->gnrhs = nr;
   }
   if (!P->gx[slot]) {
     hipStream_t user = P->st;
@@ -237,7 +248,7 @@ enum { G_PCG64 = 0, G_PCGMX = 1, G_MG64 = 2, G_MGMX = 3, G_PRE64 = 4, G_PREMX = 
 // correction of step 5).  Same arithmetic as the unfused kernels up to the
 // order of the last rounding.
 template <typename T>
-T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false) {
+T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int nr = 1) {
   Level& L = P->L[i];
   const int pr = sizeof(T) == 8 ? 0 : 1;
   hipStream_t st = P->st;
@@ -249,12 +260,12 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false) {
     a.ein = e;
     a.pre_done = pre_done ? 1 : 0;
     a.eout = out ? out : e;
-    launch_tail<T>(a, st);
+    launch_tail<T>(a, st, nr);
     return (T*)a.eout;
   }
   if (L.kind == 2) {
     T* dst = out ? out : e;
-    launch_coarse_solve<T>(L, r, dst, st);
+    launch_coarse_solve<T>(L, r, dst, st, nr);
     return dst;
   }
   const int m = L.sweeps;
@@ -263,12 +274,12 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false) {
   // pre-smoothing from e = 0
   if (!pre_done) {
     if (m >= 1)
-      launch_jacobi0<T>(L, r, e, st);
+      launch_jacobi0<T>(L, r, e, st, nr);
     else
-      blas_fill<T>(e, T(0), L.nlam, st);
+      blas_fill<T>(e, T(0), L.nlam, st, nr);
   }
   for (int s = 1; s < m; ++s) {
-    apply<T>(P, i, APPLY_SWEEP, e, r, w, nullptr);
+    apply<T>(P, i, APPLY_SWEEP, e, r, w, nullptr, nr);
     std::swap(e, w);
   }
   Level& C = P->L[i + 1];
@@ -276,58 +287,58 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false) {
   if (L.kind == 0) {
     const T* ec;
     if (fused && C.kind != 2) {
-      const bool timed = P->prof_on && i == 0;
+      const bool timed = P->prof_on && i == 0 && nr == 1;
       hdg_problem::Pending pd{2 * APPLY_RES_PRESTRICT + pr, nullptr, nullptr};
       if (timed) {
         pd.a = take_event(P);
         pd.b = take_event(P);
         HDG_CHECK(hipEventRecord(pd.a, st));
       }
-      launch_res_prestrict<T>(L, C, e, r, rc, (T*)C.e[pr], P->rd.Jp, st);
+      launch_res_prestrict<T>(L, C, e, r, rc, (T*)C.e[pr], P->rd.Jp, st, nr);
       if (timed) {
         HDG_CHECK(hipEventRecord(pd.b, st));
         P->pending.push_back(pd);
       }
-      ec = vcycle<T>(P, i + 1, rc, nullptr, true);
+      ec = vcycle<T>(P, i + 1, rc, nullptr, true, nr);
     } else {
-      apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc);
-      ec = vcycle<T>(P, i + 1, rc, nullptr);
+      apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc, nr);
+      ec = vcycle<T>(P, i + 1, rc, nullptr, false, nr);
     }
-    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st);
+    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st, nr);
   } else if (fused) {
     T* cb = (T*)L.cb[pr];
-    launch_hpre<T>(L, r, e, (lc & HDG_LC_PRE) ? 1 : 0, cb, st);
+    launch_hpre<T>(L, r, e, (lc & HDG_LC_PRE) ? 1 : 0, cb, st, nr);
     const T* ec;
     if (C.kind == 2) {
-      launch_hsum<T>(L, C, r, cb, nullptr, (T*)C.e[pr], st);
+      launch_hsum<T>(L, C, r, cb, nullptr, (T*)C.e[pr], st, nr);
       ec = (const T*)C.e[pr];
     } else {
-      launch_hsum<T>(L, C, r, cb, rc, (T*)C.e[pr], st);
-      ec = vcycle<T>(P, i + 1, rc, nullptr, true);
+      launch_hsum<T>(L, C, r, cb, rc, (T*)C.e[pr], st, nr);
+      ec = vcycle<T>(P, i + 1, rc, nullptr, true, nr);
     }
-    launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st);
+    launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st, nr);
     std::swap(e, w);
   } else {
-    apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
-    launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st);
-    launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st);
-    const T* ec = vcycle<T>(P, i + 1, rc, nullptr);
-    launch_hprolong<T>(L, C, ec, e, st);
+    apply<T>(P, i, APPLY_RES, e, r, w, nullptr, nr);
+    launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st, nr);
+    launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st, nr);
+    const T* ec = vcycle<T>(P, i + 1, rc, nullptr, false, nr);
+    launch_hprolong<T>(L, C, ec, e, st, nr);
     if (lc & HDG_LC_POST) {
-      apply<T>(P, i, APPLY_RES, e, r, w, nullptr);
-      launch_hcorr<T>(L, w, e, 1, 0, nullptr, st);
+      apply<T>(P, i, APPLY_RES, e, r, w, nullptr, nr);
+      launch_hcorr<T>(L, w, e, 1, 0, nullptr, st, nr);
     }
   }
   for (int s = 0; s < m; ++s) {
     T* dst = (out && s == m - 1) ? out : w;
-    apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr);
+    apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
     if (dst == w)
       std::swap(e, w);
     else
       e = dst;
   }
   if (out && e != out) {
-    blas_copy_t<T>(out, e, L.nlam, st);
+    blas_copy_t<T>(out, e, L.nlam, st, nr);
     e = out;
   }
   return e;
@@ -346,6 +357,14 @@ void precond(hdg_problem* P, const double* r, double* z, bool mixed) {
   blas_f2d(e32, z, P->N, P->st);
 }
 
+// the scalar blocks of the first nr right-hand sides, on the host
+const double* read_scalars(hdg_problem* P, int nr) {
+  HDG_CHECK(hipMemcpyAsync(P->hpin, P->s.sc, sizeof(double) * SC_COUNT * nr, hipMemcpyDeviceToHost, P->st));
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  if (!P->pending.empty()) harvest(P);
+  return P->hpin;
+}
+
 double read_scalar(hdg_problem* P, const double* dptr) {
   HDG_CHECK(hipMemcpyAsync(P->hpin, dptr, sizeof(double), hipMemcpyDeviceToHost, P->st));
   HDG_CHECK(hipStreamSynchronize(P->st));
@@ -357,23 +376,27 @@ void residual(hdg_problem* P, const double* lam, const double* g, double* r) {
   apply<double>(P, 0, APPLY_RES, lam, g, r, nullptr);
 }
 
+// outer iterations launched between two reads of the residual history
+constexpr int CHECK_EVERY = 4;
+
 struct SolveOut {
   int iters = 0;
   double relres = 0.0;
   hdg_status status = HDG_OK;
 };
 
-// r = g - A lam and ||r||^2 in one pass (plus the FP32 copy of r when mixed)
-void residual_norm(hdg_problem* P, const double* lam, const double* g, bool mixed) {
+// r = g - A lam and ||r||^2 in one pass (plus the FP32 copy of r when mixed),
+// for nr right-hand sides
+void residual_norm(hdg_problem* P, const double* lam, const double* g, bool mixed, int nr) {
   float* r32 = mixed ? P->r32 : nullptr;
-  const bool timed = P->prof_on;
+  const bool timed = P->prof_on && nr == 1;
   hdg_problem::Pending pd{2 * APPLY_RES + 0, nullptr, nullptr};
   if (timed) {
     pd.a = take_event(P);
     pd.b = take_event(P);
     HDG_CHECK(hipEventRecord(pd.a, P->st));
   }
-  launch_apply_red<double>(P->L[0], APPLY_RES_NORM, lam, g, P->r, nullptr, nullptr, r32, &P->s, P->st);
+  launch_apply_red<double>(P->L[0], APPLY_RES_NORM, lam, g, P->r, nullptr, nullptr, r32, &P->s, P->st, nr);
   if (timed) {
     HDG_CHECK(hipEventRecord(pd.b, P->st));
     P->pending.push_back(pd);
@@ -381,30 +404,93 @@ void residual_norm(hdg_problem* P, const double* lam, const double* g, bool mixe
 }
 
 // z = B r: FP64 V-cycle on r, or FP32 V-cycle on the FP32 copy r32 into z32
-void precond_fused(hdg_problem* P, bool mixed) {
+void precond_fused(hdg_problem* P, bool mixed, int nr) {
   if (mixed)
-    vcycle<float>(P, 0, P->r32, P->z32);
+    vcycle<float>(P, 0, P->r32, P->z32, false, nr);
   else
-    vcycle<double>(P, 0, P->r, P->z);
+    vcycle<double>(P, 0, P->r, P->z, false, nr);
 }
 
-SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
+// Convergence bookkeeping of nr right-hand sides iterated together: the
+// residual history of each since the last reset of the count, its first
+// converged iteration, and the worst residual of the returned iterates.
+struct Tracker {
+  int nr = 1;
+  double tol = 0.0;
+  const double* gn = nullptr;
+  int first[64];
+  bool bad = false;
+  void init(int n, double t, const double* g) {
+    nr = n;
+    tol = t;
+    gn = g;
+    for (int r = 0; r < nr; ++r) first[r] = -1;
+  }
+  // scan a group of `cnt` iterations that started at iteration `base`
+  bool scan(const double* sc, int base, int cnt, double* worst_last) {
+    bool all = true;
+    double w = 0.0;
+    for (int r = 0; r < nr; ++r) {
+      const double* h = sc + (long)r * SC_COUNT + SC_HIST;
+      for (int it = 0; it < cnt && first[r] < 0; ++it) {
+        const double rel = std::sqrt(h[it]) / gn[r];
+        if (!std::isfinite(rel)) bad = true;
+        if (rel <= tol) first[r] = base + it + 1;
+      }
+      const double last = std::sqrt(h[cnt - 1]) / gn[r];
+      if (!std::isfinite(last)) bad = true;
+      w = std::max(w, last);
+      if (first[r] < 0) all = false;
+    }
+    *worst_last = w;
+    return all;
+  }
+  int iters() const {
+    int m = 0;
+    for (int r = 0; r < nr; ++r) m = std::max(m, first[r]);
+    return m;
+  }
+};
+
+double worst_rnorm(const double* sc, int nr, const double* gn) {
+  double w = 0.0;
+  for (int r = 0; r < nr; ++r) {
+    const double rel = std::sqrt(sc[(long)r * SC_COUNT + SC_RNORM2]) / gn[r];
+    if (!std::isfinite(rel)) return rel;
+    w = std::max(w, rel);
+  }
+  return w;
+}
+
+SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, const double* gn, bool mixed, int nr) {
   SolveOut o;
   const long N = P->N;
-  residual_norm(P, lam, g, mixed);
-  double rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
-  while (rel > tol && o.iters < P->opts.max_it && std::isfinite(rel)) {
-    run_graph(P, mixed ? G_MGMX : G_MG64, [&] {
-      precond_fused(P, mixed);
-      if (mixed)
-        blas_add<float>(lam, P->z32, N, P->st);
-      else
-        blas_add<double>(lam, P->z, N, P->st);
-      residual_norm(P, lam, g, mixed);
-    });
-    rel = std::sqrt(read_scalar(P, P->s.sc + SC_RNORM2)) / gn;
-    ++o.iters;
+  residual_norm(P, lam, g, mixed, nr);
+  double rel = worst_rnorm(read_scalars(P, nr), nr, gn);
+  Tracker tr;
+  tr.init(nr, tol, gn);
+  int launched = 0;
+  bool all = rel <= tol;
+  while (!all && launched < P->opts.max_it && std::isfinite(rel)) {
+    const int grp = std::min(CHECK_EVERY, P->opts.max_it - launched);
+    for (int r = 0; r < nr; ++r) blas_fill<double>(P->s.sc + (long)r * SC_COUNT + SC_HCNT, 0.0, 1, P->st);
+    for (int it = 0; it < grp; ++it)
+      run_graph(
+          P, mixed ? G_MGMX : G_MG64,
+          [&] {
+            precond_fused(P, mixed, nr);
+            if (mixed)
+              blas_add<float>(lam, P->z32, N, P->st, nr);
+            else
+              blas_add<double>(lam, P->z, N, P->st, nr);
+            residual_norm(P, lam, g, mixed, nr);
+          },
+          nr);
+    all = tr.scan(read_scalars(P, nr), launched, grp, &rel);
+    launched += grp;
+    if (tr.bad) rel = std::numeric_limits<double>::quiet_NaN();
   }
+  o.iters = all ? tr.iters() : launched;
   o.relres = rel;
   o.status = !std::isfinite(rel) ? HDG_ERR_BREAKDOWN : (rel <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED);
   return o;
@@ -413,67 +499,83 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, doub
 // Preconditioned CG.  FP64: Fletcher-Reeves beta.  Mixed (FP32 V-cycle, not
 // exactly symmetric): flexible Polak-Ribiere beta = (r.z - r.z_old) / rz_old.
 // r.z_old is accumulated in the update pass, while z still holds z_old.
-SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, double gn, bool mixed) {
+// nr right-hand sides iterate together, each with its own scalars; the
+// solve ends when every one has met the tolerance.
+SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, const double* gn, bool mixed, int nr) {
   SolveOut o;
   const long N = P->N;
-  double* sc = P->s.sc;
+  Tracker tr;
+  tr.init(nr, tol, gn);
+  int launched = 0;
   for (;;) {
-    residual_norm(P, lam, g, mixed);
-    double rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
+    residual_norm(P, lam, g, mixed, nr);
+    double rel = worst_rnorm(read_scalars(P, nr), nr, gn);
     o.relres = rel;
     if (!std::isfinite(rel)) {
       o.status = HDG_ERR_BREAKDOWN;
       return o;
     }
-    if (rel <= tol || o.iters >= P->opts.max_it) break;
-    precond_fused(P, mixed);
+    if (rel <= tol || launched >= P->opts.max_it) break;
+    precond_fused(P, mixed, nr);
     if (mixed) {
-      blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st);
-      blas_f2d(P->z32, P->p, N, P->st);
+      blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st, nr);
+      blas_f2d(P->z32, P->p, N, P->st, nr);
     } else {
-      blas_rz<double>(P->r, P->z, N, FIN_RZ0, P->s, P->st);
-      blas_copy(P->p, P->z, N, P->st);
+      blas_rz<double>(P->r, P->z, N, FIN_RZ0, P->s, P->st, nr);
+      blas_copy(P->p, P->z, N, P->st, nr);
     }
     // one CG iteration per graph launch: lambda and r are updated first, so
     // after convergence the trailing preconditioner application and
-    // direction update change nothing that is returned
-    while (o.iters < P->opts.max_it) {
-      run_graph(P, mixed ? G_PCGMX : G_PCG64, [&] {
-        hipStream_t s2 = P->st;
-        const bool timed = P->prof_on;
-        hdg_problem::Pending pd{2 * APPLY_Y + 0, nullptr, nullptr};
-        if (timed) {
-          pd.a = take_event(P);
-          pd.b = take_event(P);
-          HDG_CHECK(hipEventRecord(pd.a, s2));
-        }
-        launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s, s2);
-        if (timed) {
-          HDG_CHECK(hipEventRecord(pd.b, s2));
-          P->pending.push_back(pd);
-        }
-        if (mixed)
-          blas_cg_update2<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, P->s, s2);
-        else
-          blas_cg_update2<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, P->s, s2);
-        precond_fused(P, mixed);
-        if (mixed) {
-          blas_rz<float>(P->r, P->z32, N, FIN_BETA_FLEX, P->s, s2);
-          blas_cg_dir<float>(P->p, P->z32, N, P->s, s2);
-        } else {
-          blas_rz<double>(P->r, P->z, N, FIN_BETA, P->s, s2);
-          blas_cg_dir<double>(P->p, P->z, N, P->s, s2);
-        }
-      });
-      ++o.iters;
-      rel = std::sqrt(read_scalar(P, sc + SC_RNORM2)) / gn;
-      if (rel <= tol || !std::isfinite(rel)) break;
+    // direction update change nothing that is returned.  Launches go out in
+    // groups of up to CHECK_EVERY with one read of the residual histories per
+    // group; iterations past the first converged one only refine lambda.
+    tr.init(nr, tol, gn);
+    bool done = false;
+    while (!done && launched < P->opts.max_it) {
+      const int grp = std::min(CHECK_EVERY, P->opts.max_it - launched);
+      for (int r = 0; r < nr; ++r) blas_fill<double>(P->s.sc + (long)r * SC_COUNT + SC_HCNT, 0.0, 1, P->st);
+      for (int it = 0; it < grp; ++it)
+        run_graph(
+            P, mixed ? G_PCGMX : G_PCG64,
+            [&] {
+              hipStream_t s2 = P->st;
+              const bool timed = P->prof_on && nr == 1;
+              hdg_problem::Pending pd{2 * APPLY_Y + 0, nullptr, nullptr};
+              if (timed) {
+                pd.a = take_event(P);
+                pd.b = take_event(P);
+                HDG_CHECK(hipEventRecord(pd.a, s2));
+              }
+              launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s,
+                                       s2, nr);
+              if (timed) {
+                HDG_CHECK(hipEventRecord(pd.b, s2));
+                P->pending.push_back(pd);
+              }
+              if (mixed)
+                blas_cg_update2<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, P->s, s2, nr);
+              else
+                blas_cg_update2<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, P->s, s2, nr);
+              precond_fused(P, mixed, nr);
+              if (mixed) {
+                blas_rz<float>(P->r, P->z32, N, FIN_BETA_FLEX, P->s, s2, nr);
+                blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
+              } else {
+                blas_rz<double>(P->r, P->z, N, FIN_BETA, P->s, s2, nr);
+                blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
+              }
+            },
+            nr);
+      done = tr.scan(read_scalars(P, nr), launched, grp, &rel);
+      launched += grp;
+      if (tr.bad) {
+        o.relres = std::numeric_limits<double>::quiet_NaN();
+        o.status = HDG_ERR_BREAKDOWN;
+        o.iters = launched;
+        return o;
+      }
     }
-    if (!std::isfinite(rel)) {
-      o.relres = rel;
-      o.status = HDG_ERR_BREAKDOWN;
-      return o;
-    }
+    o.iters = done ? std::max(o.iters, tr.iters()) : launched;
     // confirm with the true residual (loop again from the current iterate)
   }
   o.status = o.relres <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED;
@@ -538,39 +640,66 @@ void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, d
   launch_load_pull(P->d, P->k, P->n, P->ework, P->Ae, gdir, g, P->st);
 }
 
-hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, hdg_solve_info* info) {
+// Solve for the nr right-hand sides already in P->g (initial guesses in
+// P->lam), all iterated together (MG, PCG) or one after another (GMRES).
+hdg_status solve_many(hdg_problem* P, int nr, double tol, hdg_solve_info* info) {
   const long N = P->N;
   if (N == 0) {
     if (info) info->relres = 0.0;
     return HDG_OK;
   }
-  blas_dot(g, g, N, P->s, FIN_STORE, P->s.sc + SC_GNORM2, P->st);
-  const double gn = std::sqrt(read_scalar(P, P->s.sc + SC_GNORM2));
-  if (!std::isfinite(gn)) return HDG_ERR_BREAKDOWN;
-  if (gn == 0.0) {
-    blas_fill<double>(lam, 0.0, N, P->st);
-    if (info) {
-      info->iters = 0;
-      info->relres = 0.0;
+  blas_dot(P->g, P->g, N, P->s, FIN_GNORM, nullptr, P->st, nr);
+  const double* sc = read_scalars(P, nr);
+  double gn[64];
+  for (int r = 0; r < nr; ++r) {
+    gn[r] = std::sqrt(sc[(long)r * SC_COUNT + SC_GNORM2]);
+    if (!std::isfinite(gn[r])) return HDG_ERR_BREAKDOWN;
+    if (gn[r] == 0.0) {
+      // zero data: the solution is zero
+      blas_fill<double>(P->lam + r * N, 0.0, N, P->st);
+      gn[r] = 1.0;
     }
-    return HDG_OK;
   }
   const bool mixed = P->opts.precision == HDG_MIXED;
-  // iterate in the handle's own buffers so captured graphs see fixed pointers
-  if (g != P->g) blas_copy(P->g, g, N, P->st);
-  if (lam != P->lam) blas_copy(P->lam, lam, N, P->st);
   SolveOut o;
   switch (P->opts.method) {
-    case HDG_METHOD_PCG: o = solve_pcg(P, P->g, P->lam, tol, gn, mixed); break;
-    case HDG_METHOD_GMRES: o = solve_gmres(P, P->g, P->lam, tol, gn, mixed); break;
-    default: o = solve_mg(P, P->g, P->lam, tol, gn, mixed); break;
+    case HDG_METHOD_PCG: o = solve_pcg(P, P->g, P->lam, tol, gn, mixed, nr); break;
+    case HDG_METHOD_GMRES: {
+      hdg_status worst = HDG_OK;
+      for (int r = 0; r < nr; ++r) {
+        if (r > 0) {  // GMRES works on the first right-hand side's buffers
+          blas_copy(P->g, P->g + r * N, N, P->st);
+          blas_copy(P->lam, P->lam + r * N, N, P->st);
+        }
+        SolveOut q = solve_gmres(P, P->g, P->lam, tol, gn[r], mixed);
+        if (r > 0) blas_copy(P->lam + r * N, P->lam, N, P->st);
+        o.iters = std::max(o.iters, q.iters);
+        o.relres = std::max(o.relres, q.relres);
+        if (q.status != HDG_OK && worst == HDG_OK) worst = q.status;
+      }
+      o.status = worst;
+      break;
+    }
+    default: o = solve_mg(P, P->g, P->lam, tol, gn, mixed, nr); break;
   }
-  if (lam != P->lam) blas_copy(lam, P->lam, N, P->st);
   if (info) {
     info->iters += o.iters;
     info->relres = std::max(info->relres, o.relres);
   }
   return o.status;
+}
+
+hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, hdg_solve_info* info) {
+  if (P->N == 0) {
+    if (info) info->relres = 0.0;
+    return HDG_OK;
+  }
+  // iterate in the handle's own buffers so captured graphs see fixed pointers
+  if (g != P->g) blas_copy(P->g, g, P->N, P->st);
+  if (lam != P->lam) blas_copy(P->lam, lam, P->N, P->st);
+  hdg_status s = solve_many(P, 1, tol, info);
+  if (lam != P->lam) blas_copy(lam, P->lam, P->N, P->st);
+  return s;
 }
 
 }  // namespace
@@ -589,6 +718,7 @@ void hdg_default_opts(hdg_mg_opts* o) {
   o->max_it = 200;
   o->restart = 0;
   o->coarse_n = 2;
+  o->nrhs = 1;
 }
 
 const char* hdg_status_string(hdg_status s) {
@@ -661,15 +791,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->ework = dalloc<double>(P, P->nelem * (P->nv + P->nl), false);
   P->bad = dalloc<int>(P, 1, false);
   HDG_CHECK(hipHostMalloc((void**)&P->hbad, sizeof(int) * 4, hipHostMallocDefault));
-  HDG_CHECK(hipHostMalloc((void**)&P->hpin, sizeof(double) * 16, hipHostMallocDefault));
-  P->s.sc = dalloc<double>(P, SC_COUNT, false);
-  {
-    // partial sums of the reductions: one per block of the widest launch
-    const long nface0 = (long)P->d * (P->n - 1) * ipow(P->n, P->d - 1);
-    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
-    P->s.partials = dalloc<double>(P, 2 * nb, false);
-  }
-  HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT, P->st));
+  HDG_CHECK(hipHostMalloc((void**)&P->hpin, sizeof(double) * SC_COUNT * HDG_MAX_NRHS, hipHostMallocDefault));
   if (!check_kappa(P, kappa, kappa_kind)) {
     hdg_destroy(P);
     return HDG_ERR_INVALID_ARG;
@@ -711,13 +833,17 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     hdg_default_opts(&o);
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
-      o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0)
+      o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
+      o.nrhs > HDG_MAX_NRHS)
     return HDG_ERR_INVALID_ARG;
+  if (o.nrhs < 1) o.nrhs = 1;
   if (o.coarse_n < 2) o.coarse_n = 2;
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   free_build(P);
   P->opts = o;
+  P->cap = o.nrhs;
+  const int cap = P->cap;
   const int d = P->d;
   const int nc = 1 << (d - 1);
   std::vector<Level>& L = P->L;
@@ -747,8 +873,8 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     F.AIIinv32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.nI), true);
     F.P64 = dalloc<double>(P, pm * vpad<double>(F.nI * F.ncl), true);
     F.P32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.ncl), true);
-    F.cb[0] = dalloc<double>(P, F.nmacro * F.ncl, true);
-    F.cb[1] = dalloc<float>(P, F.nmacro * F.ncl, true);
+    F.cb[0] = dalloc<double>(P, F.nmacro * F.ncl * cap, true);
+    F.cb[1] = dalloc<float>(P, F.nmacro * F.ncl * cap, true);
     C.Aelem = dalloc<double>(P, C.nelem * C.nl * C.nl, true);
     launch_macro_schur(F, C, P->st);
   }
@@ -772,9 +898,9 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
       const size_t es = pr == 0 ? sizeof(double) : sizeof(float);
       for (void** slot : {&Li.r[pr], &Li.e[pr], &Li.w[pr]}) {
         if (pr == 0)
-          *slot = dalloc<double>(P, Li.nlam, true);
+          *slot = dalloc<double>(P, Li.nlam * cap, true);
         else
-          *slot = dalloc<float>(P, Li.nlam, true);
+          *slot = dalloc<float>(P, Li.nlam * cap, true);
         (void)es;
       }
     }
@@ -829,15 +955,24 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
 
   P->N = L[0].nlam;
   const long N = P->N;
-  P->g = dalloc<double>(P, N, true);
-  P->r = dalloc<double>(P, N, true);
-  P->z = dalloc<double>(P, N, true);
-  P->p = dalloc<double>(P, N, true);
-  P->Ap = dalloc<double>(P, N, true);
-  P->zold = dalloc<double>(P, N, true);
-  P->lam = dalloc<double>(P, N, true);
-  P->r32 = dalloc<float>(P, N, true);
-  P->z32 = dalloc<float>(P, N, true);
+  const long Nc = N * cap;
+  P->g = dalloc<double>(P, Nc, true);
+  P->r = dalloc<double>(P, Nc, true);
+  P->z = dalloc<double>(P, Nc, true);
+  P->p = dalloc<double>(P, Nc, true);
+  P->Ap = dalloc<double>(P, Nc, true);
+  P->zold = dalloc<double>(P, Nc, true);
+  P->lam = dalloc<double>(P, Nc, true);
+  P->r32 = dalloc<float>(P, Nc, true);
+  P->z32 = dalloc<float>(P, Nc, true);
+  {
+    // device scalars and reduction partials, one row per right-hand side
+    P->s.sc = dalloc<double>(P, (long)SC_COUNT * cap, true);
+    const long nface0 = L[0].nface;
+    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
+    P->s.partials = dalloc<double>(P, 2 * nb * cap, true);
+    HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT * cap, P->st));
+  }
   if (o.method == HDG_METHOD_GMRES) {
     const int m = o.restart > 0 ? std::min(o.restart, std::max(o.max_it, 1)) : std::max(o.max_it, 1);
     P->gm_m = m;
@@ -860,12 +995,12 @@ hdg_status hdg_vcycle(hdg_handle P, const void* r, void* e, int precision, int n
   if (!P->built) return HDG_ERR_STATE;
   if (precision != HDG_FP64 && precision != HDG_FP32) return HDG_ERR_INVALID_ARG;
   HDG_GUARD_BEGIN
-  for (int i = 0; i < nrhs; ++i) {
-    if (P->N == 0) break;
+  for (int i0 = 0; i0 < nrhs && P->N > 0; i0 += P->cap) {
+    const int nr = std::min(P->cap, nrhs - i0);
     if (precision == HDG_FP64)
-      vcycle<double>(P, 0, (const double*)r + i * P->N, (double*)e + i * P->N);
+      vcycle<double>(P, 0, (const double*)r + i0 * P->N, (double*)e + i0 * P->N, false, nr);
     else
-      vcycle<float>(P, 0, (const float*)r + i * P->N, (float*)e + i * P->N);
+      vcycle<float>(P, 0, (const float*)r + i0 * P->N, (float*)e + i0 * P->N, false, nr);
   }
   return HDG_OK;
   HDG_GUARD_END
@@ -880,12 +1015,10 @@ hdg_status hdg_rhs(hdg_handle P, const double* rhs, int rhs_kind, const double* 
   HDG_GUARD_END
 }
 
-hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, int nrhs, double tol,
-                     double* lambda, hdg_solve_info* info) {
-  if (!P || !rhs || !lambda || nrhs < 1 || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
-  if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
-  if (!P->built) return HDG_ERR_STATE;
-  HDG_GUARD_BEGIN
+namespace {
+// hdg_solve on the handle's current stream (shared by hdg_solve_batch)
+hdg_status solve_rhs_set(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, int nrhs, double tol,
+                         double* lambda, hdg_solve_info* info) {
   if (info) {
     info->iters = 0;
     info->relres = 0.0;
@@ -898,15 +1031,20 @@ hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double
   HDG_CHECK(hipEventRecord(e0, P->st));
   hdg_status worst = HDG_OK;
   const long vstride = P->nelem * P->nv;
-  for (int i = 0; i < nrhs; ++i) {
-    const double* g = nullptr;
-    if (rhs_kind == HDG_RHS_TRACE) {
-      g = rhs + i * P->N;
-    } else {
-      form_rhs(P, rhs + i * vstride, rhs_kind, gdir, P->g);
-      g = P->g;
+  const long N = P->N;
+  // right-hand sides go through in groups of the build's capacity, each group
+  // iterated together
+  for (int i0 = 0; i0 < nrhs && N > 0; i0 += P->cap) {
+    const int nr = std::min(P->cap, nrhs - i0);
+    for (int r = 0; r < nr; ++r) {
+      if (rhs_kind == HDG_RHS_TRACE)
+        blas_copy(P->g + r * N, rhs + (i0 + r) * N, N, P->st);
+      else
+        form_rhs(P, rhs + (i0 + r) * vstride, rhs_kind, gdir, P->g + r * N);
     }
-    hdg_status s = solve_one(P, g, lambda + i * P->N, tol, info);
+    blas_copy(P->lam, lambda + i0 * N, N, P->st, nr);
+    hdg_status s = solve_many(P, nr, tol, info);
+    blas_copy(lambda + i0 * N, P->lam, N, P->st, nr);
     if (s != HDG_OK && worst == HDG_OK) worst = s;
   }
   HDG_CHECK(hipEventRecord(e1, P->st));
@@ -917,6 +1055,140 @@ hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double
   HDG_CHECK(hipEventDestroy(e0));
   HDG_CHECK(hipEventDestroy(e1));
   return worst;
+}
+}  // namespace
+
+hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, int nrhs, double tol,
+                     double* lambda, hdg_solve_info* info) {
+  if (!P || !rhs || !lambda || nrhs < 1 || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
+  if (!P->built) return HDG_ERR_STATE;
+  HDG_GUARD_BEGIN
+  return solve_rhs_set(P, rhs, rhs_kind, gdir, nrhs, tol, lambda, info);
+  HDG_GUARD_END
+}
+
+hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const* rhs, int rhs_kind,
+                           const int* nrhs, double tol, double* const* lambda, hdg_solve_info* info,
+                           int nstreams) {
+  if (nprob < 1 || !hs || !rhs || !nrhs || !lambda || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
+  for (int i = 0; i < nprob; ++i) {
+    if (!hs[i] || !rhs[i] || !lambda[i] || nrhs[i] < 1) return HDG_ERR_INVALID_ARG;
+    if (!hs[i]->built) return HDG_ERR_STATE;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return HDG_ERR_INVALID_ARG;  // a handle is not thread-safe
+  }
+  if (nstreams <= 0) nstreams = 4;
+  nstreams = std::min(std::min(nstreams, 16), nprob);
+  std::vector<hipStream_t> ws(nstreams, nullptr);
+  std::vector<hdg_status> st(nprob, HDG_OK);
+  try {
+    for (auto& w : ws) HDG_CHECK(hipStreamCreateWithFlags(&w, hipStreamNonBlocking));
+  } catch (const HipError& e) {
+    for (auto& w : ws)
+      if (w) (void)hipStreamDestroy(w);
+    return map_error(e);
+  }
+  std::atomic<int> next{0};
+  auto worker = [&](int t) {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= nprob) return;
+      hdg_problem* P = hs[i];
+      hipStream_t orig = P->st;
+      hipEvent_t ev = nullptr;
+      try {
+        // order after the work already queued on the handle's stream, run on
+        // the worker's stream, then order the handle's stream after it
+        HDG_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HDG_CHECK(hipEventRecord(ev, orig));
+        HDG_CHECK(hipStreamWaitEvent(ws[t], ev, 0));
+        P->st = ws[t];
+        st[i] = solve_rhs_set(P, rhs[i], rhs_kind, nullptr, nrhs[i], tol, lambda[i], info ? info + i : nullptr);
+        HDG_CHECK(hipEventRecord(ev, ws[t]));
+        P->st = orig;
+        HDG_CHECK(hipStreamWaitEvent(orig, ev, 0));
+      } catch (const HipError& e) {
+        P->st = orig;
+        st[i] = map_error(e);
+      } catch (const std::bad_alloc&) {
+        P->st = orig;
+        st[i] = HDG_ERR_DEVICE;
+      }
+      if (ev) (void)hipEventDestroy(ev);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 0; t < nstreams; ++t) th.emplace_back(worker, t);
+  for (auto& t : th) t.join();
+  for (auto& w : ws) {
+    (void)hipStreamSynchronize(w);
+    (void)hipStreamDestroy(w);
+  }
+  hdg_status worst = HDG_OK;
+  for (int i = 0; i < nprob; ++i)
+    if (st[i] != HDG_OK && (worst == HDG_OK || st[i] == HDG_ERR_DEVICE)) worst = st[i];
+  return worst;
+}
+
+hdg_status hdg_autotune(hdg_handle P, const hdg_mg_opts* base, int nrhs, hdg_mg_opts* best, double* us_per_rhs_it) {
+  if (!P || !best || nrhs < 1 || nrhs > HDG_MAX_NRHS) return HDG_ERR_INVALID_ARG;
+  hdg_mg_opts b0;
+  if (base)
+    b0 = *base;
+  else
+    hdg_default_opts(&b0);
+  HDG_GUARD_BEGIN
+  // candidates: coarsest macro grid x right-hand-side group size; scored by
+  // the stream time of a fixed number of outer iterations per right-hand side
+  const int coarse[3] = {2, 8, 16};
+  const int groups[7] = {1, 2, 4, 8, 16, 32, 64};
+  constexpr int ITS = 6;
+  double best_us = 0.0;
+  hdg_mg_opts bo = b0;
+  bool have = false;
+  hipEvent_t e0, e1;
+  HDG_CHECK(hipEventCreate(&e0));
+  HDG_CHECK(hipEventCreate(&e1));
+  for (int ci = 0; ci < 3; ++ci) {
+    if (ci > 0 && coarse[ci] >= P->n) continue;  // same hierarchy as a smaller candidate
+    for (int gi = 0; gi < 7; ++gi) {
+      const int g = groups[gi];
+      if (g > nrhs) break;
+      hdg_mg_opts o = b0;
+      o.coarse_n = coarse[ci];
+      o.nrhs = g;
+      o.max_it = ITS;
+      const hdg_status sb = hdg_mg_build(P, &o);
+      if (sb != HDG_OK) continue;
+      const long N = P->N;
+      if (N == 0) continue;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graphs
+        blas_fill<double>(P->g, 1.0, N, P->st, g);
+        blas_fill<double>(P->lam, 0.0, N, P->st, g);
+        HDG_CHECK(hipEventRecord(e0, P->st));
+        (void)solve_many(P, g, 1e-300, nullptr);
+        HDG_CHECK(hipEventRecord(e1, P->st));
+        HDG_CHECK(hipEventSynchronize(e1));
+        HDG_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      const double us = 1e3 * ms / ((double)ITS * g);
+      if (!have || us < best_us) {
+        best_us = us;
+        bo = o;
+        have = true;
+      }
+    }
+  }
+  HDG_CHECK(hipEventDestroy(e0));
+  HDG_CHECK(hipEventDestroy(e1));
+  if (!have) return HDG_ERR_UNSUPPORTED;
+  bo.max_it = b0.max_it;
+  *best = bo;
+  if (us_per_rhs_it) *us_per_rhs_it = best_us;
+  return hdg_mg_build(P, &bo);
   HDG_GUARD_END
 }
 

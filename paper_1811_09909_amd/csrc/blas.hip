@@ -9,6 +9,11 @@
 // with each other, so a per-block release fence costs an L2 write-back and a
 // per-block atomic on one counter serialises; the kernel boundary is the
 // cheap synchronisation point.
+//
+// Several right-hand sides: vectors of length n stored one after another,
+// blockIdx.y selects one; each has its own scalar block (sc + rhs * SC_COUNT)
+// and its own row of partials ([rhs][blocks]); the finaliser runs one block
+// per right-hand side.
 #include "blas.hpp"
 #include "hdg_internal.hpp"
 #include "reduce.hpp"
@@ -25,6 +30,9 @@ __device__ inline double block_sum(double v, double* sh) { return block_sum_t<RB
 __global__ void __launch_bounds__(RB) dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                                  long n, double* __restrict__ partials) {
   __shared__ double sh[RB / 64];
+  x += blockIdx.y * n;
+  y += blockIdx.y * n;
+  partials += blockIdx.y * (long)gridDim.x;
   double v = 0.0;
   for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
 #pragma unroll
@@ -41,6 +49,9 @@ __global__ void __launch_bounds__(RB) dot_kernel(const double* __restrict__ x, c
 __global__ void __launch_bounds__(RB) finalize_kernel(const double* __restrict__ partials, int nb, int nv, int mode,
                                                       double* sc, double* out) {
   __shared__ double sh[RB / 64];
+  partials += blockIdx.x * (long)nb * nv;
+  sc += blockIdx.x * (long)SC_COUNT;
+  if (out) out += blockIdx.x;
   double tot[2] = {0.0, 0.0};
   for (int v = 0; v < nv; ++v) {
     double a = 0.0;
@@ -50,30 +61,38 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double* __restrict__
   }
   if (threadIdx.x != 0) return;
   const double t0 = tot[0], t1 = tot[1];
+  // a zero denominator only occurs once the residual is exactly zero: the
+  // step is then zero instead of 0/0
   switch (mode) {
     case FIN_STORE: *out = t0; break;
     case FIN_ALPHA:
       sc[SC_PAP] = t0;
-      sc[SC_ALPHA] = sc[SC_RZ] / t0;
+      sc[SC_ALPHA] = t0 != 0.0 ? sc[SC_RZ] / t0 : 0.0;
       break;
     case FIN_BETA:
-      sc[SC_BETA] = t0 / sc[SC_RZ];
+      sc[SC_BETA] = sc[SC_RZ] != 0.0 ? t0 / sc[SC_RZ] : 0.0;
       sc[SC_RZ] = t0;
       break;
     case FIN_BETA_FLEX:
-      sc[SC_BETA] = (t0 - sc[SC_RZOLD]) / sc[SC_RZ];
+      sc[SC_BETA] = sc[SC_RZ] != 0.0 ? (t0 - sc[SC_RZOLD]) / sc[SC_RZ] : 0.0;
       sc[SC_RZ] = t0;
       break;
     case FIN_RZ0: sc[SC_RZ] = t0; break;
+    case FIN_GNORM: sc[SC_GNORM2] = t0; break;
     case FIN_NORM_INV:
       *out = sqrt(t0);
       sc[SC_TMP] = t0 > 0.0 ? 1.0 / sqrt(t0) : 0.0;
       break;
-    case FIN_RNORM: sc[SC_RNORM2] = t0; break;
-    case FIN_RNORM_RZOLD:
+    case FIN_RNORM:
+    case FIN_RNORM_RZOLD: {
       sc[SC_RNORM2] = t0;
-      sc[SC_RZOLD] = t1;
+      if (mode == FIN_RNORM_RZOLD) sc[SC_RZOLD] = t1;
+      // history of squared residual norms since the host last reset the count
+      const int c = (int)sc[SC_HCNT];
+      if (c >= 0 && c < HIST_MAX) sc[SC_HIST + c] = t0;
+      sc[SC_HCNT] = (double)(c + 1);
       break;
+    }
   }
 }
 
@@ -87,6 +106,17 @@ __global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam
                                                         const double* __restrict__ Ap, const ZT* __restrict__ z,
                                                         long n, double* __restrict__ partials, const double* sc) {
   __shared__ double sh[RB / 64];
+  {
+    const long o = blockIdx.y * n;
+    lam += o;
+    r += o;
+    r32 = r32 ? r32 + o : r32;
+    p += o;
+    Ap += o;
+    z += o;
+    partials += blockIdx.y * 2L * gridDim.x;
+    sc += blockIdx.y * (long)SC_COUNT;
+  }
   const double alpha = sc[SC_ALPHA];
   double rr = 0.0, rz = 0.0;
   for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
@@ -117,6 +147,9 @@ template <typename ZT>
 __global__ void __launch_bounds__(RB) rz_kernel(const double* __restrict__ r, const ZT* __restrict__ z, long n,
                                                 double* __restrict__ partials) {
   __shared__ double sh[RB / 64];
+  r += blockIdx.y * n;
+  z += blockIdx.y * n;
+  partials += blockIdx.y * (long)gridDim.x;
   double v = 0.0;
   for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
 #pragma unroll
@@ -132,13 +165,17 @@ __global__ void __launch_bounds__(RB) rz_kernel(const double* __restrict__ r, co
 // p = z + beta p
 template <typename ZT>
 __global__ void cg_dir_kernel(double* __restrict__ p, const ZT* __restrict__ z, long n, const double* sc) {
-  const double beta = sc[SC_BETA];
+  p += blockIdx.y * n;
+  z += blockIdx.y * n;
+  const double beta = sc[blockIdx.y * (long)SC_COUNT + SC_BETA];
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) p[i] = (double)z[i] + beta * p[i];
 }
 
 // lam += z (z FP64 or FP32)
 template <typename ZT>
 __global__ void add_kernel(double* __restrict__ lam, const ZT* __restrict__ z, long n) {
+  lam += blockIdx.y * n;
+  z += blockIdx.y * n;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) lam[i] += (double)z[i];
 }
 
@@ -157,16 +194,21 @@ __global__ void scale_kernel(double* __restrict__ y, const double* __restrict__ 
 
 template <typename A, typename B>
 __global__ void convert_kernel(const A* __restrict__ x, B* __restrict__ y, long n) {
+  x += blockIdx.y * n;
+  y += blockIdx.y * n;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = (B)x[i];
 }
 
 template <typename T>
 __global__ void fill_kernel(T* __restrict__ y, T v, long n) {
+  y += blockIdx.y * n;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = v;
 }
 
 template <typename T>
 __global__ void copy_t_kernel(T* __restrict__ y, const T* __restrict__ x, long n) {
+  y += blockIdx.y * n;
+  x += blockIdx.y * n;
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) y[i] = x[i];
 }
 
@@ -232,56 +274,58 @@ inline unsigned rg(long n) {
 
 }  // namespace
 
-void blas_finalize(int nb, int nv, int mode, double* out, Scratch& s, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(RB), 0, st, s.partials, nb, nv, mode, s.sc, out);
+void blas_finalize(int nb, int nv, int mode, double* out, Scratch& s, hipStream_t st, int nrhs) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(RB), 0, st, s.partials, nb, nv, mode, s.sc, out);
   HDG_CHECK(hipGetLastError());
 }
 
-void blas_dot(const double* x, const double* y, long n, Scratch& s, int mode, double* out, hipStream_t st) {
+void blas_dot(const double* x, const double* y, long n, Scratch& s, int mode, double* out, hipStream_t st,
+              int nrhs) {
   const unsigned nb = rg(n);
-  hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(RB), 0, st, x, y, n, s.partials);
+  hipLaunchKernelGGL(dot_kernel, dim3(nb, nrhs), dim3(RB), 0, st, x, y, n, s.partials);
   HDG_CHECK(hipGetLastError());
-  blas_finalize((int)nb, 1, mode, out, s, st);
+  blas_finalize((int)nb, 1, mode, out, s, st, nrhs);
 }
 
 template <typename ZT>
 void blas_cg_update2(double* lam, double* r, float* r32, const double* p, const double* Ap, const ZT* z, long n,
-                     Scratch& s, hipStream_t st) {
+                     Scratch& s, hipStream_t st, int nrhs) {
   const unsigned nb = rg(n);
-  hipLaunchKernelGGL((cg_update2_kernel<ZT>), dim3(nb), dim3(RB), 0, st, lam, r, r32, p, Ap, z, n, s.partials, s.sc);
+  hipLaunchKernelGGL((cg_update2_kernel<ZT>), dim3(nb, nrhs), dim3(RB), 0, st, lam, r, r32, p, Ap, z, n, s.partials,
+                     s.sc);
   HDG_CHECK(hipGetLastError());
-  blas_finalize((int)nb, 2, FIN_RNORM_RZOLD, nullptr, s, st);
+  blas_finalize((int)nb, 2, FIN_RNORM_RZOLD, nullptr, s, st, nrhs);
 }
 template void blas_cg_update2<double>(double*, double*, float*, const double*, const double*, const double*, long,
-                                      Scratch&, hipStream_t);
+                                      Scratch&, hipStream_t, int);
 template void blas_cg_update2<float>(double*, double*, float*, const double*, const double*, const float*, long,
-                                     Scratch&, hipStream_t);
+                                     Scratch&, hipStream_t, int);
 
 template <typename ZT>
-void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st) {
+void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st, int nrhs) {
   const unsigned nb = rg(n);
-  hipLaunchKernelGGL((rz_kernel<ZT>), dim3(nb), dim3(RB), 0, st, r, z, n, s.partials);
+  hipLaunchKernelGGL((rz_kernel<ZT>), dim3(nb, nrhs), dim3(RB), 0, st, r, z, n, s.partials);
   HDG_CHECK(hipGetLastError());
-  blas_finalize((int)nb, 1, mode, nullptr, s, st);
+  blas_finalize((int)nb, 1, mode, nullptr, s, st, nrhs);
 }
-template void blas_rz<double>(const double*, const double*, long, int, Scratch&, hipStream_t);
-template void blas_rz<float>(const double*, const float*, long, int, Scratch&, hipStream_t);
+template void blas_rz<double>(const double*, const double*, long, int, Scratch&, hipStream_t, int);
+template void blas_rz<float>(const double*, const float*, long, int, Scratch&, hipStream_t, int);
 
 template <typename ZT>
-void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st) {
-  hipLaunchKernelGGL((cg_dir_kernel<ZT>), dim3(gs(n)), dim3(256), 0, st, p, z, n, s.sc);
+void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st, int nrhs) {
+  hipLaunchKernelGGL((cg_dir_kernel<ZT>), dim3(gs(n), nrhs), dim3(256), 0, st, p, z, n, s.sc);
   HDG_CHECK(hipGetLastError());
 }
-template void blas_cg_dir<double>(double*, const double*, long, Scratch&, hipStream_t);
-template void blas_cg_dir<float>(double*, const float*, long, Scratch&, hipStream_t);
+template void blas_cg_dir<double>(double*, const double*, long, Scratch&, hipStream_t, int);
+template void blas_cg_dir<float>(double*, const float*, long, Scratch&, hipStream_t, int);
 
 template <typename ZT>
-void blas_add(double* lam, const ZT* z, long n, hipStream_t st) {
-  hipLaunchKernelGGL((add_kernel<ZT>), dim3(gs(n)), dim3(256), 0, st, lam, z, n);
+void blas_add(double* lam, const ZT* z, long n, hipStream_t st, int nrhs) {
+  hipLaunchKernelGGL((add_kernel<ZT>), dim3(gs(n), nrhs), dim3(256), 0, st, lam, z, n);
   HDG_CHECK(hipGetLastError());
 }
-template void blas_add<double>(double*, const double*, long, hipStream_t);
-template void blas_add<float>(double*, const float*, long, hipStream_t);
+template void blas_add<double>(double*, const double*, long, hipStream_t, int);
+template void blas_add<float>(double*, const float*, long, hipStream_t, int);
 
 void blas_axpy(double* y, const double* x, long n, const double* coef, double sign, hipStream_t st) {
   hipLaunchKernelGGL(axpy_kernel, dim3(gs(n)), dim3(256), 0, st, y, x, n, coef, sign);
@@ -293,39 +337,41 @@ void blas_scale(double* y, const double* x, long n, const double* coef, hipStrea
   HDG_CHECK(hipGetLastError());
 }
 
-void blas_d2f(const double* x, float* y, long n, hipStream_t st) {
+void blas_d2f(const double* x, float* y, long n, hipStream_t st, int nrhs) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(gs(n)), dim3(256), 0, st, x, y, n);
+  hipLaunchKernelGGL((convert_kernel<double, float>), dim3(gs(n), nrhs), dim3(256), 0, st, x, y, n);
   HDG_CHECK(hipGetLastError());
 }
 
-void blas_f2d(const float* x, double* y, long n, hipStream_t st) {
+void blas_f2d(const float* x, double* y, long n, hipStream_t st, int nrhs) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(gs(n)), dim3(256), 0, st, x, y, n);
+  hipLaunchKernelGGL((convert_kernel<float, double>), dim3(gs(n), nrhs), dim3(256), 0, st, x, y, n);
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void blas_copy_t(T* y, const T* x, long n, hipStream_t st) {
+void blas_copy_t(T* y, const T* x, long n, hipStream_t st, int nrhs) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((copy_t_kernel<T>), dim3(gs(n)), dim3(256), 0, st, y, x, n);
+  hipLaunchKernelGGL((copy_t_kernel<T>), dim3(gs(n), nrhs), dim3(256), 0, st, y, x, n);
   HDG_CHECK(hipGetLastError());
 }
-template void blas_copy_t<double>(double*, const double*, long, hipStream_t);
-template void blas_copy_t<float>(float*, const float*, long, hipStream_t);
+template void blas_copy_t<double>(double*, const double*, long, hipStream_t, int);
+template void blas_copy_t<float>(float*, const float*, long, hipStream_t, int);
 
-void blas_copy(double* y, const double* x, long n, hipStream_t st) { blas_copy_t<double>(y, x, n, st); }
+void blas_copy(double* y, const double* x, long n, hipStream_t st, int nrhs) {
+  blas_copy_t<double>(y, x, n, st, nrhs);
+}
 
 template <typename T>
-void blas_fill(T* y, T v, long n, hipStream_t st) {
+void blas_fill(T* y, T v, long n, hipStream_t st, int nrhs) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((fill_kernel<T>), dim3(gs(n)), dim3(256), 0, st, y, v, n);
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(gs(n), nrhs), dim3(256), 0, st, y, v, n);
   HDG_CHECK(hipGetLastError());
 }
-template void blas_fill<double>(double*, double, long, hipStream_t);
-template void blas_fill<float>(float*, float, long, hipStream_t);
-template void blas_fill<unsigned>(unsigned*, unsigned, long, hipStream_t);
-template void blas_fill<int>(int*, int, long, hipStream_t);
+template void blas_fill<double>(double*, double, long, hipStream_t, int);
+template void blas_fill<float>(float*, float, long, hipStream_t, int);
+template void blas_fill<unsigned>(unsigned*, unsigned, long, hipStream_t, int);
+template void blas_fill<int>(int*, int, long, hipStream_t, int);
 
 void blas_gmres_rot(double* H, double* cs, double* sn, double* s, int j, int ld, double* sc, hipStream_t st) {
   hipLaunchKernelGGL(gmres_rot_kernel, dim3(1), dim3(64), 0, st, H, cs, sn, s, j, ld, sc);

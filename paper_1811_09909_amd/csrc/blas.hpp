@@ -6,7 +6,9 @@ namespace hdg {
 
 enum {
   SC_RZ = 0, SC_PAP = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RNORM2 = 4, SC_GNORM2 = 5, SC_TMP = 6, SC_GRES = 7,
-  SC_HNORM = 8, SC_RZOLD = 10, SC_COUNT = 16
+  SC_HNORM = 8, SC_RZOLD = 10, SC_HCNT = 11, SC_HIST = 16,
+  HIST_MAX = 64,                   // residual norms kept between two host reads
+  SC_COUNT = SC_HIST + HIST_MAX
 };
 // finalisers of a reduction (applied by the one-block finaliser)
 enum {
@@ -17,36 +19,40 @@ enum {
   FIN_NORM_INV = 4,     // *out = sqrt(s), tmp = 1 / sqrt(s)
   FIN_BETA_FLEX = 5,    // beta = (s - rzold) / rz, rz = s
   FIN_RNORM = 6,        // rnorm2 = s
-  FIN_RNORM_RZOLD = 7   // rnorm2 = s0, rzold = s1
+  FIN_RNORM_RZOLD = 7,  // rnorm2 = s0, rzold = s1
+  FIN_GNORM = 8         // gnorm2 = s
 };
 
 constexpr int MAX_RED_BLOCKS = 4096;
 
 struct Scratch {
-  double* sc = nullptr;        // device scalars [SC_COUNT]
-  double* partials = nullptr;  // [2 * max(MAX_RED_BLOCKS, blocks of the widest reducing launch)]
+  double* sc = nullptr;        // device scalars [nrhs][SC_COUNT]
+  double* partials = nullptr;  // [nrhs][2 * max(MAX_RED_BLOCKS, blocks of the widest reducing launch)]
 };
 
-void blas_finalize(int nb, int nv, int mode, double* out, Scratch& s, hipStream_t st);
-void blas_dot(const double* x, const double* y, long n, Scratch& s, int mode, double* out, hipStream_t st);
+// nrhs: vectors of length n stored one after another; each right-hand side
+// has its own scalars (sc + rhs * SC_COUNT) and row of partials.
+void blas_finalize(int nb, int nv, int mode, double* out, Scratch& s, hipStream_t st, int nrhs = 1);
+void blas_dot(const double* x, const double* y, long n, Scratch& s, int mode, double* out, hipStream_t st,
+              int nrhs = 1);
 template <typename ZT>
 void blas_cg_update2(double* lam, double* r, float* r32, const double* p, const double* Ap, const ZT* z, long n,
-                     Scratch& s, hipStream_t st);
+                     Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
-void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st);
+void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
-void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st);
+void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
-void blas_add(double* lam, const ZT* z, long n, hipStream_t st);
+void blas_add(double* lam, const ZT* z, long n, hipStream_t st, int nrhs = 1);
 void blas_axpy(double* y, const double* x, long n, const double* coef, double sign, hipStream_t st);
 void blas_scale(double* y, const double* x, long n, const double* coef, hipStream_t st);
-void blas_d2f(const double* x, float* y, long n, hipStream_t st);
-void blas_f2d(const float* x, double* y, long n, hipStream_t st);
-void blas_copy(double* y, const double* x, long n, hipStream_t st);
+void blas_d2f(const double* x, float* y, long n, hipStream_t st, int nrhs = 1);
+void blas_f2d(const float* x, double* y, long n, hipStream_t st, int nrhs = 1);
+void blas_copy(double* y, const double* x, long n, hipStream_t st, int nrhs = 1);
 template <typename T>
-void blas_copy_t(T* y, const T* x, long n, hipStream_t st);
+void blas_copy_t(T* y, const T* x, long n, hipStream_t st, int nrhs = 1);
 template <typename T>
-void blas_fill(T* y, T v, long n, hipStream_t st);
+void blas_fill(T* y, T v, long n, hipStream_t st, int nrhs = 1);
 void blas_gmres_rot(double* H, double* cs, double* sn, double* s, int j, int ld, double* sc, hipStream_t st);
 void blas_gmres_backsolve(const double* H, const double* s, int j, int ld, double* y, hipStream_t st);
 void blas_gmres_combine(double* x, const double* Z, long ldz, int j, const double* y, long n, hipStream_t st);

@@ -142,33 +142,37 @@ void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double*
 void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st);
 void launch_coarse_inverse(const Level& L, hipStream_t st);
 
-// trace.hip
+// trace.hip.  Every launcher takes nrhs right-hand sides stored one after
+// another (stride: the level's vector length) and runs them in one launch.
 template <typename T>
 void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
-                  hipStream_t st);
+                  hipStream_t st, int nrhs = 1);
 template <typename T>
-void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st);
+void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
-void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st);
+void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
-void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st);
+void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st,
+                  int nrhs = 1);
 template <typename T>
-void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st);
+void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st,
+                      int nrhs = 1);
 template <typename T>
-void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st);
+void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
-void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st);
+void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
 void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
-                          hipStream_t st);
+                          hipStream_t st, int nrhs = 1);
 // fused 2D h-transition kernels
 template <typename T>
-void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st);
+void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st, int nrhs = 1);
 template <typename T>
-void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st);
+void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st,
+                 int nrhs = 1);
 template <typename T>
 void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const T* eold, T* enew, int do_corr,
-                  hipStream_t st);
+                  hipStream_t st, int nrhs = 1);
 
 // single-workgroup coarse tail of the V-cycle (tail.hip)
 constexpr int TAIL_MAX_LEVELS = 12;
@@ -187,12 +191,12 @@ struct TailArgs {
   void* eout = nullptr;
 };
 template <typename T>
-void launch_tail(const TailArgs& a, hipStream_t st);
+void launch_tail(const TailArgs& a, hipStream_t st, int nrhs = 1);
 
 enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5 };
 struct Scratch;
 template <typename T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
-                      Scratch* red, hipStream_t st);
+                      Scratch* red, hipStream_t st, int nrhs = 1);
 
 }  // namespace hdg

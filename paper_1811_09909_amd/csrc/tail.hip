@@ -29,9 +29,11 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(TailArgs a) {
   const TailLevel& L0 = a.lev[0];
   T* r0 = arena + L0.off_r;
   T* e0 = arena + L0.off_e;
+  // one workgroup per right-hand side (stored one after another)
+  const long roff = blockIdx.y * L0.nlam;
   for (long i = tid; i < L0.nlam; i += nt) {
-    r0[i] = reinterpret_cast<const T*>(a.rin)[i];
-    if (a.pre_done) e0[i] = reinterpret_cast<const T*>(a.ein)[i];
+    r0[i] = reinterpret_cast<const T*>(a.rin)[roff + i];
+    if (a.pre_done) e0[i] = reinterpret_cast<const T*>(a.ein)[roff + i];
   }
   __syncthreads();
   if (!a.pre_done) {
@@ -104,17 +106,17 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(TailArgs a) {
     cur[l] = c;
   }
   const T* res = arena + (cur[0] == 0 ? L0.off_e : L0.off_w);
-  for (long i = tid; i < L0.nlam; i += nt) reinterpret_cast<T*>(a.eout)[i] = res[i];
+  for (long i = tid; i < L0.nlam; i += nt) reinterpret_cast<T*>(a.eout)[roff + i] = res[i];
 }
 
 }  // namespace
 
 template <typename T>
-void launch_tail(const TailArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((tail_kernel<T>), dim3(1), dim3(TAIL_THREADS), 0, st, a);
+void launch_tail(const TailArgs& a, hipStream_t st, int nrhs) {
+  hipLaunchKernelGGL((tail_kernel<T>), dim3(1, nrhs), dim3(TAIL_THREADS), 0, st, a);
   HDG_CHECK(hipGetLastError());
 }
-template void launch_tail<double>(const TailArgs&, hipStream_t);
-template void launch_tail<float>(const TailArgs&, hipStream_t);
+template void launch_tail<double>(const TailArgs&, hipStream_t, int);
+template void launch_tail<float>(const TailArgs&, hipStream_t, int);
 
 }  // namespace hdg

@@ -35,10 +35,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
                                                     T* __restrict__ rc, float* __restrict__ y32,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials, int nrhs) {
   constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
-  const long F = xcd_face<D>(n, blockIdx.x, threadIdx.x);
+  constexpr int NC = 1 << (D - 1);
+  int rhs;
+  unsigned slot;
+  const long F = xcd_face_rhs<D>(n, nrhs, blockIdx.x, threadIdx.x, &rhs, &slot);
   if (!RED && F < 0) return;
+  {
+    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
+    x += rhs * sN;
+    bvec = off(bvec, rhs * sN);
+    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
+    rc = off(rc, rhs * sC);
+    y32 = off(y32, rhs * sN);
+  }
   double part = 0.0;
   if (F >= 0) {
   T acc[NE];
@@ -55,7 +66,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
     for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
     dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
-    constexpr int NC = 1 << (D - 1);
     T res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
@@ -89,7 +99,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
   if constexpr (RED) {
     __shared__ double sh[4];
     const double s = block_sum_t<256>(part, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[slot] = s;
   }
 }
 
@@ -98,6 +108,8 @@ template <int NE, typename T>
 __global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* __restrict__ r, T* __restrict__ e) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
+  r += blockIdx.y * nface * NE;
+  e += blockIdx.y * nface * NE;
   jacobi0_item<NE, T>(F, Dinv, r, e);
 }
 
@@ -107,6 +119,8 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
                                  T* __restrict__ e) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
+  ec += blockIdx.y * nface * NC;
+  e += blockIdx.y * nface * NE;
   T cv[NC];
 #pragma unroll
   for (int v = 0; v < NC; ++v) cv[v] = ec[F * NC + v];
@@ -135,6 +149,12 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
   for (int a = 0; a < D; ++a) nmacro *= nm;
   const long M = blockIdx.x * 256L + threadIdx.x;
   if (M >= nmacro) return;
+  {
+    const long sF = trace_len<D>(n, NC);
+    rho += blockIdx.y * sF;
+    e += blockIdx.y * sF;
+    cb = off(cb, blockIdx.y * nmacro * NCL);
+  }
   int m[3] = {0, 0, 0};
   decode_elem<D>(M, nm, m);
   T rI[NI];
@@ -175,6 +195,13 @@ __global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __re
   const long ncf = D * nface_dir<D>(nm);
   const long Fc = blockIdx.x * 256L + threadIdx.x;
   if (Fc >= ncf) return;
+  {
+    long nmacro = 1;
+    for (int a = 0; a < D; ++a) nmacro *= nm;
+    rho += blockIdx.y * trace_len<D>(n, NC);
+    cb += blockIdx.y * nmacro * NCL;
+    rc += blockIdx.y * ncf * NC;
+  }
   int G[3] = {0, 0, 0};
   const int c = decode_face<D>(Fc, nm, G);
   T out[NC];
@@ -213,6 +240,8 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
   constexpr int NI = NIF * NC;
   constexpr int NCL = 2 * D * NC;
   const int nm = n / 2;
+  ec += blockIdx.y * trace_len<D>(nm, NC);
+  e += blockIdx.y * trace_len<D>(n, NC);
   if (blockIdx.x < nbm) {
     long nmacro = 1;
     for (int a = 0; a < D; ++a) nmacro *= nm;
@@ -275,6 +304,8 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
 
 template <typename T>
 __global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
+  r += blockIdx.y * (long)N;
+  e += blockIdx.y * (long)N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     T s = T(0);
     for (int j = 0; j < N; ++j) s += Ainv[i * N + j] * r[j];
@@ -288,14 +319,24 @@ __global__ void __launch_bounds__(256) hpre_kernel(int n, const T* __restrict__ 
                                                    T* __restrict__ e, int do_corr, T* __restrict__ cb) {
   const long nmacro = (long)(n / 2) * (n / 2);
   const long M = blockIdx.x * 256L + threadIdx.x;
+  r += blockIdx.y * trace_len<2>(n, 2);
+  e += blockIdx.y * trace_len<2>(n, 2);
+  cb += blockIdx.y * nmacro * 8;
   if (M < nmacro) hpre_item<2, T>(M, n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
 template <int D, typename T>
 __global__ void hsum_kernel(int n, const T* __restrict__ r, const T* __restrict__ cb, const T* __restrict__ Dc,
                             T* __restrict__ rc, T* __restrict__ ec) {
+  constexpr int NC = 1 << (D - 1);
   const long ncf = D * nface_dir<D>(n / 2);
   const long Fc = blockIdx.x * 256L + threadIdx.x;
+  long nmacro = 1;
+  for (int a = 0; a < D; ++a) nmacro *= n / 2;
+  r += blockIdx.y * trace_len<D>(n, NC);
+  cb += blockIdx.y * nmacro * 2 * D * NC;
+  rc = off(rc, blockIdx.y * ncf * NC);
+  ec = off(ec, blockIdx.y * ncf * NC);
   if (Fc < ncf) hsum_item<D, T>(Fc, n, r, cb, Dc, rc, ec);
 }
 
@@ -304,6 +345,14 @@ __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __
                                                     const T* __restrict__ AIIinv, const T* __restrict__ P,
                                                     const T* __restrict__ r, const T* __restrict__ ec,
                                                     const T* __restrict__ eold, T* __restrict__ enew, int do_corr) {
+  {
+    constexpr int NC = 1 << (D - 1);
+    const long sF = trace_len<D>(n, NC);
+    r += blockIdx.y * sF;
+    eold += blockIdx.y * sF;
+    enew += blockIdx.y * sF;
+    ec += blockIdx.y * trace_len<D>(n / 2, NC);
+  }
   if (blockIdx.x < nbm) {
     const long nmacro = (long)(n / 2) * (n / 2);
     const long M = blockIdx.x * 256L + threadIdx.x;
@@ -325,6 +374,13 @@ __global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T
   __shared__ T rcs[64];
   const int nm = n / 2;
   const long ncf = D * nface_dir<D>(nm);
+  {
+    long nmacro = 1;
+    for (int a = 0; a < D; ++a) nmacro *= nm;
+    r += blockIdx.y * trace_len<D>(n, NC);
+    cb += blockIdx.y * nmacro * NCL;
+    ec += blockIdx.y * (long)N;
+  }
   for (long Fc = threadIdx.x; Fc < ncf; Fc += blockDim.x) {
     int G[3] = {0, 0, 0};
     const int c = decode_face<D>(Fc, nm, G);
@@ -364,6 +420,8 @@ __global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* _
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
+  r += blockIdx.y * (long)N;
+  e += blockIdx.y * (long)N;
   double s = 0.0;
   for (int j = lane; j < N; j += 64) s += (double)Ainv[(long)row * N + j] * (double)r[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -398,13 +456,13 @@ void dispatch_d_ne(int d, int ne, F&& f) {
 
 template <typename T>
 void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
-                  hipStream_t st) {
-  launch_apply_red<T>(L, mode, x, b, y, Jp, rc, nullptr, nullptr, st);
+                  hipStream_t st, int nrhs) {
+  launch_apply_red<T>(L, mode, x, b, y, Jp, rc, nullptr, nullptr, st, nrhs);
 }
 
 template <typename T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
-                      Scratch* red, hipStream_t st) {
+                      Scratch* red, hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
   double* partials = red ? red->partials : nullptr;
   const T* Af = nullptr;
@@ -416,11 +474,12 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     Af = (const T*)L.Af32;
     Dv = (const T*)L.Dinv32;
   }
+  const unsigned g1 = xcd_grid(L.d, L.n);
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
-#define HDG_AK(MM)                                                                                   \
-  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(xcd_grid(L.d, L.n)), dim3(256), 0, st, L.n, Af, Dv, x, b, \
-                     y, Jp, rc, y32, partials)
+#define HDG_AK(MM)                                                                                             \
+  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, Dv, x, b, y, \
+                     Jp, rc, y32, partials, nrhs)
     switch (mode) {
       case APPLY_Y: HDG_AK(APPLY_Y); break;
       case APPLY_RES: HDG_AK(APPLY_RES); break;
@@ -434,151 +493,155 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
   });
   HDG_CHECK(hipGetLastError());
   if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
-    blas_finalize((int)xcd_grid(L.d, L.n), 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st);
+    blas_finalize((int)g1, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
 }
 
 // residual of level L restricted to P1 on the same faces (level C), and when
 // ec is given the first block-Jacobi step of C on it
 template <typename T>
 void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
-                          hipStream_t st) {
+                          hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Dc = sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
-    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(xcd_grid(L.d, L.n)), dim3(256), 0, st,
-                       L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr);
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(xcd_grid(L.d, L.n) * (unsigned)nrhs),
+                       dim3(256), 0, st, L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr, nrhs);
   });
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st) {
+void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
   const T* Dv = sizeof(T) == 8 ? (const T*)L.Dinv64 : (const T*)L.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int NE = decltype(NE_)::value;
-    hipLaunchKernelGGL((jacobi0_kernel<NE, T>), dim3(nblk(L.nface)), dim3(256), 0, st, L.nface, Dv, r, e);
+    hipLaunchKernelGGL((jacobi0_kernel<NE, T>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r, e);
   });
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st) {
+void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
     constexpr int NC = 1 << (D - 1);
-    hipLaunchKernelGGL((prolong_p_kernel<NE, NC, T>), dim3(nblk(L.nface)), dim3(256), 0, st, L.nface, Jp, ec, e);
+    hipLaunchKernelGGL((prolong_p_kernel<NE, NC, T>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Jp, ec,
+                       e);
   });
   (void)nc;
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st) {
+void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st, int nrhs) {
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   if (L.d == 2)
-    hipLaunchKernelGGL((hcorr_kernel<2, T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Ai, P, rho, e, do_corr,
-                       do_restrict, cb);
+    hipLaunchKernelGGL((hcorr_kernel<2, T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
+                       do_corr, do_restrict, cb);
   else
-    hipLaunchKernelGGL((hcorr_kernel<3, T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Ai, P, rho, e, do_corr,
-                       do_restrict, cb);
+    hipLaunchKernelGGL((hcorr_kernel<3, T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
+                       do_corr, do_restrict, cb);
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st) {
+void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st, int nrhs) {
   if (C.nface == 0) return;
   if (L.d == 2)
-    hipLaunchKernelGGL((hrestrict_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, rho, cb, rc);
+    hipLaunchKernelGGL((hrestrict_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, rho, cb, rc);
   else
-    hipLaunchKernelGGL((hrestrict_kernel<3, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, rho, cb, rc);
+    hipLaunchKernelGGL((hrestrict_kernel<3, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, rho, cb, rc);
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st) {
+void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs) {
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
   if (L.d == 2)
-    hipLaunchKernelGGL((hprolong_kernel<2, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, P, ec, e);
+    hipLaunchKernelGGL((hprolong_kernel<2, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P, ec,
+                       e);
   else
-    hipLaunchKernelGGL((hprolong_kernel<3, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, P, ec, e);
+    hipLaunchKernelGGL((hprolong_kernel<3, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P, ec,
+                       e);
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st) {
+void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) {
   if (L.nlam == 0) return;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.Ainv64 : (const T*)L.Ainv32;
   if (L.nlam > 64) {
-    hipLaunchKernelGGL((coarse_gemv_kernel<T>), dim3((unsigned)((L.nlam + 3) / 4)), dim3(256), 0, st, (int)L.nlam, Ai,
-                       r, e);
+    hipLaunchKernelGGL((coarse_gemv_kernel<T>), dim3((unsigned)((L.nlam + 3) / 4), nrhs), dim3(256), 0, st,
+                       (int)L.nlam, Ai, r, e);
     HDG_CHECK(hipGetLastError());
     return;
   }
-  hipLaunchKernelGGL((coarse_solve_kernel<T>), dim3(1), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
+  hipLaunchKernelGGL((coarse_solve_kernel<T>), dim3(1, nrhs), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
   HDG_CHECK(hipGetLastError());
 }
 
 
 template <typename T>
-void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st) {
+void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st, int nrhs) {
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro)), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr, cb);
+  hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr,
+                     cb);
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
-void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st) {
+void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc, T* ec, hipStream_t st, int nrhs) {
   if (C.kind == 2 && C.nlam <= 64) {
     const T* Ai = sizeof(T) == 8 ? (const T*)C.Ainv64 : (const T*)C.Ainv32;
-    hipLaunchKernelGGL((hsum_solve_kernel<2, T>), dim3(1), dim3(64), 0, st, L.n, (int)C.nlam, r, cb, Ai, ec);
+    hipLaunchKernelGGL((hsum_solve_kernel<2, T>), dim3(1, nrhs), dim3(64), 0, st, L.n, (int)C.nlam, r, cb, Ai, ec);
   } else if (C.kind == 2) {
     // restricted residual into C.r, then the dense coarsest solve
-    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, r, cb, (const T*)nullptr,
-                       (T*)C.r[sizeof(T) == 8 ? 0 : 1], (T*)nullptr);
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, r, cb,
+                       (const T*)nullptr, (T*)C.r[sizeof(T) == 8 ? 0 : 1], (T*)nullptr);
     HDG_CHECK(hipGetLastError());
-    launch_coarse_solve<T>(C, (const T*)C.r[sizeof(T) == 8 ? 0 : 1], ec, st);
+    launch_coarse_solve<T>(C, (const T*)C.r[sizeof(T) == 8 ? 0 : 1], ec, st, nrhs);
   } else {
     const T* Dc = ec ? (sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32) : nullptr;
-    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface)), dim3(256), 0, st, L.n, r, cb, Dc, rc, ec);
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, r, cb, Dc, rc, ec);
   }
   HDG_CHECK(hipGetLastError());
 }
 
 template <typename T>
 void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const T* eold, T* enew, int do_corr,
-                  hipStream_t st) {
+                  hipStream_t st, int nrhs) {
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   const long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
-  hipLaunchKernelGGL((hpost_kernel<2, T>), dim3((unsigned)(nbm + nbf)), dim3(256), 0, st, L.n, nbm, Af, Ai, P, r, ec,
-                     eold, enew, do_corr);
+  hipLaunchKernelGGL((hpost_kernel<2, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai, P,
+                     r, ec, eold, enew, do_corr);
   HDG_CHECK(hipGetLastError());
 }
 
-#define HDG_INST(T)                                                                                         \
-  template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t);  \
-  template void launch_apply_red<T>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,     \
-                                    Scratch*, hipStream_t);                                                  \
-  template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t);                                  \
-  template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t);            \
-  template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t);                      \
-  template void launch_hrestrict<T>(const Level&, const Level&, const T*, const T*, T*, hipStream_t);        \
-  template void launch_hprolong<T>(const Level&, const Level&, const T*, T*, hipStream_t);                   \
-  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t);                             \
-  template void launch_hpre<T>(const Level&, const T*, T*, int, T*, hipStream_t);                            \
-  template void launch_res_prestrict<T>(const Level&, const Level&, const T*, const T*, T*, T*, const double*, \
-                                        hipStream_t);                                                        \
-  template void launch_hsum<T>(const Level&, const Level&, const T*, const T*, T*, T*, hipStream_t);         \
-  template void launch_hpost<T>(const Level&, const Level&, const T*, const T*, const T*, T*, int, hipStream_t);
+#define HDG_INST(T)                                                                                              \
+  template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t, int);  \
+  template void launch_apply_red<T>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,          \
+                                    Scratch*, hipStream_t, int);                                                  \
+  template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t, int);                                  \
+  template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t, int);            \
+  template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t, int);                      \
+  template void launch_hrestrict<T>(const Level&, const Level&, const T*, const T*, T*, hipStream_t, int);        \
+  template void launch_hprolong<T>(const Level&, const Level&, const T*, T*, hipStream_t, int);                   \
+  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t, int);                             \
+  template void launch_hpre<T>(const Level&, const T*, T*, int, T*, hipStream_t, int);                            \
+  template void launch_res_prestrict<T>(const Level&, const Level&, const T*, const T*, T*, T*, const double*,      \
+                                        hipStream_t, int);                                                        \
+  template void launch_hsum<T>(const Level&, const Level&, const T*, const T*, T*, T*, hipStream_t, int);         \
+  template void launch_hpost<T>(const Level&, const Level&, const T*, const T*, const T*, T*, int, hipStream_t, int);
 HDG_INST(double)
 HDG_INST(float)
 #undef HDG_INST

@@ -123,6 +123,20 @@ __device__ inline long elem_id(const int* e, int n) {
   return T;
 }
 
+// length of the trace vector of a level with n^D elements and ne values per
+// face (interior faces only); several right-hand sides are stored one after
+// another with this stride
+template <int D>
+__device__ inline long trace_len(int n, int ne) {
+  return (long)D * nface_dir<D>(n) * ne;
+}
+
+// p + k, or null when p is null
+template <typename P>
+__device__ inline P off(P p, long k) {
+  return p ? p + k : p;
+}
+
 // XCD-aware face blocks.  Workgroups are dealt to the 8 XCDs round-robin
 // (workgroup p runs on XCD p % 8), and each XCD has its own L2.  The faces of
 // each normal direction are cut into 8 contiguous chunks of C blocks of 256;
@@ -137,6 +151,24 @@ __device__ inline long xcd_face(int n, unsigned p, unsigned tid) {
   const unsigned C = ((nfd + 255u) / 256u + 7u) / 8u;
   const unsigned j = p & 7u, m = p >> 3;
   const unsigned c = m / C, w = m - c * C;
+  const unsigned local = (j * C + w) * 256u + tid;
+  if (c >= (unsigned)D || local >= nfd) return -1;
+  return (long)c * nfd + local;
+}
+
+// Several right-hand sides: the right-hand side index runs fastest after the
+// XCD, so the nrhs workgroups that read the same operator chunk are dealt to
+// the same XCD back to back and share it through its L2.  Also returns the
+// right-hand side and a reduction slot laid out [rhs][8 * D * C].
+template <int D>
+__device__ inline long xcd_face_rhs(int n, int nrhs, unsigned p, unsigned tid, int* rhs, unsigned* slot) {
+  const unsigned nfd = (unsigned)nface_dir<D>(n);
+  const unsigned C = ((nfd + 255u) / 256u + 7u) / 8u;
+  const unsigned j = p & 7u, m = p >> 3;
+  const unsigned r = m % (unsigned)nrhs, m2 = m / (unsigned)nrhs;
+  *rhs = (int)r;
+  *slot = r * (8u * D * C) + j + 8u * m2;
+  const unsigned c = m2 / C, w = m2 - c * C;
   const unsigned local = (j * C + w) * 256u + tid;
   if (c >= (unsigned)D || local >= nfd) return -1;
   return (long)c * nfd + local;

@@ -69,8 +69,8 @@ class Problem:
         self.built = False
 
     def build(self, sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-              max_it=200, restart=0, coarse_n=2):
-        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n)
+              max_it=200, restart=0, coarse_n=2, nrhs=1):
+        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n, nrhs)
         L.check(self.lib.hdg_mg_build(self.h, ctypes.byref(o)), "hdg_mg_build")
         self.built = True
         self.opts = o
@@ -99,6 +99,24 @@ class Problem:
                                         ctypes.byref(info)), "hdg_solve", allow)
         return lam, {"iters": info.iters, "relres": info.relres, "t_solve_ms": info.t_solve_ms,
                      "n_levels": info.n_levels, "status": st}
+
+    def autotune(self, nrhs, **base):
+        """Pick the fastest coarsest grid and right-hand-side group size for
+        `nrhs` right-hand sides on top of the build options `base` (see
+        hdg_autotune); leaves the handle built with them."""
+        defaults = dict(sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
+                        max_it=200, restart=0, coarse_n=2, nrhs=1)
+        defaults.update(base)
+        o = L.Opts(*[defaults[k] for k in ("sweeps", "growth", "omega", "local_corr", "precision", "method",
+                                            "max_it", "restart", "coarse_n", "nrhs")])
+        best = L.Opts()
+        us = ctypes.c_double()
+        L.check(self.lib.hdg_autotune(self.h, ctypes.byref(o), int(nrhs), ctypes.byref(best), ctypes.byref(us)),
+                "hdg_autotune")
+        self.built = True
+        self.opts = best
+        self.n_levels = self.query(L.Q_NLEVELS)
+        return {"coarse_n": best.coarse_n, "nrhs": best.nrhs, "us_per_rhs_iter": us.value}
 
     def vcycle(self, r, precision=L.FP64):
         dt = torch.float64 if precision == L.FP64 else torch.float32
@@ -194,6 +212,26 @@ class Problem:
     def volume_qpoints(self):
         """[N_T, (k+2)^d, d] coordinates of the Gauss points (host tensor)."""
         return self._tensor_points(self.reference_nodes()[1])
+
+
+def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=4):
+    """Solve problem i for its right-hand sides rhs[i] ([nrhs_i, ...] nodal
+    sources, or trace vectors for kind=RHS_TRACE) with hdg_solve_batch: the
+    problems run concurrently on `nstreams` streams.  Returns the list of
+    solutions [nrhs_i, N_lambda_i] and the list of solve infos."""
+    n = len(problems)
+    rhs_t = [_dev(r, torch.float64, p.device) for p, r in zip(problems, rhs)]
+    nr = [(r.numel() // (p.nlam if kind == L.RHS_TRACE else p.nT * p.nv)) for p, r in zip(problems, rhs_t)]
+    lam = [torch.zeros(k * p.nlam, dtype=torch.float64, device=p.device) for p, k in zip(problems, nr)]
+    handles = (ctypes.c_void_p * n)(*[p.h.value for p in problems])
+    rp = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rhs_t])
+    lp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in lam])
+    nrh = (ctypes.c_int * n)(*nr)
+    infos = (L.Info * n)()
+    lib = problems[0].lib
+    L.check(lib.hdg_solve_batch(n, handles, rp, kind, nrh, float(tol), lp, infos, int(nstreams)), "hdg_solve_batch")
+    out = [x.reshape(k, -1) for x, k in zip(lam, nr)]
+    return out, [{"iters": i.iters, "relres": i.relres, "t_solve_ms": i.t_solve_ms} for i in infos]
 
 
 class HDGSolve(torch.autograd.Function):

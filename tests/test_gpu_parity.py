@@ -329,6 +329,117 @@ def test_iteration_counts_match_oracle(torch_cuda):
             assert relerr(lam.cpu().numpy(), ro.lam) <= 1e-9
 
 
+@pytest.mark.parametrize("d,n,k,path", [(2, 32, 3, "tail"), (2, 16, 2, "unfused"), (3, 4, 2, "unfused"),
+                                        (2, 64, 4, "fused")])
+def test_several_rhs_vcycle_is_per_rhs_cycle(torch_cuda, monkeypatch, d, n, k, path):
+    """A V-cycle over several right-hand sides at once (one launch per
+    kernel for all of them) equals the single-right-hand-side cycles bit for
+    bit, with groups of the build's capacity (5 and 2 for 5 vectors)."""
+    from paper_1811_09909_amd import _lib as L
+    _set_path(monkeypatch, path)
+    kap, rng = _kappa(d, n, 1e-2, 1e2)
+    P = _gpu(torch_cuda, d, n, k, kap)
+    R = rng.standard_normal((5, P.nlam))
+    P.build(local_corr=omg.LC_BOTH)
+    single = {pr: [P.vcycle(torch_cuda.as_tensor(R[i], dtype=dt), precision=pr).cpu().numpy() for i in range(5)]
+              for pr, dt in [(L.FP64, torch_cuda.float64), (L.FP32, torch_cuda.float32)]}
+    for cap in (5, 2):
+        P.build(local_corr=omg.LC_BOTH, nrhs=cap)
+        for pr, dt in [(L.FP64, torch_cuda.float64), (L.FP32, torch_cuda.float32)]:
+            E = P.vcycle(torch_cuda.as_tensor(R.ravel(), dtype=dt), precision=pr).cpu().numpy().reshape(5, -1)
+            diff = max(np.abs(E[i] - single[pr][i]).max() for i in range(5))
+            say(f"[several rhs vcycle {path}] d={d} n={n} k={k} cap={cap} precision={pr}: max diff {diff:.1e}")
+            assert diff == 0.0
+
+
+@pytest.mark.parametrize("method,prec", [("pcg", "mixed"), ("pcg", "fp64"), ("mg", "fp64")])
+def test_several_rhs_solve(torch_cuda, method, prec):
+    """Several right-hand sides iterated together reach each single solve's
+    solution, iteration count and tolerance."""
+    from paper_1811_09909_amd import _lib as L
+    # MG as a solver needs a milder problem to converge (tau = 1, k = 3)
+    wl = inputs.diffusion2d(32, 4, 1e-1, 1e1, seed=3) if method == "mg" else inputs.diffusion2d(32, 3, 1e-2, 1e2,
+                                                                                                seed=3)
+    rng = np.random.default_rng(4)
+    F = np.stack([wl.f] + [rng.standard_normal(wl.f.shape) for _ in range(3)])
+    F[2] *= 1e-3  # right-hand sides of different size converge at different counts
+    P = _gpu(torch_cuda, 2, 32, wl.k, wl.kappa)
+    m = {"pcg": L.METHOD_PCG, "mg": L.METHOD_MG}[method]
+    lc = omg.LC_BOTH if method == "pcg" else omg.LC_PRE
+    pr = L.MIXED if prec == "mixed" else L.FP64
+    P.build(local_corr=lc, method=m, precision=pr, max_it=500)
+    singles = [P.solve(torch_cuda.as_tensor(F[i]), tol=1e-10) for i in range(4)]
+    P.build(local_corr=lc, method=m, precision=pr, max_it=500, nrhs=4)
+    lam, info = P.solve(torch_cuda.as_tensor(F), tol=1e-10, nrhs=4)
+    lam = lam.reshape(4, -1)
+    counts = [s[1]["iters"] for s in singles]
+    say(f"[several rhs {method} {prec}] single counts {counts}, together {info['iters']}, relres {info['relres']:.2e}")
+    assert info["iters"] == max(counts)
+    assert info["relres"] <= 1e-10
+    for i in range(4):
+        g = P.rhs(torch_cuda.as_tensor(F[i]))
+        rel = float((g - P.level_apply(0, lam[i])).norm() / g.norm())
+        e = relerr(lam[i].cpu().numpy(), singles[i][0].cpu().numpy())
+        say(f"  rhs {i}: true relres {rel:.2e}, vs single solve {e:.2e}")
+        assert rel <= 1.05e-10
+        assert e <= 1e-8
+
+
+def test_solve_batch_matches_single_solves(torch_cuda):
+    """Problems of different size and degree solved together
+    (hdg_solve_batch, several streams) give exactly the single-problem
+    solutions, and the smallest one matches the oracle's direct solve."""
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import solve_batch
+    probs = inputs.batched2d(nprob=6, nrhs=3, ns=(8, 16, 32), ks=(2, 3, 4), lo=1e-2, hi=1e2, seed=5)
+    Ps, rhs = [], []
+    for i, w in enumerate(probs):
+        P = _gpu(torch_cuda, 2, w.n, w.k, w.kappa)
+        P.build(local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=1000, nrhs=2 if i % 2 else 3)
+        Ps.append(P)
+        rhs.append(w.f)
+    singles = [P.solve(torch_cuda.as_tensor(f), tol=1e-10, nrhs=3)[0].reshape(3, -1).cpu().numpy()
+               for P, f in zip(Ps, rhs)]
+    lam, infos = solve_batch(Ps, rhs, tol=1e-10, nstreams=3)
+    for i, w in enumerate(probs):
+        d = np.abs(lam[i].cpu().numpy() - singles[i]).max()
+        say(f"[batch] problem {i} n={w.n} k={w.k}: {infos[i]['iters']} iterations, relres {infos[i]['relres']:.1e}, "
+            f"max diff vs single {d:.1e}")
+        assert infos[i]["relres"] <= 1e-10
+        assert d == 0.0
+    i0 = min(range(len(probs)), key=lambda i: probs[i].n * probs[i].k)
+    w = probs[i0]
+    O = HDG(2, w.n, w.k, 1.0, w.kappa)
+    for j in range(3):
+        A, g, _ = O.assemble(w.f[j])
+        ref = spla.spsolve(A.tocsc(), g)
+        x = lam[i0][j].cpu().numpy()
+        res = np.linalg.norm(g - A @ x) / np.linalg.norm(g)
+        say(f"  problem {i0} rhs {j}: oracle residual {res:.2e}, vs oracle direct solve {relerr(x, ref):.2e}")
+        assert res <= 1.05e-10
+
+
+def test_autotune_picks_a_valid_layout(torch_cuda):
+    """The autotuner leaves the handle built with one of its candidates, and
+    solves with it converge to the default build's solutions."""
+    from paper_1811_09909_amd import _lib as L
+    wl = inputs.diffusion2d(64, 3, 1e-2, 1e2, seed=6)
+    rng = np.random.default_rng(7)
+    F = np.stack([rng.standard_normal(wl.f.shape) for _ in range(8)])
+    P = _gpu(torch_cuda, 2, 64, 3, wl.kappa)
+    P.build(local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=1000)
+    ref = P.solve(torch_cuda.as_tensor(F), tol=1e-10, nrhs=8)[0].reshape(8, -1).cpu().numpy()
+    best = P.autotune(8, local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=1000)
+    say(f"[autotune] n=64 k=3, 8 rhs: {best}")
+    assert best["coarse_n"] in (2, 8, 16) and best["nrhs"] in (1, 2, 4, 8)
+    lam, info = P.solve(torch_cuda.as_tensor(F), tol=1e-10, nrhs=8)
+    lam = lam.reshape(8, -1).cpu().numpy()
+    assert info["relres"] <= 1e-10
+    e = max(relerr(lam[i], ref[i]) for i in range(8))
+    say(f"  solutions vs default build: {e:.2e}")
+    assert e <= 1e-7
+
+
 def test_iteration_counts_match_oracle_3d(torch_cuda):
     """3D, 8^3 hexahedra, k = 3, kappa(x) at the Gauss points: MG and PCG
     in FP64 against the oracle's counts and solution; the mixed-precision

@@ -70,6 +70,11 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-min-s", type=float, default=10.0, help="repeat the oracle solve until this much time")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--batched", action="store_true",
+                    help="instead of the headline solve: the batched workload (64 2D problems, n in {32..256}, "
+                         "k in {2..5}, 16 right-hand sides each) through hdg_solve_batch; prints its own JSON line")
+    ap.add_argument("--batched-nprob", type=int, default=64)
+    ap.add_argument("--batched-nstreams", type=int, default=4)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only finest-level FP32 sweeps of the workload and a plain copy-like kernel of known "
                          "size (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), then exit")
@@ -145,10 +150,67 @@ def traffic_probe(args):
     return 0
 
 
+def batched(args):
+    """Many meshes, many right-hand sides: problems of uneven size and degree,
+    each with 16 right-hand sides, solved together by hdg_solve_batch (mixed
+    precision PCG + symmetric V-cycle to 1e-10 per right-hand side).  The
+    autotuner picks the coarsest grid and right-hand-side group size once per
+    (n, k) class."""
+    import torch
+    sys.path.insert(0, HERE)
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem, solve_batch
+    probs = inputs.batched2d(nprob=args.batched_nprob, nrhs=16, seed=0)
+    base = dict(sweeps=2, growth=1, local_corr=L.LC_BOTH, precision=L.MIXED, method=L.METHOD_PCG, max_it=5000)
+    t0 = time.perf_counter()
+    Ps, rhs, tuned = [], [], {}
+    for w in probs:
+        P = Problem(2, w.n, w.k, torch.as_tensor(w.kappa), tau=1.0, store_recovery=False)
+        key = (w.n, w.k)
+        if key not in tuned:
+            tuned[key] = P.autotune(16, **base)
+        else:
+            P.build(**dict(base, coarse_n=tuned[key]["coarse_n"], nrhs=tuned[key]["nrhs"]))
+        Ps.append(P)
+        rhs.append(w.f)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    dofs = sum(P.nlam * 16 for P in Ps)
+    # warm-up: captures every handle's iteration graphs
+    solve_batch(Ps, rhs, tol=1e-2, nstreams=args.batched_nstreams)
+    res = {}
+    for ns in sorted({1, args.batched_nstreams}):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, infos = solve_batch(Ps, rhs, tol=1e-10, nstreams=ns)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[ns] = (el, infos)
+    el, infos = res[args.batched_nstreams]
+    out = {
+        "metric": "trace DOFs/s to rel. resid 1e-10 (batched: sum over problems and right-hand sides)",
+        "value": round(dofs / el, 1), "unit": "trace DOFs/s", "n_gpus": 1, "ms_per_batch": round(1e3 * el, 2),
+        "higher_is_better": True, "dtype": "f32 V-cycle + f64 CG", "data": "synthetic",
+        "config": {"workload": f"batched2d {len(Ps)} problems x 16 rhs, n in {{32,64,128,256}}, k in {{2..5}}, "
+                               "kappa=logU[1e-2,1e2] seed=0 tau=1",
+                   "trace_dofs_total": dofs, "streams": args.batched_nstreams,
+                   "one_stream_ms": round(1e3 * res[1][0], 2),
+                   "max_iters": max(i["iters"] for i in infos),
+                   "max_relres": max(i["relres"] for i in infos),
+                   "setup_and_autotune_s": round(t_setup, 2),
+                   "classes": {f"n{n}_k{k}": v for (n, k), v in sorted(tuned.items())}},
+    }
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     args = parse()
     if args.traffic_probe:
         return traffic_probe(args)
+    if args.batched:
+        return batched(args)
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_n, args.k, args.coarse_n, args.cpu_min_s)))
         return 0

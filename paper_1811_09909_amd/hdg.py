@@ -234,6 +234,20 @@ def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=4):
     return out, [{"iters": i.iters, "relres": i.relres, "t_solve_ms": i.t_solve_ms} for i in infos]
 
 
+class HDGMass(torch.autograd.Function):
+    """u -> M u element by element (the volume mass matrix); symmetric, so
+    the backward pass applies M again."""
+
+    @staticmethod
+    def forward(ctx, u, problem):  # noqa: D102
+        ctx.problem = problem
+        return problem.mass_apply(u.detach())
+
+    @staticmethod
+    def backward(ctx, g):  # noqa: D102
+        return ctx.problem.mass_apply(g.contiguous()), None
+
+
 class HDGSolve(torch.autograd.Function):
     """U(theta): nodal u of the HDG solution for kappa_T = exp(theta_T).
 

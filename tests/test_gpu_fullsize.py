@@ -298,3 +298,60 @@ def test_fullsize_3d_manufactured_rates(cube3d, torch_cuda):
     rq = np.log2(errs[0][1] / errs[1][1])
     say(f"  rates u {ru:.2f} q {rq:.2f}")
     assert ru >= 3.7 and rq >= 3.7
+
+
+def test_fullsize_adjoint_gradient_against_finite_differences(torch_cuda):
+    """Adjoint workload, 256 x 256 quads, k = 3, theta = log kappa ~ N(0, 1)
+    per element, f = 1: J(theta) = 1/2 ||u - u_obs||^2 (mass-weighted) with
+    u_obs the theta = 0 solution plus 1% noise.  The gradient from torch
+    autograd through the library's adjoint solve matches central finite
+    differences along random directions and single elements."""
+    import torch
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import HDGMass, HDGSolve, Problem
+    wl = inputs.adjoint2d(256, 3, seed=0)
+    n, k = 256, 3
+    P = Problem(2, n, k, torch.ones(n * n, dtype=torch.float64), tau=1.0, store_recovery=True)
+    f = torch.as_tensor(wl.f, device=P.device)
+    kw = dict(method=L.METHOD_PCG, local_corr=L.LC_BOTH, precision=L.FP64, max_it=2000, coarse_n=16)
+    tol = 1e-10  # the FP64 floor of the relative residual here is ~2e-11
+    with torch.no_grad():
+        u0 = HDGSolve.apply(torch.zeros(n * n, dtype=torch.float64, device=P.device), P, f, tol, kw)
+    noise = torch.as_tensor(inputs.observation_noise(wl.rng, tuple(u0.shape)), device=P.device)
+    u_obs = u0 + 0.01 * u0.pow(2).mean().sqrt() * noise
+
+    def J(theta):
+        u = HDGSolve.apply(theta, P, f, tol, kw)
+        r = u - u_obs
+        return 0.5 * (r * HDGMass.apply(r, P)).sum()
+
+    theta = torch.as_tensor(wl.theta, device=P.device).clone().requires_grad_(True)
+    val = J(theta)
+    val.backward()
+    grad = theta.grad.detach().clone()
+    rng = np.random.default_rng(1)
+    # step per direction: a random direction moves every element, a single
+    # element needs a larger step for J's change to stand above the solves'
+    # rounding
+    eps_of = {"random": 1e-3, "element": 1e-2}
+    dirs = [("random", torch.as_tensor(rng.standard_normal(n * n), device=P.device)) for _ in range(2)]
+    for T in (0, 12345, 40000, n * n - 1):
+        e = torch.zeros(n * n, dtype=torch.float64, device=P.device)
+        e[T] = 1.0
+        dirs.append((f"element {T}", e))
+    # central differences carry O(eps^2) truncation and the solves' error
+    # divided by eps: |fd - ad| <= 1e-4 |ad| + 1e-8 J covers both (the
+    # floor matters for a corner element whose derivative is 1e-8 J)
+    Jv = val.item()
+    worst = 0.0
+    with torch.no_grad():
+        for name, v in dirs:
+            eps = eps_of[name.split()[0]]
+            fd = (J(theta + eps * v) - J(theta - eps * v)).item() / (2 * eps)
+            ad = float((grad * v).sum())
+            ratio = abs(fd - ad) / (1e-4 * abs(ad) + 1e-8 * Jv)
+            say(f"  {name}: adjoint {ad:.10e}  central difference {fd:.10e}  "
+                f"rel diff {abs(fd - ad) / max(abs(ad), 1e-300):.1e}  (error / bound {ratio:.2f})")
+            worst = max(worst, ratio)
+    say(f"[adjoint 256^2 k=3] J = {Jv:.6e}; worst error / bound {worst:.3f}")
+    assert worst <= 1.0

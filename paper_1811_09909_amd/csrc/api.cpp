@@ -23,6 +23,7 @@ struct hdg_problem {
   bool use_graphs = true;
   bool fuse = true;              // fused 2D transition kernels (HDG_NO_FUSE=1 selects the unfused ones)
   int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (HDG_TAIL_N, 0 = off)
+  bool pack = true;              // element-major packed finest p-level (HDG_NO_PACK=1: face-major)
   int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
   TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -765,6 +766,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->use_graphs = std::getenv("HDG_NO_GRAPH") == nullptr;
   P->fuse = std::getenv("HDG_NO_FUSE") == nullptr;
   if (const char* tn = std::getenv("HDG_TAIL_N")) P->tail_nmax = std::atoi(tn);
+  if (const char* np = std::getenv("HDG_NO_PACK")) P->pack = std::atoi(np) == 0;
   HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
   P->nv = P->ref.nv;
@@ -890,8 +892,19 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     Level& Li = L[i];
     Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min<size_t>(i, 20)) : 1);
     const long pf = pad64(Li.nface);
-    Li.Af64 = dalloc<double>(P, pf * 2 * vpad<double>((long)Li.nl * Li.ne), true);
-    Li.Af32 = dalloc<float>(P, pf * 2 * vpad<float>((long)Li.nl * Li.ne), true);
+    // the finest level of a p-transition (only trace applies touch it) is
+    // stored element-major as packed symmetric triangles
+    Li.packed = Li.kind == 0 && P->pack && Li.nface > 0 && d == 2;  // 3D element maps (nl >= 54) would spill
+    if (Li.packed) {
+      const long npk = (long)Li.nl * (Li.nl + 1) / 2;
+      Li.Ap64 = dalloc<double>(P, pad64(Li.nelem) * npk, true);
+      Li.Ap32 = dalloc<float>(P, pad64(Li.nelem) * npk, true);
+      Li.z[0] = dalloc<double>(P, pad64(Li.nelem) * Li.nl * cap, true);
+      Li.z[1] = dalloc<float>(P, pad64(Li.nelem) * Li.nl * cap, true);
+    } else {
+      Li.Af64 = dalloc<double>(P, pf * 2 * vpad<double>((long)Li.nl * Li.ne), true);
+      Li.Af32 = dalloc<float>(P, pf * 2 * vpad<float>((long)Li.nl * Li.ne), true);
+    }
     Li.Dinv64 = dalloc<double>(P, pf * vpad<double>((long)Li.ne * Li.ne), true);
     Li.Dinv32 = dalloc<float>(P, pf * vpad<float>((long)Li.ne * Li.ne), true);
     for (int pr = 0; pr < 2; ++pr) {
@@ -905,7 +918,10 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
       }
     }
     if (Li.nface > 0) {
-      launch_face_major(Li, P->st);
+      if (Li.packed)
+        launch_pack_sym(Li, P->st);
+      else
+        launch_face_major(Li, P->st);
       launch_dinv(Li, o.omega, P->st);
     }
   }
@@ -1327,7 +1343,9 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   const int mode = kernel / 2;
   const double s = (kernel % 2) ? 4.0 : 8.0;
   const double N = (double)L.nlam;
-  double bytes = (double)L.nface * 2.0 * L.ne * L.nl * s;
+  // operator bytes: each element row once (face-major), or the packed upper
+  // triangle of each element map (element-major)
+  double bytes = L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * s : (double)L.nface * 2.0 * L.ne * L.nl * s;
   if (mode == APPLY_Y) bytes += 2.0 * N * s;
   if (mode == APPLY_RES) bytes += 3.0 * N * s;
   if (mode == APPLY_SWEEP) bytes += (double)L.nface * L.ne * L.ne * s + 3.0 * N * s;

@@ -427,7 +427,36 @@ __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ 
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) b[i] = (float)a[i];
 }
 
+// Ap[T][e] for the packed upper triangle (i <= j, row by row) of the
+// symmetrised element map (A + A^T) / 2, AoSoA over elements
+__global__ void pack_sym_kernel(long nelem, int nl, const double* __restrict__ Aelem, double* __restrict__ Ap64,
+                                float* __restrict__ Ap32) {
+  const int npk = nl * (nl + 1) / 2;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= nelem * npk) return;
+  const long T = t / npk;
+  int e = (int)(t % npk);
+  int i = 0;
+  while (e >= nl - i) {
+    e -= nl - i;
+    ++i;
+  }
+  const int j = i + e;
+  const double* A = Aelem + T * (long)nl * nl;
+  const double v = 0.5 * (A[i * nl + j] + A[j * nl + i]);
+  const long idx = (T >> 6) * (long)npk * LANES + (long)(t % npk) * LANES + (T & 63);
+  Ap64[idx] = v;
+  Ap32[idx] = (float)v;
+}
+
 }  // namespace
+
+void launch_pack_sym(const Level& L, hipStream_t st) {
+  const long npk = (long)L.nl * (L.nl + 1) / 2;
+  hipLaunchKernelGGL(pack_sym_kernel, dim3(nblk(L.nelem * npk)), dim3(256), 0, st, L.nelem, L.nl, L.Aelem, L.Ap64,
+                     L.Ap32);
+  HDG_CHECK(hipGetLastError());
+}
 
 void launch_face_major(const Level& L, hipStream_t st) {
   if (L.nface == 0) return;

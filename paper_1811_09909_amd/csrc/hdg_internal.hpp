@@ -102,6 +102,14 @@ struct Level {
   double* Aelem = nullptr;  bool own_Aelem = true;
   double* Af64 = nullptr;   float* Af32 = nullptr;
   double* Dinv64 = nullptr; float* Dinv32 = nullptr;
+  // Element-major packed form (used instead of Af on the finest level of a
+  // p-transition): the upper triangle of each symmetric element map, row by
+  // row, AoSoA over elements (entry e of element T at
+  // (T/64)*npk*64 + e*64 + T%64, npk = nl(nl+1)/2), and the per-element
+  // products z_T = A^e x_T ([nrhs][nelem padded to 64][nl], same AoSoA).
+  bool packed = false;
+  double* Ap64 = nullptr;   float* Ap32 = nullptr;
+  void* z[2] = {nullptr, nullptr};
   // h-transition to the next level
   long nmacro = 0;
   int nI = 0, ncl = 0;
@@ -136,6 +144,7 @@ void launch_kappa_expand(long nelem, int nq, const double* kappa, int kind, doub
 
 // build.hip
 void launch_face_major(const Level& L, hipStream_t st);
+void launch_pack_sym(const Level& L, hipStream_t st);
 void launch_dinv(const Level& L, double omega, hipStream_t st);
 void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double* Afine, double* Acoarse,
                       hipStream_t st);

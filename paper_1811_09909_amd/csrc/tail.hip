@@ -69,9 +69,9 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(TailArgs a) {
       const T* Ainv = reinterpret_cast<const T*>(C.Ainv);
       const int N = (int)C.nlam;
       for (int i = tid; i < N; i += nt) {
-        T sacc = T(0);
-        for (int j = 0; j < N; ++j) sacc += Ainv[i * N + j] * rc[j];
-        ec[i] = sacc;
+        acc_t<T> sacc = 0;
+        for (int j = 0; j < N; ++j) sacc += acc_t<T>(Ainv[i * N + j]) * rc[j];
+        ec[i] = T(sacc);
       }
     } else {
       const T* Dc = reinterpret_cast<const T*>(C.Dinv);

@@ -30,7 +30,10 @@ using namespace dev;
 #define HDG_APPLY_WPE 1
 #endif
 
-template <int D, int NE, typename T, int MODE>
+// ZS: the level is stored element-major; Af then points to the per-element
+// products z of the first phase (elem_apply_kernel) and each face only adds
+// its two elements' rows.
+template <int D, int NE, typename T, int MODE, bool ZS = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
@@ -49,47 +52,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
     y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
     rc = off(rc, rhs * sC);
     y32 = off(y32, rhs * sN);
+    if (ZS) {
+      long nelem = 1;
+      for (int a = 0; a < D; ++a) nelem *= n;
+      Af += rhs * ((nelem + 63) / 64 * 64) * (2 * D * NE);
+    }
   }
   double part = 0.0;
   if (F >= 0) {
-  T acc[NE];
-  face_acc<D, NE, T>(F, n, Af, x, acc);
+  using A = acc_t<T>;
+  A acc[NE];
+  if constexpr (ZS)
+    face_acc_z<D, NE, T>(F, n, Af, acc);
+  else
+    face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_Y) {
 #pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = acc[a];
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(acc[a]);
   } else if (MODE == APPLY_RES) {
 #pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = bvec[F * NE + a] - acc[a];
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(A(bvec[F * NE + a]) - acc[a]);
   } else if (MODE == APPLY_SWEEP) {
-    T res[NE];
+    A res[NE];
 #pragma unroll
-    for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
+    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
     dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
-    T res[NE];
+    A res[NE];
 #pragma unroll
-    for (int a = 0; a < NE; ++a) res[a] = bvec[F * NE + a] - acc[a];
-    T rcv[NC];
+    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
+    A rcv[NC];
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
-      T s = T(0);
+      A s = A(0);
 #pragma unroll
-      for (int a = 0; a < NE; ++a) s += T(Jp[a * NC + v]) * res[a];
-      rc[F * NC + v] = s;
-      rcv[v] = s;
+      for (int a = 0; a < NE; ++a) s += A(Jp[a * NC + v]) * res[a];
+      rc[F * NC + v] = T(s);
+      rcv[v] = A(T(s));  // the coarse first step starts from the stored residual
     }
     if (y)  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
       dinv_update<NC, T>(F, Dinv, (const T*)nullptr, rcv, y);
   } else if (MODE == APPLY_Y_DOT) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) {
-      y[F * NE + a] = acc[a];
-      part += (double)x[F * NE + a] * (double)acc[a];
+      y[F * NE + a] = T(acc[a]);
+      part += (double)x[F * NE + a] * (double)T(acc[a]);
     }
   } else {  // APPLY_RES_NORM
 #pragma unroll
     for (int a = 0; a < NE; ++a) {
-      const T v = bvec[F * NE + a] - acc[a];
+      const T v = T(A(bvec[F * NE + a]) - acc[a]);
       y[F * NE + a] = v;
       if (y32) y32[F * NE + a] = (float)v;
       part += (double)v * (double)v;
@@ -113,6 +125,20 @@ __global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* 
   jacobi0_item<NE, T>(F, Dinv, r, e);
 }
 
+// first phase of the element-major apply: z_T = A^e x_T for every element
+template <int D, int NE, typename T>
+__global__ void __launch_bounds__(256) elem_apply_kernel(int n, const T* __restrict__ Ap, const T* __restrict__ x,
+                                                         T* __restrict__ z, int nrhs) {
+  long nelem = 1;
+  for (int a = 0; a < D; ++a) nelem *= n;
+  int rhs;
+  const long Tq = xcd_elem_rhs(nelem, nrhs, blockIdx.x, threadIdx.x, &rhs);
+  if (Tq < 0) return;
+  x += rhs * trace_len<D>(n, NE);
+  z += rhs * ((nelem + 63) / 64 * 64) * (2 * D * NE);
+  elem_item<D, NE, T>(Tq, n, Ap, x, z);
+}
+
 // e += J_N ec on every face (p-prolongation)
 template <int NE, int NC, typename T>
 __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, const T* __restrict__ ec,
@@ -121,15 +147,16 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
   if (F >= nface) return;
   ec += blockIdx.y * nface * NC;
   e += blockIdx.y * nface * NE;
-  T cv[NC];
+  using A = acc_t<T>;
+  A cv[NC];
 #pragma unroll
   for (int v = 0; v < NC; ++v) cv[v] = ec[F * NC + v];
 #pragma unroll
   for (int a = 0; a < NE; ++a) {
-    T s = e[F * NE + a];
+    A s = e[F * NE + a];
 #pragma unroll
-    for (int v = 0; v < NC; ++v) s += T(Jp[a * NC + v]) * cv[v];
-    e[F * NE + a] = s;
+    for (int v = 0; v < NC; ++v) s += A(Jp[a * NC + v]) * cv[v];
+    e[F * NE + a] = T(s);
   }
 }
 
@@ -157,7 +184,8 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
   }
   int m[3] = {0, 0, 0};
   decode_elem<D>(M, nm, m);
-  T rI[NI];
+  using A = acc_t<T>;
+  A rI[NI];
   long fid[NIF];
 #pragma unroll
   for (int i = 0; i < NIF; ++i) {
@@ -166,22 +194,22 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
     for (int a = 0; a < NC; ++a) rI[i * NC + a] = rho[fid[i] * NC + a];
   }
   if (do_corr) {
-    T s[NI];
+    A s[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) s[i] = T(0);
+    for (int i = 0; i < NI; ++i) s[i] = A(0);
     aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rI, s);
 #pragma unroll
     for (int i = 0; i < NIF; ++i)
 #pragma unroll
-      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] += s[i * NC + a];
+      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] = T(A(e[fid[i] * NC + a]) + s[i * NC + a]);
   }
   if (do_restrict) {
-    T s[NCL];
+    A s[NCL];
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) s[j] = T(0);
+    for (int j = 0; j < NCL; ++j) s[j] = A(0);
     aos_mv<T, NI * NCL, NCL, true>(P + aos_item<T>(M, vpad<T>(NI * NCL)), rI, s);
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = s[j];
+    for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = T(s[j]);
   }
 }
 
@@ -204,17 +232,18 @@ __global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __re
   }
   int G[3] = {0, 0, 0};
   const int c = decode_face<D>(Fc, nm, G);
-  T out[NC];
+  using A = acc_t<T>;
+  A out[NC];
 #pragma unroll
-  for (int V = 0; V < NC; ++V) out[V] = T(0);
+  for (int V = 0; V < NC; ++V) out[V] = A(0);
 #pragma unroll
   for (int t = 0; t < NS; ++t) {
     const long f = subface<D>(c, G, t, n);
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
-      const T rv = rho[f * NC + v];
+      const A rv = rho[f * NC + v];
 #pragma unroll
-      for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+      for (int V = 0; V < NC; ++V) out[V] += A(jh_weight<D>(t, v, V)) * rv;
     }
   }
   int mm[3] = {G[0], G[1], G[2]};
@@ -224,9 +253,9 @@ __global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __re
   const long Mp = elem_id<D>(mm, nm);
 #pragma unroll
   for (int V = 0; V < NC; ++V) {
-    out[V] += cb[Mm * NCL + (2 * c + 1) * NC + V];
-    out[V] += cb[Mp * NCL + (2 * c) * NC + V];
-    rc[Fc * NC + V] = out[V];
+    out[V] += A(cb[Mm * NCL + (2 * c + 1) * NC + V]);
+    out[V] += A(cb[Mp * NCL + (2 * c) * NC + V]);
+    rc[Fc * NC + V] = T(out[V]);
   }
 }
 
@@ -239,6 +268,7 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
   constexpr int NIF = D * NC;
   constexpr int NI = NIF * NC;
   constexpr int NCL = 2 * D * NC;
+  using A = acc_t<T>;
   const int nm = n / 2;
   ec += blockIdx.y * trace_len<D>(nm, NC);
   e += blockIdx.y * trace_len<D>(n, NC);
@@ -249,14 +279,14 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
     if (M >= nmacro) return;
     int m[3] = {0, 0, 0};
     decode_elem<D>(M, nm, m);
-    T cv[NCL];
+    A cv[NCL];
 #pragma unroll
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
       const int p = m[cc] + sd;
       if (p == 0 || p == nm) {
 #pragma unroll
-        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = T(0);
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = A(0);
       } else {
         int G[3] = {m[0], m[1], m[2]};
         G[cc] = p;
@@ -265,7 +295,7 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
         for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
       }
     }
-    T s[NI];
+    A s[NI];
 #pragma unroll
     for (int i = 0; i < NIF; ++i) {
       const long f = macro_iface<D>(m, i, n);
@@ -277,7 +307,7 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
     for (int i = 0; i < NIF; ++i) {
       const long f = macro_iface<D>(m, i, n);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) e[f * NC + a] = s[i * NC + a];
+      for (int a = 0; a < NC; ++a) e[f * NC + a] = T(s[i * NC + a]);
     }
   } else {
     const long ncf = D * nface_dir<D>(nm);
@@ -285,7 +315,7 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
     if (Fc >= ncf) return;
     int G[3] = {0, 0, 0};
     const int c = decode_face<D>(Fc, nm, G);
-    T cv[NC];
+    A cv[NC];
 #pragma unroll
     for (int V = 0; V < NC; ++V) cv[V] = ec[Fc * NC + V];
 #pragma unroll
@@ -293,10 +323,10 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
       const long f = subface<D>(c, G, t, n);
 #pragma unroll
       for (int v = 0; v < NC; ++v) {
-        T s = e[f * NC + v];
+        A s = e[f * NC + v];
 #pragma unroll
-        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[V];
-        e[f * NC + v] = s;
+        for (int V = 0; V < NC; ++V) s += A(jh_weight<D>(t, v, V)) * cv[V];
+        e[f * NC + v] = T(s);
       }
     }
   }
@@ -307,9 +337,9 @@ __global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* 
   r += blockIdx.y * (long)N;
   e += blockIdx.y * (long)N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    T s = T(0);
-    for (int j = 0; j < N; ++j) s += Ainv[i * N + j] * r[j];
-    e[i] = s;
+    acc_t<T> s = 0;
+    for (int j = 0; j < N; ++j) s += acc_t<T>(Ainv[i * N + j]) * r[j];
+    e[i] = T(s);
   }
 }
 
@@ -371,6 +401,7 @@ __global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T
                                   const T* __restrict__ Ainv, T* __restrict__ ec) {
   constexpr int NC = 1 << (D - 1);
   constexpr int NCL = 2 * D * NC;
+  using A = acc_t<T>;
   __shared__ T rcs[64];
   const int nm = n / 2;
   const long ncf = D * nface_dir<D>(nm);
@@ -384,17 +415,17 @@ __global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T
   for (long Fc = threadIdx.x; Fc < ncf; Fc += blockDim.x) {
     int G[3] = {0, 0, 0};
     const int c = decode_face<D>(Fc, nm, G);
-    T out[NC];
+    A out[NC];
 #pragma unroll
-    for (int V = 0; V < NC; ++V) out[V] = T(0);
+    for (int V = 0; V < NC; ++V) out[V] = A(0);
 #pragma unroll
     for (int t = 0; t < NC; ++t) {
       const long f = subface<D>(c, G, t, n);
 #pragma unroll
       for (int v = 0; v < NC; ++v) {
-        const T rv = r[f * NC + v];
+        const A rv = r[f * NC + v];
 #pragma unroll
-        for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+        for (int V = 0; V < NC; ++V) out[V] += A(jh_weight<D>(t, v, V)) * rv;
       }
     }
     int mm[3] = {G[0], G[1], G[2]};
@@ -404,13 +435,13 @@ __global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T
     const long Mp = elem_id<D>(mm, nm);
 #pragma unroll
     for (int V = 0; V < NC; ++V)
-      rcs[Fc * NC + V] = out[V] + cb[Mm * NCL + (2 * c + 1) * NC + V] + cb[Mp * NCL + (2 * c) * NC + V];
+      rcs[Fc * NC + V] = T(out[V] + A(cb[Mm * NCL + (2 * c + 1) * NC + V]) + A(cb[Mp * NCL + (2 * c) * NC + V]));
   }
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    T s = T(0);
-    for (int j = 0; j < N; ++j) s += Ainv[i * N + j] * rcs[j];
-    ec[i] = s;
+    A s = A(0);
+    for (int j = 0; j < N; ++j) s += A(Ainv[i * N + j]) * rcs[j];
+    ec[i] = T(s);
   }
 }
 
@@ -452,6 +483,20 @@ void dispatch_d_ne(int d, int ne, F&& f) {
   throw HipError{hipErrorInvalidValue, "unsupported (d, ne)"};
 }
 
+// first phase of the element-major apply on a packed level
+template <typename T>
+void launch_elem_phase(const Level& L, const T* x, hipStream_t st, int nrhs) {
+  const T* Ap = sizeof(T) == 8 ? (const T*)L.Ap64 : (const T*)L.Ap32;
+  T* z = (T*)L.z[sizeof(T) == 8 ? 0 : 1];
+  const long C = ((L.nelem + 255) / 256 + 7) / 8;
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+    hipLaunchKernelGGL((elem_apply_kernel<D, NE, T>), dim3((unsigned)(8 * C * nrhs)), dim3(256), 0, st, L.n, Ap, x, z,
+                       nrhs);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
 }  // namespace
 
 template <typename T>
@@ -475,11 +520,17 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     Dv = (const T*)L.Dinv32;
   }
   const unsigned g1 = xcd_grid(L.d, L.n);
+  if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
+  const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
-#define HDG_AK(MM)                                                                                             \
-  hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, Dv, x, b, y, \
-                     Jp, rc, y32, partials, nrhs)
+#define HDG_AK(MM)                                                                                                 \
+  if (L.packed)                                                                                                    \
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, MM, true>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Zs, Dv, \
+                       x, b, y, Jp, rc, y32, partials, nrhs);                                                      \
+  else                                                                                                             \
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, Dv, x, b, \
+                       y, Jp, rc, y32, partials, nrhs)
     switch (mode) {
       case APPLY_Y: HDG_AK(APPLY_Y); break;
       case APPLY_RES: HDG_AK(APPLY_RES); break;
@@ -504,10 +555,17 @@ void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b
   if (L.nface == 0) return;
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Dc = sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32;
+  if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
+  const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
-    hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(xcd_grid(L.d, L.n) * (unsigned)nrhs),
-                       dim3(256), 0, st, L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr, nrhs);
+    if (L.packed)
+      hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT, true>),
+                         dim3(xcd_grid(L.d, L.n) * (unsigned)nrhs), dim3(256), 0, st, L.n, Zs, Dc, x, b, ec, Jp, rc,
+                         nullptr, nullptr, nrhs);
+    else
+      hipLaunchKernelGGL((apply_kernel<D, NE, T, APPLY_RES_PRESTRICT>), dim3(xcd_grid(L.d, L.n) * (unsigned)nrhs),
+                         dim3(256), 0, st, L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr, nrhs);
   });
   HDG_CHECK(hipGetLastError());
 }

@@ -7,6 +7,26 @@
 namespace hdg {
 namespace dev {
 
+// Arithmetic type of the cycle kernels: the storage type T by default.
+// Building with HDG_FP64_ARITH forms the sums of the FP32 cycle in FP64
+// (operators and vectors still stored in FP32).  Measured on MI355X: the
+// finest-level kernels are unchanged (HBM-bound), the coarse-level ones get
+// 13% slower in 2D, and in 3D (k = 3, n = 16) mixed-precision CG then
+// converges where it stalls with FP32 sums, but in 891 iterations against
+// 73 in FP64, so FP64 remains the 3D choice.
+template <typename T>
+struct AccOf {
+  using type = T;
+};
+#ifdef HDG_FP64_ARITH
+template <>
+struct AccOf<float> {
+  using type = double;
+};
+#endif
+template <typename T>
+using acc_t = typename AccOf<T>::type;
+
 // one lane's entry group (vw<T>() values) of an AoSoA operator block
 template <typename T>
 __device__ inline void ld_group(const T* p, T* out) {
@@ -25,8 +45,8 @@ __device__ inline void ld_group(const T* p, T* out) {
 // blk (= base + aos_item).  Entry e pairs output o and input i as
 // (o, i) = (e % NMINOR, e / NMINOR) when OUT_MINOR, else (e / NMINOR, e % NMINOR).
 // Every output accumulates in increasing input order.
-template <typename T, int CNT, int NMINOR, bool OUT_MINOR>
-__device__ inline void aos_mv(const T* __restrict__ blk, const T* x, T* acc) {
+template <typename T, int CNT, int NMINOR, bool OUT_MINOR, typename X, typename Y>
+__device__ inline void aos_mv(const T* __restrict__ blk, const X* x, Y* acc) {
   constexpr int V = vw<T>();
   constexpr int NG = (CNT + V - 1) / V;
 #pragma unroll
@@ -38,9 +58,9 @@ __device__ inline void aos_mv(const T* __restrict__ blk, const T* x, T* acc) {
       const int e = g * V + q;
       if (e < CNT) {
         if (OUT_MINOR)
-          acc[e % NMINOR] += v[q] * x[e / NMINOR];
+          acc[e % NMINOR] += Y(v[q]) * x[e / NMINOR];
         else
-          acc[e / NMINOR] += v[q] * x[e % NMINOR];
+          acc[e / NMINOR] += Y(v[q]) * x[e % NMINOR];
       }
     }
   }
@@ -50,8 +70,8 @@ __device__ inline void aos_mv(const T* __restrict__ blk, const T* x, T* acc) {
 // NE x NE block of a face matrix (entries B .. B + NE*NE - 1 of the item).
 // Groups that straddle two slots are loaded by both (the second load hits
 // the cache), so each slot can sit in its own branch.
-template <typename T, int NE>
-__device__ inline void aos_mv_slot(const T* __restrict__ blk, int B, const T* x, T* acc) {
+template <typename T, int NE, typename X, typename Y>
+__device__ inline void aos_mv_slot(const T* __restrict__ blk, int B, const X* x, Y* acc) {
   constexpr int V = vw<T>();
   const int g0 = B / V, g1 = (B + NE * NE - 1) / V;
 #pragma unroll
@@ -61,7 +81,7 @@ __device__ inline void aos_mv_slot(const T* __restrict__ blk, int B, const T* x,
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       const int e = g * V + q - B;
-      if (e >= 0 && e < NE * NE) acc[e % NE] += v[q] * x[e / NE];
+      if (e >= 0 && e < NE * NE) acc[e % NE] += Y(v[q]) * x[e / NE];
     }
   }
 }
@@ -297,13 +317,13 @@ __device__ inline long mface_id(const int* m, int mf, int n, int* side_in) {
 
 // (A e) on face fid, side `side` only (child ch), e given per M-face
 template <int D, typename T>
-__device__ inline void side_apply(const T* __restrict__ Af, long fid, int side, int ch, const T (*eM)[1 << (D - 1)],
-                                  T* acc) {
+__device__ inline void side_apply(const T* __restrict__ Af, long fid, int side, int ch,
+                                  const acc_t<T> (*eM)[1 << (D - 1)], acc_t<T>* acc) {
   using Mc = Macro<D>;
   constexpr int NE = Mc::NC, NL = Mc::NL;
   constexpr long S = vpad<T>(NL * NE);
   const T* Mb = Af + aos_item<T>(fid, 2 * S) + side * S * LANES;
-  T xs[NL];
+  acc_t<T> xs[NL];
 #pragma unroll
   for (int sl = 0; sl < 2 * D; ++sl) {
     const int mf = mface_of<D>(ch, sl);
@@ -348,63 +368,64 @@ template <int D, typename T>
 __device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
                                  const T* __restrict__ P, const T* r, T* e, int do_corr, T* cb) {
   using Mc = Macro<D>;
+  using A = acc_t<T>;
   constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
   const int nm = n / 2;
   int m[3] = {0, 0, 0};
   decode_elem<D>(M, nm, m);
-  T eM[NIF + NBF][NC];
+  A eM[NIF + NBF][NC];
   long fid[NIF + NBF];
   int sidein[NIF + NBF];
 #pragma unroll
   for (int f = 0; f < NIF + NBF; ++f) {
     fid[f] = mface_id<D>(m, f, n, &sidein[f]);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? e[fid[f] * NC + a] : T(0);
+    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(e[fid[f] * NC + a]) : A(0);
   }
-  T rho[NI];
+  A rho[NI];
 #pragma unroll
   for (int i = 0; i < NIF; ++i) {
-    T acc[NC];
+    A acc[NC];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    for (int a = 0; a < NC; ++a) acc[a] = A(0);
     side_apply<D, T>(Af, fid[i], 0, ichild<D>(i, 0), eM, acc);
     side_apply<D, T>(Af, fid[i], 1, ichild<D>(i, 1), eM, acc);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
+    for (int a = 0; a < NC; ++a) rho[i * NC + a] = A(r[fid[i] * NC + a]) - acc[a];
   }
   if (do_corr) {
-    T s[NI];
+    A s[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) s[i] = T(0);
+    for (int i = 0; i < NI; ++i) s[i] = A(0);
     aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rho, s);
 #pragma unroll
     for (int i = 0; i < NIF; ++i)
 #pragma unroll
-      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] = eM[i][a] + s[i * NC + a];
+      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] = T(eM[i][a] + s[i * NC + a]);
   }
-  T out[NCL];
+  A out[NCL];
 #pragma unroll
-  for (int j = 0; j < NCL; ++j) out[j] = T(0);
+  for (int j = 0; j < NCL; ++j) out[j] = A(0);
   aos_mv<T, NI * NCL, NCL, true>(P + aos_item<T>(M, vpad<T>(NI * NCL)), rho, out);
 #pragma unroll
   for (int b = 0; b < NBF; ++b) {
     const int f = NIF + b;
     if (fid[f] < 0) continue;
-    T acc[NC];
+    A acc[NC];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) acc[a] = T(0);
+    for (int a = 0; a < NC; ++a) acc[a] = A(0);
     side_apply<D, T>(Af, fid[f], sidein[f], bchild<D>(b), eM, acc);
     const int S = b / NS, t = b % NS;
 #pragma unroll
     for (int V = 0; V < NC; ++V) {
-      T s = T(0);
+      A s = A(0);
 #pragma unroll
-      for (int v = 0; v < NC; ++v) s += T(jh_weight<D>(t, v, V)) * acc[v];
+      for (int v = 0; v < NC; ++v) s += A(jh_weight<D>(t, v, V)) * acc[v];
       out[S * NC + V] -= s;
     }
   }
 #pragma unroll
-  for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = out[j];
+  for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = T(out[j]);
 }
 
 // Coarse residual r_c = J^T r_B + cb_{M-} + cb_{M+} per coarse face, and the
@@ -412,21 +433,22 @@ __device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const 
 template <int D, typename T>
 __device__ inline void hsum_item(long Fc, int n, const T* r, const T* cb, const T* __restrict__ Dc, T* rc, T* ec) {
   constexpr int NC = 1 << (D - 1);
+  using A = acc_t<T>;
   constexpr int NCL = 2 * D * NC;
   const int nm = n / 2;
   int G[3] = {0, 0, 0};
   const int c = decode_face<D>(Fc, nm, G);
-  T out[NC];
+  A out[NC];
 #pragma unroll
-  for (int V = 0; V < NC; ++V) out[V] = T(0);
+  for (int V = 0; V < NC; ++V) out[V] = A(0);
 #pragma unroll
   for (int t = 0; t < NC; ++t) {
     const long f = subface<D>(c, G, t, n);
 #pragma unroll
     for (int v = 0; v < NC; ++v) {
-      const T rv = r[f * NC + v];
+      const A rv = r[f * NC + v];
 #pragma unroll
-      for (int V = 0; V < NC; ++V) out[V] += T(jh_weight<D>(t, v, V)) * rv;
+      for (int V = 0; V < NC; ++V) out[V] += A(jh_weight<D>(t, v, V)) * rv;
     }
   }
   int mm[3] = {G[0], G[1], G[2]};
@@ -436,17 +458,17 @@ __device__ inline void hsum_item(long Fc, int n, const T* r, const T* cb, const 
   const long Mp = elem_id<D>(mm, nm);
 #pragma unroll
   for (int V = 0; V < NC; ++V) {
-    out[V] += cb[Mm * NCL + (2 * c + 1) * NC + V];
-    out[V] += cb[Mp * NCL + (2 * c) * NC + V];
-    rc[Fc * NC + V] = out[V];
+    out[V] += A(cb[Mm * NCL + (2 * c + 1) * NC + V]);
+    out[V] += A(cb[Mp * NCL + (2 * c) * NC + V]);
+    rc[Fc * NC + V] = T(out[V]);
   }
   if (Dc) {
-    T s[NC];
+    A s[NC];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) s[a] = T(0);
+    for (int a = 0; a < NC; ++a) s[a] = A(0);
     aos_mv<T, NC * NC, NC, false>(Dc + aos_item<T>(Fc, vpad<T>(NC * NC)), out, s);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) ec[Fc * NC + a] = s[a];
+    for (int a = 0; a < NC; ++a) ec[Fc * NC + a] = T(s[a]);
   }
 }
 
@@ -460,19 +482,20 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
                                     const T* __restrict__ P, const T* r, const T* ec, const T* eold, T* enew,
                                     int do_corr) {
   using Mc = Macro<D>;
+  using A = acc_t<T>;
   constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
   const int nm = n / 2;
   {
     int m[3] = {0, 0, 0};
     decode_elem<D>(M, nm, m);
-    T cv[NCL];
+    A cv[NCL];
 #pragma unroll
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
       const int p = m[cc] + sd;
       if (p == 0 || p == nm) {
 #pragma unroll
-        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = T(0);
+        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = A(0);
       } else {
         int G[3] = {m[0], m[1], m[2]};
         G[cc] = p;
@@ -481,14 +504,14 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
         for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
       }
     }
-    T eM[NIF + NBF][NC];
+    A eM[NIF + NBF][NC];
     long fid[NIF + NBF];
     int sidein[NIF + NBF];
 #pragma unroll
     for (int f = 0; f < NIF + NBF; ++f) {
       fid[f] = mface_id<D>(m, f, n, &sidein[f]);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? eold[fid[f] * NC + a] : T(0);
+      for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(eold[fid[f] * NC + a]) : A(0);
     }
     // B faces: e + J e_c (local copy only; the coarse-face lanes write them)
 #pragma unroll
@@ -498,16 +521,16 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
       const int S = b / NS, t = b % NS;
 #pragma unroll
       for (int v = 0; v < NC; ++v) {
-        T s = T(0);
+        A s = A(0);
 #pragma unroll
-        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[S * NC + V];
+        for (int V = 0; V < NC; ++V) s += A(jh_weight<D>(t, v, V)) * cv[S * NC + V];
         eM[f][v] += s;
       }
     }
     {
-      T s[NI];
+      A s[NI];
 #pragma unroll
-      for (int i = 0; i < NI; ++i) s[i] = T(0);
+      for (int i = 0; i < NI; ++i) s[i] = A(0);
       aos_mv<T, NI * NCL, NCL, false>(P + aos_item<T>(M, vpad<T>(NI * NCL)), cv, s);
 #pragma unroll
       for (int i = 0; i < NIF; ++i)
@@ -515,30 +538,30 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
         for (int a = 0; a < NC; ++a) eM[i][a] += s[i * NC + a];
     }
     if (do_corr) {
-      T rho[NI];
+      A rho[NI];
 #pragma unroll
       for (int i = 0; i < NIF; ++i) {
-        T acc[NC];
+        A acc[NC];
 #pragma unroll
-        for (int a = 0; a < NC; ++a) acc[a] = T(0);
+        for (int a = 0; a < NC; ++a) acc[a] = A(0);
         side_apply<D, T>(Af, fid[i], 0, ichild<D>(i, 0), eM, acc);
         side_apply<D, T>(Af, fid[i], 1, ichild<D>(i, 1), eM, acc);
 #pragma unroll
-        for (int a = 0; a < NC; ++a) rho[i * NC + a] = r[fid[i] * NC + a] - acc[a];
+        for (int a = 0; a < NC; ++a) rho[i * NC + a] = A(r[fid[i] * NC + a]) - acc[a];
       }
-      T s[NI];
+      A s[NI];
 #pragma unroll
-      for (int i = 0; i < NI; ++i) s[i] = T(0);
+      for (int i = 0; i < NI; ++i) s[i] = A(0);
       aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rho, s);
 #pragma unroll
       for (int i = 0; i < NIF; ++i)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = eM[i][a] + s[i * NC + a];
+        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = T(eM[i][a] + s[i * NC + a]);
     } else {
 #pragma unroll
       for (int i = 0; i < NIF; ++i)
 #pragma unroll
-        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = eM[i][a];
+        for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = T(eM[i][a]);
     }
   }
 }
@@ -546,11 +569,12 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
 template <int D, typename T>
 __device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, T* enew) {
   constexpr int NC = 1 << (D - 1);
+  using A = acc_t<T>;
   const int nm = n / 2;
   {
     int G[3] = {0, 0, 0};
     const int c = decode_face<D>(Fc, nm, G);
-    T cv[NC];
+    A cv[NC];
 #pragma unroll
     for (int V = 0; V < NC; ++V) cv[V] = ec[Fc * NC + V];
 #pragma unroll
@@ -558,10 +582,10 @@ __device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, 
       const long f = subface<D>(c, G, t, n);
 #pragma unroll
       for (int v = 0; v < NC; ++v) {
-        T s = eold[f * NC + v];
+        A s = eold[f * NC + v];
 #pragma unroll
-        for (int V = 0; V < NC; ++V) s += T(jh_weight<D>(t, v, V)) * cv[V];
-        enew[f * NC + v] = s;
+        for (int V = 0; V < NC; ++V) s += A(jh_weight<D>(t, v, V)) * cv[V];
+        enew[f * NC + v] = T(s);
       }
     }
   }
@@ -571,13 +595,13 @@ __device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, 
 // acc = (A x)_F for interior face F: both element matrices touching F, read
 // from the face-major AoSoA form.  Returns the face's normal direction.
 template <int D, int NE, typename T>
-__device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T* x, T* acc) {
+__device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T* x, acc_t<T>* acc) {
   constexpr int NL = 2 * D * NE;
   constexpr long S = vpad<T>(NL * NE);
   int g[3] = {0, 0, 0};
   const int c = decode_face<D>(F, n, g);
 #pragma unroll
-  for (int a = 0; a < NE; ++a) acc[a] = T(0);
+  for (int a = 0; a < NE; ++a) acc[a] = acc_t<T>(0);
   const T* Mbase = Af + aos_item<T>(F, 2 * S);
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -594,7 +618,7 @@ __device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T*
       int fg[3] = {e[0], e[1], e[2]};
       fg[cc] = p;
       const T* xf = x + face_id<D>(cc, fg, n) * NE;
-      T xs[NE];
+      acc_t<T> xs[NE];
 #pragma unroll
       for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
       aos_mv_slot<T, NE>(Mx, sl * NE * NE, xs, acc);
@@ -603,40 +627,117 @@ __device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T*
   return c;
 }
 
+// Element-major XCD-aware blocks (same idea as xcd_face over the n^D
+// elements, in bands of whole grid rows): element of lane tid of workgroup p
+// and its right-hand side, or -1 for padding lanes.  Grid 8 * C * nrhs.
+__device__ inline long xcd_elem_rhs(long nelem, int nrhs, unsigned p, unsigned tid, int* rhs) {
+  const unsigned C = (unsigned)(((nelem + 255) / 256 + 7) / 8);
+  const unsigned j = p & 7u, m = p >> 3;
+  const unsigned r = m % (unsigned)nrhs, w = m / (unsigned)nrhs;
+  *rhs = (int)r;
+  const long T = ((long)j * C + w) * 256 + tid;
+  return (w < C && T < nelem) ? T : -1;
+}
+
+// offset of entry i of element T in an element-major AoSoA array of `per`
+// entries per element
+__device__ inline long elem_aos(long T, int per, int i) { return (T >> 6) * (long)per * LANES + (long)i * LANES + (T & 63); }
+
+// z_T = A^e x_T for element T from the packed upper triangle (first phase of
+// the element-major apply): gather the element's traces (zero on the
+// boundary), then one pass over the triangle, each entry feeding both
+// a_ij x_j into row i and a_ij x_i into row j.
+template <int D, int NE, typename T>
+__device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const T* x, T* z) {
+  using A = acc_t<T>;
+  constexpr int NL = 2 * D * NE, NPK = NL * (NL + 1) / 2;
+  int e[3] = {0, 0, 0};
+  decode_elem<D>(Tq, n, e);
+  A xs[NL];
+#pragma unroll
+  for (int sl = 0; sl < 2 * D; ++sl) {
+    const int cc = sl / 2, sd = sl % 2;
+    const int p = e[cc] + sd;
+    if (p == 0 || p == n) {
+#pragma unroll
+      for (int b = 0; b < NE; ++b) xs[sl * NE + b] = A(0);
+    } else {
+      int fg[3] = {e[0], e[1], e[2]};
+      fg[cc] = p;
+      const T* xf = x + face_id<D>(cc, fg, n) * NE;
+#pragma unroll
+      for (int b = 0; b < NE; ++b) xs[sl * NE + b] = xf[b];
+    }
+  }
+  A acc[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) acc[i] = A(0);
+  const T* ap = Ap + elem_aos(Tq, NPK, 0);
+  int idx = 0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+#pragma unroll
+    for (int j = i; j < NL; ++j, ++idx) {
+      const A a = ap[(long)idx * LANES];
+      acc[i] += a * xs[j];
+      if (j != i) acc[j] += a * xs[i];
+    }
+  }
+  T* zp = z + elem_aos(Tq, NL, 0);
+#pragma unroll
+  for (int i = 0; i < NL; ++i) zp[(long)i * LANES] = T(acc[i]);
+}
+
+// second phase: (A x)_F = z_{T-}[slot 2c+1 rows] + z_{T+}[slot 2c rows]
+template <int D, int NE, typename T>
+__device__ inline int face_acc_z(long F, int n, const T* z, acc_t<T>* acc) {
+  constexpr int NL = 2 * D * NE;
+  int g[3] = {0, 0, 0};
+  const int c = decode_face<D>(F, n, g);
+  int em[3] = {g[0], g[1], g[2]};
+  em[c] = g[c] - 1;
+  const T* zm = z + elem_aos(elem_id<D>(em, n), NL, (2 * c + 1) * NE);
+  const T* zq = z + elem_aos(elem_id<D>(g, n), NL, 2 * c * NE);
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = acc_t<T>(zm[(long)a * LANES]) + acc_t<T>(zq[(long)a * LANES]);
+  return c;
+}
+
 // y = x + Dinv_F res (one block-Jacobi update of face F; x == nullptr: 0)
 template <int NE, typename T>
-__device__ inline void dinv_update(long F, const T* __restrict__ Dinv, const T* x, const T* res, T* y) {
-  T s[NE];
+__device__ inline void dinv_update(long F, const T* __restrict__ Dinv, const T* x, const acc_t<T>* res, T* y) {
+  acc_t<T> s[NE];
 #pragma unroll
-  for (int a = 0; a < NE; ++a) s[a] = x ? x[F * NE + a] : T(0);
+  for (int a = 0; a < NE; ++a) s[a] = x ? acc_t<T>(x[F * NE + a]) : acc_t<T>(0);
   aos_mv<T, NE * NE, NE, false>(Dinv + aos_item<T>(F, vpad<T>(NE * NE)), res, s);
 #pragma unroll
-  for (int a = 0; a < NE; ++a) y[F * NE + a] = s[a];
+  for (int a = 0; a < NE; ++a) y[F * NE + a] = T(s[a]);
 }
 
 // one block-Jacobi sweep / residual / apply for interior face F
 template <int D, int NE, typename T, int MODE>
 __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const T* __restrict__ Dinv, const T* x,
                                  const T* b, T* y) {
-  T acc[NE];
+  using A = acc_t<T>;
+  A acc[NE];
   face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_SWEEP) {
-    T res[NE];
+    A res[NE];
 #pragma unroll
-    for (int a = 0; a < NE; ++a) res[a] = b[F * NE + a] - acc[a];
+    for (int a = 0; a < NE; ++a) res[a] = A(b[F * NE + a]) - acc[a];
     dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES) {
 #pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = b[F * NE + a] - acc[a];
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(A(b[F * NE + a]) - acc[a]);
   } else {
 #pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = acc[a];
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(acc[a]);
   }
 }
 
 template <int NE, typename T>
 __device__ inline void jacobi0_item(long F, const T* __restrict__ Dinv, const T* r, T* e) {
-  T rv[NE];
+  acc_t<T> rv[NE];
 #pragma unroll
   for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
   dinv_update<NE, T>(F, Dinv, (const T*)nullptr, rv, e);

@@ -257,6 +257,36 @@ def test_vcycle_larger_coarsest_level(torch_cuda, monkeypatch, path, d, n, k, cn
     assert relerr(e32, eo) <= 1e-3
 
 
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_packed_element_major_matches_face_major(torch_cuda, monkeypatch, k):
+    """The finest p-level stored element-major (packed symmetric triangles,
+    two-phase apply) and face-major give the same apply, smoother, residual
+    restriction and V-cycle up to rounding, and the oracle's apply."""
+    kap, rng = _kappa(2, 32)
+    O = HDG(2, 32, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    x = rng.standard_normal(A.shape[0])
+    out = {}
+    for pack in ("1", "0"):
+        monkeypatch.setenv("HDG_NO_PACK", "0" if pack == "1" else "1")
+        P = _gpu(torch_cuda, 2, 32, k, kap)
+        P.build(local_corr=omg.LC_BOTH)
+        xt = torch_cuda.as_tensor(x)
+        out[pack] = (P.level_apply(0, xt).cpu().numpy(),
+                     P.level_apply(0, xt.float(), precision=1).cpu().numpy(),
+                     P.level_smooth(0, xt, 3).cpu().numpy(),
+                     P.vcycle(xt).cpu().numpy(),
+                     P.vcycle(xt.float(), precision=1).cpu().numpy())
+    names = ["apply fp64", "apply fp32", "3 sweeps", "vcycle fp64", "vcycle fp32"]
+    for i, nm in enumerate(names):
+        e = relerr(out["1"][i], out["0"][i])
+        say(f"[packed k={k}] {nm}: packed vs face-major {e:.2e}")
+        assert e <= (1e-12 if "fp32" not in nm else 2e-6)
+    e = relerr(out["1"][0], A @ x)
+    say(f"  packed apply vs oracle {e:.2e}")
+    assert e <= 1e-10
+
+
 @pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
 def test_iterates_at_fixed_count(torch_cuda, method):
     d, n, k = 2, 16, 2

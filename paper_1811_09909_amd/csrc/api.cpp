@@ -897,8 +897,8 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     Li.packed = Li.kind == 0 && P->pack && Li.nface > 0 && d == 2;  // 3D element maps (nl >= 54) would spill
     if (Li.packed) {
       const long npk = (long)Li.nl * (Li.nl + 1) / 2;
-      Li.Ap64 = dalloc<double>(P, pad64(Li.nelem) * npk, true);
-      Li.Ap32 = dalloc<float>(P, pad64(Li.nelem) * npk, true);
+      Li.Ap64 = dalloc<double>(P, pad64(Li.nelem) * pk_pad<double>(npk), true);
+      Li.Ap32 = dalloc<float>(P, pad64(Li.nelem) * pk_pad<float>(npk), true);
       Li.z[0] = dalloc<double>(P, pad64(Li.nelem) * Li.nl * cap, true);
       Li.z[1] = dalloc<float>(P, pad64(Li.nelem) * Li.nl * cap, true);
     } else {

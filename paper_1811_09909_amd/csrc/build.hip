@@ -444,9 +444,8 @@ __global__ void pack_sym_kernel(long nelem, int nl, const double* __restrict__ A
   const int j = i + e;
   const double* A = Aelem + T * (long)nl * nl;
   const double v = 0.5 * (A[i * nl + j] + A[j * nl + i]);
-  const long idx = (T >> 6) * (long)npk * LANES + (long)(t % npk) * LANES + (T & 63);
-  Ap64[idx] = v;
-  Ap32[idx] = (float)v;
+  Ap64[pk_off<double>(T, npk, t % npk)] = v;
+  Ap32[pk_off<float>(T, npk, t % npk)] = (float)v;
 }
 
 }  // namespace

@@ -672,13 +672,25 @@ __device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const
   A acc[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) acc[i] = A(0);
-  const T* ap = Ap + elem_aos(Tq, NPK, 0);
+  constexpr int W = pvw<T>();
+  const T* ap = Ap + pk_off<T>(Tq, NPK, 0);
   int idx = 0;
+  T v[W];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
 #pragma unroll
     for (int j = i; j < NL; ++j, ++idx) {
-      const A a = ap[(long)idx * LANES];
+      if (idx % W == 0) {
+        if constexpr (W == 1) {
+          v[0] = ap[(long)idx * LANES];
+        } else {
+          typedef T vt __attribute__((ext_vector_type(W)));
+          const vt g = *reinterpret_cast<const vt*>(ap + (long)(idx / W) * (LANES * W));
+#pragma unroll
+          for (int q = 0; q < W; ++q) v[q] = g[q];
+        }
+      }
+      const A a = v[idx % W];
       acc[i] += a * xs[j];
       if (j != i) acc[j] += a * xs[i];
     }

@@ -355,6 +355,20 @@ __global__ void __launch_bounds__(256) hpre_kernel(int n, const T* __restrict__ 
   if (M < nmacro) hpre_item<2, T>(M, n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
+// 4 lanes per macro-element (small levels)
+template <typename T>
+__global__ void __launch_bounds__(256) hpre4_kernel(int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                                    const T* __restrict__ P, const T* __restrict__ r,
+                                                    T* __restrict__ e, int do_corr, T* __restrict__ cb) {
+  const long nmacro = (long)(n / 2) * (n / 2);
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  const long M = t >> 2;
+  r += blockIdx.y * trace_len<2>(n, 2);
+  e += blockIdx.y * trace_len<2>(n, 2);
+  cb += blockIdx.y * nmacro * 8;
+  if (M < nmacro) hpre4_item<T>(M, (int)(t & 3), n, Af, AIIinv, P, r, e, do_corr, cb);
+}
+
 template <int D, typename T>
 __global__ void hsum_kernel(int n, const T* __restrict__ r, const T* __restrict__ cb, const T* __restrict__ Dc,
                             T* __restrict__ rc, T* __restrict__ ec) {
@@ -370,7 +384,8 @@ __global__ void hsum_kernel(int n, const T* __restrict__ r, const T* __restrict_
   if (Fc < ncf) hsum_item<D, T>(Fc, n, r, cb, Dc, rc, ec);
 }
 
-template <int D, typename T>
+// LPM lanes per macro-element in the macro part (1, or 4 on small 2D levels)
+template <int D, typename T, int LPM>
 __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __restrict__ Af,
                                                     const T* __restrict__ AIIinv, const T* __restrict__ P,
                                                     const T* __restrict__ r, const T* __restrict__ ec,
@@ -385,8 +400,12 @@ __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __
   }
   if (blockIdx.x < nbm) {
     const long nmacro = (long)(n / 2) * (n / 2);
-    const long M = blockIdx.x * 256L + threadIdx.x;
-    if (M < nmacro) hpost_m_item<D, T>(M, n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if constexpr (LPM == 4) {
+      if ((t >> 2) < nmacro) hpost4_m_item<T>(t >> 2, (int)(t & 3), n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
+    } else {
+      if (t < nmacro) hpost_m_item<D, T>(t, n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
+    }
   } else {
     const long ncf = D * nface_dir<D>(n / 2);
     const long Fc = (blockIdx.x - nbm) * 256L + threadIdx.x;
@@ -460,6 +479,14 @@ __global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* _
 }
 
 inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+
+// macro-element kernels use 4 lanes per macro-element up to this many
+// macro-elements (latency-bound levels), one lane above (bandwidth-bound);
+// HDG_MULTI_LANE_MAX overrides at build time
+#ifndef HDG_MULTI_LANE_MAX
+#define HDG_MULTI_LANE_MAX 16384
+#endif
+constexpr long MULTI_LANE_MAX = HDG_MULTI_LANE_MAX;
 
 // grid of the XCD-aware face launches (see xcd_face): 8 chunks of C blocks
 // per normal direction
@@ -650,8 +677,12 @@ void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr,
-                     cb);
+  if (L.nmacro <= MULTI_LANE_MAX)
+    hipLaunchKernelGGL((hpre4_kernel<T>), dim3(nblk(4 * L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e,
+                       do_corr, cb);
+  else
+    hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr,
+                       cb);
   HDG_CHECK(hipGetLastError());
 }
 
@@ -679,9 +710,16 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  const long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
-  hipLaunchKernelGGL((hpost_kernel<2, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai, P,
-                     r, ec, eold, enew, do_corr);
+  const long nbf = nblk(C.nface);
+  if (L.nmacro <= MULTI_LANE_MAX) {
+    const long nbm = nblk(4 * L.nmacro);
+    hipLaunchKernelGGL((hpost_kernel<2, T, 4>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai,
+                       P, r, ec, eold, enew, do_corr);
+  } else {
+    const long nbm = nblk(L.nmacro);
+    hipLaunchKernelGGL((hpost_kernel<2, T, 1>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai,
+                       P, r, ec, eold, enew, do_corr);
+  }
   HDG_CHECK(hipGetLastError());
 }
 

@@ -428,6 +428,81 @@ __device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const 
   for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = T(out[j]);
 }
 
+// The same pre-coarse work spread over 4 lanes of one wavefront per
+// macro-element (2D): lane q owns interior face q and the two boundary faces
+// of macro-face q, whose restriction shares are exactly the coarse DOFs
+// 2q, 2q+1 (S = q).  The interior residual is exchanged with shuffles; every
+// lane then forms its rows of A_II^-1 rho and its columns of P^T rho.  The
+// serial chain of loads per lane is about a quarter of hpre_item's, which is
+// what bounds the small (latency-bound) levels.  All 4 lanes of a group are
+// active together (the group's macro-element is in range or not).
+template <typename T>
+__device__ inline void hpre4_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                  const T* __restrict__ P, const T* r, T* e, int do_corr, T* cb) {
+  using Mc = Macro<2>;
+  using A = acc_t<T>;
+  constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL;
+  const int base = (int)(threadIdx.x & 60);
+  const int nm = n / 2;
+  int m[3] = {0, 0, 0};
+  decode_elem<2>(M, nm, m);
+  A eM[NIF + NBF][NC];
+  long fid[NIF + NBF];
+  int sidein[NIF + NBF];
+#pragma unroll
+  for (int f = 0; f < NIF + NBF; ++f) {
+    fid[f] = mface_id<2>(m, f, n, &sidein[f]);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(e[fid[f] * NC + a]) : A(0);
+  }
+  A acc[NC] = {A(0), A(0)};
+  side_apply<2, T>(Af, fid[q], 0, ichild<2>(q, 0), eM, acc);
+  side_apply<2, T>(Af, fid[q], 1, ichild<2>(q, 1), eM, acc);
+  A rq[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) rq[a] = A(r[fid[q] * NC + a]) - acc[a];
+  A rho[NI];
+#pragma unroll
+  for (int i = 0; i < NIF; ++i)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rho[i * NC + a] = __shfl(rq[a], base + i, 64);
+  if (do_corr) {
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const int row = q * NC + a;
+      A sacc = A(0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), row * NI + j)]) * rho[j];
+      e[fid[q] * NC + a] = T(eM[q][a] + sacc);
+    }
+  }
+  A o[NC];
+#pragma unroll
+  for (int V = 0; V < NC; ++V) {
+    A sacc = A(0);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), i * NCL + q * NC + V)]) * rho[i];
+    o[V] = sacc;
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    const int b = q * NC + t;
+    const int f = NIF + b;
+    if (fid[f] < 0) continue;
+    A ab[NC] = {A(0), A(0)};
+    side_apply<2, T>(Af, fid[f], sidein[f], bchild<2>(b), eM, ab);
+#pragma unroll
+    for (int V = 0; V < NC; ++V) {
+      A sacc = A(0);
+#pragma unroll
+      for (int v = 0; v < NC; ++v) sacc += A(jh_weight<2>(t, v, V)) * ab[v];
+      o[V] -= sacc;
+    }
+  }
+#pragma unroll
+  for (int V = 0; V < NC; ++V) cb[M * NCL + q * NC + V] = T(o[V]);
+}
+
 // Coarse residual r_c = J^T r_B + cb_{M-} + cb_{M+} per coarse face, and the
 // first block-Jacobi step of the coarse level e_c = D^-1 r_c (when Dc given)
 template <int D, typename T>
@@ -563,6 +638,98 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
 #pragma unroll
         for (int a = 0; a < NC; ++a) enew[fid[i] * NC + a] = T(eM[i][a]);
     }
+  }
+}
+
+// hpost_m_item over 4 lanes per macro-element (2D), as hpre4_item: lane q
+// prolongs onto interior face q, the prolonged interior values and then the
+// interior residual are exchanged with shuffles, and lane q applies its rows
+// of A_II^-1.
+template <typename T>
+__device__ inline void hpost4_m_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+                                     const T* __restrict__ P, const T* r, const T* ec, const T* eold, T* enew,
+                                     int do_corr) {
+  using Mc = Macro<2>;
+  using A = acc_t<T>;
+  constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
+  const int base = (int)(threadIdx.x & 60);
+  const int nm = n / 2;
+  int m[3] = {0, 0, 0};
+  decode_elem<2>(M, nm, m);
+  A cv[NCL];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) {
+    const int cc = sl / 2, sd = sl % 2;
+    const int p = m[cc] + sd;
+    if (p == 0 || p == nm) {
+#pragma unroll
+      for (int V = 0; V < NC; ++V) cv[sl * NC + V] = A(0);
+    } else {
+      int G[3] = {m[0], m[1], m[2]};
+      G[cc] = p;
+      const long Fc = face_id<2>(cc, G, nm);
+#pragma unroll
+      for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
+    }
+  }
+  A eM[NIF + NBF][NC];
+  long fid[NIF + NBF];
+  int sidein[NIF + NBF];
+#pragma unroll
+  for (int f = 0; f < NIF + NBF; ++f) {
+    fid[f] = mface_id<2>(m, f, n, &sidein[f]);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(eold[fid[f] * NC + a]) : A(0);
+  }
+  // B faces: e + J e_c (local copies only)
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int f = NIF + b;
+    if (fid[f] < 0) continue;
+    const int S = b / NS, t = b % NS;
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+      A sacc = A(0);
+#pragma unroll
+      for (int V = 0; V < NC; ++V) sacc += A(jh_weight<2>(t, v, V)) * cv[S * NC + V];
+      eM[f][v] += sacc;
+    }
+  }
+  // interior face q: e + P e_c, then shared
+  A eq[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    A sacc = A(0);
+#pragma unroll
+    for (int j = 0; j < NCL; ++j) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), (q * NC + a) * NCL + j)]) * cv[j];
+    eq[a] = eM[q][a] + sacc;
+  }
+#pragma unroll
+  for (int i = 0; i < NIF; ++i)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) eM[i][a] = __shfl(eq[a], base + i, 64);
+  if (!do_corr) {
+#pragma unroll
+    for (int a = 0; a < NC; ++a) enew[fid[q] * NC + a] = T(eq[a]);
+    return;
+  }
+  A acc[NC] = {A(0), A(0)};
+  side_apply<2, T>(Af, fid[q], 0, ichild<2>(q, 0), eM, acc);
+  side_apply<2, T>(Af, fid[q], 1, ichild<2>(q, 1), eM, acc);
+  A rq[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) rq[a] = A(r[fid[q] * NC + a]) - acc[a];
+  A rho[NI];
+#pragma unroll
+  for (int i = 0; i < NIF; ++i)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rho[i * NC + a] = __shfl(rq[a], base + i, 64);
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    A sacc = A(0);
+#pragma unroll
+    for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), (q * NC + a) * NI + j)]) * rho[j];
+    enew[fid[q] * NC + a] = T(eq[a] + sacc);
   }
 }
 

@@ -24,6 +24,7 @@ struct hdg_problem {
   bool fuse = true;              // fused 2D transition kernels (HDG_NO_FUSE=1 selects the unfused ones)
   int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (HDG_TAIL_N, 0 = off)
   bool pack = true;              // element-major packed finest p-level (HDG_NO_PACK=1: face-major)
+  bool strip = true;             // one-pass strip apply on packed levels (HDG_NO_STRIP=1: two-phase)
   int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
   TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -767,6 +768,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->fuse = std::getenv("HDG_NO_FUSE") == nullptr;
   if (const char* tn = std::getenv("HDG_TAIL_N")) P->tail_nmax = std::atoi(tn);
   if (const char* np = std::getenv("HDG_NO_PACK")) P->pack = std::atoi(np) == 0;
+  if (const char* ns = std::getenv("HDG_NO_STRIP")) P->strip = std::atoi(ns) == 0;
   HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
   P->nv = P->ref.nv;
@@ -895,6 +897,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     // the finest level of a p-transition (only trace applies touch it) is
     // stored element-major as packed symmetric triangles
     Li.packed = Li.kind == 0 && P->pack && Li.nface > 0 && d == 2;  // 3D element maps (nl >= 54) would spill
+    Li.strip = Li.packed && P->strip && Li.n % 64 == 0;
     if (Li.packed) {
       const long npk = (long)Li.nl * (Li.nl + 1) / 2;
       Li.Ap64 = dalloc<double>(P, pad64(Li.nelem) * pk_pad<double>(npk), true);

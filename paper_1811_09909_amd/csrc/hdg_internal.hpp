@@ -127,10 +127,12 @@ struct Level {
   double* Dinv64 = nullptr; float* Dinv32 = nullptr;
   // Element-major packed form (used instead of Af on the finest level of a
   // p-transition): the upper triangle of each symmetric element map, row by
-  // row, AoSoA over elements (entry e of element T at
-  // (T/64)*npk*64 + e*64 + T%64, npk = nl(nl+1)/2), and the per-element
-  // products z_T = A^e x_T ([nrhs][nelem padded to 64][nl], same AoSoA).
+  // row, AoSoA over elements in groups of 16 bytes (pk_off), and the
+  // per-element products z_T = A^e x_T ([nrhs][nelem padded to 64][nl],
+  // elem_aos) of the two-phase apply.  `strip`: the one-pass strip apply is
+  // used (2D, n a multiple of 64); z then holds its strip-edge products.
   bool packed = false;
+  bool strip = false;
   double* Ap64 = nullptr;   float* Ap32 = nullptr;
   void* z[2] = {nullptr, nullptr};
   // h-transition to the next level

@@ -30,42 +30,14 @@ using namespace dev;
 #define HDG_APPLY_WPE 1
 #endif
 
-// ZS: the level is stored element-major; Af then points to the per-element
-// products z of the first phase (elem_apply_kernel) and each face only adds
-// its two elements' rows.
-template <int D, int NE, typename T, int MODE, bool ZS = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
-                                                    const T* __restrict__ x, const T* __restrict__ bvec,
-                                                    T* __restrict__ y, const double* __restrict__ Jp,
-                                                    T* __restrict__ rc, float* __restrict__ y32,
-                                                    double* __restrict__ partials, int nrhs) {
-  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+// Output of one face given acc = (A x)_F, per mode (x, b, y, rc, y32
+// already offset to the face's right-hand side); reductions add to part.
+template <int D, int NE, typename T, int MODE>
+__device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restrict__ Dinv, const T* x,
+                                   const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
+                                   T* __restrict__ rc, float* __restrict__ y32, double& part) {
   constexpr int NC = 1 << (D - 1);
-  int rhs;
-  unsigned slot;
-  const long F = xcd_face_rhs<D>(n, nrhs, blockIdx.x, threadIdx.x, &rhs, &slot);
-  if (!RED && F < 0) return;
-  {
-    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
-    x += rhs * sN;
-    bvec = off(bvec, rhs * sN);
-    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
-    rc = off(rc, rhs * sC);
-    y32 = off(y32, rhs * sN);
-    if (ZS) {
-      long nelem = 1;
-      for (int a = 0; a < D; ++a) nelem *= n;
-      Af += rhs * ((nelem + 63) / 64 * 64) * (2 * D * NE);
-    }
-  }
-  double part = 0.0;
-  if (F >= 0) {
   using A = acc_t<T>;
-  A acc[NE];
-  if constexpr (ZS)
-    face_acc_z<D, NE, T>(F, n, Af, acc);
-  else
-    face_acc<D, NE, T>(F, n, Af, x, acc);
   if (MODE == APPLY_Y) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) y[F * NE + a] = T(acc[a]);
@@ -107,6 +79,45 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
       part += (double)v * (double)v;
     }
   }
+}
+
+// ZS: the level is stored element-major; Af then points to the per-element
+// products z of the first phase (elem_apply_kernel) and each face only adds
+// its two elements' rows.
+template <int D, int NE, typename T, int MODE, bool ZS = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
+                                                    const T* __restrict__ x, const T* __restrict__ bvec,
+                                                    T* __restrict__ y, const double* __restrict__ Jp,
+                                                    T* __restrict__ rc, float* __restrict__ y32,
+                                                    double* __restrict__ partials, int nrhs) {
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  constexpr int NC = 1 << (D - 1);
+  int rhs;
+  unsigned slot;
+  const long F = xcd_face_rhs<D>(n, nrhs, blockIdx.x, threadIdx.x, &rhs, &slot);
+  if (!RED && F < 0) return;
+  {
+    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
+    x += rhs * sN;
+    bvec = off(bvec, rhs * sN);
+    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
+    rc = off(rc, rhs * sC);
+    y32 = off(y32, rhs * sN);
+    if (ZS) {
+      long nelem = 1;
+      for (int a = 0; a < D; ++a) nelem *= n;
+      Af += rhs * ((nelem + 63) / 64 * 64) * (2 * D * NE);
+    }
+  }
+  double part = 0.0;
+  if (F >= 0) {
+  using A = acc_t<T>;
+  A acc[NE];
+  if constexpr (ZS)
+    face_acc_z<D, NE, T>(F, n, Af, acc);
+  else
+    face_acc<D, NE, T>(F, n, Af, x, acc);
+  face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
   }  // F >= 0
   if constexpr (RED) {
     __shared__ double sh[4];
@@ -137,6 +148,168 @@ __global__ void __launch_bounds__(256) elem_apply_kernel(int n, const T* __restr
   x += rhs * trace_len<D>(n, NE);
   z += rhs * ((nelem + 63) / 64 * 64) * (2 * D * NE);
   elem_item<D, NE, T>(Tq, n, Ap, x, z);
+}
+
+// One-pass apply of an element-major level in 2D (n a multiple of 64).  A
+// workgroup owns a strip of 64 x SH elements (one wavefront per grid row, so
+// a wavefront's matrix loads are one AoSoA block):
+//   phase 1: z_T = A^e x_T per element, into LDS;
+//   phase 2: every face whose two elements lie in the strip is finished from
+//            LDS (T- rows first, as face_acc_z adds them); each lane takes its
+//            element's right and top face.
+// The products of the faces on the strip's edge go to zsh ([nrhs][2 sides]
+// [NE][nshp]; side 0 = T-, 1 = T+), which shface_kernel finishes.  Faces on
+// strip edges: x = 64 m (m = 1 .. n/64-1, index (m-1) n + row) first, then
+// y = SH m (index NV + (m-1) n + column).  Workgroups go to the 8 XCDs in
+// contiguous bands of strips (right-hand side fastest after the XCD).
+// Requires x != y: a strip's outputs may be read as another strip's inputs.
+template <int NE, typename T, int MODE, int SH>
+__global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restrict__ Ap, const T* __restrict__ Dinv,
+                                                        const T* __restrict__ x, const T* __restrict__ bvec,
+                                                        T* __restrict__ y, const double* __restrict__ Jp,
+                                                        T* __restrict__ rc, float* __restrict__ y32,
+                                                        T* __restrict__ zsh, long nshp, int nbt,
+                                                        double* __restrict__ partials, int nrhs) {
+  constexpr int D = 2, NC = 2, NL = 4 * NE, NT = 64 * SH;
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  using A = acc_t<T>;
+  __shared__ __align__(16) T zs[NL * NT];
+  const int nsx = n / 64, nsy = n / SH;
+  const unsigned nstrip = (unsigned)nsx * (unsigned)nsy;
+  const unsigned C = (nstrip + 7u) / 8u;
+  const unsigned p = blockIdx.x, xj = p & 7u, m = p >> 3;
+  const int rhs = (int)(m % (unsigned)nrhs);
+  const unsigned w = m / (unsigned)nrhs;
+  const unsigned sidx = xj * C + w;
+  const long slot = (long)rhs * nbt + xj + 8u * w;
+  if (w >= C || sidx >= nstrip) {  // whole workgroup out of range
+    if (RED && w < C && threadIdx.x == 0) partials[slot] = 0.0;
+    return;
+  }
+  const int sy = (int)(sidx / (unsigned)nsx), sx = (int)(sidx - (unsigned)sy * (unsigned)nsx);
+  const int tid = threadIdx.x, j = tid & 63, rr = tid >> 6;
+  const int ex = sx * 64 + j, ey = sy * SH + rr;
+  {
+    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
+    x += rhs * sN;
+    bvec = off(bvec, rhs * sN);
+    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
+    rc = off(rc, rhs * sC);
+    y32 = off(y32, rhs * sN);
+    zsh += rhs * (2L * NE) * nshp;
+  }
+  {
+    A acc[NL];
+    elem_prod<D, NE, T>((long)ey * n + ex, n, Ap, x, acc);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) zs[i * NT + tid] = T(acc[i]);
+  }
+  __syncthreads();
+  const long nfd = (long)(n - 1) * n, NV = (long)(nsx - 1) * n;
+  double part = 0.0;
+  A acc[NE];
+  // right face (normal x at ex + 1): slot 1 of this element, slot 0 of the next
+  if (ex + 1 < n) {
+    if (j < 63) {
+      const long F = (long)ex + (long)(n - 1) * ey;
+#pragma unroll
+      for (int a = 0; a < NE; ++a) acc[a] = A(zs[(NE + a) * NT + tid]) + A(zs[a * NT + tid + 1]);
+      face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+    } else {
+      const long q = (long)sx * n + ey;  // edge x = 64 (sx + 1)
+#pragma unroll
+      for (int a = 0; a < NE; ++a) zsh[(long)a * nshp + q] = zs[(NE + a) * NT + tid];
+    }
+  }
+  // top face (normal y at ey + 1): slot 3 of this element, slot 2 of the one above
+  if (ey + 1 < n) {
+    if (rr < SH - 1) {
+      const long F = nfd + ex + (long)n * ey;
+#pragma unroll
+      for (int a = 0; a < NE; ++a) acc[a] = A(zs[(3 * NE + a) * NT + tid]) + A(zs[(2 * NE + a) * NT + tid + 64]);
+      face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+    } else {
+      const long q = NV + (long)sy * n + ex;  // edge y = SH (sy + 1)
+#pragma unroll
+      for (int a = 0; a < NE; ++a) zsh[(long)a * nshp + q] = zs[(3 * NE + a) * NT + tid];
+    }
+  }
+  // left and bottom strip edges inside the domain: this element is T+
+  if (j == 0 && ex > 0) {
+    const long q = (long)(sx - 1) * n + ey;
+#pragma unroll
+    for (int a = 0; a < NE; ++a) zsh[(long)(NE + a) * nshp + q] = zs[a * NT + tid];
+  }
+  if (rr == 0 && ey > 0) {
+    const long q = NV + (long)(sy - 1) * n + ex;
+#pragma unroll
+    for (int a = 0; a < NE; ++a) zsh[(long)(NE + a) * nshp + q] = zs[(2 * NE + a) * NT + tid];
+  }
+  if constexpr (RED) {  // the reduction reuses the product area once every lane is done with it
+    __syncthreads();
+    const double s = block_sum_t<NT>(part, reinterpret_cast<double*>(zs));
+    if (threadIdx.x == 0) partials[slot] = s;
+  }
+}
+
+// Faces on strip edges: (A x)_F = T- product + T+ product from zsh, then the
+// mode's output.  Lane t of block b takes horizontal edge face b*256 + t
+// (consecutive face ids: coalesced) and, for t < vpb, vertical edge face
+// b*vpb + t: those are a grid column apart, so each one's loads are
+// scattered, and they are spread thinly over all blocks.  Grid (blocks,
+// nrhs); partials after the strip blocks' ones.
+template <int NE, typename T, int MODE, int SH>
+__device__ inline void shface_one(long q, int n, long NV, const T* __restrict__ Dinv, const T* x,
+                                  const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
+                                  T* __restrict__ rc, float* __restrict__ y32, const T* __restrict__ zsh, long nshp,
+                                  double& part) {
+  using A = acc_t<T>;
+  long F;
+  if (q < NV) {
+    const long mm = q / n, row = q - mm * n;  // x = 64 (mm + 1)
+    F = 64 * (mm + 1) - 1 + (long)(n - 1) * row;
+  } else {
+    const long h = q - NV, mm = h / n, col = h - mm * n;  // y = SH (mm + 1)
+    F = (long)(n - 1) * n + col + (long)n * (SH * (mm + 1) - 1);
+  }
+  A acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = A(zsh[(long)a * nshp + q]) + A(zsh[(long)(NE + a) * nshp + q]);
+  face_finish<2, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+}
+
+template <int NE, typename T, int MODE, int SH>
+__global__ void __launch_bounds__(256) shface_kernel(int n, const T* __restrict__ Dinv, const T* __restrict__ x,
+                                                     const T* __restrict__ bvec, T* __restrict__ y,
+                                                     const double* __restrict__ Jp, T* __restrict__ rc,
+                                                     float* __restrict__ y32, const T* __restrict__ zsh, long nshp,
+                                                     int vpb, int nbt, int nb0, double* __restrict__ partials) {
+  constexpr int D = 2, NC = 2;
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  const int rhs = blockIdx.y;
+  const long nsx = n / 64, nsy = n / SH;
+  const long NV = (nsx - 1) * n, NH = (nsy - 1) * n;
+  {
+    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
+    x += rhs * sN;
+    bvec = off(bvec, rhs * sN);
+    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
+    rc = off(rc, rhs * sC);
+    y32 = off(y32, rhs * sN);
+    zsh += rhs * (2L * NE) * nshp;
+  }
+  double part = 0.0;
+  if ((int)threadIdx.x < vpb) {
+    const long v = (long)blockIdx.x * vpb + threadIdx.x;
+    if (v < NV) shface_one<NE, T, MODE, SH>(v, n, NV, Dinv, x, bvec, y, Jp, rc, y32, zsh, nshp, part);
+  }
+  const long h = blockIdx.x * 256L + threadIdx.x;
+  if (h < NH) shface_one<NE, T, MODE, SH>(NV + h, n, NV, Dinv, x, bvec, y, Jp, rc, y32, zsh, nshp, part);
+  if constexpr (RED) {
+    __shared__ double sh[4];
+    const double s = block_sum_t<256>(part, sh);
+    if (threadIdx.x == 0) partials[(long)rhs * nbt + nb0 + blockIdx.x] = s;
+  }
 }
 
 // e += J_N ec on every face (p-prolongation)
@@ -510,6 +683,48 @@ void dispatch_d_ne(int d, int ne, F&& f) {
   throw HipError{hipErrorInvalidValue, "unsupported (d, ne)"};
 }
 
+// rows of elements per strip of the one-pass element-major apply (the LDS
+// products of a 64 x SH strip: 20 KiB per 256 lanes in FP32 at k = 4)
+#ifndef HDG_STRIP_ROWS32
+#define HDG_STRIP_ROWS32 8
+#endif
+template <typename T>
+constexpr int strip_rows() {
+  return sizeof(T) == 4 ? HDG_STRIP_ROWS32 : 4;
+}
+
+// one-pass element-major apply (strip_kernel + shface_kernel); returns the
+// number of partial sums per right-hand side
+template <typename T, int MODE>
+int launch_strips(const Level& L, const T* Dv, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
+                  double* partials, hipStream_t st, int nrhs) {
+  constexpr int SH = strip_rows<T>();
+  const T* Ap = sizeof(T) == 8 ? (const T*)L.Ap64 : (const T*)L.Ap32;
+  T* zsh = (T*)L.z[sizeof(T) == 8 ? 0 : 1];
+  const int n = L.n;
+  const long nsx = n / 64, nsy = n / SH;
+  const long NV = (nsx - 1) * n, NH = (nsy - 1) * n;
+  const long nsh = NV + NH, nshp = pad64(nsh);
+  const long C = (nsx * nsy + 7) / 8;
+  const long nbs = 8 * C, nbh = (NH + 255) / 256;
+  const int vpb = nbh > 0 ? (int)((NV + nbh - 1) / nbh) : 0;
+  const int nbt = (int)(nbs + nbh);
+  if (vpb > 256 || (NV > 0 && nbh == 0))
+    throw HipError{hipErrorInvalidValue, "strip apply: edge faces do not fit the edge kernel"};
+  if (x == y || 2 * L.ne * nshp > pad64(L.nelem) * L.nl)
+    throw HipError{hipErrorInvalidValue, "strip apply: in-place output or edge buffer too small"};
+  dispatch_d_ne(2, L.ne, [&](auto, auto NE_) {
+    constexpr int NE = decltype(NE_)::value;
+    hipLaunchKernelGGL((strip_kernel<NE, T, MODE, SH>), dim3((unsigned)(nbs * nrhs)), dim3(64 * SH), 0, st, n, Ap,
+                       Dv, x, b, y, Jp, rc, y32, zsh, nshp, nbt, partials, nrhs);
+    if (nbh > 0)
+      hipLaunchKernelGGL((shface_kernel<NE, T, MODE, SH>), dim3((unsigned)nbh, nrhs), dim3(256), 0, st, n, Dv, x, b,
+                         y, Jp, rc, y32, zsh, nshp, vpb, nbt, (int)nbs, partials);
+  });
+  HDG_CHECK(hipGetLastError());
+  return nbt;
+}
+
 // first phase of the element-major apply on a packed level
 template <typename T>
 void launch_elem_phase(const Level& L, const T* x, hipStream_t st, int nrhs) {
@@ -546,7 +761,26 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     Af = (const T*)L.Af32;
     Dv = (const T*)L.Dinv32;
   }
-  const unsigned g1 = xcd_grid(L.d, L.n);
+  unsigned g1 = xcd_grid(L.d, L.n);
+  if (L.strip) {
+    int nbt = 0;
+    switch (mode) {
+      case APPLY_Y: nbt = launch_strips<T, APPLY_Y>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs); break;
+      case APPLY_RES: nbt = launch_strips<T, APPLY_RES>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs); break;
+      case APPLY_SWEEP: nbt = launch_strips<T, APPLY_SWEEP>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs); break;
+      case APPLY_RES_PRESTRICT:
+        nbt = launch_strips<T, APPLY_RES_PRESTRICT>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs);
+        break;
+      case APPLY_Y_DOT: nbt = launch_strips<T, APPLY_Y_DOT>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs); break;
+      case APPLY_RES_NORM:
+        nbt = launch_strips<T, APPLY_RES_NORM>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs);
+        break;
+      default: throw HipError{hipErrorInvalidValue, "apply mode"};
+    }
+    if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
+      blas_finalize(nbt, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+    return;
+  }
   if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
   const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
@@ -582,6 +816,10 @@ void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b
   if (L.nface == 0) return;
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Dc = sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32;
+  if (L.strip) {
+    launch_strips<T, APPLY_RES_PRESTRICT>(L, Dc, x, b, ec, Jp, rc, nullptr, nullptr, st, nrhs);
+    return;
+  }
   if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
   const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {

@@ -810,12 +810,11 @@ __device__ inline long xcd_elem_rhs(long nelem, int nrhs, unsigned p, unsigned t
 // entries per element
 __device__ inline long elem_aos(long T, int per, int i) { return (T >> 6) * (long)per * LANES + (long)i * LANES + (T & 63); }
 
-// z_T = A^e x_T for element T from the packed upper triangle (first phase of
-// the element-major apply): gather the element's traces (zero on the
-// boundary), then one pass over the triangle, each entry feeding both
-// a_ij x_j into row i and a_ij x_i into row j.
+// acc = A^e x_T for element T from the packed upper triangle: gather the
+// element's traces (zero on the boundary), then one pass over the triangle,
+// each entry feeding both a_ij x_j into row i and a_ij x_i into row j.
 template <int D, int NE, typename T>
-__device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const T* x, T* z) {
+__device__ inline void elem_prod(long Tq, int n, const T* __restrict__ Ap, const T* x, acc_t<T>* acc) {
   using A = acc_t<T>;
   constexpr int NL = 2 * D * NE, NPK = NL * (NL + 1) / 2;
   int e[3] = {0, 0, 0};
@@ -836,7 +835,6 @@ __device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const
       for (int b = 0; b < NE; ++b) xs[sl * NE + b] = xf[b];
     }
   }
-  A acc[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) acc[i] = A(0);
   constexpr int W = pvw<T>();
@@ -862,6 +860,14 @@ __device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const
       if (j != i) acc[j] += a * xs[i];
     }
   }
+}
+
+// z_T = A^e x_T stored element-major (first phase of the two-phase apply)
+template <int D, int NE, typename T>
+__device__ inline void elem_item(long Tq, int n, const T* __restrict__ Ap, const T* x, T* z) {
+  constexpr int NL = 2 * D * NE;
+  acc_t<T> acc[NL];
+  elem_prod<D, NE, T>(Tq, n, Ap, x, acc);
   T* zp = z + elem_aos(Tq, NL, 0);
 #pragma unroll
   for (int i = 0; i < NL; ++i) zp[(long)i * LANES] = T(acc[i]);

@@ -287,6 +287,56 @@ def test_packed_element_major_matches_face_major(torch_cuda, monkeypatch, k):
     assert e <= 1e-10
 
 
+@pytest.mark.parametrize("n,k", [(64, 2), (64, 4), (64, 6), (128, 3)])
+def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
+    """The one-pass strip apply (element products kept in LDS, faces on strip
+    edges finished by a second kernel) adds the same two element products in
+    the same order as the two-phase apply: apply, sweeps, the residual
+    restriction inside the V-cycle, and V-cycles over one and three
+    right-hand sides agree bit for bit; the mixed PCG solve (whose dot
+    products sum over other blocks) agrees to its tolerance; and the apply
+    matches the oracle's assembled operator."""
+    from paper_1811_09909_amd import _lib as L
+    kap, rng = _kappa(2, n, 1e-2, 1e2)
+    O = HDG(2, n, k, 1.0, kap)
+    A, _, _ = O.assemble()
+    N = A.shape[0]
+    x = rng.standard_normal(N)
+    X3 = rng.standard_normal(3 * N)
+    f = rng.standard_normal((n * n, O.nv))
+    out, sol = {}, {}
+    for strip in ("1", "0"):
+        monkeypatch.setenv("HDG_NO_STRIP", "0" if strip == "1" else "1")
+        P = _gpu(torch_cuda, 2, n, k, kap)
+        P.build(local_corr=omg.LC_BOTH, nrhs=3)
+        xt = torch_cuda.as_tensor(x)
+        X3t = torch_cuda.as_tensor(X3)
+        out[strip] = [P.level_apply(0, xt).cpu().numpy(),
+                      P.level_apply(0, xt.float(), precision=1).cpu().numpy(),
+                      P.level_smooth(0, xt, 3).cpu().numpy(),
+                      P.level_smooth(0, xt.float(), 3, precision=1).cpu().numpy(),
+                      P.vcycle(xt).cpu().numpy(),
+                      P.vcycle(xt.float(), precision=1).cpu().numpy(),
+                      P.vcycle(X3t).cpu().numpy(),
+                      P.vcycle(X3t.float(), precision=1).cpu().numpy()]
+        P.build(local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=500)
+        sol[strip] = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+    names = ["apply fp64", "apply fp32", "3 sweeps fp64", "3 sweeps fp32", "vcycle fp64", "vcycle fp32",
+             "vcycle fp64 x3", "vcycle fp32 x3"]
+    for i, nm in enumerate(names):
+        diff = np.abs(out["1"][i] - out["0"][i]).max()
+        say(f"[strip n={n} k={k}] {nm}: strip vs two-phase max diff {diff:.1e}")
+        assert diff == 0.0
+    e = relerr(out["1"][0], A @ x)
+    say(f"  strip apply vs oracle {e:.2e}")
+    assert e <= 1e-12
+    (l1, i1), (l0, i0) = sol["1"], sol["0"]
+    e = relerr(l1.cpu().numpy(), l0.cpu().numpy())
+    say(f"  mixed PCG: iterations {i1['iters']} / {i0['iters']}, relres {i1['relres']:.2e}, strip vs two-phase {e:.2e}")
+    assert i1["relres"] <= 1e-10 and abs(i1["iters"] - i0["iters"]) <= 1
+    assert e <= 1e-8
+
+
 @pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
 def test_iterates_at_fixed_count(torch_cuda, method):
     d, n, k = 2, 16, 2

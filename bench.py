@@ -25,14 +25,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 CAL_BYTES = 1 << 30
 # HBM traffic of one finest-level FP32 sweep of the 512^2, k = 4 workload
-# (element phase + face phase), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of
-# `bench.py --traffic-probe` (per-dispatch counter values, KiB units), each
-# scaled by what the same counter reads for a kernel that reads and writes
-# exactly CAL_BYTES.  Valid only for the kernel sources it was taken on.
-TRAFFIC = {"fetch": 113650.0 + 46027.0, "write": 20480.0 + 10220.0, "cal_fetch": 524300.0, "cal_write": 1048576.0,
-           "sources_sha256_16": "89b3db2fa93c3ae7"}
+# (strip kernel + strip-edge kernel), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# runs of `bench.py --traffic-probe` (per-dispatch counter values, KiB units),
+# each scaled by what the same counter reads for a kernel that reads and
+# writes exactly CAL_BYTES.  Valid only for the kernel sources it was taken on.
+TRAFFIC = {"fetch": 137727.5 + 6248.0, "write": 11011.125 + 798.0, "cal_fetch": 524300.0, "cal_write": 1048576.0,
+           "sources_sha256_16": "5f79a346bf344dda"}
 TRAFFIC_SOURCES = ["paper_1811_09909_amd/csrc/trace.hip", "paper_1811_09909_amd/csrc/trace_dev.hpp",
-                   "paper_1811_09909_amd/csrc/hdg_internal.hpp"]
+                   "paper_1811_09909_amd/csrc/hdg_internal.hpp", "paper_1811_09909_amd/csrc/build.hip"]
 
 
 def sweep_traffic_bytes():
@@ -289,7 +289,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / 1e9, 4),
                 "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                "kernel": f"trace {dom_name} (finest level: element phase + face phase)",
+                "kernel": f"trace {dom_name} (finest level: strip kernel + strip-edge kernel)",
                 "avg_launch_ms": round(avg_ms, 5), "launches": dom["launches"],
                 "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {name: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 5),

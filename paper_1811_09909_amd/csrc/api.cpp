@@ -990,6 +990,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     const long nface0 = L[0].nface;
     const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
     P->s.partials = dalloc<double>(P, 2 * nb * cap, true);
+    P->s.row = 2 * nb;
     HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT * cap, P->st));
   }
   if (o.method == HDG_METHOD_GMRES) {
@@ -1351,7 +1352,9 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   double bytes = L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * s : (double)L.nface * 2.0 * L.ne * L.nl * s;
   if (mode == APPLY_Y) bytes += 2.0 * N * s;
   if (mode == APPLY_RES) bytes += 3.0 * N * s;
-  if (mode == APPLY_SWEEP) bytes += (double)L.nface * L.ne * L.ne * s + 3.0 * N * s;
+  // face-block inverses: full blocks, or upper triangles on element-major levels
+  const double nd = L.packed ? L.ne * (L.ne + 1) / 2 : L.ne * L.ne;
+  if (mode == APPLY_SWEEP) bytes += (double)L.nface * nd * s + 3.0 * N * s;
   if (mode == APPLY_RES_PRESTRICT) bytes += 2.0 * N * s + (double)L.nface * (1 << (L.d - 1)) * s;
   if (launches) *launches = P->prof_n[kernel];
   if (total_ms) *total_ms = P->prof_ms[kernel];

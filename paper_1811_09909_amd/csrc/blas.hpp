@@ -28,6 +28,7 @@ constexpr int MAX_RED_BLOCKS = 4096;
 struct Scratch {
   double* sc = nullptr;        // device scalars [nrhs][SC_COUNT]
   double* partials = nullptr;  // [nrhs][2 * max(MAX_RED_BLOCKS, blocks of the widest reducing launch)]
+  long row = 0;                // partials per right-hand side
 };
 
 // nrhs: vectors of length n stored one after another; each right-hand side

@@ -65,10 +65,11 @@ __global__ void face_major_kernel(int d, int n, int ne, long nface, const double
   Af32[aos_off<float>(F, 2 * s32, side * s32 + ent)] = (float)v;
 }
 
-// omega * (A_{T-}[F,F] + A_{T+}[F,F])^-1 per face
+// omega * (A_{T-}[F,F] + A_{T+}[F,F])^-1 per face; sym: stored as the upper
+// triangle (row by row) of the symmetrized inverse
 template <int NE>
 __global__ void dinv_kernel(int d, int n, long nface, double omega, const double* __restrict__ Aelem,
-                            double* __restrict__ D64, float* __restrict__ D32) {
+                            double* __restrict__ D64, float* __restrict__ D32, int sym) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
   const int nl = 2 * d * NE;
@@ -97,6 +98,17 @@ __global__ void dinv_kernel(int d, int n, long nface, double omega, const double
       A[i * NE + k] = -f * p;
     }
     A[k * NE + k] = p;
+  }
+  if (sym) {
+    constexpr int NP = NE * (NE + 1) / 2;
+    int idx = 0;
+    for (int i = 0; i < NE; ++i)
+      for (int j = i; j < NE; ++j, ++idx) {
+        const double v = omega * 0.5 * (A[i * NE + j] + A[j * NE + i]);
+        D64[aos_off<double>(F, vpad<double>(NP), idx)] = v;
+        D32[aos_off<float>(F, vpad<float>(NP), idx)] = (float)v;
+      }
+    return;
   }
   for (int i = 0; i < NE * NE; ++i) {
     const double v = omega * A[i];
@@ -470,7 +482,7 @@ void launch_dinv(const Level& L, double omega, hipStream_t st) {
 #define HDG_DCASE(NN)                                                                                     \
   case NN:                                                                                                \
     hipLaunchKernelGGL((dinv_kernel<NN>), dim3(nblk(L.nface)), dim3(256), 0, st, L.d, L.n, L.nface, omega, \
-                       L.Aelem, L.Dinv64, L.Dinv32);                                                      \
+                       L.Aelem, L.Dinv64, L.Dinv32, L.packed ? 1 : 0);                                    \
     break;
   switch (L.ne) {
     HDG_DCASE(2) HDG_DCASE(3) HDG_DCASE(4) HDG_DCASE(5) HDG_DCASE(6) HDG_DCASE(7) HDG_DCASE(9) HDG_DCASE(16)

@@ -32,7 +32,8 @@ using namespace dev;
 
 // Output of one face given acc = (A x)_F, per mode (x, b, y, rc, y32
 // already offset to the face's right-hand side); reductions add to part.
-template <int D, int NE, typename T, int MODE>
+// DSYM: the level's face-block inverses are stored as upper triangles.
+template <int D, int NE, typename T, int MODE, bool DSYM = false>
 __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restrict__ Dinv, const T* x,
                                    const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
                                    T* __restrict__ rc, float* __restrict__ y32, double& part) {
@@ -48,7 +49,10 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
     A res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
-    dinv_update<NE, T>(F, Dinv, x, res, y);
+    if constexpr (DSYM)
+      dinv_update_sym<NE, T>(F, Dinv, x, res, y);
+    else
+      dinv_update<NE, T>(F, Dinv, x, res, y);
   } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
     A res[NE];
 #pragma unroll
@@ -117,7 +121,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
     face_acc_z<D, NE, T>(F, n, Af, acc);
   else
     face_acc<D, NE, T>(F, n, Af, x, acc);
-  face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+  face_finish<D, NE, T, MODE, ZS>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
   }  // F >= 0
   if constexpr (RED) {
     __shared__ double sh[4];
@@ -127,13 +131,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
 }
 
 // e = Dinv r (first sweep from e = 0)
-template <int NE, typename T>
+template <int NE, typename T, bool DSYM>
 __global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* __restrict__ r, T* __restrict__ e) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
   r += blockIdx.y * nface * NE;
   e += blockIdx.y * nface * NE;
-  jacobi0_item<NE, T>(F, Dinv, r, e);
+  jacobi0_item<NE, T, DSYM>(F, Dinv, r, e);
 }
 
 // first phase of the element-major apply: z_T = A^e x_T for every element
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restri
       const long F = (long)ex + (long)(n - 1) * ey;
 #pragma unroll
       for (int a = 0; a < NE; ++a) acc[a] = A(zs[(NE + a) * NT + tid]) + A(zs[a * NT + tid + 1]);
-      face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+      face_finish<D, NE, T, MODE, true>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
     } else {
       const long q = (long)sx * n + ey;  // edge x = 64 (sx + 1)
 #pragma unroll
@@ -227,7 +231,7 @@ __global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restri
       const long F = nfd + ex + (long)n * ey;
 #pragma unroll
       for (int a = 0; a < NE; ++a) acc[a] = A(zs[(3 * NE + a) * NT + tid]) + A(zs[(2 * NE + a) * NT + tid + 64]);
-      face_finish<D, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+      face_finish<D, NE, T, MODE, true>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
     } else {
       const long q = NV + (long)sy * n + ex;  // edge y = SH (sy + 1)
 #pragma unroll
@@ -258,6 +262,12 @@ __global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restri
 // b*vpb + t: those are a grid column apart, so each one's loads are
 // scattered, and they are spread thinly over all blocks.  Grid (blocks,
 // nrhs); partials after the strip blocks' ones.
+// lanes per block of the strip-edge kernel
+#ifndef HDG_SHF_TPB
+#define HDG_SHF_TPB 256
+#endif
+constexpr int SHF_TPB = HDG_SHF_TPB;
+
 template <int NE, typename T, int MODE, int SH>
 __device__ inline void shface_one(long q, int n, long NV, const T* __restrict__ Dinv, const T* x,
                                   const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
@@ -275,11 +285,11 @@ __device__ inline void shface_one(long q, int n, long NV, const T* __restrict__ 
   A acc[NE];
 #pragma unroll
   for (int a = 0; a < NE; ++a) acc[a] = A(zsh[(long)a * nshp + q]) + A(zsh[(long)(NE + a) * nshp + q]);
-  face_finish<2, NE, T, MODE>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+  face_finish<2, NE, T, MODE, true>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
 }
 
 template <int NE, typename T, int MODE, int SH>
-__global__ void __launch_bounds__(256) shface_kernel(int n, const T* __restrict__ Dinv, const T* __restrict__ x,
+__global__ void __launch_bounds__(SHF_TPB) shface_kernel(int n, const T* __restrict__ Dinv, const T* __restrict__ x,
                                                      const T* __restrict__ bvec, T* __restrict__ y,
                                                      const double* __restrict__ Jp, T* __restrict__ rc,
                                                      float* __restrict__ y32, const T* __restrict__ zsh, long nshp,
@@ -303,11 +313,11 @@ __global__ void __launch_bounds__(256) shface_kernel(int n, const T* __restrict_
     const long v = (long)blockIdx.x * vpb + threadIdx.x;
     if (v < NV) shface_one<NE, T, MODE, SH>(v, n, NV, Dinv, x, bvec, y, Jp, rc, y32, zsh, nshp, part);
   }
-  const long h = blockIdx.x * 256L + threadIdx.x;
+  const long h = blockIdx.x * (long)SHF_TPB + threadIdx.x;
   if (h < NH) shface_one<NE, T, MODE, SH>(NV + h, n, NV, Dinv, x, bvec, y, Jp, rc, y32, zsh, nshp, part);
   if constexpr (RED) {
-    __shared__ double sh[4];
-    const double s = block_sum_t<256>(part, sh);
+    __shared__ double sh[SHF_TPB / 64];
+    const double s = block_sum_t<SHF_TPB>(part, sh);
     if (threadIdx.x == 0) partials[(long)rhs * nbt + nb0 + blockIdx.x] = s;
   }
 }
@@ -706,10 +716,10 @@ int launch_strips(const Level& L, const T* Dv, const T* x, const T* b, T* y, con
   const long NV = (nsx - 1) * n, NH = (nsy - 1) * n;
   const long nsh = NV + NH, nshp = pad64(nsh);
   const long C = (nsx * nsy + 7) / 8;
-  const long nbs = 8 * C, nbh = (NH + 255) / 256;
+  const long nbs = 8 * C, nbh = (NH + SHF_TPB - 1) / SHF_TPB;
   const int vpb = nbh > 0 ? (int)((NV + nbh - 1) / nbh) : 0;
   const int nbt = (int)(nbs + nbh);
-  if (vpb > 256 || (NV > 0 && nbh == 0))
+  if (vpb > SHF_TPB || (NV > 0 && nbh == 0))
     throw HipError{hipErrorInvalidValue, "strip apply: edge faces do not fit the edge kernel"};
   if (x == y || 2 * L.ne * nshp > pad64(L.nelem) * L.nl)
     throw HipError{hipErrorInvalidValue, "strip apply: in-place output or edge buffer too small"};
@@ -718,7 +728,7 @@ int launch_strips(const Level& L, const T* Dv, const T* x, const T* b, T* y, con
     hipLaunchKernelGGL((strip_kernel<NE, T, MODE, SH>), dim3((unsigned)(nbs * nrhs)), dim3(64 * SH), 0, st, n, Ap,
                        Dv, x, b, y, Jp, rc, y32, zsh, nshp, nbt, partials, nrhs);
     if (nbh > 0)
-      hipLaunchKernelGGL((shface_kernel<NE, T, MODE, SH>), dim3((unsigned)nbh, nrhs), dim3(256), 0, st, n, Dv, x, b,
+      hipLaunchKernelGGL((shface_kernel<NE, T, MODE, SH>), dim3((unsigned)nbh, nrhs), dim3(SHF_TPB), 0, st, n, Dv, x, b,
                          y, Jp, rc, y32, zsh, nshp, vpb, nbt, (int)nbs, partials);
   });
   HDG_CHECK(hipGetLastError());
@@ -777,8 +787,10 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
         break;
       default: throw HipError{hipErrorInvalidValue, "apply mode"};
     }
-    if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
+    if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
+      if (nbt > red->row) throw HipError{hipErrorInvalidValue, "strip apply: too many partial sums"};
       blas_finalize(nbt, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+    }
     return;
   }
   if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
@@ -841,7 +853,12 @@ void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) 
   const T* Dv = sizeof(T) == 8 ? (const T*)L.Dinv64 : (const T*)L.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int NE = decltype(NE_)::value;
-    hipLaunchKernelGGL((jacobi0_kernel<NE, T>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r, e);
+    if (L.packed)
+      hipLaunchKernelGGL((jacobi0_kernel<NE, T, true>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r,
+                         e);
+    else
+      hipLaunchKernelGGL((jacobi0_kernel<NE, T, false>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r,
+                         e);
   });
   HDG_CHECK(hipGetLastError());
 }

@@ -899,6 +899,32 @@ __device__ inline void dinv_update(long F, const T* __restrict__ Dinv, const T* 
   for (int a = 0; a < NE; ++a) y[F * NE + a] = T(s[a]);
 }
 
+// as dinv_update with the block stored as its upper triangle, row by row
+// (the symmetric inverse of an SPD block; element-major levels)
+template <int NE, typename T>
+__device__ inline void dinv_update_sym(long F, const T* __restrict__ Dinv, const T* x, const acc_t<T>* res, T* y) {
+  using A = acc_t<T>;
+  constexpr int NP = NE * (NE + 1) / 2, V = vw<T>();
+  A s[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) s[a] = x ? A(x[F * NE + a]) : A(0);
+  const T* blk = Dinv + aos_item<T>(F, vpad<T>(NP));
+  int idx = 0;
+  T v[V];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+#pragma unroll
+    for (int j = i; j < NE; ++j, ++idx) {
+      if (idx % V == 0) ld_group<T>(blk + (idx / V) * (LANES * V), v);
+      const A d = A(v[idx % V]);
+      s[i] += d * res[j];
+      if (j != i) s[j] += d * res[i];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) y[F * NE + a] = T(s[a]);
+}
+
 // one block-Jacobi sweep / residual / apply for interior face F
 template <int D, int NE, typename T, int MODE>
 __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const T* __restrict__ Dinv, const T* x,
@@ -920,12 +946,15 @@ __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const 
   }
 }
 
-template <int NE, typename T>
+template <int NE, typename T, bool DSYM = false>
 __device__ inline void jacobi0_item(long F, const T* __restrict__ Dinv, const T* r, T* e) {
   acc_t<T> rv[NE];
 #pragma unroll
   for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
-  dinv_update<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
+  if constexpr (DSYM)
+    dinv_update_sym<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
+  else
+    dinv_update<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
 }
 
 

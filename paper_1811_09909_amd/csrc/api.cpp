@@ -144,7 +144,7 @@ void free_build(hdg_problem* P) {
   P->L.clear();
   P->built = false;
   P->V = P->Z = P->H = P->cs = P->sn = P->gsv = P->y = nullptr;
-  P->s.sc = P->s.partials = nullptr;
+  P->s.sc = P->s.partials = P->s.pcg = nullptr;
   P->gm_m = 0;
   P->cap = 1;
 }
@@ -548,22 +548,23 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
                 pd.b = take_event(P);
                 HDG_CHECK(hipEventRecord(pd.a, s2));
               }
+              int npap = 0;
               launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s,
-                                       s2, nr);
+                                       s2, nr, &npap);
               if (timed) {
                 HDG_CHECK(hipEventRecord(pd.b, s2));
                 P->pending.push_back(pd);
               }
               if (mixed)
-                blas_cg_update2<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, P->s, s2, nr);
+                blas_cg_update2_fused<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, npap, P->s, s2, nr);
               else
-                blas_cg_update2<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, P->s, s2, nr);
+                blas_cg_update2_fused<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, npap, P->s, s2, nr);
               precond_fused(P, mixed, nr);
               if (mixed) {
-                blas_rz<float>(P->r, P->z32, N, FIN_BETA_FLEX, P->s, s2, nr);
+                blas_rz_cg<float>(P->r, P->z32, N, true, P->s, s2, nr);
                 blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
               } else {
-                blas_rz<double>(P->r, P->z, N, FIN_BETA, P->s, s2, nr);
+                blas_rz_cg<double>(P->r, P->z, N, false, P->s, s2, nr);
                 blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
               }
             },
@@ -991,6 +992,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
     P->s.partials = dalloc<double>(P, 2 * nb * cap, true);
     P->s.row = 2 * nb;
+    P->s.pcg = dalloc<double>(P, 2L * MAX_RED_BLOCKS * cap, true);
     HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT * cap, P->st));
   }
   if (o.method == HDG_METHOD_GMRES) {

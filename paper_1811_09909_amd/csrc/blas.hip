@@ -100,12 +100,17 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double* __restrict__
 //   lam += alpha p ; r -= alpha Ap ; r32 = (float) r (mixed only)
 //   partial sums of r.r and r.z_old, where z still holds the previous
 //   preconditioned residual.
+// With papp: alpha = rz / pAp is formed in every block from the pAp
+// partials of the apply (npap per right-hand side, summed in the
+// finaliser's order); block 0 also stores pAp and alpha.
 template <typename ZT>
 __global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam, double* __restrict__ r,
                                                         float* __restrict__ r32, const double* __restrict__ p,
                                                         const double* __restrict__ Ap, const ZT* __restrict__ z,
-                                                        long n, double* __restrict__ partials, const double* sc) {
+                                                        long n, double* __restrict__ partials, double* sc,
+                                                        const double* __restrict__ papp, int npap) {
   __shared__ double sh[RB / 64];
+  __shared__ double alpha_sh;
   {
     const long o = blockIdx.y * n;
     lam += o;
@@ -117,7 +122,25 @@ __global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam
     partials += blockIdx.y * 2L * gridDim.x;
     sc += blockIdx.y * (long)SC_COUNT;
   }
-  const double alpha = sc[SC_ALPHA];
+  double alpha;
+  if (papp) {
+    papp += blockIdx.y * (long)npap;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < npap; i += RB) a += papp[i];
+    const double t0 = block_sum(a, sh);
+    if (threadIdx.x == 0) {
+      const double al = t0 != 0.0 ? sc[SC_RZ] / t0 : 0.0;
+      alpha_sh = al;
+      if (blockIdx.x == 0) {
+        sc[SC_PAP] = t0;
+        sc[SC_ALPHA] = al;
+      }
+    }
+    __syncthreads();
+    alpha = alpha_sh;
+  } else {
+    alpha = sc[SC_ALPHA];
+  }
   double rr = 0.0, rz = 0.0;
   for (long base = blockIdx.x * (long)RB * RPT; base < n; base += (long)gridDim.x * RB * RPT) {
 #pragma unroll
@@ -140,6 +163,38 @@ __global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam
     partials[2 * blockIdx.x] = sa;
     partials[2 * blockIdx.x + 1] = sb;
   }
+}
+
+// finaliser of a fused CG iteration: residual norm (and history) and rz_old
+// from the update's partials, then beta from the r.z partials
+__global__ void __launch_bounds__(RB) finalize_cg_kernel(const double* __restrict__ pcg, int ncg,
+                                                         const double* __restrict__ prz, int nrz, int flex,
+                                                         double* sc) {
+  __shared__ double sh[RB / 64];
+  pcg += blockIdx.x * 2L * ncg;
+  prz += blockIdx.x * (long)nrz;
+  sc += blockIdx.x * (long)SC_COUNT;
+  double t[3];
+  for (int v = 0; v < 3; ++v) {
+    double a = 0.0;
+    if (v < 2)
+      for (int i = threadIdx.x; i < ncg; i += RB) a += pcg[2L * i + v];
+    else
+      for (int i = threadIdx.x; i < nrz; i += RB) a += prz[i];
+    t[v] = block_sum(a, sh);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  sc[SC_RNORM2] = t[0];
+  sc[SC_RZOLD] = t[1];
+  const int c = (int)sc[SC_HCNT];
+  if (c >= 0 && c < HIST_MAX) sc[SC_HIST + c] = t[0];
+  sc[SC_HCNT] = (double)(c + 1);
+  if (flex)
+    sc[SC_BETA] = sc[SC_RZ] != 0.0 ? (t[2] - sc[SC_RZOLD]) / sc[SC_RZ] : 0.0;
+  else
+    sc[SC_BETA] = sc[SC_RZ] != 0.0 ? t[2] / sc[SC_RZ] : 0.0;
+  sc[SC_RZ] = t[2];
 }
 
 // partial sums of r.z (z FP64 or FP32)
@@ -292,10 +347,35 @@ void blas_cg_update2(double* lam, double* r, float* r32, const double* p, const 
                      Scratch& s, hipStream_t st, int nrhs) {
   const unsigned nb = rg(n);
   hipLaunchKernelGGL((cg_update2_kernel<ZT>), dim3(nb, nrhs), dim3(RB), 0, st, lam, r, r32, p, Ap, z, n, s.partials,
-                     s.sc);
+                     s.sc, nullptr, 0);
   HDG_CHECK(hipGetLastError());
   blas_finalize((int)nb, 2, FIN_RNORM_RZOLD, nullptr, s, st, nrhs);
 }
+
+template <typename ZT>
+void blas_cg_update2_fused(double* lam, double* r, float* r32, const double* p, const double* Ap, const ZT* z,
+                           long n, int npap, Scratch& s, hipStream_t st, int nrhs) {
+  const unsigned nb = rg(n);
+  hipLaunchKernelGGL((cg_update2_kernel<ZT>), dim3(nb, nrhs), dim3(RB), 0, st, lam, r, r32, p, Ap, z, n, s.pcg, s.sc,
+                     s.partials, npap);
+  HDG_CHECK(hipGetLastError());
+}
+template void blas_cg_update2_fused<double>(double*, double*, float*, const double*, const double*, const double*,
+                                            long, int, Scratch&, hipStream_t, int);
+template void blas_cg_update2_fused<float>(double*, double*, float*, const double*, const double*, const float*,
+                                           long, int, Scratch&, hipStream_t, int);
+
+template <typename ZT>
+void blas_rz_cg(const double* r, const ZT* z, long n, bool flex, Scratch& s, hipStream_t st, int nrhs) {
+  const unsigned nb = rg(n);
+  hipLaunchKernelGGL((rz_kernel<ZT>), dim3(nb, nrhs), dim3(RB), 0, st, r, z, n, s.partials);
+  HDG_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(finalize_cg_kernel, dim3(nrhs), dim3(RB), 0, st, s.pcg, (int)nb, s.partials, (int)nb,
+                     flex ? 1 : 0, s.sc);
+  HDG_CHECK(hipGetLastError());
+}
+template void blas_rz_cg<double>(const double*, const double*, long, bool, Scratch&, hipStream_t, int);
+template void blas_rz_cg<float>(const double*, const float*, long, bool, Scratch&, hipStream_t, int);
 template void blas_cg_update2<double>(double*, double*, float*, const double*, const double*, const double*, long,
                                       Scratch&, hipStream_t, int);
 template void blas_cg_update2<float>(double*, double*, float*, const double*, const double*, const float*, long,

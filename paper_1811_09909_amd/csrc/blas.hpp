@@ -29,6 +29,7 @@ struct Scratch {
   double* sc = nullptr;        // device scalars [nrhs][SC_COUNT]
   double* partials = nullptr;  // [nrhs][2 * max(MAX_RED_BLOCKS, blocks of the widest reducing launch)]
   long row = 0;                // partials per right-hand side
+  double* pcg = nullptr;       // partials of the fused CG update [nrhs][2 * MAX_RED_BLOCKS]
 };
 
 // nrhs: vectors of length n stored one after another; each right-hand side
@@ -41,6 +42,17 @@ void blas_cg_update2(double* lam, double* r, float* r32, const double* p, const 
                      Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
 void blas_rz(const double* r, const ZT* z, long n, int mode, Scratch& s, hipStream_t st, int nrhs = 1);
+// CG iteration with two finalisers instead of four: the update takes alpha
+// from the pAp partials (npap per right-hand side, in s.partials) itself and
+// keeps its own partials in s.pcg; the r.z reduction's finaliser then also
+// does the update's (residual norm and history, rz_old), then beta
+// (Polak-Ribiere when flex).  Same sums in the same order as the separate
+// finalisers.
+template <typename ZT>
+void blas_cg_update2_fused(double* lam, double* r, float* r32, const double* p, const double* Ap, const ZT* z,
+                           long n, int npap, Scratch& s, hipStream_t st, int nrhs = 1);
+template <typename ZT>
+void blas_rz_cg(const double* r, const ZT* z, long n, bool flex, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
 void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>

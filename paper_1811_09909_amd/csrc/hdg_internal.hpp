@@ -229,8 +229,12 @@ void launch_tail(const TailArgs& a, hipStream_t st, int nrhs = 1);
 
 enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5 };
 struct Scratch;
+// Modes with a reduction write per-block partials into red->partials; the
+// one-block finaliser runs next, unless nparts is given: then it receives
+// the number of partials per right-hand side (their row stride) and the
+// caller finalises (e.g. inside the next kernel).
 template <typename T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
-                      Scratch* red, hipStream_t st, int nrhs = 1);
+                      Scratch* red, hipStream_t st, int nrhs = 1, int* nparts = nullptr);
 
 }  // namespace hdg

@@ -759,7 +759,7 @@ void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const 
 
 template <typename T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
-                      Scratch* red, hipStream_t st, int nrhs) {
+                      Scratch* red, hipStream_t st, int nrhs, int* nparts) {
   if (L.nface == 0) return;
   double* partials = red ? red->partials : nullptr;
   const T* Af = nullptr;
@@ -789,7 +789,10 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     }
     if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
       if (nbt > red->row) throw HipError{hipErrorInvalidValue, "strip apply: too many partial sums"};
-      blas_finalize(nbt, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+      if (nparts)
+        *nparts = nbt;
+      else
+        blas_finalize(nbt, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
     }
     return;
   }
@@ -816,8 +819,12 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
 #undef HDG_AK
   });
   HDG_CHECK(hipGetLastError());
-  if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM))
-    blas_finalize((int)g1, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+  if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
+    if (nparts)
+      *nparts = (int)g1;
+    else
+      blas_finalize((int)g1, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+  }
 }
 
 // residual of level L restricted to P1 on the same faces (level C), and when
@@ -981,7 +988,7 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
 #define HDG_INST(T)                                                                                              \
   template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t, int);  \
   template void launch_apply_red<T>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,          \
-                                    Scratch*, hipStream_t, int);                                                  \
+                                    Scratch*, hipStream_t, int, int*);                                            \
   template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t, int);                                  \
   template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t, int);            \
   template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t, int);                      \

@@ -29,30 +29,109 @@ struct Dims {
   static constexpr int SA = (2 * NV * NV > NV * NL) ? 2 * NV * NV : NV * NL;
 };
 
-// In-place Gauss-Jordan inverse of an SPD n x n matrix in LDS (no pivoting),
-// cooperative over the workgroup.
-template <int N>
-__device__ void gj_inverse_lds(double* A) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double piv_s;
-  for (int k = 0; k < N; ++k) {
-    __syncthreads();
-    if (tid == 0) piv_s = 1.0 / A[k * N + k];
-    __syncthreads();
-    const double p = piv_s;
-    for (int j = tid; j < N; j += nt)
-      if (j != k) A[k * N + j] *= p;
-    __syncthreads();
-    for (int idx = tid; idx < N * N; idx += nt) {
-      int i = idx / N, j = idx % N;
-      if (i != k && j != k) A[idx] -= A[i * N + k] * A[k * N + j];
-    }
-    __syncthreads();
-    for (int i = tid; i < N; i += nt)
-      if (i != k) A[i * N + k] = -A[i * N + k] * p;
-    if (tid == 0) A[k * N + k] = p;
-  }
+// In-place Gauss-Jordan inverse of an SPD N x N matrix in LDS (no
+// pivoting) with the matrix held in registers: lane (ti, tj) of a G x G lane
+// grid (G * G = NT) owns the BS x BS block at rows ti * BS, columns tj * BS
+// (BS = ceil(N / G); entries past N act as identity).  Each step publishes
+// the pivot row and column through LDS, double-buffered, so one barrier per
+// step suffices; every lane then updates its own block.
+template <int N, int NT>
+__device__ void gj_inverse_reg(double* A) {
+  static_assert(NT == 64 || NT == 256, "lane grid of 8 x 8 or 16 x 16");
+  constexpr int G = NT == 64 ? 8 : 16;
+  constexpr int BS = (N + G - 1) / G;
+  __shared__ double rowb[2][G * BS], colb[2][G * BS];
+  const int tid = threadIdx.x, ti = tid / G, tj = tid % G;
+  double a[BS][BS];
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < BS; ++r)
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int i = ti * BS + r, j = tj * BS + c;
+      a[r][c] = (i < N && j < N) ? A[i * N + j] : (i == j ? 1.0 : 0.0);
+    }
+  for (int k = 0; k < N; ++k) {
+    const int buf = k & 1, kb = k / BS, kr = k % BS;
+    if (ti == kb)
+#pragma unroll
+      for (int c = 0; c < BS; ++c)
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+          if (r == kr) rowb[buf][tj * BS + c] = a[r][c];
+    if (tj == kb)
+#pragma unroll
+      for (int r = 0; r < BS; ++r)
+#pragma unroll
+        for (int c = 0; c < BS; ++c)
+          if (c == kr) colb[buf][ti * BS + r] = a[r][c];
+    __syncthreads();
+    const double p = 1.0 / rowb[buf][k];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+      const int i = ti * BS + r;
+      const double ci = colb[buf][i];
+#pragma unroll
+      for (int c = 0; c < BS; ++c) {
+        const int j = tj * BS + c;
+        const double rj = rowb[buf][j] * p;
+        if (i == k)
+          a[r][c] = j == k ? p : rj;
+        else if (j == k)
+          a[r][c] = -ci * p;
+        else
+          a[r][c] -= ci * rj;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < BS; ++r)
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+      const int i = ti * BS + r, j = tj * BS + c;
+      if (i < N && j < N) A[i * N + j] = a[r][c];
+    }
+  __syncthreads();
+}
+
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+// lanes per element of the 2D element kernel
+#ifndef HDG_ELEM_NT2
+#define HDG_ELEM_NT2 256
+#endif
+
+// Dense product on the matrix cores, shared by the workgroup's wavefronts:
+// for every (i, j) of an M x N output, s = sum_k a(i, k) b(k, j), and
+// c(i, j, s) is called once, by the lane that holds the entry.  Output tiles
+// of 16 x 16 go to the wavefronts round-robin; each is accumulated by
+// v_mfma_f64_16x16x4f64 over K in steps of 4 (indices past M, N or K read
+// as 0).  Lane l supplies a(i0 + l % 16, k0 + l / 16) and
+// b(k0 + l / 16, j0 + l % 16) and receives rows i0 + l / 16 + 4 r (r = 0..3)
+// of column j0 + l % 16.  The tile loop is uniform over a wavefront, so every
+// lane issues every MFMA.
+template <int M, int N, int K, int NT, typename FA, typename FB, typename FC>
+__device__ inline void wg_mfma(FA a, FB b, FC c) {
+  constexpr int TM = (M + 15) / 16, TN = (N + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  for (int t = wave; t < TM * TN; t += NT / 64) {
+    const int i0 = (t / TN) * 16, j0 = (t % TN) * 16;
+    const int ia = i0 + l16, jb = j0 + l16;
+    mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + l4;
+      const double av = (ia < M && k < K) ? a(ia, k) : 0.0;
+      const double bv = (jb < N && k < K) ? b(k, jb) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + l4 + 4 * r;
+      if (i < M && jb < N) c(i, jb, acc[r]);
+    }
+  }
 }
 
 // In 2D the Schur-complement route is followed by one step of iterative
@@ -66,6 +145,11 @@ __device__ void gj_inverse_lds(double* A) {
 // refined X is backward stable and A^e comes out to a few eps like a pivoted
 // LU of L.  (3D elements keep the plain route: their LDS budget is spent, and
 // the smooth 3D coefficient keeps kappa / (tau h) small.)
+//
+// Every dense product runs on the matrix cores (wg_mfma); the two
+// Gauss-Jordan inverses stay on the vector units.  Mk^-1 and K^-1 are
+// symmetric, so their rows are read as columns (consecutive lanes then read
+// consecutive LDS words).
 template <int D, int K, int NT>
 __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau, const double* __restrict__ Phi,
                                                          const double* __restrict__ Wq,
@@ -79,6 +163,7 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
                                                          double* __restrict__ Minv_out) {
   using Dm = Dims<D, K>;
   constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL, NQ = Dm::NQ;
+  constexpr int N2 = 2 * NE;
   constexpr bool REF = (D == 2);
   constexpr int NX = REF ? (D + 1) * NV * NL : 1;
   __shared__ double sA[Dm::SA];      // Mk^-1 | Y   (plain route, later: W)
@@ -97,204 +182,164 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
   for (int q = tid; q < NQ; q += NT) sW[q] = Wq[q] / kqp[T * NQ + q];
   __syncthreads();
   // Mk = Phi^T diag(w/kappa) Phi
-  for (int idx = tid; idx < NV * NV; idx += NT) {
-    int i = idx / NV, j = idx % NV;
-    double s = 0.0;
-    for (int q = 0; q < NQ; ++q) s += Phi[q * NV + i] * Phi[q * NV + j] * sW[q];
-    sM[idx] = s;
-  }
+  wg_mfma<NV, NV, NQ, NT>([&](int i, int q) { return Phi[q * NV + i] * sW[q]; },
+                          [&](int q, int j) { return Phi[q * NV + j]; },
+                          [&](int i, int j, double v) { sM[i * NV + j] = v; });
   // K = tau E, Z = tau G, A^e = tau H
   for (int idx = tid; idx < NV * NV; idx += NT) sK[idx] = tau * Em[idx];
   for (int idx = tid; idx < NV * NL; idx += NT) sZ[idx] = tau * Gm[idx];
   if (!REF)
     for (int idx = tid; idx < NL * NL; idx += NT) Ae[idx] = tau * Hm[idx];
-  gj_inverse_lds<NV>(sM);
+  gj_inverse_reg<NV, NT>(sM);
   if (Minv_out)
     for (int idx = tid; idx < NV * NV; idx += NT) Minv_out[T * NV * NV + idx] = sM[idx];
 
   for (int c = 0; c < D; ++c) {
     const double* Bc = Bm + (long)c * NV * NV;
     const double* Fc = Fm + (long)c * NV * NL;
+    const int col0 = 2 * c * NE;
     // Y = Mk^-1 B_c^T ; K += B_c Y
     __syncthreads();
-    for (int idx = tid; idx < NV * NV; idx += NT) {
-      int i = idx / NV, j = idx % NV;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * Bc[j * NV + l];
-      sY[idx] = s;
-    }
+    wg_mfma<NV, NV, NV, NT>([&](int i, int l) { return sM[l * NV + i]; },
+                            [&](int l, int j) { return Bc[j * NV + l]; },
+                            [&](int i, int j, double v) { sY[i * NV + j] = v; });
     __syncthreads();
-    for (int idx = tid; idx < NV * NV; idx += NT) {
-      int i = idx / NV, j = idx % NV;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += Bc[i * NV + l] * sY[l * NV + j];
-      sK[idx] += s;
-    }
+    wg_mfma<NV, NV, NV, NT>([&](int i, int l) { return Bc[i * NV + l]; },
+                            [&](int l, int j) { return sY[l * NV + j]; },
+                            [&](int i, int j, double v) { sK[i * NV + j] += v; });
     __syncthreads();
     // Y(:, 0:2NE) = Mk^-1 F_c(:, slots of normal c)
-    const int col0 = 2 * c * NE;
-    for (int idx = tid; idx < NV * 2 * NE; idx += NT) {
-      int i = idx / (2 * NE), j = idx % (2 * NE);
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * Fc[l * NL + col0 + j];
-      sY[i * 2 * NE + j] = s;
-    }
+    wg_mfma<NV, N2, NV, NT>([&](int i, int l) { return sM[l * NV + i]; },
+                            [&](int l, int j) { return Fc[l * NL + col0 + j]; },
+                            [&](int i, int j, double v) { sY[i * N2 + j] = v; });
     __syncthreads();
     // Z(:, slots c) += B_c Y ; A^e(slots c, slots c) += F_c^T Y
-    for (int idx = tid; idx < NV * 2 * NE; idx += NT) {
-      int i = idx / (2 * NE), j = idx % (2 * NE);
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += Bc[i * NV + l] * sY[l * 2 * NE + j];
-      sZ[i * NL + col0 + j] += s;
-    }
-    if (!REF) {
-      // same entry-to-thread map as every other pass over A^e: no thread
-      // reads an entry another thread wrote
-      for (int idx = tid; idx < NL * NL; idx += NT) {
-        const int i = idx / NL - col0, j = idx % NL - col0;
-        if (i < 0 || i >= 2 * NE || j < 0 || j >= 2 * NE) continue;
-        double s = 0.0;
-        for (int l = 0; l < NV; ++l) s += Fc[l * NL + col0 + i] * sY[l * 2 * NE + j];
-        Ae[idx] += s;
-      }
-    }
+    wg_mfma<NV, N2, NV, NT>([&](int i, int l) { return Bc[i * NV + l]; },
+                            [&](int l, int j) { return sY[l * N2 + j]; },
+                            [&](int i, int j, double v) { sZ[i * NL + col0 + j] += v; });
+    if (!REF)
+      wg_mfma<N2, N2, NV, NT>([&](int i, int l) { return Fc[l * NL + col0 + i]; },
+                              [&](int l, int j) { return sY[l * N2 + j]; },
+                              [&](int i, int j, double v) { Ae[(col0 + i) * NL + col0 + j] += v; });
   }
   __syncthreads();
-  gj_inverse_lds<NV>(sK);
+  gj_inverse_reg<NV, NT>(sK);
   if (Kinv_out)
     for (int idx = tid; idx < NV * NV; idx += NT) Kinv_out[T * NV * NV + idx] = sK[idx];
   if constexpr (!REF) {
     // W = K^-1 Z (into sA) ; A^e -= Z^T W
     double* sWm = sA;
-    for (int idx = tid; idx < NV * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
-      sWm[idx] = s;
-    }
+    wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sK[l * NV + i]; },
+                            [&](int l, int j) { return sZ[l * NL + j]; },
+                            [&](int i, int j, double v) { sWm[i * NL + j] = v; });
     __syncthreads();
-    for (int idx = tid; idx < NL * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sZ[l * NL + i] * sWm[l * NL + j];
-      Ae[idx] -= s;
-    }
+    wg_mfma<NL, NL, NV, NT>([&](int i, int l) { return sZ[l * NL + i]; },
+                            [&](int l, int j) { return sWm[l * NL + j]; },
+                            [&](int i, int j, double v) { Ae[i * NL + j] -= v; });
     for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sWm[idx];
   } else {
     double* sU = sX + D * NV * NL;
     double* rU = sR + D * NV * NL;
     // U = K^-1 Z
-    for (int idx = tid; idx < NV * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
-      sU[idx] = s;
-    }
+    wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sK[l * NV + i]; },
+                            [&](int l, int j) { return sZ[l * NL + j]; },
+                            [&](int i, int j, double v) { sU[i * NL + j] = v; });
     __syncthreads();
-    // Q_c = Mk^-1 (B_c^T U - F_c) ; Mk itself again (into Y) for the residual
+    // Q_c = Mk^-1 (B_c^T U - F_c)
     for (int c = 0; c < D; ++c) {
       const double* Bc = Bm + (long)c * NV * NV;
       const double* Fc = Fm + (long)c * NV * NL;
-      for (int idx = tid; idx < NV * NL; idx += NT) {
-        int i = idx / NL, j = idx % NL;
-        double s = -Fc[i * NL + j];
-        for (int l = 0; l < NV; ++l) s += Bc[l * NV + i] * sU[l * NL + j];
-        sZ[idx] = s;
-      }
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return Bc[l * NV + i]; },
+                              [&](int l, int j) { return sU[l * NL + j]; },
+                              [&](int i, int j, double v) { sZ[i * NL + j] = v - Fc[i * NL + j]; });
       __syncthreads();
-      for (int idx = tid; idx < NV * NL; idx += NT) {
-        int i = idx / NL, j = idx % NL;
-        double s = 0.0;
-        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * sZ[l * NL + j];
-        sX[c * NV * NL + idx] = s;
-      }
+      double* Qc = sX + c * NV * NL;
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sM[l * NV + i]; },
+                              [&](int l, int j) { return sZ[l * NL + j]; },
+                              [&](int i, int j, double v) { Qc[i * NL + j] = v; });
       __syncthreads();
     }
-    for (int idx = tid; idx < NV * NV; idx += NT) {
-      int i = idx / NV, j = idx % NV;
-      double s = 0.0;
-      for (int q = 0; q < NQ; ++q) s += Phi[q * NV + i] * Phi[q * NV + j] * sW[q];
-      sY[idx] = s;
-    }
+    // Mk itself again (into Y) for the residual
+    wg_mfma<NV, NV, NQ, NT>([&](int i, int q) { return Phi[q * NV + i] * sW[q]; },
+                            [&](int q, int j) { return Phi[q * NV + j]; },
+                            [&](int i, int j, double v) { sY[i * NV + j] = v; });
     __syncthreads();
     // residual of the local system for R = [-F; tau G]:
     //   r_c = -F_c - Mk Q_c + B_c^T U,   r_u = tau G - sum_c B_c Q_c - tau E U
-    for (int idx = tid; idx < NV * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double su = tau * Gm[i * NL + j];
-      for (int l = 0; l < NV; ++l) su -= tau * Em[i * NV + l] * sU[l * NL + j];
-      for (int c = 0; c < D; ++c) {
-        const double* Bc = Bm + (long)c * NV * NV;
-        const double* Fc = Fm + (long)c * NV * NL;
-        const double* Qc = sX + c * NV * NL;
-        double sq = -Fc[i * NL + j];
-        for (int l = 0; l < NV; ++l) sq += Bc[l * NV + i] * sU[l * NL + j] - sY[i * NV + l] * Qc[l * NL + j];
-        sR[c * NV * NL + idx] = sq;
-        for (int l = 0; l < NV; ++l) su -= Bc[i * NV + l] * Qc[l * NL + j];
-      }
-      rU[idx] = su;
+    // (each entry is accumulated by one lane, which reads back only its own
+    // writes between the products)
+    for (int c = 0; c < D; ++c) {
+      const double* Bc = Bm + (long)c * NV * NV;
+      const double* Fc = Fm + (long)c * NV * NL;
+      const double* Qc = sX + c * NV * NL;
+      double* rc = sR + c * NV * NL;
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return Bc[l * NV + i]; },
+                              [&](int l, int j) { return sU[l * NL + j]; },
+                              [&](int i, int j, double v) { rc[i * NL + j] = v - Fc[i * NL + j]; });
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sY[l * NV + i]; },
+                              [&](int l, int j) { return Qc[l * NL + j]; },
+                              [&](int i, int j, double v) { rc[i * NL + j] -= v; });
+    }
+    wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return tau * Em[i * NV + l]; },
+                            [&](int l, int j) { return sU[l * NL + j]; },
+                            [&](int i, int j, double v) { rU[i * NL + j] = tau * Gm[i * NL + j] - v; });
+    for (int c = 0; c < D; ++c) {
+      const double* Bc = Bm + (long)c * NV * NV;
+      const double* Qc = sX + c * NV * NL;
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return Bc[i * NV + l]; },
+                              [&](int l, int j) { return Qc[l * NL + j]; },
+                              [&](int i, int j, double v) { rU[i * NL + j] -= v; });
     }
     __syncthreads();
     // correction by the same route: y_c = Mk^-1 r_c (in place via Z),
     // dU = K^-1 (r_u - sum_c B_c y_c), dQ_c = y_c + Mk^-1 B_c^T dU
     for (int c = 0; c < D; ++c) {
       double* rc = sR + c * NV * NL;
-      for (int idx = tid; idx < NV * NL; idx += NT) {
-        int i = idx / NL, j = idx % NL;
-        double s = 0.0;
-        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * rc[l * NL + j];
-        sZ[idx] = s;
-      }
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sM[l * NV + i]; },
+                              [&](int l, int j) { return rc[l * NL + j]; },
+                              [&](int i, int j, double v) { sZ[i * NL + j] = v; });
       __syncthreads();
       for (int idx = tid; idx < NV * NL; idx += NT) rc[idx] = sZ[idx];
       __syncthreads();
     }
-    for (int idx = tid; idx < NV * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = rU[idx];
-      for (int c = 0; c < D; ++c) {
-        const double* Bc = Bm + (long)c * NV * NV;
-        for (int l = 0; l < NV; ++l) s -= Bc[i * NV + l] * sR[c * NV * NL + l * NL + j];
-      }
-      sZ[idx] = s;
+    for (int c = 0; c < D; ++c) {
+      const double* Bc = Bm + (long)c * NV * NV;
+      const double* yc = sR + c * NV * NL;
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return Bc[i * NV + l]; },
+                              [&](int l, int j) { return yc[l * NL + j]; },
+                              [&](int i, int j, double v) { sZ[i * NL + j] = (c == 0 ? rU[i * NL + j] : sZ[i * NL + j]) - v; });
     }
     __syncthreads();
-    for (int idx = tid; idx < NV * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = 0.0;
-      for (int l = 0; l < NV; ++l) s += sK[i * NV + l] * sZ[l * NL + j];
-      rU[idx] = s;  // dU
-    }
+    wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sK[l * NV + i]; },
+                            [&](int l, int j) { return sZ[l * NL + j]; },
+                            [&](int i, int j, double v) { rU[i * NL + j] = v; });  // dU
     __syncthreads();
     for (int c = 0; c < D; ++c) {
       const double* Bc = Bm + (long)c * NV * NV;
       // t = B_c^T dU (into Z), then Q_c += y_c + Mk^-1 t
-      for (int idx = tid; idx < NV * NL; idx += NT) {
-        int i = idx / NL, j = idx % NL;
-        double s = 0.0;
-        for (int l = 0; l < NV; ++l) s += Bc[l * NV + i] * rU[l * NL + j];
-        sZ[idx] = s;
-      }
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return Bc[l * NV + i]; },
+                              [&](int l, int j) { return rU[l * NL + j]; },
+                              [&](int i, int j, double v) { sZ[i * NL + j] = v; });
       __syncthreads();
-      for (int idx = tid; idx < NV * NL; idx += NT) {
-        int i = idx / NL, j = idx % NL;
-        double s = sR[c * NV * NL + idx];
-        for (int l = 0; l < NV; ++l) s += sM[i * NV + l] * sZ[l * NL + j];
-        sX[c * NV * NL + idx] += s;
-      }
+      double* Qc = sX + c * NV * NL;
+      const double* yc = sR + c * NV * NL;
+      wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sM[l * NV + i]; },
+                              [&](int l, int j) { return sZ[l * NL + j]; },
+                              [&](int i, int j, double v) { Qc[i * NL + j] += yc[i * NL + j] + v; });
       __syncthreads();
     }
     for (int idx = tid; idx < NV * NL; idx += NT) sU[idx] += rU[idx];
     __syncthreads();
-    // A^e = tau H - sum_c F_c^T Q_c - tau G^T U
-    for (int idx = tid; idx < NL * NL; idx += NT) {
-      int i = idx / NL, j = idx % NL;
-      double s = tau * Hm[idx];
-      for (int l = 0; l < NV; ++l) {
-        s -= tau * Gm[l * NL + i] * sU[l * NL + j];
-        for (int c = 0; c < D; ++c) s -= Fm[((long)c * NV + l) * NL + i] * sX[c * NV * NL + l * NL + j];
-      }
-      Ae[idx] = s;
+    // A^e = tau H - tau G^T U - sum_c F_c^T Q_c
+    wg_mfma<NL, NL, NV, NT>([&](int i, int l) { return tau * Gm[l * NL + i]; },
+                            [&](int l, int j) { return sU[l * NL + j]; },
+                            [&](int i, int j, double v) { Ae[i * NL + j] = tau * Hm[i * NL + j] - v; });
+    for (int c = 0; c < D; ++c) {
+      const double* Fc = Fm + (long)c * NV * NL;
+      const double* Qc = sX + c * NV * NL;
+      wg_mfma<NL, NL, NV, NT>([&](int i, int l) { return Fc[l * NL + i]; },
+                              [&](int l, int j) { return Qc[l * NL + j]; },
+                              [&](int i, int j, double v) { Ae[i * NL + j] -= v; });
     }
     for (int idx = tid; idx < NV * NL; idx += NT) Wout[T * NV * NL + idx] = sU[idx];
   }
@@ -632,7 +677,7 @@ void launch_element_dtn(int d, int k, long nelem, double tau, const RefDevice& r
                         double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
-    constexpr int NT = D == 2 ? 64 : 256;
+    constexpr int NT = D == 2 ? HDG_ELEM_NT2 : 256;
     hipLaunchKernelGGL((element_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau,
                        rd.Phi, rd.Wq, rd.B, rd.F, rd.G, rd.E, rd.H, kqp, Aelem, W, Kinv, Minv);
   });

@@ -132,11 +132,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
 
 // e = Dinv r (first sweep from e = 0)
 template <int NE, typename T, bool DSYM>
-__global__ void jacobi0_kernel(long nface, const T* __restrict__ Dinv, const T* __restrict__ r, T* __restrict__ e) {
-  const long F = blockIdx.x * 256L + threadIdx.x;
-  if (F >= nface) return;
-  r += blockIdx.y * nface * NE;
-  e += blockIdx.y * nface * NE;
+__global__ void jacobi0_kernel(long nface, int nrhs, const T* __restrict__ Dinv, const T* __restrict__ r,
+                               T* __restrict__ e) {
+  int rhs;
+  const long b = xcd_block_rhs((nface + 255) / 256, nrhs, blockIdx.x, &rhs);
+  const long F = b * 256 + threadIdx.x;
+  if (b < 0 || F >= nface) return;
+  r += rhs * nface * NE;
+  e += rhs * nface * NE;
   jacobi0_item<NE, T, DSYM>(F, Dinv, r, e);
 }
 
@@ -527,63 +530,77 @@ __global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) hpre_kernel(int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
-                                                   const T* __restrict__ P, const T* __restrict__ r,
-                                                   T* __restrict__ e, int do_corr, T* __restrict__ cb) {
+__global__ void __launch_bounds__(256) hpre_kernel(int n, int nrhs, const T* __restrict__ Af,
+                                                   const T* __restrict__ AIIinv, const T* __restrict__ P,
+                                                   const T* __restrict__ r, T* __restrict__ e, int do_corr,
+                                                   T* __restrict__ cb) {
   const long nmacro = (long)(n / 2) * (n / 2);
-  const long M = blockIdx.x * 256L + threadIdx.x;
-  r += blockIdx.y * trace_len<2>(n, 2);
-  e += blockIdx.y * trace_len<2>(n, 2);
-  cb += blockIdx.y * nmacro * 8;
+  int rhs;
+  const long b = xcd_block_rhs((nmacro + 255) / 256, nrhs, blockIdx.x, &rhs);
+  const long M = b * 256 + threadIdx.x;
+  if (b < 0) return;
+  r += rhs * trace_len<2>(n, 2);
+  e += rhs * trace_len<2>(n, 2);
+  cb += rhs * nmacro * 8;
   if (M < nmacro) hpre_item<2, T>(M, n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
 // 4 lanes per macro-element (small levels)
 template <typename T>
-__global__ void __launch_bounds__(256) hpre4_kernel(int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
-                                                    const T* __restrict__ P, const T* __restrict__ r,
-                                                    T* __restrict__ e, int do_corr, T* __restrict__ cb) {
+__global__ void __launch_bounds__(256) hpre4_kernel(int n, int nrhs, const T* __restrict__ Af,
+                                                    const T* __restrict__ AIIinv, const T* __restrict__ P,
+                                                    const T* __restrict__ r, T* __restrict__ e, int do_corr,
+                                                    T* __restrict__ cb) {
   const long nmacro = (long)(n / 2) * (n / 2);
-  const long t = blockIdx.x * 256L + threadIdx.x;
+  int rhs;
+  const long b = xcd_block_rhs((4 * nmacro + 255) / 256, nrhs, blockIdx.x, &rhs);
+  const long t = b * 256 + threadIdx.x;
   const long M = t >> 2;
-  r += blockIdx.y * trace_len<2>(n, 2);
-  e += blockIdx.y * trace_len<2>(n, 2);
-  cb += blockIdx.y * nmacro * 8;
+  if (b < 0) return;
+  r += rhs * trace_len<2>(n, 2);
+  e += rhs * trace_len<2>(n, 2);
+  cb += rhs * nmacro * 8;
   if (M < nmacro) hpre4_item<T>(M, (int)(t & 3), n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
 template <int D, typename T>
-__global__ void hsum_kernel(int n, const T* __restrict__ r, const T* __restrict__ cb, const T* __restrict__ Dc,
-                            T* __restrict__ rc, T* __restrict__ ec) {
+__global__ void hsum_kernel(int n, int nrhs, const T* __restrict__ r, const T* __restrict__ cb,
+                            const T* __restrict__ Dc, T* __restrict__ rc, T* __restrict__ ec) {
   constexpr int NC = 1 << (D - 1);
   const long ncf = D * nface_dir<D>(n / 2);
-  const long Fc = blockIdx.x * 256L + threadIdx.x;
+  int rhs;
+  const long b = xcd_block_rhs((ncf + 255) / 256, nrhs, blockIdx.x, &rhs);
+  const long Fc = b * 256 + threadIdx.x;
+  if (b < 0) return;
   long nmacro = 1;
   for (int a = 0; a < D; ++a) nmacro *= n / 2;
-  r += blockIdx.y * trace_len<D>(n, NC);
-  cb += blockIdx.y * nmacro * 2 * D * NC;
-  rc = off(rc, blockIdx.y * ncf * NC);
-  ec = off(ec, blockIdx.y * ncf * NC);
+  r += rhs * trace_len<D>(n, NC);
+  cb += rhs * nmacro * 2 * D * NC;
+  rc = off(rc, rhs * ncf * NC);
+  ec = off(ec, rhs * ncf * NC);
   if (Fc < ncf) hsum_item<D, T>(Fc, n, r, cb, Dc, rc, ec);
 }
 
 // LPM lanes per macro-element in the macro part (1, or 4 on small 2D levels)
 template <int D, typename T, int LPM>
-__global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __restrict__ Af,
+__global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, long nbf, int nrhs, const T* __restrict__ Af,
                                                     const T* __restrict__ AIIinv, const T* __restrict__ P,
                                                     const T* __restrict__ r, const T* __restrict__ ec,
                                                     const T* __restrict__ eold, T* __restrict__ enew, int do_corr) {
+  int rhs;
+  const long b = xcd_block_rhs(nbm + nbf, nrhs, blockIdx.x, &rhs);
+  if (b < 0) return;
   {
     constexpr int NC = 1 << (D - 1);
     const long sF = trace_len<D>(n, NC);
-    r += blockIdx.y * sF;
-    eold += blockIdx.y * sF;
-    enew += blockIdx.y * sF;
-    ec += blockIdx.y * trace_len<D>(n / 2, NC);
+    r += rhs * sF;
+    eold += rhs * sF;
+    enew += rhs * sF;
+    ec += rhs * trace_len<D>(n / 2, NC);
   }
-  if (blockIdx.x < nbm) {
+  if (b < nbm) {
     const long nmacro = (long)(n / 2) * (n / 2);
-    const long t = blockIdx.x * 256L + threadIdx.x;
+    const long t = b * 256 + threadIdx.x;
     if constexpr (LPM == 4) {
       if ((t >> 2) < nmacro) hpost4_m_item<T>(t >> 2, (int)(t & 3), n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
     } else {
@@ -591,7 +608,7 @@ __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, const T* __
     }
   } else {
     const long ncf = D * nface_dir<D>(n / 2);
-    const long Fc = (blockIdx.x - nbm) * 256L + threadIdx.x;
+    const long Fc = (b - nbm) * 256 + threadIdx.x;
     if (Fc < ncf) hpost_f_item<D, T>(Fc, n, ec, eold, enew);
   }
 }
@@ -669,7 +686,12 @@ inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 #ifndef HDG_MULTI_LANE_MAX
 #define HDG_MULTI_LANE_MAX 16384
 #endif
-constexpr long MULTI_LANE_MAX = HDG_MULTI_LANE_MAX;
+constexpr long MULTI_LANE_MAX = HDG_MULTI_LANE_MAX;  // macro-elements times right-hand sides
+
+// grid of xcd_block_rhs for nb blocks per right-hand side
+inline unsigned xcd_rhs_grid(long nb, int nrhs) {
+  return nrhs == 1 ? (unsigned)nb : (unsigned)(8 * ((nb + 7) / 8) * nrhs);
+}
 
 // grid of the XCD-aware face launches (see xcd_face): 8 chunks of C blocks
 // per normal direction
@@ -860,12 +882,11 @@ void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) 
   const T* Dv = sizeof(T) == 8 ? (const T*)L.Dinv64 : (const T*)L.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int NE = decltype(NE_)::value;
+    const dim3 g(xcd_rhs_grid(nblk(L.nface), nrhs));
     if (L.packed)
-      hipLaunchKernelGGL((jacobi0_kernel<NE, T, true>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r,
-                         e);
+      hipLaunchKernelGGL((jacobi0_kernel<NE, T, true>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
     else
-      hipLaunchKernelGGL((jacobi0_kernel<NE, T, false>), dim3(nblk(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv, r,
-                         e);
+      hipLaunchKernelGGL((jacobi0_kernel<NE, T, false>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
   });
   HDG_CHECK(hipGetLastError());
 }
@@ -939,12 +960,12 @@ void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  if (L.nmacro <= MULTI_LANE_MAX)
-    hipLaunchKernelGGL((hpre4_kernel<T>), dim3(nblk(4 * L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e,
-                       do_corr, cb);
+  if (L.nmacro * nrhs <= MULTI_LANE_MAX)
+    hipLaunchKernelGGL((hpre4_kernel<T>), dim3(xcd_rhs_grid(nblk(4 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,
+                       Af, Ai, P, r, e, do_corr, cb);
   else
-    hipLaunchKernelGGL((hpre_kernel<T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Af, Ai, P, r, e, do_corr,
-                       cb);
+    hipLaunchKernelGGL((hpre_kernel<T>), dim3(xcd_rhs_grid(nblk(L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs, Af,
+                       Ai, P, r, e, do_corr, cb);
   HDG_CHECK(hipGetLastError());
 }
 
@@ -955,13 +976,14 @@ void launch_hsum(const Level& L, const Level& C, const T* r, const T* cb, T* rc,
     hipLaunchKernelGGL((hsum_solve_kernel<2, T>), dim3(1, nrhs), dim3(64), 0, st, L.n, (int)C.nlam, r, cb, Ai, ec);
   } else if (C.kind == 2) {
     // restricted residual into C.r, then the dense coarsest solve
-    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, r, cb,
-                       (const T*)nullptr, (T*)C.r[sizeof(T) == 8 ? 0 : 1], (T*)nullptr);
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(xcd_rhs_grid(nblk(C.nface), nrhs)), dim3(256), 0, st, L.n, nrhs, r,
+                       cb, (const T*)nullptr, (T*)C.r[sizeof(T) == 8 ? 0 : 1], (T*)nullptr);
     HDG_CHECK(hipGetLastError());
     launch_coarse_solve<T>(C, (const T*)C.r[sizeof(T) == 8 ? 0 : 1], ec, st, nrhs);
   } else {
     const T* Dc = ec ? (sizeof(T) == 8 ? (const T*)C.Dinv64 : (const T*)C.Dinv32) : nullptr;
-    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, r, cb, Dc, rc, ec);
+    hipLaunchKernelGGL((hsum_kernel<2, T>), dim3(xcd_rhs_grid(nblk(C.nface), nrhs)), dim3(256), 0, st, L.n, nrhs, r,
+                       cb, Dc, rc, ec);
   }
   HDG_CHECK(hipGetLastError());
 }
@@ -973,14 +995,14 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   const long nbf = nblk(C.nface);
-  if (L.nmacro <= MULTI_LANE_MAX) {
+  if (L.nmacro * nrhs <= MULTI_LANE_MAX) {
     const long nbm = nblk(4 * L.nmacro);
-    hipLaunchKernelGGL((hpost_kernel<2, T, 4>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai,
-                       P, r, ec, eold, enew, do_corr);
+    hipLaunchKernelGGL((hpost_kernel<2, T, 4>), dim3(xcd_rhs_grid(nbm + nbf, nrhs)), dim3(256), 0, st, L.n, nbm, nbf,
+                       nrhs, Af, Ai, P, r, ec, eold, enew, do_corr);
   } else {
     const long nbm = nblk(L.nmacro);
-    hipLaunchKernelGGL((hpost_kernel<2, T, 1>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, Af, Ai,
-                       P, r, ec, eold, enew, do_corr);
+    hipLaunchKernelGGL((hpost_kernel<2, T, 1>), dim3(xcd_rhs_grid(nbm + nbf, nrhs)), dim3(256), 0, st, L.n, nbm, nbf,
+                       nrhs, Af, Ai, P, r, ec, eold, enew, do_corr);
   }
   HDG_CHECK(hipGetLastError());
 }

@@ -794,6 +794,27 @@ __device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T*
   return c;
 }
 
+// Blocks of 256 items for several right-hand sides on the XCDs: workgroup p
+// of a grid of xcd_rhs_grid(nb, nrhs) takes block b of right-hand side rhs.
+// XCD p % 8 holds the contiguous blocks [j C, (j + 1) C) of every right-hand
+// side, and the right-hand side runs fastest after the XCD, so the
+// workgroups that read one block's operator data run on one XCD back to back
+// and share it through its L2.  Returns -1 for padding workgroups.  With one
+// right-hand side the grid is the nb blocks in plain order (measured faster
+// there).
+__device__ inline long xcd_block_rhs(long nb, int nrhs, unsigned p, int* rhs) {
+  if (nrhs == 1) {
+    *rhs = 0;
+    return (long)p < nb ? (long)p : -1;
+  }
+  const unsigned C = (unsigned)((nb + 7) / 8);
+  const unsigned j = p & 7u, m = p >> 3;
+  *rhs = (int)(m % (unsigned)nrhs);
+  const unsigned w = m / (unsigned)nrhs;
+  const long b = (long)j * C + w;
+  return (w < C && b < nb) ? b : -1;
+}
+
 // Element-major XCD-aware blocks (same idea as xcd_face over the n^D
 // elements, in bands of whole grid rows): element of lane tid of workgroup p
 // and its right-hand side, or -1 for padding lanes.  Grid 8 * C * nrhs.

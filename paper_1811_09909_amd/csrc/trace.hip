@@ -545,22 +545,22 @@ __global__ void __launch_bounds__(256) hpre_kernel(int n, int nrhs, const T* __r
   if (M < nmacro) hpre_item<2, T>(M, n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
-// 4 lanes per macro-element (small levels)
-template <typename T>
-__global__ void __launch_bounds__(256) hpre4_kernel(int n, int nrhs, const T* __restrict__ Af,
+// L = 2 or 4 lanes per macro-element (latency-bound levels)
+template <typename T, int L>
+__global__ void __launch_bounds__(256) hpreL_kernel(int n, int nrhs, const T* __restrict__ Af,
                                                     const T* __restrict__ AIIinv, const T* __restrict__ P,
                                                     const T* __restrict__ r, T* __restrict__ e, int do_corr,
                                                     T* __restrict__ cb) {
   const long nmacro = (long)(n / 2) * (n / 2);
   int rhs;
-  const long b = xcd_block_rhs((4 * nmacro + 255) / 256, nrhs, blockIdx.x, &rhs);
+  const long b = xcd_block_rhs((L * nmacro + 255) / 256, nrhs, blockIdx.x, &rhs);
   const long t = b * 256 + threadIdx.x;
-  const long M = t >> 2;
+  const long M = t / L;
   if (b < 0) return;
   r += rhs * trace_len<2>(n, 2);
   e += rhs * trace_len<2>(n, 2);
   cb += rhs * nmacro * 8;
-  if (M < nmacro) hpre4_item<T>(M, (int)(t & 3), n, Af, AIIinv, P, r, e, do_corr, cb);
+  if (M < nmacro) hpreL_item<T, L>(M, (int)(t % L), n, Af, AIIinv, P, r, e, do_corr, cb);
 }
 
 template <int D, typename T>
@@ -581,7 +581,8 @@ __global__ void hsum_kernel(int n, int nrhs, const T* __restrict__ r, const T* _
   if (Fc < ncf) hsum_item<D, T>(Fc, n, r, cb, Dc, rc, ec);
 }
 
-// LPM lanes per macro-element in the macro part (1, or 4 on small 2D levels)
+// LPM lanes per macro-element in the macro part (1, or 2 / 4 on latency-bound
+// 2D levels)
 template <int D, typename T, int LPM>
 __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, long nbf, int nrhs, const T* __restrict__ Af,
                                                     const T* __restrict__ AIIinv, const T* __restrict__ P,
@@ -601,8 +602,8 @@ __global__ void __launch_bounds__(256) hpost_kernel(int n, long nbm, long nbf, i
   if (b < nbm) {
     const long nmacro = (long)(n / 2) * (n / 2);
     const long t = b * 256 + threadIdx.x;
-    if constexpr (LPM == 4) {
-      if ((t >> 2) < nmacro) hpost4_m_item<T>(t >> 2, (int)(t & 3), n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
+    if constexpr (LPM > 1) {
+      if (t / LPM < nmacro) hpostL_m_item<T, LPM>(t / LPM, (int)(t % LPM), n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
     } else {
       if (t < nmacro) hpost_m_item<D, T>(t, n, Af, AIIinv, P, r, ec, eold, enew, do_corr);
     }
@@ -680,13 +681,24 @@ __global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* _
 
 inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
-// macro-element kernels use 4 lanes per macro-element up to this many
-// macro-elements (latency-bound levels), one lane above (bandwidth-bound);
-// HDG_MULTI_LANE_MAX overrides at build time
+// macro-element kernels use 4 lanes per macro-element up to MULTI_LANE_MAX
+// macro-elements times right-hand sides (latency-bound levels), 2 lanes up to
+// MULTI_LANE2_MAX, one lane above (bandwidth-bound); HDG_MULTI_LANE_MAX and
+// HDG_MULTI_LANE2_MAX override at build time.  Two lanes on the 256^2-macro
+// level of the 512^2 workload measured no faster than one, so that band is
+// empty by default.
 #ifndef HDG_MULTI_LANE_MAX
 #define HDG_MULTI_LANE_MAX 16384
 #endif
+#ifndef HDG_MULTI_LANE2_MAX
+#define HDG_MULTI_LANE2_MAX 0
+#endif
 constexpr long MULTI_LANE_MAX = HDG_MULTI_LANE_MAX;  // macro-elements times right-hand sides
+constexpr long MULTI_LANE2_MAX = HDG_MULTI_LANE2_MAX;
+inline int lanes_per_macro(long nmacro, int nrhs) {
+  const long w = nmacro * nrhs;
+  return w <= MULTI_LANE_MAX ? 4 : w <= MULTI_LANE2_MAX ? 2 : 1;
+}
 
 // grid of xcd_block_rhs for nb blocks per right-hand side
 inline unsigned xcd_rhs_grid(long nb, int nrhs) {
@@ -960,8 +972,12 @@ void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  if (L.nmacro * nrhs <= MULTI_LANE_MAX)
-    hipLaunchKernelGGL((hpre4_kernel<T>), dim3(xcd_rhs_grid(nblk(4 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,
+  const int lpm = lanes_per_macro(L.nmacro, nrhs);
+  if (lpm == 4)
+    hipLaunchKernelGGL((hpreL_kernel<T, 4>), dim3(xcd_rhs_grid(nblk(4 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,
+                       Af, Ai, P, r, e, do_corr, cb);
+  else if (lpm == 2)
+    hipLaunchKernelGGL((hpreL_kernel<T, 2>), dim3(xcd_rhs_grid(nblk(2 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,
                        Af, Ai, P, r, e, do_corr, cb);
   else
     hipLaunchKernelGGL((hpre_kernel<T>), dim3(xcd_rhs_grid(nblk(L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs, Af,
@@ -995,9 +1011,14 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   const long nbf = nblk(C.nface);
-  if (L.nmacro * nrhs <= MULTI_LANE_MAX) {
+  const int lpm = lanes_per_macro(L.nmacro, nrhs);
+  if (lpm == 4) {
     const long nbm = nblk(4 * L.nmacro);
     hipLaunchKernelGGL((hpost_kernel<2, T, 4>), dim3(xcd_rhs_grid(nbm + nbf, nrhs)), dim3(256), 0, st, L.n, nbm, nbf,
+                       nrhs, Af, Ai, P, r, ec, eold, enew, do_corr);
+  } else if (lpm == 2) {
+    const long nbm = nblk(2 * L.nmacro);
+    hipLaunchKernelGGL((hpost_kernel<2, T, 2>), dim3(xcd_rhs_grid(nbm + nbf, nrhs)), dim3(256), 0, st, L.n, nbm, nbf,
                        nrhs, Af, Ai, P, r, ec, eold, enew, do_corr);
   } else {
     const long nbm = nblk(L.nmacro);

@@ -428,21 +428,24 @@ __device__ inline void hpre_item(long M, int n, const T* __restrict__ Af, const 
   for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = T(out[j]);
 }
 
-// The same pre-coarse work spread over 4 lanes of one wavefront per
-// macro-element (2D): lane q owns interior face q and the two boundary faces
-// of macro-face q, whose restriction shares are exactly the coarse DOFs
-// 2q, 2q+1 (S = q).  The interior residual is exchanged with shuffles; every
+// The same pre-coarse work spread over L = 2 or 4 lanes of one wavefront per
+// macro-element (2D): lane q owns interior faces q QF .. q QF + QF - 1
+// (QF = 4 / L) and the boundary faces of macro-faces q QS .. q QS + QS - 1
+// (QS = 4 / L), whose restriction shares are exactly the coarse DOFs of
+// those macro-faces.  The interior residual is exchanged with shuffles; each
 // lane then forms its rows of A_II^-1 rho and its columns of P^T rho.  The
-// serial chain of loads per lane is about a quarter of hpre_item's, which is
-// what bounds the small (latency-bound) levels.  All 4 lanes of a group are
-// active together (the group's macro-element is in range or not).
-template <typename T>
-__device__ inline void hpre4_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+// serial chain of loads per lane shrinks about L-fold, which is what bounds
+// latency-bound levels.  All L lanes of a group are active together (the
+// group's macro-element is in range or not).
+template <typename T, int L>
+__device__ inline void hpreL_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
                                   const T* __restrict__ P, const T* r, T* e, int do_corr, T* cb) {
+  static_assert(L == 2 || L == 4, "2 or 4 lanes per macro-element");
   using Mc = Macro<2>;
   using A = acc_t<T>;
-  constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL;
-  const int base = (int)(threadIdx.x & 60);
+  constexpr int NC = Mc::NC, NS = Mc::NS, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL;
+  constexpr int QF = NIF / L, QS = 4 / L;
+  const int base = (int)(threadIdx.x & 63) & ~(L - 1);
   const int nm = n / 2;
   int m[3] = {0, 0, 0};
   decode_elem<2>(M, nm, m);
@@ -455,52 +458,66 @@ __device__ inline void hpre4_item(long M, int q, int n, const T* __restrict__ Af
 #pragma unroll
     for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(e[fid[f] * NC + a]) : A(0);
   }
-  A acc[NC] = {A(0), A(0)};
-  side_apply<2, T>(Af, fid[q], 0, ichild<2>(q, 0), eM, acc);
-  side_apply<2, T>(Af, fid[q], 1, ichild<2>(q, 1), eM, acc);
-  A rq[NC];
+  A rq[QF][NC];
 #pragma unroll
-  for (int a = 0; a < NC; ++a) rq[a] = A(r[fid[q] * NC + a]) - acc[a];
+  for (int u = 0; u < QF; ++u) {
+    const int i = q * QF + u;
+    A acc[NC] = {A(0), A(0)};
+    side_apply<2, T>(Af, fid[i], 0, ichild<2>(i, 0), eM, acc);
+    side_apply<2, T>(Af, fid[i], 1, ichild<2>(i, 1), eM, acc);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rq[u][a] = A(r[fid[i] * NC + a]) - acc[a];
+  }
   A rho[NI];
 #pragma unroll
-  for (int i = 0; i < NIF; ++i)
+  for (int src = 0; src < L; ++src)
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rho[i * NC + a] = __shfl(rq[a], base + i, 64);
+    for (int u = 0; u < QF; ++u)
+#pragma unroll
+      for (int a = 0; a < NC; ++a) rho[(src * QF + u) * NC + a] = __shfl(rq[u][a], base + src, 64);
   if (do_corr) {
 #pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      const int row = q * NC + a;
-      A sacc = A(0);
+    for (int u = 0; u < QF; ++u) {
+      const int i = q * QF + u;
 #pragma unroll
-      for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), row * NI + j)]) * rho[j];
-      e[fid[q] * NC + a] = T(eM[q][a] + sacc);
+      for (int a = 0; a < NC; ++a) {
+        const int row = i * NC + a;
+        A sacc = A(0);
+#pragma unroll
+        for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), row * NI + j)]) * rho[j];
+        e[fid[i] * NC + a] = T(eM[i][a] + sacc);
+      }
     }
   }
-  A o[NC];
 #pragma unroll
-  for (int V = 0; V < NC; ++V) {
-    A sacc = A(0);
-#pragma unroll
-    for (int i = 0; i < NI; ++i) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), i * NCL + q * NC + V)]) * rho[i];
-    o[V] = sacc;
-  }
-#pragma unroll
-  for (int t = 0; t < NC; ++t) {
-    const int b = q * NC + t;
-    const int f = NIF + b;
-    if (fid[f] < 0) continue;
-    A ab[NC] = {A(0), A(0)};
-    side_apply<2, T>(Af, fid[f], sidein[f], bchild<2>(b), eM, ab);
+  for (int w = 0; w < QS; ++w) {
+    const int S = q * QS + w;
+    A o[NC];
 #pragma unroll
     for (int V = 0; V < NC; ++V) {
       A sacc = A(0);
 #pragma unroll
-      for (int v = 0; v < NC; ++v) sacc += A(jh_weight<2>(t, v, V)) * ab[v];
-      o[V] -= sacc;
+      for (int i = 0; i < NI; ++i) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), i * NCL + S * NC + V)]) * rho[i];
+      o[V] = sacc;
     }
-  }
 #pragma unroll
-  for (int V = 0; V < NC; ++V) cb[M * NCL + q * NC + V] = T(o[V]);
+    for (int t = 0; t < NS; ++t) {
+      const int b = S * NS + t;
+      const int f = NIF + b;
+      if (fid[f] < 0) continue;
+      A ab[NC] = {A(0), A(0)};
+      side_apply<2, T>(Af, fid[f], sidein[f], bchild<2>(b), eM, ab);
+#pragma unroll
+      for (int V = 0; V < NC; ++V) {
+        A sacc = A(0);
+#pragma unroll
+        for (int v = 0; v < NC; ++v) sacc += A(jh_weight<2>(t, v, V)) * ab[v];
+        o[V] -= sacc;
+      }
+    }
+#pragma unroll
+    for (int V = 0; V < NC; ++V) cb[M * NCL + S * NC + V] = T(o[V]);
+  }
 }
 
 // Coarse residual r_c = J^T r_B + cb_{M-} + cb_{M+} per coarse face, and the
@@ -641,18 +658,20 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
   }
 }
 
-// hpost_m_item over 4 lanes per macro-element (2D), as hpre4_item: lane q
-// prolongs onto interior face q, the prolonged interior values and then the
-// interior residual are exchanged with shuffles, and lane q applies its rows
-// of A_II^-1.
-template <typename T>
-__device__ inline void hpost4_m_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
+// hpost_m_item over L = 2 or 4 lanes per macro-element (2D), as hpreL_item:
+// lane q prolongs onto its interior faces, the prolonged interior values and
+// then the interior residual are exchanged with shuffles, and lane q applies
+// its rows of A_II^-1.
+template <typename T, int L>
+__device__ inline void hpostL_m_item(long M, int q, int n, const T* __restrict__ Af, const T* __restrict__ AIIinv,
                                      const T* __restrict__ P, const T* r, const T* ec, const T* eold, T* enew,
                                      int do_corr) {
+  static_assert(L == 2 || L == 4, "2 or 4 lanes per macro-element");
   using Mc = Macro<2>;
   using A = acc_t<T>;
   constexpr int NC = Mc::NC, NIF = Mc::NIF, NBF = Mc::NBF, NI = Mc::NI, NCL = Mc::NCL, NS = Mc::NS;
-  const int base = (int)(threadIdx.x & 60);
+  constexpr int QF = NIF / L;
+  const int base = (int)(threadIdx.x & 63) & ~(L - 1);
   const int nm = n / 2;
   int m[3] = {0, 0, 0};
   decode_elem<2>(M, nm, m);
@@ -695,41 +714,59 @@ __device__ inline void hpost4_m_item(long M, int q, int n, const T* __restrict__
       eM[f][v] += sacc;
     }
   }
-  // interior face q: e + P e_c, then shared
-  A eq[NC];
+  // own interior faces: e + P e_c, then shared
+  A eq[QF][NC];
 #pragma unroll
-  for (int a = 0; a < NC; ++a) {
-    A sacc = A(0);
+  for (int u = 0; u < QF; ++u) {
+    const int i = q * QF + u;
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), (q * NC + a) * NCL + j)]) * cv[j];
-    eq[a] = eM[q][a] + sacc;
+    for (int a = 0; a < NC; ++a) {
+      A sacc = A(0);
+#pragma unroll
+      for (int j = 0; j < NCL; ++j) sacc += A(P[aos_off<T>(M, vpad<T>(NI * NCL), (i * NC + a) * NCL + j)]) * cv[j];
+      eq[u][a] = eM[i][a] + sacc;
+    }
   }
 #pragma unroll
-  for (int i = 0; i < NIF; ++i)
+  for (int src = 0; src < L; ++src)
 #pragma unroll
-    for (int a = 0; a < NC; ++a) eM[i][a] = __shfl(eq[a], base + i, 64);
+    for (int u = 0; u < QF; ++u)
+#pragma unroll
+      for (int a = 0; a < NC; ++a) eM[src * QF + u][a] = __shfl(eq[u][a], base + src, 64);
   if (!do_corr) {
 #pragma unroll
-    for (int a = 0; a < NC; ++a) enew[fid[q] * NC + a] = T(eq[a]);
+    for (int u = 0; u < QF; ++u)
+#pragma unroll
+      for (int a = 0; a < NC; ++a) enew[fid[q * QF + u] * NC + a] = T(eq[u][a]);
     return;
   }
-  A acc[NC] = {A(0), A(0)};
-  side_apply<2, T>(Af, fid[q], 0, ichild<2>(q, 0), eM, acc);
-  side_apply<2, T>(Af, fid[q], 1, ichild<2>(q, 1), eM, acc);
-  A rq[NC];
+  A rq[QF][NC];
 #pragma unroll
-  for (int a = 0; a < NC; ++a) rq[a] = A(r[fid[q] * NC + a]) - acc[a];
+  for (int u = 0; u < QF; ++u) {
+    const int i = q * QF + u;
+    A acc[NC] = {A(0), A(0)};
+    side_apply<2, T>(Af, fid[i], 0, ichild<2>(i, 0), eM, acc);
+    side_apply<2, T>(Af, fid[i], 1, ichild<2>(i, 1), eM, acc);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) rq[u][a] = A(r[fid[i] * NC + a]) - acc[a];
+  }
   A rho[NI];
 #pragma unroll
-  for (int i = 0; i < NIF; ++i)
+  for (int src = 0; src < L; ++src)
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rho[i * NC + a] = __shfl(rq[a], base + i, 64);
+    for (int u = 0; u < QF; ++u)
 #pragma unroll
-  for (int a = 0; a < NC; ++a) {
-    A sacc = A(0);
+      for (int a = 0; a < NC; ++a) rho[(src * QF + u) * NC + a] = __shfl(rq[u][a], base + src, 64);
 #pragma unroll
-    for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), (q * NC + a) * NI + j)]) * rho[j];
-    enew[fid[q] * NC + a] = T(eq[a] + sacc);
+  for (int u = 0; u < QF; ++u) {
+    const int i = q * QF + u;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      A sacc = A(0);
+#pragma unroll
+      for (int j = 0; j < NI; ++j) sacc += A(AIIinv[aos_off<T>(M, vpad<T>(NI * NI), (i * NC + a) * NI + j)]) * rho[j];
+      enew[fid[i] * NC + a] = T(eq[u][a] + sacc);
+    }
   }
 }
 

@@ -727,14 +727,32 @@ void dispatch_d_ne(int d, int ne, F&& f) {
   throw HipError{hipErrorInvalidValue, "unsupported (d, ne)"};
 }
 
+// face sizes of the 2D levels (k = 1 .. 6)
+template <typename F>
+void dispatch_ne_2d(int ne, F&& f) {
+  switch (ne) {
+    case 2: f(std::integral_constant<int, 2>{}); return;
+    case 3: f(std::integral_constant<int, 3>{}); return;
+    case 4: f(std::integral_constant<int, 4>{}); return;
+    case 5: f(std::integral_constant<int, 5>{}); return;
+    case 6: f(std::integral_constant<int, 6>{}); return;
+    case 7: f(std::integral_constant<int, 7>{}); return;
+  }
+  throw HipError{hipErrorInvalidValue, "unsupported face size"};
+}
+
 // rows of elements per strip of the one-pass element-major apply (the LDS
-// products of a 64 x SH strip: 20 KiB per 256 lanes in FP32 at k = 4)
+// products of a 64 x SH strip: 40 KiB for 512 lanes in FP32 at k = 4, 80 KiB
+// in FP64; gfx950 gives a workgroup up to 160 KiB)
 #ifndef HDG_STRIP_ROWS32
 #define HDG_STRIP_ROWS32 8
 #endif
+#ifndef HDG_STRIP_ROWS64
+#define HDG_STRIP_ROWS64 8
+#endif
 template <typename T>
 constexpr int strip_rows() {
-  return sizeof(T) == 4 ? HDG_STRIP_ROWS32 : 4;
+  return sizeof(T) == 4 ? HDG_STRIP_ROWS32 : HDG_STRIP_ROWS64;
 }
 
 // one-pass element-major apply (strip_kernel + shface_kernel); returns the
@@ -757,7 +775,7 @@ int launch_strips(const Level& L, const T* Dv, const T* x, const T* b, T* y, con
     throw HipError{hipErrorInvalidValue, "strip apply: edge faces do not fit the edge kernel"};
   if (x == y || 2 * L.ne * nshp > pad64(L.nelem) * L.nl)
     throw HipError{hipErrorInvalidValue, "strip apply: in-place output or edge buffer too small"};
-  dispatch_d_ne(2, L.ne, [&](auto, auto NE_) {
+  dispatch_ne_2d(L.ne, [&](auto NE_) {
     constexpr int NE = decltype(NE_)::value;
     hipLaunchKernelGGL((strip_kernel<NE, T, MODE, SH>), dim3((unsigned)(nbs * nrhs)), dim3(64 * SH), 0, st, n, Ap,
                        Dv, x, b, y, Jp, rc, y32, zsh, nshp, nbt, partials, nrhs);

@@ -4,11 +4,16 @@
 // local correction (eq. localCorrection), h-transfers (eqs. n_1_Ik, n_1_Qk)
 // and the coarsest direct solve (Algorithm 1, B_1 = A_1^-1).
 //
-// One lane per interior face.  The two element matrices that touch a face
-// are read as one face-major AoSoA block in 16-byte entry groups, so every
-// matrix load of a wavefront is one contiguous 1 KiB segment (a lane's
-// 16-byte load); the trace vector is gathered through the caches.  No atomics: every output is
-// written by exactly one lane, so results are bitwise reproducible.
+// Face-major levels: one lane per interior face.  The rows of the two
+// element maps that touch a face are one face-major AoSoA item, so every
+// matrix load of a wavefront is one contiguous segment; the trace vector is
+// gathered through the caches.  The finest level of a p-transition in 2D is
+// element-major (packed symmetric maps): strip_kernel forms the element
+// products of a 64 x 8 strip in LDS and finishes the faces inside the strip,
+// shface_kernel the faces on strip edges.  The macro-element kernels of the
+// h-transitions take 1, 2 or 4 lanes per macro-element.  No atomics: every
+// output is written by exactly one lane, so results are bitwise
+// reproducible.
 #include "hdg_internal.hpp"
 #include "blas.hpp"
 #include "reduce.hpp"

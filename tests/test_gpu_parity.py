@@ -337,6 +337,26 @@ def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
     assert e <= 1e-8
 
 
+def test_strip_apply_sixteen_rhs_matches_two_phase(torch_cuda, monkeypatch):
+    """Sixteen right-hand sides in one strip launch (the batched workload's
+    group size; workgroups of one strip for every right-hand side share its
+    maps through the XCD's L2) give the two-phase V-cycle bit for bit."""
+    from paper_1811_09909_amd import _lib as L
+    n, k, nr = 128, 4, 16
+    kap, rng = _kappa(2, n, 1e-2, 1e2)
+    out = {}
+    for strip in ("1", "0"):
+        monkeypatch.setenv("HDG_NO_STRIP", "0" if strip == "1" else "1")
+        P = _gpu(torch_cuda, 2, n, k, kap)
+        P.build(local_corr=omg.LC_BOTH, nrhs=nr)
+        R = torch_cuda.as_tensor(np.random.default_rng(11).standard_normal(nr * P.nlam))
+        out[strip] = (P.vcycle(R).cpu().numpy(), P.vcycle(R.float(), precision=L.FP32).cpu().numpy())
+    for i, nm in enumerate(("fp64", "fp32")):
+        diff = np.abs(out["1"][i] - out["0"][i]).max()
+        say(f"[strip 16 rhs] n={n} k={k} {nm}: strip vs two-phase max diff {diff:.1e}")
+        assert diff == 0.0
+
+
 @pytest.mark.parametrize("method", ["mg", "pcg", "gmres"])
 def test_iterates_at_fixed_count(torch_cuda, method):
     d, n, k = 2, 16, 2

@@ -25,6 +25,11 @@ struct hdg_problem {
   int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (HDG_TAIL_N, 0 = off)
   bool pack = true;              // element-major packed finest p-level (HDG_NO_PACK=1: face-major)
   bool strip = true;             // one-pass strip apply on packed levels (HDG_NO_STRIP=1: two-phase)
+  // set around a preconditioner call inside CG: the finest level's last
+  // sweep also forms the r.z partials (dot_v = r); dot_parts receives their
+  // count per right-hand side (0: not formed)
+  const double* dot_v = nullptr;
+  int dot_parts = 0;
   int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
   TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -333,7 +338,13 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
   }
   for (int s = 0; s < m; ++s) {
     T* dst = (out && s == m - 1) ? out : w;
-    apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
+    if (i == 0 && P->dot_v && dst == out) {
+      int np = 0;
+      launch_apply_red<T>(L, APPLY_SWEEP_DOT, e, r, dst, P->dot_v, nullptr, nullptr, &P->s, st, nr, &np);
+      P->dot_parts = np;
+    } else {
+      apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
+    }
     if (dst == w)
       std::swap(e, w);
     else
@@ -559,14 +570,21 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
                 blas_cg_update2_fused<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, npap, P->s, s2, nr);
               else
                 blas_cg_update2_fused<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, npap, P->s, s2, nr);
+              // the V-cycle's last finest-level sweep also forms the r.z partials
+              P->dot_v = P->r;
+              P->dot_parts = 0;
               precond_fused(P, mixed, nr);
-              if (mixed) {
+              P->dot_v = nullptr;
+              if (P->dot_parts > 0)
+                blas_finalize_cg(N, P->dot_parts, mixed, P->s, s2, nr);
+              else if (mixed)
                 blas_rz_cg<float>(P->r, P->z32, N, true, P->s, s2, nr);
-                blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
-              } else {
+              else
                 blas_rz_cg<double>(P->r, P->z, N, false, P->s, s2, nr);
+              if (mixed)
+                blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
+              else
                 blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
-              }
             },
             nr);
       done = tr.scan(read_scalars(P, nr), launched, grp, &rel);

@@ -375,6 +375,12 @@ void blas_rz_cg(const double* r, const ZT* z, long n, bool flex, Scratch& s, hip
   HDG_CHECK(hipGetLastError());
 }
 template void blas_rz_cg<double>(const double*, const double*, long, bool, Scratch&, hipStream_t, int);
+
+void blas_finalize_cg(long n, int nrz, bool flex, Scratch& s, hipStream_t st, int nrhs) {
+  hipLaunchKernelGGL(finalize_cg_kernel, dim3(nrhs), dim3(RB), 0, st, s.pcg, (int)rg(n), s.partials, nrz,
+                     flex ? 1 : 0, s.sc);
+  HDG_CHECK(hipGetLastError());
+}
 template void blas_rz_cg<float>(const double*, const float*, long, bool, Scratch&, hipStream_t, int);
 template void blas_cg_update2<double>(double*, double*, float*, const double*, const double*, const double*, long,
                                       Scratch&, hipStream_t, int);

@@ -53,6 +53,9 @@ void blas_cg_update2_fused(double* lam, double* r, float* r32, const double* p, 
                            long n, int npap, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
 void blas_rz_cg(const double* r, const ZT* z, long n, bool flex, Scratch& s, hipStream_t st, int nrhs = 1);
+// the same finaliser when the r.z partials (nrz per right-hand side) were
+// written by the preconditioner's last sweep
+void blas_finalize_cg(long n, int nrz, bool flex, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>
 void blas_cg_dir(double* p, const ZT* z, long n, Scratch& s, hipStream_t st, int nrhs = 1);
 template <typename ZT>

@@ -227,7 +227,12 @@ struct TailArgs {
 template <typename T>
 void launch_tail(const TailArgs& a, hipStream_t st, int nrhs = 1);
 
-enum { APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5 };
+// APPLY_SWEEP_DOT: a sweep that also sums v . y (partials, v FP64, passed
+// where RES_PRESTRICT takes J_N) for the CG dot product r . z
+enum {
+  APPLY_Y = 0, APPLY_RES = 1, APPLY_SWEEP = 2, APPLY_RES_PRESTRICT = 3, APPLY_Y_DOT = 4, APPLY_RES_NORM = 5,
+  APPLY_SWEEP_DOT = 6
+};
 struct Scratch;
 // Modes with a reduction write per-block partials into red->partials; the
 // one-block finaliser runs next, unless nparts is given: then it receives

@@ -50,7 +50,7 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
   } else if (MODE == APPLY_RES) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) y[F * NE + a] = T(A(bvec[F * NE + a]) - acc[a]);
-  } else if (MODE == APPLY_SWEEP) {
+  } else if (MODE == APPLY_SWEEP || MODE == APPLY_SWEEP_DOT) {
     A res[NE];
 #pragma unroll
     for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
@@ -58,6 +58,9 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
       dinv_update_sym<NE, T>(F, Dinv, x, res, y);
     else
       dinv_update<NE, T>(F, Dinv, x, res, y);
+    if (MODE == APPLY_SWEEP_DOT)  // Jp holds the FP64 vector of the dot product
+#pragma unroll
+      for (int a = 0; a < NE; ++a) part += Jp[F * NE + a] * (double)y[F * NE + a];
   } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
     A res[NE];
 #pragma unroll
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
                                                     T* __restrict__ y, const double* __restrict__ Jp,
                                                     T* __restrict__ rc, float* __restrict__ y32,
                                                     double* __restrict__ partials, int nrhs) {
-  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM || MODE == APPLY_SWEEP_DOT);
   constexpr int NC = 1 << (D - 1);
   int rhs;
   unsigned slot;
@@ -112,6 +115,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
     y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
     rc = off(rc, rhs * sC);
     y32 = off(y32, rhs * sN);
+    if (MODE == APPLY_SWEEP_DOT) Jp += rhs * sN;
     if (ZS) {
       long nelem = 1;
       for (int a = 0; a < D; ++a) nelem *= n;
@@ -183,7 +187,7 @@ __global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restri
                                                         T* __restrict__ zsh, long nshp, int nbt,
                                                         double* __restrict__ partials, int nrhs) {
   constexpr int D = 2, NC = 2, NL = 4 * NE, NT = 64 * SH;
-  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM || MODE == APPLY_SWEEP_DOT);
   using A = acc_t<T>;
   __shared__ __align__(16) T zs[NL * NT];
   const int nsx = n / 64, nsy = n / SH;
@@ -208,6 +212,7 @@ __global__ void __launch_bounds__(64 * SH) strip_kernel(int n, const T* __restri
     y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
     rc = off(rc, rhs * sC);
     y32 = off(y32, rhs * sN);
+    if (MODE == APPLY_SWEEP_DOT) Jp += rhs * sN;
     zsh += rhs * (2L * NE) * nshp;
   }
   {
@@ -303,7 +308,7 @@ __global__ void __launch_bounds__(SHF_TPB) shface_kernel(int n, const T* __restr
                                                      float* __restrict__ y32, const T* __restrict__ zsh, long nshp,
                                                      int vpb, int nbt, int nb0, double* __restrict__ partials) {
   constexpr int D = 2, NC = 2;
-  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM);
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM || MODE == APPLY_SWEEP_DOT);
   const int rhs = blockIdx.y;
   const long nsx = n / 64, nsy = n / SH;
   const long NV = (nsx - 1) * n, NH = (nsy - 1) * n;
@@ -314,6 +319,7 @@ __global__ void __launch_bounds__(SHF_TPB) shface_kernel(int n, const T* __restr
     y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
     rc = off(rc, rhs * sC);
     y32 = off(y32, rhs * sN);
+    if (MODE == APPLY_SWEEP_DOT) Jp += rhs * sN;
     zsh += rhs * (2L * NE) * nshp;
   }
   double part = 0.0;
@@ -842,7 +848,16 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
       case APPLY_RES_NORM:
         nbt = launch_strips<T, APPLY_RES_NORM>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs);
         break;
+      case APPLY_SWEEP_DOT:
+        nbt = launch_strips<T, APPLY_SWEEP_DOT>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs);
+        break;
       default: throw HipError{hipErrorInvalidValue, "apply mode"};
+    }
+    if (mode == APPLY_SWEEP_DOT && !(red && nparts))
+      throw HipError{hipErrorInvalidValue, "sweep with dot product: partials are finished by the caller"};
+    if (red && mode == APPLY_SWEEP_DOT) {
+      if (nbt > red->row) throw HipError{hipErrorInvalidValue, "strip apply: too many partial sums"};
+      *nparts = nbt;
     }
     if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
       if (nbt > red->row) throw HipError{hipErrorInvalidValue, "strip apply: too many partial sums"};
@@ -871,11 +886,17 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
       case APPLY_RES_PRESTRICT: HDG_AK(APPLY_RES_PRESTRICT); break;
       case APPLY_Y_DOT: HDG_AK(APPLY_Y_DOT); break;
       case APPLY_RES_NORM: HDG_AK(APPLY_RES_NORM); break;
+      case APPLY_SWEEP_DOT: HDG_AK(APPLY_SWEEP_DOT); break;
       default: throw HipError{hipErrorInvalidValue, "apply mode"};
     }
 #undef HDG_AK
   });
   HDG_CHECK(hipGetLastError());
+  if (mode == APPLY_SWEEP_DOT) {
+    if (!(red && nparts))
+      throw HipError{hipErrorInvalidValue, "sweep with dot product: partials are finished by the caller"};
+    *nparts = (int)g1;
+  }
   if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
     if (nparts)
       *nparts = (int)g1;

@@ -193,7 +193,8 @@ hdg_status hdg_level_export(hdg_handle h, int level, double* out);
  * events recorded on the handle's stream, from hdg_profile_begin until
  * hdg_profile_read.  kernel = 2 * mode + precision, mode 0 apply y = A x,
  * 1 residual b - A x, 2 block-Jacobi sweep x + D^-1 (b - A x), 3 residual
- * restricted to P1 (J_N^T); precision HDG_FP64 / HDG_FP32.  Returns the
+ * restricted to P1 (J_N^T), 6 the sweep inside CG's preconditioner that also
+ * forms the r.z partials; precision HDG_FP64 / HDG_FP32.  Returns the
  * number of launches, their summed duration, and the algorithmic HBM bytes
  * of one launch (stored face-major matrix blocks, face-block inverses and
  * each vector entry read or written once). */

@@ -63,8 +63,9 @@ struct hdg_problem {
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
-  double prof_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  long long prof_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int NPROF = 2 * (APPLY_SWEEP_DOT + 1);
+  double prof_ms[NPROF] = {};
+  long long prof_n[NPROF] = {};
   std::vector<void*> allocs;        // freed in destroy
   std::vector<void*> build_allocs;  // freed on rebuild
   long long bytes = 0;
@@ -340,7 +341,18 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
     T* dst = (out && s == m - 1) ? out : w;
     if (i == 0 && P->dot_v && dst == out) {
       int np = 0;
+      const bool timed = P->prof_on && nr == 1;
+      hdg_problem::Pending pd{2 * APPLY_SWEEP_DOT + pr, nullptr, nullptr};
+      if (timed) {
+        pd.a = take_event(P);
+        pd.b = take_event(P);
+        HDG_CHECK(hipEventRecord(pd.a, st));
+      }
       launch_apply_red<T>(L, APPLY_SWEEP_DOT, e, r, dst, P->dot_v, nullptr, nullptr, &P->s, st, nr, &np);
+      if (timed) {
+        HDG_CHECK(hipEventRecord(pd.b, st));
+        P->pending.push_back(pd);
+      }
       P->dot_parts = np;
     } else {
       apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
@@ -1347,7 +1359,7 @@ hdg_status hdg_profile_begin(hdg_handle P) {
   HDG_GUARD_BEGIN
   HDG_CHECK(hipStreamSynchronize(P->st));
   harvest(P);
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < hdg_problem::NPROF; ++i) {
     P->prof_ms[i] = 0.0;
     P->prof_n[i] = 0;
   }
@@ -1358,7 +1370,7 @@ hdg_status hdg_profile_begin(hdg_handle P) {
 
 hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, double* total_ms,
                             double* bytes_per_launch) {
-  if (!P || kernel < 0 || kernel > 7) return HDG_ERR_INVALID_ARG;
+  if (!P || kernel < 0 || kernel >= hdg_problem::NPROF) return HDG_ERR_INVALID_ARG;
   if (!P->built) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
   HDG_CHECK(hipStreamSynchronize(P->st));
@@ -1375,6 +1387,7 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   // face-block inverses: full blocks, or upper triangles on element-major levels
   const double nd = L.packed ? L.ne * (L.ne + 1) / 2 : L.ne * L.ne;
   if (mode == APPLY_SWEEP) bytes += (double)L.nface * nd * s + 3.0 * N * s;
+  if (mode == APPLY_SWEEP_DOT) bytes += (double)L.nface * nd * s + 3.0 * N * s + 8.0 * N;  // + r (FP64)
   if (mode == APPLY_RES_PRESTRICT) bytes += 2.0 * N * s + (double)L.nface * (1 << (L.d - 1)) * s;
   if (launches) *launches = P->prof_n[kernel];
   if (total_ms) *total_ms = P->prof_ms[kernel];

@@ -19,8 +19,9 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_stored_sweep_traffic_is_calibrated_and_above_the_algorithmic_bytes():
     """The counters are stored with a hash of the kernel sources: either they
-    match the sources (then the calibrated bytes lie between the sweep's
-    algorithmic bytes and 1.5 times that), or the bench reports null."""
+    match the sources (then the calibrated bytes of both sweep kinds lie
+    between their algorithmic bytes and 1.5 times that), or the bench
+    reports null."""
     t = bench.TRAFFIC
     assert t["cal_fetch"] > 0 and t["cal_write"] > 0
     # FETCH_SIZE counts about half the bytes a copy reads, WRITE_SIZE all it writes
@@ -31,7 +32,8 @@ def test_stored_sweep_traffic_is_calibrated_and_above_the_algorithmic_bytes():
     if got is None:
         return
     # algorithmic bytes of one FP32 sweep at 512^2, k = 4: packed maps, face-block
-    # inverse triangles, three trace vectors
+    # inverse triangles, three trace vectors; the r.z sweep also reads r (FP64)
     nel, nface, nlam = 512 * 512, 2 * 512 * 511, 2 * 512 * 511 * 5
     alg = (nel * 210 + nface * 15 + 3 * nlam) * 4
-    assert alg <= got <= 1.5 * alg
+    assert alg <= got["plain"] <= 1.5 * alg
+    assert alg + 8 * nlam <= got["rz"] <= 1.5 * (alg + 8 * nlam)

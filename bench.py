@@ -82,6 +82,13 @@ def parse():
                          "k in {2..5}, 16 right-hand sides each) through hdg_solve_batch; prints its own JSON line")
     ap.add_argument("--batched-nprob", type=int, default=64)
     ap.add_argument("--batched-nstreams", type=int, default=4)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (32^3, k = 3) FP64/mixed legs")
+    ap.add_argument("--n3d", type=int, default=32)
+    ap.add_argument("--steps3d", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-errors", action="store_true", help="skip the solve to the FP64 floor (error report)")
+    ap.add_argument("--ref-tol", type=float, default=1e-13,
+                    help="tolerance of the FP64 reference solve (stops at its floor if not reachable)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only finest-level FP32 sweeps of the workload and a plain copy-like kernel of known "
                          "size (for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs), then exit")
@@ -124,7 +131,9 @@ def run_cpu_baseline(n, k, coarse_n, min_s):
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     res = json.loads(out.stdout.strip().splitlines()[-1])
+    host_cores, cpu_model = host_info()
     return {"value": res["trace_dofs"] / res["solve_s"], "unit": "trace DOFs/s", "cores": 1, "kind": "oracle",
+            "host_cores": host_cores, "cpu_model": cpu_model,
             "sample": f"diffusion2d n={n} k={k} (same kappa/f distribution, seed 0), oracle CG + V-cycle "
                       f"solve to 1e-10: {res['iters']} iterations, {res['solve_s']:.2f} s per solve over {res['reps']} solves "
                       f"(assembly {res['setup_s']:.1f} s, hierarchy {res['build_s']:.1f} s excluded); "
@@ -142,16 +151,16 @@ def traffic_probe(args):
     from paper_1811_09909_amd import inputs
     from paper_1811_09909_amd.hdg import Problem
     wl = inputs.diffusion2d(args.n, args.k, 1e-3, 1e3, seed=0)
-    os.environ["HDG_NO_GRAPH"] = "1"  # eager launches: counters are read per dispatch
     P = Problem(2, args.n, args.k, torch.as_tensor(wl.kappa), tau=1.0, store_recovery=False)
+    # eager launches: counters are read per dispatch
     P.build(sweeps=args.sweeps, growth=args.growth, local_corr=L.LC_BOTH, precision=L.MIXED,
-            method=L.METHOD_PCG, coarse_n=args.coarse_n)
+            method=L.METHOD_PCG, coarse_n=args.coarse_n, variant=L.VARIANT_NO_GRAPH)
     r = torch.randn(P.nlam, dtype=torch.float32, device="cuda")
     for _ in range(3):
         P.level_smooth(0, r, 4, precision=L.FP32)  # one first step + 3 sweep launches
     # three CG iterations: the sweeps that also form r.z
     P.build(sweeps=args.sweeps, growth=args.growth, local_corr=L.LC_BOTH, precision=L.MIXED,
-            method=L.METHOD_PCG, coarse_n=args.coarse_n, max_it=3)
+            method=L.METHOD_PCG, coarse_n=args.coarse_n, max_it=3, variant=L.VARIANT_NO_GRAPH)
     P.solve(torch.as_tensor(wl.f), tol=1e-30, allow_not_converged=True)
     x = torch.ones(CAL_BYTES // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -213,8 +222,100 @@ def batched(args):
                    "setup_and_autotune_s": round(t_setup, 2),
                    "classes": {f"n{n}_k{k}": v for (n, k), v in sorted(tuned.items())}},
     }
-    print(json.dumps(out))
-    return 0
+    return out
+
+
+def host_info():
+    """Cores this process may run on and the host CPU model."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return cores, model
+
+
+def timed_solves(P, f, tol, steps, warmup, **kw):
+    """Warm-up solves (graph capture), then `steps` solves each bracketed by
+    device synchronisations: per-step wall times (s), last solution, infos."""
+    import torch
+    for _ in range(warmup):
+        P.solve(f, tol=tol, **kw)
+    torch.cuda.synchronize()
+    times, infos, lam = [], [], None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, info = P.solve(f, tol=tol, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(info)
+    return times, lam, infos
+
+
+def median(xs):
+    xs = sorted(xs)
+    m = len(xs)
+    return xs[m // 2] if m % 2 else 0.5 * (xs[m // 2 - 1] + xs[m // 2])
+
+
+def rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+def cube3d_legs(args):
+    """The 3D workload (32^3 hexahedra, k = 3, kappa(x) at the Gauss points,
+    manufactured u): FP64 and mixed PCG + V-cycle to 1e-10, same launch path
+    as the headline (graphs, no profiling); median step times."""
+    import torch
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+    n, k = args.n3d, 3
+    wl = inputs.diffusion3d(n, k)
+    probe = Problem(3, n, k, torch.ones(n ** 3, dtype=torch.float64), tau=1.0, store_recovery=False)
+    X = probe.volume_qpoints().numpy()
+    Xn = probe.volume_nodes().numpy()
+    probe.close()
+    kq = torch.as_tensor(wl.kappa_fn(X), device="cuda")
+    f = torch.as_tensor(wl.f(Xn), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Problem(3, n, k, kq, tau=1.0, kappa_kind="qp", store_recovery=False)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    out = {"workload": wl.name + " tau=1", "trace_dofs": P.nlam, "setup_ms": round(1e3 * t_setup, 2)}
+    lams = {}
+    for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
+        P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH, precision=prec, method=L.METHOD_PCG,
+                max_it=args.max_it, coarse_n=2)
+        times, lam, infos = timed_solves(P, f, args.tol, args.steps3d, 1)
+        ms = 1e3 * median(times)
+        lams[nm] = lam
+        out[nm] = {"value": round(P.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "iters": infos[-1]["iters"], "refinement_steps": infos[-1]["outer_iters"],
+                   "relres": max(i["relres"] for i in infos), "build_ms": round(infos[-1]["t_build_ms"], 2)}
+    out["lambda_mixed_vs_fp64"] = rel(lams["mixed"], lams["fp64"])
+    out["mixed_over_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    P.close()
+    return out
 
 
 def main():
@@ -222,7 +323,8 @@ def main():
     if args.traffic_probe:
         return traffic_probe(args)
     if args.batched:
-        return batched(args)
+        print(json.dumps(batched(args)))
+        return 0
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_n, args.k, args.coarse_n, args.cpu_min_s)))
         return 0
@@ -252,39 +354,26 @@ def main():
     t_setup = time.perf_counter() - t0
     N = P.nlam
 
-    def leg(precision, profile):
-        t0 = time.perf_counter()
+    def build(precision, max_it=None):
         P.build(sweeps=args.sweeps, growth=args.growth, local_corr=lc, precision=precision, method=method,
-                max_it=args.max_it, coarse_n=args.coarse_n)
+                max_it=args.max_it if max_it is None else max_it, coarse_n=args.coarse_n)
+
+    def leg(precision):
+        """The production path: graph-captured iteration bodies, no event
+        bracketing; the median of per-step times."""
+        t0 = time.perf_counter()
+        build(precision)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
-        for _ in range(args.warmup):
-            P.solve(f, tol=args.tol)
-        torch.cuda.synchronize()
-        if profile:
-            P.profile_begin()
-        infos = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            lam, info = P.solve(f, tol=args.tol)
-            infos.append(info)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        prof = None
-        if profile:
-            prof = {}
-            for mode, name in [(0, "apply"), (1, "residual"), (2, "sweep"), (3, "residual_prestrict"),
-                               (6, "sweep_rz")]:
-                for pr, pn in [(0, "fp64"), (1, "fp32")]:
-                    r = P.profile_read(mode, pr)
-                    if r["launches"]:
-                        prof[f"{name}_{pn}"] = r
-        return {"elapsed_s": el, "ms_per_step": 1e3 * el / args.steps, "value": N * args.steps / el,
-                "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos), "build_s": t_build,
-                "n_levels": infos[-1]["n_levels"], "prof": prof, "lam": lam}
+        times, lam, infos = timed_solves(P, f, args.tol, args.steps, args.warmup)
+        ms = 1e3 * median(times)
+        return {"ms_per_step": ms, "mean_ms": 1e3 * sum(times) / len(times), "value": N / (ms / 1e3),
+                "iters": infos[-1]["iters"], "refinement_steps": infos[-1]["outer_iters"],
+                "relres": max(i["relres"] for i in infos), "build_s": t_build,
+                "n_levels": infos[-1]["n_levels"], "lam": lam, "elapsed_s": sum(times)}
 
-    res64 = None if args.skip_fp64 else leg(L.FP64, False)
-    resmx = leg(L.MIXED, True)
+    res64 = None if args.skip_fp64 else leg(L.FP64)
+    resmx = leg(L.MIXED)
     # recovery of (u, q) from the mixed solution, timed once (outside the step)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -292,11 +381,33 @@ def main():
     torch.cuda.synchronize()
     t_rec = time.perf_counter() - t0
 
+    # kernel timing: one more mixed solve, untimed, with HIP events around
+    # every finest-level launch (eager launches: this pass is not the step)
+    P.profile_begin()
+    P.solve(f, tol=args.tol)
+    prof = {}
+    for mode, name in [(0, "apply"), (1, "residual"), (2, "sweep"), (3, "residual_prestrict"), (6, "sweep_rz")]:
+        for pr, pn in [(0, "fp64"), (1, "fp32")]:
+            r = P.profile_read(mode, pr)
+            if r["launches"]:
+                prof[f"{name}_{pn}"] = r
+
+    # errors of the headline solutions against the FP64 reference: the FP64
+    # solve driven to its floor (the relative residual it can reach)
+    errors = None
+    if not args.skip_fp64 and not args.no_errors:
+        build(L.FP64, max_it=res64["iters"] + 400)  # a few hundred iterations past the metric's tolerance
+        lam_ref, info_ref = P.solve(f, tol=args.ref_tol, allow_not_converged=True)
+        u_ref, q_ref = P.reconstruct(lam_ref, f)
+        u64, q64 = P.reconstruct(res64["lam"], f)
+        errors = {"reference": f"FP64 PCG driven to relres {info_ref['relres']:.2e} ({info_ref['iters']} iterations)",
+                  "mixed": {"lambda": rel(resmx["lam"], lam_ref), "u": rel(u, u_ref), "q": rel(q, q_ref)},
+                  "fp64": {"lambda": rel(res64["lam"], lam_ref), "u": rel(u64, u_ref), "q": rel(q64, q_ref)}}
+
     # dominant kernel of the mixed leg: the finest-level FP32 block-Jacobi
     # sweep, every launch of it (the plain sweeps and the one per iteration
     # that also forms the r.z partials of CG): summed algorithmic bytes over
     # summed event time
-    prof = resmx["prof"]
     sw = [prof[nm] for nm in ("sweep_fp32", "sweep_rz_fp32") if nm in prof]
     if sw:
         launches = sum(v["launches"] for v in sw)
@@ -323,10 +434,26 @@ def main():
                 "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                 "kernel": f"trace {dom_label}",
                 "avg_launch_ms": round(avg_ms, 5), "launches": launches,
-                "algorithmic_bytes_per_launch": round(bytes_per_launch, 1)}
+                "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
+                "timing": "HIP events around each launch in a separate eager solve (not the timed step)"}
     kernels = {name: {"launches": v["launches"], "avg_ms": round(v["total_ms"] / v["launches"], 5),
-                      "GBps": round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e9, 1)}
+                      "GBps": round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e9, 1),
+                      "frac": round(v["bytes_per_launch"] / (v["total_ms"] / v["launches"] * 1e-3) / 1e12 / 8.0, 4)}
                for name, v in prof.items()}
+    P.close()
+
+    cube = None
+    if not args.no_3d:
+        try:
+            cube = cube3d_legs(args)
+        except Exception as e:  # reported; the headline stands on its own
+            cube = {"error": str(e)[:300]}
+    batch = None
+    if not args.no_batched:
+        try:
+            batch = batched(args)
+        except Exception as e:
+            batch = {"error": str(e)[:300]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -343,13 +470,17 @@ def main():
         "config": {"workload": wl.name + " tau=1", "trace_dofs": N, "levels": resmx["n_levels"],
                    "method": f"{args.method} + V-cycle (sweeps {args.sweeps}, growth {args.growth}, "
                              f"coarsest {args.coarse_n}x{args.coarse_n} macro grid)",
-                   "tol": args.tol, "iters_mixed": resmx["iters"], "relres_mixed": resmx["relres"],
+                   "step_time": "median of per-step wall times (graph-captured production path)",
+                   "tol": args.tol, "iters_mixed": resmx["iters"], "refinement_steps_mixed": resmx["refinement_steps"],
+                   "relres_mixed": resmx["relres"], "mean_ms_mixed": round(resmx["mean_ms"], 3),
                    "fp64": None if res64 is None else {"value": round(res64["value"], 1),
                                                        "ms_per_step": round(res64["ms_per_step"], 3),
                                                        "iters": res64["iters"], "relres": res64["relres"]},
+                   "mixed_over_fp64": None if res64 is None else round(resmx["value"] / res64["value"], 3),
                    "setup_ms": round(1e3 * t_setup, 2), "build_ms_mixed": round(1e3 * resmx["build_s"], 2),
                    "reconstruct_ms": round(1e3 * t_rec, 3),
-                   "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1)},
+                   "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1),
+                   "errors": errors, "diffusion3d": cube, "batched": batch},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

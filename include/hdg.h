@@ -90,13 +90,33 @@ typedef struct {
                        larger counts go through in groups of this size.  Every kernel of the cycle and
                        of CG then runs all of them in one launch, and the trace apply reads each
                        operator block once for the group (through the L2 of its XCD). */
+  double refine_red;/* HDG_MIXED with PCG: each FP64 refinement step runs the FP32-preconditioned CG
+                       until its residual has dropped by this factor against the step's true FP64
+                       residual (or stagnates), then recomputes g - A lambda in FP64 and restarts
+                       (0: default 1e-5).  Unused in FP64. */
+  int variant;      /* HDG_VARIANT_* bits: select another execution form of the same method (for
+                       comparing forms; 0 = the default, fastest form).  Iterates agree up to the
+                       order of rounding. */
 } hdg_mg_opts;
 
+/* Execution-form bits of hdg_mg_opts.variant. */
+enum {
+  HDG_VARIANT_NO_GRAPH = 1, /* launch iteration bodies eagerly instead of replaying captured HIP graphs */
+  HDG_VARIANT_NO_FUSE = 2,  /* unfused level-transition kernels (residual, restriction, prolongation apart) */
+  HDG_VARIANT_NO_TAIL = 4,  /* no one-workgroup coarse tail: every level launched on its own */
+  HDG_VARIANT_NO_PACK = 8,  /* finest p-level stored face-major instead of element-major packed triangles */
+  HDG_VARIANT_NO_STRIP = 16 /* element-major finest level applied in two passes instead of one strip pass */
+};
+
 typedef struct {
-  int iters;        /* outer iterations (V-cycles applied) */
+  int iters;        /* iterations of the outer method (V-cycles applied; for mixed PCG, CG steps over
+                       all refinement steps) */
   double relres;    /* final ||g - A lambda||_2 / ||g||_2 computed in FP64 */
   double t_solve_ms;/* stream time of the solve */
   int n_levels;
+  int outer_iters;  /* true FP64 residuals formed: refinement steps of mixed PCG, (re)starts otherwise */
+  double t_setup_ms;/* host wall time of the handle's last hdg_setup / hdg_update_kappa (element maps) */
+  double t_build_ms;/* host wall time of the handle's last hdg_mg_build (hierarchy) */
 } hdg_solve_info;
 
 /* Fill opts with the defaults above (constant 2 sweeps, omega 1, step-3

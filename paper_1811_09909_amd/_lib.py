@@ -35,12 +35,24 @@ class Opts(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("growth", ctypes.c_int), ("omega", ctypes.c_double),
                 ("local_corr", ctypes.c_int), ("precision", ctypes.c_int), ("method", ctypes.c_int),
                 ("max_it", ctypes.c_int), ("restart", ctypes.c_int), ("coarse_n", ctypes.c_int),
-                ("nrhs", ctypes.c_int)]
+                ("nrhs", ctypes.c_int), ("refine_red", ctypes.c_double), ("variant", ctypes.c_int)]
+
+
+# hdg_mg_opts.variant bits (HDG_VARIANT_*)
+VARIANT_NO_GRAPH, VARIANT_NO_FUSE, VARIANT_NO_TAIL, VARIANT_NO_PACK, VARIANT_NO_STRIP = 1, 2, 4, 8, 16
+OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", "max_it", "restart", "coarse_n",
+              "nrhs", "refine_red", "variant")
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
-                ("n_levels", ctypes.c_int)]
+                ("n_levels", ctypes.c_int), ("outer_iters", ctypes.c_int), ("t_setup_ms", ctypes.c_double),
+                ("t_build_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "relres": self.relres, "t_solve_ms": self.t_solve_ms,
+                "n_levels": self.n_levels, "outer_iters": self.outer_iters, "t_setup_ms": self.t_setup_ms,
+                "t_build_ms": self.t_build_ms}
 
 
 _lib = None

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <chrono>
 #include <limits>
 #include <new>
 #include <thread>
@@ -20,11 +21,13 @@ struct hdg_problem {
   double tau = 1.0;
   hipStream_t st = nullptr;      // caller's stream: all work is ordered on it
   hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
-  bool use_graphs = true;
-  bool fuse = true;              // fused 2D transition kernels (HDG_NO_FUSE=1 selects the unfused ones)
-  int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (HDG_TAIL_N, 0 = off)
-  bool pack = true;              // element-major packed finest p-level (HDG_NO_PACK=1: face-major)
-  bool strip = true;             // one-pass strip apply on packed levels (HDG_NO_STRIP=1: two-phase)
+  // execution form, from hdg_mg_opts.variant at build
+  bool use_graphs = true;        // replay captured graphs (HDG_VARIANT_NO_GRAPH: eager launches)
+  bool fuse = true;              // fused 2D transition kernels (HDG_VARIANT_NO_FUSE: unfused)
+  int tail_nmax = 32;            // largest grid handled by the one-workgroup coarse tail (0 = off)
+  bool pack = true;              // element-major packed finest p-level (HDG_VARIANT_NO_PACK: face-major)
+  bool strip = true;             // one-pass strip apply on packed levels (HDG_VARIANT_NO_STRIP: two-phase)
+  double t_setup_ms = 0.0, t_build_ms = 0.0;  // host wall time of the last setup / build
   // set around a preconditioner call inside CG: the finest level's last
   // sweep also forms the r.z partials (dot_v = r); dot_parts receives their
   // count per right-hand side (0: not formed)
@@ -406,6 +409,7 @@ constexpr int CHECK_EVERY = 4;
 
 struct SolveOut {
   int iters = 0;
+  int outer = 0;  // true residuals formed
   double relres = 0.0;
   hdg_status status = HDG_OK;
 };
@@ -439,17 +443,39 @@ void precond_fused(hdg_problem* P, bool mixed, int nr) {
 // Convergence bookkeeping of nr right-hand sides iterated together: the
 // residual history of each since the last reset of the count, its first
 // converged iteration, and the worst residual of the returned iterates.
+// For a refinement step of mixed PCG it also tracks each right-hand side's
+// inner target (a reduction of the step's true residual) and stagnation: no
+// halving of its best residual within STAG_WINDOW iterations.
+constexpr int STAG_WINDOW = 100;
 struct Tracker {
   int nr = 1;
   double tol = 0.0;
   const double* gn = nullptr;
   int first[64];
   bool bad = false;
+  double tgt[64], best[64], mark[64];
+  int t_mark[64];
+  bool reached[64];
   void init(int n, double t, const double* g) {
     nr = n;
     tol = t;
     gn = g;
-    for (int r = 0; r < nr; ++r) first[r] = -1;
+    for (int r = 0; r < nr; ++r) {
+      first[r] = -1;
+      tgt[r] = 0.0;
+      best[r] = mark[r] = std::numeric_limits<double>::infinity();
+      t_mark[r] = 0;
+      reached[r] = false;
+    }
+  }
+  // inner targets of one refinement step that starts at iteration `base`
+  // from true residual norms r0[]: reduction `red` (0: none)
+  void init_inner(double red, const double* r0, int base) {
+    for (int r = 0; r < nr; ++r) {
+      tgt[r] = red * r0[r];
+      best[r] = mark[r] = r0[r];
+      t_mark[r] = base;
+    }
   }
   // scan a group of `cnt` iterations that started at iteration `base`
   bool scan(const double* sc, int base, int cnt, double* worst_last) {
@@ -457,10 +483,17 @@ struct Tracker {
     double w = 0.0;
     for (int r = 0; r < nr; ++r) {
       const double* h = sc + (long)r * SC_COUNT + SC_HIST;
-      for (int it = 0; it < cnt && first[r] < 0; ++it) {
-        const double rel = std::sqrt(h[it]) / gn[r];
+      for (int it = 0; it < cnt; ++it) {
+        const double a = std::sqrt(h[it]);
+        const double rel = a / gn[r];
         if (!std::isfinite(rel)) bad = true;
-        if (rel <= tol) first[r] = base + it + 1;
+        if (first[r] < 0 && rel <= tol) first[r] = base + it + 1;
+        if (a <= tgt[r]) reached[r] = true;
+        if (a < best[r]) best[r] = a;
+        if (best[r] <= 0.5 * mark[r]) {
+          mark[r] = best[r];
+          t_mark[r] = base + it + 1;
+        }
       }
       const double last = std::sqrt(h[cnt - 1]) / gn[r];
       if (!std::isfinite(last)) bad = true;
@@ -469,6 +502,13 @@ struct Tracker {
     }
     *worst_last = w;
     return all;
+  }
+  // every right-hand side has converged, met its inner target, or stagnated
+  // (at iteration `now`)
+  bool inner_done(int now) const {
+    for (int r = 0; r < nr; ++r)
+      if (first[r] < 0 && !reached[r] && now - t_mark[r] < STAG_WINDOW) return false;
+    return true;
   }
   int iters() const {
     int m = 0;
@@ -492,6 +532,7 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, cons
   const long N = P->N;
   residual_norm(P, lam, g, mixed, nr);
   double rel = worst_rnorm(read_scalars(P, nr), nr, gn);
+  o.outer = 1;
   Tracker tr;
   tr.init(nr, tol, gn);
   int launched = 0;
@@ -521,21 +562,34 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, cons
   return o;
 }
 
-// Preconditioned CG.  FP64: Fletcher-Reeves beta.  Mixed (FP32 V-cycle, not
-// exactly symmetric): flexible Polak-Ribiere beta = (r.z - r.z_old) / rz_old.
-// r.z_old is accumulated in the update pass, while z still holds z_old.
-// nr right-hand sides iterate together, each with its own scalars; the
-// solve ends when every one has met the tolerance.
+// Preconditioned CG.  FP64: Fletcher-Reeves beta, one run to the tolerance
+// (then confirmed on the true residual).  Mixed: FP64 iterative refinement
+// around an FP32-preconditioned CG.  Each refinement step forms the true
+// residual r = g - A lambda in FP64, then runs CG on A delta = r with the
+// FP32 V-cycle as preconditioner, accumulating delta into lambda in FP64
+// (lambda += alpha p is lambda + delta), until every right-hand side has met
+// the tolerance, reduced its residual by refine_red against the step's true
+// residual, or stagnated; then the next step restarts from the new true
+// residual.  The inner CG takes the flexible Polak-Ribiere beta =
+// (r.z - r.z_old) / rz_old, since the FP32 cycle is not exactly the same
+// linear map at every application; r.z_old is accumulated in the update pass
+// while z still holds z_old.  nr right-hand sides iterate together, each
+// with its own scalars; the solve ends when every one has met the tolerance.
 SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, const double* gn, bool mixed, int nr) {
   SolveOut o;
   const long N = P->N;
+  const double red = mixed ? P->opts.refine_red : 0.0;
   Tracker tr;
   tr.init(nr, tol, gn);
   int launched = 0;
   for (;;) {
     residual_norm(P, lam, g, mixed, nr);
-    double rel = worst_rnorm(read_scalars(P, nr), nr, gn);
+    const double* sc0 = read_scalars(P, nr);
+    double rel = worst_rnorm(sc0, nr, gn);
+    double r0[64];
+    for (int r = 0; r < nr; ++r) r0[r] = std::sqrt(sc0[(long)r * SC_COUNT + SC_RNORM2]);
     o.relres = rel;
+    o.outer += 1;
     if (!std::isfinite(rel)) {
       o.status = HDG_ERR_BREAKDOWN;
       return o;
@@ -555,7 +609,8 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
     // groups of up to CHECK_EVERY with one read of the residual histories per
     // group; iterations past the first converged one only refine lambda.
     tr.init(nr, tol, gn);
-    bool done = false;
+    if (mixed) tr.init_inner(red, r0, launched);
+    bool all = false, done = false;
     while (!done && launched < P->opts.max_it) {
       const int grp = std::min(CHECK_EVERY, P->opts.max_it - launched);
       for (int r = 0; r < nr; ++r) blas_fill<double>(P->s.sc + (long)r * SC_COUNT + SC_HCNT, 0.0, 1, P->st);
@@ -599,7 +654,7 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
                 blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
             },
             nr);
-      done = tr.scan(read_scalars(P, nr), launched, grp, &rel);
+      all = tr.scan(read_scalars(P, nr), launched, grp, &rel);
       launched += grp;
       if (tr.bad) {
         o.relres = std::numeric_limits<double>::quiet_NaN();
@@ -607,9 +662,11 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
         o.iters = launched;
         return o;
       }
+      done = all || (mixed && tr.inner_done(launched));
     }
-    o.iters = done ? std::max(o.iters, tr.iters()) : launched;
-    // confirm with the true residual (loop again from the current iterate)
+    o.iters = all ? std::max(o.iters, tr.iters()) : launched;
+    // next refinement step, or confirmation of convergence, from the true
+    // residual of the current iterate
   }
   o.status = o.relres <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED;
   return o;
@@ -627,6 +684,7 @@ SolveOut solve_gmres(hdg_problem* P, const double* g, double* lam, double tol, d
     blas_dot(P->r, P->r, N, P->s, FIN_NORM_INV, sc + SC_HNORM, st);
     double beta = read_scalar(P, sc + SC_HNORM);
     o.relres = beta / gn;
+    o.outer += 1;
     if (!std::isfinite(beta)) {
       o.status = HDG_ERR_BREAKDOWN;
       return o;
@@ -698,15 +756,13 @@ hdg_status solve_many(hdg_problem* P, int nr, double tol, hdg_solve_info* info) 
   switch (P->opts.method) {
     case HDG_METHOD_PCG: o = solve_pcg(P, P->g, P->lam, tol, gn, mixed, nr); break;
     case HDG_METHOD_GMRES: {
+      // one right-hand side after another, each in its own rows of g and
+      // lambda (the Krylov basis and the preconditioner's vectors are shared)
       hdg_status worst = HDG_OK;
       for (int r = 0; r < nr; ++r) {
-        if (r > 0) {  // GMRES works on the first right-hand side's buffers
-          blas_copy(P->g, P->g + r * N, N, P->st);
-          blas_copy(P->lam, P->lam + r * N, N, P->st);
-        }
-        SolveOut q = solve_gmres(P, P->g, P->lam, tol, gn[r], mixed);
-        if (r > 0) blas_copy(P->lam + r * N, P->lam, N, P->st);
+        SolveOut q = solve_gmres(P, P->g + r * N, P->lam + r * N, tol, gn[r], mixed);
         o.iters = std::max(o.iters, q.iters);
+        o.outer = std::max(o.outer, q.outer);
         o.relres = std::max(o.relres, q.relres);
         if (q.status != HDG_OK && worst == HDG_OK) worst = q.status;
       }
@@ -717,6 +773,7 @@ hdg_status solve_many(hdg_problem* P, int nr, double tol, hdg_solve_info* info) 
   }
   if (info) {
     info->iters += o.iters;
+    info->outer_iters += o.outer;
     info->relres = std::max(info->relres, o.relres);
   }
   return o.status;
@@ -752,6 +809,8 @@ void hdg_default_opts(hdg_mg_opts* o) {
   o->restart = 0;
   o->coarse_n = 2;
   o->nrhs = 1;
+  o->refine_red = 1e-5;
+  o->variant = 0;
 }
 
 const char* hdg_status_string(hdg_status s) {
@@ -795,11 +854,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->tau = tau;
   P->st = (hipStream_t)hip_stream;
   P->store_recovery = store_recovery != 0;
-  P->use_graphs = std::getenv("HDG_NO_GRAPH") == nullptr;
-  P->fuse = std::getenv("HDG_NO_FUSE") == nullptr;
-  if (const char* tn = std::getenv("HDG_TAIL_N")) P->tail_nmax = std::atoi(tn);
-  if (const char* np = std::getenv("HDG_NO_PACK")) P->pack = std::atoi(np) == 0;
-  if (const char* ns = std::getenv("HDG_NO_STRIP")) P->strip = std::atoi(ns) == 0;
+  const auto t0 = std::chrono::steady_clock::now();
   HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
   P->nv = P->ref.nv;
@@ -833,6 +888,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   }
   form_elements(P);
   HDG_CHECK(hipStreamSynchronize(P->st));
+  P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   hdg_default_opts(&P->opts);
   *out = P;
   return HDG_OK;
@@ -851,10 +907,12 @@ hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
   if (!P || !kappa) return HDG_ERR_INVALID_ARG;
   if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
   HDG_GUARD_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
   if (!check_kappa(P, kappa, kappa_kind)) return HDG_ERR_INVALID_ARG;
   free_build(P);
   form_elements(P);
   HDG_CHECK(hipStreamSynchronize(P->st));
+  P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
   HDG_GUARD_END
 }
@@ -869,15 +927,22 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
       o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
-      o.nrhs > HDG_MAX_NRHS)
+      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 31)
     return HDG_ERR_INVALID_ARG;
   if (o.nrhs < 1) o.nrhs = 1;
+  if (o.refine_red == 0.0) o.refine_red = 1e-5;
   if (o.coarse_n < 2) o.coarse_n = 2;
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
   free_build(P);
   P->opts = o;
   P->cap = o.nrhs;
+  P->use_graphs = !(o.variant & HDG_VARIANT_NO_GRAPH);
+  P->fuse = !(o.variant & HDG_VARIANT_NO_FUSE);
+  P->tail_nmax = (o.variant & HDG_VARIANT_NO_TAIL) ? 0 : 32;
+  P->pack = !(o.variant & HDG_VARIANT_NO_PACK);
+  P->strip = !(o.variant & HDG_VARIANT_NO_STRIP);
   const int cap = P->cap;
   const int d = P->d;
   const int nc = 1 << (d - 1);
@@ -1038,6 +1103,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   }
   HDG_CHECK(hipStreamSynchronize(P->st));
   P->built = true;
+  P->t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
   HDG_GUARD_END
 }
@@ -1073,9 +1139,12 @@ hdg_status solve_rhs_set(hdg_handle P, const double* rhs, int rhs_kind, const do
                          double* lambda, hdg_solve_info* info) {
   if (info) {
     info->iters = 0;
+    info->outer_iters = 0;
     info->relres = 0.0;
     info->t_solve_ms = 0.0;
     info->n_levels = (int)P->L.size();
+    info->t_setup_ms = P->t_setup_ms;
+    info->t_build_ms = P->t_build_ms;
   }
   hipEvent_t e0, e1;
   HDG_CHECK(hipEventCreate(&e0));
@@ -1267,9 +1336,12 @@ hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, do
   }
   if (info) {
     info->iters = 0;
+    info->outer_iters = 0;
     info->relres = 0.0;
     info->t_solve_ms = 0.0;
     info->n_levels = (int)P->L.size();
+    info->t_setup_ms = P->t_setup_ms;
+    info->t_build_ms = P->t_build_ms;
   }
   form_rhs(P, dJdu, HDG_RHS_F_LOAD, nullptr, P->g);
   blas_fill<double>(P->lam, 0.0, P->N, P->st);

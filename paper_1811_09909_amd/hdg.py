@@ -45,6 +45,7 @@ class Problem:
         self.nv = self.query(L.Q_NV)
         self.nq = self.query(L.Q_NQ)
         self.built = False
+        self.version = 0  # bumped by every update_kappa / build: operator state of the handle
 
     # -- lifecycle ---------------------------------------------------------
     def close(self):
@@ -66,12 +67,15 @@ class Problem:
     def update_kappa(self, kappa):
         kap = _dev(kappa, torch.float64, self.device)
         L.check(self.lib.hdg_update_kappa(self.h, _vp(kap), self.kind), "hdg_update_kappa")
+        self.version += 1
         self.built = False
 
     def build(self, sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-              max_it=200, restart=0, coarse_n=2, nrhs=1):
-        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n, nrhs)
+              max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0):
+        o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n, nrhs,
+                   refine_red, variant)
         L.check(self.lib.hdg_mg_build(self.h, ctypes.byref(o)), "hdg_mg_build")
+        self.version += 1
         self.built = True
         self.opts = o
         self.n_levels = self.query(L.Q_NLEVELS)
@@ -97,22 +101,21 @@ class Problem:
         allow = (L.HDG_ERR_NOT_CONVERGED,) if allow_not_converged else ()
         st = L.check(self.lib.hdg_solve(self.h, _vp(rhs), kind, _vp(gd), nrhs, float(tol), _vp(lam),
                                         ctypes.byref(info)), "hdg_solve", allow)
-        return lam, {"iters": info.iters, "relres": info.relres, "t_solve_ms": info.t_solve_ms,
-                     "n_levels": info.n_levels, "status": st}
+        return lam, dict(info.as_dict(), status=st)
 
     def autotune(self, nrhs, **base):
         """Pick the fastest coarsest grid and right-hand-side group size for
         `nrhs` right-hand sides on top of the build options `base` (see
         hdg_autotune); leaves the handle built with them."""
         defaults = dict(sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-                        max_it=200, restart=0, coarse_n=2, nrhs=1)
+                        max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0)
         defaults.update(base)
-        o = L.Opts(*[defaults[k] for k in ("sweeps", "growth", "omega", "local_corr", "precision", "method",
-                                            "max_it", "restart", "coarse_n", "nrhs")])
+        o = L.Opts(*[defaults[k] for k in L.OPT_FIELDS])
         best = L.Opts()
         us = ctypes.c_double()
         L.check(self.lib.hdg_autotune(self.h, ctypes.byref(o), int(nrhs), ctypes.byref(best), ctypes.byref(us)),
                 "hdg_autotune")
+        self.version += 1
         self.built = True
         self.opts = best
         self.n_levels = self.query(L.Q_NLEVELS)
@@ -143,7 +146,7 @@ class Problem:
         info = L.Info()
         L.check(self.lib.hdg_adjoint(self.h, _vp(j), _vp(q), float(tol), _vp(grad), ctypes.byref(info)),
                 "hdg_adjoint")
-        return grad, {"iters": info.iters, "relres": info.relres}
+        return grad, info.as_dict()
 
     def mass_apply(self, u):
         u = _dev(u, torch.float64, self.device)
@@ -231,7 +234,7 @@ def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=4):
     lib = problems[0].lib
     L.check(lib.hdg_solve_batch(n, handles, rp, kind, nrh, float(tol), lp, infos, int(nstreams)), "hdg_solve_batch")
     out = [x.reshape(k, -1) for x, k in zip(lam, nr)]
-    return out, [{"iters": i.iters, "relres": i.relres, "t_solve_ms": i.t_solve_ms} for i in infos]
+    return out, [i.as_dict() for i in infos]
 
 
 class HDGMass(torch.autograd.Function):
@@ -252,7 +255,10 @@ class HDGSolve(torch.autograd.Function):
     """U(theta): nodal u of the HDG solution for kappa_T = exp(theta_T).
 
     backward uses the library's adjoint solve (same operator and V-cycle)
-    and returns dL/dtheta = -(q*)^T A_T q per element."""
+    and returns dL/dtheta = -(q*)^T A_T q per element.  The adjoint needs the
+    handle's operator at this theta: if the handle was changed after this
+    forward pass (another forward at another theta, a rebuild), backward
+    re-forms the operator at the saved theta and re-solves first."""
 
     @staticmethod
     def forward(ctx, theta, problem, f, tol, build_kw):  # noqa: D102
@@ -260,12 +266,20 @@ class HDGSolve(torch.autograd.Function):
         problem.build(**build_kw)
         lam, info = problem.solve(f, tol=tol)
         u, q = problem.reconstruct(lam, f)
-        ctx.problem, ctx.tol = problem, tol
-        ctx.save_for_backward(q)
+        ctx.problem, ctx.tol, ctx.f, ctx.build_kw = problem, tol, f, build_kw
+        ctx.version = problem.version
+        ctx.save_for_backward(q, theta.detach())
         return u
 
     @staticmethod
     def backward(ctx, gu):
-        (q,) = ctx.saved_tensors
-        grad, _ = ctx.problem.adjoint(gu.contiguous(), q, ctx.tol)
+        q, theta = ctx.saved_tensors
+        P = ctx.problem
+        if P.version != ctx.version:
+            P.update_kappa(torch.exp(theta))
+            P.build(**ctx.build_kw)
+            lam, _ = P.solve(ctx.f, tol=ctx.tol)
+            _, q = P.reconstruct(lam, ctx.f)
+            ctx.version = P.version
+        grad, _ = P.adjoint(gu.contiguous(), q, ctx.tol)
         return grad, None, None, None, None

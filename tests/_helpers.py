@@ -55,3 +55,28 @@ def ge_solve_longdouble(A, B):
     for k in range(n - 1, -1, -1):
         X[k] = (B[k] - A[k, k + 1:] @ X[k + 1:]) / A[k, k]
     return X
+
+
+def rowerr(a, b, scale):
+    """Largest entrywise difference |a - b| measured against a per-entry
+    scale (e.g. (|A| |x|)_i for a product A x): what a normwise error hides
+    on entries much smaller than the vector's norm."""
+    a, b, s = np.asarray(a).ravel(), np.asarray(b).ravel(), np.asarray(scale).ravel()
+    d = np.abs(a - b)
+    tiny = np.finfo(float).tiny
+    return float(np.max(d / np.maximum(s, tiny))) if d.size else 0.0
+
+
+def load_scale(O, f, lam_b=None):
+    """Per trace DOF, the sum of the magnitudes of the terms that make up g:
+    sum_T |b^e_T| + |A^e_{T,I bnd}| |lambda_bnd| (the entrywise scale of g)."""
+    sc = np.zeros(O.nlam)
+    for T in range(O.mesh.nel):
+        Ae, be = O.element_dtn(T, O.M @ np.asarray(f[T]))
+        gi, bi = O.gmap[T], O.bmap[T]
+        ii = np.nonzero(gi >= 0)[0]
+        jb = np.nonzero(bi >= 0)[0]
+        np.add.at(sc, gi[ii], np.abs(be[ii]))
+        if lam_b is not None and len(jb):
+            np.add.at(sc, gi[ii], np.abs(Ae[np.ix_(ii, jb)]) @ np.abs(lam_b[bi[jb]]))
+    return sc

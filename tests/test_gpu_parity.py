@@ -4,13 +4,15 @@ Operators on identical inputs: element DtN matrices, load vectors, trace
 apply (FP64 and FP32), every coarse operator of the hierarchy, block-Jacobi
 sweeps, one V-cycle; then iterates at fixed iteration counts, converged
 solutions, local recovery and the adjoint gradient.  Meshes span several
-64-face tiles with ragged tails.  Tolerances: 1e-12 (FP64 operators),
-FP64 parity bound 1e-10 relative for every operator, iterate and recovered
-field (kappa spans six decades, so the two codes' rounding differs by up to
-~1e-11 after the local Schur complements); FP32 operators 2e-6.  Converged
-solutions: each code's own residual meets the tolerance, and the oracle's
-residual of the GPU iterate exceeds it by at most twice the measured
-operator difference ||(A_gpu - A_oracle) lambda|| / ||g||.
+64-face tiles with ragged tails.  Tolerances: 1e-12 for every FP64
+operator on the finest two levels (element maps, load, apply, smoother,
+reconstruction), normwise and entrywise against the magnitude of the terms
+that make up each entry ((|A| |x|)_i for a product), so that entries far
+below the vector's norm (kappa spans six decades) are checked too; coarser
+levels carry a bound derived from their Schur complements (see
+test_hierarchy_operators_and_smoother).  FP32 operators: 1e-6.  Converged
+solutions: each code's own residual meets the tolerance, and the traces
+agree with the oracle's direct solve within what the two residuals allow.
 """
 import sys
 
@@ -23,7 +25,7 @@ from oracle import mg as omg
 from oracle.hdg import HDG
 from paper_1811_09909_amd import inputs
 
-from ._helpers import assemble, relerr
+from ._helpers import assemble, load_scale, relerr, rowerr
 
 pytestmark = pytest.mark.gpu
 
@@ -71,8 +73,9 @@ def test_element_dtn_matrices(torch_cuda, d, n, k, kind):
     Ae = P.level_export(0).cpu().numpy()
     Ao = O.all_element_dtn()
     worst = max(relerr(Ae[T], Ao[T]) for T in range(n ** d))
-    say(f"  worst element relerr {worst:.2e}")
-    assert worst <= 1e-10
+    ent = max(np.abs(Ae[T] - Ao[T]).max() / np.abs(Ao[T]).max() for T in range(n ** d))
+    say(f"  worst element relerr {worst:.2e}, entrywise / max entry {ent:.2e}")
+    assert worst <= 1e-12 and ent <= 1e-12
 
 
 @pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 9, 3), (3, 3, 2)])
@@ -87,14 +90,16 @@ def test_rhs_with_dirichlet_data(torch_cuda, d, n, k):
     A, g, lb = O.assemble(f, gD)
     P = _gpu(torch_cuda, d, n, k, kap)
     gg = P.rhs(torch_cuda.as_tensor(f), gdir=torch_cuda.as_tensor(lb)).cpu().numpy()
-    say(f"  relerr {relerr(gg, g):.2e}")
-    assert relerr(gg, g) <= 1e-10
+    sc = load_scale(O, f, lb)
+    say(f"  relerr {relerr(gg, g):.2e} entrywise {rowerr(gg, g, sc):.2e}")
+    assert relerr(gg, g) <= 1e-12 and rowerr(gg, g, sc) <= 1e-12
     # load form: b_T given directly
     _, g2, _ = O.assemble(f)
     b = f @ O.M.T
     gl = P.rhs(torch_cuda.as_tensor(b), kind=1).cpu().numpy()
-    say(f"  load-form relerr {relerr(gl, g2):.2e}")
-    assert relerr(gl, g2) <= 1e-10
+    sc2 = load_scale(O, f)
+    say(f"  load-form relerr {relerr(gl, g2):.2e} entrywise {rowerr(gl, g2, sc2):.2e}")
+    assert relerr(gl, g2) <= 1e-12 and rowerr(gl, g2, sc2) <= 1e-12
 
 
 @pytest.mark.parametrize("d,n,k", [(2, 8, 1), (2, 16, 2), (2, 16, 4), (2, 4, 6), (3, 4, 1), (3, 4, 3)])
@@ -106,12 +111,13 @@ def test_trace_apply_fp64_fp32(torch_cuda, d, n, k):
     P = _gpu(torch_cuda, d, n, k, kap)
     P.build()
     x = rng.standard_normal(A.shape[0])
+    sc = abs(A) @ np.abs(x)
     y = P.level_apply(0, torch_cuda.as_tensor(x)).cpu().numpy()
-    say(f"  fp64 relerr {relerr(y, A @ x):.2e}")
-    assert relerr(y, A @ x) <= 1e-10
+    say(f"  fp64 relerr {relerr(y, A @ x):.2e} entrywise {rowerr(y, A @ x, sc):.2e}")
+    assert relerr(y, A @ x) <= 1e-12 and rowerr(y, A @ x, sc) <= 1e-12
     y32 = P.level_apply(0, torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=1).cpu().numpy()
-    say(f"  fp32 relerr {relerr(y32, A @ x):.2e}")
-    assert relerr(y32, A @ x) <= 2e-6
+    say(f"  fp32 relerr {relerr(y32, A @ x):.2e} entrywise {rowerr(y32, A @ x, sc):.2e}")
+    assert relerr(y32, A @ x) <= 1e-6 and rowerr(y32, A @ x, sc) <= 1e-6
 
 
 @pytest.mark.parametrize("d,n,k", [(2, 8, 2), (2, 16, 1), (2, 16, 3), (3, 4, 2), (3, 8, 1)])
@@ -125,12 +131,14 @@ def test_hierarchy_operators_and_smoother(torch_cuda, d, n, k):
     P.build()
     assert P.n_levels == len(H.levels)
     assert P.level_sizes() == [L.A.shape[0] for L in H.levels]
-    # Each h-coarsening is a Schur complement whose local condition number
-    # (up to ~1e3 at six decades of kappa) multiplies the rounding
-    # difference of the two codes: 1e-10 down to two coarsenings below the
-    # finest P1 level, 1e-9 below that (measured: 1.05e-10 three levels down).
+    # Each h-coarsening is a Schur complement A_BB - A_BI A_II^-1 A_IB whose
+    # local condition number (up to ~1e3 at six decades of kappa) multiplies
+    # the rounding difference of the two codes.  The finest level and the P1
+    # level (a Galerkin product J^T A J, no inverse) stay at 1e-12; level l
+    # >= 2 is l - 1 Schur complements down and gets 1e-12 * 10^(l - 1) * 10,
+    # capped at 1e-9.
     def bound(lvl):
-        return 1e-10 if lvl <= 2 else 1e-9
+        return 1e-12 if lvl <= 1 else min(1e-9, 1e-12 * 10.0 ** lvl)
     for lvl in range(1, P.n_levels):
         Lo = H.levels[lvl]
         Ag = assemble(P.level_export(lvl).cpu().numpy(), d, Lo.mesh.n, Lo.m)
@@ -141,8 +149,9 @@ def test_hierarchy_operators_and_smoother(torch_cuda, d, n, k):
         Lo = H.levels[lvl]
         x = rng.standard_normal(Lo.A.shape[0])
         y = P.level_apply(lvl, torch_cuda.as_tensor(x)).cpu().numpy()
-        say(f"  level {lvl} apply err {relerr(y, Lo.A @ x):.2e}")
-        assert relerr(y, Lo.A @ x) <= bound(lvl)
+        sc = abs(Lo.A) @ np.abs(x)
+        say(f"  level {lvl} apply err {relerr(y, Lo.A @ x):.2e} entrywise {rowerr(y, Lo.A @ x, sc):.2e}")
+        assert relerr(y, Lo.A @ x) <= bound(lvl) and rowerr(y, Lo.A @ x, sc) <= bound(lvl)
         # the smoother against the oracle's block Jacobi on the GPU's own
         # level operator (the operator itself is compared above)
         Ag = Lo.A if lvl == 0 else assemble(P.level_export(lvl).cpu().numpy(), d, Lo.mesh.n, Lo.m)
@@ -152,7 +161,7 @@ def test_hierarchy_operators_and_smoother(torch_cuda, d, n, k):
             eo = omg.block_jacobi(Lg, x, m)
             say(f"  level {lvl} smoother m={m} err {relerr(e, eo):.2e} "
                 f"(vs oracle operator {relerr(e, H.block_jacobi(lvl, x, m)):.2e})")
-            assert relerr(e, eo) <= 1e-10
+            assert relerr(e, eo) <= 1e-12
 
 
 @pytest.mark.parametrize("d,n,k,lc,sweeps,growth", [(2, 8, 2, "pre", 2, 1), (2, 16, 3, "both", 2, 1),
@@ -170,29 +179,31 @@ def test_vcycle(torch_cuda, d, n, k, lc, sweeps, growth):
     r = rng.standard_normal(A.shape[0])
     eo = H.vcycle(r)
     e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
-    say(f"  fp64 relerr {relerr(e, eo):.2e}")
-    assert relerr(e, eo) <= 1e-10
+    # the cycle reaches every level: the bound of its deepest coarse
+    # operator (test_hierarchy_operators_and_smoother), never above 1e-10
+    nlev = len(H.levels)
+    b64 = min(1e-10, 1e-12 * 10.0 ** max(nlev - 2, 0))
+    say(f"  {nlev} levels: fp64 relerr {relerr(e, eo):.2e} (bound {b64:.0e})")
+    assert relerr(e, eo) <= b64
     e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy()
     say(f"  fp32 relerr {relerr(e32, eo):.2e}")
     assert relerr(e32, eo) <= 1e-3
 
 
-def _set_path(monkeypatch, path):
-    monkeypatch.delenv("HDG_TAIL_N", raising=False)
-    monkeypatch.delenv("HDG_NO_FUSE", raising=False)
-    if path == "fused":
-        monkeypatch.setenv("HDG_TAIL_N", "0")
-    if path == "unfused":
-        monkeypatch.setenv("HDG_NO_FUSE", "1")
+def _variant(path):
+    """hdg_mg_opts.variant of a V-cycle orchestration: the one-workgroup coarse
+    tail (default), fused transition kernels without the tail, unfused kernels."""
+    from paper_1811_09909_amd import _lib as L
+    return {"tail": 0, "fused": L.VARIANT_NO_TAIL, "unfused": L.VARIANT_NO_FUSE}[path]
 
 
 @pytest.mark.parametrize("path", ["tail", "fused", "unfused"])
 @pytest.mark.parametrize("d,n,k,lc", [(2, 32, 2, "both"), (2, 64, 1, "pre"), (2, 16, 3, "none")])
-def test_vcycle_orchestration_paths(torch_cuda, monkeypatch, path, d, n, k, lc):
+def test_vcycle_orchestration_paths(torch_cuda, path, d, n, k, lc):
     """The three V-cycle orchestrations (one-workgroup coarse tail, fused
     transition kernels, unfused kernels) against the oracle's Algorithm 1
     (kappa over two decades, so deep hierarchies stay inside 1e-10)."""
-    _set_path(monkeypatch, path)
+    var = _variant(path)
     say(f"[vcycle path={path}] d={d} n={n} k={k} lc={lc}")
     kap, rng = _kappa(d, n, 1e-1, 1e1)
     O = HDG(d, n, k, 1.0, kap)
@@ -200,7 +211,7 @@ def test_vcycle_orchestration_paths(torch_cuda, monkeypatch, path, d, n, k, lc):
     for sweeps, growth in [(2, 1), (1, 2)]:
         H = omg.Hierarchy(A, d, n, k, sweeps=sweeps, growth=growth, local_corr=LC[lc])
         P = _gpu(torch_cuda, d, n, k, kap)
-        P.build(sweeps=sweeps, growth=growth, local_corr=LC[lc])
+        P.build(sweeps=sweeps, growth=growth, local_corr=LC[lc], variant=var)
         r = rng.standard_normal(A.shape[0])
         eo = H.vcycle(r)
         e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
@@ -211,16 +222,16 @@ def test_vcycle_orchestration_paths(torch_cuda, monkeypatch, path, d, n, k, lc):
 
 
 @pytest.mark.parametrize("n,k,lc", [(64, 1, "pre"), (128, 2, "both")])
-def test_vcycle_paths_agree_at_high_contrast(torch_cuda, monkeypatch, n, k, lc):
+def test_vcycle_paths_agree_at_high_contrast(torch_cuda, n, k, lc):
     """At six decades of kappa the three orchestrations compute the same
     cycle on the same operators: they agree far below the oracle bound."""
     kap, rng = _kappa(2, n)
     r = None
     outs = {}
     for path in ["unfused", "fused", "tail"]:
-        _set_path(monkeypatch, path)
+        var = _variant(path)
         P = _gpu(torch_cuda, 2, n, k, kap)
-        P.build(sweeps=2, local_corr=LC[lc])
+        P.build(sweeps=2, local_corr=LC[lc], variant=var)
         if r is None:
             r = rng.standard_normal(P.nlam)
         outs[path] = (P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy(),
@@ -235,18 +246,18 @@ def test_vcycle_paths_agree_at_high_contrast(torch_cuda, monkeypatch, n, k, lc):
 @pytest.mark.parametrize("path", ["fused", "unfused"])
 @pytest.mark.parametrize("d,n,k,cn,lc", [(2, 32, 2, 8, "pre"), (2, 64, 1, 16, "both"), (3, 8, 2, 4, "pre"),
                                          (2, 16, 3, 16, "none")])
-def test_vcycle_larger_coarsest_level(torch_cuda, monkeypatch, path, d, n, k, cn, lc):
+def test_vcycle_larger_coarsest_level(torch_cuda, path, d, n, k, cn, lc):
     """Coarsening stopped at an n = cn macro grid whose operator (hundreds of
     unknowns) is inverted densely on the device, against the oracle's
     Algorithm 1 with the same number of levels."""
-    _set_path(monkeypatch, path)
+    var = _variant(path)
     say(f"[vcycle coarse_n={cn} path={path}] d={d} n={n} k={k} lc={lc}")
     kap, rng = _kappa(d, n, 1e-1, 1e1)
     O = HDG(d, n, k, 1.0, kap)
     A, _, _ = O.assemble()
     H = omg.Hierarchy(A, d, n, k, sweeps=2, local_corr=LC[lc], coarsest_n=cn)
     P = _gpu(torch_cuda, d, n, k, kap)
-    P.build(sweeps=2, local_corr=LC[lc], coarse_n=cn)
+    P.build(sweeps=2, local_corr=LC[lc], coarse_n=cn, variant=var)
     assert P.level_sizes() == [L.A.shape[0] for L in H.levels]
     r = rng.standard_normal(A.shape[0])
     eo = H.vcycle(r)
@@ -258,19 +269,20 @@ def test_vcycle_larger_coarsest_level(torch_cuda, monkeypatch, path, d, n, k, cn
 
 
 @pytest.mark.parametrize("k", [2, 4, 6])
-def test_packed_element_major_matches_face_major(torch_cuda, monkeypatch, k):
+def test_packed_element_major_matches_face_major(torch_cuda, k):
     """The finest p-level stored element-major (packed symmetric triangles,
     two-phase apply) and face-major give the same apply, smoother, residual
     restriction and V-cycle up to rounding, and the oracle's apply."""
+    from paper_1811_09909_amd import _lib as L
     kap, rng = _kappa(2, 32)
     O = HDG(2, 32, k, 1.0, kap)
     A, _, _ = O.assemble()
     x = rng.standard_normal(A.shape[0])
     out = {}
     for pack in ("1", "0"):
-        monkeypatch.setenv("HDG_NO_PACK", "0" if pack == "1" else "1")
+        var = 0 if pack == "1" else L.VARIANT_NO_PACK
         P = _gpu(torch_cuda, 2, 32, k, kap)
-        P.build(local_corr=omg.LC_BOTH)
+        P.build(local_corr=omg.LC_BOTH, variant=var)
         xt = torch_cuda.as_tensor(x)
         out[pack] = (P.level_apply(0, xt).cpu().numpy(),
                      P.level_apply(0, xt.float(), precision=1).cpu().numpy(),
@@ -288,7 +300,7 @@ def test_packed_element_major_matches_face_major(torch_cuda, monkeypatch, k):
 
 
 @pytest.mark.parametrize("n,k", [(64, 2), (64, 4), (64, 6), (128, 3)])
-def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
+def test_strip_apply_matches_two_phase(torch_cuda, n, k):
     """The one-pass strip apply (element products kept in LDS, faces on strip
     edges finished by a second kernel) adds the same two element products in
     the same order as the two-phase apply: apply, sweeps, the residual
@@ -306,9 +318,9 @@ def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
     f = rng.standard_normal((n * n, O.nv))
     out, sol = {}, {}
     for strip in ("1", "0"):
-        monkeypatch.setenv("HDG_NO_STRIP", "0" if strip == "1" else "1")
+        var = 0 if strip == "1" else L.VARIANT_NO_STRIP
         P = _gpu(torch_cuda, 2, n, k, kap)
-        P.build(local_corr=omg.LC_BOTH, nrhs=3)
+        P.build(local_corr=omg.LC_BOTH, nrhs=3, variant=var)
         xt = torch_cuda.as_tensor(x)
         X3t = torch_cuda.as_tensor(X3)
         out[strip] = [P.level_apply(0, xt).cpu().numpy(),
@@ -319,7 +331,7 @@ def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
                       P.vcycle(xt.float(), precision=1).cpu().numpy(),
                       P.vcycle(X3t).cpu().numpy(),
                       P.vcycle(X3t.float(), precision=1).cpu().numpy()]
-        P.build(local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=500)
+        P.build(local_corr=omg.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, max_it=500, variant=var)
         sol[strip] = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
     names = ["apply fp64", "apply fp32", "3 sweeps fp64", "3 sweeps fp32", "vcycle fp64", "vcycle fp32",
              "vcycle fp64 x3", "vcycle fp32 x3"]
@@ -337,7 +349,7 @@ def test_strip_apply_matches_two_phase(torch_cuda, monkeypatch, n, k):
     assert e <= 1e-8
 
 
-def test_strip_apply_sixteen_rhs_matches_two_phase(torch_cuda, monkeypatch):
+def test_strip_apply_sixteen_rhs_matches_two_phase(torch_cuda):
     """Sixteen right-hand sides in one strip launch (the batched workload's
     group size; workgroups of one strip for every right-hand side share its
     maps through the XCD's L2) give the two-phase V-cycle bit for bit."""
@@ -346,9 +358,9 @@ def test_strip_apply_sixteen_rhs_matches_two_phase(torch_cuda, monkeypatch):
     kap, rng = _kappa(2, n, 1e-2, 1e2)
     out = {}
     for strip in ("1", "0"):
-        monkeypatch.setenv("HDG_NO_STRIP", "0" if strip == "1" else "1")
+        var = 0 if strip == "1" else L.VARIANT_NO_STRIP
         P = _gpu(torch_cuda, 2, n, k, kap)
-        P.build(local_corr=omg.LC_BOTH, nrhs=nr)
+        P.build(local_corr=omg.LC_BOTH, nrhs=nr, variant=var)
         R = torch_cuda.as_tensor(np.random.default_rng(11).standard_normal(nr * P.nlam))
         out[strip] = (P.vcycle(R).cpu().numpy(), P.vcycle(R.float(), precision=L.FP32).cpu().numpy())
     for i, nm in enumerate(("fp64", "fp32")):
@@ -386,13 +398,21 @@ def test_iterates_at_fixed_count(torch_cuda, method):
 
 @pytest.mark.parametrize("method,prec", [("mg", 0), ("pcg", 0), ("gmres", 0), ("mg", 1), ("pcg", 1), ("gmres", 1)])
 def test_converged_solution(torch_cuda, method, prec):
+    """Solves to 1e-10 and 1e-12 against the oracle's direct solve, kappa
+    over four decades.  The oracle recomputes each GPU iterate's residual
+    (<= tol up to the measured operator difference); the trace differs from
+    the direct solution by A^-1 (g - A lambda), so |lambda - lambda_direct|
+    is held to the norms of A^-1 applied to both residuals (the oracle's LU)
+    and to the targets 1e-10 (FP64) / 1e-9 (mixed) relative."""
     d, n, k = 2, 32, 3
     say(f"[converged] {method} precision={prec}")
-    kap, rng = _kappa(d, n, 1e-1, 1e1)
+    kap, rng = _kappa(d, n, 1e-2, 1e2)
     O = HDG(d, n, k, 1.0, kap)
     f = rng.standard_normal((n * n, O.nv))
     A, g, _ = O.assemble(f)
-    lam_ref = spla.spsolve(A.tocsc(), g)
+    lu = spla.splu(A.tocsc())
+    lam_ref = lu.solve(g)
+    e_ref = np.linalg.norm(lu.solve(g - A @ lam_ref))
     mid = {"mg": 0, "pcg": 1, "gmres": 2}[method]
     lc = omg.LC_BOTH if method == "pcg" else omg.LC_PRE
     P = _gpu(torch_cuda, d, n, k, kap)
@@ -403,11 +423,15 @@ def test_converged_solution(torch_cuda, method, prec):
         lam = lam.cpu().numpy()
         rel = np.linalg.norm(g - A @ lam) / np.linalg.norm(g)
         delta = np.linalg.norm(P.level_apply(0, lam_g).cpu().numpy() - A @ lam) / np.linalg.norm(g)
-        say(f"  tol={tol:.0e} iters={info['iters']} gpu relres={info['relres']:.2e} oracle relres={rel:.2e} "
-            f"operator diff={delta:.2e} err vs direct={relerr(lam, lam_ref):.2e}")
+        err = relerr(lam, lam_ref)
+        bound = 1.5 * (np.linalg.norm(lu.solve(g - A @ lam)) + e_ref) / np.linalg.norm(lam_ref) + 1e-14
+        say(f"  tol={tol:.0e} iters={info['iters']} refinement steps={info['outer_iters']} "
+            f"gpu relres={info['relres']:.2e} oracle relres={rel:.2e} operator diff={delta:.2e} "
+            f"err vs direct={err:.2e} (bound from the residuals {bound:.2e})")
         assert info["relres"] <= tol
         assert rel <= tol + 2 * delta + 1e-14
-        assert relerr(lam, lam_ref) <= 1e4 * tol
+        assert err <= bound
+        assert err <= (1e-10 if prec == 0 else 1e-9)
 
 
 def test_iteration_counts_match_oracle(torch_cuda):
@@ -431,20 +455,20 @@ def test_iteration_counts_match_oracle(torch_cuda):
 
 @pytest.mark.parametrize("d,n,k,path", [(2, 32, 3, "tail"), (2, 16, 2, "unfused"), (3, 4, 2, "unfused"),
                                         (2, 64, 4, "fused")])
-def test_several_rhs_vcycle_is_per_rhs_cycle(torch_cuda, monkeypatch, d, n, k, path):
+def test_several_rhs_vcycle_is_per_rhs_cycle(torch_cuda, d, n, k, path):
     """A V-cycle over several right-hand sides at once (one launch per
     kernel for all of them) equals the single-right-hand-side cycles bit for
     bit, with groups of the build's capacity (5 and 2 for 5 vectors)."""
     from paper_1811_09909_amd import _lib as L
-    _set_path(monkeypatch, path)
+    var = _variant(path)
     kap, rng = _kappa(d, n, 1e-2, 1e2)
     P = _gpu(torch_cuda, d, n, k, kap)
     R = rng.standard_normal((5, P.nlam))
-    P.build(local_corr=omg.LC_BOTH)
+    P.build(local_corr=omg.LC_BOTH, variant=var)
     single = {pr: [P.vcycle(torch_cuda.as_tensor(R[i], dtype=dt), precision=pr).cpu().numpy() for i in range(5)]
               for pr, dt in [(L.FP64, torch_cuda.float64), (L.FP32, torch_cuda.float32)]}
     for cap in (5, 2):
-        P.build(local_corr=omg.LC_BOTH, nrhs=cap)
+        P.build(local_corr=omg.LC_BOTH, nrhs=cap, variant=var)
         for pr, dt in [(L.FP64, torch_cuda.float64), (L.FP32, torch_cuda.float32)]:
             E = P.vcycle(torch_cuda.as_tensor(R.ravel(), dtype=dt), precision=pr).cpu().numpy().reshape(5, -1)
             diff = max(np.abs(E[i] - single[pr][i]).max() for i in range(5))
@@ -581,8 +605,8 @@ def test_reconstruction(torch_cuda, d, n, k):
     P = _gpu(torch_cuda, d, n, k, kap)
     u, q = P.reconstruct(torch_cuda.as_tensor(lam), torch_cuda.as_tensor(f))
     say(f"  u {relerr(u.cpu().numpy(), uo):.2e} q {relerr(q.cpu().numpy(), qo):.2e}")
-    assert relerr(u.cpu().numpy(), uo) <= 1e-10
-    assert relerr(q.cpu().numpy(), qo) <= 1e-10
+    assert relerr(u.cpu().numpy(), uo) <= 1e-12
+    assert relerr(q.cpu().numpy(), qo) <= 1e-12
 
 
 def test_manufactured_solution_end_to_end(torch_cuda):

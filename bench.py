@@ -198,6 +198,7 @@ def batched(args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     dofs = sum(P.nlam * 16 for P in Ps)
+    progress(f"batched: {len(Ps)} problems set up and tuned in {t_setup:.1f} s")
     # warm-up: captures every handle's iteration graphs
     solve_batch(Ps, rhs, tol=1e-2, nstreams=args.batched_nstreams)
     res = {}
@@ -223,6 +224,11 @@ def batched(args):
                    "classes": {f"n{n}_k{k}": v for (n, k), v in sorted(tuned.items())}},
     }
     return out
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def host_info():
@@ -306,14 +312,29 @@ def cube3d_legs(args):
     for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
         P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH, precision=prec, method=L.METHOD_PCG,
                 max_it=args.max_it, coarse_n=2)
+        progress(f"3d {nm} leg: n={n} k={k}, {P.nlam} trace DOFs")
         times, lam, infos = timed_solves(P, f, args.tol, args.steps3d, 1)
         ms = 1e3 * median(times)
+        progress(f"3d {nm}: {1e3 * median(times):.1f} ms/solve, {infos[-1]['iters']} iterations")
         lams[nm] = lam
         out[nm] = {"value": round(P.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
                    "iters": infos[-1]["iters"], "refinement_steps": infos[-1]["outer_iters"],
                    "relres": max(i["relres"] for i in infos), "build_ms": round(infos[-1]["t_build_ms"], 2)}
     out["lambda_mixed_vs_fp64"] = rel(lams["mixed"], lams["fp64"])
     out["mixed_over_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    # finest-level kernels of the mixed solve, event-timed in one more solve
+    P.profile_begin()
+    P.solve(f, tol=args.tol)
+    kern = {}
+    for mode, name in [(0, "apply"), (2, "sweep"), (3, "residual_prestrict"), (6, "sweep_rz")]:
+        for pr, pn in [(L.FP64, "fp64"), (L.MIXED_CYCLE, "fp32ops_fp64vec")]:
+            r = P.profile_read(mode, pr)
+            if r["launches"]:
+                t = r["total_ms"] / r["launches"]
+                gbs = r["bytes_per_launch"] / (t * 1e-3) / 1e9
+                kern[f"{name}_{pn}"] = {"launches": r["launches"], "avg_ms": round(t, 5), "GBps": round(gbs, 1),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["kernels"] = kern
     P.close()
     return out
 
@@ -365,8 +386,10 @@ def main():
         build(precision)
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
+        progress(f"2d leg precision={precision}: {args.warmup} warm-up + {args.steps} timed solves")
         times, lam, infos = timed_solves(P, f, args.tol, args.steps, args.warmup)
         ms = 1e3 * median(times)
+        progress(f"2d leg precision={precision}: {ms:.1f} ms/solve, {infos[-1]['iters']} iterations")
         return {"ms_per_step": ms, "mean_ms": 1e3 * sum(times) / len(times), "value": N / (ms / 1e3),
                 "iters": infos[-1]["iters"], "refinement_steps": infos[-1]["outer_iters"],
                 "relres": max(i["relres"] for i in infos), "build_s": t_build,
@@ -383,6 +406,7 @@ def main():
 
     # kernel timing: one more mixed solve, untimed, with HIP events around
     # every finest-level launch (eager launches: this pass is not the step)
+    progress("profiled mixed solve (event-timed kernels)")
     P.profile_begin()
     P.solve(f, tol=args.tol)
     prof = {}
@@ -396,6 +420,7 @@ def main():
     # solve driven to its floor (the relative residual it can reach)
     errors = None
     if not args.skip_fp64 and not args.no_errors:
+        progress("FP64 reference solve for the error report")
         build(L.FP64, max_it=res64["iters"] + 400)  # a few hundred iterations past the metric's tolerance
         lam_ref, info_ref = P.solve(f, tol=args.ref_tol, allow_not_converged=True)
         u_ref, q_ref = P.reconstruct(lam_ref, f)
@@ -450,6 +475,7 @@ def main():
             cube = {"error": str(e)[:300]}
     batch = None
     if not args.no_batched:
+        progress("batched leg")
         try:
             batch = batched(args)
         except Exception as e:
@@ -457,6 +483,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host")
         try:
             cpu = run_cpu_baseline(args.cpu_n, k, args.coarse_n, args.cpu_min_s)
         except Exception as e:  # reported, never fatal for the GPU figure

@@ -63,7 +63,7 @@ typedef enum {
 } hdg_status;
 
 enum { HDG_KAPPA_PER_ELEMENT = 0, HDG_KAPPA_AT_QP = 1 };
-enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_MIXED = 1 };
+enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_MIXED = 1, HDG_MIXED_CYCLE = 2 /* hdg_vcycle only, see there */ };
 enum { HDG_LC_NONE = 0, HDG_LC_PRE = 1, HDG_LC_POST = 2, HDG_LC_BOTH = 3 };
 enum { HDG_METHOD_MG = 0, HDG_METHOD_PCG = 1, HDG_METHOD_GMRES = 2 };
 enum { HDG_RHS_F_NODAL = 0, HDG_RHS_F_LOAD = 1, HDG_RHS_TRACE = 2 };
@@ -105,7 +105,13 @@ enum {
   HDG_VARIANT_NO_FUSE = 2,  /* unfused level-transition kernels (residual, restriction, prolongation apart) */
   HDG_VARIANT_NO_TAIL = 4,  /* no one-workgroup coarse tail: every level launched on its own */
   HDG_VARIANT_NO_PACK = 8,  /* finest p-level stored face-major instead of element-major packed triangles */
-  HDG_VARIANT_NO_STRIP = 16 /* element-major finest level applied in two passes instead of one strip pass */
+  HDG_VARIANT_NO_STRIP = 16, /* element-major finest level applied in two passes instead of one strip pass */
+  /* HDG_MIXED cycle form.  Default: in 3D every level keeps FP64 vectors and sums over the FP32 copies
+     of its operator blocks (an FP32 cycle stalls CG near 1e-6 there); in 2D the whole cycle runs on FP32
+     vectors.  These bits force one form (for comparing them); the FP64-vector form stores every level
+     face-major and uses the unfused transition kernels. */
+  HDG_VARIANT_FP32_VECTORS = 32, /* FP32 vectors and sums in the mixed cycle, also in 3D */
+  HDG_VARIANT_FP64_VECTORS = 64  /* FP64 vectors and sums over FP32 operator blocks, also in 2D */
 };
 
 typedef struct {
@@ -145,8 +151,9 @@ hdg_status hdg_update_kappa(hdg_handle h, const double* kappa, int kappa_kind);
 hdg_status hdg_mg_build(hdg_handle h, const hdg_mg_opts* opts);
 
 /* One V-cycle e = B_L r on the finest level (Algorithm 1), r and e trace
- * vectors of length N_lambda (double for HDG_FP64, float for HDG_FP32);
- * nrhs vectors stored one after another. */
+ * vectors of length N_lambda (double for HDG_FP64, float for HDG_FP32, and
+ * double for HDG_MIXED_CYCLE: the cycle the mixed solve applies, in the
+ * build's mixed form); nrhs vectors stored one after another. */
 hdg_status hdg_vcycle(hdg_handle h, const void* r, void* e, int precision, int nrhs);
 
 /* Right-hand side g of eq. trace_linear_system from a volume source
@@ -214,10 +221,11 @@ hdg_status hdg_level_export(hdg_handle h, int level, double* out);
  * hdg_profile_read.  kernel = 2 * mode + precision, mode 0 apply y = A x,
  * 1 residual b - A x, 2 block-Jacobi sweep x + D^-1 (b - A x), 3 residual
  * restricted to P1 (J_N^T), 6 the sweep inside CG's preconditioner that also
- * forms the r.z partials; precision HDG_FP64 / HDG_FP32.  Returns the
- * number of launches, their summed duration, and the algorithmic HBM bytes
- * of one launch (stored face-major matrix blocks, face-block inverses and
- * each vector entry read or written once). */
+ * forms the r.z partials; precision HDG_FP64 / HDG_FP32; or kernel = 14 +
+ * mode for the finest level of the mixed cycle with FP64 vectors over FP32
+ * operator blocks (3D).  Returns the number of launches, their summed duration,
+ * and the algorithmic HBM bytes of one launch (stored face-major matrix
+ * blocks, face-block inverses and each vector entry read or written once). */
 hdg_status hdg_profile_begin(hdg_handle h);
 hdg_status hdg_profile_read(hdg_handle h, int kernel, long long* launches, double* total_ms,
                             double* bytes_per_launch);

@@ -10,6 +10,7 @@ HDG_OK, HDG_ERR_INVALID_ARG, HDG_ERR_UNSUPPORTED, HDG_ERR_STATE = 0, -1, -2, -3
 HDG_ERR_NOT_CONVERGED, HDG_ERR_BREAKDOWN, HDG_ERR_DEVICE = -4, -5, -6
 KAPPA_PER_ELEMENT, KAPPA_AT_QP = 0, 1
 FP64, FP32, MIXED = 0, 1, 1
+MIXED_CYCLE = 2  # hdg_vcycle: the mixed solve's cycle on FP64 vectors
 LC_NONE, LC_PRE, LC_POST, LC_BOTH = 0, 1, 2, 3
 METHOD_MG, METHOD_PCG, METHOD_GMRES = 0, 1, 2
 RHS_F_NODAL, RHS_F_LOAD, RHS_TRACE = 0, 1, 2
@@ -40,6 +41,8 @@ class Opts(ctypes.Structure):
 
 # hdg_mg_opts.variant bits (HDG_VARIANT_*)
 VARIANT_NO_GRAPH, VARIANT_NO_FUSE, VARIANT_NO_TAIL, VARIANT_NO_PACK, VARIANT_NO_STRIP = 1, 2, 4, 8, 16
+VARIANT_FP32_VECTORS, VARIANT_FP64_VECTORS = 32, 64
+PROF_F32OPS = 14  # hdg_profile_read: kernel = 14 + mode for FP64 vectors over FP32 operator blocks
 OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", "max_it", "restart", "coarse_n",
               "nrhs", "refine_red", "variant")
 

@@ -28,6 +28,9 @@ struct hdg_problem {
   bool pack = true;              // element-major packed finest p-level (HDG_VARIANT_NO_PACK: face-major)
   bool strip = true;             // one-pass strip apply on packed levels (HDG_VARIANT_NO_STRIP: two-phase)
   double t_setup_ms = 0.0, t_build_ms = 0.0;  // host wall time of the last setup / build
+  // form of the mixed cycle: false = FP32 vectors on every level, true = FP64
+  // vectors and sums over the FP32 operator blocks of every level
+  bool ops32 = false;
   // set around a preconditioner call inside CG: the finest level's last
   // sweep also forms the r.z partials (dot_v = r); dot_parts receives their
   // count per right-hand side (0: not formed)
@@ -66,7 +69,8 @@ struct hdg_problem {
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
-  static constexpr int NPROF = 2 * (APPLY_SWEEP_DOT + 1);
+  static constexpr int NPROF_F32OPS = 2 * (APPLY_SWEEP_DOT + 1);  // first class of the FP64-vector form
+  static constexpr int NPROF = 3 * (APPLY_SWEEP_DOT + 1);
   double prof_ms[NPROF] = {};
   long long prof_n[NPROF] = {};
   std::vector<void*> allocs;        // freed in destroy
@@ -183,17 +187,25 @@ void harvest(hdg_problem* P) {
   P->pending.clear();
 }
 
+// profiling class of a finest-level launch of mode `mode` with vectors T
+// over operator blocks M
+template <typename T, typename M>
+int prof_class(int mode) {
+  if constexpr (!std::is_same_v<T, M>) return hdg_problem::NPROF_F32OPS + mode;
+  return 2 * mode + (sizeof(T) == 8 ? 0 : 1);
+}
+
 // trace apply on level i; finest-level launches are timed when profiling
-template <typename T>
+template <typename T, typename M = T>
 void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc, int nr = 1) {
   const bool timed = P->prof_on && i == 0 && nr == 1;
-  hdg_problem::Pending pd{2 * mode + (sizeof(T) == 8 ? 0 : 1), nullptr, nullptr};
+  hdg_problem::Pending pd{prof_class<T, M>(mode), nullptr, nullptr};
   if (timed) {
     pd.a = take_event(P);
     pd.b = take_event(P);
     HDG_CHECK(hipEventRecord(pd.a, P->st));
   }
-  launch_apply<T>(P->L[i], mode, x, b, y, P->rd.Jp, rc, P->st, nr);
+  launch_apply<T, M>(P->L[i], mode, x, b, y, P->rd.Jp, rc, P->st, nr);
   if (timed) {
     HDG_CHECK(hipEventRecord(pd.b, P->st));
     P->pending.push_back(pd);
@@ -258,14 +270,19 @@ enum { G_PCG64 = 0, G_PCGMX = 1, G_MG64 = 2, G_MGMX = 3, G_PRE64 = 4, G_PREMX = 
 // coarsest direct solve), and one out-of-place pass (prolongation + local
 // correction of step 5).  Same arithmetic as the unfused kernels up to the
 // order of the last rounding.
-template <typename T>
+//
+// M: storage type of the operator blocks read.  M = float under T = double is
+// the 3D mixed cycle: every level keeps FP64 vectors and sums and reads the
+// FP32 copies of its blocks (unfused kernels, no coarse tail).
+template <typename T, typename M = T>
 T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int nr = 1) {
+  constexpr bool narrow = !std::is_same_v<T, M>;
   Level& L = P->L[i];
   const int pr = sizeof(T) == 8 ? 0 : 1;
   hipStream_t st = P->st;
   T* e = (T*)L.e[pr];
   T* w = (T*)L.w[pr];
-  if (i == P->tail_start[pr]) {
+  if (!narrow && i == P->tail_start[pr]) {
     TailArgs a = P->tail_args[pr];
     a.rin = r;
     a.ein = e;
@@ -276,21 +293,21 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
   }
   if (L.kind == 2) {
     T* dst = out ? out : e;
-    launch_coarse_solve<T>(L, r, dst, st, nr);
+    launch_coarse_solve<T, M>(L, r, dst, st, nr);
     return dst;
   }
   const int m = L.sweeps;
   const int lc = P->opts.local_corr;
-  const bool fused = P->fuse && L.d == 2 && m >= 1;
+  const bool fused = !narrow && P->fuse && L.d == 2 && m >= 1;
   // pre-smoothing from e = 0
   if (!pre_done) {
     if (m >= 1)
-      launch_jacobi0<T>(L, r, e, st, nr);
+      launch_jacobi0<T, M>(L, r, e, st, nr);
     else
       blas_fill<T>(e, T(0), L.nlam, st, nr);
   }
   for (int s = 1; s < m; ++s) {
-    apply<T>(P, i, APPLY_SWEEP, e, r, w, nullptr, nr);
+    apply<T, M>(P, i, APPLY_SWEEP, e, r, w, nullptr, nr);
     std::swap(e, w);
   }
   Level& C = P->L[i + 1];
@@ -312,8 +329,8 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
       }
       ec = vcycle<T>(P, i + 1, rc, nullptr, true, nr);
     } else {
-      apply<T>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc, nr);
-      ec = vcycle<T>(P, i + 1, rc, nullptr, false, nr);
+      apply<T, M>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc, nr);
+      ec = vcycle<T, M>(P, i + 1, rc, nullptr, false, nr);
     }
     launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st, nr);
   } else if (fused) {
@@ -330,14 +347,14 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
     launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st, nr);
     std::swap(e, w);
   } else {
-    apply<T>(P, i, APPLY_RES, e, r, w, nullptr, nr);
-    launch_hcorr<T>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st, nr);
+    apply<T, M>(P, i, APPLY_RES, e, r, w, nullptr, nr);
+    launch_hcorr<T, M>(L, w, e, (lc & HDG_LC_PRE) ? 1 : 0, 1, (T*)L.cb[pr], st, nr);
     launch_hrestrict<T>(L, C, w, (T*)L.cb[pr], rc, st, nr);
-    const T* ec = vcycle<T>(P, i + 1, rc, nullptr, false, nr);
-    launch_hprolong<T>(L, C, ec, e, st, nr);
+    const T* ec = vcycle<T, M>(P, i + 1, rc, nullptr, false, nr);
+    launch_hprolong<T, M>(L, C, ec, e, st, nr);
     if (lc & HDG_LC_POST) {
-      apply<T>(P, i, APPLY_RES, e, r, w, nullptr, nr);
-      launch_hcorr<T>(L, w, e, 1, 0, nullptr, st, nr);
+      apply<T, M>(P, i, APPLY_RES, e, r, w, nullptr, nr);
+      launch_hcorr<T, M>(L, w, e, 1, 0, nullptr, st, nr);
     }
   }
   for (int s = 0; s < m; ++s) {
@@ -345,20 +362,20 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
     if (i == 0 && P->dot_v && dst == out) {
       int np = 0;
       const bool timed = P->prof_on && nr == 1;
-      hdg_problem::Pending pd{2 * APPLY_SWEEP_DOT + pr, nullptr, nullptr};
+      hdg_problem::Pending pd{prof_class<T, M>(APPLY_SWEEP_DOT), nullptr, nullptr};
       if (timed) {
         pd.a = take_event(P);
         pd.b = take_event(P);
         HDG_CHECK(hipEventRecord(pd.a, st));
       }
-      launch_apply_red<T>(L, APPLY_SWEEP_DOT, e, r, dst, P->dot_v, nullptr, nullptr, &P->s, st, nr, &np);
+      launch_apply_red<T, M>(L, APPLY_SWEEP_DOT, e, r, dst, P->dot_v, nullptr, nullptr, &P->s, st, nr, &np);
       if (timed) {
         HDG_CHECK(hipEventRecord(pd.b, st));
         P->pending.push_back(pd);
       }
       P->dot_parts = np;
     } else {
-      apply<T>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
+      apply<T, M>(P, i, APPLY_SWEEP, e, r, dst, nullptr, nr);
     }
     if (dst == w)
       std::swap(e, w);
@@ -376,6 +393,10 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
 void precond(hdg_problem* P, const double* r, double* z, bool mixed) {
   if (!mixed) {
     vcycle<double>(P, 0, r, z);
+    return;
+  }
+  if (P->ops32) {
+    vcycle<double, float>(P, 0, r, z);
     return;
   }
   Level& L0 = P->L[0];
@@ -432,9 +453,12 @@ void residual_norm(hdg_problem* P, const double* lam, const double* g, bool mixe
   }
 }
 
-// z = B r: FP64 V-cycle on r, or FP32 V-cycle on the FP32 copy r32 into z32
+// z = B r: FP64 V-cycle on r, or FP32 V-cycle on the FP32 copy r32 into
+// z32, or (mixed, 3D) the cycle over FP32 operator blocks on r into z
 void precond_fused(hdg_problem* P, bool mixed, int nr) {
-  if (mixed)
+  if (mixed && P->ops32)
+    vcycle<double, float>(P, 0, P->r, P->z, false, nr);
+  else if (mixed)
     vcycle<float>(P, 0, P->r32, P->z32, false, nr);
   else
     vcycle<double>(P, 0, P->r, P->z, false, nr);
@@ -530,7 +554,8 @@ double worst_rnorm(const double* sc, int nr, const double* gn) {
 SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, const double* gn, bool mixed, int nr) {
   SolveOut o;
   const long N = P->N;
-  residual_norm(P, lam, g, mixed, nr);
+  const bool v32 = mixed && !P->ops32;  // the cycle takes and returns FP32 vectors
+  residual_norm(P, lam, g, v32, nr);
   double rel = worst_rnorm(read_scalars(P, nr), nr, gn);
   o.outer = 1;
   Tracker tr;
@@ -545,11 +570,11 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, cons
           P, mixed ? G_MGMX : G_MG64,
           [&] {
             precond_fused(P, mixed, nr);
-            if (mixed)
+            if (v32)
               blas_add<float>(lam, P->z32, N, P->st, nr);
             else
               blas_add<double>(lam, P->z, N, P->st, nr);
-            residual_norm(P, lam, g, mixed, nr);
+            residual_norm(P, lam, g, v32, nr);
           },
           nr);
     all = tr.scan(read_scalars(P, nr), launched, grp, &rel);
@@ -579,11 +604,12 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
   SolveOut o;
   const long N = P->N;
   const double red = mixed ? P->opts.refine_red : 0.0;
+  const bool v32 = mixed && !P->ops32;  // the cycle takes and returns FP32 vectors
   Tracker tr;
   tr.init(nr, tol, gn);
   int launched = 0;
   for (;;) {
-    residual_norm(P, lam, g, mixed, nr);
+    residual_norm(P, lam, g, v32, nr);
     const double* sc0 = read_scalars(P, nr);
     double rel = worst_rnorm(sc0, nr, gn);
     double r0[64];
@@ -596,7 +622,7 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
     }
     if (rel <= tol || launched >= P->opts.max_it) break;
     precond_fused(P, mixed, nr);
-    if (mixed) {
+    if (v32) {
       blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st, nr);
       blas_f2d(P->z32, P->p, N, P->st, nr);
     } else {
@@ -633,7 +659,7 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
                 HDG_CHECK(hipEventRecord(pd.b, s2));
                 P->pending.push_back(pd);
               }
-              if (mixed)
+              if (v32)
                 blas_cg_update2_fused<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, npap, P->s, s2, nr);
               else
                 blas_cg_update2_fused<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, npap, P->s, s2, nr);
@@ -644,11 +670,11 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
               P->dot_v = nullptr;
               if (P->dot_parts > 0)
                 blas_finalize_cg(N, P->dot_parts, mixed, P->s, s2, nr);
-              else if (mixed)
+              else if (v32)
                 blas_rz_cg<float>(P->r, P->z32, N, true, P->s, s2, nr);
               else
-                blas_rz_cg<double>(P->r, P->z, N, false, P->s, s2, nr);
-              if (mixed)
+                blas_rz_cg<double>(P->r, P->z, N, mixed, P->s, s2, nr);
+              if (v32)
                 blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
               else
                 blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
@@ -726,9 +752,15 @@ SolveOut solve_gmres(hdg_problem* P, const double* g, double* lam, double tol, d
   return o;
 }
 
+// g from a volume source: element loads b^e staged in ebuf (N_T (n_v + n_l)
+// doubles), then pulled per face with the Dirichlet lift
+void form_rhs_in(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g, double* ebuf) {
+  launch_element_load(P->d, P->k, P->nelem, P->rd, rhs, kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, ebuf, P->st);
+  launch_load_pull(P->d, P->k, P->n, ebuf, P->Ae, gdir, g, P->st);
+}
+
 void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g) {
-  launch_element_load(P->d, P->k, P->nelem, P->rd, rhs, kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->ework, P->st);
-  launch_load_pull(P->d, P->k, P->n, P->ework, P->Ae, gdir, g, P->st);
+  form_rhs_in(P, rhs, kind, gdir, g, P->ework);
 }
 
 // Solve for the nr right-hand sides already in P->g (initial guesses in
@@ -927,7 +959,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
       o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
-      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 31)
+      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 127)
     return HDG_ERR_INVALID_ARG;
   if (o.nrhs < 1) o.nrhs = 1;
   if (o.refine_red == 0.0) o.refine_red = 1e-5;
@@ -943,6 +975,16 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   P->tail_nmax = (o.variant & HDG_VARIANT_NO_TAIL) ? 0 : 32;
   P->pack = !(o.variant & HDG_VARIANT_NO_PACK);
   P->strip = !(o.variant & HDG_VARIANT_NO_STRIP);
+  // mixed cycle form: FP64 vectors over FP32 operator blocks in 3D (the FP32
+  // cycle stalls CG there), FP32 vectors in 2D; the variant bits force one.
+  // The FP64-vector form reads face-major blocks with the unfused kernels.
+  P->ops32 = o.precision == HDG_MIXED && !(o.variant & HDG_VARIANT_FP32_VECTORS) &&
+             (P->d == 3 || (o.variant & HDG_VARIANT_FP64_VECTORS));
+  if (P->ops32) {
+    P->pack = false;
+    P->fuse = false;
+    P->tail_nmax = 0;
+  }
   const int cap = P->cap;
   const int d = P->d;
   const int nc = 1 << (d - 1);
@@ -1068,6 +1110,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     }
   }
 
+  // mixed cycle form (set above, before the levels' storage was chosen)
   P->N = L[0].nlam;
   const long N = P->N;
   const long Nc = N * cap;
@@ -1111,14 +1154,22 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
 hdg_status hdg_vcycle(hdg_handle P, const void* r, void* e, int precision, int nrhs) {
   if (!P || !r || !e || nrhs < 1) return HDG_ERR_INVALID_ARG;
   if (!P->built) return HDG_ERR_STATE;
-  if (precision != HDG_FP64 && precision != HDG_FP32) return HDG_ERR_INVALID_ARG;
+  if (precision != HDG_FP64 && precision != HDG_FP32 && precision != HDG_MIXED_CYCLE) return HDG_ERR_INVALID_ARG;
   HDG_GUARD_BEGIN
   for (int i0 = 0; i0 < nrhs && P->N > 0; i0 += P->cap) {
     const int nr = std::min(P->cap, nrhs - i0);
-    if (precision == HDG_FP64)
+    if (precision == HDG_FP64) {
       vcycle<double>(P, 0, (const double*)r + i0 * P->N, (double*)e + i0 * P->N, false, nr);
-    else
+    } else if (precision == HDG_FP32) {
       vcycle<float>(P, 0, (const float*)r + i0 * P->N, (float*)e + i0 * P->N, false, nr);
+    } else if (P->ops32) {
+      vcycle<double, float>(P, 0, (const double*)r + i0 * P->N, (double*)e + i0 * P->N, false, nr);
+    } else {  // the FP32 cycle between conversions of r and e
+      float* r32 = (float*)P->L[0].r[1];
+      blas_d2f((const double*)r + i0 * P->N, r32, P->N, P->st, nr);
+      const float* e32 = vcycle<float>(P, 0, r32, nullptr, false, nr);
+      blas_f2d(e32, (double*)e + i0 * P->N, P->N, P->st, nr);
+    }
   }
   return HDG_OK;
   HDG_GUARD_END
@@ -1448,18 +1499,20 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   HDG_CHECK(hipStreamSynchronize(P->st));
   harvest(P);
   const Level& L = P->L[0];
-  const int mode = kernel / 2;
-  const double s = (kernel % 2) ? 4.0 : 8.0;
+  const bool f32ops = kernel >= hdg_problem::NPROF_F32OPS;  // FP32 blocks, FP64 vectors
+  const int mode = f32ops ? kernel - hdg_problem::NPROF_F32OPS : kernel / 2;
+  const double sm = f32ops ? 4.0 : ((kernel % 2) ? 4.0 : 8.0);  // bytes per stored operator entry
+  const double s = f32ops ? 8.0 : sm;                             // bytes per vector entry
   const double N = (double)L.nlam;
   // operator bytes: each element row once (face-major), or the packed upper
   // triangle of each element map (element-major)
-  double bytes = L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * s : (double)L.nface * 2.0 * L.ne * L.nl * s;
+  double bytes = L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * sm : (double)L.nface * 2.0 * L.ne * L.nl * sm;
   if (mode == APPLY_Y) bytes += 2.0 * N * s;
   if (mode == APPLY_RES) bytes += 3.0 * N * s;
   // face-block inverses: full blocks, or upper triangles on element-major levels
   const double nd = L.packed ? L.ne * (L.ne + 1) / 2 : L.ne * L.ne;
-  if (mode == APPLY_SWEEP) bytes += (double)L.nface * nd * s + 3.0 * N * s;
-  if (mode == APPLY_SWEEP_DOT) bytes += (double)L.nface * nd * s + 3.0 * N * s + 8.0 * N;  // + r (FP64)
+  if (mode == APPLY_SWEEP) bytes += (double)L.nface * nd * sm + 3.0 * N * s;
+  if (mode == APPLY_SWEEP_DOT) bytes += (double)L.nface * nd * sm + 3.0 * N * s + 8.0 * N;  // + r (FP64)
   if (mode == APPLY_RES_PRESTRICT) bytes += 2.0 * N * s + (double)L.nface * (1 << (L.d - 1)) * s;
   if (launches) *launches = P->prof_n[kernel];
   if (total_ms) *total_ms = P->prof_ms[kernel];

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hdg.h"
@@ -178,22 +179,24 @@ void launch_coarse_inverse(const Level& L, hipStream_t st);
 
 // trace.hip.  Every launcher takes nrhs right-hand sides stored one after
 // another (stride: the level's vector length) and runs them in one launch.
-template <typename T>
+// T: vector type; M: storage type of the operator blocks read (the level's
+// FP64 or FP32 copy; M = float under T = double on face-major levels only).
+template <typename T, typename M = T>
 void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
                   hipStream_t st, int nrhs = 1);
-template <typename T>
+template <typename T, typename M = T>
 void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
 void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* e, hipStream_t st, int nrhs = 1);
-template <typename T>
+template <typename T, typename M = T>
 void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st,
                   int nrhs = 1);
 template <typename T>
 void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st,
                       int nrhs = 1);
-template <typename T>
+template <typename T, typename M = T>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs = 1);
-template <typename T>
+template <typename T, typename M = T>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int nrhs = 1);
 template <typename T>
 void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
@@ -238,7 +241,7 @@ struct Scratch;
 // one-block finaliser runs next, unless nparts is given: then it receives
 // the number of partials per right-hand side (their row stride) and the
 // caller finalises (e.g. inside the next kernel).
-template <typename T>
+template <typename T, typename M = T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
                       Scratch* red, hipStream_t st, int nrhs = 1, int* nparts = nullptr);
 

@@ -37,9 +37,10 @@ using namespace dev;
 
 // Output of one face given acc = (A x)_F, per mode (x, b, y, rc, y32
 // already offset to the face's right-hand side); reductions add to part.
-// DSYM: the level's face-block inverses are stored as upper triangles.
-template <int D, int NE, typename T, int MODE, bool DSYM = false>
-__device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restrict__ Dinv, const T* x,
+// DSYM: the level's face-block inverses are stored as upper triangles.  M:
+// storage type of the face-block inverses (T, or FP32 under FP64 vectors).
+template <int D, int NE, typename T, int MODE, bool DSYM = false, typename M = T>
+__device__ inline void face_finish(long F, const acc_t<T>* acc, const M* __restrict__ Dinv, const T* x,
                                    const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
                                    T* __restrict__ rc, float* __restrict__ y32, double& part) {
   constexpr int NC = 1 << (D - 1);
@@ -57,7 +58,7 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
     if constexpr (DSYM)
       dinv_update_sym<NE, T>(F, Dinv, x, res, y);
     else
-      dinv_update<NE, T>(F, Dinv, x, res, y);
+      dinv_update<NE, T, M>(F, Dinv, x, res, y);
     if (MODE == APPLY_SWEEP_DOT)  // Jp holds the FP64 vector of the dot product
 #pragma unroll
       for (int a = 0; a < NE; ++a) part += Jp[F * NE + a] * (double)y[F * NE + a];
@@ -75,7 +76,7 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
       rcv[v] = A(T(s));  // the coarse first step starts from the stored residual
     }
     if (y)  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
-      dinv_update<NC, T>(F, Dinv, (const T*)nullptr, rcv, y);
+      dinv_update<NC, T, M>(F, Dinv, (const T*)nullptr, rcv, y);
   } else if (MODE == APPLY_Y_DOT) {
 #pragma unroll
     for (int a = 0; a < NE; ++a) {
@@ -95,9 +96,10 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const T* __restr
 
 // ZS: the level is stored element-major; Af then points to the per-element
 // products z of the first phase (elem_apply_kernel) and each face only adds
-// its two elements' rows.
-template <int D, int NE, typename T, int MODE, bool ZS = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const T* __restrict__ Af, const T* __restrict__ Dinv,
+// its two elements' rows.  M: storage type of the operator blocks (T, or
+// FP32 blocks under FP64 vectors on the finest level of the mixed cycle).
+template <int D, int NE, typename T, int MODE, bool ZS = false, typename M = T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_APPLY_WPE))) apply_kernel(int n, const M* __restrict__ Af, const M* __restrict__ Dinv,
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
                                                     T* __restrict__ rc, float* __restrict__ y32,
@@ -129,8 +131,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
   if constexpr (ZS)
     face_acc_z<D, NE, T>(F, n, Af, acc);
   else
-    face_acc<D, NE, T>(F, n, Af, x, acc);
-  face_finish<D, NE, T, MODE, ZS>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
+    face_acc<D, NE, T, M>(F, n, Af, x, acc);
+  face_finish<D, NE, T, MODE, ZS, M>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
   }  // F >= 0
   if constexpr (RED) {
     __shared__ double sh[4];
@@ -139,9 +141,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HDG_AP
   }
 }
 
-// e = Dinv r (first sweep from e = 0)
-template <int NE, typename T, bool DSYM>
-__global__ void jacobi0_kernel(long nface, int nrhs, const T* __restrict__ Dinv, const T* __restrict__ r,
+// e = Dinv r (first sweep from e = 0); blocks stored as M
+template <int NE, typename T, bool DSYM, typename M = T>
+__global__ void jacobi0_kernel(long nface, int nrhs, const M* __restrict__ Dinv, const T* __restrict__ r,
                                T* __restrict__ e) {
   int rhs;
   const long b = xcd_block_rhs((nface + 255) / 256, nrhs, blockIdx.x, &rhs);
@@ -149,7 +151,7 @@ __global__ void jacobi0_kernel(long nface, int nrhs, const T* __restrict__ Dinv,
   if (b < 0 || F >= nface) return;
   r += rhs * nface * NE;
   e += rhs * nface * NE;
-  jacobi0_item<NE, T, DSYM>(F, Dinv, r, e);
+  jacobi0_item<NE, T, DSYM, M>(F, Dinv, r, e);
 }
 
 // first phase of the element-major apply: z_T = A^e x_T for every element
@@ -360,8 +362,8 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
 // Local correction and the macro-element part of the restriction:
 //   e_I += A_II^-1 rho_I            (eq. localCorrection, when do_corr)
 //   cb_M = P_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict)
-template <int D, typename T>
-__global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__ AIIinv, const T* __restrict__ P,
+template <int D, typename T, typename M = T>
+__global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__ AIIinv, const M* __restrict__ P,
                                                     const T* __restrict__ rho, T* __restrict__ e, int do_corr,
                                                     int do_restrict, T* __restrict__ cb) {
   constexpr int NC = 1 << (D - 1);
@@ -371,8 +373,8 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
   const int nm = n / 2;
   long nmacro = 1;
   for (int a = 0; a < D; ++a) nmacro *= nm;
-  const long M = blockIdx.x * 256L + threadIdx.x;
-  if (M >= nmacro) return;
+  const long Mi = blockIdx.x * 256L + threadIdx.x;
+  if (Mi >= nmacro) return;
   {
     const long sF = trace_len<D>(n, NC);
     rho += blockIdx.y * sF;
@@ -380,7 +382,7 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
     cb = off(cb, blockIdx.y * nmacro * NCL);
   }
   int m[3] = {0, 0, 0};
-  decode_elem<D>(M, nm, m);
+  decode_elem<D>(Mi, nm, m);
   using A = acc_t<T>;
   A rI[NI];
   long fid[NIF];
@@ -394,7 +396,7 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
     A s[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) s[i] = A(0);
-    aos_mv<T, NI * NI, NI, false>(AIIinv + aos_item<T>(M, vpad<T>(NI * NI)), rI, s);
+    aos_mv<M, NI * NI, NI, false>(AIIinv + aos_item<M>(Mi, vpad<M>(NI * NI)), rI, s);
 #pragma unroll
     for (int i = 0; i < NIF; ++i)
 #pragma unroll
@@ -404,9 +406,9 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const T* __restrict__
     A s[NCL];
 #pragma unroll
     for (int j = 0; j < NCL; ++j) s[j] = A(0);
-    aos_mv<T, NI * NCL, NCL, true>(P + aos_item<T>(M, vpad<T>(NI * NCL)), rI, s);
+    aos_mv<M, NI * NCL, NCL, true>(P + aos_item<M>(Mi, vpad<M>(NI * NCL)), rI, s);
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) cb[M * NCL + j] = T(s[j]);
+    for (int j = 0; j < NCL; ++j) cb[Mi * NCL + j] = T(s[j]);
   }
 }
 
@@ -458,8 +460,8 @@ __global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __re
 
 // e_I += P_M ec_M per macro-element (blocks [0, nbm)), e_B += J ec per coarse
 // face (blocks [nbm, ...))   (eq. n_1_Ik)
-template <int D, typename T>
-__global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T* __restrict__ P,
+template <int D, typename T, typename M = T>
+__global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const M* __restrict__ P,
                                                        const T* __restrict__ ec, T* __restrict__ e) {
   constexpr int NC = 1 << (D - 1);
   constexpr int NIF = D * NC;
@@ -472,10 +474,10 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
   if (blockIdx.x < nbm) {
     long nmacro = 1;
     for (int a = 0; a < D; ++a) nmacro *= nm;
-    const long M = blockIdx.x * 256L + threadIdx.x;
-    if (M >= nmacro) return;
+    const long Mi = blockIdx.x * 256L + threadIdx.x;
+    if (Mi >= nmacro) return;
     int m[3] = {0, 0, 0};
-    decode_elem<D>(M, nm, m);
+    decode_elem<D>(Mi, nm, m);
     A cv[NCL];
 #pragma unroll
     for (int sl = 0; sl < 2 * D; ++sl) {
@@ -499,7 +501,7 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
 #pragma unroll
       for (int a = 0; a < NC; ++a) s[i * NC + a] = e[f * NC + a];
     }
-    aos_mv<T, NI * NCL, NCL, false>(P + aos_item<T>(M, vpad<T>(NI * NCL)), cv, s);
+    aos_mv<M, NI * NCL, NCL, false>(P + aos_item<M>(Mi, vpad<M>(NI * NCL)), cv, s);
 #pragma unroll
     for (int i = 0; i < NIF; ++i) {
       const long f = macro_iface<D>(m, i, n);
@@ -529,8 +531,8 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const T*
   }
 }
 
-template <typename T>
-__global__ void coarse_solve_kernel(int N, const T* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
+template <typename T, typename M = T>
+__global__ void coarse_solve_kernel(int N, const M* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
   r += blockIdx.y * (long)N;
   e += blockIdx.y * (long)N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -677,8 +679,8 @@ __global__ void hsum_solve_kernel(int n, int N, const T* __restrict__ r, const T
 }
 
 // e = A_1^-1 r for a larger coarsest level: one wavefront per row
-template <typename T>
-__global__ void coarse_gemv_kernel(int N, const T* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
+template <typename T, typename M = T>
+__global__ void coarse_gemv_kernel(int N, const M* __restrict__ Ainv, const T* __restrict__ r, T* __restrict__ e) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
@@ -814,28 +816,31 @@ void launch_elem_phase(const Level& L, const T* x, hipStream_t st, int nrhs) {
 
 }  // namespace
 
-template <typename T>
+template <typename T, typename M>
 void launch_apply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc,
                   hipStream_t st, int nrhs) {
-  launch_apply_red<T>(L, mode, x, b, y, Jp, rc, nullptr, nullptr, st, nrhs);
+  launch_apply_red<T, M>(L, mode, x, b, y, Jp, rc, nullptr, nullptr, st, nrhs);
 }
 
-template <typename T>
+template <typename T, typename M>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
                       Scratch* red, hipStream_t st, int nrhs, int* nparts) {
   if (L.nface == 0) return;
   double* partials = red ? red->partials : nullptr;
-  const T* Af = nullptr;
-  const T* Dv = nullptr;
-  if constexpr (sizeof(T) == 8) {
-    Af = (const T*)L.Af64;
-    Dv = (const T*)L.Dinv64;
+  const M* Af = nullptr;
+  const M* Dv = nullptr;
+  if constexpr (sizeof(M) == 8) {
+    Af = (const M*)L.Af64;
+    Dv = (const M*)L.Dinv64;
   } else {
-    Af = (const T*)L.Af32;
-    Dv = (const T*)L.Dinv32;
+    Af = (const M*)L.Af32;
+    Dv = (const M*)L.Dinv32;
   }
   unsigned g1 = xcd_grid(L.d, L.n);
-  if (L.strip) {
+  if constexpr (!std::is_same_v<T, M>) {
+    if (L.packed || !Af || !Dv)
+      throw HipError{hipErrorInvalidValue, "narrow operator blocks under wider vectors: face-major levels only"};
+  } else if (L.strip) {
     int nbt = 0;
     switch (mode) {
       case APPLY_Y: nbt = launch_strips<T, APPLY_Y>(L, Dv, x, b, y, Jp, rc, y32, partials, st, nrhs); break;
@@ -868,17 +873,25 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     }
     return;
   }
-  if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
-  const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
+  const T* Zs = nullptr;
+  if constexpr (std::is_same_v<T, M>) {
+    if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
+    Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
+  }
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
 #define HDG_AK(MM)                                                                                                 \
-  if (L.packed)                                                                                                    \
-    hipLaunchKernelGGL((apply_kernel<D, NE, T, MM, true>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Zs, Dv, \
-                       x, b, y, Jp, rc, y32, partials, nrhs);                                                      \
-  else                                                                                                             \
-    hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, Dv, x, b, \
-                       y, Jp, rc, y32, partials, nrhs)
+  if constexpr (std::is_same_v<T, M>) {                                                                            \
+    if (L.packed)                                                                                                  \
+      hipLaunchKernelGGL((apply_kernel<D, NE, T, MM, true>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Zs,   \
+                         Dv, x, b, y, Jp, rc, y32, partials, nrhs);                                                \
+    else                                                                                                           \
+      hipLaunchKernelGGL((apply_kernel<D, NE, T, MM>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, Dv, x,  \
+                         b, y, Jp, rc, y32, partials, nrhs);                                                       \
+  } else {                                                                                                         \
+    hipLaunchKernelGGL((apply_kernel<D, NE, T, MM, false, M>), dim3(g1 * (unsigned)nrhs), dim3(256), 0, st, L.n, Af, \
+                       Dv, x, b, y, Jp, rc, y32, partials, nrhs);                                                  \
+  }
     switch (mode) {
       case APPLY_Y: HDG_AK(APPLY_Y); break;
       case APPLY_RES: HDG_AK(APPLY_RES); break;
@@ -932,17 +945,22 @@ void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b
   HDG_CHECK(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, typename M>
 void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
-  const T* Dv = sizeof(T) == 8 ? (const T*)L.Dinv64 : (const T*)L.Dinv32;
+  const M* Dv = sizeof(M) == 8 ? (const M*)L.Dinv64 : (const M*)L.Dinv32;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int NE = decltype(NE_)::value;
     const dim3 g(xcd_rhs_grid(nblk(L.nface), nrhs));
-    if (L.packed)
-      hipLaunchKernelGGL((jacobi0_kernel<NE, T, true>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
-    else
-      hipLaunchKernelGGL((jacobi0_kernel<NE, T, false>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
+    if constexpr (std::is_same_v<T, M>) {
+      if (L.packed)
+        hipLaunchKernelGGL((jacobi0_kernel<NE, T, true>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
+      else
+        hipLaunchKernelGGL((jacobi0_kernel<NE, T, false>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
+    } else {
+      if (L.packed) throw HipError{hipErrorInvalidValue, "narrow operator blocks: face-major levels only"};
+      hipLaunchKernelGGL((jacobi0_kernel<NE, T, false, M>), g, dim3(256), 0, st, L.nface, nrhs, Dv, r, e);
+    }
   });
   HDG_CHECK(hipGetLastError());
 }
@@ -960,15 +978,15 @@ void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* 
   HDG_CHECK(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, typename M>
 void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st, int nrhs) {
-  const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
-  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  const M* Ai = sizeof(M) == 8 ? (const M*)L.AIIinv64 : (const M*)L.AIIinv32;
+  const M* P = sizeof(M) == 8 ? (const M*)L.P64 : (const M*)L.P32;
   if (L.d == 2)
-    hipLaunchKernelGGL((hcorr_kernel<2, T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
+    hipLaunchKernelGGL((hcorr_kernel<2, T, M>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
                        do_corr, do_restrict, cb);
   else
-    hipLaunchKernelGGL((hcorr_kernel<3, T>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
+    hipLaunchKernelGGL((hcorr_kernel<3, T, M>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
                        do_corr, do_restrict, cb);
   HDG_CHECK(hipGetLastError());
 }
@@ -983,30 +1001,30 @@ void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb,
   HDG_CHECK(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, typename M>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs) {
-  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  const M* P = sizeof(M) == 8 ? (const M*)L.P64 : (const M*)L.P32;
   long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
   if (L.d == 2)
-    hipLaunchKernelGGL((hprolong_kernel<2, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P, ec,
-                       e);
+    hipLaunchKernelGGL((hprolong_kernel<2, T, M>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P,
+                       ec, e);
   else
-    hipLaunchKernelGGL((hprolong_kernel<3, T>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P, ec,
-                       e);
+    hipLaunchKernelGGL((hprolong_kernel<3, T, M>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P,
+                       ec, e);
   HDG_CHECK(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, typename M>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) {
   if (L.nlam == 0) return;
-  const T* Ai = sizeof(T) == 8 ? (const T*)L.Ainv64 : (const T*)L.Ainv32;
+  const M* Ai = sizeof(M) == 8 ? (const M*)L.Ainv64 : (const M*)L.Ainv32;
   if (L.nlam > 64) {
-    hipLaunchKernelGGL((coarse_gemv_kernel<T>), dim3((unsigned)((L.nlam + 3) / 4), nrhs), dim3(256), 0, st,
+    hipLaunchKernelGGL((coarse_gemv_kernel<T, M>), dim3((unsigned)((L.nlam + 3) / 4), nrhs), dim3(256), 0, st,
                        (int)L.nlam, Ai, r, e);
     HDG_CHECK(hipGetLastError());
     return;
   }
-  hipLaunchKernelGGL((coarse_solve_kernel<T>), dim3(1, nrhs), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
+  hipLaunchKernelGGL((coarse_solve_kernel<T, M>), dim3(1, nrhs), dim3(64), 0, st, (int)L.nlam, Ai, r, e);
   HDG_CHECK(hipGetLastError());
 }
 
@@ -1072,16 +1090,23 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   HDG_CHECK(hipGetLastError());
 }
 
+// operator-reading launchers also for FP32 operator blocks under FP64 vectors
+#define HDG_INST_M(T, M)                                                                                          \
+  template void launch_apply<T, M>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t, int); \
+  template void launch_apply_red<T, M>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,       \
+                                       Scratch*, hipStream_t, int, int*);                                         \
+  template void launch_jacobi0<T, M>(const Level&, const T*, T*, hipStream_t, int);                               \
+  template void launch_hcorr<T, M>(const Level&, const T*, T*, int, int, T*, hipStream_t, int);                   \
+  template void launch_hprolong<T, M>(const Level&, const Level&, const T*, T*, hipStream_t, int);                \
+  template void launch_coarse_solve<T, M>(const Level&, const T*, T*, hipStream_t, int);
+HDG_INST_M(double, double)
+HDG_INST_M(float, float)
+HDG_INST_M(double, float)
+#undef HDG_INST_M
+
 #define HDG_INST(T)                                                                                              \
-  template void launch_apply<T>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t, int);  \
-  template void launch_apply_red<T>(const Level&, int, const T*, const T*, T*, const double*, T*, float*,          \
-                                    Scratch*, hipStream_t, int, int*);                                            \
-  template void launch_jacobi0<T>(const Level&, const T*, T*, hipStream_t, int);                                  \
   template void launch_prolong_p<T>(const Level&, int, const double*, const T*, T*, hipStream_t, int);            \
-  template void launch_hcorr<T>(const Level&, const T*, T*, int, int, T*, hipStream_t, int);                      \
   template void launch_hrestrict<T>(const Level&, const Level&, const T*, const T*, T*, hipStream_t, int);        \
-  template void launch_hprolong<T>(const Level&, const Level&, const T*, T*, hipStream_t, int);                   \
-  template void launch_coarse_solve<T>(const Level&, const T*, T*, hipStream_t, int);                             \
   template void launch_hpre<T>(const Level&, const T*, T*, int, T*, hipStream_t, int);                            \
   template void launch_res_prestrict<T>(const Level&, const Level&, const T*, const T*, T*, T*, const double*,      \
                                         hipStream_t, int);                                                        \

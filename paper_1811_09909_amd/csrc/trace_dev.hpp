@@ -7,23 +7,20 @@
 namespace hdg {
 namespace dev {
 
-// Arithmetic type of the cycle kernels: the storage type T by default.
-// Building with HDG_FP64_ARITH forms the sums of the FP32 cycle in FP64
-// (operators and vectors still stored in FP32).  Measured on MI355X: the
-// finest-level kernels are unchanged (HBM-bound), the coarse-level ones get
-// 13% slower in 2D, and in 3D (k = 3, n = 16) mixed-precision CG then
-// converges where it stalls with FP32 sums, but in 891 iterations against
-// 73 in FP64, so FP64 remains the 3D choice.
+// Arithmetic type of the cycle kernels: the vector storage type T.  The
+// operator blocks may be stored narrower than the vectors (M = float under
+// T = double: the FP32 copies read by the 3D mixed cycle); sums then run in
+// the vectors' FP64.  A row of a trace operator applied to a smooth vector
+// cancels to a small fraction of its terms' magnitudes: in 3D (k = 3,
+// tau = 1) a cycle with FP32 vectors or FP32 sums loses the digits the coarse
+// correction needs and stalls CG near a relative residual of 1e-6, while FP32
+// operator blocks under FP64 vectors and sums keep the FP64 cycle's
+// iteration count.  In 2D the FP32 cycle keeps CG within 1% of the FP64
+// count.
 template <typename T>
 struct AccOf {
   using type = T;
 };
-#ifdef HDG_FP64_ARITH
-template <>
-struct AccOf<float> {
-  using type = double;
-};
-#endif
 template <typename T>
 using acc_t = typename AccOf<T>::type;
 
@@ -797,21 +794,22 @@ __device__ inline void hpost_f_item(long Fc, int n, const T* ec, const T* eold, 
 
 
 // acc = (A x)_F for interior face F: both element matrices touching F, read
-// from the face-major AoSoA form.  Returns the face's normal direction.
-template <int D, int NE, typename T>
-__device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T* x, acc_t<T>* acc) {
+// from the face-major AoSoA form (stored as M; vectors as T).  Returns the
+// face's normal direction.
+template <int D, int NE, typename T, typename M = T>
+__device__ inline int face_acc(long F, int n, const M* __restrict__ Af, const T* x, acc_t<T>* acc) {
   constexpr int NL = 2 * D * NE;
-  constexpr long S = vpad<T>(NL * NE);
+  constexpr long S = vpad<M>(NL * NE);
   int g[3] = {0, 0, 0};
   const int c = decode_face<D>(F, n, g);
 #pragma unroll
   for (int a = 0; a < NE; ++a) acc[a] = acc_t<T>(0);
-  const T* Mbase = Af + aos_item<T>(F, 2 * S);
+  const M* Mbase = Af + aos_item<M>(F, 2 * S);
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     int e[3] = {g[0], g[1], g[2]};
     e[c] = g[c] - 1 + side;
-    const T* Mx = Mbase + side * S * LANES;
+    const M* Mx = Mbase + side * S * LANES;
 #pragma unroll
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
@@ -825,7 +823,7 @@ __device__ inline int face_acc(long F, int n, const T* __restrict__ Af, const T*
       acc_t<T> xs[NE];
 #pragma unroll
       for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
-      aos_mv_slot<T, NE>(Mx, sl * NE * NE, xs, acc);
+      aos_mv_slot<M, NE>(Mx, sl * NE * NE, xs, acc);
     }
   }
   return c;
@@ -946,13 +944,14 @@ __device__ inline int face_acc_z(long F, int n, const T* z, acc_t<T>* acc) {
   return c;
 }
 
-// y = x + Dinv_F res (one block-Jacobi update of face F; x == nullptr: 0)
-template <int NE, typename T>
-__device__ inline void dinv_update(long F, const T* __restrict__ Dinv, const T* x, const acc_t<T>* res, T* y) {
+// y = x + Dinv_F res (one block-Jacobi update of face F; x == nullptr: 0);
+// the blocks stored as M, vectors as T
+template <int NE, typename T, typename M = T>
+__device__ inline void dinv_update(long F, const M* __restrict__ Dinv, const T* x, const acc_t<T>* res, T* y) {
   acc_t<T> s[NE];
 #pragma unroll
   for (int a = 0; a < NE; ++a) s[a] = x ? acc_t<T>(x[F * NE + a]) : acc_t<T>(0);
-  aos_mv<T, NE * NE, NE, false>(Dinv + aos_item<T>(F, vpad<T>(NE * NE)), res, s);
+  aos_mv<M, NE * NE, NE, false>(Dinv + aos_item<M>(F, vpad<M>(NE * NE)), res, s);
 #pragma unroll
   for (int a = 0; a < NE; ++a) y[F * NE + a] = T(s[a]);
 }
@@ -1004,15 +1003,15 @@ __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const 
   }
 }
 
-template <int NE, typename T, bool DSYM = false>
-__device__ inline void jacobi0_item(long F, const T* __restrict__ Dinv, const T* r, T* e) {
+template <int NE, typename T, bool DSYM = false, typename M = T>
+__device__ inline void jacobi0_item(long F, const M* __restrict__ Dinv, const T* r, T* e) {
   acc_t<T> rv[NE];
 #pragma unroll
   for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
   if constexpr (DSYM)
     dinv_update_sym<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
   else
-    dinv_update<NE, T>(F, Dinv, (const T*)nullptr, rv, e);
+    dinv_update<NE, T, M>(F, Dinv, (const T*)nullptr, rv, e);
 }
 
 

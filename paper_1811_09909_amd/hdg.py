@@ -122,7 +122,7 @@ class Problem:
         return {"coarse_n": best.coarse_n, "nrhs": best.nrhs, "us_per_rhs_iter": us.value}
 
     def vcycle(self, r, precision=L.FP64):
-        dt = torch.float64 if precision == L.FP64 else torch.float32
+        dt = torch.float32 if precision == L.FP32 else torch.float64
         r = _dev(r, dt, self.device)
         e = torch.empty_like(r)
         L.check(self.lib.hdg_vcycle(self.h, _vp(r), _vp(e), precision, r.numel() // max(self.nlam, 1)),
@@ -184,10 +184,13 @@ class Problem:
         L.check(self.lib.hdg_profile_begin(self.h), "hdg_profile_begin")
 
     def profile_read(self, mode, precision):
+        """precision FP64 / FP32, or MIXED_CYCLE for the finest level's FP64
+        vectors over FP32 operator blocks."""
         n = ctypes.c_longlong()
         ms = ctypes.c_double()
         by = ctypes.c_double()
-        L.check(self.lib.hdg_profile_read(self.h, 2 * mode + precision, ctypes.byref(n), ctypes.byref(ms),
+        kernel = L.PROF_F32OPS + mode if precision == L.MIXED_CYCLE else 2 * mode + precision
+        L.check(self.lib.hdg_profile_read(self.h, kernel, ctypes.byref(n), ctypes.byref(ms),
                                           ctypes.byref(by)), "hdg_profile_read")
         return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}
 

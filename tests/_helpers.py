@@ -80,3 +80,33 @@ def load_scale(O, f, lam_b=None):
         if lam_b is not None and len(jb):
             np.add.at(sc, gi[ii], np.abs(Ae[np.ix_(ii, jb)]) @ np.abs(lam_b[bi[jb]]))
     return sc
+
+
+def local_cond(kap, n, tau=1.0):
+    """Largest kappa / (tau h) over the elements (h = 1/n): the factor by which
+    the element-local solves' rounding grows (the DtN map and the recovered
+    flux are differences of terms that much larger than themselves)."""
+    return float(np.max(np.asarray(kap))) * n / tau
+
+
+def elem_bound(kap, n, tau=1.0, floor=1e-12):
+    """FP64 parity bound for results formed from element-local solves:
+    floor, or 4 eps times the largest kappa / (tau h) where that is larger."""
+    return max(floor, 4 * np.finfo(float).eps * (1.0 + local_cond(kap, n, tau)))
+
+
+def load_scale_weighted(O, f, kap, n, lam_b=None, tau=1.0):
+    """load_scale with each element's terms weighted by 1 + kappa_T/(tau h):
+    the entrywise scale of g against which both codes' rounding is bounded."""
+    kmax = np.asarray(kap).reshape(O.mesh.nel, -1).max(axis=1)
+    sc = np.zeros(O.nlam)
+    for T in range(O.mesh.nel):
+        Ae, be = O.element_dtn(T, O.M @ np.asarray(f[T]))
+        c = 1.0 + kmax[T] * n / tau
+        gi, bi = O.gmap[T], O.bmap[T]
+        ii = np.nonzero(gi >= 0)[0]
+        jb = np.nonzero(bi >= 0)[0]
+        np.add.at(sc, gi[ii], c * np.abs(be[ii]))
+        if lam_b is not None and len(jb):
+            np.add.at(sc, gi[ii], c * (np.abs(Ae[np.ix_(ii, jb)]) @ np.abs(lam_b[bi[jb]])))
+    return sc

@@ -203,44 +203,41 @@ def test_fullsize_benchmark_solve(big2d, torch_cuda):
 
 def test_fullsize_fp64_and_mixed_agree(big2d, torch_cuda):
     """Plain FP64 and mixed precision (FP32 V-cycle inside FP64 refinement)
-    solve the same system: at the benchmark tolerance both residuals are
-    below it and the mixed solve takes no more iterations than FP64 (+5%);
-    driven to the FP64 floor of the residual, the mixed trace, u and q agree
-    with the FP64 ones to 1e-9 relative."""
+    solve the same system.  At this size the FP64 floor of the relative
+    residual is about 6e-11 (CG run on past the tolerance does not go
+    lower), so the benchmark's solves to 1e-10 are at the floor: both
+    residuals are below the tolerance, the mixed solve takes no more
+    iterations than FP64 (+5%), and its trace, u and q agree with the FP64
+    ones to 1e-9 relative."""
     from paper_1811_09909_amd import _lib as L
     wl, O, P, fids, rng = big2d
     S = _bench_solver()
     f = torch_cuda.as_tensor(wl.f)
 
-    def build(prec, max_it):
+    def build(prec):
         P.build(sweeps=S["sweeps"], growth=S["growth"], local_corr=L.LC_BOTH, precision=prec, method=L.METHOD_PCG,
-                max_it=max_it, coarse_n=S["coarse_n"])
+                max_it=S["max_it"], coarse_n=S["coarse_n"])
 
     g = P.rhs(f)
     out = {}
     try:
         for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
-            build(prec, S["max_it"])
+            build(prec)
             lam, info = P.solve(f, tol=S["tol"])
             rel = float((g - P.level_apply(0, lam)).norm() / g.norm())
-            build(prec, info["iters"] + 300)
-            lamf, infof = P.solve(f, tol=1e-13, allow_not_converged=True)
-            relf = float((g - P.level_apply(0, lamf)).norm() / g.norm())
-            u, q = P.reconstruct(lamf, f)
-            out[nm] = (info, rel, lamf, relf, u, q, infof)
-            say(f"  {nm}: {info['iters']} iterations ({info['outer_iters']} true residuals) relres {rel:.2e}; "
-                f"floor run {infof['iters']} iterations relres {relf:.2e}")
+            u, q = P.reconstruct(lam, f)
+            out[nm] = (info, rel, lam, u, q)
+            say(f"  {nm}: {info['iters']} iterations ({info['outer_iters']} true residuals) relres {rel:.2e}")
     finally:
-        build(L.MIXED, S["max_it"])
-    i64, r64, l64, f64, u64, q64, _ = out["fp64"]
-    imx, rmx, lmx, fmx, umx, qmx, _ = out["mixed"]
+        build(L.MIXED)
+    i64, r64, l64, u64, q64 = out["fp64"]
+    imx, rmx, lmx, umx, qmx = out["mixed"]
     el = float((lmx - l64).norm() / l64.norm())
     eu = float((umx - u64).norm() / u64.norm())
     eq = float((qmx - q64).norm() / q64.norm())
-    say(f"  at the floor: mixed vs FP64 lambda {el:.2e} u {eu:.2e} q {eq:.2e}")
+    say(f"  mixed vs FP64: lambda {el:.2e} u {eu:.2e} q {eq:.2e}")
     assert r64 <= 1.05 * S["tol"] and rmx <= 1.05 * S["tol"]
     assert imx["iters"] <= 1.05 * i64["iters"] + 5
-    assert f64 <= 1e-10 and fmx <= 1e-10
     assert el <= 1e-9 and eu <= 1e-9 and eq <= 1e-9
 
 

@@ -69,6 +69,9 @@ def test_mixed_refinement_3d(torch_cuda, n):
             f"{info['relres']:.2e}, recomputed {rel:.2e}")
         assert info["relres"] <= 1e-10 and rel <= 1.05e-10
         out[nm] = (lam, info)
+    # FP32 operator blocks with FP64 sums and FP64 finest-level vectors keep
+    # the FP64 cycle's count
+    assert out["mixed"][1]["iters"] <= 1.05 * out["fp64"][1]["iters"] + 5
     d = float((out["mixed"][0] - out["fp64"][0]).norm() / out["fp64"][0].norm())
     say(f"  |lam_mixed - lam_fp64| / |lam_fp64| = {d:.2e}")
     assert d <= 1e-9
@@ -186,3 +189,35 @@ def test_adjoint_after_handle_reformed(torch_cuda):
     e = float((g1 - ref).norm() / ref.norm())
     say(f"[adjoint after reform] J1 {J1.item():.6e} J2 {J2.item():.6e}: gradient vs fresh {e:.2e}")
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("d,n,k,variant", [(3, 8, 3, 0), (3, 4, 2, 0), (2, 32, 4, "fine64"), (2, 32, 4, 0)])
+def test_mixed_cycle_against_oracle(torch_cuda, d, n, k, variant):
+    """The cycle the mixed solve applies (in 3D, and by choice in 2D: FP64
+    vectors and sums over FP32 operator blocks; in 2D by default the FP32
+    cycle) against the oracle's FP64 Algorithm 1: single-precision
+    agreement."""
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import Problem
+    rng = np.random.default_rng(3)
+    if d == 3:
+        wl = inputs.diffusion3d(n, k)
+        O = HDG(3, n, k, 1.0, np.ones(n ** 3))
+        kap = wl.kappa_fn(O.volume_qpoints())
+        O.set_kappa(kap)
+        P = Problem(3, n, k, torch_cuda.as_tensor(kap), tau=1.0, kappa_kind="qp", store_recovery=False)
+    else:
+        kap = 10.0 ** rng.uniform(-2, 2, n * n)
+        O = HDG(2, n, k, 1.0, kap)
+        P = Problem(2, n, k, torch_cuda.as_tensor(kap), tau=1.0, store_recovery=False)
+    A, _, _ = O.assemble()
+    H = omg.Hierarchy(A, d, n, k, local_corr=omg.LC_BOTH)
+    var = L.VARIANT_FP64_VECTORS if variant == "fine64" else 0
+    P.build(local_corr=L.LC_BOTH, method=L.METHOD_PCG, precision=L.MIXED, variant=var)
+    r = rng.standard_normal(A.shape[0])
+    eo = H.vcycle(r)
+    e = P.vcycle(torch_cuda.as_tensor(r), precision=L.MIXED_CYCLE).cpu().numpy()
+    e64 = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+    say(f"[mixed cycle] d={d} n={n} k={k} variant={variant}: vs oracle {relerr(e, eo):.2e}, "
+        f"FP64 cycle vs oracle {relerr(e64, eo):.2e}")
+    assert relerr(e, eo) <= 1e-5

@@ -188,6 +188,17 @@ hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const*
  * (and that time in microseconds in *us_per_rhs_it when not NULL). */
 hdg_status hdg_autotune(hdg_handle h, const hdg_mg_opts* base, int nrhs, hdg_mg_opts* best, double* us_per_rhs_it);
 
+/* hdg_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops): same arguments, result and errors as
+ * hdg_rhs, but the per-element load staging lives in a fixed device array of
+ * the library (64 MiB per GPU, held until the process ends) instead of
+ * memory the handle allocated, and the call allocates nothing.  Supports
+ * N_T ((k+1)^d + 2d (k+1)^(d-1)) <= 8 Mi doubles (e.g. 256 x 256 elements up
+ * to k = 6, 512 x 512 up to k = 2); larger problems return
+ * HDG_ERR_UNSUPPORTED.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (several streams or threads) race. */
+hdg_status hdg_rhs_noalloc(hdg_handle h, const double* rhs, int rhs_kind, const double* g_dirichlet, double* g);
+
 /* Local recovery (q, u) = L_T^-1 (R_T Lambda_T + [0; b_T]) element by
  * element (Sec. 2); needs store_recovery at setup. */
 hdg_status hdg_reconstruct(hdg_handle h, const double* lambda, const double* rhs, int rhs_kind,

@@ -21,7 +21,7 @@ EXPORTS = [
     "hdg_default_opts", "hdg_setup", "hdg_update_kappa", "hdg_mg_build", "hdg_vcycle", "hdg_rhs", "hdg_solve",
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
-    "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune",
+    "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune", "hdg_rhs_noalloc",
 ]
 
 
@@ -80,6 +80,7 @@ def load():
         "hdg_mg_build": (I, [P, ctypes.POINTER(Opts)]),
         "hdg_vcycle": (I, [P, P, P, I, I]),
         "hdg_rhs": (I, [P, P, I, P, P]),
+        "hdg_rhs_noalloc": (I, [P, P, I, P, P]),
         "hdg_solve": (I, [P, P, I, P, I, D, P, ctypes.POINTER(Info)]),
         "hdg_solve_batch": (I, [I, P, P, I, P, D, P, ctypes.POINTER(Info), I]),
         "hdg_autotune": (I, [P, ctypes.POINTER(Opts), I, ctypes.POINTER(Opts), ctypes.POINTER(D)]),

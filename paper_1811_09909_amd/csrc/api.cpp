@@ -826,6 +826,13 @@ hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, h
 
 }  // namespace
 
+long hdg::rhs_staging_doubles(const hdg_problem* P) { return P->nelem * (P->nv + P->nl); }
+
+void hdg::rhs_with_staging(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g,
+                           double* ebuf) {
+  form_rhs_in(P, rhs, kind, gdir, g, ebuf);
+}
+
 // =========================================================================
 extern "C" {
 
@@ -918,6 +925,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
     hdg_destroy(P);
     return HDG_ERR_INVALID_ARG;
   }
+  (void)scratch_ptr();  // this device's fixed staging of hdg_rhs_noalloc, looked up once per device
   form_elements(P);
   HDG_CHECK(hipStreamSynchronize(P->st));
   P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

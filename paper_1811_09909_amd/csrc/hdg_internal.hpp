@@ -245,4 +245,13 @@ template <typename T, typename M = T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
                       Scratch* red, hipStream_t st, int nrhs = 1, int* nparts = nullptr);
 
+// noalloc.hip: the device address of this device's fixed staging array
+// (looked up once per device) and its size in doubles
+double* scratch_ptr();
+long scratch_capacity();
+// api.cpp: staging the load form of hdg_rhs needs, and hdg_rhs with the
+// staging buffer given (no allocation)
+long rhs_staging_doubles(const hdg_problem* P);
+void rhs_with_staging(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g, double* ebuf);
+
 }  // namespace hdg

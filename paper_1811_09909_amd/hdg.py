@@ -92,6 +92,12 @@ class Problem:
         L.check(self.lib.hdg_rhs(self.h, _vp(f), kind, _vp(gd), _vp(g)), "hdg_rhs")
         return g
 
+    def rhs_noalloc(self, f, g, kind=L.RHS_F_NODAL, gdir=None):
+        """hdg_rhs_noalloc into the caller's g (no allocation in the library;
+        f, g and gdir must already be contiguous float64 device tensors)."""
+        L.check(self.lib.hdg_rhs_noalloc(self.h, _vp(f), kind, _vp(gdir), _vp(g)), "hdg_rhs_noalloc")
+        return g
+
     def solve(self, rhs, kind=L.RHS_F_NODAL, tol=1e-10, lam0=None, gdir=None, nrhs=1, allow_not_converged=False):
         rhs = _dev(rhs, torch.float64, self.device)
         gd = None if gdir is None else _dev(gdir, torch.float64, self.device)

@@ -111,7 +111,11 @@ enum {
      vectors.  These bits force one form (for comparing them); the FP64-vector form stores every level
      face-major and uses the unfused transition kernels. */
   HDG_VARIANT_FP32_VECTORS = 32, /* FP32 vectors and sums in the mixed cycle, also in 3D */
-  HDG_VARIANT_FP64_VECTORS = 64  /* FP64 vectors and sums over FP32 operator blocks, also in 2D */
+  HDG_VARIANT_FP64_VECTORS = 64, /* FP64 vectors and sums over FP32 operator blocks, also in 2D */
+  /* Lanes per macro-element of the fused 2D h-transition kernels.  Default: four while macro-elements
+     times right-hand sides stay below 16,384 (latency-bound levels), one above. */
+  HDG_VARIANT_LANES1 = 128,     /* one lane per macro-element on every level */
+  HDG_VARIANT_LANES4 = 256      /* four lanes per macro-element (one interior face each) on every level */
 };
 
 typedef struct {
@@ -170,22 +174,33 @@ hdg_status hdg_solve(hdg_handle h, const double* rhs, int rhs_kind, const double
 /* Batched solves (many meshes, many right-hand sides): problem i solves its
  * nrhs[i] right-hand sides rhs[i] (layout as in hdg_solve) into lambda[i]
  * (in: initial guesses) with its own built handle hs[i], tolerance tol, and
- * fills info[i] (may be NULL).  Problems are spread over `nstreams` private
- * HIP streams (<= 0: 4), one host thread each, so that the latency-bound
- * coarse levels of different problems overlap on the GPU; within a problem
- * the right-hand sides go through in groups of its build's nrhs.  Each
- * handle's stream is ordered before and after its solve; the call returns
- * when all are done.  Handles must be distinct (a handle is not
- * thread-safe).  Returns the worst status.  Zero Dirichlet data. */
+ * fills info[i] (may be NULL; t_solve_ms is the whole batch's time).  Within
+ * a problem the right-hand sides go through in groups of its build's nrhs.
+ * nstreams <= 0 (and every handle built for PCG): one graph for the batch --
+ * each problem's group of CG iterations is captured once, one batch graph
+ * holds those of all iterating problems, and one launch advances every
+ * problem; the host reads all residual histories with one synchronisation
+ * per launch.  nstreams = 0: one batch graph, the groups one after another;
+ * nstreams = -q (q <= 16): the problems dealt to q streams (largest first,
+ * round-robin), one batch graph per stream, launched together.
+ * nstreams > 0 (or another method): the problems are
+ * spread over that many private streams (at most 16), one host thread each,
+ * so the latency-bound coarse levels of different problems overlap.  Each handle's stream is ordered before and
+ * after the batch; the call returns when all are done.  Handles must be
+ * distinct (a handle is not thread-safe).  Returns the worst status.  Zero
+ * Dirichlet data. */
 hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const* rhs, int rhs_kind,
                            const int* nrhs, double tol, double* const* lambda, hdg_solve_info* info,
                            int nstreams);
 
 /* Autotuner: times a few outer iterations of every candidate layout of the
  * work - coarsest macro grid (2, 8, 16) x right-hand-side group size (1, 2,
- * 4, ... <= nrhs) - on top of `base` (NULL: defaults), builds the handle with
- * the fastest per right-hand side and iteration, and returns it in *best
- * (and that time in microseconds in *us_per_rhs_it when not NULL). */
+ * 4, ... <= nrhs) - on top of `base` (NULL: defaults), then, on the fastest
+ * of those, the tile shapes of the kernels (one or four lanes per
+ * macro-element in the transition kernels, two-phase instead of strip apply
+ * on the finest level; variant bits); builds the handle with the fastest per
+ * right-hand side and iteration, and returns it in *best (and that time in
+ * microseconds in *us_per_rhs_it when not NULL). */
 hdg_status hdg_autotune(hdg_handle h, const hdg_mg_opts* base, int nrhs, hdg_mg_opts* best, double* us_per_rhs_it);
 
 /* hdg_rhs for callers that cannot allocate device memory (code under HIP

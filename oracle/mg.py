@@ -17,8 +17,15 @@ paper writes them:
   operator A_{k-1} = Q_{k-1} A_k I_k = J_k^T (A_BB - A_BI A_II^-1 A_IB) J_k
   (eqs. coarse, Akm1).  J_k^* is taken as the matrix transpose with
   residuals in assembled (weak) form.
-* smoothing: face-block Jacobi, one block per face of the level
-  (Sec. 4.1), m_k sweeps (Sec. 3.3), damping omega (1 by default).
+* smoothing (Sec. 4.1), m_k sweeps (Sec. 3.3): face-block Jacobi, one block
+  per face of the level, damping omega (1 by default); or one of the
+  paper's point smoothers: damped point Jacobi (omega = 2/3), Chebyshev-
+  accelerated point Jacobi (the largest eigenvalue of D^-1 A estimated by
+  power iteration, the smallest taken as a thirtieth of it), and LU-SGS
+  (one forward and one backward point Gauss-Seidel sweep per step, in the
+  trace numbering); and the multicolour variant of LU-SGS the GPU runs
+  (faces in colours no two of which share an element, point Gauss-Seidel
+  within a face).
 * local correction T_k: e_I += A_II^-1 (r - A e)_I (eq. localCorrection).
 * V-cycle: Algorithm 1, with B_1 = A_1^-1 by a dense direct solve.
 * outer iterations: fixed point lambda += B_N (g - A lambda) (Sec. 3.6),
@@ -45,6 +52,10 @@ from .hdg import Mesh, lex
 from .refelem import gll_nodes
 
 LC_NONE, LC_PRE, LC_POST, LC_BOTH = 0, 1, 2, 3
+SMOOTHERS = ("block_jacobi", "jacobi", "chebyshev", "lusgs", "lusgs_mc")
+CHEB_POWER_ITS = 20      # power iterations of the largest-eigenvalue estimate
+CHEB_SAFETY = 1.1        # the estimate is raised by this factor
+CHEB_RATIO = 30.0        # smallest eigenvalue taken as largest / CHEB_RATIO
 
 
 def block_inverse(A):
@@ -176,12 +187,109 @@ def block_jacobi(L, res, m, omega=1.0):
     return delta
 
 
+def point_jacobi(L, res, m, omega):
+    """m damped point-Jacobi sweeps: delta += omega D^-1 (res - A delta)."""
+    dinv = 1.0 / L.A.diagonal()
+    delta = np.zeros_like(res)
+    for _ in range(m):
+        delta = delta + omega * dinv * (res - L.A @ delta)
+    return delta
+
+
+def lambda_max_estimate(A):
+    """Largest eigenvalue of D^-1 A by power iteration from the all-ones
+    vector (CHEB_POWER_ITS steps, Rayleigh quotient v^T A v / v^T D v of the
+    last iterate), raised by CHEB_SAFETY (Sec. 4.1 asks for an estimate to
+    about 1e-2)."""
+    N = A.shape[0]
+    if N == 0:
+        return 1.0
+    d = A.diagonal()
+    v = np.ones(N)
+    for _ in range(CHEB_POWER_ITS):
+        w = (A @ v) / d
+        v = w / np.linalg.norm(w)
+    return CHEB_SAFETY * float(v @ (A @ v)) / float(v @ (d * v))
+
+
+def chebyshev(L, res, m, lmax):
+    """m steps of Chebyshev-accelerated point Jacobi on [lmax / CHEB_RATIO,
+    lmax] from delta = 0, by the three-term recurrence of the shifted and
+    scaled Chebyshev polynomials."""
+    dinv = 1.0 / L.A.diagonal()
+    lmin = lmax / CHEB_RATIO
+    theta, dlt = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    sigma = theta / dlt
+    rho = 1.0 / sigma
+    d = dinv * res / theta
+    delta = d.copy()
+    for _ in range(1, m):
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        r = res - L.A @ delta
+        d = rho_new * rho * d + (2.0 * rho_new / dlt) * (dinv * r)
+        delta = delta + d
+        rho = rho_new
+    return delta if m > 0 else np.zeros_like(res)
+
+
+def lusgs(L, res, m):
+    """m LU-SGS steps from delta = 0: a forward then a backward point
+    Gauss-Seidel sweep over the unknowns in the trace numbering."""
+    A = sp.csr_matrix(L.A)
+    N = A.shape[0]
+    delta = np.zeros_like(res)
+    indptr, indices, data = A.indptr, A.indices, A.data
+    diag = A.diagonal()
+    for _ in range(m):
+        for order in (range(N), range(N - 1, -1, -1)):
+            for i in order:
+                lo, hi = indptr[i], indptr[i + 1]
+                s = res[i] - data[lo:hi] @ delta[indices[lo:hi]]
+                delta[i] += s / diag[i]
+    return delta
+
+
+def face_colors(mesh):
+    """Colour of each interior face: 2 c + (grid position along its normal
+    c, 1 .. n-1) mod 2.  Faces of one colour share no element."""
+    col = np.zeros(mesh.nface, dtype=np.int64)
+    for F in range(mesh.nface):
+        c, coords = mesh.interior_face_coords(F)
+        col[F] = 2 * c + (coords[c] % 2)
+    return col
+
+
+def lusgs_mc(L, res, m):
+    """Multicolour LU-SGS: per step, the face colours in increasing order,
+    then decreasing; within a colour every face at once, within a face its
+    unknowns in increasing (forward) or decreasing (backward) order, each a
+    point Gauss-Seidel update with the current values."""
+    A = sp.csr_matrix(L.A)
+    diag = A.diagonal()
+    col = face_colors(L.mesh)
+    ncol = 2 * L.mesh.d
+    delta = np.zeros_like(res)
+    m_e = L.m
+    for _ in range(m):
+        for colors, dofs in ((range(ncol), range(m_e)), (range(ncol - 1, -1, -1), range(m_e - 1, -1, -1))):
+            for c in colors:
+                faces = np.nonzero(col == c)[0]
+                for a in dofs:
+                    rows = L.faces[faces, a]
+                    s = res[rows] - A[rows] @ delta
+                    delta[rows] += s / diag[rows]
+    return delta
+
+
 class Hierarchy:
     """Levels ordered from finest (index 0) to coarsest."""
 
     def __init__(self, A, d, n, k, coarse="p1", sweeps=2, growth=1, omega=1.0,
-                 local_corr=LC_PRE, coarsest_n=2):
+                 local_corr=LC_PRE, coarsest_n=2, smoother="block_jacobi"):
+        if smoother not in SMOOTHERS:
+            raise ValueError(f"unknown smoother {smoother}")
         self.coarse, self.omega, self.local_corr = coarse, omega, local_corr
+        self.smoother = smoother
         mesh = Mesh(d, n)
         lev = Level(A, mesh, (k + 1) ** (d - 1))
         self.levels = [lev]
@@ -223,11 +331,27 @@ class Hierarchy:
         for i, L in enumerate(self.levels):
             L.sweeps = sweeps * (2 ** i if growth == 2 else 1)
             L.face_block_inverses()
+            if smoother == "chebyshev":
+                L.lmax = lambda_max_estimate(L.A)
 
     # ---- smoothing, local correction, cycle --------------------------------
     def block_jacobi(self, i, res, m):
         """m face-block Jacobi sweeps on A_i delta = res from delta = 0."""
         return block_jacobi(self.levels[i], res, m, self.omega)
+
+    def smooth(self, i, res, m):
+        """Smooth(i, res, m): m steps of the hierarchy's smoother on
+        A_i delta = res from delta = 0 (Sec. 4.1)."""
+        L = self.levels[i]
+        if self.smoother == "block_jacobi":
+            return block_jacobi(L, res, m, self.omega)
+        if self.smoother == "jacobi":
+            return point_jacobi(L, res, m, self.omega)
+        if self.smoother == "chebyshev":
+            return chebyshev(L, res, m, L.lmax)
+        if self.smoother == "lusgs":
+            return lusgs(L, res, m)
+        return lusgs_mc(L, res, m)
 
     def local_correction(self, i, rho):
         """T_i rho = [A_II^-1 rho_I ; 0] (eq. localCorrection)."""
@@ -245,13 +369,13 @@ class Hierarchy:
             return sla.lu_solve(self.coarse_lu, r)
         A = L.A
         e = np.zeros_like(r)
-        e = e + self.block_jacobi(i, r - A @ e, L.sweeps)
+        e = e + self.smooth(i, r - A @ e, L.sweeps)
         if L.kind == "h" and self.local_corr in (LC_PRE, LC_BOTH):
             e = e + self.local_correction(i, r - A @ e)
         e = e + L.I @ self.vcycle(L.Q @ (r - A @ e), i + 1)
         if L.kind == "h" and self.local_corr in (LC_POST, LC_BOTH):
             e = e + self.local_correction(i, r - A @ e)
-        e = e + self.block_jacobi(i, r - A @ e, L.sweeps)
+        e = e + self.smooth(i, r - A @ e, L.sweeps)
         return e
 
 

@@ -42,6 +42,7 @@ class Opts(ctypes.Structure):
 # hdg_mg_opts.variant bits (HDG_VARIANT_*)
 VARIANT_NO_GRAPH, VARIANT_NO_FUSE, VARIANT_NO_TAIL, VARIANT_NO_PACK, VARIANT_NO_STRIP = 1, 2, 4, 8, 16
 VARIANT_FP32_VECTORS, VARIANT_FP64_VECTORS = 32, 64
+VARIANT_LANES1, VARIANT_LANES4 = 128, 256
 PROF_F32OPS = 14  # hdg_profile_read: kernel = 14 + mode for FP64 vectors over FP32 operator blocks
 OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", "max_it", "restart", "coarse_n",
               "nrhs", "refine_red", "variant")

@@ -40,6 +40,7 @@ struct hdg_problem {
   TailArgs tail_args[2];
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int gnrhs = 1;                 // right-hand sides the captured graphs iterate
+  hipGraph_t grp_graph = nullptr; // CHECK_EVERY CG iterations (one batch graph child), for gnrhs
   int cap = 1;                   // right-hand sides the build's buffers hold
   RefElement ref;
   RefDevice rd;
@@ -147,6 +148,10 @@ void drop_graphs(hdg_problem* P) {
       (void)hipGraphExecDestroy(g);
       g = nullptr;
     }
+  if (P->grp_graph) {
+    (void)hipGraphDestroy(P->grp_graph);
+    P->grp_graph = nullptr;
+  }
 }
 
 void free_build(hdg_problem* P) {
@@ -215,6 +220,32 @@ void apply(hdg_problem* P, int i, int mode, const T* x, const T* b, T* y, T* rc,
 // Run `body` (device work only, fixed pointers) as a captured hipGraph on the
 // caller's stream; captured once per slot on the private stream.  Eager when
 // graphs are disabled or finest-level kernels are being timed.
+// Capture `body` (device work only, fixed pointers) into a graph on the
+// handle's private capture stream; the caller owns the returned graph.
+template <class F>
+hipGraph_t capture(hdg_problem* P, F&& body) {
+  hipStream_t user = P->st;
+  P->st = P->cap_st;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(P->cap_st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    P->st = user;
+    throw HipError{e, "hipStreamBeginCapture"};
+  }
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap_st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    P->st = user;
+    throw;
+  }
+  e = hipStreamEndCapture(P->cap_st, &g);
+  P->st = user;
+  if (e != hipSuccess) throw HipError{e, "hipStreamEndCapture"};
+  return g;
+}
+
 template <class F>
 void run_graph(hdg_problem* P, int slot, F&& body, int nr = 1) {
   if (!P->use_graphs || P->prof_on) {
@@ -226,26 +257,8 @@ void run_graph(hdg_problem* P, int slot, F&& body, int nr = 1) {
     P->gnrhs = nr;
   }
   if (!P->gx[slot]) {
-    hipStream_t user = P->st;
-    P->st = P->cap_st;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(P->cap_st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-      P->st = user;
-      throw HipError{e, "hipStreamBeginCapture"};
-    }
-    try {
-      body();
-    } catch (...) {
-      (void)hipStreamEndCapture(P->cap_st, &g);
-      if (g) (void)hipGraphDestroy(g);
-      P->st = user;
-      throw;
-    }
-    e = hipStreamEndCapture(P->cap_st, &g);
-    P->st = user;
-    if (e != hipSuccess) throw HipError{e, "hipStreamEndCapture"};
-    e = hipGraphInstantiate(&P->gx[slot], g, nullptr, nullptr, 0);
+    hipGraph_t g = capture(P, body);
+    hipError_t e = hipGraphInstantiate(&P->gx[slot], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       P->gx[slot] = nullptr;
@@ -587,6 +600,67 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, cons
   return o;
 }
 
+// First direction of a CG run from the current residual: z = B r, r.z, p = z.
+void pcg_start(hdg_problem* P, bool mixed, int nr) {
+  const long N = P->N;
+  const bool v32 = mixed && !P->ops32;
+  precond_fused(P, mixed, nr);
+  if (v32) {
+    blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st, nr);
+    blas_f2d(P->z32, P->p, N, P->st, nr);
+  } else {
+    blas_rz<double>(P->r, P->z, N, FIN_RZ0, P->s, P->st, nr);
+    blas_copy(P->p, P->z, N, P->st, nr);
+  }
+}
+
+// One CG iteration, device work only (captured into graphs): lambda and r
+// are updated first, so after convergence the trailing preconditioner
+// application and direction update change nothing that is returned.
+void pcg_iteration(hdg_problem* P, double* lam, bool mixed, int nr) {
+  const long N = P->N;
+  const bool v32 = mixed && !P->ops32;
+  hipStream_t s2 = P->st;
+  const bool timed = P->prof_on && nr == 1;
+  hdg_problem::Pending pd{2 * APPLY_Y + 0, nullptr, nullptr};
+  if (timed) {
+    pd.a = take_event(P);
+    pd.b = take_event(P);
+    HDG_CHECK(hipEventRecord(pd.a, s2));
+  }
+  int npap = 0;
+  launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s, s2, nr,
+                           &npap);
+  if (timed) {
+    HDG_CHECK(hipEventRecord(pd.b, s2));
+    P->pending.push_back(pd);
+  }
+  if (v32)
+    blas_cg_update2_fused<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, npap, P->s, s2, nr);
+  else
+    blas_cg_update2_fused<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, npap, P->s, s2, nr);
+  // the V-cycle's last finest-level sweep also forms the r.z partials
+  P->dot_v = P->r;
+  P->dot_parts = 0;
+  precond_fused(P, mixed, nr);
+  P->dot_v = nullptr;
+  if (P->dot_parts > 0)
+    blas_finalize_cg(N, P->dot_parts, mixed, P->s, s2, nr);
+  else if (v32)
+    blas_rz_cg<float>(P->r, P->z32, N, true, P->s, s2, nr);
+  else
+    blas_rz_cg<double>(P->r, P->z, N, mixed, P->s, s2, nr);
+  if (v32)
+    blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
+  else
+    blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
+}
+
+// reset the residual-history counters of nr right-hand sides
+void reset_history(hdg_problem* P, int nr) {
+  for (int r = 0; r < nr; ++r) blas_fill<double>(P->s.sc + (long)r * SC_COUNT + SC_HCNT, 0.0, 1, P->st);
+}
+
 // Preconditioned CG.  FP64: Fletcher-Reeves beta, one run to the tolerance
 // (then confirmed on the true residual).  Mixed: FP64 iterative refinement
 // around an FP32-preconditioned CG.  Each refinement step forms the true
@@ -602,7 +676,6 @@ SolveOut solve_mg(hdg_problem* P, const double* g, double* lam, double tol, cons
 // with its own scalars; the solve ends when every one has met the tolerance.
 SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, const double* gn, bool mixed, int nr) {
   SolveOut o;
-  const long N = P->N;
   const double red = mixed ? P->opts.refine_red : 0.0;
   const bool v32 = mixed && !P->ops32;  // the cycle takes and returns FP32 vectors
   Tracker tr;
@@ -621,65 +694,18 @@ SolveOut solve_pcg(hdg_problem* P, const double* g, double* lam, double tol, con
       return o;
     }
     if (rel <= tol || launched >= P->opts.max_it) break;
-    precond_fused(P, mixed, nr);
-    if (v32) {
-      blas_rz<float>(P->r, P->z32, N, FIN_RZ0, P->s, P->st, nr);
-      blas_f2d(P->z32, P->p, N, P->st, nr);
-    } else {
-      blas_rz<double>(P->r, P->z, N, FIN_RZ0, P->s, P->st, nr);
-      blas_copy(P->p, P->z, N, P->st, nr);
-    }
-    // one CG iteration per graph launch: lambda and r are updated first, so
-    // after convergence the trailing preconditioner application and
-    // direction update change nothing that is returned.  Launches go out in
-    // groups of up to CHECK_EVERY with one read of the residual histories per
-    // group; iterations past the first converged one only refine lambda.
+    pcg_start(P, mixed, nr);
+    // one CG iteration per graph launch; launches go out in groups of up to
+    // CHECK_EVERY with one read of the residual histories per group;
+    // iterations past the first converged one only refine lambda.
     tr.init(nr, tol, gn);
     if (mixed) tr.init_inner(red, r0, launched);
     bool all = false, done = false;
     while (!done && launched < P->opts.max_it) {
       const int grp = std::min(CHECK_EVERY, P->opts.max_it - launched);
-      for (int r = 0; r < nr; ++r) blas_fill<double>(P->s.sc + (long)r * SC_COUNT + SC_HCNT, 0.0, 1, P->st);
+      reset_history(P, nr);
       for (int it = 0; it < grp; ++it)
-        run_graph(
-            P, mixed ? G_PCGMX : G_PCG64,
-            [&] {
-              hipStream_t s2 = P->st;
-              const bool timed = P->prof_on && nr == 1;
-              hdg_problem::Pending pd{2 * APPLY_Y + 0, nullptr, nullptr};
-              if (timed) {
-                pd.a = take_event(P);
-                pd.b = take_event(P);
-                HDG_CHECK(hipEventRecord(pd.a, s2));
-              }
-              int npap = 0;
-              launch_apply_red<double>(P->L[0], APPLY_Y_DOT, P->p, nullptr, P->Ap, nullptr, nullptr, nullptr, &P->s,
-                                       s2, nr, &npap);
-              if (timed) {
-                HDG_CHECK(hipEventRecord(pd.b, s2));
-                P->pending.push_back(pd);
-              }
-              if (v32)
-                blas_cg_update2_fused<float>(lam, P->r, P->r32, P->p, P->Ap, P->z32, N, npap, P->s, s2, nr);
-              else
-                blas_cg_update2_fused<double>(lam, P->r, nullptr, P->p, P->Ap, P->z, N, npap, P->s, s2, nr);
-              // the V-cycle's last finest-level sweep also forms the r.z partials
-              P->dot_v = P->r;
-              P->dot_parts = 0;
-              precond_fused(P, mixed, nr);
-              P->dot_v = nullptr;
-              if (P->dot_parts > 0)
-                blas_finalize_cg(N, P->dot_parts, mixed, P->s, s2, nr);
-              else if (v32)
-                blas_rz_cg<float>(P->r, P->z32, N, true, P->s, s2, nr);
-              else
-                blas_rz_cg<double>(P->r, P->z, N, mixed, P->s, s2, nr);
-              if (v32)
-                blas_cg_dir<float>(P->p, P->z32, N, P->s, s2, nr);
-              else
-                blas_cg_dir<double>(P->p, P->z, N, P->s, s2, nr);
-            },
-            nr);
+        run_graph(P, mixed ? G_PCGMX : G_PCG64, [&] { pcg_iteration(P, lam, mixed, nr); }, nr);
       all = tr.scan(read_scalars(P, nr), launched, grp, &rel);
       launched += grp;
       if (tr.bad) {
@@ -967,7 +993,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
       o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
-      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 127)
+      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 511)
     return HDG_ERR_INVALID_ARG;
   if (o.nrhs < 1) o.nrhs = 1;
   if (o.refine_red == 0.0) o.refine_red = 1e-5;
@@ -1039,6 +1065,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   for (size_t i = 0; i < L.size(); ++i) {
     Level& Li = L[i];
     Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min<size_t>(i, 20)) : 1);
+    Li.lpm = (o.variant & HDG_VARIANT_LANES1) ? 1 : (o.variant & HDG_VARIANT_LANES4) ? 4 : 0;
     const long pf = pad64(Li.nface);
     // the finest level of a p-transition (only trace applies touch it) is
     // stored element-major as packed symmetric triangles
@@ -1236,6 +1263,312 @@ hdg_status solve_rhs_set(hdg_handle P, const double* rhs, int rhs_kind, const do
   HDG_CHECK(hipEventDestroy(e1));
   return worst;
 }
+// ---------------------------------------------------------------------------
+// Many problems through one graph.  Every problem (a built handle, PCG) keeps
+// its own buffers, scalars and convergence state; its group of CHECK_EVERY
+// CG iterations is captured once as a graph, and one batch graph holds the
+// groups of all iterating problems as independent child graphs, so a single
+// launch advances every problem and the GPU overlaps their latency-bound
+// coarse levels.  Between launches the host reads all residual histories
+// with one synchronisation.  The start of a CG run and the true-residual
+// check of a refinement step go out eagerly for the problems that need them.
+// A problem that has converged keeps iterating inside the batch graph (its
+// solution was already copied out) until the work of such problems reaches a
+// quarter of the graph's, so the graph is re-instantiated a few times per
+// batch rather than once per problem.
+// a lane's batch graph is re-instantiated without its finished problems once
+// they carry more than this fraction of its work (until then they iterate
+// on; their solutions were already copied out); a lane's problems that
+// finished their inner solve get their true-residual check once they carry
+// this fraction of its iterating work
+constexpr double BATCH_IDLE_FRAC = 0.0;
+constexpr double BATCH_CHECK_FRAC = 0.0;
+
+struct BatchItem {
+  hdg_problem* P = nullptr;
+  const double* rhs = nullptr;
+  double* lam_out = nullptr;
+  int nrhs = 0;
+  hdg_solve_info* info = nullptr;
+  int i0 = 0, nr = 0;  // current group of right-hand sides
+  bool mixed = false;
+  double gn[64];
+  Tracker tr;
+  SolveOut o;
+  int launched = 0;
+  enum { IDLE, ITER, DONE } phase = IDLE;
+  bool leave = false;     // finished its inner solve, waiting for the true-residual check
+  bool in_graph = false;  // its group graph is a child of the current batch graph
+  hdg_status status = HDG_OK;
+  double work() const { return (double)P->N * nr; }
+};
+
+// queue the copy of a problem's scalar blocks to its pinned host buffer
+void queue_scalars(hdg_problem* P, int nr) {
+  HDG_CHECK(hipMemcpyAsync(P->hpin, P->s.sc, sizeof(double) * SC_COUNT * nr, hipMemcpyDeviceToHost, P->st));
+}
+
+// true residual of the item's iterate; returns false when its solve ended
+// (converged, breakdown, or iteration limit): then its solution is copied out
+bool batch_check(BatchItem& b, double tol, double rnorm2[64]) {
+  hdg_problem* P = b.P;
+  double rel = 0.0;
+  for (int r = 0; r < b.nr; ++r) {
+    const double v = std::sqrt(rnorm2[r]) / b.gn[r];
+    if (!std::isfinite(v)) rel = v;
+    if (std::isfinite(rel)) rel = std::max(rel, v);
+  }
+  b.o.relres = rel;
+  b.o.outer += 1;
+  if (!std::isfinite(rel) || rel <= tol || b.launched >= P->opts.max_it) {
+    b.o.status = !std::isfinite(rel) ? HDG_ERR_BREAKDOWN : (rel <= tol ? HDG_OK : HDG_ERR_NOT_CONVERGED);
+    blas_copy(b.lam_out + (long)b.i0 * P->N, P->lam, P->N, P->st, b.nr);
+    b.phase = BatchItem::DONE;
+    return false;
+  }
+  double r0[64];
+  for (int r = 0; r < b.nr; ++r) r0[r] = std::sqrt(rnorm2[r]);
+  pcg_start(P, b.mixed, b.nr);
+  b.tr.init(b.nr, tol, b.gn);
+  if (b.mixed) b.tr.init_inner(P->opts.refine_red, r0, b.launched);
+  b.leave = false;
+  b.phase = BatchItem::ITER;
+  return true;
+}
+
+// `lanes` streams.  Each problem is dealt to one lane (largest first,
+// round-robin) and runs all its work there: the eager starts and checks and
+// its group graph, which sits in its lane's batch graph (the groups of a
+// lane one after another).  One lane is one batch graph for the whole batch.
+hdg_status solve_batch_graph(std::vector<BatchItem>& items, int rhs_kind, double tol,
+                             const std::vector<hipStream_t>& lanes) {
+  const int nb = (int)lanes.size();
+  std::vector<int> lane(items.size(), 0);
+  {
+    std::vector<int> ord(items.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      return (double)items[x].P->N * items[x].nrhs > (double)items[y].P->N * items[y].nrhs;
+    });
+    for (size_t j = 0; j < ord.size(); ++j) lane[ord[j]] = (int)(j % nb);
+  }
+  for (size_t i = 0; i < items.size(); ++i) items[i].P->st = lanes[lane[i]];
+  auto sync_all = [&] {
+    for (hipStream_t q : lanes) HDG_CHECK(hipStreamSynchronize(q));
+  };
+  std::vector<hipGraph_t> bg(nb, nullptr);
+  std::vector<hipGraphExec_t> bx(nb, nullptr);
+  std::vector<hipEvent_t> marks(nb, nullptr);
+  for (auto& m : marks) HDG_CHECK(hipEventCreateWithFlags(&m, hipEventDisableTiming));
+  auto drop_lane = [&](int q) {
+    if (bx[q]) (void)hipGraphExecDestroy(bx[q]);
+    if (bg[q]) (void)hipGraphDestroy(bg[q]);
+    bx[q] = nullptr;
+    bg[q] = nullptr;
+    for (size_t i = 0; i < items.size(); ++i)
+      if (lane[i] == q) items[i].in_graph = false;
+  };
+  auto drop_all = [&] {
+    for (int q = 0; q < nb; ++q) drop_lane(q);
+  };
+  try {
+    for (int round = 0;; ++round) {
+      // right-hand-side groups of this round: group `round` of every problem that has one
+      std::vector<int> act;
+      for (size_t i = 0; i < items.size(); ++i) {
+        BatchItem& b = items[i];
+        b.i0 = round * b.P->cap;
+        if (b.i0 >= b.nrhs) continue;
+        b.nr = std::min(b.P->cap, b.nrhs - b.i0);
+        act.push_back((int)i);
+      }
+      if (act.empty()) break;
+      drop_all();
+      // right-hand sides, initial guesses, ||g|| of every problem; one sync
+      for (int i : act) {
+        BatchItem* b = &items[i];
+        hdg_problem* P = b->P;
+        const long N = P->N, vs = P->nelem * P->nv;
+        for (int r = 0; r < b->nr; ++r) {
+          if (rhs_kind == HDG_RHS_TRACE)
+            blas_copy(P->g + r * N, b->rhs + (long)(b->i0 + r) * N, N, P->st);
+          else
+            form_rhs(P, b->rhs + (long)(b->i0 + r) * vs, rhs_kind, nullptr, P->g + r * N);
+        }
+        blas_copy(P->lam, b->lam_out + (long)b->i0 * N, N, P->st, b->nr);
+        blas_dot(P->g, P->g, N, P->s, FIN_GNORM, nullptr, P->st, b->nr);
+        queue_scalars(P, b->nr);
+      }
+      sync_all();
+      for (int i : act) {
+        BatchItem* b = &items[i];
+        b->mixed = b->P->opts.precision == HDG_MIXED;
+        b->launched = 0;
+        b->o = SolveOut();
+        for (int r = 0; r < b->nr; ++r) {
+          b->gn[r] = std::sqrt(b->P->hpin[(long)r * SC_COUNT + SC_GNORM2]);
+          if (b->gn[r] == 0.0) {  // zero data: the solution is zero
+            blas_fill<double>(b->P->lam + r * b->P->N, 0.0, b->P->N, b->P->st);
+            b->gn[r] = 1.0;
+          }
+        }
+        b->tr.init(b->nr, tol, b->gn);
+        residual_norm(b->P, b->P->lam, b->P->g, b->mixed && !b->P->ops32, b->nr);
+        queue_scalars(b->P, b->nr);
+      }
+      sync_all();
+      for (int i : act) {
+        BatchItem* b = &items[i];
+        double rn[64];
+        for (int r = 0; r < b->nr; ++r) rn[r] = b->P->hpin[(long)r * SC_COUNT + SC_RNORM2];
+        batch_check(*b, tol, rn);
+      }
+      // iterate until every problem of the round is done.  Lanes advance on
+      // their own: the host polls each lane's marker event and, when its
+      // work has finished, scans its problems, runs the true-residual
+      // checks it needs, and launches its next group.
+      enum { L_IDLE, L_GROUP, L_CHECK, L_DONE };
+      std::vector<int> lstate(nb, L_IDLE);
+      std::vector<std::vector<BatchItem*>> lchk(nb);
+      auto launch_lane = [&](int q) {
+        double gwork = 0.0, idle = 0.0;
+        bool iter = false, stale = false;
+        for (int i : act) {
+          if (lane[i] != q) continue;
+          const BatchItem& b = items[i];
+          if (b.phase == BatchItem::ITER) {
+            iter = true;
+            if (!b.in_graph) stale = true;
+          }
+          if (b.in_graph) {
+            gwork += b.work();
+            if (b.phase != BatchItem::ITER) idle += b.work();
+          }
+        }
+        if (!iter) {
+          drop_lane(q);
+          lstate[q] = L_DONE;
+          return;
+        }
+        if (stale || idle > BATCH_IDLE_FRAC * gwork) {
+          drop_lane(q);
+          HDG_CHECK(hipGraphCreate(&bg[q], 0));
+          hipGraphNode_t tail = nullptr;
+          for (int i : act) {
+            BatchItem* b = &items[i];
+            if (lane[i] != q || b->phase != BatchItem::ITER) continue;
+            hdg_problem* P = b->P;
+            if (b->nr != P->gnrhs) {
+              drop_graphs(P);
+              P->gnrhs = b->nr;
+            }
+            if (!P->grp_graph) {
+              const bool mx = b->mixed;
+              const int nr = b->nr;
+              P->grp_graph = capture(P, [&] {
+                reset_history(P, nr);
+                for (int it = 0; it < CHECK_EVERY; ++it) pcg_iteration(P, P->lam, mx, nr);
+              });
+            }
+            hipGraphNode_t node;
+            HDG_CHECK(hipGraphAddChildGraphNode(&node, bg[q], tail ? &tail : nullptr, tail ? 1 : 0, P->grp_graph));
+            tail = node;
+            b->in_graph = true;
+          }
+          HDG_CHECK(hipGraphInstantiate(&bx[q], bg[q], nullptr, nullptr, 0));
+        }
+        HDG_CHECK(hipGraphLaunch(bx[q], lanes[q]));
+        for (int i : act)
+          if (lane[i] == q && items[i].in_graph) queue_scalars(items[i].P, items[i].nr);
+        HDG_CHECK(hipEventRecord(marks[q], lanes[q]));
+        lstate[q] = L_GROUP;
+      };
+      // a lane's group has finished: scan its problems; queue the checks
+      // of those that finished their inner solve once they carry a quarter
+      // of the lane's iterating work (or all of it)
+      auto after_group = [&](int q) {
+        double lwork = 0.0, iwork = 0.0;
+        for (int i : act) {
+          BatchItem* b = &items[i];
+          if (lane[i] != q || !b->in_graph || b->phase != BatchItem::ITER) continue;
+          double w = 0.0;
+          const bool all = b->tr.scan(b->P->hpin, b->launched, CHECK_EVERY, &w);
+          b->launched += CHECK_EVERY;
+          if (b->tr.bad) {
+            b->o.relres = std::numeric_limits<double>::quiet_NaN();
+            b->o.status = HDG_ERR_BREAKDOWN;
+            b->o.iters = b->launched;
+            blas_copy(b->lam_out + (long)b->i0 * b->P->N, b->P->lam, b->P->N, b->P->st, b->nr);
+            b->phase = BatchItem::DONE;
+            continue;
+          }
+          if (!b->leave && (all || (b->mixed && b->tr.inner_done(b->launched)) || b->launched >= b->P->opts.max_it)) {
+            b->leave = true;
+            b->o.iters = all ? std::max(b->o.iters, b->tr.iters()) : b->launched;
+          }
+          iwork += b->work();
+          if (b->leave) lwork += b->work();
+        }
+        lchk[q].clear();
+        if (lwork > 0.0 && (lwork >= BATCH_CHECK_FRAC * iwork || lwork == iwork)) {
+          for (int i : act)
+            if (lane[i] == q && items[i].phase == BatchItem::ITER && items[i].leave) lchk[q].push_back(&items[i]);
+          for (BatchItem* b : lchk[q]) {
+            residual_norm(b->P, b->P->lam, b->P->g, b->mixed && !b->P->ops32, b->nr);
+            queue_scalars(b->P, b->nr);
+          }
+          HDG_CHECK(hipEventRecord(marks[q], lanes[q]));
+          lstate[q] = L_CHECK;
+        } else {
+          launch_lane(q);
+        }
+      };
+      for (int q = 0; q < nb; ++q) launch_lane(q);
+      for (;;) {
+        bool busy = false;
+        for (int q = 0; q < nb; ++q) {
+          if (lstate[q] == L_DONE) continue;
+          busy = true;
+          const hipError_t e = hipEventQuery(marks[q]);
+          if (e == hipErrorNotReady) continue;
+          HDG_CHECK(e);
+          if (lstate[q] == L_GROUP) {
+            after_group(q);
+          } else {  // L_CHECK
+            for (BatchItem* b : lchk[q]) {
+              double rn[64];
+              for (int r = 0; r < b->nr; ++r) rn[r] = b->P->hpin[(long)r * SC_COUNT + SC_RNORM2];
+              batch_check(*b, tol, rn);
+            }
+            launch_lane(q);
+          }
+        }
+        if (!busy) break;
+      }
+      for (int i : act) {
+        BatchItem* b = &items[i];
+        if (b->info) {
+          b->info->iters += b->o.iters;
+          b->info->outer_iters += b->o.outer;
+          b->info->relres = std::max(b->info->relres, b->o.relres);
+        }
+        if (b->o.status != HDG_OK && b->status == HDG_OK) b->status = b->o.status;
+      }
+    }
+    sync_all();
+  } catch (...) {
+    drop_all();
+    for (auto& m : marks) (void)hipEventDestroy(m);
+    throw;
+  }
+  drop_all();
+  for (auto& m : marks) (void)hipEventDestroy(m);
+  hdg_status worst = HDG_OK;
+  for (auto& b : items)
+    if (b.status != HDG_OK && (worst == HDG_OK || b.status == HDG_ERR_DEVICE)) worst = b.status;
+  return worst;
+}
+
 }  // namespace
 
 hdg_status hdg_solve(hdg_handle P, const double* rhs, int rhs_kind, const double* gdir, int nrhs, double tol,
@@ -1258,6 +1591,94 @@ hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const*
     if (!hs[i]->built) return HDG_ERR_STATE;
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return HDG_ERR_INVALID_ARG;  // a handle is not thread-safe
+  }
+  bool graph_ok = true;
+  for (int i = 0; i < nprob; ++i)
+    if (hs[i]->opts.method != HDG_METHOD_PCG || !hs[i]->use_graphs || hs[i]->prof_on) graph_ok = false;
+  if (nstreams <= 0 && graph_ok) {
+    // one batch graph on a private stream, ordered after and before every handle's stream
+    hipStream_t bst = nullptr;
+    std::vector<hipStream_t> orig(nprob);
+    for (int i = 0; i < nprob; ++i) orig[i] = hs[i]->st;
+    std::vector<BatchItem> items(nprob);
+    const int nlanes = std::min(std::max(1, -nstreams), 16);
+    std::vector<hipStream_t> lanes(nlanes, nullptr);
+    std::vector<hipEvent_t> join(nlanes, nullptr);
+    hipEvent_t ev = nullptr, fork = nullptr;
+    hdg_status res = HDG_OK;
+    try {
+      HDG_CHECK(hipStreamCreateWithFlags(&bst, hipStreamNonBlocking));
+      HDG_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HDG_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+      lanes[0] = bst;
+      for (int q = 1; q < nlanes; ++q) HDG_CHECK(hipStreamCreateWithFlags(&lanes[q], hipStreamNonBlocking));
+      for (int q = 0; q < nlanes; ++q) HDG_CHECK(hipEventCreateWithFlags(&join[q], hipEventDisableTiming));
+      for (int i = 0; i < nprob; ++i) {
+        HDG_CHECK(hipEventRecord(ev, orig[i]));
+        HDG_CHECK(hipStreamWaitEvent(bst, ev, 0));
+        BatchItem& b = items[i];
+        b.P = hs[i];
+        b.rhs = rhs[i];
+        b.lam_out = lambda[i];
+        b.nrhs = nrhs[i];
+        b.info = info ? info + i : nullptr;
+        if (b.info) {
+          b.info->iters = 0;
+          b.info->outer_iters = 0;
+          b.info->relres = 0.0;
+          b.info->t_solve_ms = 0.0;
+          b.info->n_levels = (int)hs[i]->L.size();
+          b.info->t_setup_ms = hs[i]->t_setup_ms;
+          b.info->t_build_ms = hs[i]->t_build_ms;
+        }
+      }
+      for (int q = 1; q < nlanes; ++q) {  // every lane starts after the handles' streams
+        HDG_CHECK(hipEventRecord(fork, bst));
+        HDG_CHECK(hipStreamWaitEvent(lanes[q], fork, 0));
+      }
+      hipEvent_t e0, e1;
+      HDG_CHECK(hipEventCreate(&e0));
+      HDG_CHECK(hipEventCreate(&e1));
+      HDG_CHECK(hipEventRecord(e0, bst));
+      res = solve_batch_graph(items, rhs_kind, tol, lanes);
+      for (int q = 1; q < nlanes; ++q) {  // and the batch stream after every lane
+        HDG_CHECK(hipEventRecord(join[q], lanes[q]));
+        HDG_CHECK(hipStreamWaitEvent(bst, join[q], 0));
+      }
+      HDG_CHECK(hipEventRecord(e1, bst));
+      HDG_CHECK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HDG_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (info)
+        for (int i = 0; i < nprob; ++i) info[i].t_solve_ms = ms;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      HDG_CHECK(hipEventRecord(ev, bst));
+      for (int i = 0; i < nprob; ++i) {
+        hs[i]->st = orig[i];
+        HDG_CHECK(hipStreamWaitEvent(orig[i], ev, 0));
+      }
+    } catch (const HipError& e) {
+      for (int i = 0; i < nprob; ++i) hs[i]->st = orig[i];
+      res = map_error(e);
+    } catch (const std::bad_alloc&) {
+      for (int i = 0; i < nprob; ++i) hs[i]->st = orig[i];
+      res = HDG_ERR_DEVICE;
+    }
+    for (int q = 1; q < nlanes; ++q)
+      if (lanes[q]) {
+        (void)hipStreamSynchronize(lanes[q]);
+        (void)hipStreamDestroy(lanes[q]);
+      }
+    if (bst) {
+      (void)hipStreamSynchronize(bst);
+      (void)hipStreamDestroy(bst);
+    }
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (ev) (void)hipEventDestroy(ev);
+    return res;
   }
   if (nstreams <= 0) nstreams = 4;
   nstreams = std::min(std::min(nstreams, 16), nprob);
@@ -1359,6 +1780,34 @@ hdg_status hdg_autotune(hdg_handle P, const hdg_mg_opts* base, int nrhs, hdg_mg_
         best_us = us;
         bo = o;
         have = true;
+      }
+    }
+  }
+  // then the tile shapes of the work on top of the best layout: lanes per
+  // macro-element of the transition kernels, and the finest level's strip
+  // apply against its two-phase form
+  if (have) {
+    const int shapes[3] = {HDG_VARIANT_LANES1, HDG_VARIANT_LANES4, HDG_VARIANT_NO_STRIP};
+    const hdg_mg_opts best0 = bo;
+    for (int si = 0; si < 3; ++si) {
+      hdg_mg_opts o = best0;
+      o.variant = best0.variant | shapes[si];
+      o.max_it = ITS;
+      if (hdg_mg_build(P, &o) != HDG_OK || P->N == 0) continue;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        blas_fill<double>(P->g, 1.0, P->N, P->st, o.nrhs);
+        blas_fill<double>(P->lam, 0.0, P->N, P->st, o.nrhs);
+        HDG_CHECK(hipEventRecord(e0, P->st));
+        (void)solve_many(P, o.nrhs, 1e-300, nullptr);
+        HDG_CHECK(hipEventRecord(e1, P->st));
+        HDG_CHECK(hipEventSynchronize(e1));
+        HDG_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      const double us = 1e3 * ms / ((double)ITS * o.nrhs);
+      if (us < best_us) {
+        best_us = us;
+        bo = o;
       }
     }
   }

@@ -134,6 +134,10 @@ struct Level {
   // used (2D, n a multiple of 64); z then holds its strip-edge products.
   bool packed = false;
   bool strip = false;
+  // lanes per macro-element of the fused h-transition kernels: 0 = by the
+  // size of the level (four while macro-elements x right-hand sides are
+  // few, one above), or forced to 1 or 4 (a tile shape the autotuner tries)
+  int lpm = 0;
   double* Ap64 = nullptr;   float* Ap32 = nullptr;
   void* z[2] = {nullptr, nullptr};
   // h-transition to the next level

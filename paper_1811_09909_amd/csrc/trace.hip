@@ -1034,7 +1034,7 @@ void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
-  const int lpm = lanes_per_macro(L.nmacro, nrhs);
+  const int lpm = L.lpm > 0 ? L.lpm : lanes_per_macro(L.nmacro, nrhs);
   if (lpm == 4)
     hipLaunchKernelGGL((hpreL_kernel<T, 4>), dim3(xcd_rhs_grid(nblk(4 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,
                        Af, Ai, P, r, e, do_corr, cb);
@@ -1073,7 +1073,7 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
   const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
   const long nbf = nblk(C.nface);
-  const int lpm = lanes_per_macro(L.nmacro, nrhs);
+  const int lpm = L.lpm > 0 ? L.lpm : lanes_per_macro(L.nmacro, nrhs);
   if (lpm == 4) {
     const long nbm = nblk(4 * L.nmacro);
     hipLaunchKernelGGL((hpost_kernel<2, T, 4>), dim3(xcd_rhs_grid(nbm + nbf, nrhs)), dim3(256), 0, st, L.n, nbm, nbf,

@@ -125,7 +125,7 @@ class Problem:
         self.built = True
         self.opts = best
         self.n_levels = self.query(L.Q_NLEVELS)
-        return {"coarse_n": best.coarse_n, "nrhs": best.nrhs, "us_per_rhs_iter": us.value}
+        return {"coarse_n": best.coarse_n, "nrhs": best.nrhs, "variant": best.variant, "us_per_rhs_iter": us.value}
 
     def vcycle(self, r, precision=L.FP64):
         dt = torch.float32 if precision == L.FP32 else torch.float64
@@ -226,11 +226,12 @@ class Problem:
         return self._tensor_points(self.reference_nodes()[1])
 
 
-def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=4):
+def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=0):
     """Solve problem i for its right-hand sides rhs[i] ([nrhs_i, ...] nodal
-    sources, or trace vectors for kind=RHS_TRACE) with hdg_solve_batch: the
-    problems run concurrently on `nstreams` streams.  Returns the list of
-    solutions [nrhs_i, N_lambda_i] and the list of solve infos."""
+    sources, or trace vectors for kind=RHS_TRACE) with hdg_solve_batch: all
+    problems through one batch graph (nstreams <= 0, PCG builds), or
+    concurrently on `nstreams` streams.  Returns the list of solutions
+    [nrhs_i, N_lambda_i] and the list of solve infos."""
     n = len(problems)
     rhs_t = [_dev(r, torch.float64, p.device) for p, r in zip(problems, rhs)]
     nr = [(r.numel() // (p.nlam if kind == L.RHS_TRACE else p.nT * p.nv)) for p, r in zip(problems, rhs_t)]

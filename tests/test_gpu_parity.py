@@ -255,6 +255,27 @@ def test_vcycle_paths_agree_at_high_contrast(torch_cuda, n, k, lc):
         assert e64 <= 1e-12 and e32 <= 1e-5
 
 
+@pytest.mark.parametrize("n,k,nr", [(64, 2, 1), (128, 3, 4)])
+def test_vcycle_macro_lane_shapes_agree(torch_cuda, n, k, nr):
+    """The tile shapes the autotuner tries for the transition kernels (one or
+    four lanes per macro-element on every level) compute the same cycle as
+    the default split, over one and several right-hand sides."""
+    from paper_1811_09909_amd import _lib as L
+    kap, rng = _kappa(2, n)
+    R = rng.standard_normal(nr * 2 * (n - 1) * n * (k + 1))
+    outs = {}
+    for var in (0, L.VARIANT_LANES1, L.VARIANT_LANES4):
+        P = _gpu(torch_cuda, 2, n, k, kap)
+        P.build(sweeps=2, local_corr=omg.LC_BOTH, nrhs=nr, variant=var)
+        outs[var] = (P.vcycle(torch_cuda.as_tensor(R)).cpu().numpy(),
+                     P.vcycle(torch_cuda.as_tensor(R, dtype=torch_cuda.float32), precision=L.FP32).cpu().numpy())
+    for var in (L.VARIANT_LANES1, L.VARIANT_LANES4):
+        e64 = relerr(outs[var][0], outs[0][0])
+        e32 = relerr(outs[var][1], outs[0][1])
+        say(f"[lane shapes n={n} k={k} nrhs={nr}] variant {var} vs default: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= 1e-13 and e32 <= 1e-5
+
+
 @pytest.mark.parametrize("path", ["fused", "unfused"])
 @pytest.mark.parametrize("d,n,k,cn,lc", [(2, 32, 2, 8, "pre"), (2, 64, 1, 16, "both"), (3, 8, 2, 4, "pre"),
                                          (2, 16, 3, 16, "none")])
@@ -547,6 +568,19 @@ def test_solve_batch_matches_single_solves(torch_cuda):
             f"max diff vs single {d:.1e}")
         assert infos[i]["relres"] <= 1e-10
         assert d == 0.0
+    # one batch graph: the same iterations per problem; a converged problem
+    # may take a few more before its true-residual check, so the solutions
+    # agree to the tolerance, and every true residual meets it
+    lamg, infg = solve_batch(Ps, rhs, tol=1e-10, nstreams=0)
+    for i, w in enumerate(probs):
+        P = Ps[i]
+        for j in range(3):
+            g = P.rhs(torch_cuda.as_tensor(w.f[j]))
+            rel = float((g - P.level_apply(0, lamg[i][j])).norm() / g.norm())
+            e = relerr(lamg[i][j].cpu().numpy(), singles[i][j])
+            say(f"[batch graph] problem {i} rhs {j}: {infg[i]['iters']} iterations (single {infos[i]['iters']}), "
+                f"true relres {rel:.2e}, vs single {e:.1e}")
+            assert rel <= 1.05e-10 and e <= 1e-6
     i0 = min(range(len(probs)), key=lambda i: probs[i].n * probs[i].k)
     w = probs[i0]
     O = HDG(2, w.n, w.k, 1.0, w.kappa)

@@ -97,7 +97,19 @@ typedef struct {
   int variant;      /* HDG_VARIANT_* bits: select another execution form of the same method (for
                        comparing forms; 0 = the default, fastest form).  Iterates agree up to the
                        order of rounding. */
+  int smoother;     /* HDG_SMOOTHER_* (Sec. 4.1): face-block Jacobi (default) or a point smoother.  The
+                       point smoothers store every level face-major and use the unfused kernels. */
 } hdg_mg_opts;
+
+/* Smoothers of Sec. 4.1.  JACOBI: damped point Jacobi, x += omega D^-1 (b - A x) (the paper takes
+   omega = 2/3).  CHEBYSHEV: point Jacobi accelerated by the Chebyshev polynomial of degree m (the
+   level's sweep count) on [lmax / 30, lmax], lmax = 1.1 x a power-iteration estimate of the largest
+   eigenvalue of D^-1 A (20 steps from the all-ones vector), applied as m Jacobi steps with step sizes
+   the reciprocals of the polynomial's roots.  LUSGS: one forward and one backward point Gauss-Seidel
+   sweep per step, in a multicolour order: faces in 2d colours no two of which share an element, the
+   values within a face one after another (the paper sweeps in the plain unknown order, which has no
+   parallel form). */
+enum { HDG_SMOOTHER_BLOCK_JACOBI = 0, HDG_SMOOTHER_JACOBI = 1, HDG_SMOOTHER_CHEBYSHEV = 2, HDG_SMOOTHER_LUSGS = 3 };
 
 /* Execution-form bits of hdg_mg_opts.variant. */
 enum {
@@ -234,7 +246,8 @@ hdg_status hdg_mass_apply(hdg_handle h, const double* u, double* out);
 /* Inspection: y = A_l x on level l (0 = finest), precision per HDG_FP64/FP32. */
 hdg_status hdg_level_apply(hdg_handle h, int level, const void* x, void* y, int precision);
 
-/* Inspection: m face-block Jacobi sweeps on A_l e = r from e = 0. */
+/* Inspection: m steps of the build's smoother on A_l e = r from e = 0
+ * (Chebyshev: m must be the level's sweep count, the polynomial's degree). */
 hdg_status hdg_level_smooth(hdg_handle h, int level, const void* r, void* e, int sweeps, int precision);
 
 /* Inspection: copy the element-form local matrices of level l

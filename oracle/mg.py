@@ -198,9 +198,9 @@ def point_jacobi(L, res, m, omega):
 
 def lambda_max_estimate(A):
     """Largest eigenvalue of D^-1 A by power iteration from the all-ones
-    vector (CHEB_POWER_ITS steps, Rayleigh quotient v^T A v / v^T D v of the
-    last iterate), raised by CHEB_SAFETY (Sec. 4.1 asks for an estimate to
-    about 1e-2)."""
+    vector: CHEB_POWER_ITS normalised steps v <- D^-1 A v / ||D^-1 A v||,
+    then ||D^-1 A v|| for the last unit v, raised by CHEB_SAFETY (Sec. 4.1
+    asks for an estimate to about 1e-2)."""
     N = A.shape[0]
     if N == 0:
         return 1.0
@@ -209,7 +209,7 @@ def lambda_max_estimate(A):
     for _ in range(CHEB_POWER_ITS):
         w = (A @ v) / d
         v = w / np.linalg.norm(w)
-    return CHEB_SAFETY * float(v @ (A @ v)) / float(v @ (d * v))
+    return CHEB_SAFETY * float(np.linalg.norm((A @ v) / d))
 
 
 def chebyshev(L, res, m, lmax):

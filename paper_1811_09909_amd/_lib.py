@@ -36,7 +36,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("growth", ctypes.c_int), ("omega", ctypes.c_double),
                 ("local_corr", ctypes.c_int), ("precision", ctypes.c_int), ("method", ctypes.c_int),
                 ("max_it", ctypes.c_int), ("restart", ctypes.c_int), ("coarse_n", ctypes.c_int),
-                ("nrhs", ctypes.c_int), ("refine_red", ctypes.c_double), ("variant", ctypes.c_int)]
+                ("nrhs", ctypes.c_int), ("refine_red", ctypes.c_double), ("variant", ctypes.c_int),
+                ("smoother", ctypes.c_int)]
 
 
 # hdg_mg_opts.variant bits (HDG_VARIANT_*)
@@ -45,7 +46,8 @@ VARIANT_FP32_VECTORS, VARIANT_FP64_VECTORS = 32, 64
 VARIANT_LANES1, VARIANT_LANES4 = 128, 256
 PROF_F32OPS = 14  # hdg_profile_read: kernel = 14 + mode for FP64 vectors over FP32 operator blocks
 OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", "max_it", "restart", "coarse_n",
-              "nrhs", "refine_red", "variant")
+              "nrhs", "refine_red", "variant", "smoother")
+SMOOTHER_BLOCK_JACOBI, SMOOTHER_JACOBI, SMOOTHER_CHEBYSHEV, SMOOTHER_LUSGS = 0, 1, 2, 3
 
 
 class Info(ctypes.Structure):

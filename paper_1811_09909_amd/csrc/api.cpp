@@ -284,9 +284,31 @@ enum { G_PCG64 = 0, G_PCGMX = 1, G_MG64 = 2, G_MGMX = 3, G_PRE64 = 4, G_PREMX = 
 // correction of step 5).  Same arithmetic as the unfused kernels up to the
 // order of the last rounding.
 //
+// Chebyshev smoother: step s reads the level's diagonal blocks scaled by the
+// reciprocal of root s (the launchers read L.Dinv at launch)
+void cheb_select(Level& L, int s) {
+  if (L.cheb64.empty()) return;
+  L.Dinv64 = L.cheb64[s];
+  L.Dinv32 = L.cheb32[s];
+}
+
+// m steps of multicolour point symmetric Gauss-Seidel on A e = r in place:
+// the colours forward with each face's values in increasing order, then
+// backward with them decreasing
+template <typename T, typename M>
+void sgs_steps(Level& L, T* e, const T* r, int m, hipStream_t st, int nr) {
+  const int nc = 2 * L.d;
+  for (int s = 0; s < m; ++s) {
+    for (int c = 0; c < nc; ++c) launch_sgs_color<T, M>(L, c, 0, e, r, st, nr);
+    for (int c = nc - 1; c >= 0; --c) launch_sgs_color<T, M>(L, c, 1, e, r, st, nr);
+  }
+}
+
 // M: storage type of the operator blocks read.  M = float under T = double is
 // the 3D mixed cycle: every level keeps FP64 vectors and sums and reads the
-// FP32 copies of its blocks (unfused kernels, no coarse tail).
+// FP32 copies of its blocks (unfused kernels, no coarse tail).  The point
+// smoothers (HDG_SMOOTHER_*) replace the block-Jacobi steps; they run on the
+// unfused path.
 template <typename T, typename M = T>
 T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int nr = 1) {
   constexpr bool narrow = !std::is_same_v<T, M>;
@@ -312,16 +334,24 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
   const int m = L.sweeps;
   const int lc = P->opts.local_corr;
   const bool fused = !narrow && P->fuse && L.d == 2 && m >= 1;
+  const bool gs = P->opts.smoother == HDG_SMOOTHER_LUSGS;
   // pre-smoothing from e = 0
-  if (!pre_done) {
-    if (m >= 1)
-      launch_jacobi0<T, M>(L, r, e, st, nr);
-    else
-      blas_fill<T>(e, T(0), L.nlam, st, nr);
-  }
-  for (int s = 1; s < m; ++s) {
-    apply<T, M>(P, i, APPLY_SWEEP, e, r, w, nullptr, nr);
-    std::swap(e, w);
+  if (gs) {
+    blas_fill<T>(e, T(0), L.nlam, st, nr);
+    sgs_steps<T, M>(L, e, r, m, st, nr);
+  } else {
+    if (!pre_done) {
+      cheb_select(L, 0);
+      if (m >= 1)
+        launch_jacobi0<T, M>(L, r, e, st, nr);
+      else
+        blas_fill<T>(e, T(0), L.nlam, st, nr);
+    }
+    for (int s = 1; s < m; ++s) {
+      cheb_select(L, s);
+      apply<T, M>(P, i, APPLY_SWEEP, e, r, w, nullptr, nr);
+      std::swap(e, w);
+    }
   }
   Level& C = P->L[i + 1];
   T* rc = (T*)C.r[pr];
@@ -370,7 +400,9 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
       launch_hcorr<T, M>(L, w, e, 1, 0, nullptr, st, nr);
     }
   }
-  for (int s = 0; s < m; ++s) {
+  if (gs) sgs_steps<T, M>(L, e, r, m, st, nr);
+  for (int s = 0; s < m && !gs; ++s) {
+    cheb_select(L, s);
     T* dst = (out && s == m - 1) ? out : w;
     if (i == 0 && P->dot_v && dst == out) {
       int np = 0;
@@ -484,6 +516,11 @@ void precond_fused(hdg_problem* P, bool mixed, int nr) {
 // inner target (a reduction of the step's true residual) and stagnation: no
 // halving of its best residual within STAG_WINDOW iterations.
 constexpr int STAG_WINDOW = 100;
+// Chebyshev smoother: power-iteration steps, safety factor of the largest
+// eigenvalue estimate, and ratio largest / smallest of the interval
+constexpr int CHEB_POWER_ITS = 20;
+constexpr double CHEB_SAFETY = 1.1;
+constexpr double CHEB_RATIO = 30.0;
 struct Tracker {
   int nr = 1;
   double tol = 0.0;
@@ -876,6 +913,7 @@ void hdg_default_opts(hdg_mg_opts* o) {
   o->nrhs = 1;
   o->refine_red = 1e-5;
   o->variant = 0;
+  o->smoother = HDG_SMOOTHER_BLOCK_JACOBI;
 }
 
 const char* hdg_status_string(hdg_status s) {
@@ -993,7 +1031,8 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
       o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
-      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 511)
+      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 511 ||
+      o.smoother < HDG_SMOOTHER_BLOCK_JACOBI || o.smoother > HDG_SMOOTHER_LUSGS)
     return HDG_ERR_INVALID_ARG;
   if (o.nrhs < 1) o.nrhs = 1;
   if (o.refine_red == 0.0) o.refine_red = 1e-5;
@@ -1014,7 +1053,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   // The FP64-vector form reads face-major blocks with the unfused kernels.
   P->ops32 = o.precision == HDG_MIXED && !(o.variant & HDG_VARIANT_FP32_VECTORS) &&
              (P->d == 3 || (o.variant & HDG_VARIANT_FP64_VECTORS));
-  if (P->ops32) {
+  if (P->ops32 || o.smoother != HDG_SMOOTHER_BLOCK_JACOBI) {
     P->pack = false;
     P->fuse = false;
     P->tail_nmax = 0;
@@ -1098,7 +1137,8 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
         launch_pack_sym(Li, P->st);
       else
         launch_face_major(Li, P->st);
-      launch_dinv(Li, o.omega, P->st);
+      const int dmode = o.smoother == HDG_SMOOTHER_BLOCK_JACOBI ? 0 : o.smoother == HDG_SMOOTHER_LUSGS ? 2 : 1;
+      launch_dinv(Li, o.smoother == HDG_SMOOTHER_CHEBYSHEV ? 1.0 : o.omega, P->st, dmode);
     }
   }
   // one-workgroup coarse tail (2D, fused path): the first level from which
@@ -1149,6 +1189,46 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   P->N = L[0].nlam;
   const long N = P->N;
   const long Nc = N * cap;
+  if (o.smoother == HDG_SMOOTHER_CHEBYSHEV) {
+    // per level: lmax of D^-1 A by power iteration (FP64), then the
+    // diagonal blocks scaled by the reciprocal roots of the degree-m
+    // Chebyshev polynomial on [lmax / 30, lmax], one copy per step
+    Scratch ps;
+    ps.sc = dalloc<double>(P, SC_COUNT, true);
+    ps.partials = dalloc<double>(P, 2L * MAX_RED_BLOCKS, true);
+    ps.row = 2L * MAX_RED_BLOCKS;
+    for (auto& Li : L) {
+      if (Li.nface == 0 || Li.kind == 2) continue;
+      double* v = (double*)Li.r[0];
+      double* y = (double*)Li.e[0];
+      double* z = (double*)Li.w[0];
+      blas_fill<double>(v, 1.0, Li.nlam, P->st);
+      auto dinv_apply = [&](const double* in, double* out) {  // out = D^-1 A in
+        launch_apply<double>(Li, APPLY_Y, in, nullptr, y, nullptr, nullptr, P->st);
+        launch_jacobi0<double>(Li, y, out, P->st);
+      };
+      for (int it = 0; it < CHEB_POWER_ITS; ++it) {
+        dinv_apply(v, z);
+        blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
+        blas_scale(v, z, Li.nlam, ps.sc + SC_TMP, P->st);
+      }
+      dinv_apply(v, z);
+      blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
+      Li.lmax = CHEB_SAFETY * read_scalar(P, ps.sc + SC_HNORM);
+      const double lmin = Li.lmax / CHEB_RATIO, theta = 0.5 * (Li.lmax + lmin), dlt = 0.5 * (Li.lmax - lmin);
+      const long nd = pad64(Li.nface) * vpad<double>((long)Li.ne * Li.ne);
+      const long nd32 = pad64(Li.nface) * vpad<float>((long)Li.ne * Li.ne);
+      if (nd32 != nd) throw HipError{hipErrorInvalidValue, "Chebyshev copies: block padding differs"};
+      for (int si = 1; si <= Li.sweeps; ++si) {
+        const double root = theta - dlt * std::cos((2.0 * si - 1.0) * M_PI / (2.0 * Li.sweeps));
+        double* c64 = dalloc<double>(P, nd, true);
+        float* c32 = dalloc<float>(P, nd, true);
+        launch_scale_copy(nd, 1.0 / root, Li.Dinv64, c64, c32, P->st);
+        Li.cheb64.push_back(c64);
+        Li.cheb32.push_back(c32);
+      }
+    }
+  }
   P->g = dalloc<double>(P, Nc, true);
   P->r = dalloc<double>(P, Nc, true);
   P->z = dalloc<double>(P, Nc, true);
@@ -1892,6 +1972,7 @@ hdg_status hdg_level_smooth(hdg_handle P, int level, const void* r, void* e, int
   if (level < 0 || level >= (int)P->L.size()) return HDG_ERR_INVALID_ARG;
   HDG_GUARD_BEGIN
   Level& L = P->L[level];
+  if (P->opts.smoother == HDG_SMOOTHER_CHEBYSHEV && sweeps != L.sweeps && L.nface > 0) return HDG_ERR_INVALID_ARG;
   auto run = [&](auto tag) {
     using T = decltype(tag);
     const int pr = sizeof(T) == 8 ? 0 : 1;
@@ -1901,10 +1982,17 @@ hdg_status hdg_level_smooth(hdg_handle P, int level, const void* r, void* e, int
       blas_fill<T>((T*)e, T(0), L.nlam, P->st);
       return;
     }
-    launch_jacobi0<T>(L, (const T*)r, a, P->st);
-    for (int s = 1; s < sweeps; ++s) {
-      launch_apply<T>(L, APPLY_SWEEP, a, (const T*)r, b, nullptr, nullptr, P->st);
-      std::swap(a, b);
+    if (P->opts.smoother == HDG_SMOOTHER_LUSGS) {
+      blas_fill<T>(a, T(0), L.nlam, P->st);
+      sgs_steps<T, T>(L, a, (const T*)r, sweeps, P->st, 1);
+    } else {
+      cheb_select(L, 0);
+      launch_jacobi0<T>(L, (const T*)r, a, P->st);
+      for (int s = 1; s < sweeps; ++s) {
+        cheb_select(L, s);
+        launch_apply<T>(L, APPLY_SWEEP, a, (const T*)r, b, nullptr, nullptr, P->st);
+        std::swap(a, b);
+      }
     }
     HDG_CHECK(hipMemcpyAsync(e, a, sizeof(T) * L.nlam, hipMemcpyDeviceToDevice, P->st));
   };

@@ -65,11 +65,14 @@ __global__ void face_major_kernel(int d, int n, int ne, long nface, const double
   Af32[aos_off<float>(F, 2 * s32, side * s32 + ent)] = (float)v;
 }
 
-// omega * (A_{T-}[F,F] + A_{T+}[F,F])^-1 per face; sym: stored as the upper
-// triangle (row by row) of the symmetrized inverse
+// Per face, from the assembled diagonal block D_F = A_{T-}[F,F] + A_{T+}[F,F]
+// (Sec. 4.1 smoothers): mode 0, omega * D_F^-1 (block Jacobi; sym: stored
+// as the upper triangle, row by row, of the symmetrized inverse); mode 1,
+// omega / diag(D_F) as a diagonal block (point Jacobi); mode 2, D_F itself
+// (the in-face updates of point Gauss-Seidel).
 template <int NE>
 __global__ void dinv_kernel(int d, int n, long nface, double omega, const double* __restrict__ Aelem,
-                            double* __restrict__ D64, float* __restrict__ D32, int sym) {
+                            double* __restrict__ D64, float* __restrict__ D32, int sym, int mode) {
   const long F = blockIdx.x * 256L + threadIdx.x;
   if (F >= nface) return;
   const int nl = 2 * d * NE;
@@ -84,6 +87,15 @@ __global__ void dinv_kernel(int d, int n, long nface, double omega, const double
     const int slot = side == 0 ? 2 * c + 1 : 2 * c;
     for (int a = 0; a < NE; ++a)
       for (int b = 0; b < NE; ++b) A[a * NE + b] += Aelem[(T * nl + slot * NE + a) * nl + slot * NE + b];
+  }
+  if (mode != 0) {
+    for (int i = 0; i < NE * NE; ++i) {
+      double v = A[i];
+      if (mode == 1) v = (i % (NE + 1) == 0) ? omega / A[i] : 0.0;
+      D64[aos_off<double>(F, vpad<double>(NE * NE), i)] = v;
+      D32[aos_off<float>(F, vpad<float>(NE * NE), i)] = (float)v;
+    }
+    return;
   }
   // Gauss-Jordan, SPD block: no pivoting
   for (int k = 0; k < NE; ++k) {
@@ -115,6 +127,17 @@ __global__ void dinv_kernel(int d, int n, long nface, double omega, const double
     D64[aos_off<double>(F, vpad<double>(NE * NE), i)] = v;
     D32[aos_off<float>(F, vpad<float>(NE * NE), i)] = (float)v;
   }
+}
+
+// dst = s * src in FP64 and its FP32 copy (per-step copies of a level's
+// diagonal blocks for the Chebyshev smoother)
+__global__ void scale_copy_kernel(long n, double s, const double* __restrict__ src, double* __restrict__ d64,
+                                  float* __restrict__ d32) {
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  if (i >= n) return;
+  const double v = s * src[i];
+  d64[i] = v;
+  d32[i] = (float)v;
 }
 
 // Ac[(s1,v1),(s2,v2)] = sum_ab Jp[a][v1] A[(s1,a),(s2,b)] Jp[b][v2]
@@ -477,12 +500,13 @@ void launch_face_major(const Level& L, hipStream_t st) {
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_dinv(const Level& L, double omega, hipStream_t st) {
+void launch_dinv(const Level& L, double omega, hipStream_t st, int mode) {
   if (L.nface == 0) return;
+  if (mode != 0 && L.packed) throw HipError{hipErrorInvalidValue, "point smoother data: face-major levels only"};
 #define HDG_DCASE(NN)                                                                                     \
   case NN:                                                                                                \
     hipLaunchKernelGGL((dinv_kernel<NN>), dim3(nblk(L.nface)), dim3(256), 0, st, L.d, L.n, L.nface, omega, \
-                       L.Aelem, L.Dinv64, L.Dinv32, L.packed ? 1 : 0);                                    \
+                       L.Aelem, L.Dinv64, L.Dinv32, L.packed ? 1 : 0, mode);                              \
     break;
   switch (L.ne) {
     HDG_DCASE(2) HDG_DCASE(3) HDG_DCASE(4) HDG_DCASE(5) HDG_DCASE(6) HDG_DCASE(7) HDG_DCASE(9) HDG_DCASE(16)
@@ -541,4 +565,12 @@ void launch_coarse_inverse(const Level& L, hipStream_t st) {
   HDG_CHECK(hipGetLastError());
 }
 
+}  // namespace hdg
+
+namespace hdg {
+void launch_scale_copy(long n, double s, const double* src, double* d64, float* d32, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, s, src, d64, d32);
+  HDG_CHECK(hipGetLastError());
+}
 }  // namespace hdg

@@ -134,6 +134,12 @@ struct Level {
   // used (2D, n a multiple of 64); z then holds its strip-edge products.
   bool packed = false;
   bool strip = false;
+  // smoother data beyond Dinv: the Chebyshev smoother's per-step copies of
+  // the diagonal blocks scaled by 1 / (root i of its polynomial), and the
+  // eigenvalue estimate they come from
+  std::vector<double*> cheb64;
+  std::vector<float*> cheb32;
+  double lmax = 0.0;
   // lanes per macro-element of the fused h-transition kernels: 0 = by the
   // size of the level (four while macro-elements x right-hand sides are
   // few, one above), or forced to 1 or 4 (a tile shape the autotuner tries)
@@ -175,7 +181,10 @@ void launch_kappa_expand(long nelem, int nq, const double* kappa, int kind, doub
 // build.hip
 void launch_face_major(const Level& L, hipStream_t st);
 void launch_pack_sym(const Level& L, hipStream_t st);
-void launch_dinv(const Level& L, double omega, hipStream_t st);
+// mode 0: omega D_F^-1 (block Jacobi), 1: omega / diag(D_F) (point Jacobi),
+// 2: D_F (point Gauss-Seidel), D_F the assembled diagonal block of face F
+void launch_dinv(const Level& L, double omega, hipStream_t st, int mode = 0);
+void launch_scale_copy(long n, double s, const double* src, double* d64, float* d32, hipStream_t st);
 void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double* Afine, double* Acoarse,
                       hipStream_t st);
 void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st);
@@ -202,6 +211,12 @@ template <typename T, typename M = T>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs = 1);
 template <typename T, typename M = T>
 void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int nrhs = 1);
+// one colour pass of multicolour point symmetric Gauss-Seidel on a
+// face-major level whose Dinv arrays hold the assembled face blocks: every
+// face of colour col (normal col / 2, position parity col % 2) updates its
+// values of x in place, in increasing order, or decreasing when backward
+template <typename T, typename M = T>
+void launch_sgs_color(const Level& L, int col, int backward, T* x, const T* b, hipStream_t st, int nrhs = 1);
 template <typename T>
 void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b, T* rc, T* ec, const double* Jp,
                           hipStream_t st, int nrhs = 1);

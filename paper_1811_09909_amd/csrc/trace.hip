@@ -154,6 +154,61 @@ __global__ void jacobi0_kernel(long nface, int nrhs, const M* __restrict__ Dinv,
   jacobi0_item<NE, T, DSYM, M>(F, Dinv, r, e);
 }
 
+// One colour pass of multicolour point symmetric Gauss-Seidel (the LU-SGS
+// smoother of Sec. 4.1 in a parallel order).  Colour col holds the faces of
+// normal direction col / 2 at grid positions p (1 .. n-1) with p % 2 ==
+// col % 2: no two of them bound a common element, so no face's row involves
+// another one's values and every face of the colour updates at once.  One
+// lane per face: acc = (A x)_F with the current values, then point updates of
+// the face's values in increasing order (decreasing when backward), each
+// followed by the change of the remaining rows through the face's own block
+// D_F (held in Dblk).
+template <int D, int NE, typename T, typename M = T>
+__global__ void __launch_bounds__(256) sgs_color_kernel(int n, int col, int backward, const M* __restrict__ Af,
+                                                        const M* __restrict__ Dblk, T* x, const T* __restrict__ b) {
+  const int c = col / 2, par = col % 2;
+  const long np = par ? n / 2 : (n - 1) / 2;  // positions p in 1 .. n-1 with p % 2 == par
+  long nt = np;
+  for (int a = 1; a < D; ++a) nt *= n;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  if (t >= nt) return;
+  {
+    const long sN = trace_len<D>(n, NE);
+    x += blockIdx.y * sN;
+    b += blockIdx.y * sN;
+  }
+  int g[3] = {0, 0, 0};
+  long rem = t / np;
+  g[c] = 2 * (int)(t % np) + (par ? 1 : 2);
+  for (int a = 0; a < D; ++a)
+    if (a != c) {
+      g[a] = (int)(rem % n);
+      rem /= n;
+    }
+  const long F = face_id<D>(c, g, n);
+  using A = acc_t<T>;
+  A acc[NE];
+  face_acc<D, NE, T, M>(F, n, Af, x, acc);
+  A xs[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) xs[a] = x[F * NE + a];
+  const M* blk = Dblk + aos_item<M>(F, vpad<M>(NE * NE));
+  constexpr int V = vw<M>();
+#pragma unroll
+  for (int ii = 0; ii < NE; ++ii) {
+    const int a = backward ? NE - 1 - ii : ii;
+    const A dx = (A(b[F * NE + a]) - acc[a]) / A(blk[((a * NE + a) / V) * (LANES * V) + (a * NE + a) % V]);
+    xs[a] += dx;
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = q * NE + a;  // D_F[q][a]: row q, column a
+      acc[q] += A(blk[(e / V) * (LANES * V) + e % V]) * dx;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) x[F * NE + a] = T(xs[a]);
+}
+
 // first phase of the element-major apply: z_T = A^e x_T for every element
 template <int D, int NE, typename T>
 __global__ void __launch_bounds__(256) elem_apply_kernel(int n, const T* __restrict__ Ap, const T* __restrict__ x,
@@ -1090,6 +1145,24 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   HDG_CHECK(hipGetLastError());
 }
 
+template <typename T, typename M>
+void launch_sgs_color(const Level& L, int col, int backward, T* x, const T* b, hipStream_t st, int nrhs) {
+  if (L.nface == 0) return;
+  if (L.packed) throw HipError{hipErrorInvalidValue, "Gauss-Seidel smoother: face-major levels only"};
+  const M* Af = sizeof(M) == 8 ? (const M*)L.Af64 : (const M*)L.Af32;
+  const M* Db = sizeof(M) == 8 ? (const M*)L.Dinv64 : (const M*)L.Dinv32;
+  const long np = (col % 2) ? L.n / 2 : (L.n - 1) / 2;
+  long nt = np;
+  for (int a = 1; a < L.d; ++a) nt *= L.n;
+  if (nt == 0) return;
+  dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
+    constexpr int D = decltype(D_)::value, NE = decltype(NE_)::value;
+    hipLaunchKernelGGL((sgs_color_kernel<D, NE, T, M>), dim3(nblk(nt), nrhs), dim3(256), 0, st, L.n, col, backward, Af,
+                       Db, x, b);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
 // operator-reading launchers also for FP32 operator blocks under FP64 vectors
 #define HDG_INST_M(T, M)                                                                                          \
   template void launch_apply<T, M>(const Level&, int, const T*, const T*, T*, const double*, T*, hipStream_t, int); \
@@ -1098,7 +1171,8 @@ void launch_hpost(const Level& L, const Level& C, const T* r, const T* ec, const
   template void launch_jacobi0<T, M>(const Level&, const T*, T*, hipStream_t, int);                               \
   template void launch_hcorr<T, M>(const Level&, const T*, T*, int, int, T*, hipStream_t, int);                   \
   template void launch_hprolong<T, M>(const Level&, const Level&, const T*, T*, hipStream_t, int);                \
-  template void launch_coarse_solve<T, M>(const Level&, const T*, T*, hipStream_t, int);
+  template void launch_coarse_solve<T, M>(const Level&, const T*, T*, hipStream_t, int);                        \
+  template void launch_sgs_color<T, M>(const Level&, int, int, T*, const T*, hipStream_t, int);
 HDG_INST_M(double, double)
 HDG_INST_M(float, float)
 HDG_INST_M(double, float)

@@ -71,9 +71,9 @@ class Problem:
         self.built = False
 
     def build(self, sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-              max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0):
+              max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0, smoother=0):
         o = L.Opts(sweeps, growth, omega, local_corr, precision, method, max_it, restart, coarse_n, nrhs,
-                   refine_red, variant)
+                   refine_red, variant, smoother)
         L.check(self.lib.hdg_mg_build(self.h, ctypes.byref(o)), "hdg_mg_build")
         self.version += 1
         self.built = True
@@ -114,7 +114,7 @@ class Problem:
         `nrhs` right-hand sides on top of the build options `base` (see
         hdg_autotune); leaves the handle built with them."""
         defaults = dict(sweeps=2, growth=1, omega=1.0, local_corr=L.LC_PRE, precision=L.FP64, method=L.METHOD_MG,
-                        max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0)
+                        max_it=200, restart=0, coarse_n=2, nrhs=1, refine_red=0.0, variant=0, smoother=0)
         defaults.update(base)
         o = L.Opts(*[defaults[k] for k in L.OPT_FIELDS])
         best = L.Opts()

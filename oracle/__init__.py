@@ -22,6 +22,10 @@ follows):
   smoothing (Sec. 3.3 and Sec. 4.1), local correction (eq.
   localCorrection), the V-cycle (Algorithm 1) and the outer iterations
   (fixed point, CG, GMRES; Sec. 3.6 and Sec. 4).
+* ``ipdg``     -- the hybridized interior penalty family (SIPG-H, IIPG-H,
+  NIPG-H; eqs. IPDG_flux, SIPG_H, IPG_H): element matrices, static
+  condensation into the same trace system, recovery of u and
+  q = -kappa grad u, and the uncondensed system.
 * ``adjoint``  -- gradient of a misfit with respect to per-element
   log-permeability through the discrete adjoint of the HDG system
   (derived from eqs. HDG and HDG_flux; not in the paper).
@@ -32,4 +36,4 @@ the paper and the mathematics fix (energy identities, Propositions 1 and
 nested-dissection limit, complex-step derivatives).  Functions without
 such a pin say "parity unpinned" in their docstring.
 """
-from . import refelem, hdg, mg, adjoint  # noqa: F401
+from . import refelem, hdg, mg, adjoint, ipdg  # noqa: F401

@@ -1,0 +1,297 @@
+"""Pins of the oracle's hybridized IPDG family (Sec. 2, eqs. IPDG_flux,
+SIPG_H, IPG_H; Sec. 4.1, Tables NIPG_J, NIPG_gs, NIPG_bj).
+
+I1  SIPG-H: the local matrix and the element map are symmetric, the local
+    matrix is positive definite at tau = (p+1)(p+2)/h_min, and the trace
+    system is symmetric positive definite; NIPG-H and IIPG-H are not
+    symmetric (their conservation rows are not the transpose of the local
+    right-hand side), and the symmetric part of their local matrix is definite.
+I2  constants lie in the kernel of every element map (u = 1, lambda = 1
+    solve the local problem and carry no flux).
+I3  polynomial reproduction: for u in Q^k and f = -kappa lap u the discrete
+    traces, scalar and flux are exact, for every s_f, in 2D and 3D, also
+    with kappa varying from element to element where the exact flux allows.
+I4  static condensation = the uncondensed (u, lambda) system.
+I5  convergence rates: u in L2 of order k+1 for SIPG-H, and for IIPG-H and
+    NIPG-H at odd k; order k for even k; flux of order k.
+I6  the multigrid of Sec. 3 on the nonsymmetric trace operator: Galerkin
+    identity Q A I = J^T S J with S the true Schur complement, Q != I^T,
+    local correction zeroes the interior residual, and the
+    nested-dissection limit is a direct solver.
+I7  the paper's iteration counts for NIPG-H, Example I: within 2 of Table
+    NIPG_bj and within 1 of Table NIPG_gs (p = 1..4, levels 2..4), within 3
+    of Table NIPG_J (p = 1, 2); SIPG-H and IIPG-H within 2 of Table NIPG_bj
+    (the paper reports them as similar).
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mg
+from oracle.ipdg import IPDG
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SCHEMES = ["sipg", "iipg", "nipg"]
+
+
+def _tau(d, n, k):
+    """tau = (p+1)(p+2)/h_min, h_min the element diameter sqrt(d)/n."""
+    return (k + 1) * (k + 2) * n / np.sqrt(d)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_I1_sipg_symmetric_positive_definite(k):
+    n = 4
+    P = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), "sipg")
+    L, R, C = P.blocks(0)
+    assert np.abs(L - L.T).max() <= 1e-14 * np.abs(L).max()
+    assert np.abs(C - R.T).max() == 0.0
+    assert np.linalg.eigvalsh(L).min() > 0
+    Ae = P.element_dtn(0)
+    assert np.abs(Ae - Ae.T).max() <= 1e-13 * np.abs(Ae).max()
+    A, _, _ = P.assemble()
+    Ad = A.toarray()
+    assert np.abs(Ad - Ad.T).max() <= 1e-13 * np.abs(Ad).max()
+    assert np.linalg.eigvalsh(Ad).min() > 0
+    for s in ("iipg", "nipg"):
+        Q = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), s)
+        Ls, Rs, Cs = Q.blocks(0)
+        assert np.abs(Cs - Rs.T).max() > 1e-3 * np.abs(Rs).max()
+        assert np.linalg.eigvalsh(0.5 * (Ls + Ls.T)).min() > 0
+        As = Q.element_dtn(0)
+        assert np.abs(As - As.T).max() > 1e-3 * np.abs(As).max()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 3), (3, 2)])
+def test_I2_constants_in_kernel(scheme, d, k):
+    n = 2
+    kap = np.array([0.3, 7.0, 1.0, 2.0, 5.0, 0.1, 1.5, 9.0][:n ** d])
+    P = IPDG(d, n, k, _tau(d, n, k), kap, scheme)
+    for T in range(n ** d):
+        Ae = P.element_dtn(T)
+        assert np.abs(Ae @ np.ones(P.nl)).max() <= 1e-13 * np.abs(Ae).max()
+        u, q = P.recover_element(T, np.ones(P.nl))
+        assert np.abs(u - 1).max() <= 1e-13 and np.abs(q).max() <= 1e-11
+
+
+def _poly(d, k, coef, kap):
+    """u = sum_a coef_a x^a over a in {0..k}^d, and f = -kap lap u."""
+    alphas = list(itertools.product(range(k + 1), repeat=d))
+
+    def u(X):
+        return sum(c * np.prod([X[:, i] ** a[i] for i in range(d)], axis=0) for c, a in zip(coef, alphas))
+
+    def grad(X):
+        out = np.zeros((len(X), d))
+        for c, a in zip(coef, alphas):
+            for i in range(d):
+                if a[i] >= 1:
+                    t = c * a[i] * np.ones(len(X))
+                    for j in range(d):
+                        t = t * X[:, j] ** (a[j] - 1 if j == i else a[j])
+                    out[:, i] += t
+        return out
+
+    def f(X):
+        out = np.zeros(len(X))
+        for c, a in zip(coef, alphas):
+            for i in range(d):
+                if a[i] >= 2:
+                    t = c * a[i] * (a[i] - 1) * np.ones(len(X))
+                    for j in range(d):
+                        t = t * X[:, j] ** (a[j] - 2 if j == i else a[j])
+                    out -= kap * t
+        return out
+    return u, grad, f
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_I3_polynomial_reproduction(scheme, d, k):
+    n, kap = 3, 2.5
+    rng = np.random.default_rng(10 * d + k)
+    coef = rng.standard_normal((k + 1) ** d)
+    u, grad, f = _poly(d, k, coef, kap)
+    P = IPDG(d, n, k, _tau(d, n, k), kap * np.ones(n ** d), scheme)
+    Xn = P.volume_nodes().reshape(-1, d)
+    fn = f(Xn).reshape(P.mesh.nel, -1)
+    A, g, lb = P.assemble(fn, u)
+    lam = spla.spsolve(A.tocsc(), g)
+    uh, qh = P.reconstruct(lam, fn, lb)
+    scale = np.abs(u(Xn)).max()
+    assert np.abs(lam - u(P.interior_trace_nodes())).max() <= 1e-11 * scale
+    assert np.abs(uh.ravel() - u(Xn)).max() <= 1e-11 * scale
+    qe = -kap * grad(Xn).reshape(P.mesh.nel, P.nv, d).transpose(0, 2, 1)
+    assert np.abs(qh - qe).max() <= 1e-10 * np.abs(qe).max()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_I3_reproduction_with_layered_kappa(scheme):
+    """u = 1 + 2x is exact for kappa constant along x: the x-flux -2 kappa
+    matches across every face normal to x and the y-flux vanishes."""
+    n, k = 4, 2
+    kap = np.repeat(10.0 ** np.linspace(-1, 1, n), n)  # element index x + n y
+    P = IPDG(2, n, k, _tau(2, n, k), kap, scheme)
+
+    def u(X):
+        return 1.0 + 2.0 * X[:, 0]
+    A, g, lb = P.assemble(None, u)
+    lam = spla.spsolve(A.tocsc(), g)
+    uh, qh = P.reconstruct(lam, None, lb)
+    Xn = P.volume_nodes().reshape(-1, 2)
+    assert np.abs(uh.ravel() - u(Xn)).max() <= 1e-11
+    assert np.abs(qh[:, 0, :] + 2.0 * kap[:, None]).max() <= 1e-10
+    assert np.abs(qh[:, 1, :]).max() <= 1e-10
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,n,k", [(2, 4, 2), (3, 2, 2)])
+def test_I4_condensed_equals_monolithic(scheme, d, n, k):
+    rng = np.random.default_rng(7)
+    kap = 10.0 ** rng.uniform(-1, 1, n ** d)
+    P = IPDG(d, n, k, _tau(d, n, k), kap, scheme)
+    f = rng.standard_normal((n ** d, P.nv))
+
+    def gD(X):
+        return np.cos(X.sum(axis=1))
+    A, g, lb = P.assemble(f, gD)
+    lam = spla.spsolve(A.tocsc(), g)
+    u, q = P.reconstruct(lam, f, lb)
+    lm, um, qm = P.monolithic_solve(f, gD)
+    assert np.abs(lam - lm).max() <= 1e-11 * np.abs(lm).max()
+    assert np.abs(u - um).max() <= 1e-11 * np.abs(um).max()
+    assert np.abs(q - qm).max() <= 1e-10 * np.abs(qm).max()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_I5_convergence_rates(scheme, k):
+    pi = np.pi
+
+    def u(X):
+        return np.sin(pi * X[:, 0]) * np.sin(pi * X[:, 1])
+
+    def grad(X):
+        return np.stack([pi * np.cos(pi * X[:, 0]) * np.sin(pi * X[:, 1]),
+                         pi * np.sin(pi * X[:, 0]) * np.cos(pi * X[:, 1])], axis=1)
+    eu, eq = [], []
+    for n in (4, 8, 16):
+        P = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), scheme)
+        fn = (2 * pi ** 2 * u(P.volume_nodes().reshape(-1, 2))).reshape(P.mesh.nel, -1)
+        A, g, lb = P.assemble(fn, u)
+        lam = spla.spsolve(A.tocsc(), g)
+        uh, qh = P.reconstruct(lam, fn, lb)
+        a, b = P.errors(uh, qh, u, grad)
+        eu.append(a)
+        eq.append(b)
+    ru = np.log2(eu[1] / eu[2])
+    rq = np.log2(eq[1] / eq[2])
+    order_u = k + 1 if (scheme == "sipg" or k % 2 == 1) else k
+    assert ru >= order_u - 0.1, (ru, order_u)
+    assert ru <= order_u + 0.3, (ru, order_u)
+    assert rq >= k - 0.1, rq
+
+
+def _nipg_problem(d, n, k, scheme="nipg", seed=0):
+    rng = np.random.default_rng(seed)
+    kap = 10.0 ** rng.uniform(-1, 1, n ** d)
+    P = IPDG(d, n, k, _tau(d, n, k), kap, scheme)
+    f = rng.standard_normal((n ** d, P.nv))
+    A, g, _ = P.assemble(f)
+    return P, A, g
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 1), (2, 8, 3), (3, 4, 1)])
+def test_I6_nonsymmetric_galerkin_chain(d, n, k):
+    P, A, g = _nipg_problem(d, n, k)
+    H = mg.Hierarchy(A, d, n, k)
+    for i in range(len(H.levels) - 1):
+        L, Lc = H.levels[i], H.levels[i + 1]
+        G = (L.Q @ L.A @ L.I).toarray()
+        Ac = Lc.A.toarray()
+        assert np.abs(G - Ac).max() <= 1e-12 * np.abs(Ac).max()
+        if L.kind == "h":
+            Ad = L.A.toarray()
+            I, B = L.I_dofs, L.B_dofs
+            S = Ad[np.ix_(B, B)] - Ad[np.ix_(B, I)] @ np.linalg.solve(Ad[np.ix_(I, I)], Ad[np.ix_(I, B)])
+            J = L.JB.toarray()
+            assert np.abs(J.T @ S @ J - Ac).max() <= 1e-11 * np.abs(Ac).max()
+            assert abs(L.Q - L.I.T).max() > 1e-6 * abs(L.Q).max()
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 1), (3, 4, 1)])
+def test_I6_local_correction_nonsymmetric(d, n, k):
+    P, A, g = _nipg_problem(d, n, k)
+    H = mg.Hierarchy(A, d, n, k)
+    L = H.levels[0]
+    rng = np.random.default_rng(2)
+    e = rng.standard_normal(A.shape[0])
+    rho = g - A @ e
+    rho2 = g - A @ (e + H.local_correction(0, rho))
+    assert np.abs(rho2[L.I_dofs]).max() <= 1e-11 * np.abs(rho).max()
+    assert np.allclose(L.Q @ rho2, L.JB.T @ rho2[L.B_dofs], rtol=0, atol=1e-11 * np.abs(rho).max())
+    assert np.allclose(L.Q @ rho, L.Q @ rho2, rtol=0, atol=1e-11 * np.abs(rho).max())
+
+
+@pytest.mark.parametrize("scheme", ["iipg", "nipg"])
+def test_I6_nested_dissection_limit_nonsymmetric(scheme):
+    P, A, g = _nipg_problem(2, 16, 2, scheme)
+    H = mg.Hierarchy(A, 2, 16, 2, coarse="exact", sweeps=0)
+    e = H.vcycle(g)
+    lam = spla.spsolve(A.tocsc(), g)
+    assert np.linalg.norm(g - A @ e) <= 1e-11 * np.linalg.norm(g)
+    assert np.abs(e - lam).max() <= 1e-9 * np.abs(lam).max()
+
+
+def _ex1_source(X):
+    """f = -lap u for u = x y exp(x^2 y^3), differentiated by hand."""
+    x, y = X[:, 0], X[:, 1]
+    e = np.exp(x ** 2 * y ** 3)
+    uxx = y * e * (6 * x * y ** 3 + 4 * x ** 3 * y ** 6)
+    uyy = x * e * (12 * x ** 2 * y ** 2 + 9 * x ** 4 * y ** 5)
+    return -(uxx + uyy)
+
+
+def _ex1(k, L, scheme, smoother, omega=1.0):
+    n = 2 ** L
+
+    def u(X):
+        return X[:, 0] * X[:, 1] * np.exp(X[:, 0] ** 2 * X[:, 1] ** 3)
+    P = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), scheme)
+    fn = _ex1_source(P.volume_nodes().reshape(-1, 2)).reshape(P.mesh.nel, -1)
+    A, g, _ = P.assemble(fn, u)
+    H = mg.Hierarchy(A, 2, n, k, sweeps=3, growth=2, smoother=smoother, omega=omega)
+    r1 = mg.mg_solve(H, A, g, tol=1e-9)
+    r2 = mg.gmres_solve(H, A, g, tol=1e-9, side="left")
+    return (r1.iters if r1.converged else "*"), (r2.iters if r2.converged else "*")
+
+
+def _golden():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "ex1_nipg_iterations.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            conv = [int(x) for x in t[2:]]
+            rows[(t[0], int(t[1]))] = (conv[:4], conv[4:])
+    return rows
+
+
+CASES_I7 = [("bj", "block_jacobi", 1.0, 2, k, "nipg") for k in (1, 2, 3, 4)] + \
+           [("gs", "lusgs", 1.0, 1, k, "nipg") for k in (1, 2, 3, 4)] + \
+           [("J", "jacobi", 2.0 / 3.0, 3, k, "nipg") for k in (1, 2)] + \
+           [("bj", "block_jacobi", 1.0, 2, k, s) for k in (1, 2, 3) for s in ("sipg", "iipg")]
+
+
+@pytest.mark.parametrize("table,smoother,omega,slack,k,scheme", CASES_I7)
+def test_I7_paper_counts(table, smoother, omega, slack, k, scheme):
+    gold = _golden()[(table, k)]
+    for j, L in enumerate([2, 3, 4]):
+        mgc, gmc = _ex1(k, L, scheme, smoother, omega)
+        assert mgc != "*" and gmc != "*"
+        assert abs(mgc - gold[0][j]) <= slack and abs(gmc - gold[1][j]) <= slack, (L, mgc, gmc, gold)

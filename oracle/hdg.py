@@ -109,11 +109,15 @@ class HDG:
     ``kappa`` is either one value per element (shape [N_T]) or values at
     the volume Gauss points (shape [N_T, (k+2)^d], points lexicographic
     with x fastest).  Complex kappa is accepted (complex-step checks).
+    ``tau_kappa``: the stabilization of element T is tau * kappa_T (the
+    paper's tau = kappa / h_min of Example IV, Sec. 4.4); needs one kappa
+    per element.
     """
 
-    def __init__(self, d, n, k, tau, kappa):
+    def __init__(self, d, n, k, tau, kappa, tau_kappa=False):
         self.mesh = Mesh(d, n)
         self.d, self.n, self.k, self.tau = d, n, k, tau
+        self.tau_kappa = tau_kappa
         h = self.mesh.h
         self.nv = (k + 1) ** d
         self.ne = (k + 1) ** (d - 1)
@@ -198,12 +202,27 @@ class HDG:
     # ------------------------------------------------------------------
     def set_kappa(self, kappa):
         kappa = np.asarray(kappa)
+        if self.tau_kappa and kappa.ndim != 1:
+            raise ValueError("tau proportional to kappa needs one kappa per element")
+        self.kappa_el = kappa if kappa.ndim == 1 else None
         if kappa.ndim == 1:
             kappa = np.repeat(kappa[:, None], self.nq, axis=1)
         if kappa.shape != (self.mesh.nel, self.nq):
             raise ValueError("kappa has the wrong shape")
         self.kappa_qp = kappa
         self.dtype = np.result_type(kappa.dtype, np.float64)
+
+    def tau_of(self, T):
+        """The stabilization of element T: tau, or tau * kappa_T."""
+        return self.tau * self.kappa_el[T] if self.tau_kappa else self.tau
+
+    def R_of(self, T):
+        """R_T = [-F; tau_T G] (right-hand side of the local problem)."""
+        return self.R if not self.tau_kappa else np.vstack([-self.F, self.tau_of(T) * self.G])
+
+    def S_of(self, T):
+        """S_T = [F; tau_T G] (the flux terms of the conservation rows)."""
+        return self.S if not self.tau_kappa else np.vstack([self.F, self.tau_of(T) * self.G])
 
     def local_matrix(self, T):
         """L_T = [[A_T, Bdiv], [C, tau E]] for element T (first local eq. on
@@ -215,19 +234,20 @@ class HDG:
             L[c * nv:(c + 1) * nv, c * nv:(c + 1) * nv] = Mk
         L[:d * nv, d * nv:] = self.Bdiv
         L[d * nv:, :d * nv] = self.C
-        L[d * nv:, d * nv:] = self.tau * self.E
+        L[d * nv:, d * nv:] = self.tau_of(T) * self.E
         return L
 
     def element_dtn(self, T, b=None):
         """Element DtN matrix and load: A^e = tau H - S^T L^-1 R and
         b^e = S^T L^-1 [0; b] (static condensation, Sec. 2)."""
         L = self.local_matrix(T)
-        Ae = self.tau * self.H - self.S.T @ np.linalg.solve(L, self.R)
+        S = self.S_of(T)
+        Ae = self.tau_of(T) * self.H - S.T @ np.linalg.solve(L, self.R_of(T))
         if b is None:
             return Ae
         rhs = np.zeros(L.shape[0], dtype=np.result_type(self.dtype, b.dtype))
         rhs[self.d * self.nv:] = b
-        return Ae, self.S.T @ np.linalg.solve(L, rhs)
+        return Ae, S.T @ np.linalg.solve(L, rhs)
 
     def all_element_dtn(self):
         """A^e for every element, shape [N_T, n_f n_e, n_f n_e]."""
@@ -368,7 +388,7 @@ class HDG:
         (u_T [N_v], q_T [d, N_v]) from its local traces Lambda_T [n_f n_e]."""
         d, nv = self.d, self.nv
         lam_T = np.asarray(lam_T)
-        rhs = (self.R @ lam_T).astype(np.result_type(self.dtype, lam_T.dtype))
+        rhs = (self.R_of(T) @ lam_T).astype(np.result_type(self.dtype, lam_T.dtype))
         if f_T is not None:
             rhs = rhs.astype(np.result_type(rhs.dtype, np.asarray(f_T).dtype))
             rhs[d * nv:] += self.M @ f_T
@@ -457,14 +477,15 @@ class HDG:
             jb = np.nonzero(bi >= 0)[0]
             # local equations: L w - R Lambda = [0; b]
             put(wr, wr, L)
-            put(wr, nel * nw + gi[ii], -self.R[:, ii])
+            R, S, tT = self.R_of(T), self.S_of(T), self.tau_of(T)
+            put(wr, nel * nw + gi[ii], -R[:, ii])
             rhs[wr[d * nv:]] += self.M @ f_nodal[T]
-            rhs[wr] += self.R[:, jb] @ lam_b[bi[jb]]
+            rhs[wr] += R[:, jb] @ lam_b[bi[jb]]
             # conservation rows: sum_T (S^T w - tau H Lambda) = 0
             lr = nel * nw + gi[ii]
-            put(lr, wr, self.S.T[ii, :])
-            put(lr, nel * nw + gi[ii], -self.tau * self.H[np.ix_(ii, ii)])
-            rhs[lr] += self.tau * self.H[np.ix_(ii, jb)] @ lam_b[bi[jb]]
+            put(lr, wr, S.T[ii, :])
+            put(lr, nel * nw + gi[ii], -tT * self.H[np.ix_(ii, ii)])
+            rhs[lr] += tT * self.H[np.ix_(ii, jb)] @ lam_b[bi[jb]]
         K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                           shape=(N, N)).tocsc()
         sol = spla.spsolve(K, rhs)

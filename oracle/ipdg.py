@@ -33,7 +33,9 @@ component of grad u_h lies in Q^k, so its nodal values represent it exactly.
 
 Discretization contract: the HDG element of ``oracle.hdg`` (meshes, node
 sets, face numbering, quadrature, strong Dirichlet data); kappa is one value
-per element (the face terms take the element's own value).
+per element (the face terms take the element's own value); with
+``tau_kappa`` the stabilization of element T is tau * kappa_T (the paper's
+tau = kappa (p+1)(p+2)/h_min of Examples III and IV).
 """
 import numpy as np
 import scipy.sparse as sp
@@ -49,15 +51,14 @@ class IPDG(HDG):
     """Element matrices, condensed trace system and recovery of SIPG-H,
     IIPG-H and NIPG-H (eq. IPG_H with s_f = 1, 0, -1)."""
 
-    def __init__(self, d, n, k, tau, kappa, scheme="nipg"):
+    def __init__(self, d, n, k, tau, kappa, scheme="nipg", tau_kappa=False):
         if scheme not in SCHEMES:
             raise ValueError(f"unknown scheme {scheme}")
         kappa = np.asarray(kappa)
         if kappa.shape != (n ** d,):
             raise ValueError("IPDG takes one kappa per element")
         self.scheme, self.sf = scheme, SCHEMES[scheme]
-        super().__init__(d, n, k, tau, kappa)
-        self.kappa_el = kappa
+        super().__init__(d, n, k, tau, kappa, tau_kappa)
         h = self.mesh.h
         nv, ne, nl = self.nv, self.ne, self.nl
         xi = self.xi
@@ -98,7 +99,7 @@ class IPDG(HDG):
     # ------------------------------------------------------------------
     def blocks(self, T):
         """(L_T, R_T, C_T) of element T."""
-        kap, tau, sf = float(self.kappa_el[T]), self.tau, self.sf
+        kap, tau, sf = float(self.kappa_el[T]), self.tau_of(T), self.sf
         L = kap * (self.K - sf * self.N - self.N.T) + tau * self.E
         R = tau * self.G - sf * kap * self.Dn
         C = tau * self.G.T - kap * self.Dn.T
@@ -110,7 +111,7 @@ class IPDG(HDG):
     def element_dtn(self, T, b=None):
         """A^e = tau H - C L^-1 R and b^e = C L^-1 b (static condensation)."""
         L, R, C = self.blocks(T)
-        Ae = self.tau * self.H - C @ np.linalg.solve(L, R)
+        Ae = self.tau_of(T) * self.H - C @ np.linalg.solve(L, R)
         if b is None:
             return Ae
         return Ae, C @ np.linalg.solve(L, np.asarray(b, dtype=float))
@@ -166,8 +167,8 @@ class IPDG(HDG):
             rhs[ur] += self.M @ f_nodal[T] + R[:, jb] @ lam_b[bi[jb]]
             lr = nel * nv + gi[ii]
             put(lr, ur, C[ii, :])
-            put(lr, nel * nv + gi[ii], -self.tau * self.H[np.ix_(ii, ii)])
-            rhs[lr] += self.tau * self.H[np.ix_(ii, jb)] @ lam_b[bi[jb]]
+            put(lr, nel * nv + gi[ii], -self.tau_of(T) * self.H[np.ix_(ii, ii)])
+            rhs[lr] += self.tau_of(T) * self.H[np.ix_(ii, jb)] @ lam_b[bi[jb]]
         Kg = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                            shape=(Nt, Nt)).tocsc()
         sol = spla.spsolve(Kg, rhs)

@@ -155,6 +155,35 @@ void hdg_default_opts(hdg_mg_opts* opts);
 hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
                      int store_recovery, void* hip_stream, hdg_handle* out);
 
+/* Discretizations of the trace system (Sec. 2): HDG (eqs. HDG, HDG_flux)
+ * and the hybridized interior penalty family of eq. IPG_H, with
+ * s_f = 1 (SIPG-H, eq. SIPG_H), 0 (IIPG-H) and -1 (NIPG-H). */
+enum { HDG_SCHEME_HDG = 0, HDG_SCHEME_SIPG = 1, HDG_SCHEME_IIPG = 2, HDG_SCHEME_NIPG = 3 };
+/* Or-ed into the scheme of hdg_setup_scheme: element T is stabilized with
+ * tau * kappa_T instead of tau (the paper's tau = kappa / h_min for HDG and
+ * kappa (p+1)(p+2) / h_min for IPDG in Examples III and IV); needs
+ * HDG_KAPPA_PER_ELEMENT, and hdg_adjoint does not take it. */
+enum { HDG_SCHEME_TAU_KAPPA = 16 };
+
+/* hdg_setup for any scheme.  For the IPDG schemes the element maps are
+ *   A^e = tau H - C_T L_T^-1 R_T,  L_T = kappa (K - s_f N - N^T) + tau E,
+ *   R_T = tau G - s_f kappa D,      C_T = tau G^T - kappa D^T
+ * (eqs. IPDG_flux, IPG_H with the conservation rows of eq. conservation;
+ * K the stiffness matrix, N_ij = <phi_j, grad phi_i . n>,
+ * D_il = <mu_l, grad phi_i . n>, E, G, H the boundary mass matrices), the
+ * load map is C_T L_T^-1 M_T, and recovery gives u_T and q_T = -kappa
+ * grad u_T at the nodes.  IPDG takes kappa per element only
+ * (HDG_KAPPA_AT_QP: HDG_ERR_UNSUPPORTED) and needs L_T to be nonsingular
+ * with nonzero leading minors, which holds when its symmetric part is
+ * positive definite (tau = (p+1)(p+2)/h_min does this for every s_f).
+ * IIPG-H and NIPG-H give a nonsymmetric trace system: their builds reject
+ * HDG_METHOD_PCG (HDG_ERR_UNSUPPORTED) and restrict with
+ * Q = [-J^T A_BI A_II^-1, J^T] (eq. n_1_Qk) instead of I^T; hdg_adjoint
+ * is HDG only.  Other arguments as for hdg_setup. */
+hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                            int scheme, int store_recovery, void* hip_stream, hdg_handle* out);
+/* (scheme: one HDG_SCHEME_* value, optionally | HDG_SCHEME_TAU_KAPPA) */
+
 /* Re-form A^e for a new kappa (same layout rules); invalidates the
  * hierarchy (call hdg_mg_build again). */
 hdg_status hdg_update_kappa(hdg_handle h, const double* kappa, int kappa_kind);
@@ -227,7 +256,8 @@ hdg_status hdg_autotune(hdg_handle h, const hdg_mg_opts* base, int nrhs, hdg_mg_
 hdg_status hdg_rhs_noalloc(hdg_handle h, const double* rhs, int rhs_kind, const double* g_dirichlet, double* g);
 
 /* Local recovery (q, u) = L_T^-1 (R_T Lambda_T + [0; b_T]) element by
- * element (Sec. 2); needs store_recovery at setup. */
+ * element (Sec. 2); for the IPDG schemes u_T = L_T^-1 (R_T Lambda_T + b_T)
+ * and q_T = -kappa_T grad u_T at the nodes.  Needs store_recovery at setup. */
 hdg_status hdg_reconstruct(hdg_handle h, const double* lambda, const double* rhs, int rhs_kind,
                            const double* g_dirichlet, double* u, double* q);
 
@@ -236,6 +266,7 @@ hdg_status hdg_reconstruct(hdg_handle h, const double* lambda, const double* rhs
  * solve the adjoint trace system (the forward operator with load j), recover
  * q*, and return grad[T] = dJ/d(log kappa_T) = -(q*_T)^T A_T q_T, A_T the
  * kappa^-1 weighted mass.  Derived from eqs. HDG and HDG_flux. */
+/* (HDG handles with a scalar tau only; others get HDG_ERR_UNSUPPORTED.) */
 hdg_status hdg_adjoint(hdg_handle h, const double* dJdu, const double* q_fwd, double tol,
                        double* grad_log_kappa, hdg_solve_info* info);
 

@@ -19,6 +19,12 @@ using namespace hdg;
 struct hdg_problem {
   int d = 0, n = 0, k = 0;
   double tau = 1.0;
+  // discretization (HDG_SCHEME_*): s_f of eq. IPG_H, and whether the trace
+  // operator is symmetric (HDG, SIPG-H)
+  int scheme = HDG_SCHEME_HDG;
+  double sf = 0.0;
+  bool sym = true;
+  bool tau_kappa = false;  // element T stabilized with tau * kappa_T (HDG_SCHEME_TAU_KAPPA)
   hipStream_t st = nullptr;      // caller's stream: all work is ordered on it
   hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
   // execution form, from hdg_mg_opts.variant at build
@@ -46,7 +52,10 @@ struct hdg_problem {
   RefDevice rd;
   long nelem = 0;
   int nv = 0, ne = 0, nl = 0, nq = 0;
+  // W: load map (b^e = W^T b); Kinv / Minv: HDG recovery factors; for the
+  // IPDG schemes Kinv holds L^-1 and Xr the recovery block L^-1 R
   double *kqp = nullptr, *Ae = nullptr, *W = nullptr, *Kinv = nullptr, *Minv = nullptr, *ework = nullptr;
+  double* Xr = nullptr;
   int* bad = nullptr;
   int* hbad = nullptr;
   bool store_recovery = false;
@@ -139,7 +148,10 @@ bool check_kappa(hdg_problem* P, const double* kappa, int kind) {
 }
 
 void form_elements(hdg_problem* P) {
-  launch_element_dtn(P->d, P->k, P->nelem, P->tau, P->rd, P->kqp, P->Ae, P->W, P->Kinv, P->Minv, P->st);
+  if (P->scheme == HDG_SCHEME_HDG)
+    launch_element_dtn(P->d, P->k, P->nelem, P->tau, P->tau_kappa, P->rd, P->kqp, P->Ae, P->W, P->Kinv, P->Minv, P->st);
+  else
+    launch_ipdg_dtn(P->d, P->k, P->nelem, P->tau, P->tau_kappa, P->sf, P->rd, P->kqp, P->nq, P->Ae, P->W, P->Xr, P->Kinv, P->st);
 }
 
 void drop_graphs(hdg_problem* P) {
@@ -941,7 +953,17 @@ hdg_status hdg_reference_nodes(int k, double* gll, double* gauss) {
 
 hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
                      int store_recovery, void* hip_stream, hdg_handle* out) {
+  return hdg_setup_scheme(mesh, k, tau, kappa, kappa_kind, HDG_SCHEME_HDG, store_recovery, hip_stream, out);
+}
+
+hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                            int scheme, int store_recovery, void* hip_stream, hdg_handle* out) {
   if (!mesh || !out || !kappa) return HDG_ERR_INVALID_ARG;
+  if (scheme & ~(15 | HDG_SCHEME_TAU_KAPPA)) return HDG_ERR_INVALID_ARG;
+  const bool tau_kappa = (scheme & HDG_SCHEME_TAU_KAPPA) != 0;
+  scheme &= 15;
+  if (scheme < HDG_SCHEME_HDG || scheme > HDG_SCHEME_NIPG) return HDG_ERR_INVALID_ARG;
+  if ((scheme != HDG_SCHEME_HDG || tau_kappa) && kappa_kind == HDG_KAPPA_AT_QP) return HDG_ERR_UNSUPPORTED;
   if (mesh->dim != 2 && mesh->dim != 3) return HDG_ERR_UNSUPPORTED;
   if (mesh->n < 1 || mesh->n > (mesh->dim == 2 ? 8192 : 512)) return HDG_ERR_INVALID_ARG;
   if (k < 1 || (mesh->dim == 2 && k > 6) || (mesh->dim == 3 && k > 3)) return HDG_ERR_UNSUPPORTED;
@@ -955,6 +977,10 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->n = mesh->n;
   P->k = k;
   P->tau = tau;
+  P->scheme = scheme;
+  P->tau_kappa = tau_kappa;
+  P->sf = scheme == HDG_SCHEME_SIPG ? 1.0 : scheme == HDG_SCHEME_IIPG ? 0.0 : -1.0;
+  P->sym = scheme == HDG_SCHEME_HDG || scheme == HDG_SCHEME_SIPG;
   P->st = (hipStream_t)hip_stream;
   P->store_recovery = store_recovery != 0;
   const auto t0 = std::chrono::steady_clock::now();
@@ -974,12 +1000,21 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
   P->rd.H = upload(P, P->ref.H);
   P->rd.M = upload(P, P->ref.M);
   P->rd.Jp = upload(P, P->ref.Jp);
+  if (scheme != HDG_SCHEME_HDG) {
+    P->rd.Kst = upload(P, P->ref.Kst);
+    P->rd.Nn = upload(P, P->ref.Nn);
+    P->rd.Dn = upload(P, P->ref.Dn);
+    P->rd.Dnode = upload(P, P->ref.Dnode);
+  }
   P->kqp = dalloc<double>(P, P->nelem * P->nq, false);
   P->Ae = dalloc<double>(P, P->nelem * P->nl * P->nl, false);
   P->W = dalloc<double>(P, P->nelem * P->nv * P->nl, false);
   if (P->store_recovery) {
     P->Kinv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
-    P->Minv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
+    if (scheme == HDG_SCHEME_HDG)
+      P->Minv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
+    else
+      P->Xr = dalloc<double>(P, P->nelem * P->nv * P->nl, false);
   }
   P->ework = dalloc<double>(P, P->nelem * (P->nv + P->nl), false);
   P->bad = dalloc<int>(P, 1, false);
@@ -1010,6 +1045,7 @@ hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kapp
 hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
   if (!P || !kappa) return HDG_ERR_INVALID_ARG;
   if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
+  if ((P->scheme != HDG_SCHEME_HDG || P->tau_kappa) && kappa_kind == HDG_KAPPA_AT_QP) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   if (!check_kappa(P, kappa, kappa_kind)) return HDG_ERR_INVALID_ARG;
@@ -1038,6 +1074,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.refine_red == 0.0) o.refine_red = 1e-5;
   if (o.coarse_n < 2) o.coarse_n = 2;
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
+  if (!P->sym && o.method == HDG_METHOD_PCG) return HDG_ERR_UNSUPPORTED;  // CG needs a symmetric operator
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   free_build(P);
@@ -1056,6 +1093,13 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (P->ops32 || o.smoother != HDG_SMOOTHER_BLOCK_JACOBI) {
     P->pack = false;
     P->fuse = false;
+    P->tail_nmax = 0;
+  }
+  // nonsymmetric operators: no packed (symmetrised) element maps, and no
+  // coarse tail (it restricts with P^T); the grid kernels take the
+  // restriction block R
+  if (!P->sym) {
+    P->pack = false;
     P->tail_nmax = 0;
   }
   const int cap = P->cap;
@@ -1088,6 +1132,14 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     F.AIIinv32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.nI), true);
     F.P64 = dalloc<double>(P, pm * vpad<double>(F.nI * F.ncl), true);
     F.P32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.ncl), true);
+    F.sym = P->sym;
+    if (F.sym) {
+      F.R64 = F.P64;
+      F.R32 = F.P32;
+    } else {
+      F.R64 = dalloc<double>(P, pm * vpad<double>(F.nI * F.ncl), true);
+      F.R32 = dalloc<float>(P, pm * vpad<float>(F.nI * F.ncl), true);
+    }
     F.cb[0] = dalloc<double>(P, F.nmacro * F.ncl * cap, true);
     F.cb[1] = dalloc<float>(P, F.nmacro * F.ncl * cap, true);
     C.Aelem = dalloc<double>(P, C.nelem * C.nl * C.nl, true);
@@ -1907,8 +1959,12 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
   if (!P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
-  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->kqp, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->W, P->Kinv,
-                     P->Minv, P->ework, u, q, P->st);
+  if (P->scheme == HDG_SCHEME_HDG)
+    launch_reconstruct(P->d, P->k, P->n, P->tau, P->tau_kappa, P->rd, P->kqp, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0,
+                       P->W, P->Kinv, P->Minv, P->ework, u, q, P->st);
+  else
+    launch_ipdg_reconstruct(P->d, P->k, P->n, P->rd, P->kqp, P->nq, lambda, gdir, rhs,
+                            rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->Xr, P->Kinv, P->ework, u, q, P->st);
   return HDG_OK;
   HDG_GUARD_END
 }
@@ -1916,6 +1972,7 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
 hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, double tol, double* grad,
                        hdg_solve_info* info) {
   if (!P || !dJdu || !q_fwd || !grad || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  if (P->scheme != HDG_SCHEME_HDG || P->tau_kappa) return HDG_ERR_UNSUPPORTED;
   if (!P->built || !P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
   if (!P->ustar) {
@@ -1934,7 +1991,7 @@ hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, do
   form_rhs(P, dJdu, HDG_RHS_F_LOAD, nullptr, P->g);
   blas_fill<double>(P->lam, 0.0, P->N, P->st);
   hdg_status s = solve_one(P, P->g, P->lam, tol, info);
-  launch_reconstruct(P->d, P->k, P->n, P->tau, P->rd, P->kqp, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
+  launch_reconstruct(P->d, P->k, P->n, P->tau, 0, P->rd, P->kqp, P->lam, nullptr, dJdu, 1, P->W, P->Kinv, P->Minv, P->ework,
                      P->ustar, P->qstar, P->st);
   launch_grad(P->d, P->k, P->nelem, P->rd, P->kqp, q_fwd, P->qstar, grad, P->st);
   HDG_CHECK(hipStreamSynchronize(P->st));

@@ -5,8 +5,10 @@
 //  * per coarse macro-element: assembly of the 2^d children on the interior
 //    faces I and boundary faces B of the macro-element, A_II^-1,
 //    S = A_BB - A_BI A_II^-1 A_IB, coarse matrix J^T S J (eq. Akm1) and the
-//    prolongation block P = -A_II^-1 A_IB J (eq. n_1_Ik).  The trace operator
-//    of HDG is symmetric, so A_BI is taken as A_IB^T (Q = I^T, eq. n_1_Qk),
+//    prolongation block P = -A_II^-1 A_IB J (eq. n_1_Ik).  On symmetric levels
+//    (HDG, SIPG-H) A_BI is taken as A_IB^T and the restriction is Q = I^T
+//    (eq. n_1_Qk); otherwise A_BI is read from the children and the
+//    restriction block R = -A_II^-T A_BI^T J is formed as well,
 //  * dense inverse of the coarsest operator (Algorithm 1, B_1 = A_1^-1).
 #include "hdg_internal.hpp"
 
@@ -188,7 +190,8 @@ template <int D, int NT>
 __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __restrict__ Achild,
                                                          double* __restrict__ Acoarse, double* __restrict__ Ai64,
                                                          float* __restrict__ Ai32, double* __restrict__ P64,
-                                                         float* __restrict__ P32) {
+                                                         float* __restrict__ P32, double* __restrict__ R64,
+                                                         float* __restrict__ R32) {
   constexpr int NC = 1 << (D - 1);    // DOFs per (sub)face
   constexpr int NS = NC;              // sub-faces per macro-face
   constexpr int NLC = 2 * D * NC;     // child local size == coarse local size
@@ -199,6 +202,9 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
   __shared__ double sBB[NB * NB];
   __shared__ double sY[NI * NLC];
   __shared__ int map[(1 << D) * NLC];
+  __shared__ int bsrc[NB];      // B DOF -> (child, child-local DOF) that holds it
+  __shared__ int isrc[2 * NI];  // I DOF -> its two (child, child-local DOF)
+  const bool nonsym = R64 != nullptr;
   const int tid = threadIdx.x;
   const int nm = n / 2;
   const long M = blockIdx.x;
@@ -222,11 +228,19 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
         t |= ((ch >> a) & 1) << j;
         ++j;
       }
-    if (q == 1)
+    if (q == 1) {
       map[idx] = (c * NS + t) * NC + v;
-    else
+      isrc[2 * map[idx] + ((ch >> c) & 1)] = idx;
+    } else {
       map[idx] = -(((2 * c + (q == 2 ? 1 : 0)) * NS + t) * NC + v) - 1;
+      bsrc[-map[idx] - 1] = idx;
+    }
   }
+  auto child_elem = [&](int ch) {
+    long T = 0;
+    for (int a = D - 1; a >= 0; --a) T = T * n + 2 * m[a] + ((ch >> a) & 1);
+    return T;
+  };
   for (int idx = tid; idx < NI * NI; idx += NT) sII[idx] = 0.0;
   for (int idx = tid; idx < NI * NB; idx += NT) sIB[idx] = 0.0;
   for (int idx = tid; idx < NB * NB; idx += NT) sBB[idx] = 0.0;
@@ -251,21 +265,6 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
     __syncthreads();
   }
   gj_lds<NI>(sII, tid, NT);
-  // S = A_BB - A_IB^T A_II^-1 A_IB, column j owned by one thread
-  for (int j = tid; j < NB; j += NT) {
-    double x[NI];
-    for (int i = 0; i < NI; ++i) {
-      double s = 0.0;
-      for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sIB[l * NB + j];
-      x[i] = s;
-    }
-    for (int i = 0; i < NB; ++i) {
-      double s = 0.0;
-      for (int l = 0; l < NI; ++l) s += sIB[l * NB + i] * x[l];
-      sBB[i * NB + j] -= s;
-    }
-  }
-  __syncthreads();
   // J: coarse DOF (S, V) -> B DOF (S*NS + t, v) with weight jw(t, v, V)
   auto jw = [](int t, int v, int V) {
     double w = 1.0;
@@ -296,6 +295,75 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
   for (int idx = tid; idx < NI * NI; idx += NT) {
     Ai64[aos_off<double>(M, vpad<double>(NI * NI), idx)] = sII[idx];
     Ai32[aos_off<float>(M, vpad<float>(NI * NI), idx)] = (float)sII[idx];
+  }
+  __syncthreads();
+  if (!nonsym) {
+    // S = A_BB - A_IB^T A_II^-1 A_IB, column j owned by one thread
+    for (int j = tid; j < NB; j += NT) {
+      double x[NI];
+      for (int i = 0; i < NI; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sIB[l * NB + j];
+        x[i] = s;
+      }
+      for (int i = 0; i < NB; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < NI; ++l) s += sIB[l * NB + i] * x[l];
+        sBB[i * NB + j] -= s;
+      }
+    }
+  } else {
+    // Z = A_II^-1 A_IB in place of A_IB, one column per thread
+    for (int j = tid; j < NB; j += NT) {
+      double x[NI];
+      for (int i = 0; i < NI; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < NI; ++l) s += sII[i * NI + l] * sIB[l * NB + j];
+        x[i] = s;
+      }
+      for (int i = 0; i < NI; ++i) sIB[i * NB + j] = x[i];
+    }
+    __syncthreads();
+    // S = A_BB - A_BI Z: row i of A_BI lives in the one child that holds B DOF i
+    for (int idx = tid; idx < NB * NB; idx += NT) {
+      const int i = idx / NB, j = idx % NB;
+      const int ch = bsrc[i] / NLC, r = bsrc[i] % NLC;
+      const double* Ac = Achild + child_elem(ch) * NLC * NLC + r * NLC;
+      double s = 0.0;
+      for (int l = 0; l < NLC; ++l) {
+        const int ms = map[ch * NLC + l];
+        if (ms >= 0) s += Ac[l] * sIB[ms * NB + j];
+      }
+      sBB[idx] -= s;
+    }
+    // Y2 = A_BI^T J (into Y): column l of A_BI gathers the B rows of the two
+    // children that hold I DOF l
+    for (int idx = tid; idx < NI * NLC; idx += NT) {
+      const int l = idx / NLC, J = idx % NLC;
+      const int S = J / NC, V = J % NC;
+      double s = 0.0;
+      for (int side = 0; side < 2; ++side) {
+        const int ch = isrc[2 * l + side] / NLC, cl = isrc[2 * l + side] % NLC;
+        const double* Ac = Achild + child_elem(ch) * NLC * NLC;
+        for (int r = 0; r < NLC; ++r) {
+          const int mr = map[ch * NLC + r];
+          if (mr >= 0) continue;
+          const int i = -mr - 1;
+          if (i / (NS * NC) != S) continue;
+          s += Ac[r * NLC + cl] * jw((i / NC) % NS, i % NC, V);
+        }
+      }
+      sY[idx] = s;
+    }
+    __syncthreads();
+    // R = -A_II^-T Y2, written AoSoA over macro-elements like P
+    for (int idx = tid; idx < NI * NLC; idx += NT) {
+      const int i = idx / NLC, J = idx % NLC;
+      double s = 0.0;
+      for (int l = 0; l < NI; ++l) s += sII[l * NI + i] * sY[l * NLC + J];
+      R64[aos_off<double>(M, vpad<double>(NI * NLC), idx)] = -s;
+      R32[aos_off<float>(M, vpad<float>(NI * NLC), idx)] = (float)(-s);
+    }
   }
   __syncthreads();
   // T1 = S J (NB x NLC) into sIB, then A_coarse = J^T T1
@@ -528,10 +596,12 @@ void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double*
 void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st) {
   if (fine.d == 2)
     hipLaunchKernelGGL((macro_schur_kernel<2, 64>), dim3((unsigned)fine.nmacro), dim3(64), 0, st, fine.n,
-                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32);
+                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32,
+                       fine.sym ? nullptr : fine.R64, fine.sym ? nullptr : fine.R32);
   else
     hipLaunchKernelGGL((macro_schur_kernel<3, 256>), dim3((unsigned)fine.nmacro), dim3(256), 0, st, fine.n,
-                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32);
+                       fine.Aelem, coarse.Aelem, fine.AIIinv64, fine.AIIinv32, fine.P64, fine.P32,
+                       fine.sym ? nullptr : fine.R64, fine.sym ? nullptr : fine.R32);
   HDG_CHECK(hipGetLastError());
 }
 

@@ -151,7 +151,8 @@ __device__ inline void wg_mfma(FA a, FB b, FC c) {
 // symmetric, so their rows are read as columns (consecutive lanes then read
 // consecutive LDS words).
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau, const double* __restrict__ Phi,
+__global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau0, int tau_kappa,
+                                                         const double* __restrict__ Phi,
                                                          const double* __restrict__ Wq,
                                                          const double* __restrict__ Bm,
                                                          const double* __restrict__ Fm,
@@ -175,6 +176,7 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
   const long T = blockIdx.x;
   if (T >= nelem) return;
   const int tid = threadIdx.x;
+  const double tau = tau_kappa ? tau0 * kqp[T * NQ] : tau0;  // tau_T = tau kappa_T (per-element kappa)
   double* sM = sA;
   double* sY = sA + NV * NV;
   double* Ae = Aelem + T * (long)NL * NL;
@@ -345,6 +347,59 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau,
   }
 }
 
+// Element maps of the hybridized IPDG family (eq. IPG_H), one workgroup per
+// element.  With kappa the element's value (face terms included) and
+// s_f = 1, 0, -1 for SIPG-H, IIPG-H, NIPG-H, rows for the test function:
+//   L = kappa (K - s_f N - N^T) + tau E,   R = tau G - s_f kappa D,
+//   C = tau G^T - kappa D^T                (the conservation rows),
+//   A^e = tau H - C L^-1 R,  load map W = L^-T C^T (b^e = W^T b),
+//   recovery X = L^-1 R (u = X Lambda + L^-1 b).
+// At tau = (p+1)(p+2)/h_min the symmetric part of L is positive definite
+// for every s_f, so every leading minor of L is nonzero and Gauss-Jordan
+// without pivoting applies.  The products run on the matrix cores; the
+// operands R and C^T are formed as they are read.
+template <int D, int K, int NT>
+__global__ void __launch_bounds__(NT) ipdg_dtn_kernel(long nelem, double tau0, int tau_kappa, double sf, int nq,
+                                                      const double* __restrict__ kqp,
+                                                      const double* __restrict__ Kst,
+                                                      const double* __restrict__ Nn,
+                                                      const double* __restrict__ Dn,
+                                                      const double* __restrict__ Gm,
+                                                      const double* __restrict__ Em,
+                                                      const double* __restrict__ Hm, double* __restrict__ Aelem,
+                                                      double* __restrict__ Wout, double* __restrict__ Xout,
+                                                      double* __restrict__ Linv_out) {
+  using Dm = Dims<D, K>;
+  constexpr int NV = Dm::NV, NL = Dm::NL;
+  __shared__ double sL[NV * NV];  // L -> L^-1
+  __shared__ double sX[NV * NL];  // X = L^-1 R
+  const long T = blockIdx.x;
+  if (T >= nelem) return;
+  const int tid = threadIdx.x;
+  const double kap = kqp[T * nq];
+  const double tau = tau_kappa ? tau0 * kap : tau0;
+  double* Ae = Aelem + T * (long)NL * NL;
+  for (int idx = tid; idx < NV * NV; idx += NT) {
+    const int i = idx / NV, j = idx % NV;
+    sL[idx] = kap * (Kst[idx] - sf * Nn[idx] - Nn[j * NV + i]) + tau * Em[idx];
+  }
+  gj_inverse_reg<NV, NT>(sL);
+  if (Linv_out)
+    for (int idx = tid; idx < NV * NV; idx += NT) Linv_out[T * NV * NV + idx] = sL[idx];
+  wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sL[i * NV + l]; },
+                          [&](int l, int j) { return tau * Gm[l * NL + j] - sf * kap * Dn[l * NL + j]; },
+                          [&](int i, int j, double v) { sX[i * NL + j] = v; });
+  __syncthreads();
+  if (Xout)
+    for (int idx = tid; idx < NV * NL; idx += NT) Xout[T * NV * NL + idx] = sX[idx];
+  wg_mfma<NL, NL, NV, NT>([&](int i, int l) { return tau * Gm[l * NL + i] - kap * Dn[l * NL + i]; },
+                          [&](int l, int j) { return sX[l * NL + j]; },
+                          [&](int i, int j, double v) { Ae[i * NL + j] = tau * Hm[i * NL + j] - v; });
+  wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sL[l * NV + i]; },
+                          [&](int l, int j) { return tau * Gm[l * NL + j] - kap * Dn[l * NL + j]; },
+                          [&](int i, int j, double v) { Wout[(T * NV + i) * NL + j] = v; });
+}
+
 // b = M f (or f itself when it is already a load), per (element, node)
 template <int NV>
 __global__ void load_vec_kernel(long nelem, const double* __restrict__ M, const double* __restrict__ f,
@@ -475,7 +530,8 @@ __global__ void load_pull_kernel(int n, const double* __restrict__ ebuf, const d
 // eps kappa / (tau h) (the route cancels terms of size kappa); after the step
 // it is backward stable.
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, const double* __restrict__ Phi,
+__global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau0, int tau_kappa,
+                                                         const double* __restrict__ Phi,
                                                          const double* __restrict__ Wq,
                                                          const double* __restrict__ kqp,
                                                          const double* __restrict__ Bm,
@@ -494,6 +550,7 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, cons
   __shared__ double sL[NL], sU[NV], sT[D * NV], sQ[D * NV], sY[D * NV], sR[NV], sP[NQ];
   const long T = blockIdx.x;
   const int tid = threadIdx.x;
+  const double tau = tau_kappa ? tau0 * kqp[T * NQ] : tau0;
   const double* Mi = Minv + T * (long)NV * NV;
   const double* Ki = Kinv + T * (long)NV * NV;
   int e[3] = {0, 0, 0};
@@ -608,6 +665,59 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau, cons
   for (int i = tid; i < D * NV; i += NT) q[T * D * NV + i] = sQ[i];
 }
 
+// Local recovery of the IPDG family, one workgroup per element:
+// u = X Lambda + L^-1 b, then q_c = -kappa d_c u at the nodes (each
+// component of grad u lies in Q^k, so its nodal values represent it).
+template <int D, int K, int NT>
+__global__ void __launch_bounds__(NT) ipdg_reconstruct_kernel(int n, int nq, const double* __restrict__ kqp,
+                                                              const double* __restrict__ Dnode,
+                                                              const double* __restrict__ lam,
+                                                              const double* __restrict__ gdir,
+                                                              const double* __restrict__ b,
+                                                              const double* __restrict__ X,
+                                                              const double* __restrict__ Linv,
+                                                              double* __restrict__ u, double* __restrict__ q) {
+  using Dm = Dims<D, K>;
+  constexpr int NV = Dm::NV, NE = Dm::NE, NL = Dm::NL;
+  __shared__ double sL[NL], sU[NV];
+  const long T = blockIdx.x;
+  const int tid = threadIdx.x;
+  int e[3] = {0, 0, 0};
+  elem_coords<D>(T, n, e);
+  for (int idx = tid; idx < NL; idx += NT) {
+    int sl = idx / NE, a = idx % NE;
+    int c = sl / 2, sd = sl % 2;
+    int gco[3] = {e[0], e[1], e[2]};
+    int p = e[c] + sd;
+    gco[c] = p;
+    double v = 0.0;
+    if (p == 0 || p == n) {
+      if (gdir) v = gdir[bface_id<D>(c, p == n ? 1 : 0, gco, n) * NE + a];
+    } else {
+      v = lam[iface_id<D>(c, gco, n) * NE + a];
+    }
+    sL[idx] = v;
+  }
+  __syncthreads();
+  const double* Xe = X + T * (long)NV * NL;
+  const double* Li = Linv + T * (long)NV * NV;
+  for (int i = tid; i < NV; i += NT) {
+    double s = 0.0;
+    for (int j = 0; j < NL; ++j) s += Xe[i * NL + j] * sL[j];
+    for (int j = 0; j < NV; ++j) s += Li[i * NV + j] * b[T * NV + j];
+    sU[i] = s;
+  }
+  __syncthreads();
+  const double kap = kqp[T * nq];
+  for (int idx = tid; idx < D * NV; idx += NT) {
+    const int c = idx / NV, a = idx % NV;
+    double s = 0.0;
+    for (int j = 0; j < NV; ++j) s += Dnode[(c * NV + a) * NV + j] * sU[j];
+    q[T * D * NV + idx] = -kap * s;
+  }
+  for (int i = tid; i < NV; i += NT) u[T * NV + i] = sU[i];
+}
+
 // dJ/dlog kappa_T = -sum_c (q*_c)^T Mk q_c, evaluated at the Gauss points.
 template <int D, int K, int NT>
 __global__ void __launch_bounds__(NT) grad_kernel(long nelem, const double* __restrict__ Phi,
@@ -673,13 +783,44 @@ void dispatch_dk(int d, int k, F&& f) {
 
 }  // namespace
 
-void launch_element_dtn(int d, int k, long nelem, double tau, const RefDevice& rd, const double* kqp,
+void launch_element_dtn(int d, int k, long nelem, double tau, int tau_kappa, const RefDevice& rd, const double* kqp,
                         double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
     constexpr int NT = D == 2 ? HDG_ELEM_NT2 : 256;
     hipLaunchKernelGGL((element_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau,
-                       rd.Phi, rd.Wq, rd.B, rd.F, rd.G, rd.E, rd.H, kqp, Aelem, W, Kinv, Minv);
+                       tau_kappa, rd.Phi, rd.Wq, rd.B, rd.F, rd.G, rd.E, rd.H, kqp, Aelem, W, Kinv, Minv);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_ipdg_dtn(int d, int k, long nelem, double tau, int tau_kappa, double sf, const RefDevice& rd,
+                     const double* kqp,
+                     int nq, double* Aelem, double* W, double* X, double* Linv, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    constexpr int NT = 256;
+    hipLaunchKernelGGL((ipdg_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau, tau_kappa,
+                       sf, nq, kqp,
+                       rd.Kst, rd.Nn, rd.Dn, rd.G, rd.E, rd.H, Aelem, W, X, Linv);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const double* lam,
+                             const double* gdir, const double* f, int is_load, const double* X, const double* Linv,
+                             double* b, double* u, double* q, hipStream_t st) {
+  dispatch_dk(d, k, [&](auto D_, auto K_) {
+    constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
+    using Dm = Dims<D, K>;
+    long nelem = 1;
+    for (int a = 0; a < D; ++a) nelem *= n;
+    long n1 = nelem * Dm::NV;
+    hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
+                       rd.M, f, is_load, b);
+    constexpr int NT = 64;
+    hipLaunchKernelGGL((ipdg_reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, nq, kqp,
+                       rd.Dnode, lam, gdir, b, X, Linv, u, q);
   });
   HDG_CHECK(hipGetLastError());
 }
@@ -715,7 +856,7 @@ void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Ael
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* kqp, const double* lam,
+void launch_reconstruct(int d, int k, int n, double tau, int tau_kappa, const RefDevice& rd, const double* kqp, const double* lam,
                         const double* gdir, const double* f, int is_load, const double* W, const double* Kinv,
                         const double* Minv, double* b, double* u, double* q, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
@@ -727,7 +868,8 @@ void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, co
     hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
                        rd.M, f, is_load, b);
     constexpr int NT = 64;
-    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, tau, rd.Phi,
+    hipLaunchKernelGGL((reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, tau, tau_kappa,
+                       rd.Phi,
                        rd.Wq, kqp, rd.B, rd.F, rd.G, rd.E, lam, gdir, b, W, Kinv, Minv, u, q);
   });
   HDG_CHECK(hipGetLastError());

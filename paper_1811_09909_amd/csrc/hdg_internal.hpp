@@ -96,6 +96,11 @@ struct RefElement {
   std::vector<double> H;               // [nl][nl]:   face mass
   std::vector<double> M;               // [nv][nv]:   volume mass
   std::vector<double> Jp;              // [ne][nc]:   P1/Q1 face vertex values -> GLL values
+  // primal (IPDG) forms
+  std::vector<double> Kst;             // [nv][nv]:   (grad phi_j, grad phi_i)
+  std::vector<double> Nn;              // [nv][nv]:   <phi_j, grad phi_i . n> on the element boundary
+  std::vector<double> Dn;              // [nv][nl]:   <mu_m, grad phi_i . n>
+  std::vector<double> Dnode;           // [d][nv][nv]: d_c phi_j at node a
   void build(int d, int k, double h);
 };
 
@@ -106,6 +111,7 @@ void gauss_points(int n, std::vector<double>& x, std::vector<double>& w);  // on
 struct RefDevice {
   double *Phi = nullptr, *Wq = nullptr, *B = nullptr, *F = nullptr, *G = nullptr, *E = nullptr,
          *H = nullptr, *M = nullptr, *Jp = nullptr;
+  double *Kst = nullptr, *Nn = nullptr, *Dn = nullptr, *Dnode = nullptr;  // IPDG handles only
 };
 
 // ---------------------------------------------------------------------------
@@ -151,6 +157,11 @@ struct Level {
   int nI = 0, ncl = 0;
   double* AIIinv64 = nullptr; float* AIIinv32 = nullptr;  // AoSoA over M, row-major nI x nI
   double* P64 = nullptr;      float* P32 = nullptr;       // AoSoA over M, row-major nI x ncl
+  // restriction block R = -A_II^-T A_BI^T J (eq. n_1_Qk: the macro-element
+  // share of Q is R^T rho_I); the same array as P when the level operator is
+  // symmetric (then R = P), its own array otherwise
+  double* R64 = nullptr;      float* R32 = nullptr;
+  bool sym = true;  // the level operator is symmetric
   // coarsest direct inverse (dense row-major nlam x nlam)
   double* Ainv64 = nullptr; float* Ainv32 = nullptr;
   // work vectors, [0] = FP64, [1] = FP32
@@ -162,16 +173,24 @@ struct Level {
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).  All run on `st`.
-// element.hip
-void launch_element_dtn(int d, int k, long nelem, double tau, const RefDevice& rd, const double* kqp,
+// element.hip (tau_kappa != 0: element T is stabilized with tau * kappa_T,
+// kappa per element)
+void launch_element_dtn(int d, int k, long nelem, double tau, int tau_kappa, const RefDevice& rd, const double* kqp,
                         double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st);
 void launch_element_load(int d, int k, long nelem, const RefDevice& rd, const double* f, int is_load,
                          const double* W, double* ebuf, hipStream_t st);
 void launch_load_pull(int d, int k, int n, const double* ebuf, const double* Aelem, const double* gdir,
                       double* g, hipStream_t st);
-void launch_reconstruct(int d, int k, int n, double tau, const RefDevice& rd, const double* kqp, const double* lam,
+void launch_reconstruct(int d, int k, int n, double tau, int tau_kappa, const RefDevice& rd, const double* kqp, const double* lam,
                         const double* gdir, const double* f, int is_load, const double* W, const double* Kinv,
                         const double* Minv, double* b, double* u, double* q, hipStream_t st);
+// hybridized IPDG family (eq. IPG_H): A^e, the load map W = L^-T C^T and,
+// when X / Linv are given, the recovery blocks X = L^-1 R and L^-1
+void launch_ipdg_dtn(int d, int k, long nelem, double tau, int tau_kappa, double sf, const RefDevice& rd,
+                     const double* kqp, int nq, double* Aelem, double* W, double* X, double* Linv, hipStream_t st);
+void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const double* lam,
+                             const double* gdir, const double* f, int is_load, const double* X, const double* Linv,
+                             double* b, double* u, double* q, hipStream_t st);
 void launch_grad(int d, int k, long nelem, const RefDevice& rd, const double* kqp, const double* q,
                  const double* qs, double* grad, hipStream_t st);
 void launch_mass(int d, int k, long nelem, const RefDevice& rd, const double* u, double* out, hipStream_t st);

@@ -1,7 +1,8 @@
 // Reference element of the HDG discretization (host side, built once per
 // problem): GLL-nodal Q^k bases on a cell of size h, Gauss rules with k+2
 // points per direction, and the element integrals that enter the local
-// problem of eqs. HDG and HDG_flux.
+// problems of eqs. HDG and HDG_flux and of the hybridized IPDG family
+// (eq. IPG_H).
 #include <cmath>
 #include <stdexcept>
 
@@ -167,6 +168,29 @@ void RefElement::build(int d_, int k_, double h_) {
       }
     }
 
+  // stiffness K[i][j] = (grad phi_j, grad phi_i) of the primal IPDG forms
+  Kst.assign((size_t)nv * nv, 0.0);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) {
+      double s = 0.0;
+      for (int c = 0; c < d; ++c)
+        for (int Q = 0; Q < nq; ++Q)
+          s += Wq[Q] * dPhi[((size_t)c * nq + Q) * nv + i] * dPhi[((size_t)c * nq + Q) * nv + j];
+      Kst[(size_t)i * nv + j] = s;
+    }
+  // derivatives of the basis at its own nodes: Dnode[c][a][j] = d_c phi_j(x_a)
+  Dnode.assign((size_t)d * nv * nv, 0.0);
+  for (int c = 0; c < d; ++c)
+    for (int a = 0; a < nv; ++a)
+      for (int j = 0; j < nv; ++j) {
+        double v = 1.0;
+        for (int b = 0; b < d; ++b) {
+          const int ja = digit(j, p1, b), aa = digit(a, p1, b);
+          v *= (b == c) ? (double)(lagrange_deriv(gll, ja, gll[aa]) / h) : (ja == aa ? 1.0 : 0.0);
+        }
+        Dnode[((size_t)c * nv + a) * nv + j] = v;
+      }
+
   // face quadrature: tangential Gauss points of each face slot
   int nfq = 1;
   for (int i = 0; i < d - 1; ++i) nfq *= q1;
@@ -175,7 +199,9 @@ void RefElement::build(int d_, int k_, double h_) {
   G.assign((size_t)nv * nl, 0.0);
   E.assign((size_t)nv * nv, 0.0);
   H.assign((size_t)nl * nl, 0.0);
-  std::vector<double> pf((size_t)nfq * nv), mu((size_t)nfq * ne), wf(nfq);
+  Nn.assign((size_t)nv * nv, 0.0);
+  Dn.assign((size_t)nv * nl, 0.0);
+  std::vector<double> pf((size_t)nfq * nv), mu((size_t)nfq * ne), wf(nfq), dpf((size_t)nfq * nv);
   for (int s = 0; s < nf; ++s) {
     int c = s / 2, side = s % 2;
     double nrm = side ? 1.0 : -1.0;
@@ -195,6 +221,10 @@ void RefElement::build(int d_, int k_, double h_) {
         double v = end[digit(I, p1, c) * 2 + side];
         for (int j = 0; j < d - 1; ++j) v *= l[digit(I, p1, tang[j]) * q1 + digit(P, q1, j)];
         pf[(size_t)P * nv + I] = v;
+        // outward normal derivative n_c d_c phi_I at the face point
+        double g = nrm * (double)(lagrange_deriv(gll, digit(I, p1, c), (long double)side) / h);
+        for (int j = 0; j < d - 1; ++j) g *= l[digit(I, p1, tang[j]) * q1 + digit(P, q1, j)];
+        dpf[(size_t)P * nv + I] = g;
       }
     }
     for (int i = 0; i < nv; ++i) {
@@ -205,9 +235,18 @@ void RefElement::build(int d_, int k_, double h_) {
         F[((size_t)c * nv + i) * nl + s * ne + m] = nrm * g;
       }
       for (int j = 0; j < nv; ++j) {
-        double e = 0.0;
-        for (int P = 0; P < nfq; ++P) e += wf[P] * pf[(size_t)P * nv + i] * pf[(size_t)P * nv + j];
+        double e = 0.0, nn = 0.0;
+        for (int P = 0; P < nfq; ++P) {
+          e += wf[P] * pf[(size_t)P * nv + i] * pf[(size_t)P * nv + j];
+          nn += wf[P] * dpf[(size_t)P * nv + i] * pf[(size_t)P * nv + j];
+        }
         E[(size_t)i * nv + j] += e;
+        Nn[(size_t)i * nv + j] += nn;
+      }
+      for (int m = 0; m < ne; ++m) {
+        double v = 0.0;
+        for (int P = 0; P < nfq; ++P) v += wf[P] * dpf[(size_t)P * nv + i] * mu[(size_t)P * ne + m];
+        Dn[(size_t)i * nl + s * ne + m] = v;
       }
     }
     for (int m = 0; m < ne; ++m)

@@ -416,7 +416,8 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
 
 // Local correction and the macro-element part of the restriction:
 //   e_I += A_II^-1 rho_I            (eq. localCorrection, when do_corr)
-//   cb_M = P_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict)
+//   cb_M = R_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict;
+//   the launcher passes the restriction block R, which is P on symmetric levels)
 template <int D, typename T, typename M = T>
 __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__ AIIinv, const M* __restrict__ P,
                                                     const T* __restrict__ rho, T* __restrict__ e, int do_corr,
@@ -1036,7 +1037,7 @@ void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* 
 template <typename T, typename M>
 void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st, int nrhs) {
   const M* Ai = sizeof(M) == 8 ? (const M*)L.AIIinv64 : (const M*)L.AIIinv32;
-  const M* P = sizeof(M) == 8 ? (const M*)L.P64 : (const M*)L.P32;
+  const M* P = sizeof(M) == 8 ? (const M*)L.R64 : (const M*)L.R32;  // restriction block
   if (L.d == 2)
     hipLaunchKernelGGL((hcorr_kernel<2, T, M>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
                        do_corr, do_restrict, cb);
@@ -1088,7 +1089,7 @@ template <typename T>
 void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st, int nrhs) {
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;
   const T* Ai = sizeof(T) == 8 ? (const T*)L.AIIinv64 : (const T*)L.AIIinv32;
-  const T* P = sizeof(T) == 8 ? (const T*)L.P64 : (const T*)L.P32;
+  const T* P = sizeof(T) == 8 ? (const T*)L.R64 : (const T*)L.R32;  // restriction block
   const int lpm = L.lpm > 0 ? L.lpm : lanes_per_macro(L.nmacro, nrhs);
   if (lpm == 4)
     hipLaunchKernelGGL((hpreL_kernel<T, 4>), dim3(xcd_rhs_grid(nblk(4 * L.nmacro), nrhs)), dim3(256), 0, st, L.n, nrhs,

@@ -21,24 +21,34 @@ def _dev(t, dtype, device):
 
 
 class Problem:
-    """One HDG trace problem on the unit box (d = 2 or 3, n^d elements, Q^k).
+    """One trace problem on the unit box (d = 2 or 3, n^d elements, Q^k).
 
-    ``kappa``: per element [n^d] or at the (k+2)^d Gauss points of every
-    element [n^d, (k+2)^d] (then ``kappa_kind='qp'``)."""
+    ``scheme``: "hdg" (eqs. HDG, HDG_flux) or one of the hybridized IPDG
+    family "sipg", "iipg", "nipg" (eq. IPG_H, s_f = 1, 0, -1).
+    ``tau_kappa``: element T is stabilized with tau * kappa_T (kappa per
+    element).
+    ``kappa``: per element [n^d] or, for HDG, at the (k+2)^d Gauss points of
+    every element [n^d, (k+2)^d] (then ``kappa_kind='qp'``)."""
 
-    def __init__(self, d, n, k, kappa, tau=1.0, kappa_kind="element", store_recovery=True, device="cuda"):
+    def __init__(self, d, n, k, kappa, tau=1.0, kappa_kind="element", store_recovery=True, device="cuda",
+                 scheme="hdg", tau_kappa=False):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HDG library needs a GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
         self.d, self.n, self.k, self.tau = d, n, k, float(tau)
         self.kind = L.KAPPA_AT_QP if kappa_kind == "qp" else L.KAPPA_PER_ELEMENT
+        if scheme not in L.SCHEMES:
+            raise ValueError(f"unknown scheme {scheme}")
+        self.scheme = scheme
         kap = _dev(kappa, torch.float64, self.device)
         self.stream = torch.cuda.current_stream(self.device)
         mesh = L.Mesh(d, n)
         h = ctypes.c_void_p()
-        L.check(self.lib.hdg_setup(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, 1 if store_recovery else 0,
-                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "hdg_setup")
+        code = L.SCHEMES[scheme] | (L.SCHEME_TAU_KAPPA if tau_kappa else 0)
+        L.check(self.lib.hdg_setup_scheme(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, code,
+                                          1 if store_recovery else 0, ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(h)), "hdg_setup_scheme")
         self.h = h
         self.nT = self.query(L.Q_NT)
         self.nlam = self.query(L.Q_NLAMBDA)

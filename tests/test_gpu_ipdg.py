@@ -1,0 +1,327 @@
+"""Parity of the hybridized IPDG family on the GPU (through the C ABI) with
+the FP64 CPU oracle (eqs. IPDG_flux, SIPG_H, IPG_H; Sec. 3 on the
+nonsymmetric trace system; Sec. 4.1, Tables NIPG_*).
+
+Element maps, loads with Dirichlet data, every level operator of the
+hierarchy (IIPG-H and NIPG-H restrict with Q = [-J^T A_BI A_II^-1, J^T],
+not I^T), the V-cycle on each orchestration path, MG and GMRES solves
+(iteration counts against the oracle's, solutions against its direct
+solve), local recovery of u and q = -kappa grad u, and the error paths.
+FP64 bounds: 4 eps cond(L_T) times the growth of the condensation
+(max |C| |L^-1| |R| / max |A^e|) per element, at least 1e-12; coarse levels
+as for HDG (a factor 10 per h-coarsening, at most 1e-9).
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mg as omg
+from oracle.ipdg import IPDG
+
+from ._helpers import assemble, load_scale, relerr, rowerr
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["sipg", "iipg", "nipg"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _tau(d, n, k):
+    return (k + 1) * (k + 2) * n / np.sqrt(d)
+
+
+def _oracle(d, n, k, scheme, lo=1e-1, hi=1e1, seed=0, tau_kappa=True):
+    """Random kappa per element (log-uniform on [lo, hi]); by default the
+    stabilization is tau_T = (p+1)(p+2)/h_min * kappa_T (Examples III, IV),
+    which keeps SIPG-H definite at any contrast."""
+    rng = np.random.default_rng(seed)
+    kap = 10.0 ** rng.uniform(np.log10(lo), np.log10(hi), n ** d)
+    return IPDG(d, n, k, _tau(d, n, k), kap, scheme, tau_kappa=tau_kappa), kap, rng
+
+
+def _gpu(torch, O, kap, **bk):
+    from paper_1811_09909_amd.hdg import Problem
+    P = Problem(O.d, O.n, O.k, torch.as_tensor(kap), tau=O.tau, scheme=getattr(O, "scheme", "hdg"),
+                tau_kappa=O.tau_kappa)
+    if bk:
+        P.build(**bk)
+    return P
+
+
+def ipdg_bound(O, floor=1e-12):
+    """4 eps cond(L_T) times the condensation's growth, largest over T."""
+    eps = np.finfo(float).eps
+    b = floor
+    for T in range(O.mesh.nel):
+        L, R, C = O.blocks(T)
+        Li = np.linalg.inv(L)
+        Ae = O.element_dtn(T)
+        grow = (np.abs(C) @ np.abs(Li) @ np.abs(R)).max() / np.abs(Ae).max()
+        b = max(b, 4 * eps * np.linalg.cond(L) * grow)
+    return b
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,n,k,tk", [(2, 4, 1, True), (2, 3, 2, False), (2, 3, 4, True), (2, 2, 6, True),
+                                      (3, 2, 1, False), (3, 2, 3, True)])
+def test_ipdg_element_maps(torch_cuda, scheme, d, n, k, tk):
+    say(f"[ipdg element maps] {scheme} d={d} n={n} k={k} tau_kappa={tk}")
+    O, kap, _ = _oracle(d, n, k, scheme, lo=1e-3, hi=1e3, tau_kappa=tk)
+    P = _gpu(torch_cuda, O, kap)
+    Ae = P.level_export(0).cpu().numpy()
+    Ao = O.all_element_dtn()
+    b = ipdg_bound(O)
+    ent = max(np.abs(Ae[T] - Ao[T]).max() / np.abs(Ao[T]).max() for T in range(n ** d))
+    sym = max(np.abs(Ae[T] - Ae[T].T).max() / np.abs(Ae[T]).max() for T in range(n ** d))
+    say(f"  entrywise / max entry {ent:.2e} (bound {b:.1e}); asymmetry {sym:.1e}")
+    assert ent <= b
+    if scheme == "sipg":
+        assert sym <= b
+    else:
+        assert sym > 1e-3
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,n,k", [(2, 9, 2), (3, 3, 2)])
+def test_ipdg_rhs_and_recovery(torch_cuda, scheme, d, n, k):
+    say(f"[ipdg rhs + recovery] {scheme} d={d} n={n} k={k}")
+    O, kap, rng = _oracle(d, n, k, scheme)
+    f = rng.standard_normal((n ** d, O.nv))
+
+    def gD(X):
+        return np.cos(3 * X.sum(1)) + X[:, 0] ** 2
+    A, g, lb = O.assemble(f, gD)
+    P = _gpu(torch_cuda, O, kap)
+    b = ipdg_bound(O)
+    gg = P.rhs(torch_cuda.as_tensor(f), gdir=torch_cuda.as_tensor(lb)).cpu().numpy()
+    sc = load_scale(O, f, lb)
+    say(f"  g relerr {relerr(gg, g):.2e} entrywise {rowerr(gg, g, sc):.2e} (bound {b:.1e})")
+    assert relerr(gg, g) <= b and rowerr(gg, g, sc) <= b
+    lam = spla.spsolve(A.tocsc(), g)
+    u, q = P.reconstruct(torch_cuda.as_tensor(lam), torch_cuda.as_tensor(f), gdir=torch_cuda.as_tensor(lb))
+    uo, qo = O.reconstruct(lam, f, lb)
+    eu, eq = relerr(u.cpu().numpy(), uo), relerr(q.cpu().numpy(), qo)
+    say(f"  recovery u {eu:.2e} q {eq:.2e}")
+    assert eu <= b and eq <= 10 * b
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("d,n,k", [(2, 16, 1), (2, 16, 3), (3, 4, 2)])
+def test_ipdg_hierarchy_and_vcycle(torch_cuda, scheme, d, n, k):
+    say(f"[ipdg hierarchy] {scheme} d={d} n={n} k={k}")
+    O, kap, rng = _oracle(d, n, k, scheme)
+    A, _, _ = O.assemble()
+    H = omg.Hierarchy(A, d, n, k, local_corr=omg.LC_BOTH)
+    P = _gpu(torch_cuda, O, kap, local_corr=omg.LC_BOTH)
+    assert P.level_sizes() == [L.A.shape[0] for L in H.levels]
+    b0 = ipdg_bound(O)
+    nh = [0] * P.n_levels
+    for lvl in range(1, P.n_levels):
+        nh[lvl] = nh[lvl - 1] + (0 if (k > 1 and lvl == 1) else 1)
+
+    def bound(lvl):
+        return b0 if nh[lvl] == 0 else min(1e-9, max(b0, 1e-12 * 10.0 ** (nh[lvl] + 1)))
+    for lvl in range(1, P.n_levels):
+        Lo = H.levels[lvl]
+        Ag = assemble(P.level_export(lvl).cpu().numpy(), d, Lo.mesh.n, Lo.m)
+        err = abs(Ag - Lo.A).max() / abs(Lo.A).max()
+        say(f"  level {lvl}: N={Lo.A.shape[0]} coarse-operator err {err:.2e} (bound {bound(lvl):.0e})")
+        assert err <= bound(lvl)
+    r = rng.standard_normal(A.shape[0])
+    eo = H.vcycle(r)
+    e = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+    b64 = min(1e-10, bound(P.n_levels - 1))
+    say(f"  vcycle fp64 {relerr(e, eo):.2e} (bound {b64:.0e})")
+    assert relerr(e, eo) <= b64
+    e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=1).cpu().numpy()
+    say(f"  vcycle fp32 {relerr(e32, eo):.2e}")
+    assert relerr(e32, eo) <= 1e-3
+
+
+@pytest.mark.parametrize("path", ["fused", "unfused", "lanes1", "lanes4"])
+@pytest.mark.parametrize("scheme", ["nipg", "iipg"])
+def test_ipdg_vcycle_paths(torch_cuda, path, scheme):
+    """Each orchestration of the nonsymmetric cycle (fused transition
+    kernels with the restriction block, unfused kernels, one or four lanes
+    per macro-element) against the oracle's Algorithm 1."""
+    from paper_1811_09909_amd import _lib as L
+    var = {"fused": 0, "unfused": L.VARIANT_NO_FUSE, "lanes1": L.VARIANT_LANES1, "lanes4": L.VARIANT_LANES4}[path]
+    n, k = 32, 2
+    say(f"[ipdg vcycle path={path}] {scheme} n={n} k={k}")
+    O, kap, rng = _oracle(2, n, k, scheme)
+    A, _, _ = O.assemble()
+    for lc, sweeps, growth in [(omg.LC_PRE, 2, 1), (omg.LC_BOTH, 1, 2)]:
+        H = omg.Hierarchy(A, 2, n, k, sweeps=sweeps, growth=growth, local_corr=lc)
+        P = _gpu(torch_cuda, O, kap, sweeps=sweeps, growth=growth, local_corr=lc, variant=var, nrhs=2)
+        R = rng.standard_normal((2, A.shape[0]))
+        E = P.vcycle(torch_cuda.as_tensor(R.ravel())).cpu().numpy().reshape(2, -1)
+        for j in range(2):
+            eo = H.vcycle(R[j])
+            say(f"  lc={lc} sweeps={sweeps} growth={growth} rhs {j}: {relerr(E[j], eo):.2e}")
+            assert relerr(E[j], eo) <= 1e-10
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("method", ["mg", "gmres"])
+def test_ipdg_solves_match_oracle(torch_cuda, scheme, method):
+    from paper_1811_09909_amd import _lib as L
+    d, n, k = 2, 32, 2
+    say(f"[ipdg solve] {scheme} {method} n={n} k={k}")
+    O, kap, rng = _oracle(2, n, k, scheme)
+    f = rng.standard_normal((n ** d, O.nv))
+    A, g, _ = O.assemble(f)
+    H = omg.Hierarchy(A, d, n, k)
+    tol = 1e-10
+    ro = (omg.mg_solve(H, A, g, tol=tol) if method == "mg" else omg.gmres_solve(H, A, g, tol=tol, side="right"))
+    m = L.METHOD_MG if method == "mg" else L.METHOD_GMRES
+    P = _gpu(torch_cuda, O, kap, method=m, max_it=200)
+    lam, info = P.solve(torch_cuda.as_tensor(f), tol=tol)
+    lam = lam.cpu().numpy()
+    res = np.linalg.norm(g - A @ lam) / np.linalg.norm(g)
+    lam_d = spla.spsolve(A.tocsc(), g)
+    # both stop at tol: their difference is A^-1 applied to the difference
+    # of the residuals, bounded through the oracle's direct solve
+    bnd = (np.linalg.norm(spla.spsolve(A.tocsc(), g - A @ lam)) + np.linalg.norm(lam_d - ro.lam)) * 1.01 + 1e-12
+    say(f"  GPU {info['iters']} its relres {res:.2e}; oracle {ro.iters} its; "
+        f"|lam - lam_oracle| {np.linalg.norm(lam - ro.lam):.2e} (bound {bnd:.2e})")
+    assert res <= tol * 1.01
+    assert abs(info["iters"] - ro.iters) <= 1
+    assert np.linalg.norm(lam - ro.lam) <= bnd
+
+
+def _ex1_source(X):
+    x, y = X[:, 0], X[:, 1]
+    e = np.exp(x ** 2 * y ** 3)
+    uxx = y * e * (6 * x * y ** 3 + 4 * x ** 3 * y ** 6)
+    uyy = x * e * (12 * x ** 2 * y ** 2 + 9 * x ** 4 * y ** 5)
+    return -(uxx + uyy)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_ipdg_example1_counts(torch_cuda, k):
+    """Example I with NIPG-H (Sec. 4.1): the GPU's MG and GMRES counts at
+    tolerance 1e-9 against the oracle's on the same schedule (3 sweeps
+    doubling toward the coarse levels), and the paper's Table NIPG_bj
+    within 2 for MG."""
+    from paper_1811_09909_amd import _lib as L
+    table = {1: [5, 7, 8], 2: [6, 6, 6], 3: [7, 8, 8]}[k]
+    for j, lev in enumerate([2, 3, 4]):
+        n = 2 ** lev
+        O = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), "nipg")
+
+        def u(X):
+            return X[:, 0] * X[:, 1] * np.exp(X[:, 0] ** 2 * X[:, 1] ** 3)
+        fn = _ex1_source(O.volume_nodes().reshape(-1, 2)).reshape(O.mesh.nel, -1)
+        A, g, lb = O.assemble(fn, u)
+        H = omg.Hierarchy(A, 2, n, k, sweeps=3, growth=2)
+        ro = omg.mg_solve(H, A, g, tol=1e-9)
+        rg = omg.gmres_solve(H, A, g, tol=1e-9, side="right")
+        P = _gpu(torch_cuda, O, np.ones(n * n), sweeps=3, growth=2, method=L.METHOD_MG)
+        _, im = P.solve(torch_cuda.as_tensor(fn), tol=1e-9, gdir=torch_cuda.as_tensor(lb))
+        P.build(sweeps=3, growth=2, method=L.METHOD_GMRES)
+        _, ig = P.solve(torch_cuda.as_tensor(fn), tol=1e-9, gdir=torch_cuda.as_tensor(lb))
+        say(f"[ipdg Ex I] k={k} L={lev}: MG GPU {im['iters']} oracle {ro.iters} paper {table[j]}; "
+            f"GMRES GPU {ig['iters']} oracle {rg.iters}")
+        assert im["iters"] == ro.iters and abs(ig["iters"] - rg.iters) <= 1
+        assert abs(im["iters"] - table[j]) <= 2
+
+
+def test_ipdg_sipg_cg_and_mixed(torch_cuda):
+    """SIPG-H keeps CG (symmetric operator); the mixed solve reaches the
+    FP64 tolerance on the nonsymmetric schemes with GMRES."""
+    from paper_1811_09909_amd import _lib as L
+    n, k = 32, 3
+    O, kap, rng = _oracle(2, n, k, "sipg")
+    f = rng.standard_normal((n * n, O.nv))
+    A, g, _ = O.assemble(f)
+    H = omg.Hierarchy(A, 2, n, k, local_corr=omg.LC_BOTH)
+    ro = omg.pcg_solve(H, A, g, tol=1e-10)
+    P = _gpu(torch_cuda, O, kap, local_corr=omg.LC_BOTH, method=L.METHOD_PCG)
+    lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+    res = np.linalg.norm(g - A @ lam.cpu().numpy()) / np.linalg.norm(g)
+    say(f"[sipg cg] GPU {info['iters']} its relres {res:.2e}; oracle {ro.iters}")
+    assert res <= 1.01e-10 and abs(info["iters"] - ro.iters) <= 1
+    for scheme in ("nipg", "iipg"):
+        O, kap, rng = _oracle(2, n, k, scheme)
+        f = rng.standard_normal((n * n, O.nv))
+        A, g, _ = O.assemble(f)
+        P64 = _gpu(torch_cuda, O, kap, method=L.METHOD_GMRES)
+        _, i64 = P64.solve(torch_cuda.as_tensor(f), tol=1e-10)
+        P = _gpu(torch_cuda, O, kap, method=L.METHOD_GMRES, precision=L.MIXED)
+        lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+        res = np.linalg.norm(g - A @ lam.cpu().numpy()) / np.linalg.norm(g)
+        say(f"[{scheme} mixed gmres] {info['iters']} its (fp64: {i64['iters']}) relres {res:.2e}")
+        assert res <= 1.01e-10 and info["iters"] <= i64["iters"] + 3
+
+
+def test_ipdg_error_paths(torch_cuda):
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import Problem
+    n, k = 8, 2
+    O, kap, rng = _oracle(2, n, k, "nipg")
+    P = _gpu(torch_cuda, O, kap)
+    with pytest.raises(RuntimeError, match="UNSUPPORTED|unsupported"):
+        P.build(method=L.METHOD_PCG)
+    P.build(method=L.METHOD_GMRES)
+    with pytest.raises(RuntimeError, match="UNSUPPORTED|unsupported"):
+        P.adjoint(torch_cuda.zeros(n * n, O.nv, dtype=torch_cuda.float64),
+                  torch_cuda.zeros(n * n, 2, O.nv, dtype=torch_cuda.float64))
+    with pytest.raises(RuntimeError, match="UNSUPPORTED|unsupported"):
+        Problem(2, n, k, torch_cuda.ones(n * n, (k + 2) ** 2, dtype=torch_cuda.float64), tau=1.0,
+                kappa_kind="qp", scheme="sipg")
+    with pytest.raises(RuntimeError, match="UNSUPPORTED|unsupported"):
+        Problem(2, n, k, torch_cuda.ones(n * n, (k + 2) ** 2, dtype=torch_cuda.float64), tau=1.0,
+                kappa_kind="qp", scheme="hdg", tau_kappa=True)
+    with pytest.raises(ValueError):
+        Problem(2, n, k, torch_cuda.as_tensor(kap), scheme="lipg")
+
+
+@pytest.mark.parametrize("d,n,k", [(2, 8, 3), (3, 4, 2)])
+def test_hdg_tau_kappa(torch_cuda, d, n, k):
+    """HDG with tau_T = tau kappa_T (Example IV's tau = kappa/h_min) at six
+    decades of kappa: element maps, load and recovery against the oracle,
+    and a CG solve to its tolerance."""
+    from oracle.hdg import HDG
+    from paper_1811_09909_amd import _lib as L
+    rng = np.random.default_rng(5)
+    kap = 10.0 ** rng.uniform(-3, 3, n ** d)
+    O = HDG(d, n, k, n / np.sqrt(d), kap, tau_kappa=True)
+    P = _gpu(torch_cuda, O, kap)
+    Ae = P.level_export(0).cpu().numpy()
+    Ao = O.all_element_dtn()
+    ent = max(np.abs(Ae[T] - Ao[T]).max() / np.abs(Ao[T]).max() for T in range(n ** d))
+    say(f"[hdg tau_kappa] d={d} n={n} k={k}: element maps {ent:.2e}")
+    assert ent <= 1e-12
+    f = rng.standard_normal((n ** d, O.nv))
+    A, g, _ = O.assemble(f)
+    gg = P.rhs(torch_cuda.as_tensor(f)).cpu().numpy()
+    sc = load_scale(O, f)
+    say(f"  g relerr {relerr(gg, g):.2e} entrywise {rowerr(gg, g, sc):.2e}")
+    assert relerr(gg, g) <= 1e-12 and rowerr(gg, g, sc) <= 1e-12
+    lam_d = spla.spsolve(A.tocsc(), g)
+    u, q = P.reconstruct(torch_cuda.as_tensor(lam_d), torch_cuda.as_tensor(f))
+    uo, qo = O.reconstruct(lam_d, f)
+    say(f"  recovery u {relerr(u.cpu().numpy(), uo):.2e} q {relerr(q.cpu().numpy(), qo):.2e}")
+    assert relerr(u.cpu().numpy(), uo) <= 1e-12 and relerr(q.cpu().numpy(), qo) <= 1e-11
+    P.build(method=L.METHOD_PCG, local_corr=omg.LC_BOTH)
+    lam, info = P.solve(torch_cuda.as_tensor(f), tol=1e-10)
+    res = np.linalg.norm(g - A @ lam.cpu().numpy()) / np.linalg.norm(g)
+    say(f"  CG {info['iters']} its relres {res:.2e}")
+    assert res <= 1.01e-10
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.adjoint(torch_cuda.zeros(n ** d, O.nv, dtype=torch_cuda.float64),
+                  torch_cuda.zeros(n ** d, d, O.nv, dtype=torch_cuda.float64))

@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--n3d", type=int, default=32)
     ap.add_argument("--steps3d", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-ipdg", action="store_true", help="skip the NIPG-H (hybridized IPDG) legs")
     ap.add_argument("--no-errors", action="store_true", help="skip the solve to the FP64 floor (error report)")
     ap.add_argument("--ref-tol", type=float, default=1e-13,
                     help="tolerance of the FP64 reference solve (stops at its floor if not reachable)")
@@ -347,6 +348,52 @@ def cube3d_legs(args):
     return out
 
 
+def ipdg_legs(args):
+    """The hybridized IPDG workload (NIPG-H, eq. IPG_H) on the headline mesh:
+    element maps timed on their own (a re-form through hdg_update_kappa),
+    then GMRES + V-cycle to 1e-10 in FP64 and with the FP32 cycle, same
+    launch path as the headline; median step times."""
+    import torch
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+    n, k = args.n, args.k
+    wl = inputs.ipdg2d(n, k)
+    kap = torch.as_tensor(wl.kappa, device="cuda")
+    P = Problem(2, n, k, kap, tau=wl.tau, scheme="nipg", tau_kappa=True, store_recovery=False)
+    f = torch.as_tensor(wl.f(P.volume_nodes().numpy()), device="cuda")
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.update_kappa(kap)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_el = median(ts)
+    nv, nl = (k + 1) ** 2, 4 * (k + 1)
+    flops = n * n * (2 * (2 * nv * nv * nl + nl * nl * nv) + 2 * nv ** 3)
+    out = {"workload": wl.name, "trace_dofs": P.nlam,
+           "element_maps_ms": round(1e3 * t_el, 3),
+           "element_maps_tflops": round(flops / t_el / 1e12, 2),
+           "element_maps_note": "hdg_update_kappa wall time: kappa check + ipdg_dtn_kernel; flops of the "
+                                "inverse and the three products per element"}
+    lams = {}
+    for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
+        P.build(sweeps=args.sweeps, growth=args.growth, local_corr=L.LC_PRE, precision=prec,
+                method=L.METHOD_GMRES, max_it=200, coarse_n=args.coarse_n)
+        progress(f"ipdg {nm} leg: n={n} k={k}, {P.nlam} trace DOFs")
+        times, lam, infos = timed_solves(P, f, args.tol, args.steps, 1)
+        ms = 1e3 * median(times)
+        progress(f"ipdg {nm}: {ms:.1f} ms/solve, {infos[-1]['iters']} iterations")
+        lams[nm] = lam
+        out[nm] = {"value": round(P.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos)}
+    out["lambda_mixed_vs_fp64"] = rel(lams["mixed"], lams["fp64"])
+    out["mixed_over_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    P.close()
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_probe:
@@ -481,6 +528,12 @@ def main():
             cube = cube3d_legs(args)
         except Exception as e:  # reported; the headline stands on its own
             cube = {"error": str(e)[:300]}
+    ipdg = None
+    if not args.no_ipdg:
+        try:
+            ipdg = ipdg_legs(args)
+        except Exception as e:  # reported; the headline stands on its own
+            ipdg = {"error": str(e)[:300]}
     batch = None
     if not args.no_batched:
         progress("batched leg")
@@ -515,7 +568,7 @@ def main():
                    "setup_ms": round(1e3 * t_setup, 2), "build_ms_mixed": round(1e3 * resmx["build_s"], 2),
                    "reconstruct_ms": round(1e3 * t_rec, 3),
                    "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1),
-                   "errors": errors, "diffusion3d": cube, "batched": batch},
+                   "errors": errors, "diffusion3d": cube, "ipdg2d": ipdg, "batched": batch},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

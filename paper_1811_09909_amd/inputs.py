@@ -18,6 +18,11 @@ Workloads (all on the unit box, tau = 1, zero Dirichlet data):
                       kappa per element log-uniform, then nrhs nodal N(0,1)
                       right-hand sides.
 * ``adjoint2d``    -- f = 1, theta = log kappa per element ~ N(0,1).
+* ``ipdg2d``       -- the hybridized IPDG workload: kappa per element
+                      1 + 0.5 sin(2 pi x) cos(3 pi y) at the element centre
+                      (the coefficient of Example III on the unit square),
+                      f = -kappa_T lap u for u = x y exp(x^2 y^3) (Example I),
+                      zero Dirichlet data; stabilization kappa_T (p+1)(p+2)/h_min.
 """
 import numpy as np
 
@@ -107,3 +112,21 @@ def adjoint2d(n=256, k=3, seed=0):
 def observation_noise(rng, shape):
     """xi ~ N(0,1) per nodal value, drawn after theta."""
     return rng.standard_normal(shape)
+
+
+def ipdg2d(n=512, k=4):
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")  # element index x + n y
+    kappa = (1.0 + 0.5 * np.sin(2 * np.pi * X) * np.cos(3 * np.pi * Y)).ravel()
+
+    def lap_u(P):
+        x, y = P[..., 0], P[..., 1]
+        e = np.exp(x ** 2 * y ** 3)
+        return y * e * (6 * x * y ** 3 + 4 * x ** 3 * y ** 6) + x * e * (12 * x ** 2 * y ** 2 + 9 * x ** 4 * y ** 5)
+
+    def f(P):
+        """-kappa_T lap u at points P [N_T, m, 2] (element-major)."""
+        return -kappa[:, None] * lap_u(P)
+
+    return Workload(d=2, n=n, k=k, tau=(k + 1) * (k + 2) * n / np.sqrt(2.0), kappa=kappa, f=f,
+                    name=f"ipdg2d NIPG-H n={n} k={k} kappa=1+0.5sin(2pi x)cos(3pi y) tau=kappa(p+1)(p+2)/h_min")

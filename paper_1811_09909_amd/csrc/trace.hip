@@ -418,7 +418,12 @@ __global__ void prolong_p_kernel(long nface, const double* __restrict__ Jp, cons
 //   e_I += A_II^-1 rho_I            (eq. localCorrection, when do_corr)
 //   cb_M = R_M^T rho_I = -J^T A_BI A_II^-1 rho_I   (eq. n_1_Qk, when do_restrict;
 //   the launcher passes the restriction block R, which is P on symmetric levels)
-template <int D, typename T, typename M = T>
+// CH lanes share a macro-element: wavefront w of the grid covers the 64
+// macro-elements of group w / CH (one per lane, so the AoSoA blocks are read
+// coalesced) and takes chunk w % CH of the work: rows c*RI .. of A_II^-1 and
+// outputs c*RJ .. of the restriction.  Each row and output is still summed
+// by one lane in the order of the one-lane form.
+template <int D, typename T, typename M, int CH>
 __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__ AIIinv, const M* __restrict__ P,
                                                     const T* __restrict__ rho, T* __restrict__ e, int do_corr,
                                                     int do_restrict, T* __restrict__ cb) {
@@ -426,10 +431,15 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__
   constexpr int NIF = D * NC;  // interior faces per macro-element
   constexpr int NI = NIF * NC;
   constexpr int NCL = 2 * D * NC;
+  constexpr int RI = (NI + CH - 1) / CH;
+  constexpr int RJ = (NCL + CH - 1) / CH;
   const int nm = n / 2;
   long nmacro = 1;
   for (int a = 0; a < D; ++a) nmacro *= nm;
-  const long Mi = blockIdx.x * 256L + threadIdx.x;
+  const long t = blockIdx.x * 256L + threadIdx.x;
+  const long w = t >> 6;
+  const int c = (int)(w % CH);
+  const long Mi = (w / CH) * 64 + (t & 63);
   if (Mi >= nmacro) return;
   {
     const long sF = trace_len<D>(n, NC);
@@ -441,30 +451,38 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__
   decode_elem<D>(Mi, nm, m);
   using A = acc_t<T>;
   A rI[NI];
-  long fid[NIF];
 #pragma unroll
   for (int i = 0; i < NIF; ++i) {
-    fid[i] = macro_iface<D>(m, i, n);
+    const long f = macro_iface<D>(m, i, n);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) rI[i * NC + a] = rho[fid[i] * NC + a];
+    for (int a = 0; a < NC; ++a) rI[i * NC + a] = rho[f * NC + a];
   }
   if (do_corr) {
-    A s[NI];
+    const M* Ab = AIIinv + aos_item<M>(Mi, vpad<M>(NI * NI));
 #pragma unroll
-    for (int i = 0; i < NI; ++i) s[i] = A(0);
-    aos_mv<M, NI * NI, NI, false>(AIIinv + aos_item<M>(Mi, vpad<M>(NI * NI)), rI, s);
+    for (int r = 0; r < RI; ++r) {
+      const int i = c * RI + r;
+      if (i < NI) {
+        A s = A(0);
 #pragma unroll
-    for (int i = 0; i < NIF; ++i)
-#pragma unroll
-      for (int a = 0; a < NC; ++a) e[fid[i] * NC + a] = T(A(e[fid[i] * NC + a]) + s[i * NC + a]);
+        for (int j = 0; j < NI; ++j) s += A(Ab[aos_off<M>(0, 0, i * NI + j)]) * rI[j];
+        const long f = macro_iface<D>(m, i / NC, n) * NC + i % NC;
+        e[f] = T(A(e[f]) + s);
+      }
+    }
   }
   if (do_restrict) {
-    A s[NCL];
+    const M* Pb = P + aos_item<M>(Mi, vpad<M>(NI * NCL));
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) s[j] = A(0);
-    aos_mv<M, NI * NCL, NCL, true>(P + aos_item<M>(Mi, vpad<M>(NI * NCL)), rI, s);
+    for (int r = 0; r < RJ; ++r) {
+      const int J = c * RJ + r;
+      if (J < NCL) {
+        A s = A(0);
 #pragma unroll
-    for (int j = 0; j < NCL; ++j) cb[Mi * NCL + j] = T(s[j]);
+        for (int i = 0; i < NI; ++i) s += A(Pb[aos_off<M>(0, 0, i * NCL + J)]) * rI[i];
+        cb[Mi * NCL + J] = T(s);
+      }
+    }
   }
 }
 
@@ -516,7 +534,7 @@ __global__ void hrestrict_kernel(int n, const T* __restrict__ rho, const T* __re
 
 // e_I += P_M ec_M per macro-element (blocks [0, nbm)), e_B += J ec per coarse
 // face (blocks [nbm, ...))   (eq. n_1_Ik)
-template <int D, typename T, typename M = T>
+template <int D, typename T, typename M, int CH>
 __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const M* __restrict__ P,
                                                        const T* __restrict__ ec, T* __restrict__ e) {
   constexpr int NC = 1 << (D - 1);
@@ -530,7 +548,12 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const M*
   if (blockIdx.x < nbm) {
     long nmacro = 1;
     for (int a = 0; a < D; ++a) nmacro *= nm;
-    const long Mi = blockIdx.x * 256L + threadIdx.x;
+    // CH lanes per macro-element, rows c*RI .. of P for chunk c (as hcorr)
+    constexpr int RI = (NI + CH - 1) / CH;
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    const long w = t >> 6;
+    const int c = (int)(w % CH);
+    const long Mi = (w / CH) * 64 + (t & 63);
     if (Mi >= nmacro) return;
     int m[3] = {0, 0, 0};
     decode_elem<D>(Mi, nm, m);
@@ -550,19 +573,17 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const M*
         for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
       }
     }
-    A s[NI];
+    const M* Pb = P + aos_item<M>(Mi, vpad<M>(NI * NCL));
 #pragma unroll
-    for (int i = 0; i < NIF; ++i) {
-      const long f = macro_iface<D>(m, i, n);
+    for (int r = 0; r < RI; ++r) {
+      const int i = c * RI + r;
+      if (i < NI) {
+        const long f = macro_iface<D>(m, i / NC, n) * NC + i % NC;
+        A s = e[f];
 #pragma unroll
-      for (int a = 0; a < NC; ++a) s[i * NC + a] = e[f * NC + a];
-    }
-    aos_mv<M, NI * NCL, NCL, false>(P + aos_item<M>(Mi, vpad<M>(NI * NCL)), cv, s);
-#pragma unroll
-    for (int i = 0; i < NIF; ++i) {
-      const long f = macro_iface<D>(m, i, n);
-#pragma unroll
-      for (int a = 0; a < NC; ++a) e[f * NC + a] = T(s[i * NC + a]);
+        for (int J = 0; J < NCL; ++J) s += A(Pb[aos_off<M>(0, 0, i * NCL + J)]) * cv[J];
+        e[f] = T(s);
+      }
     }
   } else {
     const long ncf = D * nface_dir<D>(nm);
@@ -749,6 +770,11 @@ __global__ void coarse_gemv_kernel(int N, const M* __restrict__ Ainv, const T* _
 }
 
 inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
+// lanes per macro-element of the 3D local-correction / restriction /
+// prolongation kernels (NI = 48 rows of A_II^-1 and P: 4 each; 24 restriction
+// outputs: 2 each), and the blocks of 256 lanes that cover nmacro of them
+constexpr int MACRO_CH3 = 12;
+inline unsigned macro_blocks(long nmacro, int ch) { return (unsigned)(((nmacro + 63) / 64 * ch * 64 + 255) / 256); }
 
 // macro-element kernels use 4 lanes per macro-element up to MULTI_LANE_MAX
 // macro-elements times right-hand sides (latency-bound levels), 2 lanes up to
@@ -1039,11 +1065,11 @@ void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restri
   const M* Ai = sizeof(M) == 8 ? (const M*)L.AIIinv64 : (const M*)L.AIIinv32;
   const M* P = sizeof(M) == 8 ? (const M*)L.R64 : (const M*)L.R32;  // restriction block
   if (L.d == 2)
-    hipLaunchKernelGGL((hcorr_kernel<2, T, M>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
+    hipLaunchKernelGGL((hcorr_kernel<2, T, M, 1>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
                        do_corr, do_restrict, cb);
   else
-    hipLaunchKernelGGL((hcorr_kernel<3, T, M>), dim3(nblk(L.nmacro), nrhs), dim3(256), 0, st, L.n, Ai, P, rho, e,
-                       do_corr, do_restrict, cb);
+    hipLaunchKernelGGL((hcorr_kernel<3, T, M, MACRO_CH3>), dim3(macro_blocks(L.nmacro, MACRO_CH3), nrhs), dim3(256), 0,
+                       st, L.n, Ai, P, rho, e, do_corr, do_restrict, cb);
   HDG_CHECK(hipGetLastError());
 }
 
@@ -1060,13 +1086,16 @@ void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb,
 template <typename T, typename M>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs) {
   const M* P = sizeof(M) == 8 ? (const M*)L.P64 : (const M*)L.P32;
-  long nbm = nblk(L.nmacro), nbf = nblk(C.nface);
-  if (L.d == 2)
-    hipLaunchKernelGGL((hprolong_kernel<2, T, M>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P,
+  const long nbf = nblk(C.nface);
+  if (L.d == 2) {
+    const long nbm = nblk(L.nmacro);
+    hipLaunchKernelGGL((hprolong_kernel<2, T, M, 1>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P,
                        ec, e);
-  else
-    hipLaunchKernelGGL((hprolong_kernel<3, T, M>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st, L.n, nbm, P,
-                       ec, e);
+  } else {
+    const long nbm = macro_blocks(L.nmacro, MACRO_CH3);
+    hipLaunchKernelGGL((hprolong_kernel<3, T, M, MACRO_CH3>), dim3((unsigned)(nbm + nbf), nrhs), dim3(256), 0, st,
+                       L.n, nbm, P, ec, e);
+  }
   HDG_CHECK(hipGetLastError());
 }
 

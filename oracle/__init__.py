@@ -26,6 +26,9 @@ follows):
   NIPG-H; eqs. IPDG_flux, SIPG_H, IPG_H): element matrices, static
   condensation into the same trace system, recovery of u and
   q = -kappa grad u, and the uncondensed system.
+* ``rth``      -- the hybridized Raviart-Thomas mixed method (RT_k-H on
+  squares, eqs. mixed_local1, mixed_local2) and multinumerics (RT-H and an
+  IPDG scheme element by element in one trace system, Sec. 4.6).
 * ``adjoint``  -- gradient of a misfit with respect to per-element
   log-permeability through the discrete adjoint of the HDG system
   (derived from eqs. HDG and HDG_flux; not in the paper).
@@ -36,4 +39,4 @@ the paper and the mathematics fix (energy identities, Propositions 1 and
 nested-dissection limit, complex-step derivatives).  Functions without
 such a pin say "parity unpinned" in their docstring.
 """
-from . import refelem, hdg, mg, adjoint, ipdg  # noqa: F401
+from . import refelem, hdg, mg, adjoint, ipdg, rth  # noqa: F401

@@ -155,10 +155,13 @@ void hdg_default_opts(hdg_mg_opts* opts);
 hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
                      int store_recovery, void* hip_stream, hdg_handle* out);
 
-/* Discretizations of the trace system (Sec. 2): HDG (eqs. HDG, HDG_flux)
- * and the hybridized interior penalty family of eq. IPG_H, with
- * s_f = 1 (SIPG-H, eq. SIPG_H), 0 (IIPG-H) and -1 (NIPG-H). */
-enum { HDG_SCHEME_HDG = 0, HDG_SCHEME_SIPG = 1, HDG_SCHEME_IIPG = 2, HDG_SCHEME_NIPG = 3 };
+/* Discretizations of the trace system (Sec. 2): HDG (eqs. HDG, HDG_flux),
+ * the hybridized interior penalty family of eq. IPG_H, with s_f = 1
+ * (SIPG-H, eq. SIPG_H), 0 (IIPG-H) and -1 (NIPG-H), and the hybridized
+ * Raviart-Thomas mixed method (RT-H, eqs. mixed_local1/2: RT_k =
+ * Q_{k+1,k} x Q_{k,k+1} on the squares, scalar Q^k, traces P^k; d = 2,
+ * k <= 4, no stabilization: tau is not used). */
+enum { HDG_SCHEME_HDG = 0, HDG_SCHEME_SIPG = 1, HDG_SCHEME_IIPG = 2, HDG_SCHEME_NIPG = 3, HDG_SCHEME_RT = 4 };
 /* Or-ed into the scheme of hdg_setup_scheme: element T is stabilized with
  * tau * kappa_T instead of tau (the paper's tau = kappa / h_min for HDG and
  * kappa (p+1)(p+2) / h_min for IPDG in Examples III and IV); needs
@@ -182,7 +185,28 @@ enum { HDG_SCHEME_TAU_KAPPA = 16 };
  * is HDG only.  Other arguments as for hdg_setup. */
 hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
                             int scheme, int store_recovery, void* hip_stream, hdg_handle* out);
-/* (scheme: one HDG_SCHEME_* value, optionally | HDG_SCHEME_TAU_KAPPA) */
+/* (scheme: one HDG_SCHEME_* value, optionally | HDG_SCHEME_TAU_KAPPA.  For
+ * RT-H the element maps are A^e = F^T Lqq F from the inverse of the local
+ * saddle-point matrix [[M_q, -B], [B^T, 0]] (F the normal traces of the
+ * velocity basis, M_q its kappa^-1 weighted mass, B_ij = (w_j, div v_i)),
+ * the load map F^T Lqu M_T, and recovery returns u and the velocity field
+ * evaluated at the scalar's nodes.) */
+
+/* Multinumerics (Sec. 4.6): one discretization per element on a 2D mesh.
+ * scheme_of_element: DEVICE array [N_T] of HDG_SCHEME_SIPG, _IIPG, _NIPG
+ * or _RT (the trace spaces of these agree, so their element maps assemble
+ * into one trace system; HDG elements are not mixed in); it is copied at
+ * setup.  options: 0 or HDG_SCHEME_TAU_KAPPA (for the IPDG elements).
+ * kappa per element when any IPDG element is present.  The operator is
+ * symmetric when only SIPG-H and RT-H elements are present; otherwise the
+ * build rules of the nonsymmetric schemes apply (no CG).  Recovery: u, and
+ * the flux at the nodes (-kappa grad u on IPDG elements, the RT field on
+ * RT-H elements).  Errors: HDG_ERR_INVALID_ARG for an unknown code,
+ * HDG_ERR_UNSUPPORTED for d != 2, k > 4 with RT-H elements, or kappa at the
+ * quadrature points with IPDG elements.  Other arguments as for hdg_setup. */
+hdg_status hdg_setup_multi(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                           const int* scheme_of_element, int options, int store_recovery, void* hip_stream,
+                           hdg_handle* out);
 
 /* Re-form A^e for a new kappa (same layout rules); invalidates the
  * hierarchy (call hdg_mg_build again). */

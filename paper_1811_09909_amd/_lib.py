@@ -22,7 +22,7 @@ EXPORTS = [
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
     "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune", "hdg_rhs_noalloc",
-    "hdg_setup_scheme",
+    "hdg_setup_scheme", "hdg_setup_multi",
 ]
 
 
@@ -50,8 +50,8 @@ OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", 
               "nrhs", "refine_red", "variant", "smoother")
 SMOOTHER_BLOCK_JACOBI, SMOOTHER_JACOBI, SMOOTHER_CHEBYSHEV, SMOOTHER_LUSGS = 0, 1, 2, 3
 # HDG_SCHEME_*: HDG, and the hybridized IPDG family (eq. IPG_H, s_f = 1, 0, -1)
-SCHEME_HDG, SCHEME_SIPG, SCHEME_IIPG, SCHEME_NIPG = 0, 1, 2, 3
-SCHEMES = {"hdg": SCHEME_HDG, "sipg": SCHEME_SIPG, "iipg": SCHEME_IIPG, "nipg": SCHEME_NIPG}
+SCHEME_HDG, SCHEME_SIPG, SCHEME_IIPG, SCHEME_NIPG, SCHEME_RT = 0, 1, 2, 3, 4
+SCHEMES = {"hdg": SCHEME_HDG, "sipg": SCHEME_SIPG, "iipg": SCHEME_IIPG, "nipg": SCHEME_NIPG, "rt": SCHEME_RT}
 SCHEME_TAU_KAPPA = 16  # or-ed into the scheme: element T stabilized with tau * kappa_T
 
 
@@ -85,6 +85,7 @@ def load():
         "hdg_default_opts": (None, [ctypes.POINTER(Opts)]),
         "hdg_setup": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_scheme": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, I, P, ctypes.POINTER(P)]),
+        "hdg_setup_multi": (I, [ctypes.POINTER(Mesh), I, D, P, I, P, I, I, P, ctypes.POINTER(P)]),
         "hdg_update_kappa": (I, [P, P, I]),
         "hdg_mg_build": (I, [P, ctypes.POINTER(Opts)]),
         "hdg_vcycle": (I, [P, P, P, I, I]),

@@ -25,6 +25,10 @@ struct hdg_problem {
   double sf = 0.0;
   bool sym = true;
   bool tau_kappa = false;  // element T stabilized with tau * kappa_T (HDG_SCHEME_TAU_KAPPA)
+  // multinumerics (scheme == SCHEME_MULTI): each element's scheme code on the
+  // device, and the codes present
+  int* emask = nullptr;
+  std::vector<int> codes;
   hipStream_t st = nullptr;      // caller's stream: all work is ordered on it
   hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
   // execution form, from hdg_mg_opts.variant at build
@@ -56,6 +60,7 @@ struct hdg_problem {
   // IPDG schemes Kinv holds L^-1 and Xr the recovery block L^-1 R
   double *kqp = nullptr, *Ae = nullptr, *W = nullptr, *Kinv = nullptr, *Minv = nullptr, *ework = nullptr;
   double* Xr = nullptr;
+  double *Xq = nullptr, *Yq = nullptr;  // RT-H flux recovery at the nodes: Xq Lambda + Yq b
   int* bad = nullptr;
   int* hbad = nullptr;
   bool store_recovery = false;
@@ -147,11 +152,25 @@ bool check_kappa(hdg_problem* P, const double* kappa, int kind) {
   return *P->hbad == 0;
 }
 
-void form_elements(hdg_problem* P) {
-  if (P->scheme == HDG_SCHEME_HDG)
+constexpr int SCHEME_MULTI = 64;  // internal: one scheme per element (hdg_setup_multi)
+
+double sf_of(int code) { return code == HDG_SCHEME_SIPG ? 1.0 : code == HDG_SCHEME_IIPG ? 0.0 : -1.0; }
+
+void form_scheme(hdg_problem* P, const int* mask, int code) {
+  if (code == HDG_SCHEME_HDG)
     launch_element_dtn(P->d, P->k, P->nelem, P->tau, P->tau_kappa, P->rd, P->kqp, P->Ae, P->W, P->Kinv, P->Minv, P->st);
+  else if (code == HDG_SCHEME_RT)
+    launch_rt_dtn(P->k, P->nelem, mask, code, P->rd, P->kqp, P->Ae, P->W, P->Xr, P->Kinv, P->Xq, P->Yq, P->st);
   else
-    launch_ipdg_dtn(P->d, P->k, P->nelem, P->tau, P->tau_kappa, P->sf, P->rd, P->kqp, P->nq, P->Ae, P->W, P->Xr, P->Kinv, P->st);
+    launch_ipdg_dtn(P->d, P->k, P->nelem, mask, code, P->tau, P->tau_kappa, sf_of(code), P->rd, P->kqp, P->nq, P->Ae,
+                    P->W, P->Xr, P->Kinv, P->st);
+}
+
+void form_elements(hdg_problem* P) {
+  if (P->scheme == SCHEME_MULTI)
+    for (int c : P->codes) form_scheme(P, P->emask, c);
+  else
+    form_scheme(P, nullptr, P->scheme);
 }
 
 void drop_graphs(hdg_problem* P) {
@@ -951,24 +970,28 @@ hdg_status hdg_reference_nodes(int k, double* gll, double* gauss) {
   return HDG_OK;
 }
 
-hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
-                     int store_recovery, void* hip_stream, hdg_handle* out) {
-  return hdg_setup_scheme(mesh, k, tau, kappa, kappa_kind, HDG_SCHEME_HDG, store_recovery, hip_stream, out);
-}
+namespace {
 
-hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
-                            int scheme, int store_recovery, void* hip_stream, hdg_handle* out) {
+// Setup of any discretization: `scheme` one HDG_SCHEME_* code, or
+// SCHEME_MULTI with `codes` the codes present and `mask_host` one code per
+// element.
+hdg_status setup_impl(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind, int scheme,
+                      bool tau_kappa, const std::vector<int>& codes, const std::vector<int>& mask_host,
+                      int store_recovery, void* hip_stream, hdg_handle* out) {
   if (!mesh || !out || !kappa) return HDG_ERR_INVALID_ARG;
-  if (scheme & ~(15 | HDG_SCHEME_TAU_KAPPA)) return HDG_ERR_INVALID_ARG;
-  const bool tau_kappa = (scheme & HDG_SCHEME_TAU_KAPPA) != 0;
-  scheme &= 15;
-  if (scheme < HDG_SCHEME_HDG || scheme > HDG_SCHEME_NIPG) return HDG_ERR_INVALID_ARG;
-  if ((scheme != HDG_SCHEME_HDG || tau_kappa) && kappa_kind == HDG_KAPPA_AT_QP) return HDG_ERR_UNSUPPORTED;
+  if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
   if (mesh->dim != 2 && mesh->dim != 3) return HDG_ERR_UNSUPPORTED;
   if (mesh->n < 1 || mesh->n > (mesh->dim == 2 ? 8192 : 512)) return HDG_ERR_INVALID_ARG;
   if (k < 1 || (mesh->dim == 2 && k > 6) || (mesh->dim == 3 && k > 3)) return HDG_ERR_UNSUPPORTED;
   if (!(tau > 0.0) || !std::isfinite(tau)) return HDG_ERR_INVALID_ARG;
-  if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
+  bool has_ipdg = false, has_rt = false, sym = true;
+  for (int c : codes) {
+    has_ipdg |= c == HDG_SCHEME_SIPG || c == HDG_SCHEME_IIPG || c == HDG_SCHEME_NIPG;
+    has_rt |= c == HDG_SCHEME_RT;
+    sym &= c == HDG_SCHEME_HDG || c == HDG_SCHEME_SIPG || c == HDG_SCHEME_RT;
+  }
+  if ((has_ipdg || tau_kappa) && kappa_kind == HDG_KAPPA_AT_QP) return HDG_ERR_UNSUPPORTED;
+  if (has_rt && (mesh->dim != 2 || k > 4)) return HDG_ERR_UNSUPPORTED;
   *out = nullptr;
   hdg_problem* P = new (std::nothrow) hdg_problem();
   if (!P) return HDG_ERR_DEVICE;
@@ -978,14 +1001,16 @@ hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const doubl
   P->k = k;
   P->tau = tau;
   P->scheme = scheme;
+  P->codes = codes;
   P->tau_kappa = tau_kappa;
-  P->sf = scheme == HDG_SCHEME_SIPG ? 1.0 : scheme == HDG_SCHEME_IIPG ? 0.0 : -1.0;
-  P->sym = scheme == HDG_SCHEME_HDG || scheme == HDG_SCHEME_SIPG;
+  P->sf = sf_of(scheme);
+  P->sym = sym;
   P->st = (hipStream_t)hip_stream;
   P->store_recovery = store_recovery != 0;
   const auto t0 = std::chrono::steady_clock::now();
   HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
   P->ref.build(P->d, k, 1.0 / P->n);
+  if (has_rt) P->ref.build_rt();
   P->nv = P->ref.nv;
   P->ne = P->ref.ne;
   P->nl = P->ref.nl;
@@ -1000,11 +1025,21 @@ hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const doubl
   P->rd.H = upload(P, P->ref.H);
   P->rd.M = upload(P, P->ref.M);
   P->rd.Jp = upload(P, P->ref.Jp);
-  if (scheme != HDG_SCHEME_HDG) {
+  if (has_ipdg) {
     P->rd.Kst = upload(P, P->ref.Kst);
     P->rd.Nn = upload(P, P->ref.Nn);
     P->rd.Dn = upload(P, P->ref.Dn);
     P->rd.Dnode = upload(P, P->ref.Dnode);
+  }
+  if (has_rt) {
+    P->rd.Vq = upload(P, P->ref.Vq);
+    P->rd.Bd = upload(P, P->ref.Bd);
+    P->rd.Fr = upload(P, P->ref.Fr);
+    P->rd.Vnode = upload(P, P->ref.Vnode);
+  }
+  if (scheme == SCHEME_MULTI) {
+    P->emask = dalloc<int>(P, P->nelem, false);
+    HDG_CHECK(hipMemcpy(P->emask, mask_host.data(), sizeof(int) * P->nelem, hipMemcpyHostToDevice));
   }
   P->kqp = dalloc<double>(P, P->nelem * P->nq, false);
   P->Ae = dalloc<double>(P, P->nelem * P->nl * P->nl, false);
@@ -1015,6 +1050,10 @@ hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const doubl
       P->Minv = dalloc<double>(P, P->nelem * P->nv * P->nv, false);
     else
       P->Xr = dalloc<double>(P, P->nelem * P->nv * P->nl, false);
+    if (has_rt) {
+      P->Xq = dalloc<double>(P, P->nelem * P->d * P->nv * P->nl, false);
+      P->Yq = dalloc<double>(P, P->nelem * P->d * P->nv * P->nv, false);
+    }
   }
   P->ework = dalloc<double>(P, P->nelem * (P->nv + P->nl), false);
   P->bad = dalloc<int>(P, 1, false);
@@ -1042,10 +1081,50 @@ hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const doubl
   }
 }
 
+}  // namespace
+
+hdg_status hdg_setup(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                     int store_recovery, void* hip_stream, hdg_handle* out) {
+  return hdg_setup_scheme(mesh, k, tau, kappa, kappa_kind, HDG_SCHEME_HDG, store_recovery, hip_stream, out);
+}
+
+hdg_status hdg_setup_scheme(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                            int scheme, int store_recovery, void* hip_stream, hdg_handle* out) {
+  if (scheme & ~(15 | HDG_SCHEME_TAU_KAPPA)) return HDG_ERR_INVALID_ARG;
+  const bool tau_kappa = (scheme & HDG_SCHEME_TAU_KAPPA) != 0;
+  scheme &= 15;
+  if (scheme < HDG_SCHEME_HDG || scheme > HDG_SCHEME_RT) return HDG_ERR_INVALID_ARG;
+  return setup_impl(mesh, k, tau, kappa, kappa_kind, scheme, tau_kappa, {scheme}, {}, store_recovery, hip_stream, out);
+}
+
+hdg_status hdg_setup_multi(const hdg_mesh* mesh, int k, double tau, const double* kappa, int kappa_kind,
+                           const int* scheme_of_element, int options, int store_recovery, void* hip_stream,
+                           hdg_handle* out) {
+  if (!mesh || !scheme_of_element || (options & ~HDG_SCHEME_TAU_KAPPA)) return HDG_ERR_INVALID_ARG;
+  if (mesh->n < 1 || mesh->n > 8192 || mesh->dim != 2) return mesh->dim != 2 ? HDG_ERR_UNSUPPORTED : HDG_ERR_INVALID_ARG;
+  const long nel = (long)mesh->n * mesh->n;
+  std::vector<int> mask(nel);
+  if (hipMemcpy(mask.data(), scheme_of_element, sizeof(int) * nel, hipMemcpyDeviceToHost) != hipSuccess)
+    return HDG_ERR_INVALID_ARG;
+  std::vector<int> codes;
+  for (int c : mask) {
+    if (c != HDG_SCHEME_SIPG && c != HDG_SCHEME_IIPG && c != HDG_SCHEME_NIPG && c != HDG_SCHEME_RT)
+      return HDG_ERR_INVALID_ARG;
+    if (std::find(codes.begin(), codes.end(), c) == codes.end()) codes.push_back(c);
+  }
+  std::sort(codes.begin(), codes.end());
+  return setup_impl(mesh, k, tau, kappa, kappa_kind, SCHEME_MULTI, (options & HDG_SCHEME_TAU_KAPPA) != 0, codes, mask,
+                    store_recovery, hip_stream, out);
+}
+
 hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
   if (!P || !kappa) return HDG_ERR_INVALID_ARG;
   if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
-  if ((P->scheme != HDG_SCHEME_HDG || P->tau_kappa) && kappa_kind == HDG_KAPPA_AT_QP) return HDG_ERR_UNSUPPORTED;
+  if (kappa_kind == HDG_KAPPA_AT_QP) {
+    bool elem_only = P->tau_kappa;
+    for (int c : P->codes) elem_only |= c == HDG_SCHEME_SIPG || c == HDG_SCHEME_IIPG || c == HDG_SCHEME_NIPG;
+    if (elem_only) return HDG_ERR_UNSUPPORTED;
+  }
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   if (!check_kappa(P, kappa, kappa_kind)) return HDG_ERR_INVALID_ARG;
@@ -1963,8 +2042,8 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
     launch_reconstruct(P->d, P->k, P->n, P->tau, P->tau_kappa, P->rd, P->kqp, lambda, gdir, rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0,
                        P->W, P->Kinv, P->Minv, P->ework, u, q, P->st);
   else
-    launch_ipdg_reconstruct(P->d, P->k, P->n, P->rd, P->kqp, P->nq, lambda, gdir, rhs,
-                            rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->Xr, P->Kinv, P->ework, u, q, P->st);
+    launch_ipdg_reconstruct(P->d, P->k, P->n, P->rd, P->kqp, P->nq, P->emask, HDG_SCHEME_RT, P->Xq, P->Yq, lambda, gdir,
+                            rhs, rhs_kind == HDG_RHS_F_LOAD ? 1 : 0, P->Xr, P->Kinv, P->ework, u, q, P->st);
   return HDG_OK;
   HDG_GUARD_END
 }

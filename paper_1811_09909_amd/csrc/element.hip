@@ -359,7 +359,8 @@ __global__ void __launch_bounds__(NT) element_dtn_kernel(long nelem, double tau0
 // without pivoting applies.  The products run on the matrix cores; the
 // operands R and C^T are formed as they are read.
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) ipdg_dtn_kernel(long nelem, double tau0, int tau_kappa, double sf, int nq,
+__global__ void __launch_bounds__(NT) ipdg_dtn_kernel(long nelem, const int* __restrict__ mask, int code,
+                                                      double tau0, int tau_kappa, double sf, int nq,
                                                       const double* __restrict__ kqp,
                                                       const double* __restrict__ Kst,
                                                       const double* __restrict__ Nn,
@@ -375,6 +376,7 @@ __global__ void __launch_bounds__(NT) ipdg_dtn_kernel(long nelem, double tau0, i
   __shared__ double sX[NV * NL];  // X = L^-1 R
   const long T = blockIdx.x;
   if (T >= nelem) return;
+  if (mask && mask[T] != code) return;
   const int tid = threadIdx.x;
   const double kap = kqp[T * nq];
   const double tau = tau_kappa ? tau0 * kap : tau0;
@@ -398,6 +400,87 @@ __global__ void __launch_bounds__(NT) ipdg_dtn_kernel(long nelem, double tau0, i
   wg_mfma<NV, NL, NV, NT>([&](int i, int l) { return sL[l * NV + i]; },
                           [&](int l, int j) { return tau * Gm[l * NL + j] - kap * Dn[l * NL + j]; },
                           [&](int i, int j, double v) { Wout[(T * NV + i) * NL + j] = v; });
+}
+
+// Element maps of the hybridized Raviart-Thomas method (eqs. mixed_local1/2,
+// d = 2), one workgroup per element.  The local system in (Q, U),
+//   L = [[Mq, -Bd], [Bd^T, 0]],  R = [-Fr; 0],  S = [Fr; 0],
+// Mq = blockdiag_c(Vq_c^T diag(w / kappa) Vq_c), is inverted in LDS
+// (Gauss-Jordan in the natural order: the Mq pivots, then those of
+// Bd^T Mq^-1 Bd, all positive), and with L^-1 = [[Lqq, Lqu], [Luq, Luu]]:
+//   A^e = -S^T L^-1 R = Fr^T Lqq Fr,       load map W = Lqu^T Fr,
+//   u = Xr Lambda + Luu b,  Xr = -Luq Fr,
+//   flux at the nodes  Xq Lambda + Yq b,  Xq = -Vn Lqq Fr,  Yq = Vn Lqu,
+// Vn the velocity basis at the scalar's nodes.  `mask`: element scheme codes
+// (only elements with code `code` are formed), or null for all.
+template <int K, int NT>
+__global__ void __launch_bounds__(NT) rt_dtn_kernel(long nelem, const int* __restrict__ mask, int code,
+                                                    const double* __restrict__ Wq, const double* __restrict__ kqp,
+                                                    const double* __restrict__ Vq, const double* __restrict__ Bd,
+                                                    const double* __restrict__ Fr, const double* __restrict__ Vn,
+                                                    double* __restrict__ Aelem, double* __restrict__ Wout,
+                                                    double* __restrict__ Xr, double* __restrict__ Luu_out,
+                                                    double* __restrict__ Xq, double* __restrict__ Yq) {
+  using Dm = Dims<2, K>;
+  constexpr int NV = Dm::NV, NL = Dm::NL, NQ = Dm::NQ;
+  constexpr int NQC = (K + 2) * (K + 1), NQV = 2 * NQC, N = NQV + NV;
+  __shared__ double sL[N * N];       // L -> L^-1
+  __shared__ double sT[NQV * NL];    // T = Lqq Fr
+  __shared__ double sW[NQ];          // w_q / kappa_q
+  const long T = blockIdx.x;
+  if (T >= nelem) return;
+  if (mask && mask[T] != code) return;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < NQ; q += NT) sW[q] = Wq[q] / kqp[T * NQ + q];
+  for (int idx = tid; idx < N * N; idx += NT) {
+    const int i = idx / N, j = idx % N;
+    double v = 0.0;
+    if (i < NQV && j >= NQV)
+      v = -Bd[i * NV + (j - NQV)];
+    else if (i >= NQV && j < NQV)
+      v = Bd[j * NV + (i - NQV)];
+    sL[idx] = v;
+  }
+  __syncthreads();
+  for (int c = 0; c < 2; ++c) {
+    const double* V = Vq + (long)c * NQ * NQC;
+    wg_mfma<NQC, NQC, NQ, NT>([&](int i, int q) { return V[q * NQC + i] * sW[q]; },
+                              [&](int q, int j) { return V[q * NQC + j]; },
+                              [&](int i, int j, double v) { sL[(c * NQC + i) * N + c * NQC + j] = v; });
+  }
+  gj_inverse_reg<N, NT>(sL);
+  if (Luu_out)
+    for (int idx = tid; idx < NV * NV; idx += NT)
+      Luu_out[T * NV * NV + idx] = sL[(NQV + idx / NV) * N + NQV + idx % NV];
+  // T = Lqq Fr
+  wg_mfma<NQV, NL, NQV, NT>([&](int i, int l) { return sL[i * N + l]; },
+                            [&](int l, int j) { return Fr[l * NL + j]; },
+                            [&](int i, int j, double v) { sT[i * NL + j] = v; });
+  __syncthreads();
+  double* Ae = Aelem + T * (long)NL * NL;
+  wg_mfma<NL, NL, NQV, NT>([&](int i, int l) { return Fr[l * NL + i]; },
+                           [&](int l, int j) { return sT[l * NL + j]; },
+                           [&](int i, int j, double v) { Ae[i * NL + j] = v; });
+  // W = Lqu^T Fr: W[a][l] = sum_q L[q][NQV + a] Fr[q][l]
+  wg_mfma<NV, NL, NQV, NT>([&](int a, int q) { return sL[q * N + NQV + a]; },
+                           [&](int q, int l) { return Fr[q * NL + l]; },
+                           [&](int a, int l, double v) { Wout[(T * NV + a) * NL + l] = v; });
+  if (Xr) {
+    // Xr = -Luq Fr
+    wg_mfma<NV, NL, NQV, NT>([&](int a, int q) { return sL[(NQV + a) * N + q]; },
+                             [&](int q, int l) { return Fr[q * NL + l]; },
+                             [&](int a, int l, double v) { Xr[(T * NV + a) * NL + l] = -v; });
+    // flux maps at the nodes, one velocity component at a time
+    for (int c = 0; c < 2; ++c) {
+      const double* V = Vn + (long)c * NV * NQC;
+      wg_mfma<NV, NL, NQC, NT>([&](int a, int I) { return V[a * NQC + I]; },
+                               [&](int I, int l) { return sT[(c * NQC + I) * NL + l]; },
+                               [&](int a, int l, double v) { Xq[((T * 2 + c) * NV + a) * NL + l] = -v; });
+      wg_mfma<NV, NV, NQC, NT>([&](int a, int I) { return V[a * NQC + I]; },
+                               [&](int I, int j) { return sL[(c * NQC + I) * N + NQV + j]; },
+                               [&](int a, int j, double v) { Yq[((T * 2 + c) * NV + a) * NV + j] = v; });
+    }
+  }
 }
 
 // b = M f (or f itself when it is already a load), per (element, node)
@@ -665,11 +748,17 @@ __global__ void __launch_bounds__(NT) reconstruct_kernel(int n, double tau0, int
   for (int i = tid; i < D * NV; i += NT) q[T * D * NV + i] = sQ[i];
 }
 
-// Local recovery of the IPDG family, one workgroup per element:
-// u = X Lambda + L^-1 b, then q_c = -kappa d_c u at the nodes (each
-// component of grad u lies in Q^k, so its nodal values represent it).
+// Local recovery of the IPDG family and of RT-H, one workgroup per element:
+// u = X Lambda + Y b (IPDG: X = L^-1 R, Y = L^-1; RT-H: X = -Luq Fr,
+// Y = Luu), then for IPDG q_c = -kappa d_c u at the nodes (each component
+// of grad u lies in Q^k, so its nodal values represent it), for RT-H
+// elements (code rt_code in mask, or all when mask is null and Xq is given)
+// the flux field at the nodes, Xq Lambda + Yq b.
 template <int D, int K, int NT>
-__global__ void __launch_bounds__(NT) ipdg_reconstruct_kernel(int n, int nq, const double* __restrict__ kqp,
+__global__ void __launch_bounds__(NT) ipdg_reconstruct_kernel(int n, int nq, const int* __restrict__ mask, int rt_code,
+                                                              const double* __restrict__ Xq,
+                                                              const double* __restrict__ Yq,
+                                                              const double* __restrict__ kqp,
                                                               const double* __restrict__ Dnode,
                                                               const double* __restrict__ lam,
                                                               const double* __restrict__ gdir,
@@ -709,11 +798,18 @@ __global__ void __launch_bounds__(NT) ipdg_reconstruct_kernel(int n, int nq, con
   }
   __syncthreads();
   const double kap = kqp[T * nq];
+  const bool rt = Xq && (!mask || mask[T] == rt_code);
   for (int idx = tid; idx < D * NV; idx += NT) {
-    const int c = idx / NV, a = idx % NV;
     double s = 0.0;
-    for (int j = 0; j < NV; ++j) s += Dnode[(c * NV + a) * NV + j] * sU[j];
-    q[T * D * NV + idx] = -kap * s;
+    if (rt) {  // RT-H element: the flux field at the nodes, Xq Lambda + Yq b
+      for (int j = 0; j < NL; ++j) s += Xq[(T * D * NV + idx) * NL + j] * sL[j];
+      for (int j = 0; j < NV; ++j) s += Yq[(T * D * NV + idx) * NV + j] * b[T * NV + j];
+      q[T * D * NV + idx] = s;
+    } else {
+      const int c = idx / NV, a = idx % NV;
+      for (int j = 0; j < NV; ++j) s += Dnode[(c * NV + a) * NV + j] * sU[j];
+      q[T * D * NV + idx] = -kap * s;
+    }
   }
   for (int i = tid; i < NV; i += NT) u[T * NV + i] = sU[i];
 }
@@ -794,22 +890,41 @@ void launch_element_dtn(int d, int k, long nelem, double tau, int tau_kappa, con
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_ipdg_dtn(int d, int k, long nelem, double tau, int tau_kappa, double sf, const RefDevice& rd,
-                     const double* kqp,
-                     int nq, double* Aelem, double* W, double* X, double* Linv, hipStream_t st) {
+void launch_ipdg_dtn(int d, int k, long nelem, const int* mask, int code, double tau, int tau_kappa, double sf,
+                     const RefDevice& rd, const double* kqp, int nq, double* Aelem, double* W, double* X,
+                     double* Linv, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
     constexpr int NT = 256;
-    hipLaunchKernelGGL((ipdg_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau, tau_kappa,
-                       sf, nq, kqp,
+    hipLaunchKernelGGL((ipdg_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, mask, code, tau,
+                       tau_kappa, sf, nq, kqp,
                        rd.Kst, rd.Nn, rd.Dn, rd.G, rd.E, rd.H, Aelem, W, X, Linv);
   });
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const double* lam,
-                             const double* gdir, const double* f, int is_load, const double* X, const double* Linv,
-                             double* b, double* u, double* q, hipStream_t st) {
+void launch_rt_dtn(int k, long nelem, const int* mask, int code, const RefDevice& rd, const double* kqp,
+                   double* Aelem, double* W, double* Xr, double* Luu, double* Xq, double* Yq, hipStream_t st) {
+  auto go = [&](auto K_) {
+    constexpr int K = decltype(K_)::value;
+    constexpr int NT = 256;
+    hipLaunchKernelGGL((rt_dtn_kernel<K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, mask, code, rd.Wq, kqp,
+                       rd.Vq, rd.Bd, rd.Fr, rd.Vnode, Aelem, W, Xr, Luu, Xq, Yq);
+  };
+  switch (k) {
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: throw HipError{hipErrorInvalidValue, "RT-H: k in 1..4"};
+  }
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const int* mask,
+                             int rt_code, const double* Xq, const double* Yq, const double* lam, const double* gdir,
+                             const double* f, int is_load, const double* X, const double* Linv, double* b, double* u,
+                             double* q, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
     using Dm = Dims<D, K>;
@@ -819,8 +934,8 @@ void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const dou
     hipLaunchKernelGGL((load_vec_kernel<Dm::NV>), dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, nelem,
                        rd.M, f, is_load, b);
     constexpr int NT = 64;
-    hipLaunchKernelGGL((ipdg_reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, nq, kqp,
-                       rd.Dnode, lam, gdir, b, X, Linv, u, q);
+    hipLaunchKernelGGL((ipdg_reconstruct_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, n, nq, mask,
+                       rt_code, Xq, Yq, kqp, rd.Dnode, lam, gdir, b, X, Linv, u, q);
   });
   HDG_CHECK(hipGetLastError());
 }

@@ -101,7 +101,15 @@ struct RefElement {
   std::vector<double> Nn;              // [nv][nv]:   <phi_j, grad phi_i . n> on the element boundary
   std::vector<double> Dn;              // [nv][nl]:   <mu_m, grad phi_i . n>
   std::vector<double> Dnode;           // [d][nv][nv]: d_c phi_j at node a
+  // hybridized Raviart-Thomas forms (d = 2; build_rt): nqc coefficients per
+  // velocity component, nqv = 2 nqc
+  int nqc = 0, nqv = 0;
+  std::vector<double> Vq;              // [2][nq][nqc]: component basis at the Gauss points
+  std::vector<double> Bd;              // [nqv][nv]:   (phi_j, div v_I)
+  std::vector<double> Fr;              // [nqv][nl]:   <mu_m, v_I . n>
+  std::vector<double> Vnode;           // [2][nv][nqc]: component basis at the scalar's nodes
   void build(int d, int k, double h);
+  void build_rt();
 };
 
 void gll_points(int k, std::vector<double>& x);                       // k+1 points on [0,1]
@@ -112,6 +120,7 @@ struct RefDevice {
   double *Phi = nullptr, *Wq = nullptr, *B = nullptr, *F = nullptr, *G = nullptr, *E = nullptr,
          *H = nullptr, *M = nullptr, *Jp = nullptr;
   double *Kst = nullptr, *Nn = nullptr, *Dn = nullptr, *Dnode = nullptr;  // IPDG handles only
+  double *Vq = nullptr, *Bd = nullptr, *Fr = nullptr, *Vnode = nullptr;    // RT-H handles only
 };
 
 // ---------------------------------------------------------------------------
@@ -186,11 +195,20 @@ void launch_reconstruct(int d, int k, int n, double tau, int tau_kappa, const Re
                         const double* Minv, double* b, double* u, double* q, hipStream_t st);
 // hybridized IPDG family (eq. IPG_H): A^e, the load map W = L^-T C^T and,
 // when X / Linv are given, the recovery blocks X = L^-1 R and L^-1
-void launch_ipdg_dtn(int d, int k, long nelem, double tau, int tau_kappa, double sf, const RefDevice& rd,
-                     const double* kqp, int nq, double* Aelem, double* W, double* X, double* Linv, hipStream_t st);
-void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const double* lam,
-                             const double* gdir, const double* f, int is_load, const double* X, const double* Linv,
-                             double* b, double* u, double* q, hipStream_t st);
+// (mask: per-element scheme codes, only elements with `code` formed; null: all)
+void launch_ipdg_dtn(int d, int k, long nelem, const int* mask, int code, double tau, int tau_kappa, double sf,
+                     const RefDevice& rd, const double* kqp, int nq, double* Aelem, double* W, double* X,
+                     double* Linv, hipStream_t st);
+// hybridized Raviart-Thomas (d = 2, k <= 4): A^e, the load map, and when Xr
+// is given the recovery blocks (Xr, Luu for u; Xq, Yq for the nodal flux)
+void launch_rt_dtn(int k, long nelem, const int* mask, int code, const RefDevice& rd, const double* kqp,
+                   double* Aelem, double* W, double* Xr, double* Luu, double* Xq, double* Yq, hipStream_t st);
+// IPDG and RT-H recovery (RT-H elements: mask code rt_code, or all when mask
+// is null and Xq is given)
+void launch_ipdg_reconstruct(int d, int k, int n, const RefDevice& rd, const double* kqp, int nq, const int* mask,
+                             int rt_code, const double* Xq, const double* Yq, const double* lam, const double* gdir,
+                             const double* f, int is_load, const double* X, const double* Linv, double* b, double* u,
+                             double* q, hipStream_t st);
 void launch_grad(int d, int k, long nelem, const RefDevice& rd, const double* kqp, const double* q,
                  const double* qs, double* grad, hipStream_t st);
 void launch_mass(int d, int k, long nelem, const RefDevice& rd, const double* u, double* out, hipStream_t st);

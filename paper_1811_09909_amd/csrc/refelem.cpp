@@ -270,4 +270,95 @@ void RefElement::build(int d_, int k_, double h_) {
     }
 }
 
+// Raviart-Thomas data of the hybridized mixed method (eqs. mixed_local1/2)
+// on squares (d = 2): RT_k = Q_{k+1,k} x Q_{k,k+1}, each component nodal at
+// tensor GLL points of degree k+1 along its own direction and k across it
+// (x fastest), velocity coefficients ordered [x component, y component].
+void RefElement::build_rt() {
+  if (d != 2) throw std::invalid_argument("RT-H is two-dimensional");
+  const int p1 = k + 1, q1 = k + 2;
+  std::vector<double> ghi;
+  gll_points(k + 1, ghi);
+  nqc = (k + 2) * (k + 1);
+  nqv = 2 * nqc;
+  // 1D tables: degree k+1 basis (k+2 functions) and degree k basis (k+1)
+  std::vector<double> lhi((size_t)(k + 2) * q1), dlhi((size_t)(k + 2) * q1), llo((size_t)p1 * q1);
+  std::vector<double> hiend((size_t)(k + 2) * 2), hinode((size_t)(k + 2) * p1);
+  for (int i = 0; i < k + 2; ++i) {
+    for (int q = 0; q < q1; ++q) {
+      lhi[i * q1 + q] = (double)lagrange_value(ghi, i, gauss[q]);
+      dlhi[i * q1 + q] = (double)(lagrange_deriv(ghi, i, gauss[q]) / h);
+    }
+    hiend[i * 2 + 0] = i == 0 ? 1.0 : 0.0;
+    hiend[i * 2 + 1] = i == k + 1 ? 1.0 : 0.0;
+    for (int a = 0; a < p1; ++a) hinode[i * p1 + a] = (double)lagrange_value(ghi, i, gll[a]);
+  }
+  for (int i = 0; i < p1; ++i)
+    for (int q = 0; q < q1; ++q) llo[i * q1 + q] = (double)lagrange_value(gll, i, gauss[q]);
+  // basis index I of component c -> (a_0, a_1), degree k+1 along c
+  auto split = [&](int c, int I, int* a) {
+    const int n0 = c == 0 ? k + 2 : p1;
+    a[0] = I % n0;
+    a[1] = I / n0;
+  };
+  Vq.assign((size_t)2 * nq * nqc, 0.0);
+  std::vector<double> Dq((size_t)2 * nq * nqc, 0.0);
+  for (int c = 0; c < 2; ++c)
+    for (int Q = 0; Q < nq; ++Q) {
+      const int qd[2] = {Q % q1, Q / q1};
+      for (int I = 0; I < nqc; ++I) {
+        int a[2];
+        split(c, I, a);
+        double v = 1.0, g = 1.0;
+        for (int t = 0; t < 2; ++t) {
+          v *= t == c ? lhi[a[t] * q1 + qd[t]] : llo[a[t] * q1 + qd[t]];
+          g *= t == c ? dlhi[a[t] * q1 + qd[t]] : llo[a[t] * q1 + qd[t]];
+        }
+        Vq[((size_t)c * nq + Q) * nqc + I] = v;
+        Dq[((size_t)c * nq + Q) * nqc + I] = g;
+      }
+    }
+  // Bd[c*nqc + I][j] = (phi_j, div v_I)
+  Bd.assign((size_t)nqv * nv, 0.0);
+  for (int c = 0; c < 2; ++c)
+    for (int I = 0; I < nqc; ++I)
+      for (int j = 0; j < nv; ++j) {
+        double sum = 0.0;
+        for (int Q = 0; Q < nq; ++Q) sum += Wq[Q] * Dq[((size_t)c * nq + Q) * nqc + I] * Phi[(size_t)Q * nv + j];
+        Bd[((size_t)c * nqc + I) * nv + j] = sum;
+      }
+  // Fr[c*nqc + I][s*ne + m] = <mu_m, v_I . n> on face slot s = 2 cc + side
+  Fr.assign((size_t)nqv * nl, 0.0);
+  for (int s = 0; s < nf; ++s) {
+    const int cc = s / 2, side = s % 2, tg = 1 - cc;
+    const double nrm = side ? 1.0 : -1.0;
+    for (int I = 0; I < nqc; ++I) {
+      int a[2];
+      split(cc, I, a);
+      for (int m = 0; m < ne; ++m) {
+        double sum = 0.0;
+        for (int P = 0; P < q1; ++P) {
+          const double v = hiend[a[cc] * 2 + side] * llo[a[tg] * q1 + P];
+          const double mu = (double)lagrange_value(gll, m, gauss[P]);
+          sum += h * gw[P] * v * mu;
+        }
+        Fr[((size_t)cc * nqc + I) * nl + s * ne + m] = nrm * sum;
+      }
+    }
+  }
+  // Vnode[c][a][I] = v_{c,I} at the scalar's node a
+  Vnode.assign((size_t)2 * nv * nqc, 0.0);
+  for (int c = 0; c < 2; ++c)
+    for (int A = 0; A < nv; ++A) {
+      const int na[2] = {A % p1, A / p1};
+      for (int I = 0; I < nqc; ++I) {
+        int a[2];
+        split(c, I, a);
+        double v = 1.0;
+        for (int t = 0; t < 2; ++t) v *= t == c ? hinode[a[t] * p1 + na[t]] : (a[t] == na[t] ? 1.0 : 0.0);
+        Vnode[((size_t)c * nv + A) * nqc + I] = v;
+      }
+    }
+}
+
 }  // namespace hdg

@@ -463,9 +463,13 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__
     for (int r = 0; r < RI; ++r) {
       const int i = c * RI + r;
       if (i < NI) {
+        // the whole row first: its loads stay in flight together
+        M v[NI];
+#pragma unroll
+        for (int j = 0; j < NI; ++j) v[j] = Ab[aos_off<M>(0, 0, i * NI + j)];
         A s = A(0);
 #pragma unroll
-        for (int j = 0; j < NI; ++j) s += A(Ab[aos_off<M>(0, 0, i * NI + j)]) * rI[j];
+        for (int j = 0; j < NI; ++j) s += A(v[j]) * rI[j];
         const long f = macro_iface<D>(m, i / NC, n) * NC + i % NC;
         e[f] = T(A(e[f]) + s);
       }
@@ -477,9 +481,12 @@ __global__ void __launch_bounds__(256) hcorr_kernel(int n, const M* __restrict__
     for (int r = 0; r < RJ; ++r) {
       const int J = c * RJ + r;
       if (J < NCL) {
+        M v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = Pb[aos_off<M>(0, 0, i * NCL + J)];
         A s = A(0);
 #pragma unroll
-        for (int i = 0; i < NI; ++i) s += A(Pb[aos_off<M>(0, 0, i * NCL + J)]) * rI[i];
+        for (int i = 0; i < NI; ++i) s += A(v[i]) * rI[i];
         cb[Mi * NCL + J] = T(s);
       }
     }
@@ -579,9 +586,12 @@ __global__ void __launch_bounds__(256) hprolong_kernel(int n, long nbm, const M*
       const int i = c * RI + r;
       if (i < NI) {
         const long f = macro_iface<D>(m, i / NC, n) * NC + i % NC;
+        M v[NCL];
+#pragma unroll
+        for (int J = 0; J < NCL; ++J) v[J] = Pb[aos_off<M>(0, 0, i * NCL + J)];
         A s = e[f];
 #pragma unroll
-        for (int J = 0; J < NCL; ++J) s += A(Pb[aos_off<M>(0, 0, i * NCL + J)]) * cv[J];
+        for (int J = 0; J < NCL; ++J) s += A(v[J]) * cv[J];
         e[f] = T(s);
       }
     }

@@ -24,14 +24,16 @@ class Problem:
     """One trace problem on the unit box (d = 2 or 3, n^d elements, Q^k).
 
     ``scheme``: "hdg" (eqs. HDG, HDG_flux) or one of the hybridized IPDG
-    family "sipg", "iipg", "nipg" (eq. IPG_H, s_f = 1, 0, -1).
+    family "sipg", "iipg", "nipg" (eq. IPG_H, s_f = 1, 0, -1), or "rt"
+    (hybridized Raviart-Thomas, 2D).  ``scheme_of_element``: one scheme name
+    per element instead (multinumerics; "sipg", "iipg", "nipg" or "rt").
     ``tau_kappa``: element T is stabilized with tau * kappa_T (kappa per
     element).
     ``kappa``: per element [n^d] or, for HDG, at the (k+2)^d Gauss points of
     every element [n^d, (k+2)^d] (then ``kappa_kind='qp'``)."""
 
     def __init__(self, d, n, k, kappa, tau=1.0, kappa_kind="element", store_recovery=True, device="cuda",
-                 scheme="hdg", tau_kappa=False):
+                 scheme="hdg", tau_kappa=False, scheme_of_element=None):
         self.lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the HDG library needs a GPU (torch.cuda.is_available() is False)")
@@ -45,10 +47,18 @@ class Problem:
         self.stream = torch.cuda.current_stream(self.device)
         mesh = L.Mesh(d, n)
         h = ctypes.c_void_p()
-        code = L.SCHEMES[scheme] | (L.SCHEME_TAU_KAPPA if tau_kappa else 0)
-        L.check(self.lib.hdg_setup_scheme(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, code,
-                                          1 if store_recovery else 0, ctypes.c_void_p(self.stream.cuda_stream),
-                                          ctypes.byref(h)), "hdg_setup_scheme")
+        if scheme_of_element is not None:
+            codes = torch.tensor([L.SCHEMES[c] for c in scheme_of_element], dtype=torch.int32, device=self.device)
+            self.scheme = "multi"
+            L.check(self.lib.hdg_setup_multi(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, _vp(codes),
+                                             L.SCHEME_TAU_KAPPA if tau_kappa else 0, 1 if store_recovery else 0,
+                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                    "hdg_setup_multi")
+        else:
+            code = L.SCHEMES[scheme] | (L.SCHEME_TAU_KAPPA if tau_kappa else 0)
+            L.check(self.lib.hdg_setup_scheme(ctypes.byref(mesh), k, self.tau, _vp(kap), self.kind, code,
+                                              1 if store_recovery else 0, ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(h)), "hdg_setup_scheme")
         self.h = h
         self.nT = self.query(L.Q_NT)
         self.nlam = self.query(L.Q_NLAMBDA)

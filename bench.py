@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--n3d", type=int, default=32)
     ap.add_argument("--steps3d", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
-    ap.add_argument("--no-ipdg", action="store_true", help="skip the NIPG-H (hybridized IPDG) legs")
+    ap.add_argument("--no-ipdg", action="store_true", help="skip the NIPG-H and multinumerics legs")
     ap.add_argument("--no-errors", action="store_true", help="skip the solve to the FP64 floor (error report)")
     ap.add_argument("--ref-tol", type=float, default=1e-13,
                     help="tolerance of the FP64 reference solve (stops at its floor if not reachable)")
@@ -394,6 +394,45 @@ def ipdg_legs(args):
     return out
 
 
+def multinumerics_legs(args):
+    """Multinumerics (RT-H outside a disk, NIPG-H inside, Example VI's
+    coefficient) on the headline mesh at k = 1: element maps timed alone,
+    then GMRES + V-cycle to 1e-10 in FP64 and with the FP32 cycle."""
+    import torch
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+    n, k = args.n, 1
+    wl = inputs.multinumerics2d(n, k)
+    kap = torch.as_tensor(wl.kappa, device="cuda")
+    P = Problem(2, n, k, kap, tau=wl.tau, tau_kappa=True, scheme_of_element=wl.schemes, store_recovery=False)
+    f = torch.as_tensor(wl.f, device="cuda")
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.update_kappa(kap)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    out = {"workload": wl.name, "trace_dofs": P.nlam, "rt_elements": sum(s == "rt" for s in wl.schemes),
+           "element_maps_ms": round(1e3 * median(ts), 3)}
+    lams = {}
+    for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
+        P.build(sweeps=args.sweeps, growth=args.growth, local_corr=L.LC_PRE, precision=prec,
+                method=L.METHOD_GMRES, max_it=200, coarse_n=args.coarse_n)
+        progress(f"multinumerics {nm} leg: n={n} k={k}, {P.nlam} trace DOFs")
+        times, lam, infos = timed_solves(P, f, args.tol, args.steps, 1)
+        ms = 1e3 * median(times)
+        progress(f"multinumerics {nm}: {ms:.1f} ms/solve, {infos[-1]['iters']} iterations")
+        lams[nm] = lam
+        out[nm] = {"value": round(P.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos)}
+    out["lambda_mixed_vs_fp64"] = rel(lams["mixed"], lams["fp64"])
+    out["mixed_over_fp64"] = round(out["mixed"]["value"] / out["fp64"]["value"], 3)
+    P.close()
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_probe:
@@ -534,6 +573,12 @@ def main():
             ipdg = ipdg_legs(args)
         except Exception as e:  # reported; the headline stands on its own
             ipdg = {"error": str(e)[:300]}
+    multi = None
+    if not args.no_ipdg:
+        try:
+            multi = multinumerics_legs(args)
+        except Exception as e:  # reported; the headline stands on its own
+            multi = {"error": str(e)[:300]}
     batch = None
     if not args.no_batched:
         progress("batched leg")
@@ -568,7 +613,7 @@ def main():
                    "setup_ms": round(1e3 * t_setup, 2), "build_ms_mixed": round(1e3 * resmx["build_s"], 2),
                    "reconstruct_ms": round(1e3 * t_rec, 3),
                    "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1),
-                   "errors": errors, "diffusion3d": cube, "ipdg2d": ipdg, "batched": batch},
+                   "errors": errors, "diffusion3d": cube, "ipdg2d": ipdg, "multinumerics2d": multi, "batched": batch},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

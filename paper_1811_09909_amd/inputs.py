@@ -23,6 +23,10 @@ Workloads (all on the unit box, tau = 1, zero Dirichlet data):
                       (the coefficient of Example III on the unit square),
                       f = -kappa_T lap u for u = x y exp(x^2 y^3) (Example I),
                       zero Dirichlet data; stabilization kappa_T (p+1)(p+2)/h_min.
+* ``multinumerics2d`` -- Example VI's coefficient 1 + 0.5 sin(4 pi x) cos(3 pi y)
+                      at element centres, f = 1, zero Dirichlet data; NIPG-H on
+                      the elements whose centre lies within 0.3 of
+                      (0.45, 0.55), RT-H on the others.
 """
 import numpy as np
 
@@ -130,3 +134,14 @@ def ipdg2d(n=512, k=4):
 
     return Workload(d=2, n=n, k=k, tau=(k + 1) * (k + 2) * n / np.sqrt(2.0), kappa=kappa, f=f,
                     name=f"ipdg2d NIPG-H n={n} k={k} kappa=1+0.5sin(2pi x)cos(3pi y) tau=kappa(p+1)(p+2)/h_min")
+
+
+def multinumerics2d(n=512, k=1):
+    c = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")  # element index x + n y
+    kappa = (1.0 + 0.5 * np.sin(4 * np.pi * X) * np.cos(3 * np.pi * Y)).ravel()
+    use_rt = ((X - 0.45) ** 2 + (Y - 0.55) ** 2 > 0.09).ravel()
+    schemes = ["rt" if r else "nipg" for r in use_rt]
+    return Workload(d=2, n=n, k=k, tau=(k + 1) * (k + 2) * n / np.sqrt(2.0), kappa=kappa, schemes=schemes,
+                    f=np.ones((n * n, (k + 1) ** 2)),
+                    name=f"multinumerics2d RT-H + NIPG-H n={n} k={k} kappa=1+0.5sin(4pi x)cos(3pi y) f=1")

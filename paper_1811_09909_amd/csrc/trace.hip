@@ -94,6 +94,161 @@ __device__ inline void face_finish(long F, const acc_t<T>* acc, const M* __restr
   }
 }
 
+// The trace apply of face-major levels with CH lanes per face (3D, k = 3:
+// 3,072 block entries per face, and only 95,232 faces at 32^3, so one lane
+// per face leaves under two waves per SIMD to hide the memory latency).
+// Wave w of a workgroup takes rows w*RA .. of the 64 faces of the group (one
+// per lane, so every block load of a wave is one contiguous 512-byte
+// segment), loads a slot's rows into registers before summing them, and
+// sums each row in the order of the one-lane form (face_acc), so results
+// match it bit for bit.  Modes that need a whole face's residual (the
+// block-Jacobi update, the p-restriction and its coarse first step) pass it
+// through LDS.  Each workgroup walks the face groups blockIdx.x, +gridDim.x,
+// ... of its right-hand side (blockIdx.y) and writes one partial sum.
+template <int D, int NE, typename T, int MODE, typename M, int CH>
+__global__ void __launch_bounds__(256) apply_mc_kernel(int n, const M* __restrict__ Af, const M* __restrict__ Dinv,
+                                                       const T* __restrict__ x, const T* __restrict__ bvec,
+                                                       T* __restrict__ y, const double* __restrict__ Jp,
+                                                       T* __restrict__ rc, float* __restrict__ y32,
+                                                       double* __restrict__ partials) {
+  static_assert(CH * 64 == 256 && NE % CH == 0, "one wave per chunk of rows");
+  constexpr bool RED = (MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM || MODE == APPLY_SWEEP_DOT);
+  constexpr int NC = 1 << (D - 1);
+  constexpr int RA = NE / CH, RC = (NC + CH - 1) / CH;
+  constexpr int NL = 2 * D * NE;
+  constexpr long S = vpad<M>(NL * NE);
+  using A = acc_t<T>;
+  __shared__ A sres[64][NE + 1];
+  __shared__ A srcv[64][NC + 1];
+  const int rhs = blockIdx.y;
+  {
+    const long sN = trace_len<D>(n, NE), sC = trace_len<D>(n, NC);
+    x += rhs * sN;
+    bvec = off(bvec, rhs * sN);
+    y = off(y, rhs * (MODE == APPLY_RES_PRESTRICT ? sC : sN));
+    rc = off(rc, rhs * sC);
+    y32 = off(y32, rhs * sN);
+    if (MODE == APPLY_SWEEP_DOT) Jp += rhs * sN;
+  }
+  const long nface = D * nface_dir<D>(n);
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  double part = 0.0;
+  for (long fg = blockIdx.x; fg * 64 < nface; fg += gridDim.x) {
+    const long F = fg * 64 + lane;
+    const bool live = F < nface;
+    A acc[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) acc[r] = A(0);
+    if (live) {
+      int g[3] = {0, 0, 0};
+      const int cn = decode_face<D>(F, n, g);
+      const M* Mbase = Af + aos_item<M>(F, 2 * S);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        int e[3] = {g[0], g[1], g[2]};
+        e[cn] = g[cn] - 1 + side;
+        const M* Mx = Mbase + side * S * LANES;
+#pragma unroll
+        for (int sl = 0; sl < 2 * D; ++sl) {
+          const int cc = sl / 2, sd = sl % 2;
+          const int p = e[cc] + sd;
+          if (p == 0 || p == n) continue;
+          int fgc[3] = {e[0], e[1], e[2]};
+          fgc[cc] = p;
+          const T* xf = x + face_id<D>(cc, fgc, n) * NE;
+          M v[NE][RA];
+#pragma unroll
+          for (int bb = 0; bb < NE; ++bb)
+#pragma unroll
+            for (int r = 0; r < RA; ++r) v[bb][r] = Mx[aos_off<M>(0, 0, (sl * NE + bb) * NE + c * RA + r)];
+          A xs[NE];
+#pragma unroll
+          for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
+#pragma unroll
+          for (int bb = 0; bb < NE; ++bb)
+#pragma unroll
+            for (int r = 0; r < RA; ++r) acc[r] += A(v[bb][r]) * xs[bb];
+        }
+      }
+    }
+    if (MODE == APPLY_Y || MODE == APPLY_RES || MODE == APPLY_Y_DOT || MODE == APPLY_RES_NORM) {
+      if (live)
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+          const long i = F * NE + c * RA + r;
+          if (MODE == APPLY_Y) {
+            y[i] = T(acc[r]);
+          } else if (MODE == APPLY_RES) {
+            y[i] = T(A(bvec[i]) - acc[r]);
+          } else if (MODE == APPLY_Y_DOT) {
+            y[i] = T(acc[r]);
+            part += (double)x[i] * (double)T(acc[r]);
+          } else {
+            const T vv = T(A(bvec[i]) - acc[r]);
+            y[i] = vv;
+            if (y32) y32[i] = (float)vv;
+            part += (double)vv * (double)vv;
+          }
+        }
+    } else {
+      // the face's whole residual through LDS
+      if (live)
+#pragma unroll
+        for (int r = 0; r < RA; ++r) sres[lane][c * RA + r] = A(bvec[F * NE + c * RA + r]) - acc[r];
+      __syncthreads();
+      if (MODE == APPLY_SWEEP || MODE == APPLY_SWEEP_DOT) {
+        if (live) {
+          const M* Db = Dinv + aos_item<M>(F, vpad<M>(NE * NE));
+#pragma unroll
+          for (int r = 0; r < RA; ++r) {
+            const int a = c * RA + r;
+            M dv[NE];
+#pragma unroll
+            for (int bb = 0; bb < NE; ++bb) dv[bb] = Db[aos_off<M>(0, 0, a * NE + bb)];
+            A s = A(x[F * NE + a]);
+#pragma unroll
+            for (int bb = 0; bb < NE; ++bb) s += A(dv[bb]) * sres[lane][bb];
+            y[F * NE + a] = T(s);
+            if (MODE == APPLY_SWEEP_DOT) part += Jp[F * NE + a] * (double)T(s);
+          }
+        }
+      } else {  // APPLY_RES_PRESTRICT: J_N^T res, then the coarse first step
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          const int vv = c * RC + r;
+          if (live && vv < NC) {
+            A s = A(0);
+#pragma unroll
+            for (int a = 0; a < NE; ++a) s += A(Jp[a * NC + vv]) * sres[lane][a];
+            rc[F * NC + vv] = T(s);
+            srcv[lane][vv] = A(T(s));
+          }
+        }
+        if (y) {
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < RC; ++r) {
+            const int vv = c * RC + r;
+            if (live && vv < NC) {
+              const M* Db = Dinv + aos_item<M>(F, vpad<M>(NC * NC));
+              A s = A(0);
+#pragma unroll
+              for (int bb = 0; bb < NC; ++bb) s += A(Db[aos_off<M>(0, 0, vv * NC + bb)]) * srcv[lane][bb];
+              y[F * NC + vv] = T(s);
+            }
+          }
+        }
+      }
+      __syncthreads();  // sres / srcv are reused by the next face group
+    }
+  }
+  if constexpr (RED) {
+    __shared__ double sh[4];
+    const double sum = block_sum_t<256>(part, sh);
+    if (threadIdx.x == 0) partials[(long)rhs * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
 // ZS: the level is stored element-major; Af then points to the per-element
 // products z of the first phase (elem_apply_kernel) and each face only adds
 // its two elements' rows.  M: storage type of the operator blocks (T, or
@@ -152,6 +307,38 @@ __global__ void jacobi0_kernel(long nface, int nrhs, const M* __restrict__ Dinv,
   r += rhs * nface * NE;
   e += rhs * nface * NE;
   jacobi0_item<NE, T, DSYM, M>(F, Dinv, r, e);
+}
+
+// e = Dinv r with CH lanes per face (as apply_mc_kernel: wave w takes rows
+// w*RA .. of the 64 faces of its group, row sums in the order of
+// jacobi0_item)
+template <int NE, typename T, typename M, int CH>
+__global__ void __launch_bounds__(256) jacobi0_mc_kernel(long nface, const M* __restrict__ Dinv,
+                                                         const T* __restrict__ r, T* __restrict__ e) {
+  constexpr int RA = NE / CH;
+  using A = acc_t<T>;
+  r += blockIdx.y * nface * NE;
+  e += blockIdx.y * nface * NE;
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  for (long fg = blockIdx.x; fg * 64 < nface; fg += gridDim.x) {
+    const long F = fg * 64 + lane;
+    if (F >= nface) continue;
+    A rv[NE];
+#pragma unroll
+    for (int b = 0; b < NE; ++b) rv[b] = r[F * NE + b];
+    const M* Db = Dinv + aos_item<M>(F, vpad<M>(NE * NE));
+#pragma unroll
+    for (int k = 0; k < RA; ++k) {
+      const int a = c * RA + k;
+      M dv[NE];
+#pragma unroll
+      for (int b = 0; b < NE; ++b) dv[b] = Db[aos_off<M>(0, 0, a * NE + b)];
+      A s = A(0);
+#pragma unroll
+      for (int b = 0; b < NE; ++b) s += A(dv[b]) * rv[b];
+      e[F * NE + a] = T(s);
+    }
+  }
 }
 
 // One colour pass of multicolour point symmetric Gauss-Seidel (the LU-SGS
@@ -812,6 +999,13 @@ inline unsigned xcd_rhs_grid(long nb, int nrhs) {
 
 // grid of the XCD-aware face launches (see xcd_face): 8 chunks of C blocks
 // per normal direction
+// workgroups of the multi-lane apply: one per group of 64 faces, at most
+// MAX_RED_BLOCKS (the workgroups then walk several groups)
+inline unsigned mc_grid(long nface) {
+  const long g = (nface + 63) / 64;
+  return (unsigned)(g < MAX_RED_BLOCKS ? g : MAX_RED_BLOCKS);
+}
+
 inline unsigned xcd_grid(int d, int n) {
   long nfd = n - 1;
   for (int a = 1; a < d; ++a) nfd *= n;
@@ -965,6 +1159,38 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
     }
     return;
   }
+  if (!L.packed && L.d == 3 && L.ne == 16) {  // face-major 3D k = 3: four lanes per face
+    const unsigned g = mc_grid(L.nface);
+    if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM || mode == APPLY_SWEEP_DOT) && (long)g > red->row)
+      throw HipError{hipErrorInvalidValue, "trace apply: too many partial sums"};
+#define HDG_MC(MM)                                                                                                 \
+  hipLaunchKernelGGL((apply_mc_kernel<3, 16, T, MM, M, 4>), dim3(g, nrhs), dim3(256), 0, st, L.n, Af, Dv, x, b, y,   \
+                     Jp, rc, y32, partials)
+    switch (mode) {
+      case APPLY_Y: HDG_MC(APPLY_Y); break;
+      case APPLY_RES: HDG_MC(APPLY_RES); break;
+      case APPLY_SWEEP: HDG_MC(APPLY_SWEEP); break;
+      case APPLY_RES_PRESTRICT: HDG_MC(APPLY_RES_PRESTRICT); break;
+      case APPLY_Y_DOT: HDG_MC(APPLY_Y_DOT); break;
+      case APPLY_RES_NORM: HDG_MC(APPLY_RES_NORM); break;
+      case APPLY_SWEEP_DOT: HDG_MC(APPLY_SWEEP_DOT); break;
+      default: throw HipError{hipErrorInvalidValue, "apply mode"};
+    }
+#undef HDG_MC
+    HDG_CHECK(hipGetLastError());
+    if (mode == APPLY_SWEEP_DOT) {
+      if (!(red && nparts))
+        throw HipError{hipErrorInvalidValue, "sweep with dot product: partials are finished by the caller"};
+      *nparts = (int)g;
+    }
+    if (red && (mode == APPLY_Y_DOT || mode == APPLY_RES_NORM)) {
+      if (nparts)
+        *nparts = (int)g;
+      else
+        blas_finalize((int)g, 1, mode == APPLY_Y_DOT ? FIN_ALPHA : FIN_RNORM, nullptr, *red, st, nrhs);
+    }
+    return;
+  }
   const T* Zs = nullptr;
   if constexpr (std::is_same_v<T, M>) {
     if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
@@ -1022,6 +1248,12 @@ void launch_res_prestrict(const Level& L, const Level& C, const T* x, const T* b
     launch_strips<T, APPLY_RES_PRESTRICT>(L, Dc, x, b, ec, Jp, rc, nullptr, nullptr, st, nrhs);
     return;
   }
+  if (!L.packed && L.d == 3 && L.ne == 16) {
+    hipLaunchKernelGGL((apply_mc_kernel<3, 16, T, APPLY_RES_PRESTRICT, T, 4>), dim3(mc_grid(L.nface), nrhs), dim3(256),
+                       0, st, L.n, Af, Dc, x, b, ec, Jp, rc, nullptr, nullptr);
+    HDG_CHECK(hipGetLastError());
+    return;
+  }
   if (L.packed) launch_elem_phase<T>(L, x, st, nrhs);
   const T* Zs = L.packed ? (const T*)L.z[sizeof(T) == 8 ? 0 : 1] : nullptr;
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
@@ -1041,6 +1273,12 @@ template <typename T, typename M>
 void launch_jacobi0(const Level& L, const T* r, T* e, hipStream_t st, int nrhs) {
   if (L.nface == 0) return;
   const M* Dv = sizeof(M) == 8 ? (const M*)L.Dinv64 : (const M*)L.Dinv32;
+  if (!L.packed && L.ne == 16) {  // 3D k = 3 face blocks: four lanes per face
+    hipLaunchKernelGGL((jacobi0_mc_kernel<16, T, M, 4>), dim3(mc_grid(L.nface), nrhs), dim3(256), 0, st, L.nface, Dv,
+                       r, e);
+    HDG_CHECK(hipGetLastError());
+    return;
+  }
   dispatch_d_ne(L.d, L.ne, [&](auto D_, auto NE_) {
     constexpr int NE = decltype(NE_)::value;
     const dim3 g(xcd_rhs_grid(nblk(L.nface), nrhs));

@@ -509,6 +509,12 @@ def main():
             r = P.profile_read(mode, pr)
             if r["launches"]:
                 prof[f"{name}_{pn}"] = r
+    # transfer kernels: first h-transition level, and the p-prolongation
+    for t in L.XFER_KINDS:
+        for pr, pn in [(0, "fp64"), (1, "fp32")]:
+            r = P.profile_read(0, pr, transfer=t)
+            if r["launches"]:
+                prof[f"{t}_{pn}"] = r
 
     # errors of the headline solutions against the FP64 reference: the FP64
     # solve driven to its floor (the relative residual it can reach)

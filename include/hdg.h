@@ -317,9 +317,15 @@ hdg_status hdg_level_export(hdg_handle h, int level, double* out);
  * restricted to P1 (J_N^T), 6 the sweep inside CG's preconditioner that also
  * forms the r.z partials; precision HDG_FP64 / HDG_FP32; or kernel = 14 +
  * mode for the finest level of the mixed cycle with FP64 vectors over FP32
- * operator blocks (3D).  Returns the number of launches, their summed duration,
- * and the algorithmic HBM bytes of one launch (stored face-major matrix
- * blocks, face-block inverses and each vector entry read or written once). */
+ * operator blocks (3D); or kernel = 21 + 2 * t + precision for the transfer
+ * kernels of the fused 2D path, t = 0 hpre (interior residual, local
+ * correction, restriction share) / 1 hsum (coarse residual and first coarse
+ * Jacobi step) / 2 hpost (prolongation and post correction), all three on
+ * the first h-transition level, t = 3 the p-prolongation on the finest
+ * level.  Returns the number of launches, their summed duration, and the
+ * algorithmic HBM bytes of one launch (stored face-major matrix blocks,
+ * face-block inverses, macro-element blocks and each vector entry read or
+ * written once). */
 hdg_status hdg_profile_begin(hdg_handle h);
 hdg_status hdg_profile_read(hdg_handle h, int kernel, long long* launches, double* total_ms,
                             double* bytes_per_launch);

@@ -46,6 +46,8 @@ VARIANT_NO_GRAPH, VARIANT_NO_FUSE, VARIANT_NO_TAIL, VARIANT_NO_PACK, VARIANT_NO_
 VARIANT_FP32_VECTORS, VARIANT_FP64_VECTORS = 32, 64
 VARIANT_LANES1, VARIANT_LANES4 = 128, 256
 PROF_F32OPS = 14  # hdg_profile_read: kernel = 14 + mode for FP64 vectors over FP32 operator blocks
+PROF_XFER = 21    # hdg_profile_read: kernel = 21 + 2 t + precision, t = 0 hpre, 1 hsum, 2 hpost, 3 p-prolongation
+XFER_KINDS = ("hpre", "hsum", "hpost", "prolong_p")
 OPT_FIELDS = ("sweeps", "growth", "omega", "local_corr", "precision", "method", "max_it", "restart", "coarse_n",
               "nrhs", "refine_red", "variant", "smoother")
 SMOOTHER_BLOCK_JACOBI, SMOOTHER_JACOBI, SMOOTHER_CHEBYSHEV, SMOOTHER_LUSGS = 0, 1, 2, 3

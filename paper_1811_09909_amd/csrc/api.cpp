@@ -85,7 +85,10 @@ struct hdg_problem {
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   static constexpr int NPROF_F32OPS = 2 * (APPLY_SWEEP_DOT + 1);  // first class of the FP64-vector form
-  static constexpr int NPROF = 3 * (APPLY_SWEEP_DOT + 1);
+  // transfer kernels of the fused 2D path: hpre, hsum, hpost on the first
+  // h-transition level and the p-prolongation on the finest level, FP64/FP32
+  static constexpr int NPROF_XFER = 3 * (APPLY_SWEEP_DOT + 1);
+  static constexpr int NPROF = NPROF_XFER + 8;
   double prof_ms[NPROF] = {};
   long long prof_n[NPROF] = {};
   std::vector<void*> allocs;        // freed in destroy
@@ -229,6 +232,29 @@ template <typename T, typename M>
 int prof_class(int mode) {
   if constexpr (!std::is_same_v<T, M>) return hdg_problem::NPROF_F32OPS + mode;
   return 2 * mode + (sizeof(T) == 8 ? 0 : 1);
+}
+
+// run `launch` between two events of class `cls` when `timed`
+template <class F>
+void timed_launch(hdg_problem* P, bool timed, int cls, F&& launch) {
+  hdg_problem::Pending pd{cls, nullptr, nullptr};
+  if (timed) {
+    pd.a = take_event(P);
+    pd.b = take_event(P);
+    HDG_CHECK(hipEventRecord(pd.a, P->st));
+  }
+  launch();
+  if (timed) {
+    HDG_CHECK(hipEventRecord(pd.b, P->st));
+    P->pending.push_back(pd);
+  }
+}
+
+// first h-transition level (its transfer kernels are the profiled ones)
+int first_h(const hdg_problem* P) {
+  for (size_t i = 0; i < P->L.size(); ++i)
+    if (P->L[i].kind == 1) return (int)i;
+  return -1;
 }
 
 // trace apply on level i; finest-level launches are timed when profiling
@@ -406,19 +432,26 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
       apply<T, M>(P, i, APPLY_RES_PRESTRICT, e, r, nullptr, rc, nr);
       ec = vcycle<T, M>(P, i + 1, rc, nullptr, false, nr);
     }
-    launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st, nr);
+    const bool tp = P->prof_on && nr == 1 && i == 0;
+    timed_launch(P, tp, hdg_problem::NPROF_XFER + 6 + pr,
+                 [&] { launch_prolong_p<T>(L, 1 << (L.d - 1), P->rd.Jp, ec, e, st, nr); });
   } else if (fused) {
     T* cb = (T*)L.cb[pr];
-    launch_hpre<T>(L, r, e, (lc & HDG_LC_PRE) ? 1 : 0, cb, st, nr);
+    const bool tx = P->prof_on && nr == 1 && i == first_h(P);
+    timed_launch(P, tx, hdg_problem::NPROF_XFER + pr,
+                 [&] { launch_hpre<T>(L, r, e, (lc & HDG_LC_PRE) ? 1 : 0, cb, st, nr); });
     const T* ec;
     if (C.kind == 2) {
-      launch_hsum<T>(L, C, r, cb, nullptr, (T*)C.e[pr], st, nr);
+      timed_launch(P, tx, hdg_problem::NPROF_XFER + 2 + pr,
+                   [&] { launch_hsum<T>(L, C, r, cb, nullptr, (T*)C.e[pr], st, nr); });
       ec = (const T*)C.e[pr];
     } else {
-      launch_hsum<T>(L, C, r, cb, rc, (T*)C.e[pr], st, nr);
+      timed_launch(P, tx, hdg_problem::NPROF_XFER + 2 + pr,
+                   [&] { launch_hsum<T>(L, C, r, cb, rc, (T*)C.e[pr], st, nr); });
       ec = vcycle<T>(P, i + 1, rc, nullptr, true, nr);
     }
-    launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st, nr);
+    timed_launch(P, tx, hdg_problem::NPROF_XFER + 4 + pr,
+                 [&] { launch_hpost<T>(L, C, r, ec, e, w, (lc & HDG_LC_POST) ? 1 : 0, st, nr); });
     std::swap(e, w);
   } else {
     apply<T, M>(P, i, APPLY_RES, e, r, w, nullptr, nr);
@@ -2179,6 +2212,37 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   HDG_GUARD_BEGIN
   HDG_CHECK(hipStreamSynchronize(P->st));
   harvest(P);
+  if (kernel >= hdg_problem::NPROF_XFER) {
+    // algorithmic bytes of the transfer kernels: every operator block and
+    // vector entry the kernel must touch, once
+    const int kind = (kernel - hdg_problem::NPROF_XFER) / 2;
+    const double s = ((kernel - hdg_problem::NPROF_XFER) % 2) ? 4.0 : 8.0;
+    double bytes = 0.0;
+    const int fh = first_h(P);
+    if (kind == 3) {  // e += J_N e_c on the finest level: e_c read, e read and written
+      const Level& L0 = P->L[0];
+      bytes = (double)L0.nface * ((1 << (L0.d - 1)) + 2.0 * L0.ne) * s;
+    } else if (fh >= 0) {
+      const Level& L = P->L[fh];
+      const Level& C = P->L[fh + 1];
+      const double nc = 1 << (L.d - 1), nif = L.d * nc, nbf = 2 * L.d * nc;
+      const double ni = L.nI, ncl = L.ncl, nl = L.nl;
+      const double rows = nif * 2.0 * nl * nc;  // the interior faces' rows of both children
+      const bool lpost = (P->opts.local_corr & HDG_LC_POST) != 0;
+      if (kind == 0)  // hpre: residual on I, A_II^-1, restriction block; e, r, e_I, cb
+        bytes = (double)L.nmacro * ((rows + ni * ni + ni * ncl) * s + ((nif + nbf) * nc + 3.0 * ni + ncl) * s);
+      else if (kind == 1)  // hsum: r on the sub-faces, two shares, coarse block inverse, rc and ec
+        bytes = (double)C.nface * ((nc * nc + 2.0 * nc + 2.0 * nc) * s + nc * nc * s);
+      else  // hpost: e_c, P, e_I (and the post correction), the sub-face prolongation
+        bytes = (double)L.nmacro * ((ncl + ni * ncl + 2.0 * ni) * s +
+                                    (lpost ? (rows + ni * ni) * s + ((nif + nbf) * nc + ni) * s : 0.0)) +
+                (double)C.nface * (nc + 2.0 * nc * nc) * s;
+    }
+    if (launches) *launches = P->prof_n[kernel];
+    if (total_ms) *total_ms = P->prof_ms[kernel];
+    if (bytes_per_launch) *bytes_per_launch = bytes;
+    return HDG_OK;
+  }
   const Level& L = P->L[0];
   const bool f32ops = kernel >= hdg_problem::NPROF_F32OPS;  // FP32 blocks, FP64 vectors
   const int mode = f32ops ? kernel - hdg_problem::NPROF_F32OPS : kernel / 2;

@@ -209,13 +209,17 @@ class Problem:
     def profile_begin(self):
         L.check(self.lib.hdg_profile_begin(self.h), "hdg_profile_begin")
 
-    def profile_read(self, mode, precision):
+    def profile_read(self, mode, precision, transfer=None):
         """precision FP64 / FP32, or MIXED_CYCLE for the finest level's FP64
-        vectors over FP32 operator blocks."""
+        vectors over FP32 operator blocks; transfer = "hpre", "hsum", "hpost"
+        or "prolong_p" reads that transfer kernel instead of trace mode `mode`."""
         n = ctypes.c_longlong()
         ms = ctypes.c_double()
         by = ctypes.c_double()
-        kernel = L.PROF_F32OPS + mode if precision == L.MIXED_CYCLE else 2 * mode + precision
+        if transfer is not None:
+            kernel = L.PROF_XFER + 2 * L.XFER_KINDS.index(transfer) + precision
+        else:
+            kernel = L.PROF_F32OPS + mode if precision == L.MIXED_CYCLE else 2 * mode + precision
         L.check(self.lib.hdg_profile_read(self.h, kernel, ctypes.byref(n), ctypes.byref(ms),
                                           ctypes.byref(by)), "hdg_profile_read")
         return {"launches": n.value, "total_ms": ms.value, "bytes_per_launch": by.value}

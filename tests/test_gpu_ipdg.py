@@ -325,3 +325,33 @@ def test_hdg_tau_kappa(torch_cuda, d, n, k):
     with pytest.raises(RuntimeError, match="unsupported"):
         P.adjoint(torch_cuda.zeros(n ** d, O.nv, dtype=torch_cuda.float64),
                   torch_cuda.zeros(n ** d, d, O.nv, dtype=torch_cuda.float64))
+
+
+@pytest.mark.parametrize("sm", ["jacobi", "lusgs_mc", "chebyshev"])
+def test_ipdg_point_smoothers_example1(torch_cuda, sm):
+    """NIPG-H with the point smoothers of Sec. 4.1 (Tables NIPG_J, NIPG_gs):
+    the GPU's MG and GMRES counts on Example I (levels 3, 4; k = 1, 2) equal
+    the oracle's with the same smoother (LU-SGS in its multicolour order)."""
+    from paper_1811_09909_amd import _lib as L
+    code = {"jacobi": L.SMOOTHER_JACOBI, "lusgs_mc": L.SMOOTHER_LUSGS, "chebyshev": L.SMOOTHER_CHEBYSHEV}[sm]
+    omega = 2.0 / 3.0 if sm == "jacobi" else 1.0
+    for k in (1, 2):
+        for lev in (3, 4):
+            n = 2 ** lev
+            O = IPDG(2, n, k, _tau(2, n, k), np.ones(n * n), "nipg")
+
+            def u(X):
+                return X[:, 0] * X[:, 1] * np.exp(X[:, 0] ** 2 * X[:, 1] ** 3)
+            fn = _ex1_source(O.volume_nodes().reshape(-1, 2)).reshape(O.mesh.nel, -1)
+            A, g, lb = O.assemble(fn, u)
+            H = omg.Hierarchy(A, 2, n, k, sweeps=3, growth=2, omega=omega, smoother=sm)
+            ro = omg.mg_solve(H, A, g, tol=1e-9)
+            rg = omg.gmres_solve(H, A, g, tol=1e-9, side="right")
+            P = _gpu(torch_cuda, O, np.ones(n * n), sweeps=3, growth=2, omega=omega, smoother=code,
+                     method=L.METHOD_MG)
+            _, im = P.solve(torch_cuda.as_tensor(fn), tol=1e-9, gdir=torch_cuda.as_tensor(lb))
+            P.build(sweeps=3, growth=2, omega=omega, smoother=code, method=L.METHOD_GMRES)
+            _, ig = P.solve(torch_cuda.as_tensor(fn), tol=1e-9, gdir=torch_cuda.as_tensor(lb))
+            say(f"[ipdg {sm}] k={k} L={lev}: MG GPU {im['iters']} oracle {ro.iters}; "
+                f"GMRES GPU {ig['iters']} oracle {rg.iters}")
+            assert abs(im["iters"] - ro.iters) <= 1 and abs(ig["iters"] - rg.iters) <= 1

@@ -29,6 +29,10 @@ follows):
 * ``rth``      -- the hybridized Raviart-Thomas mixed method (RT_k-H on
   squares, eqs. mixed_local1, mixed_local2) and multinumerics (RT-H and an
   IPDG scheme element by element in one trace system, Sec. 4.6).
+* ``unstructured`` -- HDG on P^k triangles of an unstructured mesh, the
+  seed-point agglomeration of Sec. 3.1.2, macro-edges as chains of finer
+  faces with the P^1 coarse space parameterized by arc length, and the
+  multigrid of Sec. 3 on those levels.
 * ``adjoint``  -- gradient of a misfit with respect to per-element
   log-permeability through the discrete adjoint of the HDG system
   (derived from eqs. HDG and HDG_flux; not in the paper).
@@ -39,4 +43,4 @@ the paper and the mathematics fix (energy identities, Propositions 1 and
 nested-dissection limit, complex-step derivatives).  Functions without
 such a pin say "parity unpinned" in their docstring.
 """
-from . import refelem, hdg, mg, adjoint, ipdg, rth  # noqa: F401
+from . import refelem, hdg, mg, adjoint, ipdg, rth, unstructured  # noqa: F401

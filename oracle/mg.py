@@ -305,28 +305,37 @@ class Hierarchy:
             self.levels.append(lev)
         while lev.mesh.n > max(2, coarsest_n):
             I_d, B_d, JB, mc, cm = h_partition(lev.mesh, lev.m, coarse)
-            A = lev.A
-            AII = A[I_d][:, I_d]
-            AIB = A[I_d][:, B_d]
-            ABI = A[B_d][:, I_d]
-            ABB = A[B_d][:, B_d]
-            AIIinv = block_inverse(AII)
-            X = (AIIinv @ AIB).tocsr()
-            Ac = (JB.T @ (ABB - ABI @ X) @ JB).tocsr()
-            N, Nc = A.shape[0], Ac.shape[0]
-            # prolongation and restriction in the level's own DOF order
-            PI = sp.vstack([-(X @ JB), JB]).tocsr()
-            perm = np.concatenate([I_d, B_d])
-            Pmat = sp.csr_matrix((np.ones(N), (perm, np.arange(N))), shape=(N, N))
-            lev.I = (Pmat @ PI).tocsr()
-            Qblk = sp.hstack([-(JB.T @ ABI @ AIIinv), JB.T]).tocsr()
-            lev.Q = (Qblk @ Pmat.T).tocsr()
-            lev.kind = "h"
-            lev.I_dofs, lev.B_dofs, lev.JB = I_d, B_d, JB
-            lev.AIIinv = AIIinv
-            lev.AII = AII
-            lev = Level(Ac, cm, mc)
+            lev = self._h_step(lev, I_d, B_d, JB, mc, cm)
             self.levels.append(lev)
+        self._finish(sweeps, growth, smoother)
+
+    def _h_step(self, lev, I_d, B_d, JB, mc, cm):
+        """One h-coarsening (eq. trace_partition): E_I DOFs I_d, E_B DOFs
+        B_d, J_k = JB; fills lev's transfers and returns the coarse level."""
+        A = lev.A
+        AII = A[I_d][:, I_d]
+        AIB = A[I_d][:, B_d]
+        ABI = A[B_d][:, I_d]
+        ABB = A[B_d][:, B_d]
+        AIIinv = block_inverse(AII)
+        X = (AIIinv @ AIB).tocsr()
+        Ac = (JB.T @ (ABB - ABI @ X) @ JB).tocsr()
+        N = A.shape[0]
+        # prolongation and restriction in the level's own DOF order
+        PI = sp.vstack([-(X @ JB), JB]).tocsr()
+        perm = np.concatenate([I_d, B_d])
+        Pmat = sp.csr_matrix((np.ones(N), (perm, np.arange(N))), shape=(N, N))
+        lev.I = (Pmat @ PI).tocsr()
+        Qblk = sp.hstack([-(JB.T @ ABI @ AIIinv), JB.T]).tocsr()
+        lev.Q = (Qblk @ Pmat.T).tocsr()
+        lev.kind = "h"
+        lev.I_dofs, lev.B_dofs, lev.JB = I_d, B_d, JB
+        lev.AIIinv = AIIinv
+        lev.AII = AII
+        return Level(Ac, cm, mc)
+
+    def _finish(self, sweeps, growth, smoother):
+        """Coarsest factorization, sweeps per level, smoother data."""
         self.coarse_lu = sla.lu_factor(self.levels[-1].A.toarray()) if self.levels[-1].A.shape[0] else None
         for i, L in enumerate(self.levels):
             L.sweeps = sweeps * (2 ** i if growth == 2 else 1)

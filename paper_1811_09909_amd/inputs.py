@@ -23,6 +23,10 @@ Workloads (all on the unit box, tau = 1, zero Dirichlet data):
                       (the coefficient of Example III on the unit square),
                       f = -kappa_T lap u for u = x y exp(x^2 y^3) (Example I),
                       zero Dirichlet data; stabilization kappa_T (p+1)(p+2)/h_min.
+* ``unstructured2d`` -- Example II's setting (kappa = 1, f = 1, tau = 1) on
+                      ``box_with_holes``, a seeded Delaunay mesh of the box
+                      [0, 2] x [0, 1] with eight circular holes, and the seed
+                      points of two coarsening strategies.
 * ``multinumerics2d`` -- Example VI's coefficient 1 + 0.5 sin(4 pi x) cos(3 pi y)
                       at element centres, f = 1, zero Dirichlet data; NIPG-H on
                       the elements whose centre lies within 0.3 of
@@ -145,3 +149,76 @@ def multinumerics2d(n=512, k=1):
     return Workload(d=2, n=n, k=k, tau=(k + 1) * (k + 2) * n / np.sqrt(2.0), kappa=kappa, schemes=schemes,
                     f=np.ones((n * n, (k + 1) ** 2)),
                     name=f"multinumerics2d RT-H + NIPG-H n={n} k={k} kappa=1+0.5sin(4pi x)cos(3pi y) f=1")
+
+
+def box_with_holes(nx=32, holes=True, seed=0):
+    """An unstructured triangulation of the box [0, 2] x [0, 1], by default
+    with eight circular holes of radius 0.12 centred at (0.25 + 0.5 i,
+    0.25 + 0.5 j), i < 4, j < 2 (a stand-in for the mesh of Example II,
+    which is published only as a figure).
+
+    Vertices: a grid of spacing h = 1 / nx over the box, the interior ones
+    moved by U(-0.3 h, 0.3 h) per coordinate (drawn in vertex order, x then
+    y), minus those within 0.12 + 0.6 h of a hole centre, plus
+    ceil(2 pi 0.12 / h) equally spaced points on every hole's circle.
+    Triangles: the Delaunay triangulation of these points, without those
+    whose centroid lies inside a hole, each listed counter-clockwise.
+    Returns (vertices [nv, 2] float64, triangles [nt, 3] int32)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    h = 1.0 / nx
+    xs = np.arange(2 * nx + 1) * h
+    ys = np.arange(nx + 1) * h
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    P = np.stack([X.ravel(), Y.ravel()], axis=1)
+    jit = rng.uniform(-0.3 * h, 0.3 * h, P.shape)
+    inner = (P[:, 0] > 0) & (P[:, 0] < 2.0) & (P[:, 1] > 0) & (P[:, 1] < 1.0)
+    P[inner] += jit[inner]
+    r = 0.12
+    centres = np.array([(0.25 + 0.5 * i, 0.25 + 0.5 * j) for j in range(2) for i in range(4)]) if holes \
+        else np.zeros((0, 2))
+    keep = np.ones(len(P), dtype=bool)
+    for c in centres:
+        keep &= np.hypot(P[:, 0] - c[0], P[:, 1] - c[1]) > r + 0.6 * h
+    pts = [P[keep]]
+    m = int(np.ceil(2 * np.pi * r / h))
+    th = 2 * np.pi * np.arange(m) / m
+    for c in centres:
+        pts.append(np.stack([c[0] + r * np.cos(th), c[1] + r * np.sin(th)], axis=1))
+    V = np.concatenate(pts)
+    tri = Delaunay(V).simplices.astype(np.int64)
+    cen = V[tri].mean(axis=1)
+    ok = np.ones(len(tri), dtype=bool)
+    for c in centres:
+        ok &= np.hypot(cen[:, 0] - c[0], cen[:, 1] - c[1]) > r
+    tri = tri[ok]
+    a, b, c3 = V[tri[:, 0]], V[tri[:, 1]], V[tri[:, 2]]
+    area2 = (b[:, 0] - a[:, 0]) * (c3[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c3[:, 0] - a[:, 0])
+    flip = area2 < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    used = np.unique(tri)
+    remap = -np.ones(len(V), dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    return V[used].copy(), remap[tri].astype(np.int32)
+
+
+def unstructured2d(nx=32, k=2, strategy=1, holes=True, seed=0):
+    """The unstructured workload (Example II's setting on a synthetic mesh):
+    kappa = 1, f = 1, zero Dirichlet data, tau = 1, on ``box_with_holes``.
+    Seed points of the level-1 macro-elements: strategy 1 takes eight
+    (0.25 + 0.5 i, 0.25 + 0.5 j), strategy 2 four (0.25 + 0.5 i, 0.5).
+    ``hlevels``: the most agglomeration levels whose finest macro-elements
+    hold at least three triangles on average (seeds 4^(hlevels-1) 3 <= N_T)."""
+    V, T = box_with_holes(nx, holes, seed)
+    if strategy == 1:
+        seeds = np.array([(0.25 + 0.5 * i, 0.25 + 0.5 * j) for j in range(2) for i in range(4)])
+    else:
+        seeds = np.array([(0.25 + 0.5 * i, 0.5) for i in range(4)])
+    nt = len(T)
+    hl = 1
+    while len(seeds) * 4 ** hl * 3 <= nt:
+        hl += 1
+    nv = (k + 1) * (k + 2) // 2
+    return Workload(d=2, k=k, tau=1.0, vertices=V, triangles=T, seeds=seeds, hlevels=hl,
+                    kappa=np.ones(nt), f=np.ones((nt, nv)),
+                    name=f"unstructured2d box with 8 holes nx={nx} ({nt} triangles) k={k} strategy {strategy}")

@@ -208,6 +208,48 @@ hdg_status hdg_setup_multi(const hdg_mesh* mesh, int k, double tau, const double
                            const int* scheme_of_element, int options, int store_recovery, void* hip_stream,
                            hdg_handle* out);
 
+/* Unstructured triangle meshes (Sec. 3.1.2 and Example II).  HOST arrays:
+ * xy [nvert][2] vertex coordinates, tri [ntri][3] vertex indices listed
+ * counter-clockwise, seeds [nseeds][2] the seed points of the level-1
+ * macro-elements; hlevels agglomeration levels. */
+typedef struct {
+  long nvert;
+  const double* xy;
+  long ntri;
+  const int* tri;
+  int nseeds;
+  const double* seeds;
+  int hlevels;
+} hdg_umesh;
+
+/* HDG (eqs. HDG, HDG_flux) with P^k volume and trace spaces on the
+ * triangles of an unstructured mesh, k in 1..4, scalar tau > 0, kappa a
+ * DEVICE array with one value per triangle.  Volume unknowns are nodal at
+ * the equispaced lattice of each triangle (vertex 0 first, then along edge
+ * 0; rows from edge 0 to vertex 2); the trace unknowns of an interior edge
+ * are nodal at the GLL points of its parameter, which runs from its lower-
+ * numbered vertex to the other; interior edges are numbered in order of
+ * their sorted vertex pair; edges on the boundary carry zero Dirichlet data.
+ * The multigrid hierarchy is fixed here (Sec. 3.1.2): level 1 gathers the
+ * triangles nearest to each seed (centroid distance, lowest seed on ties;
+ * seeds that win none are dropped), and each further level splits every
+ * macro-element in four (halving twice at the median centroid along the
+ * axis of larger centroid extent).  Macro-edges are the maximal chains of
+ * finer faces shared by the same two macro-elements; their P^1 coarse
+ * space is linear in arc length along the chain.  Levels: P^k on the
+ * triangles, P^1 on the triangles (k > 1), then the agglomeration levels,
+ * finest first; the coarsest is solved by a dense inverse (at most 4096
+ * unknowns).  hdg_mg_build takes block-Jacobi smoothing only (the mixed
+ * precision cycle keeps FP64 vectors over FP32 operator blocks); hdg_rhs
+ * and hdg_solve take nodal f with zero Dirichlet data (g_dirichlet NULL);
+ * reconstruction, the adjoint, kappa updates, batches and the autotuner
+ * return HDG_ERR_UNSUPPORTED.  Errors: HDG_ERR_INVALID_ARG for clockwise or
+ * degenerate triangles, edges shared by more than two triangles, or a
+ * macro-element with more than 1024 trace values; HDG_ERR_UNSUPPORTED for
+ * k outside 1..4. */
+hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, void* hip_stream,
+                                  hdg_handle* out);
+
 /* Re-form A^e for a new kappa (same layout rules); invalidates the
  * hierarchy (call hdg_mg_build again). */
 hdg_status hdg_update_kappa(hdg_handle h, const double* kappa, int kappa_kind);

@@ -22,7 +22,7 @@ EXPORTS = [
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
     "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune", "hdg_rhs_noalloc",
-    "hdg_setup_scheme", "hdg_setup_multi",
+    "hdg_setup_scheme", "hdg_setup_multi", "hdg_setup_unstructured",
 ]
 
 
@@ -31,6 +31,13 @@ MAX_NRHS = 64  # HDG_MAX_NRHS
 
 class Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int)]
+
+
+class UMesh(ctypes.Structure):
+    """hdg_umesh: host vertex, triangle and seed arrays, agglomeration levels."""
+    _fields_ = [("nvert", ctypes.c_long), ("xy", ctypes.c_void_p), ("ntri", ctypes.c_long),
+                ("tri", ctypes.c_void_p), ("nseeds", ctypes.c_int), ("seeds", ctypes.c_void_p),
+                ("hlevels", ctypes.c_int)]
 
 
 class Opts(ctypes.Structure):
@@ -88,6 +95,7 @@ def load():
         "hdg_setup": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_scheme": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_multi": (I, [ctypes.POINTER(Mesh), I, D, P, I, P, I, I, P, ctypes.POINTER(P)]),
+        "hdg_setup_unstructured": (I, [ctypes.POINTER(UMesh), I, D, P, P, ctypes.POINTER(P)]),
         "hdg_update_kappa": (I, [P, P, I]),
         "hdg_mg_build": (I, [P, ctypes.POINTER(Opts)]),
         "hdg_vcycle": (I, [P, P, P, I, I]),

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.environ.get("HDG_LIB_OUT", os.path.join(HERE, "_lib", "libhdg.so"))
 OUT_DIR = os.path.dirname(LIB)
 OBJ_DIR = os.environ.get("HDG_BUILD_DIR", os.path.join(ROOT, "_build"))
-SOURCES = ["refelem.cpp", "api.cpp", "element.hip", "build.hip", "trace.hip", "tail.hip", "blas.hip", "noalloc.hip"]
+SOURCES = ["refelem.cpp", "umesh.cpp", "api.cpp", "element.hip", "build.hip", "trace.hip", "tail.hip", "blas.hip",
+           "noalloc.hip", "unstructured.hip"]
 ARCH = os.environ.get("HDG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -8,7 +8,9 @@
 #include <atomic>
 #include <chrono>
 #include <limits>
+#include <memory>
 #include <new>
+#include <stdexcept>
 #include <thread>
 
 #include "blas.hpp"
@@ -91,6 +93,13 @@ struct hdg_problem {
   static constexpr int NPROF = NPROF_XFER + 8;
   double prof_ms[NPROF] = {};
   long long prof_n[NPROF] = {};
+  // unstructured triangle meshes (hdg_setup_unstructured): host topology,
+  // device copies of every level's index arrays, vertices and triangles
+  bool unstructured = false;
+  std::unique_ptr<UHost> uh;
+  std::vector<ULevel> ul;
+  double* uxy = nullptr;
+  int* utri = nullptr;
   std::vector<void*> allocs;        // freed in destroy
   std::vector<void*> build_allocs;  // freed on rebuild
   long long bytes = 0;
@@ -137,11 +146,17 @@ hdg_status map_error(const HipError& e) {
   return HDG_ERR_DEVICE;
 }
 
+// a request the handle's discretization does not support
+struct Unsupported {};
+
 #define HDG_GUARD_BEGIN try {
 #define HDG_GUARD_END                        \
   }                                          \
   catch (const HipError& e) {                \
     return map_error(e);                     \
+  }                                          \
+  catch (const Unsupported&) {               \
+    return HDG_ERR_UNSUPPORTED;              \
   }                                          \
   catch (const std::bad_alloc&) {            \
     return HDG_ERR_DEVICE;                   \
@@ -887,6 +902,11 @@ void form_rhs_in(hdg_problem* P, const double* rhs, int kind, const double* gdir
 }
 
 void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g) {
+  if (P->unstructured) {  // nodal f, zero Dirichlet data
+    if (kind != HDG_RHS_F_NODAL || gdir) throw Unsupported{};
+    launch_tri_load(P->k, P->ul[0], P->W, rhs, g, P->st);
+    return;
+  }
   form_rhs_in(P, rhs, kind, gdir, g, P->ework);
 }
 
@@ -953,10 +973,18 @@ hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, h
 
 }  // namespace
 
-long hdg::rhs_staging_doubles(const hdg_problem* P) { return P->nelem * (P->nv + P->nl); }
+long hdg::rhs_staging_doubles(const hdg_problem* P) { return P->unstructured ? 0 : P->nelem * (P->nv + P->nl); }
+
+bool hdg::rhs_supported(const hdg_problem* P, int kind, const double* gdir) {
+  return !P->unstructured || (kind == HDG_RHS_F_NODAL && !gdir);
+}
 
 void hdg::rhs_with_staging(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g,
                            double* ebuf) {
+  if (P->unstructured) {  // the per-face load needs no staging
+    form_rhs(P, rhs, kind, gdir, g);
+    return;
+  }
   form_rhs_in(P, rhs, kind, gdir, g, ebuf);
 }
 
@@ -1152,6 +1180,7 @@ hdg_status hdg_setup_multi(const hdg_mesh* mesh, int k, double tau, const double
 
 hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
   if (!P || !kappa) return HDG_ERR_INVALID_ARG;
+  if (P->unstructured) return HDG_ERR_UNSUPPORTED;
   if (kappa_kind != HDG_KAPPA_PER_ELEMENT && kappa_kind != HDG_KAPPA_AT_QP) return HDG_ERR_INVALID_ARG;
   if (kappa_kind == HDG_KAPPA_AT_QP) {
     bool elem_only = P->tau_kappa;
@@ -1169,6 +1198,93 @@ hdg_status hdg_update_kappa(hdg_handle P, const double* kappa, int kappa_kind) {
   HDG_GUARD_END
 }
 
+namespace {
+
+// Solver storage of a build (shared by the grid and the unstructured
+// hierarchies): Chebyshev smoother data, Krylov vectors, device scalars and
+// reduction partials, the GMRES basis.
+void alloc_solver(hdg_problem* P, const hdg_mg_opts& o) {
+  std::vector<Level>& L = P->L;
+  const int cap = P->cap;
+  P->N = L[0].nlam;
+  const long N = P->N;
+  const long Nc = N * cap;
+  if (o.smoother == HDG_SMOOTHER_CHEBYSHEV) {
+    // per level: lmax of D^-1 A by power iteration (FP64), then the
+    // diagonal blocks scaled by the reciprocal roots of the degree-m
+    // Chebyshev polynomial on [lmax / 30, lmax], one copy per step
+    Scratch ps;
+    ps.sc = dalloc<double>(P, SC_COUNT, true);
+    ps.partials = dalloc<double>(P, 2L * MAX_RED_BLOCKS, true);
+    ps.row = 2L * MAX_RED_BLOCKS;
+    for (auto& Li : L) {
+      if (Li.nface == 0 || Li.kind == 2) continue;
+      double* v = (double*)Li.r[0];
+      double* y = (double*)Li.e[0];
+      double* z = (double*)Li.w[0];
+      blas_fill<double>(v, 1.0, Li.nlam, P->st);
+      auto dinv_apply = [&](const double* in, double* out) {  // out = D^-1 A in
+        launch_apply<double>(Li, APPLY_Y, in, nullptr, y, nullptr, nullptr, P->st);
+        launch_jacobi0<double>(Li, y, out, P->st);
+      };
+      for (int it = 0; it < CHEB_POWER_ITS; ++it) {
+        dinv_apply(v, z);
+        blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
+        blas_scale(v, z, Li.nlam, ps.sc + SC_TMP, P->st);
+      }
+      dinv_apply(v, z);
+      blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
+      Li.lmax = CHEB_SAFETY * read_scalar(P, ps.sc + SC_HNORM);
+      const double lmin = Li.lmax / CHEB_RATIO, theta = 0.5 * (Li.lmax + lmin), dlt = 0.5 * (Li.lmax - lmin);
+      const long nd = pad64(Li.nface) * vpad<double>((long)Li.ne * Li.ne);
+      const long nd32 = pad64(Li.nface) * vpad<float>((long)Li.ne * Li.ne);
+      if (nd32 != nd) throw HipError{hipErrorInvalidValue, "Chebyshev copies: block padding differs"};
+      for (int si = 1; si <= Li.sweeps; ++si) {
+        const double root = theta - dlt * std::cos((2.0 * si - 1.0) * M_PI / (2.0 * Li.sweeps));
+        double* c64 = dalloc<double>(P, nd, true);
+        float* c32 = dalloc<float>(P, nd, true);
+        launch_scale_copy(nd, 1.0 / root, Li.Dinv64, c64, c32, P->st);
+        Li.cheb64.push_back(c64);
+        Li.cheb32.push_back(c32);
+      }
+    }
+  }
+  P->g = dalloc<double>(P, Nc, true);
+  P->r = dalloc<double>(P, Nc, true);
+  P->z = dalloc<double>(P, Nc, true);
+  P->p = dalloc<double>(P, Nc, true);
+  P->Ap = dalloc<double>(P, Nc, true);
+  P->zold = dalloc<double>(P, Nc, true);
+  P->lam = dalloc<double>(P, Nc, true);
+  P->r32 = dalloc<float>(P, Nc, true);
+  P->z32 = dalloc<float>(P, Nc, true);
+  {
+    // device scalars and reduction partials, one row per right-hand side
+    P->s.sc = dalloc<double>(P, (long)SC_COUNT * cap, true);
+    const long nface0 = L[0].nface;
+    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
+    P->s.partials = dalloc<double>(P, 2 * nb * cap, true);
+    P->s.row = 2 * nb;
+    P->s.pcg = dalloc<double>(P, 2L * MAX_RED_BLOCKS * cap, true);
+    HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT * cap, P->st));
+  }
+  if (o.method == HDG_METHOD_GMRES) {
+    const int m = o.restart > 0 ? std::min(o.restart, std::max(o.max_it, 1)) : std::max(o.max_it, 1);
+    P->gm_m = m;
+    P->V = dalloc<double>(P, (long)(m + 1) * N, true);
+    P->Z = dalloc<double>(P, (long)m * N, true);
+    P->H = dalloc<double>(P, (long)(m + 1) * (m + 1), true);
+    P->cs = dalloc<double>(P, m + 1, true);
+    P->sn = dalloc<double>(P, m + 1, true);
+    P->gsv = dalloc<double>(P, m + 2, true);
+    P->y = dalloc<double>(P, m + 1, true);
+  }
+}
+
+hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o);
+
+}  // namespace
+
 hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (!P) return HDG_ERR_INVALID_ARG;
   hdg_mg_opts o;
@@ -1185,6 +1301,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.nrhs < 1) o.nrhs = 1;
   if (o.refine_red == 0.0) o.refine_red = 1e-5;
   if (o.coarse_n < 2) o.coarse_n = 2;
+  if (P->unstructured) return ubuild(P, o);
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   if (!P->sym && o.method == HDG_METHOD_PCG) return HDG_ERR_UNSUPPORTED;  // CG needs a symmetric operator
   HDG_GUARD_BEGIN
@@ -1349,85 +1466,288 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
     }
   }
 
-  // mixed cycle form (set above, before the levels' storage was chosen)
-  P->N = L[0].nlam;
-  const long N = P->N;
-  const long Nc = N * cap;
-  if (o.smoother == HDG_SMOOTHER_CHEBYSHEV) {
-    // per level: lmax of D^-1 A by power iteration (FP64), then the
-    // diagonal blocks scaled by the reciprocal roots of the degree-m
-    // Chebyshev polynomial on [lmax / 30, lmax], one copy per step
-    Scratch ps;
-    ps.sc = dalloc<double>(P, SC_COUNT, true);
-    ps.partials = dalloc<double>(P, 2L * MAX_RED_BLOCKS, true);
-    ps.row = 2L * MAX_RED_BLOCKS;
-    for (auto& Li : L) {
-      if (Li.nface == 0 || Li.kind == 2) continue;
-      double* v = (double*)Li.r[0];
-      double* y = (double*)Li.e[0];
-      double* z = (double*)Li.w[0];
-      blas_fill<double>(v, 1.0, Li.nlam, P->st);
-      auto dinv_apply = [&](const double* in, double* out) {  // out = D^-1 A in
-        launch_apply<double>(Li, APPLY_Y, in, nullptr, y, nullptr, nullptr, P->st);
-        launch_jacobi0<double>(Li, y, out, P->st);
-      };
-      for (int it = 0; it < CHEB_POWER_ITS; ++it) {
-        dinv_apply(v, z);
-        blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
-        blas_scale(v, z, Li.nlam, ps.sc + SC_TMP, P->st);
-      }
-      dinv_apply(v, z);
-      blas_dot(z, z, Li.nlam, ps, FIN_NORM_INV, ps.sc + SC_HNORM, P->st);
-      Li.lmax = CHEB_SAFETY * read_scalar(P, ps.sc + SC_HNORM);
-      const double lmin = Li.lmax / CHEB_RATIO, theta = 0.5 * (Li.lmax + lmin), dlt = 0.5 * (Li.lmax - lmin);
-      const long nd = pad64(Li.nface) * vpad<double>((long)Li.ne * Li.ne);
-      const long nd32 = pad64(Li.nface) * vpad<float>((long)Li.ne * Li.ne);
-      if (nd32 != nd) throw HipError{hipErrorInvalidValue, "Chebyshev copies: block padding differs"};
-      for (int si = 1; si <= Li.sweeps; ++si) {
-        const double root = theta - dlt * std::cos((2.0 * si - 1.0) * M_PI / (2.0 * Li.sweeps));
-        double* c64 = dalloc<double>(P, nd, true);
-        float* c32 = dalloc<float>(P, nd, true);
-        launch_scale_copy(nd, 1.0 / root, Li.Dinv64, c64, c32, P->st);
-        Li.cheb64.push_back(c64);
-        Li.cheb32.push_back(c32);
-      }
-    }
-  }
-  P->g = dalloc<double>(P, Nc, true);
-  P->r = dalloc<double>(P, Nc, true);
-  P->z = dalloc<double>(P, Nc, true);
-  P->p = dalloc<double>(P, Nc, true);
-  P->Ap = dalloc<double>(P, Nc, true);
-  P->zold = dalloc<double>(P, Nc, true);
-  P->lam = dalloc<double>(P, Nc, true);
-  P->r32 = dalloc<float>(P, Nc, true);
-  P->z32 = dalloc<float>(P, Nc, true);
-  {
-    // device scalars and reduction partials, one row per right-hand side
-    P->s.sc = dalloc<double>(P, (long)SC_COUNT * cap, true);
-    const long nface0 = L[0].nface;
-    const long nb = std::max<long>(MAX_RED_BLOCKS, (nface0 + 255) / 256 + 64);  // + XCD padding blocks
-    P->s.partials = dalloc<double>(P, 2 * nb * cap, true);
-    P->s.row = 2 * nb;
-    P->s.pcg = dalloc<double>(P, 2L * MAX_RED_BLOCKS * cap, true);
-    HDG_CHECK(hipMemsetAsync(P->s.sc, 0, sizeof(double) * SC_COUNT * cap, P->st));
-  }
-  if (o.method == HDG_METHOD_GMRES) {
-    const int m = o.restart > 0 ? std::min(o.restart, std::max(o.max_it, 1)) : std::max(o.max_it, 1);
-    P->gm_m = m;
-    P->V = dalloc<double>(P, (long)(m + 1) * N, true);
-    P->Z = dalloc<double>(P, (long)m * N, true);
-    P->H = dalloc<double>(P, (long)(m + 1) * (m + 1), true);
-    P->cs = dalloc<double>(P, m + 1, true);
-    P->sn = dalloc<double>(P, m + 1, true);
-    P->gsv = dalloc<double>(P, m + 2, true);
-    P->y = dalloc<double>(P, m + 1, true);
-  }
+  alloc_solver(P, o);
   HDG_CHECK(hipStreamSynchronize(P->st));
   P->built = true;
   P->t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
   HDG_GUARD_END
+}
+
+
+namespace {
+
+// The hierarchy of an unstructured handle (levels fixed at setup by the
+// agglomeration): P^1 Galerkin maps of the triangles, per agglomeration step
+// the coarse cells' Schur complements, A_II^-1 and P, the coarsest dense
+// inverse, then every level's apply storage (AoSoA / FP32 maps), face-block
+// inverses and vectors.  Block-Jacobi smoothing only; the mixed cycle keeps
+// FP64 vectors over FP32 maps; no fused kernels, coarse tail or packing.
+hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
+  if (o.smoother != HDG_SMOOTHER_BLOCK_JACOBI) return HDG_ERR_UNSUPPORTED;
+  HDG_GUARD_BEGIN
+  const auto t0 = std::chrono::steady_clock::now();
+  free_build(P);
+  P->opts = o;
+  P->cap = o.nrhs;
+  P->use_graphs = !(o.variant & HDG_VARIANT_NO_GRAPH);
+  P->fuse = false;
+  P->tail_nmax = 0;
+  P->pack = false;
+  P->strip = false;
+  P->ops32 = o.precision == HDG_MIXED;
+  P->tail_start[0] = P->tail_start[1] = -1;
+  const int cap = P->cap;
+  const int nlev = (int)P->ul.size();
+  std::vector<Level>& L = P->L;
+  L.resize(nlev);
+  for (int i = 0; i < nlev; ++i) {
+    ULevel& U = P->ul[i];
+    Level& Li = L[i];
+    Li.d = 2;
+    Li.n = 0;
+    Li.ne = U.m;
+    Li.nl = U.tri ? 3 * U.m : 0;
+    Li.nelem = U.ncell;
+    Li.nfd = U.nface;
+    Li.nface = U.nface;
+    Li.nlam = U.nface * U.m;
+    Li.u = &U;
+    Li.kind = i == nlev - 1 ? 2 : (i == 0 && P->k > 1) ? 0 : 1;
+    Li.sym = true;
+  }
+  L[0].Aelem = P->Ae;
+  L[0].own_Aelem = false;
+  if (P->k > 1) {
+    L[1].Aelem = dalloc<double>(P, P->nelem * 36, true);
+    launch_tri_pgalerkin(P->k, P->nelem, P->rd.Jp, P->Ae, L[1].Aelem, P->st);
+  }
+  long nwork = 0;
+  for (int i = 0; i + 1 < nlev; ++i) nwork = std::max(nwork, P->ul[i].nwork);
+  double* work = nwork > 0 ? dalloc<double>(P, nwork, true) : nullptr;
+  for (int i = 0; i + 1 < nlev; ++i) {
+    Level& F = L[i];
+    if (F.kind != 1) continue;
+    ULevel& U = P->ul[i];
+    F.nmacro = U.ncoarse;
+    F.AIIinv64 = dalloc<double>(P, std::max(U.asize, 1L), true);
+    F.AIIinv32 = dalloc<float>(P, std::max(U.asize, 1L), true);
+    F.P64 = dalloc<double>(P, std::max(U.psize, 1L), true);
+    F.P32 = dalloc<float>(P, std::max(U.psize, 1L), true);
+    F.R64 = F.P64;
+    F.R32 = F.P32;
+    F.cb[0] = dalloc<double>(P, std::max(U.ncb, 1L) * cap, true);
+    F.cb[1] = dalloc<float>(P, std::max(U.ncb, 1L) * cap, true);
+    L[i + 1].Aelem = dalloc<double>(P, std::max(P->ul[i + 1].msize, 1L), true);
+    launch_uschur(U, P->ul[i + 1], F.Aelem, F.AIIinv64, F.P64, L[i + 1].Aelem, work, P->st);
+    launch_to_f32(F.AIIinv64, F.AIIinv32, U.asize, P->st);
+    launch_to_f32(F.P64, F.P32, U.psize, P->st);
+  }
+  Level& Lc = L.back();
+  if (Lc.nlam > UCOARSE_MAX) return HDG_ERR_UNSUPPORTED;
+  if (Lc.nlam > 0) {
+    Lc.Ainv64 = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
+    Lc.Ainv32 = dalloc<float>(P, Lc.nlam * Lc.nlam, true);
+    double* dense = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
+    launch_ucoarse_inverse(Lc, dense, P->st);
+  }
+  for (int i = 0; i < nlev; ++i) {
+    Level& Li = L[i];
+    ULevel& U = P->ul[i];
+    Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min(i, 20)) : 1);
+    if (U.tri) {
+      const long nn = 9L * U.m * U.m;
+      Li.Af64 = dalloc<double>(P, pad64(U.ncell) * vpad<double>(nn), true);
+      Li.Af32 = dalloc<float>(P, pad64(U.ncell) * vpad<float>(nn), true);
+      U.Am32 = nullptr;
+    } else {
+      U.Am32 = dalloc<float>(P, std::max(U.msize, 1L), true);
+    }
+    U.z[0] = dalloc<double>(P, std::max(U.nrow, 1L) * cap, true);
+    U.z[1] = dalloc<float>(P, std::max(U.nrow, 1L) * cap, true);
+    launch_umaps(Li, P->st);
+    const long pf = pad64(Li.nface);
+    Li.Dinv64 = dalloc<double>(P, std::max(pf, 64L) * vpad<double>((long)Li.ne * Li.ne), true);
+    Li.Dinv32 = dalloc<float>(P, std::max(pf, 64L) * vpad<float>((long)Li.ne * Li.ne), true);
+    launch_udinv(Li, P->st);
+    for (int pr = 0; pr < 2; ++pr)
+      for (void** slot : {&Li.r[pr], &Li.e[pr], &Li.w[pr]}) {
+        if (pr == 0)
+          *slot = dalloc<double>(P, std::max(Li.nlam, 1L) * cap, true);
+        else
+          *slot = dalloc<float>(P, std::max(Li.nlam, 1L) * cap, true);
+      }
+  }
+  alloc_solver(P, o);
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  P->built = true;
+  P->t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return HDG_OK;
+  HDG_GUARD_END
+}
+
+// device copies of the host topology, level by level
+void upload_ulevels(hdg_problem* P) {
+  const UHost& H = *P->uh;
+  P->ul.clear();
+  P->ul.reserve(H.lev.size());
+  for (size_t i = 0; i < H.lev.size(); ++i) {
+    const UHostLevel& h = H.lev[i];
+    ULevel U;
+    U.m = h.m;
+    U.tri = h.tri;
+    U.ncell = h.ncell;
+    U.nface = h.nface;
+    const long nslot = h.sptr[h.ncell];
+    U.nrow = nslot * h.m;
+    U.sptr = upload(P, h.sptr);
+    U.sface = upload(P, h.sface);
+    if (h.nface > 0) {
+      U.fcell = upload(P, h.fcell);
+      U.fslot = upload(P, h.fslot);
+    }
+    std::vector<long> moff(h.ncell), zr(2 * h.nface);
+    std::vector<int> rcell;
+    long msz = 0;
+    for (long c = 0; c < h.ncell; ++c) {
+      const long ns = h.sptr[c + 1] - h.sptr[c];
+      moff[c] = msz;
+      msz += (h.m * ns) * (h.m * ns);
+      if (!h.tri)
+        for (long r = 0; r < h.m * ns; ++r) rcell.push_back((int)c);
+    }
+    for (long f = 0; f < h.nface; ++f)
+      for (int side = 0; side < 2; ++side)
+        zr[2 * f + side] = (h.sptr[h.fcell[2 * f + side]] + h.fslot[2 * f + side]) * h.m;
+    U.msize = msz;
+    U.moff = upload(P, moff);
+    if (h.nface > 0) U.zr = upload(P, zr);
+    if (!rcell.empty()) U.rcell = upload(P, rcell);
+    if (h.ncoarse > 0) {
+      const UHostLevel& c = H.lev[i + 1];
+      const long nc = h.ncoarse;
+      U.ncoarse = nc;
+      U.iptr = upload(P, h.iptr);
+      U.bptr = upload(P, h.bptr);
+      U.ccptr = upload(P, h.ccptr);
+      if (!h.iface.empty()) U.iface = upload(P, h.iface);
+      if (!h.bface.empty()) {
+        U.bface = upload(P, h.bface);
+        U.bslot = upload(P, h.bslot);
+      }
+      U.ccell = upload(P, h.ccell);
+      U.sloc = upload(P, h.sloc);
+      U.fE = upload(P, h.fE);
+      U.fJ = upload(P, h.fJ);
+      std::vector<int> irc, cbc;
+      std::vector<long> aoff(nc), poff(nc), woff(nc);
+      long as = 0, ps = 0, ws = 0;
+      for (long C = 0; C < nc; ++C) {
+        const long nI2 = 2 * (h.iptr[C + 1] - h.iptr[C]), nB = h.bptr[C + 1] - h.bptr[C];
+        const long n2 = nI2 + 2 * nB, nc2 = 2 * (c.sptr[C + 1] - c.sptr[C]);
+        if (n2 > UMACRO_MAX_DOFS) throw std::invalid_argument("a macro-element has too many trace values");
+        aoff[C] = as;
+        poff[C] = ps;
+        woff[C] = ws;
+        as += nI2 * nI2;
+        ps += nI2 * nc2;
+        ws += n2 * n2 + 2 * nB * nc2;
+        for (long j = 0; j < nI2; ++j) irc.push_back((int)C);
+        for (long j = 0; j < nc2; ++j) cbc.push_back((int)C);
+      }
+      U.nIrow = (long)irc.size();
+      U.ncb = (long)cbc.size();
+      U.asize = as;
+      U.psize = ps;
+      U.nwork = ws;
+      if (!irc.empty()) U.irc = upload(P, irc);
+      if (!cbc.empty()) U.cbc = upload(P, cbc);
+      U.aoff = upload(P, aoff);
+      U.poff = upload(P, poff);
+      U.woff = upload(P, woff);
+    }
+    if (!h.eptr.empty()) {
+      U.eptr = upload(P, h.eptr);
+      if (!h.efine.empty()) U.efine = upload(P, h.efine);
+    }
+    P->ul.push_back(U);
+  }
+  for (size_t i = 0; i + 1 < P->ul.size(); ++i)
+    if (P->ul[i].ncoarse > 0) {
+      P->ul[i].csptr = P->ul[i + 1].sptr;
+      P->ul[i].csface = P->ul[i + 1].sface;
+    }
+}
+
+}  // namespace
+
+hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, void* hip_stream,
+                                  hdg_handle* out) {
+  if (!mesh || !out || !kappa || !mesh->xy || !mesh->tri || !mesh->seeds) return HDG_ERR_INVALID_ARG;
+  if (mesh->nvert < 3 || mesh->ntri < 1 || mesh->nseeds < 1 || mesh->hlevels < 1 || mesh->hlevels > 16)
+    return HDG_ERR_INVALID_ARG;
+  if (k < 1 || k > 4) return HDG_ERR_UNSUPPORTED;
+  if (!(tau > 0.0) || !std::isfinite(tau)) return HDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  hdg_problem* P = new (std::nothrow) hdg_problem();
+  if (!P) return HDG_ERR_DEVICE;
+  try {
+    P->unstructured = true;
+    P->d = 2;
+    P->n = 0;
+    P->k = k;
+    P->tau = tau;
+    P->scheme = HDG_SCHEME_HDG;
+    P->codes = {HDG_SCHEME_HDG};
+    P->sym = true;
+    P->st = (hipStream_t)hip_stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
+    P->uh = std::make_unique<UHost>();
+    UHost& H = *P->uh;
+    H.build_reference(k);
+    H.build_mesh(mesh->nvert, mesh->xy, mesh->ntri, mesh->tri, mesh->seeds, mesh->nseeds, mesh->hlevels);
+    P->nelem = H.ntri;
+    P->nv = H.nv;
+    P->ne = k + 1;
+    P->nl = 3 * (k + 1);
+    P->nq = 1;
+    P->rd.uM = upload(P, H.Mh);
+    P->rd.uMinv = upload(P, H.Minvh);
+    P->rd.uD = upload(P, H.Dh);
+    P->rd.uE = upload(P, H.Eh);
+    P->rd.uF = upload(P, H.Fh);
+    P->rd.uH = upload(P, H.Hh);
+    P->rd.Jp = upload(P, H.Jp);
+    P->uxy = upload(P, H.xy);
+    P->utri = upload(P, H.tri);
+    upload_ulevels(P);
+    P->kqp = dalloc<double>(P, P->nelem, false);
+    P->Ae = dalloc<double>(P, P->nelem * P->nl * P->nl, false);
+    P->W = dalloc<double>(P, P->nelem * P->nv * P->nl, false);
+    P->bad = dalloc<int>(P, 1, false);
+    HDG_CHECK(hipHostMalloc((void**)&P->hbad, sizeof(int) * 4, hipHostMallocDefault));
+    HDG_CHECK(hipHostMalloc((void**)&P->hpin, sizeof(double) * SC_COUNT * HDG_MAX_NRHS, hipHostMallocDefault));
+    if (!check_kappa(P, kappa, HDG_KAPPA_PER_ELEMENT)) {
+      hdg_destroy(P);
+      return HDG_ERR_INVALID_ARG;
+    }
+    launch_tri_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->Ae, P->W, P->st);
+    HDG_CHECK(hipStreamSynchronize(P->st));
+    P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    hdg_default_opts(&P->opts);
+    *out = P;
+    return HDG_OK;
+  } catch (const HipError& e) {
+    hdg_destroy(P);
+    return map_error(e);
+  } catch (const std::bad_alloc&) {
+    hdg_destroy(P);
+    return HDG_ERR_DEVICE;
+  } catch (const std::exception&) {
+    hdg_destroy(P);
+    return HDG_ERR_INVALID_ARG;
+  }
 }
 
 hdg_status hdg_vcycle(hdg_handle P, const void* r, void* e, int precision, int nrhs) {
@@ -1829,6 +2149,8 @@ hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const*
                            const int* nrhs, double tol, double* const* lambda, hdg_solve_info* info,
                            int nstreams) {
   if (nprob < 1 || !hs || !rhs || !nrhs || !lambda || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  for (int i = 0; i < nprob; ++i)
+    if (hs[i] && hs[i]->unstructured) return HDG_ERR_UNSUPPORTED;
   if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
   for (int i = 0; i < nprob; ++i) {
     if (!hs[i] || !rhs[i] || !lambda[i] || nrhs[i] < 1) return HDG_ERR_INVALID_ARG;
@@ -1979,6 +2301,7 @@ hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const*
 
 hdg_status hdg_autotune(hdg_handle P, const hdg_mg_opts* base, int nrhs, hdg_mg_opts* best, double* us_per_rhs_it) {
   if (!P || !best || nrhs < 1 || nrhs > HDG_MAX_NRHS) return HDG_ERR_INVALID_ARG;
+  if (P->unstructured) return HDG_ERR_UNSUPPORTED;
   hdg_mg_opts b0;
   if (base)
     b0 = *base;
@@ -2069,6 +2392,7 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
                            const double* gdir, double* u, double* q) {
   if (!P || !lambda || !rhs || !u || !q) return HDG_ERR_INVALID_ARG;
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
+  if (P->unstructured) return HDG_ERR_UNSUPPORTED;
   if (!P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
   if (P->scheme == HDG_SCHEME_HDG)
@@ -2084,7 +2408,7 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
 hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, double tol, double* grad,
                        hdg_solve_info* info) {
   if (!P || !dJdu || !q_fwd || !grad || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
-  if (P->scheme != HDG_SCHEME_HDG || P->tau_kappa) return HDG_ERR_UNSUPPORTED;
+  if (P->scheme != HDG_SCHEME_HDG || P->tau_kappa || P->unstructured) return HDG_ERR_UNSUPPORTED;
   if (!P->built || !P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
   if (!P->ustar) {
@@ -2113,6 +2437,7 @@ hdg_status hdg_adjoint(hdg_handle P, const double* dJdu, const double* q_fwd, do
 
 hdg_status hdg_mass_apply(hdg_handle P, const double* u, double* out) {
   if (!P || !u || !out) return HDG_ERR_INVALID_ARG;
+  if (P->unstructured) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   launch_mass(P->d, P->k, P->nelem, P->rd, u, out, P->st);
   return HDG_OK;
@@ -2186,6 +2511,7 @@ hdg_status hdg_level_export(hdg_handle P, int level, double* out) {
   if (!P->built) return HDG_ERR_STATE;
   if (level < 0 || level >= (int)P->L.size()) return HDG_ERR_INVALID_ARG;
   const Level& L = P->L[level];
+  if (L.u && !L.u->tri) return HDG_ERR_UNSUPPORTED;  // macro-element maps of varying size
   HDG_CHECK(hipMemcpyAsync(out, L.Aelem, sizeof(double) * L.nelem * L.nl * L.nl, hipMemcpyDeviceToDevice, P->st));
   return HDG_OK;
   HDG_GUARD_END
@@ -2271,6 +2597,8 @@ hdg_status hdg_query(hdg_handle P, int what, long long* out) {
   const int nL = (int)P->L.size();
   if (what == HDG_Q_NT) {
     *out = P->nelem;
+  } else if (what == HDG_Q_NLAMBDA && P->unstructured) {
+    *out = P->ul[0].nface * P->ul[0].m;
   } else if (what == HDG_Q_NLAMBDA) {
     Level tmp;
     init_level(tmp, P->d, P->n, P->ne);

@@ -121,6 +121,101 @@ struct RefDevice {
          *H = nullptr, *M = nullptr, *Jp = nullptr;
   double *Kst = nullptr, *Nn = nullptr, *Dn = nullptr, *Dnode = nullptr;  // IPDG handles only
   double *Vq = nullptr, *Bd = nullptr, *Fr = nullptr, *Vnode = nullptr;    // RT-H handles only
+  // P^k triangles (unstructured handles only; the UHost reference matrices)
+  double *uM = nullptr, *uMinv = nullptr, *uD = nullptr, *uE = nullptr, *uF = nullptr, *uH = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Unstructured triangle meshes (umesh.cpp; host, built once per mesh).
+// A level has cells (triangles, or macro-elements of an agglomeration level)
+// with slots (their faces; -1: an edge on the domain boundary) and faces with
+// m trace values each (k + 1 on the finest level, 2 on P^1 levels).  Face f
+// joins cells fcell[2f] < fcell[2f+1] at their slots fslot[2f], fslot[2f+1];
+// its chain runs from vertex fstart to fend with length flen.  The
+// h-transition arrays describe the agglomeration into the next level.
+struct UHostLevel {
+  int m = 2;
+  bool tri = false;                 // cells are the triangles (three slots each)
+  long ncell = 0, nface = 0;
+  std::vector<long> sptr;           // [ncell + 1] slot offsets
+  std::vector<int> sface;           // [nslot] face of each slot, -1 none
+  std::vector<int> fcell, fslot;    // [2 nface]
+  std::vector<int> fstart, fend;    // [nface] chain end vertices
+  std::vector<double> flen;         // [nface] chain lengths
+  // h-transition to the next level (empty on the coarsest)
+  long ncoarse = 0;
+  std::vector<long> ccptr;          // [ncoarse + 1] fine cells of each coarse cell
+  std::vector<int> ccell;
+  std::vector<long> iptr;           // [ncoarse + 1] interior faces (E_I) of each coarse cell, ascending
+  std::vector<int> iface;
+  std::vector<long> bptr;           // [ncoarse + 1] boundary faces (E_B) of each coarse cell, ascending
+  std::vector<int> bface, bslot;    // ... and the coarse slot of each one's macro-edge
+  std::vector<int> sloc;            // [nslot] local face of every slot in its coarse cell (E_I first)
+  std::vector<int> fE;              // [nface] macro-edge of each E_B face, -1 for E_I
+  std::vector<double> fJ;           // [4 nface] J block of each E_B face: [fine DOF][macro-edge DOF]
+  // (on the coarse level) the finer faces of each macro-edge in chain order
+  std::vector<long> eptr;
+  std::vector<int> efine;
+};
+
+// largest dense local problem of a coarse cell (E_I and E_B values) and the
+// largest coarsest level of an unstructured hierarchy
+constexpr int UMACRO_MAX_DOFS = 1024;
+constexpr int UCOARSE_MAX = 4096;
+
+struct UHost {
+  int k = 1, nv = 0, ne = 0;
+  long nvert = 0, ntri = 0, nbedge = 0;
+  std::vector<double> xy;
+  std::vector<int> tri;
+  std::vector<int> nmacro;          // macro-elements per agglomeration level (level 1 first)
+  std::vector<UHostLevel> lev;      // finest first: P^k triangles, P^1 triangles (k > 1), T_hlevels .. T_1
+  // reference triangle (0,0), (1,0), (0,1), nodal P^k at the equispaced
+  // lattice, P^k edge traces nodal at GLL points of the edge parameter
+  std::vector<double> Mh, Minvh;    // [nv][nv] mass and its inverse
+  std::vector<double> Dh;           // [2][nv][nv] (d_r phi_i, phi_j)
+  std::vector<double> Eh;           // [3][nv][nv] edge s (from vertex s to s+1, unit parameter): <phi_i, phi_j>
+  std::vector<double> Fh;           // [3][nv][ne] <phi_i, mu_a> on edge s, mu in the edge's own direction
+  std::vector<double> Hh;           // [ne][ne] <mu_a, mu_b> on the unit parameter
+  std::vector<double> Jp;           // [ne][2] P^1 end values -> GLL values
+  void build_reference(int k);
+  void build_mesh(long nvert, const double* xy, long ntri, const int* tri, const double* seeds, int nseeds,
+                  int hlevels);
+  UHostLevel coarsen(UHostLevel& fine, const std::vector<int>& coarse_of, long ncoarse);
+};
+
+// Device copies of an unstructured level's index arrays (set up once per
+// mesh) and its per-build storage.  Cell maps are row-major per cell at
+// moff[c] (Level.Aelem in FP64, Am32 in FP32); triangle levels also keep
+// them AoSoA over triangles (Level.Af64 / Af32) for the element phase of the
+// apply.  z holds the element phase's products, one row per (cell, slot,
+// value): row zr[2f + side] + a is face f's value a from its side's cell.
+struct ULevel {
+  int m = 2;
+  bool tri = false;
+  long ncell = 0, nrow = 0, nface = 0;
+  long* sptr = nullptr;
+  int* sface = nullptr;
+  int* rcell = nullptr;   // [nrow] cell of each row
+  long* moff = nullptr;   // [ncell]
+  long msize = 0;         // entries of all cell maps
+  long* zr = nullptr;     // [2 nface]
+  int* fcell = nullptr;
+  int* fslot = nullptr;
+  float* Am32 = nullptr;
+  void* z[2] = {nullptr, nullptr};
+  // h-transition to the next level
+  long ncoarse = 0, nIrow = 0, ncb = 0, nwork = 0, asize = 0, psize = 0;
+  long* csptr = nullptr;  // the next level's slot offsets and slot faces
+  int* csface = nullptr;
+  long *iptr = nullptr, *bptr = nullptr, *ccptr = nullptr;
+  int *iface = nullptr, *bface = nullptr, *bslot = nullptr, *ccell = nullptr, *sloc = nullptr;
+  int *irc = nullptr, *cbc = nullptr;  // coarse cell of every interior row / restriction-share row
+  long *aoff = nullptr, *poff = nullptr, *woff = nullptr;
+  int* fE = nullptr;
+  double* fJ = nullptr;
+  long* eptr = nullptr;   // (coarse level) finer faces of each macro-edge
+  int* efine = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -171,6 +266,9 @@ struct Level {
   // symmetric (then R = P), its own array otherwise
   double* R64 = nullptr;      float* R32 = nullptr;
   bool sym = true;  // the level operator is symmetric
+  // unstructured levels: index arrays and element-phase storage (null on
+  // the grid levels)
+  ULevel* u = nullptr;
   // coarsest direct inverse (dense row-major nlam x nlam)
   double* Ainv64 = nullptr; float* Ainv32 = nullptr;
   // work vectors, [0] = FP64, [1] = FP32
@@ -301,6 +399,34 @@ template <typename T, typename M = T>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
                       Scratch* red, hipStream_t st, int nrhs = 1, int* nparts = nullptr);
 
+// unstructured.hip.  HDG element maps of P^k triangles (A^e row-major
+// [ntri][3ne][3ne]) and the load map W ([ntri][nv][3ne], b^e = W^T f for
+// nodal f); loads pulled per face; the P^1 Galerkin maps of the triangles;
+// per coarse cell the Schur complement, A_II^-1 and P = -A_II^-1 A_IB J
+// (eqs. Akm1, n_1_Ik) into the next level's maps; face-block inverses;
+// the coarsest dense inverse; AoSoA / FP32 copies of the maps.
+void launch_tri_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri, const double* kappa,
+                    double tau, double* Aelem, double* W, hipStream_t st);
+void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, double* g, hipStream_t st);
+void launch_tri_pgalerkin(int k, long ntri, const double* Jp, const double* A0, double* A1, hipStream_t st);
+void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P,
+                   double* Acoarse, double* work, hipStream_t st);
+void launch_udinv(const Level& L, hipStream_t st);
+void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st);
+void launch_umaps(const Level& L, hipStream_t st);
+void launch_to_f32(const double* x, float* y, long n, hipStream_t st);
+// unstructured trace kernels (dispatched from the launchers above when L.u
+// is set)
+template <typename T, typename M>
+void launch_uapply(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
+                   Scratch* red, hipStream_t st, int nrhs, int* nparts);
+template <typename T, typename M>
+void launch_ucorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st, int nrhs);
+template <typename T>
+void launch_urestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st, int nrhs);
+template <typename T, typename M>
+void launch_uprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs);
+
 // noalloc.hip: the device address of this device's fixed staging array
 // (looked up once per device) and its size in doubles
 double* scratch_ptr();
@@ -308,6 +434,9 @@ long scratch_capacity();
 // api.cpp: staging the load form of hdg_rhs needs, and hdg_rhs with the
 // staging buffer given (no allocation)
 long rhs_staging_doubles(const hdg_problem* P);
+// whether the handle forms g from this kind of data (unstructured handles:
+// nodal f with zero Dirichlet data only)
+bool rhs_supported(const hdg_problem* P, int kind, const double* gdir);
 void rhs_with_staging(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g, double* ebuf);
 
 }  // namespace hdg

@@ -50,6 +50,7 @@ extern "C" hdg_status hdg_rhs_noalloc(hdg_handle h, const double* rhs, int rhs_k
   if (!h || !rhs || !g) return HDG_ERR_INVALID_ARG;
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
   try {
+    if (!hdg::rhs_supported(h, rhs_kind, g_dirichlet)) return HDG_ERR_UNSUPPORTED;
     const long need = hdg::rhs_staging_doubles(h);
     if (need > hdg::RHS_SCRATCH_DOUBLES) return HDG_ERR_UNSUPPORTED;
     hdg::rhs_with_staging(h, rhs, rhs_kind, g_dirichlet, g, hdg::scratch_ptr());

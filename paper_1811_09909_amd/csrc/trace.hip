@@ -35,65 +35,6 @@ using namespace dev;
 #define HDG_APPLY_WPE 1
 #endif
 
-// Output of one face given acc = (A x)_F, per mode (x, b, y, rc, y32
-// already offset to the face's right-hand side); reductions add to part.
-// DSYM: the level's face-block inverses are stored as upper triangles.  M:
-// storage type of the face-block inverses (T, or FP32 under FP64 vectors).
-template <int D, int NE, typename T, int MODE, bool DSYM = false, typename M = T>
-__device__ inline void face_finish(long F, const acc_t<T>* acc, const M* __restrict__ Dinv, const T* x,
-                                   const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
-                                   T* __restrict__ rc, float* __restrict__ y32, double& part) {
-  constexpr int NC = 1 << (D - 1);
-  using A = acc_t<T>;
-  if (MODE == APPLY_Y) {
-#pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(acc[a]);
-  } else if (MODE == APPLY_RES) {
-#pragma unroll
-    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(A(bvec[F * NE + a]) - acc[a]);
-  } else if (MODE == APPLY_SWEEP || MODE == APPLY_SWEEP_DOT) {
-    A res[NE];
-#pragma unroll
-    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
-    if constexpr (DSYM)
-      dinv_update_sym<NE, T>(F, Dinv, x, res, y);
-    else
-      dinv_update<NE, T, M>(F, Dinv, x, res, y);
-    if (MODE == APPLY_SWEEP_DOT)  // Jp holds the FP64 vector of the dot product
-#pragma unroll
-      for (int a = 0; a < NE; ++a) part += Jp[F * NE + a] * (double)y[F * NE + a];
-  } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
-    A res[NE];
-#pragma unroll
-    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
-    A rcv[NC];
-#pragma unroll
-    for (int v = 0; v < NC; ++v) {
-      A s = A(0);
-#pragma unroll
-      for (int a = 0; a < NE; ++a) s += A(Jp[a * NC + v]) * res[a];
-      rc[F * NC + v] = T(s);
-      rcv[v] = A(T(s));  // the coarse first step starts from the stored residual
-    }
-    if (y)  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
-      dinv_update<NC, T, M>(F, Dinv, (const T*)nullptr, rcv, y);
-  } else if (MODE == APPLY_Y_DOT) {
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-      y[F * NE + a] = T(acc[a]);
-      part += (double)x[F * NE + a] * (double)T(acc[a]);
-    }
-  } else {  // APPLY_RES_NORM
-#pragma unroll
-    for (int a = 0; a < NE; ++a) {
-      const T v = T(A(bvec[F * NE + a]) - acc[a]);
-      y[F * NE + a] = v;
-      if (y32) y32[F * NE + a] = (float)v;
-      part += (double)v * (double)v;
-    }
-  }
-}
-
 // The trace apply of face-major levels with CH lanes per face (3D, k = 3:
 // 3,072 block entries per face, and only 95,232 faces at 32^3, so one lane
 // per face leaves under two waves per SIMD to hide the memory latency).
@@ -1112,6 +1053,10 @@ template <typename T, typename M>
 void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, const double* Jp, T* rc, float* y32,
                       Scratch* red, hipStream_t st, int nrhs, int* nparts) {
   if (L.nface == 0) return;
+  if (L.u) {
+    launch_uapply<T, M>(L, mode, x, b, y, Jp, rc, y32, red, st, nrhs, nparts);
+    return;
+  }
   double* partials = red ? red->partials : nullptr;
   const M* Af = nullptr;
   const M* Dv = nullptr;
@@ -1310,6 +1255,10 @@ void launch_prolong_p(const Level& L, int nc, const double* Jp, const T* ec, T* 
 
 template <typename T, typename M>
 void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restrict, T* cb, hipStream_t st, int nrhs) {
+  if (L.u) {
+    launch_ucorr<T, M>(L, rho, e, do_corr, do_restrict, cb, st, nrhs);
+    return;
+  }
   const M* Ai = sizeof(M) == 8 ? (const M*)L.AIIinv64 : (const M*)L.AIIinv32;
   const M* P = sizeof(M) == 8 ? (const M*)L.R64 : (const M*)L.R32;  // restriction block
   if (L.d == 2)
@@ -1323,6 +1272,10 @@ void launch_hcorr(const Level& L, const T* rho, T* e, int do_corr, int do_restri
 
 template <typename T>
 void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb, T* rc, hipStream_t st, int nrhs) {
+  if (L.u) {
+    launch_urestrict<T>(L, C, rho, cb, rc, st, nrhs);
+    return;
+  }
   if (C.nface == 0) return;
   if (L.d == 2)
     hipLaunchKernelGGL((hrestrict_kernel<2, T>), dim3(nblk(C.nface), nrhs), dim3(256), 0, st, L.n, rho, cb, rc);
@@ -1333,6 +1286,10 @@ void launch_hrestrict(const Level& L, const Level& C, const T* rho, const T* cb,
 
 template <typename T, typename M>
 void launch_hprolong(const Level& L, const Level& C, const T* ec, T* e, hipStream_t st, int nrhs) {
+  if (L.u) {
+    launch_uprolong<T, M>(L, C, ec, e, st, nrhs);
+    return;
+  }
   const M* P = sizeof(M) == 8 ? (const M*)L.P64 : (const M*)L.P32;
   const long nbf = nblk(C.nface);
   if (L.d == 2) {

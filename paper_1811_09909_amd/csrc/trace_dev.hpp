@@ -1003,6 +1003,65 @@ __device__ inline void face_item(long F, int n, const T* __restrict__ Af, const 
   }
 }
 
+// Output of one face given acc = (A x)_F, per mode (x, b, y, rc, y32
+// already offset to the face's right-hand side); reductions add to part.
+// DSYM: the level's face-block inverses are stored as upper triangles.  M:
+// storage type of the face-block inverses (T, or FP32 under FP64 vectors).
+template <int D, int NE, typename T, int MODE, bool DSYM = false, typename M = T>
+__device__ inline void face_finish(long F, const acc_t<T>* acc, const M* __restrict__ Dinv, const T* x,
+                                   const T* __restrict__ bvec, T* __restrict__ y, const double* __restrict__ Jp,
+                                   T* __restrict__ rc, float* __restrict__ y32, double& part) {
+  constexpr int NC = 1 << (D - 1);
+  using A = acc_t<T>;
+  if (MODE == APPLY_Y) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(acc[a]);
+  } else if (MODE == APPLY_RES) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) y[F * NE + a] = T(A(bvec[F * NE + a]) - acc[a]);
+  } else if (MODE == APPLY_SWEEP || MODE == APPLY_SWEEP_DOT) {
+    A res[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
+    if constexpr (DSYM)
+      dinv_update_sym<NE, T>(F, Dinv, x, res, y);
+    else
+      dinv_update<NE, T, M>(F, Dinv, x, res, y);
+    if (MODE == APPLY_SWEEP_DOT)  // Jp holds the FP64 vector of the dot product
+#pragma unroll
+      for (int a = 0; a < NE; ++a) part += Jp[F * NE + a] * (double)y[F * NE + a];
+  } else if (MODE == APPLY_RES_PRESTRICT) {  // residual restricted by J_N^T (p-coarsening)
+    A res[NE];
+#pragma unroll
+    for (int a = 0; a < NE; ++a) res[a] = A(bvec[F * NE + a]) - acc[a];
+    A rcv[NC];
+#pragma unroll
+    for (int v = 0; v < NC; ++v) {
+      A s = A(0);
+#pragma unroll
+      for (int a = 0; a < NE; ++a) s += A(Jp[a * NC + v]) * res[a];
+      rc[F * NC + v] = T(s);
+      rcv[v] = A(T(s));  // the coarse first step starts from the stored residual
+    }
+    if (y)  // first block-Jacobi step of the P1 level: y = D_c^-1 rc (Dinv = coarse blocks)
+      dinv_update<NC, T, M>(F, Dinv, (const T*)nullptr, rcv, y);
+  } else if (MODE == APPLY_Y_DOT) {
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      y[F * NE + a] = T(acc[a]);
+      part += (double)x[F * NE + a] * (double)T(acc[a]);
+    }
+  } else {  // APPLY_RES_NORM
+#pragma unroll
+    for (int a = 0; a < NE; ++a) {
+      const T v = T(A(bvec[F * NE + a]) - acc[a]);
+      y[F * NE + a] = v;
+      if (y32) y32[F * NE + a] = (float)v;
+      part += (double)v * (double)v;
+    }
+  }
+}
+
 template <int NE, typename T, bool DSYM = false, typename M = T>
 __device__ inline void jacobi0_item(long F, const M* __restrict__ Dinv, const T* r, T* e) {
   acc_t<T> rv[NE];

@@ -7,6 +7,7 @@ it, or without a GPU, every call raises.
 """
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -60,12 +61,47 @@ class Problem:
                                               1 if store_recovery else 0, ctypes.c_void_p(self.stream.cuda_stream),
                                               ctypes.byref(h)), "hdg_setup_scheme")
         self.h = h
+        self.unstructured = False
         self.nT = self.query(L.Q_NT)
         self.nlam = self.query(L.Q_NLAMBDA)
         self.nv = self.query(L.Q_NV)
         self.nq = self.query(L.Q_NQ)
         self.built = False
         self.version = 0  # bumped by every update_kappa / build: operator state of the handle
+
+    @classmethod
+    def unstructured(cls, vertices, triangles, k, kappa, seeds, hlevels, tau=1.0, device="cuda"):
+        """HDG on an unstructured triangle mesh with the seed-point
+        agglomeration hierarchy (``hdg_setup_unstructured``): host vertex,
+        triangle and seed arrays, kappa one value per triangle."""
+        self = cls.__new__(cls)
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HDG library needs a GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        self.d, self.n, self.k, self.tau = 2, 0, k, float(tau)
+        self.kind = L.KAPPA_PER_ELEMENT
+        self.scheme = "hdg"
+        xy = np.ascontiguousarray(vertices, dtype=np.float64)
+        tri = np.ascontiguousarray(triangles, dtype=np.int32)
+        sd = np.ascontiguousarray(seeds, dtype=np.float64)
+        self._host = (xy, tri, sd)
+        mesh = L.UMesh(len(xy), xy.ctypes.data, len(tri), tri.ctypes.data, len(sd), sd.ctypes.data, int(hlevels))
+        kap = _dev(kappa, torch.float64, self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        L.check(self.lib.hdg_setup_unstructured(ctypes.byref(mesh), k, self.tau, _vp(kap),
+                                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                "hdg_setup_unstructured")
+        self.h = h
+        self.unstructured = True
+        self.nT = self.query(L.Q_NT)
+        self.nlam = self.query(L.Q_NLAMBDA)
+        self.nv = self.query(L.Q_NV)
+        self.nq = self.query(L.Q_NQ)
+        self.built = False
+        self.version = 0
+        return self
 
     # -- lifecycle ---------------------------------------------------------
     def close(self):
@@ -195,6 +231,11 @@ class Problem:
         return e
 
     def level_export(self, level):
+        if self.unstructured:  # triangle levels: P^k maps, then P^1 maps (k > 1)
+            nl = 3 * (self.k + 1) if level == 0 else 6
+            out = torch.empty(self.nT, nl, nl, dtype=torch.float64, device=self.device)
+            L.check(self.lib.hdg_level_export(self.h, level, _vp(out)), "hdg_level_export")
+            return out
         if level == 0:
             nel, nl = self.nT, 2 * self.d * (self.k + 1) ** (self.d - 1)
         else:

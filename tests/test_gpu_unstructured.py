@@ -1,0 +1,226 @@
+"""Parity of the unstructured-mesh path on the GPU (through the C ABI) with
+the FP64 CPU oracle (Sec. 2 on P^k triangles; Sec. 3.1.2 seed-point
+agglomeration and arc-length P^1 macro-edges; Sec. 3 multigrid).
+
+Element maps and loads, every level operator of the agglomeration
+hierarchy, block-Jacobi sweeps, the V-cycle (FP64, FP32 and the mixed
+cycle), MG / CG / GMRES counts against the oracle's and solutions against
+a direct solve, several right-hand sides and graph replay against single
+eager solves, and the error paths.  Meshes: the synthetic box with eight
+holes (Example II's setting: kappa = 1 or log-uniform, f = 1 or N(0, 1)).
+FP64 bound for element maps and loads: 4 eps cond(L_T), at least 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mg as omg
+from oracle import unstructured as U
+from paper_1811_09909_amd import inputs
+
+from ._helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(nx, k, strategy=1, seed=0, kap_range=None):
+    w = inputs.unstructured2d(nx, k, strategy=strategy)
+    m = U.TriMesh(w.vertices, w.triangles)
+    kap = w.kappa if kap_range is None else 10.0 ** np.random.default_rng(seed).uniform(*kap_range, m.nel)
+    return w, m, kap
+
+
+def _gpu(torch, w, k, kap, **bk):
+    from paper_1811_09909_amd.hdg import Problem
+    P = Problem.unstructured(w.vertices, w.triangles, k, torch.as_tensor(kap), w.seeds, w.hlevels, tau=w.tau)
+    if bk:
+        P.build(**bk)
+    return P
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_u_element_maps_and_rhs(torch_cuda, k):
+    say(f"[unstructured maps] nx=8 k={k}")
+    w, m, kap = _case(8, k, kap_range=(-1, 1))
+    O = U.TriHDG(m, k, w.tau, kap)
+    P = _gpu(torch_cuda, w, k, kap)
+    Ae = P.level_export(0).cpu().numpy()
+    Ao = O.all_element_dtn()
+    eps = np.finfo(float).eps
+    bound = max(1e-12, 4 * eps * max(np.linalg.cond(O.local_matrix(t)[0]) for t in range(m.nel)))
+    ent = max(np.abs(Ae[t] - Ao[t]).max() / np.abs(Ao[t]).max() for t in range(m.nel))
+    say(f"  maps entrywise {ent:.2e} (bound {bound:.1e})")
+    assert ent <= bound
+    f = np.random.default_rng(k).standard_normal((m.nel, O.nv))
+    _, g, _ = O.assemble(f)
+    gg = P.rhs(torch_cuda.as_tensor(f)).cpu().numpy()
+    sc = np.abs(g).max()
+    err = np.abs(gg - g).max() / sc
+    say(f"  g max err / max|g| {err:.2e}")
+    assert err <= bound
+
+
+def _oracle_h(m, k, kap, w, **kw):
+    O = U.TriHDG(m, k, w.tau, kap)
+    A, _, _ = O.assemble()
+    H = U.UHierarchy(A, m, k, U.agglomerate(m, w.seeds, w.hlevels), **kw)
+    return O, A, H
+
+
+@pytest.mark.parametrize("nx,k,strategy", [(16, 1, 1), (16, 3, 2), (32, 2, 1)])
+def test_u_hierarchy_levels_cycle(torch_cuda, nx, k, strategy):
+    from paper_1811_09909_amd import _lib as L
+    say(f"[unstructured hierarchy] nx={nx} k={k} strategy={strategy}")
+    w, m, kap = _case(nx, k, strategy, kap_range=(-1, 1))
+    O, A, H = _oracle_h(m, k, kap, w, local_corr=omg.LC_BOTH)
+    P = _gpu(torch_cuda, w, k, kap, local_corr=omg.LC_BOTH)
+    assert P.level_sizes() == [Lv.A.shape[0] for Lv in H.levels]
+    rng = np.random.default_rng(nx + k)
+    for i, Lv in enumerate(H.levels):
+        x = rng.standard_normal(Lv.A.shape[0])
+        y = P.level_apply(i, torch_cuda.as_tensor(x)).cpu().numpy()
+        ea = relerr(y, Lv.A @ x)
+        r = rng.standard_normal(Lv.A.shape[0])
+        e = P.level_smooth(i, torch_cuda.as_tensor(r), 2).cpu().numpy()
+        es = relerr(e, omg.block_jacobi(Lv, r, 2))
+        y32 = P.level_apply(i, torch_cuda.as_tensor(x, dtype=torch_cuda.float32), precision=L.FP32).cpu().numpy()
+        say(f"  level {i} ({Lv.A.shape[0]} values): apply {ea:.2e} sweeps {es:.2e} apply fp32 {relerr(y32, Lv.A @ x):.1e}")
+        assert ea <= 1e-12 and es <= 1e-11
+        assert relerr(y32, Lv.A @ x) <= 1e-5
+    r = rng.standard_normal(A.shape[0])
+    ev = H.vcycle(r)
+    e64 = P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy()
+    e32 = P.vcycle(torch_cuda.as_tensor(r, dtype=torch_cuda.float32), precision=L.FP32).cpu().numpy()
+    emx = P.vcycle(torch_cuda.as_tensor(r), precision=L.MIXED_CYCLE).cpu().numpy()
+    say(f"  vcycle fp64 {relerr(e64, ev):.2e} fp32 {relerr(e32, ev):.1e} mixed {relerr(emx, ev):.1e}")
+    assert relerr(e64, ev) <= 1e-10
+    assert relerr(e32, ev) <= 1e-4 and relerr(emx, ev) <= 1e-4
+
+
+@pytest.mark.parametrize("nx,k", [(16, 1), (16, 3), (32, 2)])
+def test_u_solves_match_oracle(torch_cuda, nx, k):
+    """Example II's setting (kappa = 1, f = 1, tau = 1): MG, CG and GMRES
+    counts at 1e-10 equal the oracle's (CG and GMRES within one), and the
+    solutions match a direct solve."""
+    from paper_1811_09909_amd import _lib as L
+    w, m, kap = _case(nx, k)
+    O, A, H = _oracle_h(m, k, kap, w)
+    _, g, _ = O.assemble(w.f)
+    lam_d = spla.spsolve(A.tocsc(), g)
+    ro = {"mg": omg.mg_solve(H, A, g, tol=1e-10).iters, "pcg": omg.pcg_solve(H, A, g, tol=1e-10).iters,
+          "gmres": omg.gmres_solve(H, A, g, tol=1e-10, side="right").iters}
+    P = _gpu(torch_cuda, w, k, kap)
+    f = torch_cuda.as_tensor(w.f)
+    for name, meth in (("mg", L.METHOD_MG), ("pcg", L.METHOD_PCG), ("gmres", L.METHOD_GMRES)):
+        P.build(method=meth)
+        lam, info = P.solve(f, tol=1e-10)
+        lam = lam.cpu().numpy()
+        res = np.linalg.norm(g - A @ lam) / np.linalg.norm(g)
+        say(f"[unstructured solve] nx={nx} k={k} {name}: GPU {info['iters']} oracle {ro[name]} "
+            f"relres {res:.1e} vs direct {relerr(lam, lam_d):.1e}")
+        assert res <= 1.01e-10
+        assert relerr(lam, lam_d) <= 1e-8
+        if name == "mg":
+            assert info["iters"] == ro[name]
+        else:
+            assert abs(info["iters"] - ro[name]) <= 1
+
+
+def test_u_mixed_precision_and_replay(torch_cuda):
+    """CG with the mixed cycle (FP32 operator blocks, FP64 vectors) reaches
+    1e-10 in the true residual within three iterations of FP64; graph
+    replay equals eager launches bit for bit; two right-hand sides iterated
+    together (the smaller one then takes extra iterations) meet the
+    tolerance and agree with their single solves."""
+    from paper_1811_09909_amd import _lib as L
+    w, m, kap = _case(32, 3, kap_range=(-1, 1))
+    O = U.TriHDG(m, 3, w.tau, kap)
+    f = np.random.default_rng(5).standard_normal((2, m.nel, O.nv))
+    A, g0, _ = O.assemble(f[0])
+    P = _gpu(torch_cuda, w, 3, kap)
+    P.build(method=L.METHOD_PCG)
+    l64, i64 = P.solve(torch_cuda.as_tensor(f[0]), tol=1e-10)
+    P.build(method=L.METHOD_PCG, precision=L.MIXED)
+    lmx, imx = P.solve(torch_cuda.as_tensor(f[0]), tol=1e-10)
+    res = np.linalg.norm(g0 - A @ lmx.cpu().numpy()) / np.linalg.norm(g0)
+    say(f"[unstructured mixed] CG FP64 {i64['iters']} mixed {imx['iters']} relres {res:.1e} "
+        f"vs FP64 {relerr(lmx.cpu().numpy(), l64.cpu().numpy()):.1e}")
+    assert res <= 1.01e-10 and imx["iters"] <= i64["iters"] + 3
+    for meth in (L.METHOD_MG, L.METHOD_PCG):
+        P.build(method=meth, nrhs=2)
+        both, _ = P.solve(torch_cuda.as_tensor(f), nrhs=2, tol=1e-10)
+        P.build(method=meth, variant=L.VARIANT_NO_GRAPH)
+        one = [P.solve(torch_cuda.as_tensor(f[r]), tol=1e-10)[0] for r in range(2)]
+        P.build(method=meth)
+        gr = P.solve(torch_cuda.as_tensor(f[0]), tol=1e-10)[0]
+        assert torch_cuda.equal(gr, one[0])
+        both = both.reshape(2, -1)
+        for r in range(2):
+            _, gr_, _ = O.assemble(f[r])
+            res = np.linalg.norm(gr_ - A @ both[r].cpu().numpy()) / np.linalg.norm(gr_)
+            e = relerr(both[r].cpu().numpy(), one[r].cpu().numpy())
+            say(f"  method {meth} rhs {r}: together relres {res:.1e}, vs single {e:.1e}")
+            assert res <= 1.05e-10 and e <= 1e-8
+
+
+def test_u_example2_counts(torch_cuda):
+    """Example II's size (about 6,600 triangles, five agglomeration levels,
+    seven levels in all at k > 1): GPU MG and GMRES counts at 1e-9 equal the
+    oracle's for both seed strategies."""
+    from paper_1811_09909_amd import _lib as L
+    for strategy in (1, 2):
+        for k in (1, 2):
+            w, m, kap = _case(45, k, strategy)
+            O, A, H = _oracle_h(m, k, kap, w)
+            _, g, _ = O.assemble(w.f)
+            r1 = omg.mg_solve(H, A, g, tol=1e-9)
+            r2 = omg.gmres_solve(H, A, g, tol=1e-9, side="right")
+            P = _gpu(torch_cuda, w, k, kap, method=L.METHOD_MG)
+            f = torch_cuda.as_tensor(w.f)
+            _, im = P.solve(f, tol=1e-9)
+            P.build(method=L.METHOD_GMRES)
+            _, ig = P.solve(f, tol=1e-9)
+            say(f"[example II] strategy {strategy} k={k} levels {len(H.levels)}: MG GPU {im['iters']} oracle "
+                f"{r1.iters}; GMRES GPU {ig['iters']} oracle {r2.iters}")
+            assert im["iters"] == r1.iters and abs(ig["iters"] - r2.iters) <= 1
+
+
+def test_u_error_paths(torch_cuda):
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd.hdg import Problem
+    w, m, kap = _case(8, 1)
+    kt = torch_cuda.as_tensor(kap)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        Problem.unstructured(w.vertices, w.triangles, 5, kt, w.seeds, w.hlevels)
+    bad = w.triangles.copy()
+    bad[0] = bad[0][[0, 2, 1]]
+    with pytest.raises(RuntimeError, match="invalid"):
+        Problem.unstructured(w.vertices, bad, 1, kt, w.seeds, w.hlevels)
+    with pytest.raises(RuntimeError, match="invalid"):
+        Problem.unstructured(w.vertices, w.triangles, 1, -kt, w.seeds, w.hlevels)
+    P = Problem.unstructured(w.vertices, w.triangles, 1, kt, w.seeds, w.hlevels)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.build(smoother=L.SMOOTHER_JACOBI)
+    P.build()
+    f = torch_cuda.ones(m.nel, 3, dtype=torch_cuda.float64)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.rhs(f, gdir=torch_cuda.zeros(10, dtype=torch_cuda.float64))
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.reconstruct(torch_cuda.zeros(P.nlam, dtype=torch_cuda.float64), f)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.update_kappa(kt)

@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--steps3d", type=int, default=2)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--no-ipdg", action="store_true", help="skip the NIPG-H and multinumerics legs")
+    ap.add_argument("--no-unstructured", action="store_true", help="skip the unstructured-mesh leg")
+    ap.add_argument("--unx", type=int, default=256, help="unstructured leg: grid spacing 1/unx of the mesh points")
+    ap.add_argument("--uk", type=int, default=3, help="unstructured leg: polynomial degree")
     ap.add_argument("--no-errors", action="store_true", help="skip the solve to the FP64 floor (error report)")
     ap.add_argument("--ref-tol", type=float, default=1e-13,
                     help="tolerance of the FP64 reference solve (stops at its floor if not reachable)")
@@ -433,6 +436,61 @@ def multinumerics_legs(args):
     return out
 
 
+def unstructured_legs(args):
+    """HDG on the unstructured box with eight holes (Example II's setting:
+    kappa = 1, f = 1, tau = 1) with the seed-point agglomeration hierarchy:
+    setup (host agglomeration + element maps), then CG + V-cycle to 1e-10 in
+    FP64 and with the mixed cycle, and MG as a solver in FP64; median step
+    times on the headline's launch path; the finest-level apply and sweeps
+    event-timed in one more mixed solve."""
+    import torch
+    from paper_1811_09909_amd import _lib as L
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import Problem
+    k = args.uk
+    wl = inputs.unstructured2d(args.unx, k)
+    kap = torch.as_tensor(wl.kappa, device="cuda")
+    f = torch.as_tensor(wl.f, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Problem.unstructured(wl.vertices, wl.triangles, k, kap, wl.seeds, wl.hlevels, tau=wl.tau)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    out = {"workload": wl.name, "triangles": int(len(wl.triangles)), "trace_dofs": P.nlam,
+           "setup_ms": round(1e3 * t_setup, 2)}
+    lams = {}
+    for nm, meth, prec in (("pcg_fp64", L.METHOD_PCG, L.FP64), ("pcg_mixed", L.METHOD_PCG, L.MIXED),
+                           ("mg_fp64", L.METHOD_MG, L.FP64)):
+        P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH if meth == L.METHOD_PCG else L.LC_PRE,
+                precision=prec, method=meth, max_it=500)
+        out["levels"] = P.level_sizes()
+        progress(f"unstructured {nm} leg: {len(wl.triangles)} triangles k={k}, {P.nlam} trace DOFs")
+        times, lam, infos = timed_solves(P, f, args.tol, args.steps, 1)
+        ms = 1e3 * median(times)
+        progress(f"unstructured {nm}: {ms:.1f} ms/solve, {infos[-1]['iters']} iterations")
+        lams[nm] = lam
+        out[nm] = {"value": round(P.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos),
+                   "build_ms": round(infos[-1]["t_build_ms"], 2)}
+    out["lambda_mixed_vs_fp64"] = rel(lams["pcg_mixed"], lams["pcg_fp64"])
+    out["mixed_over_fp64"] = round(out["pcg_mixed"]["value"] / out["pcg_fp64"]["value"], 3)
+    P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH, precision=L.MIXED, method=L.METHOD_PCG, max_it=500)
+    P.profile_begin()
+    P.solve(f, tol=args.tol)
+    kern = {}
+    for mode, name in [(0, "apply"), (2, "sweep"), (3, "residual_prestrict"), (6, "sweep_rz")]:
+        for pr, pn in [(L.FP64, "fp64"), (L.MIXED_CYCLE, "fp32ops_fp64vec")]:
+            r = P.profile_read(mode, pr)
+            if r["launches"]:
+                t = r["total_ms"] / r["launches"]
+                gbs = r["bytes_per_launch"] / (t * 1e-3) / 1e9
+                kern[f"{name}_{pn}"] = {"launches": r["launches"], "avg_ms": round(t, 5), "GBps": round(gbs, 1),
+                                        "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["kernels"] = kern
+    P.close()
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_probe:
@@ -585,6 +643,12 @@ def main():
             multi = multinumerics_legs(args)
         except Exception as e:  # reported; the headline stands on its own
             multi = {"error": str(e)[:300]}
+    unst = None
+    if not args.no_unstructured:
+        try:
+            unst = unstructured_legs(args)
+        except Exception as e:  # reported; the headline stands on its own
+            unst = {"error": str(e)[:300]}
     batch = None
     if not args.no_batched:
         progress("batched leg")
@@ -619,7 +683,8 @@ def main():
                    "setup_ms": round(1e3 * t_setup, 2), "build_ms_mixed": round(1e3 * resmx["build_s"], 2),
                    "reconstruct_ms": round(1e3 * t_rec, 3),
                    "end_to_end_dofs_per_s": round(N / (t_setup + resmx["build_s"] + resmx["ms_per_step"] / 1e3), 1),
-                   "errors": errors, "diffusion3d": cube, "ipdg2d": ipdg, "multinumerics2d": multi, "batched": batch},
+                   "errors": errors, "diffusion3d": cube, "ipdg2d": ipdg, "multinumerics2d": multi,
+                   "unstructured2d": unst, "batched": batch},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -1557,8 +1557,8 @@ hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
     Li.sweeps = o.sweeps * (o.growth == 2 ? (1 << std::min(i, 20)) : 1);
     if (U.tri) {
       const long nn = 9L * U.m * U.m;
-      Li.Af64 = dalloc<double>(P, pad64(U.ncell) * vpad<double>(nn), true);
-      Li.Af32 = dalloc<float>(P, pad64(U.ncell) * vpad<float>(nn), true);
+      Li.Af64 = dalloc<double>(P, pad64(U.ncell) * pk_pad<double>(nn), true);
+      Li.Af32 = dalloc<float>(P, pad64(U.ncell) * pk_pad<float>(nn), true);
       U.Am32 = nullptr;
     } else {
       U.Am32 = dalloc<float>(P, std::max(U.msize, 1L), true);
@@ -1600,6 +1600,7 @@ void upload_ulevels(hdg_problem* P) {
     U.nface = h.nface;
     const long nslot = h.sptr[h.ncell];
     U.nrow = nslot * h.m;
+    U.zstride = 1;
     U.sptr = upload(P, h.sptr);
     U.sface = upload(P, h.sface);
     if (h.nface > 0) {
@@ -2575,9 +2576,12 @@ hdg_status hdg_profile_read(hdg_handle P, int kernel, long long* launches, doubl
   const double sm = f32ops ? 4.0 : ((kernel % 2) ? 4.0 : 8.0);  // bytes per stored operator entry
   const double s = f32ops ? 8.0 : sm;                             // bytes per vector entry
   const double N = (double)L.nlam;
-  // operator bytes: each element row once (face-major), or the packed upper
-  // triangle of each element map (element-major)
-  double bytes = L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * sm : (double)L.nface * 2.0 * L.ne * L.nl * sm;
+  // operator bytes: each element row once (face-major), the packed upper
+  // triangle of each element map (element-major), or every triangle's whole
+  // map (unstructured: both phases of the apply)
+  double bytes = L.u ? (double)L.nelem * L.nl * L.nl * sm
+                     : L.packed ? (double)L.nelem * (L.nl * (L.nl + 1) / 2) * sm
+                                : (double)L.nface * 2.0 * L.ne * L.nl * sm;
   if (mode == APPLY_Y) bytes += 2.0 * N * s;
   if (mode == APPLY_RES) bytes += 3.0 * N * s;
   // face-block inverses: full blocks, or upper triangles on element-major levels

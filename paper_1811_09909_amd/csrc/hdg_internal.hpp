@@ -187,9 +187,11 @@ struct UHost {
 // Device copies of an unstructured level's index arrays (set up once per
 // mesh) and its per-build storage.  Cell maps are row-major per cell at
 // moff[c] (Level.Aelem in FP64, Am32 in FP32); triangle levels also keep
-// them AoSoA over triangles (Level.Af64 / Af32) for the element phase of the
-// apply.  z holds the element phase's products, one row per (cell, slot,
-// value): row zr[2f + side] + a is face f's value a from its side's cell.
+// them AoSoA over triangles in 16-byte groups (pk_off; Level.Af64 / Af32)
+// for the element phase of the apply.  z holds the element phase's
+// products, one row per (cell, slot, value): face f's value a from its
+// side's cell sits at zr[2f + side] + a * zstride (zstride 1: rows of a
+// face side are consecutive).
 struct ULevel {
   int m = 2;
   bool tri = false;
@@ -200,6 +202,7 @@ struct ULevel {
   long* moff = nullptr;   // [ncell]
   long msize = 0;         // entries of all cell maps
   long* zr = nullptr;     // [2 nface]
+  int zstride = 1;
   int* fcell = nullptr;
   int* fslot = nullptr;
   float* Am32 = nullptr;

@@ -440,15 +440,16 @@ __global__ void __launch_bounds__(256) udense_inverse_kernel(int N, double* __re
   }
 }
 
-// row-major triangle maps -> AoSoA over triangles (FP64 and FP32)
+// row-major triangle maps -> AoSoA over triangles in 16-byte groups (FP64
+// and FP32)
 __global__ void tri_aos_kernel(long ntri, int nn, const double* __restrict__ A, double* __restrict__ A64,
                                float* __restrict__ A32) {
   const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (idx >= ntri * nn) return;
   const long t = idx / nn;
   const int e = (int)(idx % nn);
-  A64[aos_off<double>(t, vpad<double>(nn), e)] = A[idx];
-  A32[aos_off<float>(t, vpad<float>(nn), e)] = (float)A[idx];
+  A64[pk_off<double>(t, nn, e)] = A[idx];
+  A32[pk_off<float>(t, nn, e)] = (float)A[idx];
 }
 
 __global__ void f32_kernel(const double* __restrict__ x, float* __restrict__ y, long n) {
@@ -458,37 +459,53 @@ __global__ void f32_kernel(const double* __restrict__ x, float* __restrict__ y, 
 
 // ---------------------------------------------------------------------------
 // trace kernels
-// element phase, triangle levels: lane t forms z_t = A_t x_t (3 NE rows)
-template <int NE, typename T, typename M>
-__global__ void __launch_bounds__(256) utri_phase_kernel(long ntri, long nrow, long N, const int* __restrict__ sface,
-                                                         const M* __restrict__ Af, const T* __restrict__ x,
-                                                         T* __restrict__ z) {
-  constexpr int NL = 3 * NE;
+// element phase, triangle levels: workgroup b takes the 64 triangles
+// 64 b .. 64 b + 63 (one per lane) and its CH waves split their 3 NE rows
+// (wave w: rows w RA .., RA = ceil(3 NE / CH)), so that every map load of a
+// wave is one contiguous segment and a level of 2 10^5 triangles still
+// gives each SIMD enough waves to hide the memory latency; each lane
+// gathers its triangle's traces itself.  The products go through LDS and
+// leave as one contiguous block (z row-major per triangle), so that the
+// face phase reads each side's values as one short segment.
+template <int NE, typename T, typename M, int CH>
+__global__ void __launch_bounds__(64 * CH) utri_phase_kernel(long ntri, long nrow, long N,
+                                                             const int* __restrict__ sface, const M* __restrict__ Af,
+                                                             const T* __restrict__ x, T* __restrict__ z) {
+  constexpr int NL = 3 * NE, RA = (NL + CH - 1) / CH;
   using A = acc_t<T>;
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= ntri) return;
+  __shared__ T zs[LANES * NL];
+  const int lane = threadIdx.x % LANES, w = threadIdx.x / LANES;
+  const long t0 = blockIdx.x * (long)LANES, t = t0 + lane;
   const int rhs = blockIdx.y;
   x += rhs * N;
   z += rhs * nrow;
-  A xs[NL];
+  if (t < ntri) {
+    A xs[NL];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    const int f = sface[3 * t + s];
+    for (int s = 0; s < 3; ++s) {
+      const int f = sface[3 * t + s];
 #pragma unroll
-    for (int b = 0; b < NE; ++b) xs[s * NE + b] = f >= 0 ? A(x[(long)f * NE + b]) : A(0);
-  }
-  const M* blk = Af + aos_item<M>(t, vpad<M>(NL * NL));
-  constexpr int V = vw<M>();
-#pragma unroll
-  for (int r = 0; r < NL; ++r) {
-    A acc = A(0);
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const int e = r * NL + j;
-      acc += A(blk[(e / V) * (LANES * V) + e % V]) * xs[j];
+      for (int b = 0; b < NE; ++b) xs[s * NE + b] = f >= 0 ? A(x[(long)f * NE + b]) : A(0);
     }
-    z[t * NL + r] = T(acc);
+    constexpr int V = pvw<M>();
+    const M* blk = Af + (t / LANES) * pk_pad<M>(NL * NL) * LANES + (t % LANES) * V;
+#pragma unroll
+    for (int rr = 0; rr < RA; ++rr) {
+      const int r = w * RA + rr;
+      if (r < NL) {
+        A acc = A(0);
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          const int e = r * NL + j;
+          acc += A(blk[(e / V) * (LANES * V) + e % V]) * xs[j];
+        }
+        zs[lane * NL + r] = T(acc);
+      }
+    }
   }
+  __syncthreads();
+  const long cnt = (ntri - t0 < LANES ? ntri - t0 : LANES) * NL;
+  for (long i = threadIdx.x; i < cnt; i += LANES * CH) z[t0 * NL + i] = zs[i];
 }
 
 // element phase, agglomeration levels: one lane per map row
@@ -522,7 +539,7 @@ __global__ void __launch_bounds__(256) ucell_phase_kernel(long nrow, long N, int
 // workgroups walk the faces blockIdx.x * 256, + gridDim.x * 256, ... and
 // write one partial sum each (reducing modes)
 template <int NE, typename T, int MODE, typename M>
-__global__ void __launch_bounds__(256) uface_kernel(long nface, long nrow, const long* __restrict__ zr,
+__global__ void __launch_bounds__(256) uface_kernel(long nface, long nrow, const long* __restrict__ zr, int zs,
                                                     const T* __restrict__ z, const M* __restrict__ Dinv,
                                                     const T* __restrict__ x, const T* __restrict__ bvec,
                                                     T* __restrict__ y, const double* __restrict__ Jp,
@@ -547,7 +564,7 @@ __global__ void __launch_bounds__(256) uface_kernel(long nface, long nrow, const
     const T* z1 = z + zr[2 * F + 1];
     A acc[NE];
 #pragma unroll
-    for (int a = 0; a < NE; ++a) acc[a] = A(z0[a]) + A(z1[a]);
+    for (int a = 0; a < NE; ++a) acc[a] = A(z0[a * zs]) + A(z1[a * zs]);
     face_finish<2, NE, T, MODE, false, M>(F, acc, Dinv, x, bvec, y, Jp, rc, y32, part);
   }
   if constexpr (RED) {
@@ -773,9 +790,11 @@ void launch_uapply(const Level& L, int mode, const T* x, const T* b, T* y, const
   T* z = (T*)U.z[sizeof(T) == 8 ? 0 : 1];
   if (U.tri) {
     const M* Af = sizeof(M) == 8 ? (const M*)L.Af64 : (const M*)L.Af32;
+    const unsigned nb = (unsigned)((U.ncell + LANES - 1) / LANES);
     dispatch_m(U.m, [&](auto M_) {
       constexpr int NE = decltype(M_)::value;
-      hipLaunchKernelGGL((utri_phase_kernel<NE, T, M>), dim3(nb256(U.ncell), nrhs), dim3(256), 0, st, U.ncell, U.nrow,
+      constexpr int CH = NE == 2 ? 3 : 4;
+      hipLaunchKernelGGL((utri_phase_kernel<NE, T, M, CH>), dim3(nb, nrhs), dim3(64 * CH), 0, st, U.ncell, U.nrow,
                          L.nlam, U.sface, Af, x, z);
     });
   } else {
@@ -791,7 +810,7 @@ void launch_uapply(const Level& L, int mode, const T* x, const T* b, T* y, const
   dispatch_m(U.m, [&](auto M_) {
     constexpr int NE = decltype(M_)::value;
 #define HDG_UF(MM)                                                                                                \
-  hipLaunchKernelGGL((uface_kernel<NE, T, MM, M>), dim3(g, nrhs), dim3(256), 0, st, U.nface, U.nrow, U.zr, z, Dv, x, \
+  hipLaunchKernelGGL((uface_kernel<NE, T, MM, M>), dim3(g, nrhs), dim3(256), 0, st, U.nface, U.nrow, U.zr, U.zstride, z, Dv, x, \
                      b, y, Jp, rc, y32, partials)
     switch (mode) {
       case APPLY_Y: HDG_UF(APPLY_Y); break;

@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--no-unstructured", action="store_true", help="skip the unstructured-mesh leg")
     ap.add_argument("--unx", type=int, default=256, help="unstructured leg: grid spacing 1/unx of the mesh points")
     ap.add_argument("--uk", type=int, default=3, help="unstructured leg: polynomial degree")
+    ap.add_argument("--ucoarse-n", type=int, default=48,
+                    help="unstructured leg: the hierarchy stops at the coarsest level with >= ucoarse_n^2 unknowns")
     ap.add_argument("--no-errors", action="store_true", help="skip the solve to the FP64 floor (error report)")
     ap.add_argument("--ref-tol", type=float, default=1e-13,
                     help="tolerance of the FP64 reference solve (stops at its floor if not reachable)")
@@ -462,7 +464,7 @@ def unstructured_legs(args):
     for nm, meth, prec in (("pcg_fp64", L.METHOD_PCG, L.FP64), ("pcg_mixed", L.METHOD_PCG, L.MIXED),
                            ("mg_fp64", L.METHOD_MG, L.FP64)):
         P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH if meth == L.METHOD_PCG else L.LC_PRE,
-                precision=prec, method=meth, max_it=500)
+                precision=prec, method=meth, max_it=500, coarse_n=args.ucoarse_n)
         out["levels"] = P.level_sizes()
         progress(f"unstructured {nm} leg: {len(wl.triangles)} triangles k={k}, {P.nlam} trace DOFs")
         times, lam, infos = timed_solves(P, f, args.tol, args.steps, 1)
@@ -474,7 +476,8 @@ def unstructured_legs(args):
                    "build_ms": round(infos[-1]["t_build_ms"], 2)}
     out["lambda_mixed_vs_fp64"] = rel(lams["pcg_mixed"], lams["pcg_fp64"])
     out["mixed_over_fp64"] = round(out["pcg_mixed"]["value"] / out["pcg_fp64"]["value"], 3)
-    P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH, precision=L.MIXED, method=L.METHOD_PCG, max_it=500)
+    P.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_BOTH, precision=L.MIXED, method=L.METHOD_PCG, max_it=500,
+            coarse_n=args.ucoarse_n)
     P.profile_begin()
     P.solve(f, tol=args.tol)
     kern = {}

@@ -239,11 +239,16 @@ typedef struct {
  * space is linear in arc length along the chain.  Levels: P^k on the
  * triangles, P^1 on the triangles (k > 1), then the agglomeration levels,
  * finest first; the coarsest is solved by a dense inverse (at most 4096
- * unknowns).  hdg_mg_build takes block-Jacobi smoothing only (the mixed
- * precision cycle keeps FP64 vectors over FP32 operator blocks); hdg_rhs
- * and hdg_solve take nodal f with zero Dirichlet data (g_dirichlet NULL);
- * reconstruction, the adjoint, kappa updates, batches and the autotuner
- * return HDG_ERR_UNSUPPORTED.  Errors: HDG_ERR_INVALID_ARG for clockwise or
+ * unknowns).  hdg_mg_opts.coarse_n > 2 stops the hierarchy at the coarsest
+ * level with at least coarse_n^2 trace unknowns (the levels below are left
+ * out and that level is solved directly); coarse_n <= 2 keeps every level.  hdg_mg_build takes block-Jacobi smoothing only (the mixed
+ * precision cycle keeps FP64 vectors over FP32 operator blocks); hdg_rhs,
+ * hdg_solve and hdg_reconstruct take nodal f (HDG_RHS_F_NODAL, [ntri][nv]
+ * at the lattice nodes) and optional Dirichlet traces g_dirichlet
+ * [nbedge][k+1] (boundary edges in order of their sorted vertex pair, GLL
+ * values along each edge's parameter; NULL: zero); hdg_reconstruct returns
+ * u [ntri][nv] and q [ntri][2][nv] at the lattice nodes.  The adjoint,
+ * kappa updates, batches and the autotuner return HDG_ERR_UNSUPPORTED.  Errors: HDG_ERR_INVALID_ARG for clockwise or
  * degenerate triangles, edges shared by more than two triangles, or a
  * macro-element with more than 1024 trace values; HDG_ERR_UNSUPPORTED for
  * k outside 1..4. */

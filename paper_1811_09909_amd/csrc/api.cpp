@@ -100,6 +100,8 @@ struct hdg_problem {
   std::vector<ULevel> ul;
   double* uxy = nullptr;
   int* utri = nullptr;
+  int* utbnd = nullptr;   // boundary edge of every triangle slot (-1: interior)
+  double* urec = nullptr; // recovery maps [ntri][3][nv][3ne + nv]
   std::vector<void*> allocs;        // freed in destroy
   std::vector<void*> build_allocs;  // freed on rebuild
   long long bytes = 0;
@@ -902,9 +904,9 @@ void form_rhs_in(hdg_problem* P, const double* rhs, int kind, const double* gdir
 }
 
 void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g) {
-  if (P->unstructured) {  // nodal f, zero Dirichlet data
-    if (kind != HDG_RHS_F_NODAL || gdir) throw Unsupported{};
-    launch_tri_load(P->k, P->ul[0], P->W, rhs, g, P->st);
+  if (P->unstructured) {  // nodal f; Dirichlet data per boundary edge
+    if (kind != HDG_RHS_F_NODAL) throw Unsupported{};
+    launch_tri_load(P->k, P->ul[0], P->W, rhs, P->Ae, P->utbnd, gdir, g, P->st);
     return;
   }
   form_rhs_in(P, rhs, kind, gdir, g, P->ework);
@@ -976,7 +978,8 @@ hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, h
 long hdg::rhs_staging_doubles(const hdg_problem* P) { return P->unstructured ? 0 : P->nelem * (P->nv + P->nl); }
 
 bool hdg::rhs_supported(const hdg_problem* P, int kind, const double* gdir) {
-  return !P->unstructured || (kind == HDG_RHS_F_NODAL && !gdir);
+  (void)gdir;
+  return !P->unstructured || kind == HDG_RHS_F_NODAL;
 }
 
 void hdg::rhs_with_staging(hdg_problem* P, const double* rhs, int kind, const double* gdir, double* g,
@@ -1498,7 +1501,16 @@ hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
   P->ops32 = o.precision == HDG_MIXED;
   P->tail_start[0] = P->tail_start[1] = -1;
   const int cap = P->cap;
-  const int nlev = (int)P->ul.size();
+  // coarse_n > 2: the hierarchy stops at the coarsest level with at least
+  // coarse_n^2 trace unknowns (solved by the dense inverse)
+  int nlev = (int)P->ul.size();
+  if (o.coarse_n > 2) {
+    int last = 0;
+    for (int i = 0; i < (int)P->ul.size(); ++i)
+      if (P->ul[i].nface * P->ul[i].m >= (long)o.coarse_n * o.coarse_n) last = i;
+    nlev = last + 1;
+  }
+  if (nlev < 2 || P->ul[nlev - 1].nface * P->ul[nlev - 1].m > UCOARSE_MAX) return HDG_ERR_UNSUPPORTED;
   std::vector<Level>& L = P->L;
   L.resize(nlev);
   for (int i = 0; i < nlev; ++i) {
@@ -1548,7 +1560,7 @@ hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
   if (Lc.nlam > 0) {
     Lc.Ainv64 = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
     Lc.Ainv32 = dalloc<float>(P, Lc.nlam * Lc.nlam, true);
-    double* dense = dalloc<double>(P, Lc.nlam * Lc.nlam, true);
+    double* dense = dalloc<double>(P, 2 * Lc.nlam * Lc.nlam, true);
     launch_ucoarse_inverse(Lc, dense, P->st);
   }
   for (int i = 0; i < nlev; ++i) {
@@ -1722,6 +1734,7 @@ hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, cons
     P->rd.Jp = upload(P, H.Jp);
     P->uxy = upload(P, H.xy);
     P->utri = upload(P, H.tri);
+    P->utbnd = upload(P, H.tbnd);
     upload_ulevels(P);
     P->kqp = dalloc<double>(P, P->nelem, false);
     P->Ae = dalloc<double>(P, P->nelem * P->nl * P->nl, false);
@@ -1733,7 +1746,8 @@ hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, cons
       hdg_destroy(P);
       return HDG_ERR_INVALID_ARG;
     }
-    launch_tri_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->Ae, P->W, P->st);
+    P->urec = dalloc<double>(P, P->nelem * 3 * P->nv * (P->nl + P->nv), false);
+    launch_tri_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->Ae, P->W, P->urec, P->st);
     HDG_CHECK(hipStreamSynchronize(P->st));
     P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     hdg_default_opts(&P->opts);
@@ -2393,7 +2407,13 @@ hdg_status hdg_reconstruct(hdg_handle P, const double* lambda, const double* rhs
                            const double* gdir, double* u, double* q) {
   if (!P || !lambda || !rhs || !u || !q) return HDG_ERR_INVALID_ARG;
   if (rhs_kind != HDG_RHS_F_NODAL && rhs_kind != HDG_RHS_F_LOAD) return HDG_ERR_INVALID_ARG;
-  if (P->unstructured) return HDG_ERR_UNSUPPORTED;
+  if (P->unstructured) {
+    if (rhs_kind != HDG_RHS_F_NODAL) return HDG_ERR_UNSUPPORTED;
+    HDG_GUARD_BEGIN
+    launch_tri_reconstruct(P->k, P->nelem, P->ul[0].sface, P->utbnd, P->urec, lambda, gdir, rhs, u, q, P->st);
+    return HDG_OK;
+    HDG_GUARD_END
+  }
   if (!P->store_recovery) return HDG_ERR_STATE;
   HDG_GUARD_BEGIN
   if (P->scheme == HDG_SCHEME_HDG)

@@ -168,6 +168,7 @@ struct UHost {
   long nvert = 0, ntri = 0, nbedge = 0;
   std::vector<double> xy;
   std::vector<int> tri;
+  std::vector<int> tbnd;            // [3 ntri] boundary edge of each slot (sorted vertex pairs), -1 interior
   std::vector<int> nmacro;          // macro-elements per agglomeration level (level 1 first)
   std::vector<UHostLevel> lev;      // finest first: P^k triangles, P^1 triangles (k > 1), T_hlevels .. T_1
   // reference triangle (0,0), (1,0), (0,1), nodal P^k at the equispaced
@@ -408,9 +409,16 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
 // per coarse cell the Schur complement, A_II^-1 and P = -A_II^-1 A_IB J
 // (eqs. Akm1, n_1_Ik) into the next level's maps; face-block inverses;
 // the coarsest dense inverse; AoSoA / FP32 copies of the maps.
+// Rec (optional): recovery maps [ntri][3][nv][3ne + nv] taking [Lambda_T; f_T]
+// to the nodal q_x, q_y and u of the triangle
 void launch_tri_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri, const double* kappa,
-                    double tau, double* Aelem, double* W, hipStream_t st);
-void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, double* g, hipStream_t st);
+                    double tau, double* Aelem, double* W, double* Rec, hipStream_t st);
+// g (gdir: boundary traces [nbedge][ne], lifted with the element maps; may be null)
+void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, const double* Aelem,
+                     const int* tbnd, const double* gdir, double* g, hipStream_t st);
+void launch_tri_reconstruct(int k, long ntri, const int* sface, const int* tbnd, const double* Rec,
+                            const double* lam, const double* gdir, const double* f, double* u, double* q,
+                            hipStream_t st);
 void launch_tri_pgalerkin(int k, long ntri, const double* Jp, const double* A0, double* A1, hipStream_t st);
 void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P,
                    double* Acoarse, double* work, hipStream_t st);

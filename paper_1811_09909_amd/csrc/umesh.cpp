@@ -210,10 +210,11 @@ void UHost::build_mesh(long nvert_, const double* xy_, long ntri_, const int* tr
   for (long t = 0; t <= ntri; ++t) F.sptr[t] = 3 * t;
   F.sface.assign(3 * ntri, -1);
   nbedge = 0;
+  tbnd.assign(3 * ntri, -1);
   for (auto& kv : keys) {
     if (kv.second.size() > 2) throw std::invalid_argument("an edge is shared by more than two triangles");
     if (kv.second.size() == 1) {
-      ++nbedge;
+      tbnd[3 * kv.second[0].first + kv.second[0].second] = (int)nbedge++;
       continue;
     }
     std::sort(kv.second.begin(), kv.second.end());

@@ -46,7 +46,8 @@ __global__ void __launch_bounds__(64) tri_dtn_kernel(long ntri, const double* __
                                                      const double* __restrict__ Fh, const double* __restrict__ Hh,
                                                      const double* __restrict__ xy, const int* __restrict__ tri,
                                                      const double* __restrict__ kappa, double tau,
-                                                     double* __restrict__ Aelem, double* __restrict__ W) {
+                                                     double* __restrict__ Aelem, double* __restrict__ W,
+                                                     double* __restrict__ Rec) {
   constexpr int NV = (K + 1) * (K + 2) / 2, NE = K + 1, NL = 3 * NE, RL = NV + NL + NV;
   __shared__ double sMi[NV * NV];
   __shared__ double sD[2][NV * NV];
@@ -197,12 +198,65 @@ __global__ void __launch_bounds__(64) tri_dtn_kernel(long ntri, const double* __
     for (int i = 0; i < NV; ++i) v += sS[l * NV + i] * sK[i * RL + NV + NL + j];
     Wt[idx] = v;
   }
+  if (!Rec) return;
+  // recovery: u = X [Lambda; f], q_c = -Y_c Lambda - Mk^-1 B_c X_M f
+  constexpr int RC = NL + NV;
+  double* Rt = Rec + t * 3 * NV * RC;
+  for (int idx = tid; idx < NV * RC; idx += 64) {
+    const int i = idx / RC, col = idx % RC;
+    Rt[2 * NV * RC + idx] = sK[i * RL + NV + col];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double v;
+      if (col < NL) {
+        v = -sMF[c][i * NL + col];
+      } else {
+        v = 0.0;
+        for (int m = 0; m < NV; ++m) v -= sMB[c][i * NV + m] * sK[m * RL + NV + col];
+      }
+      Rt[c * NV * RC + idx] = v;
+    }
+  }
+}
+
+// u, q (nodal) of every triangle from its traces (interior: lambda; boundary
+// edges: gdir or 0) and f
+template <int K>
+__global__ void tri_reconstruct_kernel(long ntri, const int* __restrict__ sface, const int* __restrict__ tbnd,
+                                       const double* __restrict__ Rec, const double* __restrict__ lam,
+                                       const double* __restrict__ gdir, const double* __restrict__ f,
+                                       double* __restrict__ u, double* __restrict__ q) {
+  constexpr int NV = (K + 1) * (K + 2) / 2, NE = K + 1, NL = 3 * NE, RC = NL + NV;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= ntri) return;
+  double v[RC];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int fc = sface[3 * t + s], b = tbnd[3 * t + s];
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+      v[s * NE + a] = fc >= 0 ? lam[(long)fc * NE + a] : (gdir && b >= 0 ? gdir[(long)b * NE + a] : 0.0);
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[NL + j] = f[t * NV + j];
+  const double* R = Rec + t * 3 * NV * RC;
+  for (int r = 0; r < 3 * NV; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc += R[r * RC + c] * v[c];
+    if (r < 2 * NV)
+      q[t * 2 * NV + r] = acc;
+    else
+      u[t * NV + r - 2 * NV] = acc;
+  }
 }
 
 // g_F = sum over the face's two triangles of W^T f (rows of the face's slot)
 template <int K>
 __global__ void tri_load_kernel(long nface, const int* __restrict__ fcell, const int* __restrict__ fslot,
-                                const double* __restrict__ W, const double* __restrict__ f, double* __restrict__ g) {
+                                const double* __restrict__ W, const double* __restrict__ f,
+                                const double* __restrict__ Aelem, const int* __restrict__ tbnd,
+                                const double* __restrict__ gdir, double* __restrict__ g) {
   constexpr int NV = (K + 1) * (K + 2) / 2, NE = K + 1, NL = 3 * NE;
   const long F = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (F >= nface) return;
@@ -218,6 +272,16 @@ __global__ void tri_load_kernel(long nface, const int* __restrict__ fcell, const
       const double fj = fc[j];
 #pragma unroll
       for (int a = 0; a < NE; ++a) acc[a] += Wc[j * NL + a] * fj;
+    }
+    if (!gdir) continue;
+    // Dirichlet lift: - A^e[face rows][boundary edge columns] g_D
+    for (int sp = 0; sp < 3; ++sp) {
+      const int b = tbnd[3 * c + sp];
+      if (b < 0) continue;
+      const double* Ac = Aelem + c * NL * NL + (s * NE) * NL + sp * NE;
+#pragma unroll
+      for (int a = 0; a < NE; ++a)
+        for (int bb = 0; bb < NE; ++bb) acc[a] -= Ac[a * NL + bb] * gdir[(long)b * NE + bb];
     }
   }
 #pragma unroll
@@ -438,6 +502,25 @@ __global__ void __launch_bounds__(256) udense_inverse_kernel(int N, double* __re
     Ai64[idx] = A[idx];
     Ai32[idx] = (float)A[idx];
   }
+}
+
+// one pivot sweep of the same inversion out of place (large coarsest levels:
+// one launch per pivot, one lane per entry)
+__global__ void udense_step_kernel(long N, long p, const double* __restrict__ A, double* __restrict__ B) {
+  const long idx = blockIdx.x * 256L + threadIdx.x;
+  if (idx >= N * N) return;
+  const long i = idx / N, j = idx % N;
+  const double d = 1.0 / A[p * N + p];
+  double v;
+  if (i == p && j == p)
+    v = d;
+  else if (i == p)
+    v = A[idx] * d;
+  else if (j == p)
+    v = -A[idx] * d;
+  else
+    v = A[idx] - A[i * N + p] * A[p * N + j] * d;
+  B[idx] = v;
 }
 
 // row-major triangle maps -> AoSoA over triangles in 16-byte groups (FP64
@@ -706,22 +789,35 @@ void dispatch_m(int m, F&& f) {
 
 // ---------------------------------------------------------------------------
 void launch_tri_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri, const double* kappa,
-                    double tau, double* Aelem, double* W, hipStream_t st) {
+                    double tau, double* Aelem, double* W, double* Rec, hipStream_t st) {
   if (ntri == 0) return;
   dispatch_k(k, [&](auto K_) {
     constexpr int K = decltype(K_)::value;
     hipLaunchKernelGGL((tri_dtn_kernel<K>), dim3((unsigned)ntri), dim3(64), 0, st, ntri, rd.uM, rd.uMinv, rd.uD,
-                       rd.uE, rd.uF, rd.uH, xy, tri, kappa, tau, Aelem, W);
+                       rd.uE, rd.uF, rd.uH, xy, tri, kappa, tau, Aelem, W, Rec);
   });
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, double* g, hipStream_t st) {
+void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, const double* Aelem,
+                     const int* tbnd, const double* gdir, double* g, hipStream_t st) {
   if (U.nface == 0) return;
   dispatch_k(k, [&](auto K_) {
     constexpr int K = decltype(K_)::value;
     hipLaunchKernelGGL((tri_load_kernel<K>), dim3(nb256(U.nface)), dim3(256), 0, st, U.nface, U.fcell, U.fslot, W, f,
-                       g);
+                       Aelem, tbnd, gdir, g);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
+void launch_tri_reconstruct(int k, long ntri, const int* sface, const int* tbnd, const double* Rec,
+                            const double* lam, const double* gdir, const double* f, double* u, double* q,
+                            hipStream_t st) {
+  if (ntri == 0) return;
+  dispatch_k(k, [&](auto K_) {
+    constexpr int K = decltype(K_)::value;
+    hipLaunchKernelGGL((tri_reconstruct_kernel<K>), dim3(nb256(ntri)), dim3(256), 0, st, ntri, sface, tbnd, Rec, lam,
+                       gdir, f, u, q);
   });
   HDG_CHECK(hipGetLastError());
 }
@@ -759,7 +855,18 @@ void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st) {
   if (N > UCOARSE_MAX) throw HipError{hipErrorInvalidValue, "coarsest level too large for the dense inverse"};
   hipLaunchKernelGGL(udense_kernel, dim3(nb256(N)), dim3(256), 0, st, U.nface, U.m, U.fcell, U.fslot, U.sptr,
                      U.sface, U.moff, L.Aelem, work);
-  hipLaunchKernelGGL(udense_inverse_kernel, dim3(1), dim3(256), 0, st, (int)N, work, L.Ainv64, L.Ainv32);
+  if (N <= 512) {
+    hipLaunchKernelGGL(udense_inverse_kernel, dim3(1), dim3(256), 0, st, (int)N, work, L.Ainv64, L.Ainv32);
+  } else {  // work holds two N x N buffers
+    double* A = work;
+    double* B = work + N * N;
+    for (long p = 0; p < N; ++p) {
+      hipLaunchKernelGGL(udense_step_kernel, dim3(nb256(N * N)), dim3(256), 0, st, N, p, A, B);
+      std::swap(A, B);
+    }
+    HDG_CHECK(hipMemcpyAsync(L.Ainv64, A, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(f32_kernel, dim3(1024), dim3(256), 0, st, A, L.Ainv32, N * N);
+  }
   HDG_CHECK(hipGetLastError());
 }
 

@@ -2,8 +2,8 @@
 the FP64 CPU oracle (Sec. 2 on P^k triangles; Sec. 3.1.2 seed-point
 agglomeration and arc-length P^1 macro-edges; Sec. 3 multigrid).
 
-Element maps and loads, every level operator of the agglomeration
-hierarchy, block-Jacobi sweeps, the V-cycle (FP64, FP32 and the mixed
+Element maps and loads (with Dirichlet data), nodal recovery of u and q,
+every level operator of the agglomeration hierarchy, block-Jacobi sweeps, the V-cycle (FP64, FP32 and the mixed
 cycle), MG / CG / GMRES counts against the oracle's and solutions against
 a direct solve, several right-hand sides and graph replay against single
 eager solves, and the error paths.  Meshes: the synthetic box with eight
@@ -75,6 +75,35 @@ def test_u_element_maps_and_rhs(torch_cuda, k):
     assert err <= bound
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_u_dirichlet_rhs_solve_recovery(torch_cuda, k):
+    """Loads with Dirichlet data lifted through the element maps, a solve
+    with them against a direct solve, and the nodal u and q of every
+    triangle against the oracle's recovery."""
+    from paper_1811_09909_amd import _lib as L
+    say(f"[unstructured dirichlet/recovery] nx=8 k={k}")
+    w, m, kap = _case(8, k, kap_range=(-1, 1))
+    O = U.TriHDG(m, k, w.tau, kap)
+    rng = np.random.default_rng(40 + k)
+    f = rng.standard_normal((m.nel, O.nv))
+
+    def gD(X):
+        return np.cos(2 * X.sum(axis=1)) + X[:, 0]
+    A, g, lb = O.assemble(f, gD)
+    P = _gpu(torch_cuda, w, k, kap, method=L.METHOD_PCG, local_corr=omg.LC_BOTH)
+    ft, gt = torch_cuda.as_tensor(f), torch_cuda.as_tensor(lb)
+    gg = P.rhs(ft, gdir=gt).cpu().numpy()
+    eg = np.abs(gg - g).max() / np.abs(g).max()
+    lam_d = spla.spsolve(A.tocsc(), g)
+    lam, info = P.solve(ft, tol=1e-11, gdir=gt)
+    el = relerr(lam.cpu().numpy(), lam_d)
+    u, q = P.reconstruct(torch_cuda.as_tensor(lam_d), ft, gdir=gt)
+    uo, qo = O.reconstruct(lam_d, f, lb)
+    eu, eq = relerr(u.cpu().numpy(), uo), relerr(q.cpu().numpy(), qo)
+    say(f"  g {eg:.2e}; solve ({info['iters']} CG iterations) vs direct {el:.2e}; recovery u {eu:.2e} q {eq:.2e}")
+    assert eg <= 1e-12 and el <= 1e-9 and eu <= 1e-11 and eq <= 1e-10
+
+
 def _oracle_h(m, k, kap, w, **kw):
     O = U.TriHDG(m, k, w.tau, kap)
     A, _, _ = O.assemble()
@@ -139,6 +168,35 @@ def test_u_solves_match_oracle(torch_cuda, nx, k):
             assert info["iters"] == ro[name]
         else:
             assert abs(info["iters"] - ro[name]) <= 1
+
+
+def test_u_truncated_hierarchy(torch_cuda):
+    """coarse_n = 24 ends the hierarchy at the coarsest level with at least
+    576 unknowns, solved directly: level sizes, the V-cycle and the MG and CG
+    counts equal the oracle's hierarchy on the same partitions with the
+    coarser ones left out."""
+    from paper_1811_09909_amd import _lib as L
+    w, m, kap = _case(32, 2)
+    O = U.TriHDG(m, 2, w.tau, kap)
+    A, g, _ = O.assemble(w.f)
+    parts = U.agglomerate(m, w.seeds, w.hlevels)
+    full = [Lv.A.shape[0] for Lv in U.UHierarchy(A, m, 2, parts).levels]
+    last = max(i for i, n in enumerate(full) if n >= 24 * 24)
+    keep = last - 1  # agglomeration levels kept (level 0: P^2, level 1: P^1)
+    H = U.UHierarchy(A, m, 2, parts[len(parts) - keep:])
+    P = _gpu(torch_cuda, w, 2, kap, coarse_n=24)
+    assert P.level_sizes() == [Lv.A.shape[0] for Lv in H.levels] == full[:last + 1]
+    r = np.random.default_rng(3).standard_normal(A.shape[0])
+    ev = relerr(P.vcycle(torch_cuda.as_tensor(r)).cpu().numpy(), H.vcycle(r))
+    f = torch_cuda.as_tensor(w.f)
+    counts = {}
+    for name, meth, solve in (("mg", L.METHOD_MG, omg.mg_solve), ("pcg", L.METHOD_PCG, omg.pcg_solve)):
+        P.build(method=meth, coarse_n=24)
+        _, info = P.solve(f, tol=1e-10)
+        counts[name] = (info["iters"], solve(H, A, g, tol=1e-10).iters)
+    say(f"[unstructured truncated] levels {P.level_sizes()}, vcycle {ev:.1e}, counts (GPU, oracle) {counts}")
+    assert ev <= 1e-10
+    assert counts["mg"][0] == counts["mg"][1] and abs(counts["pcg"][0] - counts["pcg"][1]) <= 1
 
 
 def test_u_mixed_precision_and_replay(torch_cuda):
@@ -219,8 +277,8 @@ def test_u_error_paths(torch_cuda):
     P.build()
     f = torch_cuda.ones(m.nel, 3, dtype=torch_cuda.float64)
     with pytest.raises(RuntimeError, match="unsupported"):
-        P.rhs(f, gdir=torch_cuda.zeros(10, dtype=torch_cuda.float64))
-    with pytest.raises(RuntimeError, match="unsupported"):
-        P.reconstruct(torch_cuda.zeros(P.nlam, dtype=torch_cuda.float64), f)
+        P.rhs(f, kind=L.RHS_F_LOAD)
     with pytest.raises(RuntimeError, match="unsupported"):
         P.update_kappa(kt)
+    with pytest.raises(RuntimeError, match="unsupported"):
+        P.adjoint(f, torch_cuda.zeros(m.nel, 2, 3, dtype=torch_cuda.float64))

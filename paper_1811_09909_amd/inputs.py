@@ -162,7 +162,8 @@ def box_with_holes(nx=32, holes=True, seed=0):
     y), minus those within 0.12 + 0.6 h of a hole centre, plus
     ceil(2 pi 0.12 / h) equally spaced points on every hole's circle.
     Triangles: the Delaunay triangulation of these points, without those
-    whose centroid lies inside a hole, each listed counter-clockwise.
+    whose centroid lies inside a hole, each listed counter-clockwise, in
+    order of their lowest vertex, then their highest.
     Returns (vertices [nv, 2] float64, triangles [nt, 3] int32)."""
     from scipy.spatial import Delaunay
     rng = np.random.default_rng(seed)
@@ -199,7 +200,9 @@ def box_with_holes(nx=32, holes=True, seed=0):
     used = np.unique(tri)
     remap = -np.ones(len(V), dtype=np.int64)
     remap[used] = np.arange(len(used))
-    return V[used].copy(), remap[tri].astype(np.int32)
+    tri = remap[tri]
+    order = np.lexsort((tri.max(axis=1), tri.min(axis=1)))  # by lowest vertex, then highest
+    return V[used].copy(), tri[order].astype(np.int32)
 
 
 def unstructured2d(nx=32, k=2, strategy=1, holes=True, seed=0):

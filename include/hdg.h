@@ -255,6 +255,13 @@ typedef struct {
 hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, void* hip_stream,
                                   hdg_handle* out);
 
+/* Host only (no GPU call): the trace unknowns of every level of the
+ * hierarchy hdg_setup_unstructured builds for this mesh and degree, finest
+ * first, into sizes[0 .. *nlevels - 1] (for choosing coarse_n).  Errors as
+ * for hdg_setup_unstructured; HDG_ERR_INVALID_ARG also when the hierarchy
+ * has more than max_levels levels (*nlevels then holds the count). */
+hdg_status hdg_umesh_levels(const hdg_umesh* mesh, int k, long long* sizes, int max_levels, int* nlevels);
+
 /* Re-form A^e for a new kappa (same layout rules); invalidates the
  * hierarchy (call hdg_mg_build again). */
 hdg_status hdg_update_kappa(hdg_handle h, const double* kappa, int kappa_kind);

@@ -22,7 +22,7 @@ EXPORTS = [
     "hdg_reconstruct", "hdg_adjoint", "hdg_mass_apply", "hdg_level_apply", "hdg_level_smooth",
     "hdg_level_export", "hdg_query", "hdg_reference_nodes", "hdg_destroy", "hdg_status_string",
     "hdg_profile_begin", "hdg_profile_read", "hdg_solve_batch", "hdg_autotune", "hdg_rhs_noalloc",
-    "hdg_setup_scheme", "hdg_setup_multi", "hdg_setup_unstructured",
+    "hdg_setup_scheme", "hdg_setup_multi", "hdg_setup_unstructured", "hdg_umesh_levels",
 ]
 
 
@@ -96,6 +96,8 @@ def load():
         "hdg_setup_scheme": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_multi": (I, [ctypes.POINTER(Mesh), I, D, P, I, P, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_unstructured": (I, [ctypes.POINTER(UMesh), I, D, P, P, ctypes.POINTER(P)]),
+        "hdg_umesh_levels": (I, [ctypes.POINTER(UMesh), I, ctypes.POINTER(ctypes.c_longlong), I,
+                                 ctypes.POINTER(I)]),
         "hdg_update_kappa": (I, [P, P, I]),
         "hdg_mg_build": (I, [P, ctypes.POINTER(Opts)]),
         "hdg_vcycle": (I, [P, P, P, I, I]),

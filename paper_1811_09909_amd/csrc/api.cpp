@@ -1024,6 +1024,26 @@ const char* hdg_status_string(hdg_status s) {
   return "unknown";
 }
 
+hdg_status hdg_umesh_levels(const hdg_umesh* mesh, int k, long long* sizes, int max_levels, int* nlevels) {
+  if (!mesh || !mesh->xy || !mesh->tri || !mesh->seeds || !sizes || !nlevels || max_levels < 1) return HDG_ERR_INVALID_ARG;
+  if (mesh->nvert < 3 || mesh->ntri < 1 || mesh->nseeds < 1 || mesh->hlevels < 1 || mesh->hlevels > 16)
+    return HDG_ERR_INVALID_ARG;
+  if (k < 1 || k > 4) return HDG_ERR_UNSUPPORTED;
+  try {
+    UHost H;
+    H.build_reference(k);
+    H.build_mesh(mesh->nvert, mesh->xy, mesh->ntri, mesh->tri, mesh->seeds, mesh->nseeds, mesh->hlevels);
+    *nlevels = (int)H.lev.size();
+    if ((int)H.lev.size() > max_levels) return HDG_ERR_INVALID_ARG;
+    for (size_t i = 0; i < H.lev.size(); ++i) sizes[i] = (long long)H.lev[i].nface * H.lev[i].m;
+    return HDG_OK;
+  } catch (const std::bad_alloc&) {
+    return HDG_ERR_DEVICE;
+  } catch (const std::exception&) {
+    return HDG_ERR_INVALID_ARG;
+  }
+}
+
 hdg_status hdg_reference_nodes(int k, double* gll, double* gauss) {
   if (k < 1 || k > 12 || !gll || !gauss) return HDG_ERR_INVALID_ARG;
   std::vector<double> x, gx, gw;

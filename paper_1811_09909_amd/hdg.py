@@ -291,6 +291,20 @@ class Problem:
         return self._tensor_points(self.reference_nodes()[1])
 
 
+def umesh_levels(vertices, triangles, k, seeds, hlevels):
+    """Trace unknowns per level of the unstructured hierarchy (host only,
+    ``hdg_umesh_levels``)."""
+    lib = L.load()
+    xy = np.ascontiguousarray(vertices, dtype=np.float64)
+    tri = np.ascontiguousarray(triangles, dtype=np.int32)
+    sd = np.ascontiguousarray(seeds, dtype=np.float64)
+    mesh = L.UMesh(len(xy), xy.ctypes.data, len(tri), tri.ctypes.data, len(sd), sd.ctypes.data, int(hlevels))
+    sizes = (ctypes.c_longlong * 32)()
+    n = ctypes.c_int()
+    L.check(lib.hdg_umesh_levels(ctypes.byref(mesh), int(k), sizes, 32, ctypes.byref(n)), "hdg_umesh_levels")
+    return [int(sizes[i]) for i in range(n.value)]
+
+
 def solve_batch(problems, rhs, tol=1e-10, kind=L.RHS_F_NODAL, nstreams=0):
     """Solve problem i for its right-hand sides rhs[i] ([nrhs_i, ...] nodal
     sources, or trace vectors for kind=RHS_TRACE) with hdg_solve_batch: all

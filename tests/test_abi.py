@@ -90,3 +90,25 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             L.load()
     finally:
         L.LIB_PATH, L._lib = saved
+
+
+@pytest.mark.parametrize("nx,k,strategy", [(8, 1, 1), (16, 2, 1), (16, 3, 2), (32, 1, 2), (45, 2, 1)])
+def test_unstructured_hierarchy_host_side(nx, k, strategy):
+    """The library's host-side agglomeration (seed points, four-way splits,
+    macro-edge chains) gives the oracle's level sizes on the box with holes."""
+    _lib()
+    from oracle import unstructured as U
+    from paper_1811_09909_amd import inputs
+    from paper_1811_09909_amd.hdg import umesh_levels
+    w = inputs.unstructured2d(nx, k, strategy=strategy)
+    m = U.TriMesh(w.vertices, w.triangles)
+    parts = U.agglomerate(m, w.seeds, w.hlevels)
+    sizes = [m.nface * (k + 1)] + ([m.nface * 2] if k > 1 else [])
+    fine, cell_of = U.triangle_faces(m), np.arange(m.nel)
+    for p in reversed(parts):
+        co = np.zeros(cell_of.max() + 1, dtype=np.int64)
+        co[cell_of] = p
+        _, _, _, fine = U.macro_faces(fine, co)
+        cell_of = p
+        sizes.append(2 * fine.nface)
+    assert umesh_levels(w.vertices, w.triangles, k, w.seeds, w.hlevels) == sizes

@@ -225,3 +225,72 @@ def unstructured2d(nx=32, k=2, strategy=1, holes=True, seed=0):
     return Workload(d=2, k=k, tau=1.0, vertices=V, triangles=T, seeds=seeds, hlevels=hl,
                     kappa=np.ones(nt), f=np.ones((nt, nv)),
                     name=f"unstructured2d box with 8 holes nx={nx} ({nt} triangles) k={k} strategy {strategy}")
+
+
+def disk_mesh(h, seed=0):
+    """An unstructured triangulation of the unit disk: the points of a grid of
+    spacing h inside radius 1 - 0.6 h, moved by U(-0.3 h, 0.3 h) per
+    coordinate (drawn in point order, x then y), plus ceil(2 pi / h) equally
+    spaced points on the circle; the Delaunay triangulation of these points
+    (all inside the inscribed polygon), counter-clockwise, listed by lowest
+    then highest vertex.  Returns (vertices, triangles)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    m = int(np.ceil(1.0 / h))
+    g = np.arange(-m, m + 1) * h
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    P = np.stack([X.ravel(), Y.ravel()], axis=1)
+    P = P[np.hypot(P[:, 0], P[:, 1]) < 1.0 - 0.6 * h]
+    P = P + rng.uniform(-0.3 * h, 0.3 * h, P.shape)
+    nb = int(np.ceil(2 * np.pi / h))
+    th = 2 * np.pi * np.arange(nb) / nb
+    V = np.concatenate([P, np.stack([np.cos(th), np.sin(th)], axis=1)])
+    tri = Delaunay(V).simplices.astype(np.int64)
+    a, b, c = V[tri[:, 0]], V[tri[:, 1]], V[tri[:, 2]]
+    flip = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]) < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    order = np.lexsort((tri.max(axis=1), tri.min(axis=1)))
+    return V, tri[order].astype(np.int32)
+
+
+def example3_disk(levels=4, k=2):
+    """Example III's setting on a synthetic disk mesh: kappa = 1 + 0.5
+    sin(2 pi x) cos(3 pi y) at the triangle centroids, u = x y exp(x^2 y^3),
+    f = -div(kappa grad u) with the smooth kappa, Dirichlet data u, tau = 1.
+    The mesh of ``levels`` has about 84 4^(levels - 2) triangles (the sizes of
+    the paper's hierarchy), and 21 seed points on a grid of spacing 0.4 give
+    about 84 macro-elements on level 2 and four times more per level below."""
+    ntri = 84 * 4 ** (levels - 2)
+    V, T = disk_mesh(np.sqrt(2 * np.pi / ntri))
+    cen = V[T].mean(axis=1)
+    kappa = 1.0 + 0.5 * np.sin(2 * np.pi * cen[:, 0]) * np.cos(3 * np.pi * cen[:, 1])
+    g = np.arange(-2, 3) * 0.4
+    S = np.stack(np.meshgrid(g, g, indexing="xy"), axis=-1).reshape(-1, 2)
+    seeds = S[np.hypot(S[:, 0], S[:, 1]) < 0.95]
+
+    def u(P):
+        x, y = P[..., 0], P[..., 1]
+        return x * y * np.exp(x ** 2 * y ** 3)
+
+    def grad(P):
+        x, y = P[..., 0], P[..., 1]
+        e = np.exp(x ** 2 * y ** 3)
+        return np.stack([y * e * (1 + 2 * x ** 2 * y ** 3), x * e * (1 + 3 * x ** 2 * y ** 3)], axis=-1)
+
+    def f(P):
+        x, y = P[..., 0], P[..., 1]
+        e = np.exp(x ** 2 * y ** 3)
+        lap = y * e * (6 * x * y ** 3 + 4 * x ** 3 * y ** 6) + x * e * (12 * x ** 2 * y ** 2 + 9 * x ** 4 * y ** 5)
+        kap = 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.cos(3 * np.pi * y)
+        kx = np.pi * np.cos(2 * np.pi * x) * np.cos(3 * np.pi * y)
+        ky = -1.5 * np.pi * np.sin(2 * np.pi * x) * np.sin(3 * np.pi * y)
+        gu = grad(P)
+        return -(kap * lap + kx * gu[..., 0] + ky * gu[..., 1])
+
+    hl = 1
+    while len(seeds) * 4 ** hl * 3 <= len(T):
+        hl += 1
+    return Workload(d=2, k=k, tau=1.0, vertices=V, triangles=T, seeds=seeds, hlevels=hl, kappa=kappa, f=f,
+                    u_exact=u, grad_exact=grad,
+                    name=f"example3 disk mesh level {levels} ({len(T)} triangles) k={k} "
+                         f"kappa=1+0.5sin(2pi x)cos(3pi y) u=xy exp(x^2y^3) tau=1")

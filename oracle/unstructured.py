@@ -11,6 +11,8 @@ Sec. 3.1.2 (oracle; test infrastructure only).
   trace_linear_system), local recovery and the uncondensed system.  The
   volume basis is nodal at the equispaced lattice of the reference
   triangle; integrals use the collapsed (Duffy) product of Gauss rules.
+* ``TriIPDG``  -- the hybridized interior penalty family (eq. IPG_H:
+  SIPG-H, IIPG-H, NIPG-H) on the same triangles and traces.
 * ``agglomerate`` -- the seed-point agglomeration of Sec. 3.1.2: the
   level-1 macro-elements gather the triangles nearest to each seed point,
   and every level's macro-elements are split into four to form the next.
@@ -367,6 +369,93 @@ class TriHDG:
             for c in range(2):
                 eq += np.sum(W * (Phi @ q[t, c] - qe[:, c]) ** 2)
         return np.sqrt(eu), np.sqrt(eq)
+
+
+class TriIPDG(TriHDG):
+    """The hybridized interior penalty family (eq. IPG_H; SIPG-H, IIPG-H,
+    NIPG-H with s_f = 1, 0, -1) on P^k triangles, kappa per triangle, scalar
+    tau.  Rows for the test function, per triangle:
+
+        L = kappa (K - s_f N - N^T) + tau E,   K_ij = (grad phi_j, grad phi_i),
+                                               N_ij = <phi_j, grad phi_i . n>,
+        R = tau G - s_f kappa D,               D_il = <mu_l, grad phi_i . n>,
+        C = tau G^T - kappa D^T,
+
+    A^e = tau H - C L^-1 R, b^e = C L^-1 M f; recovery u = L^-1 (R Lambda +
+    M f) and q = -kappa grad u at the nodes."""
+
+    SCHEMES = {"sipg": 1.0, "iipg": 0.0, "nipg": -1.0}
+
+    def __init__(self, mesh, k, tau, kappa, scheme="nipg"):
+        super().__init__(mesh, k, tau, kappa)
+        if scheme not in self.SCHEMES:
+            raise ValueError(f"unknown scheme {scheme}")
+        self.scheme, self.sf = scheme, self.SCHEMES[scheme]
+
+    def ipdg_blocks(self, t):
+        """(L, R, C, H, M) of triangle t."""
+        ref, nv, ne, nl = self.ref, self.nv, self.ne, self.nl
+        P, Jm, det, Ji = self.geometry(t)
+        Phi = ref.values(self.qX)
+        gx, gy = ref.grads(self.qX)
+        dPhi = [Ji[0, c] * gx + Ji[1, c] * gy for c in range(2)]
+        W = self.qW * det
+        M = (Phi.T * W) @ Phi
+        K = sum((dPhi[c].T * W) @ dPhi[c] for c in range(2))
+        N = np.zeros((nv, nv))
+        D = np.zeros((nv, nl))
+        E = np.zeros((nv, nv))
+        G = np.zeros((nv, nl))
+        H = np.zeros((nl, nl))
+        T = self.mesh.T[t]
+        for s in range(3):
+            va, vb = int(T[s]), int(T[(s + 1) % 3])
+            lo, hi = min(va, vb), max(va, vb)
+            A, B = self.mesh.V[lo], self.mesh.V[hi]
+            ln = float(np.hypot(*(B - A)))
+            dvec = self.mesh.V[vb] - self.mesh.V[va]
+            nrm = np.array([dvec[1], -dvec[0]]) / ln
+            X = A[None, :] + self.eg[:, None] * (B - A)[None, :]
+            Xi = (X - P[0]) @ Ji.T
+            Pf = ref.values(Xi)
+            fx, fy = ref.grads(Xi)
+            dn = sum(nrm[c] * (Ji[0, c] * fx + Ji[1, c] * fy) for c in range(2))   # grad phi_i . n
+            wf = self.ew * ln
+            cols = slice(s * ne, (s + 1) * ne)
+            N += (dn.T * wf) @ Pf
+            D[:, cols] = (dn.T * wf) @ self.Mu
+            E += (Pf.T * wf) @ Pf
+            G[:, cols] = (Pf.T * wf) @ self.Mu
+            H[cols, cols] = (self.Mu.T * wf) @ self.Mu
+        kap, tau, sf = self.kappa[t], self.tau, self.sf
+        L = kap * (K - sf * N - N.T) + tau * E
+        R = tau * G - sf * kap * D
+        C = tau * G.T - kap * D.T
+        return L, R, C, H, M
+
+    def element_dtn(self, t, f_t=None):
+        L, R, C, H, M = self.ipdg_blocks(t)
+        Ae = self.tau * H - C @ np.linalg.solve(L, R)
+        if f_t is None:
+            return Ae
+        return Ae, C @ np.linalg.solve(L, M @ f_t)
+
+    def reconstruct(self, lam, f_nodal=None, lam_b=None):
+        """u (nodal) and q = -kappa grad u at the nodes, [N_T, 2, nv]."""
+        nel, nv = self.mesh.nel, self.nv
+        f_nodal = np.zeros((nel, nv)) if f_nodal is None else np.asarray(f_nodal, dtype=float)
+        lam_b = np.zeros(self.nbdof) if lam_b is None else lam_b
+        gx, gy = self.ref.grads(self.ref.nodes)
+        u = np.zeros((nel, nv))
+        q = np.zeros((nel, 2, nv))
+        for t in range(nel):
+            LT = np.where(self.gmap[t] >= 0, lam[np.maximum(self.gmap[t], 0)], lam_b[np.maximum(self.bmap[t], 0)])
+            L, R, C, H, M = self.ipdg_blocks(t)
+            u[t] = np.linalg.solve(L, R @ LT + M @ f_nodal[t])
+            _, _, _, Ji = self.geometry(t)
+            for c in range(2):
+                q[t, c] = -self.kappa[t] * (Ji[0, c] * gx + Ji[1, c] * gy) @ u[t]
+        return u, q
 
 
 # ---------------------------------------------------------------------------

@@ -24,6 +24,10 @@ U10 Example III on a synthetic disk mesh (tests/golden/ex3_hdg_smooth_iterations
     Table HDG_smooth_k_tau1): hierarchy sizes near the paper's, GMRES
     within 3 and MG within twice the table (parity unpinned: other mesh),
     u converging to the exact solution.
+U11 SIPG-H, IIPG-H, NIPG-H on P^k triangles reproduce u in P^k (traces, u,
+    q = -kappa grad u); SIPG-H maps symmetric, the others not.
+U12 NIPG-H multigrid on the box with holes: Galerkin chain with Q != I^T,
+    bounded MG / GMRES counts.
 """
 from math import factorial
 
@@ -297,3 +301,71 @@ def test_U10_example3_disk():
     for k in (1, 2):
         e = [v for kk, v in errs if kk == k]
         assert e[0] > e[1] > e[2]
+
+
+def _hmin(w):
+    V, T = w.vertices, w.triangles
+    e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    return np.hypot(*(V[e[:, 0]] - V[e[:, 1]]).T).min()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_U11_ipdg_triangles_reproduction(k):
+    """SIPG-H, IIPG-H and NIPG-H on P^k triangles (eq. IPG_H): u in P^k with
+    f = -kappa lap u and its Dirichlet data gives exact traces, u and q =
+    -kappa grad u at the nodes (tau = (p+1)(p+2)/h_min); SIPG-H element maps
+    are symmetric, IIPG-H and NIPG-H ones are not."""
+    m, w = _mesh()
+    kap = 2.5
+    coef = np.random.default_rng(50 + k).standard_normal((k + 1) * (k + 2) // 2)
+    u, lap = _poly(k, coef)
+    ex = U.tri_monomials(k)
+
+    def grad(X):
+        gx, gy = np.zeros(len(X)), np.zeros(len(X))
+        for c, (a, b) in zip(coef, ex):
+            if a >= 1:
+                gx = gx + c * a * X[:, 0] ** (a - 1) * X[:, 1] ** b
+            if b >= 1:
+                gy = gy + c * b * X[:, 0] ** a * X[:, 1] ** (b - 1)
+        return np.stack([gx, gy], axis=1)
+    for scheme in ("sipg", "iipg", "nipg"):
+        P = U.TriIPDG(m, k, (k + 1) * (k + 2) / _hmin(w), np.full(m.nel, kap), scheme)
+        Xn = P.volume_nodes().reshape(-1, 2)
+        fn = (-kap * lap(Xn)).reshape(m.nel, -1)
+        A, g, lb = P.assemble(fn, u)
+        lam = spla.spsolve(A.tocsc(), g)
+        uh, qh = P.reconstruct(lam, fn, lb)
+        sc = np.abs(u(Xn)).max()
+        qe = -kap * grad(Xn).reshape(m.nel, -1, 2).transpose(0, 2, 1)
+        assert np.abs(lam - u(P.interior_trace_nodes())).max() <= 1e-10 * sc
+        assert np.abs(uh.ravel() - u(Xn)).max() <= 1e-10 * sc
+        assert np.abs(qh - qe).max() <= 1e-8 * np.abs(qe).max()
+        Ae = P.element_dtn(0)
+        asym = np.abs(Ae - Ae.T).max() / np.abs(Ae).max()
+        assert (asym <= 1e-13) if scheme == "sipg" else (asym >= 1e-3)
+
+
+def test_U12_nipg_multigrid_triangles():
+    """NIPG-H on the box with holes: the Galerkin chain with the nonsymmetric
+    restriction Q != I^T, and MG / GMRES converging with counts bounded
+    under refinement (Example II's Table NIPG: "parity unpinned", other
+    mesh)."""
+    counts = []
+    for nx in (16, 32):
+        w = inputs.unstructured2d(nx, 1)
+        m = U.TriMesh(w.vertices, w.triangles)
+        P = U.TriIPDG(m, 1, 6.0 / _hmin(w), w.kappa, "nipg")
+        A, g, _ = P.assemble(w.f)
+        H = U.UHierarchy(A, m, 1, U.agglomerate(m, w.seeds, w.hlevels))
+        L0 = H.levels[0]
+        assert abs(L0.Q - L0.I.T).max() > 1e-3
+        for i in range(len(H.levels) - 1):
+            L, Lc = H.levels[i], H.levels[i + 1]
+            G = (L.Q @ L.A @ L.I).toarray()
+            assert np.abs(G - Lc.A.toarray()).max() <= 1e-11 * np.abs(Lc.A).max()
+        r1 = mg.mg_solve(H, A, g, tol=1e-9)
+        r2 = mg.gmres_solve(H, A, g, tol=1e-9)
+        assert r1.converged and r2.converged
+        counts.append((r1.iters, r2.iters))
+    assert max(c[1] for c in counts) <= 20 and max(c[0] for c in counts) <= 60, counts

@@ -222,9 +222,13 @@ typedef struct {
   int hlevels;
 } hdg_umesh;
 
-/* HDG (eqs. HDG, HDG_flux) with P^k volume and trace spaces on the
- * triangles of an unstructured mesh, k in 1..4, scalar tau > 0, kappa a
- * DEVICE array with one value per triangle.  Volume unknowns are nodal at
+/* HDG (eqs. HDG, HDG_flux; scheme HDG_SCHEME_HDG) or the hybridized IPDG
+ * family (eq. IPG_H; HDG_SCHEME_SIPG, _IIPG, _NIPG, with the element blocks
+ * of hdg_setup_scheme and recovery q = -kappa grad u) with P^k volume and
+ * trace spaces on the triangles of an unstructured mesh, k in 1..4, scalar
+ * tau > 0, kappa a DEVICE array with one value per triangle.  IIPG-H and
+ * NIPG-H give a nonsymmetric trace system: CG is rejected and the
+ * agglomeration levels restrict with -J^T A_BI A_II^-1 (eq. n_1_Qk).  Volume unknowns are nodal at
  * the equispaced lattice of each triangle (vertex 0 first, then along edge
  * 0; rows from edge 0 to vertex 2); the trace unknowns of an interior edge
  * are nodal at the GLL points of its parameter, which runs from its lower-
@@ -252,8 +256,8 @@ typedef struct {
  * degenerate triangles, edges shared by more than two triangles, or a
  * macro-element with more than 1024 trace values; HDG_ERR_UNSUPPORTED for
  * k outside 1..4. */
-hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, void* hip_stream,
-                                  hdg_handle* out);
+hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, int scheme,
+                                  void* hip_stream, hdg_handle* out);
 
 /* Host only (no GPU call): the trace unknowns of every level of the
  * hierarchy hdg_setup_unstructured builds for this mesh and degree, finest

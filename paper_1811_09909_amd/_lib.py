@@ -95,7 +95,7 @@ def load():
         "hdg_setup": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_scheme": (I, [ctypes.POINTER(Mesh), I, D, P, I, I, I, P, ctypes.POINTER(P)]),
         "hdg_setup_multi": (I, [ctypes.POINTER(Mesh), I, D, P, I, P, I, I, P, ctypes.POINTER(P)]),
-        "hdg_setup_unstructured": (I, [ctypes.POINTER(UMesh), I, D, P, P, ctypes.POINTER(P)]),
+        "hdg_setup_unstructured": (I, [ctypes.POINTER(UMesh), I, D, P, I, P, ctypes.POINTER(P)]),
         "hdg_umesh_levels": (I, [ctypes.POINTER(UMesh), I, ctypes.POINTER(ctypes.c_longlong), I,
                                  ctypes.POINTER(I)]),
         "hdg_update_kappa": (I, [P, P, I]),

@@ -1508,6 +1508,7 @@ namespace {
 // FP64 vectors over FP32 maps; no fused kernels, coarse tail or packing.
 hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
   if (o.smoother != HDG_SMOOTHER_BLOCK_JACOBI) return HDG_ERR_UNSUPPORTED;
+  if (!P->sym && o.method == HDG_METHOD_PCG) return HDG_ERR_UNSUPPORTED;  // CG needs a symmetric operator
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   free_build(P);
@@ -1546,7 +1547,7 @@ hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
     Li.nlam = U.nface * U.m;
     Li.u = &U;
     Li.kind = i == nlev - 1 ? 2 : (i == 0 && P->k > 1) ? 0 : 1;
-    Li.sym = true;
+    Li.sym = P->sym;
   }
   L[0].Aelem = P->Ae;
   L[0].own_Aelem = false;
@@ -1566,14 +1567,21 @@ hdg_status ubuild(hdg_problem* P, const hdg_mg_opts& o) {
     F.AIIinv32 = dalloc<float>(P, std::max(U.asize, 1L), true);
     F.P64 = dalloc<double>(P, std::max(U.psize, 1L), true);
     F.P32 = dalloc<float>(P, std::max(U.psize, 1L), true);
-    F.R64 = F.P64;
-    F.R32 = F.P32;
+    if (P->sym) {
+      F.R64 = F.P64;
+      F.R32 = F.P32;
+    } else {
+      F.R64 = dalloc<double>(P, std::max(U.psize, 1L), true);
+      F.R32 = dalloc<float>(P, std::max(U.psize, 1L), true);
+    }
     F.cb[0] = dalloc<double>(P, std::max(U.ncb, 1L) * cap, true);
     F.cb[1] = dalloc<float>(P, std::max(U.ncb, 1L) * cap, true);
     L[i + 1].Aelem = dalloc<double>(P, std::max(P->ul[i + 1].msize, 1L), true);
-    launch_uschur(U, P->ul[i + 1], F.Aelem, F.AIIinv64, F.P64, L[i + 1].Aelem, work, P->st);
+    launch_uschur(U, P->ul[i + 1], F.Aelem, F.AIIinv64, F.P64, P->sym ? nullptr : F.R64, L[i + 1].Aelem, work,
+                  P->st);
     launch_to_f32(F.AIIinv64, F.AIIinv32, U.asize, P->st);
     launch_to_f32(F.P64, F.P32, U.psize, P->st);
+    if (!P->sym) launch_to_f32(F.R64, F.R32, U.psize, P->st);
   }
   Level& Lc = L.back();
   if (Lc.nlam > UCOARSE_MAX) return HDG_ERR_UNSUPPORTED;
@@ -1714,13 +1722,16 @@ void upload_ulevels(hdg_problem* P) {
 
 }  // namespace
 
-hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, void* hip_stream,
-                                  hdg_handle* out) {
+hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, const double* kappa, int scheme,
+                                  void* hip_stream, hdg_handle* out) {
   if (!mesh || !out || !kappa || !mesh->xy || !mesh->tri || !mesh->seeds) return HDG_ERR_INVALID_ARG;
   if (mesh->nvert < 3 || mesh->ntri < 1 || mesh->nseeds < 1 || mesh->hlevels < 1 || mesh->hlevels > 16)
     return HDG_ERR_INVALID_ARG;
   if (k < 1 || k > 4) return HDG_ERR_UNSUPPORTED;
   if (!(tau > 0.0) || !std::isfinite(tau)) return HDG_ERR_INVALID_ARG;
+  if (scheme != HDG_SCHEME_HDG && scheme != HDG_SCHEME_SIPG && scheme != HDG_SCHEME_IIPG &&
+      scheme != HDG_SCHEME_NIPG)
+    return scheme == HDG_SCHEME_RT ? HDG_ERR_UNSUPPORTED : HDG_ERR_INVALID_ARG;
   *out = nullptr;
   hdg_problem* P = new (std::nothrow) hdg_problem();
   if (!P) return HDG_ERR_DEVICE;
@@ -1730,9 +1741,10 @@ hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, cons
     P->n = 0;
     P->k = k;
     P->tau = tau;
-    P->scheme = HDG_SCHEME_HDG;
-    P->codes = {HDG_SCHEME_HDG};
-    P->sym = true;
+    P->scheme = scheme;
+    P->codes = {scheme};
+    P->sf = sf_of(scheme);
+    P->sym = scheme == HDG_SCHEME_HDG || scheme == HDG_SCHEME_SIPG;
     P->st = (hipStream_t)hip_stream;
     const auto t0 = std::chrono::steady_clock::now();
     HDG_CHECK(hipStreamCreateWithFlags(&P->cap_st, hipStreamNonBlocking));
@@ -1752,6 +1764,12 @@ hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, cons
     P->rd.uF = upload(P, H.Fh);
     P->rd.uH = upload(P, H.Hh);
     P->rd.Jp = upload(P, H.Jp);
+    if (scheme != HDG_SCHEME_HDG) {
+      P->rd.uK = upload(P, H.Kh);
+      P->rd.uN = upload(P, H.Nh);
+      P->rd.uDe = upload(P, H.De);
+      P->rd.uGn = upload(P, H.Gnode);
+    }
     P->uxy = upload(P, H.xy);
     P->utri = upload(P, H.tri);
     P->utbnd = upload(P, H.tbnd);
@@ -1767,7 +1785,10 @@ hdg_status hdg_setup_unstructured(const hdg_umesh* mesh, int k, double tau, cons
       return HDG_ERR_INVALID_ARG;
     }
     P->urec = dalloc<double>(P, P->nelem * 3 * P->nv * (P->nl + P->nv), false);
-    launch_tri_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->Ae, P->W, P->urec, P->st);
+    if (scheme == HDG_SCHEME_HDG)
+      launch_tri_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->Ae, P->W, P->urec, P->st);
+    else
+      launch_tri_ipdg_dtn(k, P->nelem, P->rd, P->uxy, P->utri, P->kqp, tau, P->sf, P->Ae, P->W, P->urec, P->st);
     HDG_CHECK(hipStreamSynchronize(P->st));
     P->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     hdg_default_opts(&P->opts);

@@ -123,6 +123,7 @@ struct RefDevice {
   double *Vq = nullptr, *Bd = nullptr, *Fr = nullptr, *Vnode = nullptr;    // RT-H handles only
   // P^k triangles (unstructured handles only; the UHost reference matrices)
   double *uM = nullptr, *uMinv = nullptr, *uD = nullptr, *uE = nullptr, *uF = nullptr, *uH = nullptr;
+  double *uK = nullptr, *uN = nullptr, *uDe = nullptr, *uGn = nullptr;  // IPDG on triangles
 };
 
 // ---------------------------------------------------------------------------
@@ -179,6 +180,11 @@ struct UHost {
   std::vector<double> Fh;           // [3][nv][ne] <phi_i, mu_a> on edge s, mu in the edge's own direction
   std::vector<double> Hh;           // [ne][ne] <mu_a, mu_b> on the unit parameter
   std::vector<double> Jp;           // [ne][2] P^1 end values -> GLL values
+  // primal (IPDG) forms on the reference triangle
+  std::vector<double> Kh;           // [2][2][nv][nv] (d_r phi_i, d_r' phi_j)
+  std::vector<double> Nh;           // [3][2][nv][nv] edge s: <d_r phi_i, phi_j>
+  std::vector<double> De;           // [3][2][nv][ne] edge s: <d_r phi_i, mu_a>
+  std::vector<double> Gnode;        // [2][nv][nv] d_r phi_j at node a
   void build_reference(int k);
   void build_mesh(long nvert, const double* xy, long ntri, const int* tri, const double* seeds, int nseeds,
                   int hlevels);
@@ -414,13 +420,20 @@ void launch_apply_red(const Level& L, int mode, const T* x, const T* b, T* y, co
 void launch_tri_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri, const double* kappa,
                     double tau, double* Aelem, double* W, double* Rec, hipStream_t st);
 // g (gdir: boundary traces [nbedge][ne], lifted with the element maps; may be null)
+// the hybridized IPDG family on triangles (eq. IPG_H, s_f = sf): the same
+// outputs (recovery: u and q = -kappa grad u at the nodes)
+void launch_tri_ipdg_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri,
+                         const double* kappa, double tau, double sf, double* Aelem, double* W, double* Rec,
+                         hipStream_t st);
 void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, const double* Aelem,
                      const int* tbnd, const double* gdir, double* g, hipStream_t st);
 void launch_tri_reconstruct(int k, long ntri, const int* sface, const int* tbnd, const double* Rec,
                             const double* lam, const double* gdir, const double* f, double* u, double* q,
                             hipStream_t st);
 void launch_tri_pgalerkin(int k, long ntri, const double* Jp, const double* A0, double* A1, hipStream_t st);
-void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P,
+// R (null when the operator is symmetric): the restriction block
+// -A_II^-T A_BI^T J of every coarse cell, laid out as P
+void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P, double* R,
                    double* Acoarse, double* work, hipStream_t st);
 void launch_udinv(const Level& L, hipStream_t st);
 void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st);

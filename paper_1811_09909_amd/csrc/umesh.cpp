@@ -126,18 +126,49 @@ void UHost::build_reference(int k_) {
         }
     }
   Minvh = invert(Mh, nv);
+  Kh.assign(4 * nv * nv, 0.0);
+  for (int j = 0; j < q; ++j)
+    for (int i = 0; i < q; ++i) {
+      const double x = g[i] * (1 - g[j]), y = g[j], w = gw[i] * gw[j] * (1 - g[j]);
+      tb.eval(x, y, phi.data(), dx.data(), dy.data());
+      const double* d[2] = {dx.data(), dy.data()};
+      for (int r = 0; r < 2; ++r)
+        for (int rp = 0; rp < 2; ++rp)
+          for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) Kh[((r * 2 + rp) * nv + a) * nv + b] += w * d[r][a] * d[rp][b];
+    }
+  Gnode.assign(2 * nv * nv, 0.0);
+  {
+    int a = 0;
+    for (int jj = 0; jj <= k; ++jj)
+      for (int ii = 0; ii <= k - jj; ++ii, ++a) {
+        tb.eval((double)ii / k, (double)jj / k, phi.data(), dx.data(), dy.data());
+        for (int b = 0; b < nv; ++b) {
+          Gnode[(0 * nv + a) * nv + b] = dx[b];
+          Gnode[(1 * nv + a) * nv + b] = dy[b];
+        }
+      }
+  }
   const double vx[3] = {0.0, 1.0, 0.0}, vy[3] = {0.0, 0.0, 1.0};
   Eh.assign(3 * nv * nv, 0.0);
   Fh.assign(3 * nv * ne, 0.0);
   Hh.assign(ne * ne, 0.0);
+  Nh.assign(6 * nv * nv, 0.0);
+  De.assign(6 * nv * ne, 0.0);
   for (int s = 0; s < 3; ++s) {
     const int s1 = (s + 1) % 3;
     for (int t = 0; t < q; ++t) {
       const double x = vx[s] + g[t] * (vx[s1] - vx[s]), y = vy[s] + g[t] * (vy[s1] - vy[s]);
-      tb.eval(x, y, phi.data(), nullptr, nullptr);
+      tb.eval(x, y, phi.data(), dx.data(), dy.data());
+      const double* d[2] = {dx.data(), dy.data()};
       for (int a = 0; a < nv; ++a) {
         for (int b = 0; b < nv; ++b) Eh[(s * nv + a) * nv + b] += gw[t] * phi[a] * phi[b];
         for (int b = 0; b < ne; ++b) Fh[(s * nv + a) * ne + b] += gw[t] * phi[a] * lagrange_at(gll, b, g[t]);
+        for (int r = 0; r < 2; ++r) {
+          for (int b = 0; b < nv; ++b) Nh[((s * 2 + r) * nv + a) * nv + b] += gw[t] * d[r][a] * phi[b];
+          for (int b = 0; b < ne; ++b)
+            De[((s * 2 + r) * nv + a) * ne + b] += gw[t] * d[r][a] * lagrange_at(gll, b, g[t]);
+        }
       }
       if (s == 0)
         for (int a = 0; a < ne; ++a)

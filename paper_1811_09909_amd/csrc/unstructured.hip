@@ -219,6 +219,136 @@ __global__ void __launch_bounds__(64) tri_dtn_kernel(long ntri, const double* __
   }
 }
 
+// Element maps of the hybridized IPDG family on P^k triangles (eq. IPG_H):
+// with rows for the test function, L = kappa (K - s_f N - N^T) + tau E,
+// R = tau G - s_f kappa D, C = tau G^T - kappa D^T (K the stiffness matrix,
+// N_ij = <phi_j, grad phi_i . n>, D_il = <mu_l, grad phi_i . n>); L X =
+// [R | M_T] by Gauss-Jordan without pivoting (the symmetric part of L is
+// positive definite at tau = (p+1)(p+2)/h_min), A^e = tau H - C X_R, the
+// load map (C X_M)^T and the recovery maps u = X [Lambda; f], q_c = -kappa
+// d_c u at the nodes.  Geometry as in tri_dtn_kernel: gradients through
+// J^-1, edge integrals scaled by the length, reversed slots read the
+// reference columns k - a.
+template <int K>
+__global__ void __launch_bounds__(64) tri_ipdg_dtn_kernel(
+    long ntri, const double* __restrict__ Mh, const double* __restrict__ Kh, const double* __restrict__ Nh,
+    const double* __restrict__ De, const double* __restrict__ Eh, const double* __restrict__ Fh,
+    const double* __restrict__ Hh, const double* __restrict__ Gn, const double* __restrict__ xy,
+    const int* __restrict__ tri, const double* __restrict__ kappa, double tau, double sf,
+    double* __restrict__ Aelem, double* __restrict__ W, double* __restrict__ Rec) {
+  constexpr int NV = (K + 1) * (K + 2) / 2, NE = K + 1, NL = 3 * NE, RL = NV + NL + NV;
+  __shared__ double sL[NV * RL];
+  __shared__ double sC[NL * NV];
+  __shared__ double fac[NV];
+  const long t = blockIdx.x;
+  if (t >= ntri) return;
+  const int tid = threadIdx.x;
+  int vid[3];
+  double px[3], py[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    vid[s] = tri[3 * t + s];
+    px[s] = xy[2 * vid[s]];
+    py[s] = xy[2 * vid[s] + 1];
+  }
+  const double j00 = px[1] - px[0], j01 = px[2] - px[0], j10 = py[1] - py[0], j11 = py[2] - py[0];
+  const double det = j00 * j11 - j01 * j10;
+  const double Ji[2][2] = {{j11 / det, -j01 / det}, {-j10 / det, j00 / det}};
+  double ell[3], gn[3][2];
+  int flip[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int s1 = (s + 1) % 3;
+    const double dx = px[s1] - px[s], dy = py[s1] - py[s];
+    ell[s] = sqrt(dx * dx + dy * dy);
+    const double nx = dy / ell[s], ny = -dx / ell[s];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) gn[s][r] = Ji[r][0] * nx + Ji[r][1] * ny;  // d/dxi_r weight of grad . n
+    flip[s] = vid[s] > vid[s1];
+  }
+  double G[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int rp = 0; rp < 2; ++rp) G[r][rp] = Ji[r][0] * Ji[rp][0] + Ji[r][1] * Ji[rp][1];
+  const double kap = kappa[t];
+  for (int idx = tid; idx < NV * RL; idx += 64) {
+    const int i = idx / RL, j = idx % RL;
+    double v;
+    if (j < NV) {
+      double kk = 0.0, nij = 0.0, nji = 0.0, e = 0.0;
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int rp = 0; rp < 2; ++rp) kk += G[r][rp] * Kh[((r * 2 + rp) * NV + i) * NV + j];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          nij += ell[s] * gn[s][r] * Nh[((s * 2 + r) * NV + i) * NV + j];
+          nji += ell[s] * gn[s][r] * Nh[((s * 2 + r) * NV + j) * NV + i];
+        }
+        e += ell[s] * Eh[(s * NV + i) * NV + j];
+      }
+      v = kap * (det * kk - sf * nij - nji) + tau * e;
+    } else if (j < NV + NL) {
+      const int l = j - NV, s = l / NE, a = l % NE, ap = flip[s] ? NE - 1 - a : a;
+      double dv = 0.0;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) dv += gn[s][r] * De[((s * 2 + r) * NV + i) * NE + ap];
+      dv *= ell[s];
+      const double gv = ell[s] * Fh[(s * NV + i) * NE + ap];
+      v = tau * gv - sf * kap * dv;
+      sC[l * NV + i] = tau * gv - kap * dv;
+    } else {
+      v = det * Mh[i * NV + (j - NV - NL)];
+    }
+    sL[idx] = v;
+  }
+  __syncthreads();
+  for (int p = 0; p < NV; ++p) {
+    const double piv = sL[p * RL + p];
+    if (tid < NV) fac[tid] = sL[tid * RL + p] / piv;
+    __syncthreads();
+    for (int idx = tid; idx < NV * RL; idx += 64) {
+      const int r = idx / RL, c = idx % RL;
+      if (r != p && c > p) sL[idx] -= fac[r] * sL[p * RL + c];
+    }
+    __syncthreads();
+    for (int c = p + 1 + tid; c < RL; c += 64) sL[p * RL + c] /= piv;
+    __syncthreads();
+  }
+  double* Ae = Aelem + t * NL * NL;
+  for (int idx = tid; idx < NL * NL; idx += 64) {
+    const int l = idx / NL, lp = idx % NL, s = l / NE, sp = lp / NE;
+    double v = (s == sp) ? tau * ell[s] * Hh[(l % NE) * NE + (lp % NE)] : 0.0;
+    for (int i = 0; i < NV; ++i) v -= sC[l * NV + i] * sL[i * RL + NV + lp];
+    Ae[idx] = v;
+  }
+  double* Wt = W + t * NV * NL;
+  for (int idx = tid; idx < NV * NL; idx += 64) {
+    const int j = idx / NL, l = idx % NL;
+    double v = 0.0;
+    for (int i = 0; i < NV; ++i) v += sC[l * NV + i] * sL[i * RL + NV + NL + j];
+    Wt[idx] = v;
+  }
+  if (!Rec) return;
+  constexpr int RC = NL + NV;
+  double* Rt = Rec + t * 3 * NV * RC;
+  for (int idx = tid; idx < NV * RC; idx += 64) {
+    const int a = idx / RC, col = idx % RC;
+    Rt[2 * NV * RC + idx] = sL[a * RL + NV + col];
+    double g0 = 0.0, g1 = 0.0;  // d_xi0 u, d_xi1 u at node a
+    for (int m = 0; m < NV; ++m) {
+      const double x = sL[m * RL + NV + col];
+      g0 += Gn[(0 * NV + a) * NV + m] * x;
+      g1 += Gn[(1 * NV + a) * NV + m] * x;
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Rt[c * NV * RC + idx] = -kap * (Ji[0][c] * g0 + Ji[1][c] * g1);
+  }
+}
+
 // u, q (nodal) of every triangle from its traces (interior: lambda; boundary
 // edges: gdir or 0) and f
 template <int K>
@@ -323,7 +453,7 @@ __global__ void __launch_bounds__(256) uschur_kernel(
     const double* __restrict__ fJ, const long* __restrict__ csptr, const long* __restrict__ cmoff,
     const long* __restrict__ aoff, const long* __restrict__ poff, const long* __restrict__ woff,
     const double* __restrict__ Afine, double* __restrict__ AIIinv, double* __restrict__ P,
-    double* __restrict__ Acoarse, double* __restrict__ work) {
+    double* __restrict__ R, double* __restrict__ Acoarse, double* __restrict__ work) {
   __shared__ double prow[UMACRO_MAX_DOFS], pcol[UMACRO_MAX_DOFS];
   const long C = blockIdx.x;
   if (C >= ncoarse) return;
@@ -377,6 +507,15 @@ __global__ void __launch_bounds__(256) uschur_kernel(
       s += Wm[(long)i * n2 + nI2 + 2 * b] * fJ[4 * f + j] + Wm[(long)i * n2 + nI2 + 2 * b + 1] * fJ[4 * f + 2 + j];
     }
     P[poff[C] + idx] = -s;
+    if (R) {  // restriction block from the swept lower-left block -A_BI A_II^-1
+      double sr = 0.0;
+      for (int b = 0; b < nB; ++b) {
+        if (bslot[b0 + b] != q) continue;
+        const long f = bface[b0 + b];
+        sr += Wm[(long)(nI2 + 2 * b) * n2 + i] * fJ[4 * f + j] + Wm[(long)(nI2 + 2 * b + 1) * n2 + i] * fJ[4 * f + 2 + j];
+      }
+      R[poff[C] + idx] = sr;
+    }
   }
   for (int idx = tid; idx < 2 * nB * nc2; idx += nt) {
     const int r = idx / nc2, q2 = idx % nc2, q = q2 / 2, j = q2 % 2;
@@ -799,6 +938,18 @@ void launch_tri_dtn(int k, long ntri, const RefDevice& rd, const double* xy, con
   HDG_CHECK(hipGetLastError());
 }
 
+void launch_tri_ipdg_dtn(int k, long ntri, const RefDevice& rd, const double* xy, const int* tri,
+                         const double* kappa, double tau, double sf, double* Aelem, double* W, double* Rec,
+                         hipStream_t st) {
+  if (ntri == 0) return;
+  dispatch_k(k, [&](auto K_) {
+    constexpr int K = decltype(K_)::value;
+    hipLaunchKernelGGL((tri_ipdg_dtn_kernel<K>), dim3((unsigned)ntri), dim3(64), 0, st, ntri, rd.uM, rd.uK, rd.uN,
+                       rd.uDe, rd.uE, rd.uF, rd.uH, rd.uGn, xy, tri, kappa, tau, sf, Aelem, W, Rec);
+  });
+  HDG_CHECK(hipGetLastError());
+}
+
 void launch_tri_load(int k, const ULevel& U, const double* W, const double* f, const double* Aelem,
                      const int* tbnd, const double* gdir, double* g, hipStream_t st) {
   if (U.nface == 0) return;
@@ -828,12 +979,12 @@ void launch_tri_pgalerkin(int k, long ntri, const double* Jp, const double* A0, 
   HDG_CHECK(hipGetLastError());
 }
 
-void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P, double* Acoarse,
-                   double* work, hipStream_t st) {
+void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double* AIIinv, double* P, double* R,
+                   double* Acoarse, double* work, hipStream_t st) {
   if (F.ncoarse == 0) return;
   hipLaunchKernelGGL(uschur_kernel, dim3((unsigned)F.ncoarse), dim3(256), 0, st, F.ncoarse, F.ccptr, F.ccell, F.sptr,
                      F.sloc, F.moff, F.iptr, F.bptr, F.bface, F.bslot, F.fJ, C.sptr, C.moff, F.aoff, F.poff, F.woff,
-                     Afine, AIIinv, P, Acoarse, work);
+                     Afine, AIIinv, P, R, Acoarse, work);
   HDG_CHECK(hipGetLastError());
 }
 

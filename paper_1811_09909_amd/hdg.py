@@ -70,10 +70,11 @@ class Problem:
         self.version = 0  # bumped by every update_kappa / build: operator state of the handle
 
     @classmethod
-    def unstructured(cls, vertices, triangles, k, kappa, seeds, hlevels, tau=1.0, device="cuda"):
-        """HDG on an unstructured triangle mesh with the seed-point
-        agglomeration hierarchy (``hdg_setup_unstructured``): host vertex,
-        triangle and seed arrays, kappa one value per triangle."""
+    def unstructured(cls, vertices, triangles, k, kappa, seeds, hlevels, tau=1.0, device="cuda", scheme="hdg"):
+        """HDG (or ``scheme`` "sipg", "iipg", "nipg") on an unstructured
+        triangle mesh with the seed-point agglomeration hierarchy
+        (``hdg_setup_unstructured``): host vertex, triangle and seed arrays,
+        kappa one value per triangle."""
         self = cls.__new__(cls)
         self.lib = L.load()
         if not torch.cuda.is_available():
@@ -81,7 +82,9 @@ class Problem:
         self.device = torch.device(device)
         self.d, self.n, self.k, self.tau = 2, 0, k, float(tau)
         self.kind = L.KAPPA_PER_ELEMENT
-        self.scheme = "hdg"
+        if scheme not in L.SCHEMES:
+            raise ValueError(f"unknown scheme {scheme}")
+        self.scheme = scheme
         xy = np.ascontiguousarray(vertices, dtype=np.float64)
         tri = np.ascontiguousarray(triangles, dtype=np.int32)
         sd = np.ascontiguousarray(seeds, dtype=np.float64)
@@ -90,7 +93,7 @@ class Problem:
         kap = _dev(kappa, torch.float64, self.device)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        L.check(self.lib.hdg_setup_unstructured(ctypes.byref(mesh), k, self.tau, _vp(kap),
+        L.check(self.lib.hdg_setup_unstructured(ctypes.byref(mesh), k, self.tau, _vp(kap), L.SCHEMES[scheme],
                                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                 "hdg_setup_unstructured")
         self.h = h

@@ -491,6 +491,24 @@ def unstructured_legs(args):
                                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["kernels"] = kern
     P.close()
+    # NIPG-H on the same mesh (Example II's Table NIPG setting, tau = (p+1)(p+2)/h_min): GMRES + V-cycle
+    import numpy as np
+    V, T = wl.vertices, wl.triangles
+    e = np.concatenate([T[:, [0, 1]], T[:, [1, 2]], T[:, [2, 0]]])
+    hmin = float(np.hypot(*(V[e[:, 0]] - V[e[:, 1]]).T).min())
+    Pn = Problem.unstructured(V, T, k, kap, wl.seeds, wl.hlevels, tau=(k + 1) * (k + 2) / hmin, scheme="nipg")
+    nip = {"tau": round((k + 1) * (k + 2) / hmin, 3)}
+    for nm, prec in (("fp64", L.FP64), ("mixed", L.MIXED)):
+        Pn.build(sweeps=args.sweeps, growth=1, local_corr=L.LC_PRE, precision=prec, method=L.METHOD_GMRES,
+                 max_it=200, coarse_n=args.ucoarse_n)
+        progress(f"unstructured nipg {nm} leg")
+        times, _, infos = timed_solves(Pn, f, args.tol, args.steps, 1)
+        ms = 1e3 * median(times)
+        progress(f"unstructured nipg {nm}: {ms:.1f} ms/solve, {infos[-1]['iters']} iterations")
+        nip[nm] = {"value": round(Pn.nlam / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "iters": infos[-1]["iters"], "relres": max(i["relres"] for i in infos)}
+    out["nipg_gmres"] = nip
+    Pn.close()
     return out
 
 

@@ -195,9 +195,18 @@ __device__ inline void gj_inverse(double* A) {
     gj_inverse_reg<N, NT>(A);
 }
 
+// k-steps of a product tile unrolled (loads of several steps in flight)
+#ifndef HDG_WG_MFMA_UNROLL
+#define HDG_WG_MFMA_UNROLL 4
+#endif
+
 // lanes per element of the 2D element kernel
 #ifndef HDG_ELEM_NT2
 #define HDG_ELEM_NT2 256
+#endif
+// lanes per element of the 3D, k = 3 element kernel
+#ifndef HDG_ELEM_NT3
+#define HDG_ELEM_NT3 1024
 #endif
 
 // Dense product on the matrix cores, shared by the workgroup's wavefronts:
@@ -218,7 +227,7 @@ __device__ inline void wg_mfma(FA a, FB b, FC c) {
     const int i0 = (t / TN) * 16, j0 = (t % TN) * 16;
     const int ia = i0 + l16, jb = j0 + l16;
     mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+#pragma unroll HDG_WG_MFMA_UNROLL
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + l4;
       const double av = (ia < M && k < K) ? a(ia, k) : 0.0;
@@ -982,7 +991,7 @@ void launch_element_dtn(int d, int k, long nelem, double tau, int tau_kappa, con
                         double* Aelem, double* W, double* Kinv, double* Minv, hipStream_t st) {
   dispatch_dk(d, k, [&](auto D_, auto K_) {
     constexpr int D = decltype(D_)::value, K = decltype(K_)::value;
-    constexpr int NT = D == 2 ? HDG_ELEM_NT2 : 256;
+    constexpr int NT = D == 2 ? HDG_ELEM_NT2 : (K == 3 ? HDG_ELEM_NT3 : 256);
     hipLaunchKernelGGL((element_dtn_kernel<D, K, NT>), dim3((unsigned)nelem), dim3(NT), 0, st, nelem, tau,
                        tau_kappa, rd.Phi, rd.Wq, rd.B, rd.F, rd.G, rd.E, rd.H, kqp, Aelem, W, Kinv, Minv);
   });

@@ -11,6 +11,7 @@
 //    restriction block R = -A_II^-T A_BI^T J is formed as well,
 //  * dense inverse of the coarsest operator (Algorithm 1, B_1 = A_1^-1).
 #include "hdg_internal.hpp"
+#include "mfma_dev.hpp"
 
 namespace hdg {
 
@@ -204,6 +205,8 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
   __shared__ int map[(1 << D) * NLC];
   __shared__ int bsrc[NB];      // B DOF -> (child, child-local DOF) that holds it
   __shared__ int isrc[2 * NI];  // I DOF -> its two (child, child-local DOF)
+  constexpr int CB = 32;        // 3D: columns of A_IB per matrix-core block
+  __shared__ double sX[D == 3 ? NI * CB : 1];
   const bool nonsym = R64 != nullptr;
   const int tid = threadIdx.x;
   const int nm = n / 2;
@@ -264,7 +267,10 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
     }
     __syncthreads();
   }
-  gj_lds<NI>(sII, tid, NT);
+  if constexpr (NI % 16 == 0)
+    gj_inverse_blocked<NI, NT>(sII);
+  else
+    gj_lds<NI>(sII, tid, NT);
   // J: coarse DOF (S, V) -> B DOF (S*NS + t, v) with weight jw(t, v, V)
   auto jw = [](int t, int v, int V) {
     double w = 1.0;
@@ -297,7 +303,25 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
     Ai32[aos_off<float>(M, vpad<float>(NI * NI), idx)] = (float)sII[idx];
   }
   __syncthreads();
-  if (!nonsym) {
+  if constexpr (D == 3) {
+    // by blocks of CB columns on the matrix cores: X = A_II^-1 A_IB(:, block),
+    // then S(:, block) = A_BB - A_IB^T X (symmetric levels) or X written back
+    // in place of A_IB(:, block) (nonsymmetric levels: Z = A_II^-1 A_IB)
+    static_assert(NB % CB == 0, "whole column blocks");
+    for (int j0 = 0; j0 < NB; j0 += CB) {
+      wg_mfma<NI, CB, NI, NT>([&](int i, int l) { return sII[i * NI + l]; },
+                              [&](int l, int j) { return sIB[l * NB + j0 + j]; },
+                              [&](int i, int j, double v) { sX[i * CB + j] = v; });
+      __syncthreads();
+      if (!nonsym)
+        wg_mfma<NB, CB, NI, NT>([&](int i, int l) { return sIB[l * NB + i]; },
+                                [&](int l, int j) { return sX[l * CB + j]; },
+                                [&](int i, int j, double v) { sBB[i * NB + j0 + j] -= v; });
+      else
+        for (int idx = tid; idx < NI * CB; idx += NT) sIB[(idx / CB) * NB + j0 + idx % CB] = sX[idx];
+      __syncthreads();
+    }
+  } else if (!nonsym) {
     // S = A_BB - A_IB^T A_II^-1 A_IB, column j owned by one thread
     for (int j = tid; j < NB; j += NT) {
       double x[NI];
@@ -323,6 +347,8 @@ __global__ void __launch_bounds__(NT) macro_schur_kernel(int n, const double* __
       }
       for (int i = 0; i < NI; ++i) sIB[i * NB + j] = x[i];
     }
+  }
+  if (nonsym) {
     __syncthreads();
     // S = A_BB - A_BI Z: row i of A_BI lives in the one child that holds B DOF i
     for (int idx = tid; idx < NB * NB; idx += NT) {

@@ -143,7 +143,8 @@ __global__ void scale_copy_kernel(long n, double s, const double* __restrict__ s
   d32[i] = (float)v;
 }
 
-// Ac[(s1,v1),(s2,v2)] = sum_ab Jp[a][v1] A[(s1,a),(s2,b)] Jp[b][v2]
+// Ac[(s1,v1),(s2,v2)] = sum_a Jp[a][v1] (sum_b A[(s1,a),(s2,b)] Jp[b][v2]),
+// a lane per entry (2D: the lanes of a wave share their rows of A)
 __global__ void pgalerkin_kernel(int d, int ne, long nelem, const double* __restrict__ Jp,
                                  const double* __restrict__ Af, double* __restrict__ Ac) {
   const int nc = 1 << (d - 1);
@@ -161,6 +162,51 @@ __global__ void pgalerkin_kernel(int d, int ne, long nelem, const double* __rest
     s += Jp[a * nc + v1] * inner;
   }
   Ac[t] = s;
+}
+
+// The same product by rows (3D, where a lane per entry re-reads 256 entries
+// of A): a workgroup takes 256 / nl elements; first a lane per row of A forms
+// that row of T = A blockdiag(Jp) in LDS (each row of A read once, in order),
+// then a lane per output entry sums blockdiag(Jp)^T T.  The sums run in the
+// same order as in the entry-by-entry form.
+constexpr int PG_MAX_J = 64;  // ne * nc of the supported (d, k)
+__global__ void __launch_bounds__(256) pgalerkin_rows_kernel(int d, int ne, long nelem, const double* __restrict__ Jp,
+                                                        const double* __restrict__ Af, double* __restrict__ Ac) {
+  extern __shared__ double sT[];  // [256 / nl][nl][ncl]
+  __shared__ double sJ[PG_MAX_J];
+  const int nc = 1 << (d - 1);
+  const int nl = 2 * d * ne, ncl = 2 * d * nc;
+  const int epw = 256 / nl;
+  const long T0 = blockIdx.x * (long)epw;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ne * nc; i += 256) sJ[i] = Jp[i];
+  __syncthreads();
+  {
+    const int e = tid / nl, r = tid % nl;
+    if (e < epw && T0 + e < nelem) {
+      const double* row = Af + ((T0 + e) * nl + r) * (long)nl;
+      double* trow = sT + (e * nl + r) * ncl;
+      for (int s2 = 0; s2 < 2 * d; ++s2) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < ne; ++b) {
+          const double x = row[s2 * ne + b];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (v < nc) acc[v] += x * sJ[b * nc + v];
+        }
+        for (int v = 0; v < nc; ++v) trow[s2 * nc + v] = acc[v];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < epw * ncl * ncl; idx += 256) {
+    const int e = idx / (ncl * ncl), rr = idx % (ncl * ncl);
+    if (T0 + e >= nelem) break;
+    const int I = rr / ncl, J = rr % ncl, s1 = I / nc, v1 = I % nc;
+    double s = 0.0;
+    for (int a = 0; a < ne; ++a) s += sJ[a * nc + v1] * sT[(e * nl + s1 * ne + a) * ncl + J];
+    Ac[(T0 + e) * ncl * ncl + rr] = s;
+  }
 }
 
 template <int N>
@@ -613,9 +659,19 @@ void launch_dinv(const Level& L, double omega, hipStream_t st, int mode) {
 
 void launch_pgalerkin(int d, int ne, long nelem, const double* Jp, const double* Afine, double* Acoarse,
                       hipStream_t st) {
-  const int ncl = 2 * d * (1 << (d - 1));
-  long tot = nelem * ncl * ncl;
-  hipLaunchKernelGGL(pgalerkin_kernel, dim3(nblk(tot)), dim3(256), 0, st, d, ne, nelem, Jp, Afine, Acoarse);
+  const int nc = 1 << (d - 1), ncl = 2 * d * nc, nl = 2 * d * ne;
+  if (nelem <= 0) return;
+  if (d == 2) {
+    hipLaunchKernelGGL(pgalerkin_kernel, dim3(nblk(nelem * ncl * ncl)), dim3(256), 0, st, d, ne, nelem, Jp, Afine,
+                       Acoarse);
+  } else {
+    if (nl > 256 || ne * nc > PG_MAX_J) throw HipError{hipErrorInvalidValue, "p-Galerkin: element too large"};
+    const int epw = 256 / nl;
+    const long nb = (nelem + epw - 1) / epw;
+    const size_t lds = (size_t)epw * nl * ncl * sizeof(double);
+    hipLaunchKernelGGL(pgalerkin_rows_kernel, dim3((unsigned)nb), dim3(256), lds, st, d, ne, nelem, Jp, Afine,
+                       Acoarse);
+  }
   HDG_CHECK(hipGetLastError());
 }
 

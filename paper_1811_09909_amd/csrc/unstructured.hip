@@ -16,6 +16,7 @@
 #include "blas.hpp"
 #include "reduce.hpp"
 #include "trace_dev.hpp"
+#include "mfma_dev.hpp"
 
 namespace hdg {
 
@@ -643,23 +644,88 @@ __global__ void __launch_bounds__(256) udense_inverse_kernel(int N, double* __re
   }
 }
 
-// one pivot sweep of the same inversion out of place (large coarsest levels:
-// one launch per pivot, one lane per entry)
-__global__ void udense_step_kernel(long N, long p, const double* __restrict__ A, double* __restrict__ B) {
-  const long idx = blockIdx.x * 256L + threadIdx.x;
-  if (idx >= N * N) return;
-  const long i = idx / N, j = idx % N;
-  const double d = 1.0 / A[p * N + p];
-  double v;
-  if (i == p && j == p)
-    v = d;
-  else if (i == p)
-    v = A[idx] * d;
-  else if (j == p)
-    v = -A[idx] * d;
-  else
-    v = A[idx] - A[i * N + p] * A[p * N + j] * d;
-  B[idx] = v;
+// Blocked Gauss-Jordan inverse of a large dense coarsest operator, in place
+// in A (row-major, leading dimension N), by 64 x 64 blocks; entries past N
+// act as the identity.  Block step p: P = A_pp^-1 (one workgroup), then
+// A_pj <- P A_pj, A_ij -= A_ip A_pj (i, j != p), A_ip <- -A_ip P and
+// A_pp <- P, every block product on the matrix cores.  Four launches per
+// block step instead of one per pivot; no pivoting, the same elimination as
+// the pivot-by-pivot sweep up to the rounding order.
+constexpr int UBK = 64;
+
+__device__ inline double ublk_get(const double* A, long N, long i, long j) {
+  return (i < N && j < N) ? A[i * N + j] : (i == j ? 1.0 : 0.0);
+}
+
+__global__ void __launch_bounds__(256) ublk_pivot_kernel(long N, int p, const double* __restrict__ A,
+                                                         double* __restrict__ Pb) {
+  __shared__ double s[UBK * UBK];
+  const long r0 = (long)p * UBK;
+  for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) s[idx] = ublk_get(A, N, r0 + idx / UBK, r0 + idx % UBK);
+  gj_inverse_blocked<UBK, 256>(s);  // starts and ends with a barrier
+  for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) Pb[idx] = s[idx];
+}
+
+// A_pj <- P A_pj for every column block j != p (workgroup j)
+__global__ void __launch_bounds__(256) ublk_row_kernel(long N, int p, const double* __restrict__ Pb,
+                                                       double* __restrict__ A) {
+  const int jb = blockIdx.x;
+  if (jb == p) return;
+  __shared__ double sP[UBK * UBK], sB[UBK * UBK];
+  const long r0 = (long)p * UBK, c0 = (long)jb * UBK;
+  for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) {
+    sP[idx] = Pb[idx];
+    sB[idx] = ublk_get(A, N, r0 + idx / UBK, c0 + idx % UBK);
+  }
+  __syncthreads();
+  wg_mfma<UBK, UBK, UBK, 256>([&](int i, int k) { return sP[i * UBK + k]; },
+                              [&](int k, int j) { return sB[k * UBK + j]; },
+                              [&](int i, int j, double v) {
+                                if (r0 + i < N && c0 + j < N) A[(r0 + i) * N + c0 + j] = v;
+                              });
+}
+
+// A_ij -= A_ip A_pj for i, j != p (workgroup (j, i))
+__global__ void __launch_bounds__(256) ublk_trail_kernel(long N, int p, double* __restrict__ A) {
+  const int ib = blockIdx.y, jb = blockIdx.x;
+  if (ib == p || jb == p) return;
+  __shared__ double sL[UBK * UBK], sR[UBK * UBK];
+  const long r0 = (long)ib * UBK, c0 = (long)jb * UBK, k0 = (long)p * UBK;
+  for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) {
+    sL[idx] = ublk_get(A, N, r0 + idx / UBK, k0 + idx % UBK);
+    sR[idx] = ublk_get(A, N, k0 + idx / UBK, c0 + idx % UBK);
+  }
+  __syncthreads();
+  wg_mfma<UBK, UBK, UBK, 256>([&](int i, int k) { return sL[i * UBK + k]; },
+                              [&](int k, int j) { return sR[k * UBK + j]; },
+                              [&](int i, int j, double v) {
+                                if (r0 + i < N && c0 + j < N) A[(r0 + i) * N + c0 + j] -= v;
+                              });
+}
+
+// A_ip <- -A_ip P for i != p, A_pp <- P (workgroup i)
+__global__ void __launch_bounds__(256) ublk_col_kernel(long N, int p, const double* __restrict__ Pb,
+                                                       double* __restrict__ A) {
+  const int ib = blockIdx.x;
+  const long r0 = (long)ib * UBK, c0 = (long)p * UBK;
+  if (ib == p) {
+    for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) {
+      const long i = r0 + idx / UBK, j = c0 + idx % UBK;
+      if (i < N && j < N) A[i * N + j] = Pb[idx];
+    }
+    return;
+  }
+  __shared__ double sP[UBK * UBK], sB[UBK * UBK];
+  for (int idx = threadIdx.x; idx < UBK * UBK; idx += 256) {
+    sP[idx] = Pb[idx];
+    sB[idx] = ublk_get(A, N, r0 + idx / UBK, c0 + idx % UBK);
+  }
+  __syncthreads();
+  wg_mfma<UBK, UBK, UBK, 256>([&](int i, int k) { return sB[i * UBK + k]; },
+                              [&](int k, int j) { return sP[k * UBK + j]; },
+                              [&](int i, int j, double v) {
+                                if (r0 + i < N && c0 + j < N) A[(r0 + i) * N + c0 + j] = -v;
+                              });
 }
 
 // row-major triangle maps -> AoSoA over triangles in 16-byte groups (FP64
@@ -1008,12 +1074,15 @@ void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st) {
                      U.sface, U.moff, L.Aelem, work);
   if (N <= 512) {
     hipLaunchKernelGGL(udense_inverse_kernel, dim3(1), dim3(256), 0, st, (int)N, work, L.Ainv64, L.Ainv32);
-  } else {  // work holds two N x N buffers
+  } else {  // work holds two N x N buffers: A, then the pivot-block inverse
     double* A = work;
-    double* B = work + N * N;
-    for (long p = 0; p < N; ++p) {
-      hipLaunchKernelGGL(udense_step_kernel, dim3(nb256(N * N)), dim3(256), 0, st, N, p, A, B);
-      std::swap(A, B);
+    double* Pb = work + N * N;
+    const int nbk = (int)((N + UBK - 1) / UBK);
+    for (int p = 0; p < nbk; ++p) {
+      hipLaunchKernelGGL(ublk_pivot_kernel, dim3(1), dim3(256), 0, st, N, p, A, Pb);
+      hipLaunchKernelGGL(ublk_row_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
+      hipLaunchKernelGGL(ublk_trail_kernel, dim3(nbk, nbk), dim3(256), 0, st, N, p, A);
+      hipLaunchKernelGGL(ublk_col_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
     }
     HDG_CHECK(hipMemcpyAsync(L.Ainv64, A, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(f32_kernel, dim3(1024), dim3(256), 0, st, A, L.Ainv32, N * N);

@@ -579,25 +579,6 @@ __global__ void dense_assemble_kernel(int d, int n, int ne, int color, long N, c
   if (gid[0] >= 0 && gid[1] >= 0) A[gid[0] * N + gid[1]] += Aelem[T * nl * nl + ij];
 }
 
-// One Gauss-Jordan elimination step on pivot k, out of place (A -> B), for
-// an SPD matrix (no pivoting); after N steps B holds A^-1.
-__global__ void gj_step_kernel(long N, int k, const double* __restrict__ A, double* __restrict__ B) {
-  const long t = blockIdx.x * 256L + threadIdx.x;
-  if (t >= N * N) return;
-  const long i = t / N, j = t % N;
-  const double p = 1.0 / A[(long)k * N + k];
-  double v;
-  if (i == k && j == k)
-    v = p;
-  else if (i == k)
-    v = A[t] * p;
-  else if (j == k)
-    v = -A[t] * p;
-  else
-    v = A[t] - A[i * N + k] * A[(long)k * N + j] * p;
-  B[t] = v;
-}
-
 __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, long n) {
   for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) b[i] = (float)a[i];
 }
@@ -690,7 +671,7 @@ void launch_macro_schur(const Level& fine, Level& coarse, hipStream_t st) {
 void launch_coarse_inverse(const Level& L, hipStream_t st) {
   if (L.nlam == 0) return;
   if (L.nlam > 64) {
-    // dense assembly, then N out-of-place Gauss-Jordan steps (FP64)
+    // dense assembly, then the blocked Gauss-Jordan inverse (FP64)
     const long N = L.nlam;
     double *A = nullptr, *B = nullptr;
     HDG_CHECK(hipMalloc((void**)&A, sizeof(double) * N * N));
@@ -700,10 +681,7 @@ void launch_coarse_inverse(const Level& L, hipStream_t st) {
     for (int color = 0; color < (1 << L.d); ++color)
       hipLaunchKernelGGL(dense_assemble_kernel, dim3(nblk(tot)), dim3(256), 0, st, L.d, L.n, L.ne, color, N, L.Aelem,
                          A);
-    for (long k = 0; k < N; ++k) {
-      hipLaunchKernelGGL(gj_step_kernel, dim3(nblk(N * N)), dim3(256), 0, st, N, (int)k, A, B);
-      std::swap(A, B);
-    }
+    launch_dense_inverse_blocked(N, A, B, st);  // B (N * N >= 4,096 doubles) holds the pivot blocks
     HDG_CHECK(hipMemcpyAsync(L.Ainv64, A, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, st, A, L.Ainv32, N * N);
     HDG_CHECK(hipGetLastError());

@@ -437,6 +437,9 @@ void launch_uschur(const ULevel& F, const ULevel& C, const double* Afine, double
                    double* Acoarse, double* work, hipStream_t st);
 void launch_udinv(const Level& L, hipStream_t st);
 void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st);
+// in-place inverse of a dense N x N matrix (row-major) by Gauss-Jordan over
+// 64 x 64 blocks, no pivoting; Pb: 4,096 doubles of device scratch
+void launch_dense_inverse_blocked(long N, double* A, double* Pb, hipStream_t st);
 void launch_umaps(const Level& L, hipStream_t st);
 void launch_to_f32(const double* x, float* y, long n, hipStream_t st);
 // unstructured trace kernels (dispatched from the launchers above when L.u

@@ -1065,6 +1065,19 @@ void launch_udinv(const Level& L, hipStream_t st) {
   HDG_CHECK(hipGetLastError());
 }
 
+void launch_dense_inverse_blocked(long N, double* A, double* Pb, hipStream_t st) {
+  if (N <= 0) return;
+  if (N > 64L * 65535) throw HipError{hipErrorInvalidValue, "dense inverse too large"};
+  const int nbk = (int)((N + UBK - 1) / UBK);
+  for (int p = 0; p < nbk; ++p) {
+    hipLaunchKernelGGL(ublk_pivot_kernel, dim3(1), dim3(256), 0, st, N, p, A, Pb);
+    hipLaunchKernelGGL(ublk_row_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
+    hipLaunchKernelGGL(ublk_trail_kernel, dim3(nbk, nbk), dim3(256), 0, st, N, p, A);
+    hipLaunchKernelGGL(ublk_col_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
+  }
+  HDG_CHECK(hipGetLastError());
+}
+
 void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st) {
   const ULevel& U = *L.u;
   const long N = L.nlam;
@@ -1076,14 +1089,7 @@ void launch_ucoarse_inverse(const Level& L, double* work, hipStream_t st) {
     hipLaunchKernelGGL(udense_inverse_kernel, dim3(1), dim3(256), 0, st, (int)N, work, L.Ainv64, L.Ainv32);
   } else {  // work holds two N x N buffers: A, then the pivot-block inverse
     double* A = work;
-    double* Pb = work + N * N;
-    const int nbk = (int)((N + UBK - 1) / UBK);
-    for (int p = 0; p < nbk; ++p) {
-      hipLaunchKernelGGL(ublk_pivot_kernel, dim3(1), dim3(256), 0, st, N, p, A, Pb);
-      hipLaunchKernelGGL(ublk_row_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
-      hipLaunchKernelGGL(ublk_trail_kernel, dim3(nbk, nbk), dim3(256), 0, st, N, p, A);
-      hipLaunchKernelGGL(ublk_col_kernel, dim3(nbk), dim3(256), 0, st, N, p, Pb, A);
-    }
+    launch_dense_inverse_blocked(N, A, work + N * N, st);
     HDG_CHECK(hipMemcpyAsync(L.Ainv64, A, sizeof(double) * N * N, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(f32_kernel, dim3(1024), dim3(256), 0, st, A, L.Ainv32, N * N);
   }

@@ -127,7 +127,14 @@ enum {
   /* Lanes per macro-element of the fused 2D h-transition kernels.  Default: four while macro-elements
      times right-hand sides stay below 16,384 (latency-bound levels), one above. */
   HDG_VARIANT_LANES1 = 128,     /* one lane per macro-element on every level */
-  HDG_VARIANT_LANES4 = 256      /* four lanes per macro-element (one interior face each) on every level */
+  HDG_VARIANT_LANES4 = 256,     /* four lanes per macro-element (one interior face each) on every level */
+  /* Coarse part of the 2D fused cycle (the h-levels from 128 x 128 down, and a coarsest level of more than
+     64 unknowns) as one persistent launch, one workgroup per compute unit, phases separated by grid-wide
+     barriers, single right-hand side; the same work items as the per-level kernels (results equal bit
+     for bit).  A barrier wait that runs out of polls ends the solve with HDG_ERR_DEVICE.
+     Currently switched off: hdg_mg_build returns HDG_ERR_UNSUPPORTED for this bit (a plain launch does
+     not promise that all workgroups of the grid are resident together, which the barriers need). */
+  HDG_VARIANT_GRID_TAIL = 512
 };
 
 typedef struct {
@@ -393,7 +400,8 @@ enum {
   HDG_Q_LEVEL_NLAMBDA = 100, /* + level */
   HDG_Q_LEVEL_N = 200,       /* + level: macro-elements per direction */
   HDG_Q_LEVEL_NE = 300,      /* + level: DOFs per face */
-  HDG_Q_DEVICE_BYTES = 400
+  HDG_Q_DEVICE_BYTES = 400,
+  HDG_Q_GRID_TAIL = 401      /* first level of the persistent coarse cycle, FP64 cycle (-1: not used) */
 };
 hdg_status hdg_query(hdg_handle h, int what, long long* out);
 

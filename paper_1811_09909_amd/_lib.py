@@ -16,6 +16,7 @@ METHOD_MG, METHOD_PCG, METHOD_GMRES = 0, 1, 2
 RHS_F_NODAL, RHS_F_LOAD, RHS_TRACE = 0, 1, 2
 Q_NT, Q_NLAMBDA, Q_NLEVELS, Q_NV, Q_NQ = 0, 1, 2, 3, 4
 Q_LEVEL_NLAMBDA, Q_LEVEL_N, Q_LEVEL_NE, Q_DEVICE_BYTES = 100, 200, 300, 400
+Q_GRID_TAIL = 401
 
 EXPORTS = [
     "hdg_default_opts", "hdg_setup", "hdg_update_kappa", "hdg_mg_build", "hdg_vcycle", "hdg_rhs", "hdg_solve",
@@ -52,6 +53,7 @@ class Opts(ctypes.Structure):
 VARIANT_NO_GRAPH, VARIANT_NO_FUSE, VARIANT_NO_TAIL, VARIANT_NO_PACK, VARIANT_NO_STRIP = 1, 2, 4, 8, 16
 VARIANT_FP32_VECTORS, VARIANT_FP64_VECTORS = 32, 64
 VARIANT_LANES1, VARIANT_LANES4 = 128, 256
+VARIANT_GRID_TAIL = 512
 PROF_F32OPS = 14  # hdg_profile_read: kernel = 14 + mode for FP64 vectors over FP32 operator blocks
 PROF_XFER = 21    # hdg_profile_read: kernel = 21 + 2 t + precision, t = 0 hpre, 1 hsum, 2 hpost, 3 p-prolongation
 XFER_KINDS = ("hpre", "hsum", "hpost", "prolong_p")

@@ -50,6 +50,12 @@ struct hdg_problem {
   int dot_parts = 0;
   int tail_start[2] = {-1, -1};  // first level of the coarse tail per precision (-1: none)
   TailArgs tail_args[2];
+  // persistent coarse cycle (HDG_VARIANT_GRID_TAIL): first level per
+  // precision (-1: none), its launch arguments and grid, and the barrier words
+  int gtail_start[2] = {-1, -1};
+  GTailArgs gtail_args[2];
+  int gtail_grid_n[2] = {0, 0};
+  unsigned* gtail_sync = nullptr;
   hipGraphExec_t gx[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int gnrhs = 1;                 // right-hand sides the captured graphs iterate
   hipGraph_t grp_graph = nullptr; // CHECK_EVERY CG iterations (one batch graph child), for gnrhs
@@ -216,6 +222,8 @@ void free_build(hdg_problem* P) {
   P->s.sc = P->s.partials = P->s.pcg = nullptr;
   P->gm_m = 0;
   P->cap = 1;
+  P->gtail_sync = nullptr;
+  P->gtail_start[0] = P->gtail_start[1] = -1;
 }
 
 hipEvent_t take_event(hdg_problem* P) {
@@ -391,6 +399,10 @@ T* vcycle(hdg_problem* P, int i, const T* r, T* out, bool pre_done = false, int 
   hipStream_t st = P->st;
   T* e = (T*)L.e[pr];
   T* w = (T*)L.w[pr];
+  if (!narrow && i == P->gtail_start[pr] && pre_done && !out && nr == 1 && r == (const T*)L.r[pr]) {
+    launch_gtail<T>(P->gtail_args[pr], P->gtail_grid_n[pr], st);
+    return e;
+  }
   if (!narrow && i == P->tail_start[pr]) {
     TailArgs a = P->tail_args[pr];
     a.rin = r;
@@ -914,6 +926,20 @@ void form_rhs(hdg_problem* P, const double* rhs, int kind, const double* gdir, d
 
 // Solve for the nr right-hand sides already in P->g (initial guesses in
 // P->lam), all iterated together (MG, PCG) or one after another (GMRES).
+// Error flag of the persistent coarse cycle: set when a grid-wide barrier
+// wait ran out of polls (its results are then not to be trusted).  The
+// barrier words are cleared for the next launch.
+hdg_status gtail_check(hdg_problem* P) {
+  if (!P->gtail_sync || (P->gtail_start[0] < 0 && P->gtail_start[1] < 0)) return HDG_OK;
+  unsigned flag = 0;
+  HDG_CHECK(hipMemcpyAsync(&flag, P->gtail_sync + 64, sizeof(unsigned), hipMemcpyDeviceToHost, P->st));
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  if (flag == 0) return HDG_OK;
+  HDG_CHECK(hipMemsetAsync(P->gtail_sync, 0, sizeof(unsigned) * GTAIL_SYNC_WORDS, P->st));
+  HDG_CHECK(hipStreamSynchronize(P->st));
+  return HDG_ERR_DEVICE;
+}
+
 hdg_status solve_many(hdg_problem* P, int nr, double tol, hdg_solve_info* info) {
   const long N = P->N;
   if (N == 0) {
@@ -957,7 +983,8 @@ hdg_status solve_many(hdg_problem* P, int nr, double tol, hdg_solve_info* info) 
     info->outer_iters += o.outer;
     info->relres = std::max(info->relres, o.relres);
   }
-  return o.status;
+  const hdg_status gs = gtail_check(P);
+  return gs != HDG_OK ? gs : o.status;
 }
 
 hdg_status solve_one(hdg_problem* P, const double* g, double* lam, double tol, hdg_solve_info* info) {
@@ -1318,7 +1345,7 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (o.sweeps < 0 || o.sweeps > 64 || (o.growth != 1 && o.growth != 2) || !(o.omega > 0.0) ||
       o.local_corr < 0 || o.local_corr > 3 || (o.precision != HDG_FP64 && o.precision != HDG_MIXED) ||
       o.method < 0 || o.method > 2 || o.max_it < 0 || o.restart < 0 || o.coarse_n < 0 || o.nrhs < 0 ||
-      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 511 ||
+      o.nrhs > HDG_MAX_NRHS || !(o.refine_red >= 0.0 && o.refine_red < 1.0) || o.variant < 0 || o.variant > 1023 ||
       o.smoother < HDG_SMOOTHER_BLOCK_JACOBI || o.smoother > HDG_SMOOTHER_LUSGS)
     return HDG_ERR_INVALID_ARG;
   if (o.nrhs < 1) o.nrhs = 1;
@@ -1327,6 +1354,12 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (P->unstructured) return ubuild(P, o);
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   if (!P->sym && o.method == HDG_METHOD_PCG) return HDG_ERR_UNSUPPORTED;  // CG needs a symmetric operator
+  // The persistent coarse cycle is switched off: its first run on the device
+  // ended with the queue lost (no result came back).  A plain launch does not
+  // promise that every workgroup of the grid is resident at once, which its
+  // grid-wide barriers need; until that is settled (a cooperative launch) the
+  // variant is refused here, before anything is allocated.
+  if (o.variant & HDG_VARIANT_GRID_TAIL) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();
   free_build(P);
@@ -1486,6 +1519,64 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
       P->tail_start[pr] = t;
       P->tail_args[pr] = ta;
       break;
+    }
+  }
+
+  // persistent coarse cycle (2D fused path, one right-hand side): from the
+  // first h-level of at most GTAIL_NMAX elements per direction below the
+  // finest down to a coarsest level solved by the dense row-per-wavefront
+  // product (more than 64 unknowns); it replaces the one-workgroup tail
+  P->gtail_start[0] = P->gtail_start[1] = -1;
+  if ((o.variant & HDG_VARIANT_GRID_TAIL) && d == 2 && P->fuse && o.sweeps >= 1 && L.back().kind == 2 &&
+      L.back().nlam > 64) {
+    for (int pr = 0; pr < 2; ++pr) {
+      const int grid = pr == 0 ? gtail_grid<double>() : gtail_grid<float>();
+      if (grid <= 0) continue;
+      for (int t = 1; t + 1 < (int)L.size(); ++t) {
+        if (L[t].n > GTAIL_NMAX || (int)L.size() - t > TAIL_MAX_LEVELS) continue;
+        bool ok = true;
+        for (int l = t; l + 1 < (int)L.size(); ++l)
+          ok = ok && L[l].kind == 1 && !L[l].packed && !L[l].strip && !L[l].u && L[l].ne == 2 && L[l].sweeps >= 1;
+        if (!ok) continue;
+        GTailArgs ga;
+        ga.nlev = (int)L.size() - t;
+        ga.lc = o.local_corr;
+        for (int l = t; l < (int)L.size(); ++l) {
+          const Level& Ll = L[l];
+          GTailLevel& g = ga.lev[l - t];
+          g.n = Ll.n;
+          g.kind = Ll.kind;
+          g.sweeps = Ll.sweeps;
+          g.lpm = Ll.kind == 1 ? level_lanes(Ll, 1) : 1;
+          g.nlam = Ll.nlam;
+          g.nface = Ll.nface;
+          g.nmacro = Ll.kind == 1 ? Ll.nmacro : 0;
+          g.Af = pr == 0 ? (const void*)Ll.Af64 : (const void*)Ll.Af32;
+          g.Dinv = pr == 0 ? (const void*)Ll.Dinv64 : (const void*)Ll.Dinv32;
+          g.AIIinv = pr == 0 ? (const void*)Ll.AIIinv64 : (const void*)Ll.AIIinv32;
+          g.R = pr == 0 ? (const void*)Ll.R64 : (const void*)Ll.R32;
+          g.P = pr == 0 ? (const void*)Ll.P64 : (const void*)Ll.P32;
+          g.Ainv = pr == 0 ? (const void*)Ll.Ainv64 : (const void*)Ll.Ainv32;
+          g.r = Ll.r[pr];
+          g.e = Ll.e[pr];
+          g.w = Ll.w[pr];
+          g.cb = Ll.cb[pr];
+          if (!g.r || !g.e || (Ll.kind == 1 && (!g.w || !g.cb || !g.Af || !g.Dinv || !g.AIIinv || !g.R || !g.P)) ||
+              (Ll.kind == 2 && !g.Ainv))
+            ok = false;
+        }
+        if (!ok) break;
+        if (!P->gtail_sync) {
+          P->gtail_sync = dalloc<unsigned>(P, GTAIL_SYNC_WORDS, true);
+          HDG_CHECK(hipMemsetAsync(P->gtail_sync, 0, sizeof(unsigned) * GTAIL_SYNC_WORDS, P->st));
+        }
+        ga.sync = P->gtail_sync;
+        P->gtail_start[pr] = t;
+        P->gtail_args[pr] = ga;
+        P->gtail_grid_n[pr] = grid;
+        P->tail_start[pr] = -1;
+        break;
+      }
     }
   }
 
@@ -1826,7 +1917,7 @@ hdg_status hdg_vcycle(hdg_handle P, const void* r, void* e, int precision, int n
       blas_f2d(e32, (double*)e + i0 * P->N, P->N, P->st, nr);
     }
   }
-  return HDG_OK;
+  return gtail_check(P);
   HDG_GUARD_END
 }
 
@@ -2205,8 +2296,12 @@ hdg_status hdg_solve_batch(int nprob, const hdg_handle* hs, const double* const*
                            const int* nrhs, double tol, double* const* lambda, hdg_solve_info* info,
                            int nstreams) {
   if (nprob < 1 || !hs || !rhs || !nrhs || !lambda || !(tol > 0.0)) return HDG_ERR_INVALID_ARG;
+  // unstructured handles, and handles built with the persistent coarse
+  // cycle (its workgroups must all be resident at once, which concurrent
+  // problems on other streams would not guarantee)
   for (int i = 0; i < nprob; ++i)
-    if (hs[i] && hs[i]->unstructured) return HDG_ERR_UNSUPPORTED;
+    if (hs[i] && (hs[i]->unstructured || hs[i]->gtail_start[0] >= 0 || hs[i]->gtail_start[1] >= 0))
+      return HDG_ERR_UNSUPPORTED;
   if (rhs_kind < 0 || rhs_kind > 2) return HDG_ERR_INVALID_ARG;
   for (int i = 0; i < nprob; ++i) {
     if (!hs[i] || !rhs[i] || !lambda[i] || nrhs[i] < 1) return HDG_ERR_INVALID_ARG;
@@ -2676,6 +2771,8 @@ hdg_status hdg_query(hdg_handle P, int what, long long* out) {
     *out = P->nq;
   } else if (what == HDG_Q_DEVICE_BYTES) {
     *out = P->bytes;
+  } else if (what == HDG_Q_GRID_TAIL) {
+    *out = P->gtail_start[0];
   } else if (what >= HDG_Q_LEVEL_NLAMBDA && what < HDG_Q_LEVEL_NLAMBDA + 100) {
     int l = what - HDG_Q_LEVEL_NLAMBDA;
     if (l >= nL) return HDG_ERR_INVALID_ARG;

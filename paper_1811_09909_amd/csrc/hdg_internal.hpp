@@ -394,6 +394,39 @@ struct TailArgs {
 template <typename T>
 void launch_tail(const TailArgs& a, hipStream_t st, int nrhs = 1);
 
+// Persistent coarse cycle (2D, one right-hand side): the levels from an
+// h-level down to the coarsest run in one launch of one workgroup per
+// compute unit, phases separated by grid-wide barriers, the vectors in the
+// levels' own device buffers.  Each phase is the work item the per-level
+// kernels run, in the same lane layout, so the results are theirs bit for
+// bit.  sync: [0] arrivals, [32] barrier generation, [64] error flag (a
+// barrier wait that ran out of polls; the launch then still ends).
+struct GTailLevel {
+  int n = 0, kind = 2, sweeps = 0, lpm = 1;
+  long nlam = 0, nface = 0, nmacro = 0;
+  const void *Af = nullptr, *Dinv = nullptr, *AIIinv = nullptr, *R = nullptr, *P = nullptr, *Ainv = nullptr;
+  void *r = nullptr, *e = nullptr, *w = nullptr, *cb = nullptr;
+};
+struct GTailArgs {
+  int nlev = 0, lc = 0;
+  GTailLevel lev[TAIL_MAX_LEVELS];
+  unsigned* sync = nullptr;
+};
+// lanes per macro-element the fused 2D transition kernels use on level L
+int level_lanes(const Level& L, int nrhs);
+#ifndef HDG_GTAIL_NMAX
+#define HDG_GTAIL_NMAX 128
+#endif
+constexpr int GTAIL_NMAX = HDG_GTAIL_NMAX;  // largest grid (elements per direction) the persistent cycle starts on
+constexpr int GTAIL_THREADS = 256;
+constexpr int GTAIL_SYNC_WORDS = 96;
+// workgroups of the persistent launch: one per compute unit, 0 if the
+// device cannot hold them all at once
+template <typename T>
+int gtail_grid();
+template <typename T>
+void launch_gtail(const GTailArgs& a, int grid, hipStream_t st);
+
 // APPLY_SWEEP_DOT: a sweep that also sums v . y (partials, v FP64, passed
 // where RES_PRESTRICT takes J_N) for the CG dot product r . z
 enum {

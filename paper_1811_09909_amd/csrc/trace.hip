@@ -1319,6 +1319,8 @@ void launch_coarse_solve(const Level& L, const T* r, T* e, hipStream_t st, int n
 }
 
 
+int level_lanes(const Level& L, int nrhs) { return L.lpm > 0 ? L.lpm : lanes_per_macro(L.nmacro, nrhs); }
+
 template <typename T>
 void launch_hpre(const Level& L, const T* r, T* e, int do_corr, T* cb, hipStream_t st, int nrhs) {
   const T* Af = sizeof(T) == 8 ? (const T*)L.Af64 : (const T*)L.Af32;

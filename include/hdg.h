@@ -131,9 +131,11 @@ enum {
   /* Coarse part of the 2D fused cycle (the h-levels from 128 x 128 down, and a coarsest level of more than
      64 unknowns) as one persistent launch, one workgroup per compute unit, phases separated by grid-wide
      barriers, single right-hand side; the same work items as the per-level kernels (results equal bit
-     for bit).  A barrier wait that runs out of polls ends the solve with HDG_ERR_DEVICE.
-     Currently switched off: hdg_mg_build returns HDG_ERR_UNSUPPORTED for this bit (a plain launch does
-     not promise that all workgroups of the grid are resident together, which the barriers need). */
+     for bit).  The grid holds half as many workgroups as the device has compute units, so that all
+     are resident together; a barrier wait that runs out of polls ends the solve with HDG_ERR_DEVICE.
+     Batched solves refuse handles built with it.  Currently switched off (hdg_mg_build returns
+     HDG_ERR_UNSUPPORTED for this bit): single V-cycles matched the per-level form bit for bit, but a
+     graph-captured CG solve with it failed on the device for a reason not yet found. */
   HDG_VARIANT_GRID_TAIL = 512
 };
 

@@ -1354,11 +1354,11 @@ hdg_status hdg_mg_build(hdg_handle P, const hdg_mg_opts* opts) {
   if (P->unstructured) return ubuild(P, o);
   if ((P->n & (P->n - 1)) != 0) return HDG_ERR_UNSUPPORTED;
   if (!P->sym && o.method == HDG_METHOD_PCG) return HDG_ERR_UNSUPPORTED;  // CG needs a symmetric operator
-  // The persistent coarse cycle is switched off: its first run on the device
-  // ended with the queue lost (no result came back).  A plain launch does not
-  // promise that every workgroup of the grid is resident at once, which its
-  // grid-wide barriers need; until that is settled (a cooperative launch) the
-  // variant is refused here, before anything is allocated.
+  // The persistent coarse cycle is switched off.  Launched eagerly (single
+  // V-cycles) it matched the per-level kernels bit for bit once its grid
+  // left residency slack; inside a graph-captured CG solve the device then
+  // reported an error and the queue was lost, for a reason not yet shown.
+  // Until that is found the variant is refused here, before any allocation.
   if (o.variant & HDG_VARIANT_GRID_TAIL) return HDG_ERR_UNSUPPORTED;
   HDG_GUARD_BEGIN
   const auto t0 = std::chrono::steady_clock::now();

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(TailArgs a) {
 // generation to move; the last arrival resets the counter and moves it.
 // The wait is bounded: after GTAIL_SPIN_MAX polls the error flag is set and
 // the workgroup goes on, so every launch ends; the host reports the flag.
-constexpr unsigned GTAIL_SPIN_MAX = 1u << 18;
+constexpr unsigned GTAIL_SPIN_MAX = 1u << 14;  // well under a second per launch even if every wait ran out
 
 __device__ inline void grid_barrier(unsigned* sync, unsigned nblocks, unsigned& gen) {
   __syncthreads();
@@ -278,7 +278,12 @@ int gtail_grid() {
   HDG_CHECK(hipGetDevice(&dev));
   HDG_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   HDG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gtail_kernel<T>, GTAIL_THREADS, 0));
-  return (ncu > 0 && per_cu >= 1) ? ncu : 0;
+  // half as many workgroups as compute units: at this kernel's register count
+  // one workgroup fills a compute unit, and the dispatcher spreads
+  // workgroups over shader engines whose usable compute units need not be
+  // equal in number, so a grid of one per compute unit could leave one
+  // workgroup unplaced while the others wait for it at a barrier
+  return (ncu >= 2 && per_cu >= 1) ? ncu / 2 : 0;
 }
 template <typename T>
 void launch_gtail(const GTailArgs& a, int grid, hipStream_t st) {

@@ -21,9 +21,10 @@ from ._helpers import relerr
 
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="persistent coarse cycle switched off: its first device run lost the queue (a plain "
-                            "launch does not promise that every workgroup is resident, which its grid-wide barriers "
-                            "need); hdg_mg_build refuses HDG_VARIANT_GRID_TAIL until it uses a cooperative launch"),
+    pytest.mark.skip(reason="persistent coarse cycle switched off: single eager V-cycles matched the per-level "
+                            "kernels bit for bit (and the oracle to 3.4e-14), but a graph-captured CG solve with it "
+                            "failed on the device and lost the queue, cause not yet shown; hdg_mg_build refuses "
+                            "HDG_VARIANT_GRID_TAIL"),
 ]
 
 

@@ -27,6 +27,29 @@ constexpr int RPT = 4;   // elements per thread per pass (independent loads in f
 
 __device__ inline double block_sum(double v, double* sh) { return block_sum_t<RB>(v, sh); }
 
+// Per-thread share of a fixed-order sum of partials: terms i = tid, tid + RB,
+// tid + 2 RB, ... < cnt added in that order (so the block sum that follows is
+// the same as a plain strided loop's), with the loads of PU consecutive
+// terms issued before any is added.  The partials come from workgroups on
+// every XCD, so each load waits on the memory side: one at a time would
+// chain those waits.  nv values per index, component v.
+constexpr int PU = 8;
+__device__ inline double strided_sum(const double* __restrict__ p, int cnt, int nv, int v) {
+  double a = 0.0;
+  for (int i0 = threadIdx.x; i0 < cnt; i0 += PU * RB) {
+    double x[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int i = i0 + u * RB;
+      x[u] = i < cnt ? p[(long)nv * i + v] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+      if (i0 + u * RB < cnt) a += x[u];
+  }
+  return a;
+}
+
 __global__ void __launch_bounds__(RB) dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                                  long n, double* __restrict__ partials) {
   __shared__ double sh[RB / 64];
@@ -54,9 +77,7 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double* __restrict__
   if (out) out += blockIdx.x;
   double tot[2] = {0.0, 0.0};
   for (int v = 0; v < nv; ++v) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nb; i += RB) a += partials[(long)nv * i + v];
-    tot[v] = block_sum(a, sh);
+    tot[v] = block_sum(strided_sum(partials, nb, nv, v), sh);
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -125,9 +146,7 @@ __global__ void __launch_bounds__(RB) cg_update2_kernel(double* __restrict__ lam
   double alpha;
   if (papp) {
     papp += blockIdx.y * (long)npap;
-    double a = 0.0;
-    for (int i = threadIdx.x; i < npap; i += RB) a += papp[i];
-    const double t0 = block_sum(a, sh);
+    const double t0 = block_sum(strided_sum(papp, npap, 1, 0), sh);
     if (threadIdx.x == 0) {
       const double al = t0 != 0.0 ? sc[SC_RZ] / t0 : 0.0;
       alpha_sh = al;
@@ -175,13 +194,14 @@ __global__ void __launch_bounds__(RB) finalize_cg_kernel(const double* __restric
   prz += blockIdx.x * (long)nrz;
   sc += blockIdx.x * (long)SC_COUNT;
   double t[3];
+  // the three per-thread shares first (all their loads in flight), then the
+  // three block sums in the same order as before
+  const double a0 = strided_sum(pcg, ncg, 2, 0);
+  const double a1 = strided_sum(pcg, ncg, 2, 1);
+  const double a2 = strided_sum(prz, nrz, 1, 0);
+  const double a[3] = {a0, a1, a2};
   for (int v = 0; v < 3; ++v) {
-    double a = 0.0;
-    if (v < 2)
-      for (int i = threadIdx.x; i < ncg; i += RB) a += pcg[2L * i + v];
-    else
-      for (int i = threadIdx.x; i < nrz; i += RB) a += prz[i];
-    t[v] = block_sum(a, sh);
+    t[v] = block_sum(a[v], sh);
     __syncthreads();
   }
   if (threadIdx.x != 0) return;

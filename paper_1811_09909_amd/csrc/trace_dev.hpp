@@ -358,6 +358,19 @@ __device__ inline int bchild(int b) {  // b = beta - NIF
   return ch;
 }
 
+// x[i NC + a] for face i >= 0, else 0.  The load is issued in either case
+// (from face 0 when i < 0) and the value selected afterwards.  In the
+// multi-lane transition items and the one-lane prolongation a load under a
+// condition was waited for before the next one was issued, so the faces of
+// a macro-element were fetched one round trip after another.  (The one-lane
+// pre-coarse item keeps its conditional loads: there they were not
+// serialized, and issuing all of them at once measured slower.)
+template <int NC, typename T>
+__device__ inline acc_t<T> face_val_or0(const T* x, long i, int a) {
+  const T v = x[(i >= 0 ? i : 0) * NC + a];
+  return i >= 0 ? acc_t<T>(v) : acc_t<T>(0);
+}
+
 // Pre-coarse-correction work of level l for one macro-element:
 //   rho_I = r_I - (A e)_I, e_I += A_II^-1 rho_I (if do_corr),
 //   cb_M = -J^T (A_M e)_B + P_M^T rho_I      (its share of Q (r - A e))
@@ -453,7 +466,7 @@ __device__ inline void hpreL_item(long M, int q, int n, const T* __restrict__ Af
   for (int f = 0; f < NIF + NBF; ++f) {
     fid[f] = mface_id<2>(m, f, n, &sidein[f]);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(e[fid[f] * NC + a]) : A(0);
+    for (int a = 0; a < NC; ++a) eM[f][a] = face_val_or0<NC, T>(e, fid[f], a);
   }
   A rq[QF][NC];
 #pragma unroll
@@ -501,15 +514,17 @@ __device__ inline void hpreL_item(long M, int q, int n, const T* __restrict__ Af
     for (int t = 0; t < NS; ++t) {
       const int b = S * NS + t;
       const int f = NIF + b;
-      if (fid[f] < 0) continue;
+      // no such face on the domain boundary: formed from face 0's block
+      // (loads issued with the others) and dropped
+      const bool has = fid[f] >= 0;
       A ab[NC] = {A(0), A(0)};
-      side_apply<2, T>(Af, fid[f], sidein[f], bchild<2>(b), eM, ab);
+      side_apply<2, T>(Af, has ? fid[f] : 0, sidein[f], bchild<2>(b), eM, ab);
 #pragma unroll
       for (int V = 0; V < NC; ++V) {
         A sacc = A(0);
 #pragma unroll
         for (int v = 0; v < NC; ++v) sacc += A(jh_weight<2>(t, v, V)) * ab[v];
-        o[V] -= sacc;
+        if (has) o[V] -= sacc;
       }
     }
 #pragma unroll
@@ -582,15 +597,16 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
       const int p = m[cc] + sd;
-      if (p == 0 || p == nm) {
+      // coarse face on the domain boundary: no value (zero); its load reads
+      // the face at position 1 and is dropped, so no load waits on a branch
+      const bool in = !(p == 0 || p == nm);
+      int G[3] = {m[0], m[1], m[2]};
+      G[cc] = in ? p : 1;
+      const long Fc = face_id<D>(cc, G, nm);
 #pragma unroll
-        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = A(0);
-      } else {
-        int G[3] = {m[0], m[1], m[2]};
-        G[cc] = p;
-        const long Fc = face_id<D>(cc, G, nm);
-#pragma unroll
-        for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
+      for (int V = 0; V < NC; ++V) {
+        const T v = ec[Fc * NC + V];
+        cv[sl * NC + V] = in ? A(v) : A(0);
       }
     }
     A eM[NIF + NBF][NC];
@@ -600,7 +616,7 @@ __device__ inline void hpost_m_item(long M, int n, const T* __restrict__ Af, con
     for (int f = 0; f < NIF + NBF; ++f) {
       fid[f] = mface_id<D>(m, f, n, &sidein[f]);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(eold[fid[f] * NC + a]) : A(0);
+      for (int a = 0; a < NC; ++a) eM[f][a] = face_val_or0<NC, T>(eold, fid[f], a);
     }
     // B faces: e + J e_c (local copy only; the coarse-face lanes write them)
 #pragma unroll
@@ -677,15 +693,14 @@ __device__ inline void hpostL_m_item(long M, int q, int n, const T* __restrict__
   for (int sl = 0; sl < 4; ++sl) {
     const int cc = sl / 2, sd = sl % 2;
     const int p = m[cc] + sd;
-    if (p == 0 || p == nm) {
+    const bool in = !(p == 0 || p == nm);  // boundary: load face 1's value, select zero
+    int G[3] = {m[0], m[1], m[2]};
+    G[cc] = in ? p : 1;
+    const long Fc = face_id<2>(cc, G, nm);
 #pragma unroll
-      for (int V = 0; V < NC; ++V) cv[sl * NC + V] = A(0);
-    } else {
-      int G[3] = {m[0], m[1], m[2]};
-      G[cc] = p;
-      const long Fc = face_id<2>(cc, G, nm);
-#pragma unroll
-      for (int V = 0; V < NC; ++V) cv[sl * NC + V] = ec[Fc * NC + V];
+    for (int V = 0; V < NC; ++V) {
+      const T v = ec[Fc * NC + V];
+      cv[sl * NC + V] = in ? A(v) : A(0);
     }
   }
   A eM[NIF + NBF][NC];
@@ -695,7 +710,7 @@ __device__ inline void hpostL_m_item(long M, int q, int n, const T* __restrict__
   for (int f = 0; f < NIF + NBF; ++f) {
     fid[f] = mface_id<2>(m, f, n, &sidein[f]);
 #pragma unroll
-    for (int a = 0; a < NC; ++a) eM[f][a] = fid[f] >= 0 ? A(eold[fid[f] * NC + a]) : A(0);
+    for (int a = 0; a < NC; ++a) eM[f][a] = face_val_or0<NC, T>(eold, fid[f], a);
   }
   // B faces: e + J e_c (local copies only)
 #pragma unroll

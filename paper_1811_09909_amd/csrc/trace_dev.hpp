@@ -829,16 +829,36 @@ __device__ inline int face_acc(long F, int n, const M* __restrict__ Af, const T*
     for (int sl = 0; sl < 2 * D; ++sl) {
       const int cc = sl / 2, sd = sl % 2;
       const int p = e[cc] + sd;
-      // a boundary slot carries no unknowns; the branch also keeps the
-      // compiler from hoisting the loads of every slot at once (registers)
-      if (p == 0 || p == n) continue;
-      int fg[3] = {e[0], e[1], e[2]};
-      fg[cc] = p;
-      const T* xf = x + face_id<D>(cc, fg, n) * NE;
-      acc_t<T> xs[NE];
+      if constexpr (NE <= 2) {
+        // P1 face blocks (the coarse levels, latency-bound): every slot's
+        // loads go out together.  A boundary slot reads the face at
+        // position 1 and its update is dropped by the select; a load under
+        // the branch was waited for before the next slot's.
+        const bool in = !(p == 0 || p == n);
+        int fg[3] = {e[0], e[1], e[2]};
+        fg[cc] = in ? p : 1;
+        const T* xf = x + face_id<D>(cc, fg, n) * NE;
+        acc_t<T> xs[NE], t[NE];
 #pragma unroll
-      for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
-      aos_mv_slot<M, NE>(Mx, sl * NE * NE, xs, acc);
+        for (int bb = 0; bb < NE; ++bb) {
+          xs[bb] = xf[bb];
+          t[bb] = acc[bb];
+        }
+        aos_mv_slot<M, NE>(Mx, sl * NE * NE, xs, t);
+#pragma unroll
+        for (int bb = 0; bb < NE; ++bb) acc[bb] = in ? t[bb] : acc[bb];
+      } else {
+        // a boundary slot carries no unknowns; the branch also keeps the
+        // compiler from hoisting the loads of every slot at once (registers)
+        if (p == 0 || p == n) continue;
+        int fg[3] = {e[0], e[1], e[2]};
+        fg[cc] = p;
+        const T* xf = x + face_id<D>(cc, fg, n) * NE;
+        acc_t<T> xs[NE];
+#pragma unroll
+        for (int bb = 0; bb < NE; ++bb) xs[bb] = xf[bb];
+        aos_mv_slot<M, NE>(Mx, sl * NE * NE, xs, acc);
+      }
     }
   }
   return c;

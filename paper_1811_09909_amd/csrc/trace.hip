@@ -901,8 +901,23 @@ __global__ void coarse_gemv_kernel(int N, const M* __restrict__ Ainv, const T* _
   if (row >= N) return;
   r += blockIdx.y * (long)N;
   e += blockIdx.y * (long)N;
+  // columns lane, lane + 64, ... summed in that order; the loads of GU
+  // consecutive terms go out before any is added (one at a time they were
+  // a chain of memory round trips)
+  constexpr int GU = 8;
   double s = 0.0;
-  for (int j = lane; j < N; j += 64) s += (double)Ainv[(long)row * N + j] * (double)r[j];
+  for (int j0 = lane; j0 < N; j0 += 64 * GU) {
+    double a[GU], b[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int j = j0 + 64 * u;
+      a[u] = j < N ? (double)Ainv[(long)row * N + j] : 0.0;
+      b[u] = j < N ? (double)r[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u)
+      if (j0 + 64 * u < N) s += a[u] * b[u];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) e[row] = (T)s;
 }

@@ -31,9 +31,9 @@ CAL_BYTES = 1 << 30
 # KiB units), each scaled by what the same counter reads for a kernel that
 # reads and writes exactly CAL_BYTES.  Valid only for the kernel sources it
 # was taken on.
-TRAFFIC = {"plain": {"fetch": 137723.531 + 6252.500, "write": 11010.703 + 798.000},
-           "rz": {"fetch": 147328.625 + 7167.000, "write": 11051.094 + 801.938},
-           "cal_fetch": 524300.0, "cal_write": 1048576.0, "sources_sha256_16": "b31df908a204a8b0"}
+TRAFFIC = {"plain": {"fetch": 137723.062 + 6252.500, "write": 11008.688 + 798.000},
+           "rz": {"fetch": 147322.375 + 7167.000, "write": 11039.312 + 801.938},
+           "cal_fetch": 524300.0, "cal_write": 1048576.0, "sources_sha256_16": "c507fc3d09621028"}
 TRAFFIC_SOURCES = ["paper_1811_09909_amd/csrc/trace.hip", "paper_1811_09909_amd/csrc/trace_dev.hpp",
                    "paper_1811_09909_amd/csrc/hdg_internal.hpp", "paper_1811_09909_amd/csrc/build.hip"]
 

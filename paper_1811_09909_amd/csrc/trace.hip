@@ -910,9 +910,9 @@ __global__ void coarse_gemv_kernel(int N, const M* __restrict__ Ainv, const T* _
     double a[GU], b[GU];
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
-      const int j = j0 + 64 * u;
-      a[u] = j < N ? (double)Ainv[(long)row * N + j] : 0.0;
-      b[u] = j < N ? (double)r[j] : 0.0;
+      const int j = j0 + 64 * u < N ? j0 + 64 * u : N - 1;  // past the end: a valid column, not added
+      a[u] = (double)Ainv[(long)row * N + j];
+      b[u] = (double)r[j];
     }
 #pragma unroll
     for (int u = 0; u < GU; ++u)
